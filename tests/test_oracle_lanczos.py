@@ -1,0 +1,123 @@
+"""Pins of the oracle's SFCI iteration (Sec. 2.1, Eqs. 1-11) and its small solver."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2312_01846_amd import synth
+
+
+def _closed_form_ring(L, ne):
+    eps = np.sort(-2.0 * np.cos(2.0 * np.pi * np.arange(L) / L))
+    return 2.0 * eps[:ne].sum()
+
+
+def test_jacobi_matches_lapack(orc):
+    rng = np.random.default_rng(0)
+    for m in [1, 2, 3, 7, 10, 20]:
+        A = rng.normal(size=(m, m))
+        A = A + A.T
+        w, V = orc.jacobi(A)
+        o = np.argsort(w)
+        assert np.allclose(w[o], np.linalg.eigvalsh(A), atol=1e-12)
+        assert np.allclose(V.T @ V, np.eye(m), atol=1e-12)
+        assert np.allclose(A @ V, V * w, atol=1e-11)
+
+
+def test_geneig_matches_scipy(orc):
+    rng = np.random.default_rng(1)
+    for m in [2, 5, 10]:
+        B = rng.normal(size=(m, m))
+        S = B @ B.T + m * np.eye(m)
+        T = rng.normal(size=(m, m))
+        T = T + T.T
+        lam, x, r = orc.geneig(T, S)
+        assert r == m
+        ref = sla.eigh(T, S, eigvals_only=True)[0]
+        assert abs(lam - ref) < 1e-12
+        assert np.allclose(T @ x, lam * (S @ x), atol=1e-11)
+        assert x[np.argmax(np.abs(x))] > 0
+
+
+def test_geneig_drops_null_directions(orc):
+    # Duplicate basis vectors make S singular; canonical orthogonalisation
+    # removes the null direction and the lowest eigenvalue is unchanged.
+    rng = np.random.default_rng(2)
+    n = 30
+    H = rng.normal(size=(n, n))
+    H = H + H.T
+    W = rng.normal(size=(n, 4))
+    W = np.concatenate([W, W[:, :1]], axis=1)
+    T = W.T @ H @ W
+    S = W.T @ W
+    lam, x, r = orc.geneig(T, S)
+    assert r == 4
+    ref = sla.eigh(W[:, :4].T @ H @ W[:, :4], W[:, :4].T @ W[:, :4], eigvals_only=True)[0]
+    assert abs(lam - ref) < 1e-9
+
+
+@pytest.mark.parametrize("L,ne", [(6, 3), (8, 4)])
+def test_hubbard_U0_closed_form(orc, L, ne):
+    h, g = synth.hubbard_ring(L, 1.0, 0.0)
+    P = orc.Problem(L, ne, ne, h, g)
+    a, b = synth.neel_bits(L)
+    r0 = P.rank([a], [b])
+    out = P.lanczos(r0, np.array([1.0]), None, 10, 60)
+    assert abs(out["energies"][-1] - _closed_form_ring(L, ne)) < 1e-9
+
+
+def _dense_case(orc):
+    h, g = synth.molecule_like(8, 16, 0)
+    P = orc.Problem(8, 3, 3, h, g)
+    return P, P.dense_H()
+
+
+def test_untruncated_block_is_rayleigh_ritz(orc):
+    # With M = all, T = W^T H W and S = W^T W exactly; the block energy is the
+    # lowest generalized eigenvalue, Psi's Rayleigh quotient under the dense H
+    # (built independently from the g-chain) equals it, and the first block's
+    # T is tridiagonal (Eq. 7).
+    P, H = _dense_case(orc)
+    out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), None, 10, 30, want_T=True)
+    E = out["energies"]
+    for b in range(3):
+        ref = sla.eigh(out["T"][b], out["S"][b], eigvals_only=True)[0]
+        assert abs(E[b] - ref) < 1e-10
+    psi = np.zeros(P.n_det)
+    psi[out["psi_rank"].astype(np.int64)] = out["psi_amp"]
+    rq = psi @ H @ psi / (psi @ psi)
+    assert abs(rq - E[-1]) < 1e-10
+    T0 = out["T"][0]
+    off = np.abs(np.triu(T0, 2))
+    assert off.max() < 1e-10
+    assert np.allclose(out["S"][0], np.eye(10), atol=1e-10)
+    # monotone: each block contains the previous Psi
+    assert np.all(np.diff(E) <= 1e-12)
+    # lowest eigenvalue reachable from the closed-shell start (spin-free H):
+    w, V = np.linalg.eigh(H)
+    reach = w[V[0, :] ** 2 > 1e-12][0]
+    assert E[-1] >= reach - 1e-10
+    assert E[-1] - reach < 1e-3
+
+
+def test_truncated_blocks_are_variational(orc):
+    P, H = _dense_case(orc)
+    w, V = np.linalg.eigh(H)
+    reach = w[V[0, :] ** 2 > 1e-12][0]
+    last = []
+    for M in [100, 400, 1600]:
+        out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), M, 10, 20, want_T=True)
+        E = out["energies"]
+        assert np.all(E >= reach - 1e-10)
+        for b in range(2):
+            ref = sla.eigh(out["T"][b], out["S"][b], eigvals_only=True)[0]
+            assert abs(E[b] - ref) < 1e-9
+        last.append(E[-1])
+    # error shrinks as the truncation grows (Sec. 4, Table 3 trend)
+    assert last[0] > last[1] > last[2]
+
+
+def test_truncated_vectors_have_M_entries(orc):
+    P, _ = _dense_case(orc)
+    out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 50, 10, 10)
+    assert len(out["psi_rank"]) <= 10 * 50
+    assert np.all(np.diff(out["psi_rank"].astype(np.int64)) > 0)
