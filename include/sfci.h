@@ -1,0 +1,165 @@
+/* sfci.h -- C ABI of the MI355X sparse-FCI hot path (libsfci.so).
+ *
+ * What it computes (Wang, "Sparse Full Configuration Interaction",
+ * arXiv 2312.01846):
+ *   sigma = H v for the second-quantized Hamiltonian
+ *     H = sum_pq h_pq sum_s a+_ps a_qs
+ *       + 1/2 sum_pqrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs
+ *   applied to a sparse vector of Slater determinants (Sec. 2.2: a sparse
+ *   vector is a set of (index, amplitude) pairs; matrix elements are
+ *   generated on the fly for single and double excitations, Sec. 3), the
+ *   determinant index being the combinatorial hash of Sec. 2.2, Eq. 12,
+ *   truncated to the M largest amplitudes (Sec. 2.1, Eqs. 10-11), and the
+ *   truncated-Lanczos iteration built on it (Sec. 2.1).
+ *
+ * Conventions shared by every call:
+ *   - A spin string is an n-bit mask (bit p set = spatial orbital p occupied),
+ *     1 <= n <= 32.  String rank r = sum_{t=1..k} C(c_t, t) over the ascending
+ *     0-based occupied orbitals c_t (Eq. 12).  Determinant rank
+ *     R = r_alpha * C(n, n_beta) + r_beta (alpha-major), 0 <= R < N_det.
+ *   - Integrals are FP64, real, row-major: h[p*n+q]; eri[((p*n+q)*n+r)*n+s]
+ *     = (pq|rs) in chemist notation.  h must be exactly symmetric and eri
+ *     exactly 8-fold symmetric (bitwise), else SFCI_E_NOTSYM.
+ *   - Phase convention: spin orbitals ordered all-alpha then all-beta,
+ *     orbital ascending (Jordan-Wigner).
+ *   - Sparse vectors (sfci_svec) are caller-owned DEVICE arrays: rank[] u64
+ *     strictly ascending (unique), amp[] f64; nnz entries used, capacity
+ *     allocated.  The library never frees caller memory.
+ *   - Every call returns sfci_status; SFCI_OK = 0, errors are negative and
+ *     leave the problem handle usable.  sfci_last_error() returns a
+ *     thread-local message for the last failing call on this thread.
+ *   - All device work is issued on the stream given at sfci_problem_create.
+ *     Calls that return a host count (nnz) synchronise that stream.
+ *   - The library allocates its own device workspace (dense FP64 accumulator
+ *     of N_det slots when it fits, selection and sort buffers) on first use
+ *     and keeps it until sfci_problem_destroy.
+ */
+#ifndef SFCI_H
+#define SFCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFCI_OK = 0,
+    SFCI_E_ARG = -1,         /* NULL pointer, bad size or bad option */
+    SFCI_E_RANGE = -2,       /* rank >= N_det, or N_det does not fit in 64 bits */
+    SFCI_E_DUP = -3,         /* input ranks not strictly ascending */
+    SFCI_E_CAPACITY = -4,    /* output capacity too small; out->nnz holds the size needed */
+    SFCI_E_NOMEM = -5,       /* device allocation failed */
+    SFCI_E_DEVICE = -6,      /* HIP runtime error */
+    SFCI_E_NOTSYM = -7,      /* h or eri not exactly symmetric */
+    SFCI_E_UNSUPPORTED = -8  /* n > 32, or a mode not available for this space */
+} sfci_status;
+
+typedef struct sfci_problem sfci_problem; /* opaque; owns device copies of integrals and tables */
+
+typedef struct {
+    int32_t n_orb;   /* spatial orbitals, 1..32 */
+    int32_t n_alpha; /* alpha electrons, 0..n_orb */
+    int32_t n_beta;  /* beta electrons, 0..n_orb */
+} sfci_space;
+
+typedef struct {
+    uint64_t* rank;    /* device, strictly ascending */
+    double* amp;       /* device */
+    uint64_t nnz;      /* entries in use (host value) */
+    uint64_t capacity; /* entries allocated */
+} sfci_svec;
+
+/* Deduplication of the intermediate elements (Sec. 2.2 merge step). */
+enum {
+    SFCI_DEDUP_AUTO = 0,  /* dense if 8*N_det bytes fit the device, else sort */
+    SFCI_DEDUP_DENSE = 1, /* FP64 atomic accumulation into an N_det array (fast, order not fixed) */
+    SFCI_DEDUP_SORT = 2   /* stable radix sort + in-order segmented sum (deterministic) */
+};
+
+typedef struct {
+    uint64_t M;        /* keep the M largest |sigma_k| (ties: lower rank first); UINT64_MAX = all */
+    int32_t dedup;     /* SFCI_DEDUP_* */
+    int32_t deterministic; /* 1: sort dedup and ordered reductions, bit-reproducible */
+} sfci_sigma_opts;
+
+typedef struct {
+    uint64_t terms_enumerated; /* (source, excitation) pairs visited */
+    uint64_t terms_emitted;    /* of those, with a nonzero element */
+    uint64_t candidates;       /* distinct nonzero entries of sigma before truncation */
+    double ms;                 /* device time of the call (HIP events) */
+} sfci_sigma_stats;
+
+/* N_det = C(n, n_alpha) * C(n, n_beta).  SFCI_E_RANGE if it exceeds 2^64-1. */
+sfci_status sfci_space_size(const sfci_space* space, uint64_t* n_det);
+
+/* Validate and upload the integrals (host pointers h[n*n], eri[n^4]).
+ * stream: a hipStream_t (NULL = default stream).  *out receives the handle. */
+sfci_status sfci_problem_create(const sfci_space* space, const double* h, const double* eri, void* stream,
+                                sfci_problem** out);
+sfci_status sfci_problem_destroy(sfci_problem* prob);
+
+/* Eq. 12 on device arrays: rank[i] = r(a_bits[i]) * C(n, n_beta) + r(b_bits[i]).
+ * Strings must have n_alpha / n_beta bits set within the low n bits, else SFCI_E_ARG
+ * (checked on device; the call synchronises to report it). */
+sfci_status sfci_rank(sfci_problem* prob, const uint64_t* a_bits, const uint64_t* b_bits, uint64_t count,
+                      uint64_t* rank);
+/* Inverse of sfci_rank.  SFCI_E_RANGE if some rank >= N_det. */
+sfci_status sfci_unrank(sfci_problem* prob, const uint64_t* rank, uint64_t count, uint64_t* a_bits,
+                        uint64_t* b_bits);
+
+/* sigma = H v, then the M largest entries (Eqs. 10-11 order, not normalised),
+ * written to out sorted by rank.  v must be strictly ascending with ranks < N_det.
+ * On SFCI_E_CAPACITY, out->nnz is set to the size needed and nothing is written.
+ * stats may be NULL.  Synchronises the stream (returns out->nnz). */
+sfci_status sfci_sigma(sfci_problem* prob, const sfci_svec* v, const sfci_sigma_opts* opts, sfci_svec* out,
+                       sfci_sigma_stats* stats);
+
+/* Truncation alone (Eqs. 10-11 without the division): the M largest |amp| of v
+ * (ties by lower rank), by ascending rank, into out.  Zero amplitudes are dropped.
+ * normalise != 0 divides the kept amplitudes by their 2-norm (Eq. 11). */
+sfci_status sfci_topm(sfci_problem* prob, const sfci_svec* v, uint64_t M, int32_t normalise, sfci_svec* out);
+
+typedef struct {
+    uint64_t M;            /* N_d of Sec. 2.1: entries kept per basis vector; UINT64_MAX = all */
+    int32_t n_L;           /* basis vectors per block (N_L), 1..32 */
+    int32_t n_iter;        /* sigma applications; n_iter / n_L blocks are run */
+    int32_t deterministic; /* 1: sort dedup and ordered reductions */
+    int32_t dedup;         /* SFCI_DEDUP_* (ignored when deterministic) */
+} sfci_lanczos_opts;
+
+typedef struct {
+    uint64_t sigma_calls;      /* sigma applications run */
+    uint64_t terms_enumerated; /* (source, excitation) pairs visited over all sigma calls */
+    uint64_t terms_emitted;    /* of those, with a nonzero element */
+    double sigma_ms;           /* summed device time of the sigma expansion kernels (HIP events) */
+    double total_ms;           /* device time of the whole call */
+} sfci_lanczos_stats;
+
+/* The SFCI iteration of Sec. 2.1 from start vector v0 (normalised internally).
+ * energies[b] (host, n_iter/n_L entries) receives each block's lowest
+ * generalized eigenvalue of (T, S).  psi_out (device, may be NULL) receives the
+ * last block's Psi = sum_j x_j w_j before truncation; SFCI_E_CAPACITY (with
+ * psi_out->nnz = needed) if it does not fit, energies still valid.
+ * T_out/S_out (host, may be NULL) receive each block's n_L x n_L matrices,
+ * block after block.  stats may be NULL. */
+sfci_status sfci_lanczos(sfci_problem* prob, const sfci_svec* v0, const sfci_lanczos_opts* opts, double* energies,
+                         sfci_svec* psi_out, double* T_out, double* S_out, sfci_lanczos_stats* stats);
+
+/* Backward of sigma = H(h, eri) v for a cotangent sbar (device vectors):
+ *   v_bar[i] = sum_k H_ki sbar_k for the entries i of v (device, nnz(v) doubles, may be NULL),
+ *   dh  = sym(gamma),  gamma_pq = sum_ki sbar_k v_i <k|E_pq|i>      (device n*n, may be NULL),
+ *   deri = the 8-fold symmetrisation of Gamma/2, with
+ *          Gamma_pqrs = sum_ki sbar_k v_i <k| sum_st a+_ps a+_rt a_st a_qs |i>  (device n^4, may be NULL),
+ * i.e. the gradients of sbar^T H v along symmetric perturbations of h and eri.
+ * Outputs are overwritten.  Asynchronous. */
+sfci_status sfci_sigma_backward(sfci_problem* prob, const sfci_svec* v, const sfci_svec* sbar, double* v_bar,
+                                double* dh, double* deri);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* sfci_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFCI_H */

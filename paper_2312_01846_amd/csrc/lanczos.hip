@@ -1,0 +1,376 @@
+// Truncated-Lanczos vector algebra (Sec. 2.1, Eqs. 10-11) and the small
+// generalized eigenproblem T x = lambda S x, all on the device.
+//
+// Reductions come in two flavours:
+//   fast    -- fixed-grid tree (run-to-run reproducible, not sequential order);
+//   ordered -- one wavefront adds the products strictly in ascending-rank
+//              order, which reproduces a sequential CPU sum bit for bit.
+#include <algorithm>
+#include <vector>
+
+#include "sfci_internal.h"
+
+namespace {
+
+constexpr int RB = 256;
+constexpr int RGRID = 1024;
+
+__device__ __forceinline__ double block_sum(double x, double* sh) {
+    // fixed shape tree over 256 threads
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double y_at(const u64* __restrict__ yr, const double* __restrict__ ya, u64 yn, u64 key) {
+    // lower bound in the ascending rank list
+    u64 lo = 0, hi = yn;
+    while (lo < hi) {
+        u64 mid = lo + ((hi - lo) >> 1);
+        if (yr[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < yn && yr[lo] == key) ? ya[lo] : 0.0;
+}
+
+// partial[b] = sum over a grid-stride slice of x_amp[i] * D[x_rank[i]]
+__global__ __launch_bounds__(RB) void k_dot_dense_part(const u64* __restrict__ r, const double* __restrict__ a,
+                                                       const u64* __restrict__ nnz, const double* __restrict__ D,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[RB];
+    const u64 n = *nnz;
+    double s = 0.0;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += a[i] * D[r[i]];
+    double b = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(RB) void k_dot_sparse_part(const u64* __restrict__ xr, const double* __restrict__ xa,
+                                                        const u64* __restrict__ xn, const u64* __restrict__ yr,
+                                                        const double* __restrict__ ya, const u64* __restrict__ yn,
+                                                        double* __restrict__ part) {
+    __shared__ double sh[RB];
+    const u64 n = *xn, m = *yn;
+    double s = 0.0;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) {
+        double yv = y_at(yr, ya, m, xr[i]);
+        if (yv != 0.0) s += xa[i] * yv;
+    }
+    double b = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(RB) void k_dot_final(const double* __restrict__ part, int np, double* out1, double* out2) {
+    __shared__ double sh[RB];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += RB) s += part[i];
+    double b = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        *out1 = b;
+        if (out2) *out2 = b;
+    }
+}
+
+// Ordered sums: one wavefront; products of 64 consecutive entries are formed in
+// parallel, then added one by one in index order.
+__global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict__ r, const double* __restrict__ a,
+                                                          const u64* __restrict__ nnz, const double* __restrict__ D,
+                                                          double* out1, double* out2) {
+    __shared__ double p[64];
+    const u64 n = *nnz;
+    double acc = 0.0;
+    for (u64 base = 0; base < n; base += 64) {
+        u64 i = base + threadIdx.x;
+        p[threadIdx.x] = (i < n) ? a[i] * D[r[i]] : 0.0;
+        __syncthreads();
+        u64 cnt = (n - base < 64) ? (n - base) : 64;
+        for (u64 k = 0; k < cnt; ++k) acc += p[k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out1 = acc;
+        if (out2) *out2 = acc;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_dot_sparse_ordered(const u64* __restrict__ xr, const double* __restrict__ xa,
+                                                           const u64* __restrict__ xn, const u64* __restrict__ yr,
+                                                           const double* __restrict__ ya, const u64* __restrict__ yn,
+                                                           double* out1, double* out2) {
+    __shared__ double p[64];
+    __shared__ int hit[64];
+    const u64 n = *xn, m = *yn;
+    double acc = 0.0;
+    for (u64 base = 0; base < n; base += 64) {
+        u64 i = base + threadIdx.x;
+        double yv = (i < n) ? y_at(yr, ya, m, xr[i]) : 0.0;
+        p[threadIdx.x] = (yv != 0.0) ? xa[i] * yv : 0.0;
+        hit[threadIdx.x] = (yv != 0.0);
+        __syncthreads();
+        u64 cnt = (n - base < 64) ? (n - base) : 64;
+        for (u64 k = 0; k < cnt; ++k)
+            if (hit[k]) acc += p[k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out1 = acc;
+        if (out2) *out2 = acc;
+    }
+}
+
+// D[r_i] = D[r_i] - coef * a_i  (SUB)   or   D[r_i] = D[r_i] + coef * a_i  (ADD)
+template <bool ADD>
+__global__ void k_axpy_scatter(double* __restrict__ D, const u64* __restrict__ r, const double* __restrict__ a,
+                               const u64* __restrict__ nnz, const double* __restrict__ coef) {
+    const u64 n = *nnz;
+    const double c = *coef;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        double prod = c * a[i];
+        u64 k = r[i];
+        if (ADD) D[k] = D[k] + prod;
+        else D[k] = D[k] - prod;
+    }
+}
+
+__global__ void k_scatter_set(double* __restrict__ D, const u64* __restrict__ r, const double* __restrict__ a,
+                              const u64* __restrict__ nnz) {
+    const u64 n = *nnz;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) D[r[i]] = a[i];
+}
+
+__global__ __launch_bounds__(RB) void k_sumsq_part(const double* __restrict__ a, const u64* __restrict__ nnz,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[RB];
+    const u64 n = *nnz;
+    double s = 0.0;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += a[i] * a[i];
+    double b = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(64) void k_sumsq_ordered(const double* __restrict__ a, const u64* __restrict__ nnz,
+                                                      double* out) {
+    __shared__ double p[64];
+    const u64 n = *nnz;
+    double acc = 0.0;
+    for (u64 base = 0; base < n; base += 64) {
+        u64 i = base + threadIdx.x;
+        p[threadIdx.x] = (i < n) ? a[i] * a[i] : 0.0;
+        __syncthreads();
+        u64 cnt = (n - base < 64) ? (n - base) : 64;
+        for (u64 k = 0; k < cnt; ++k) acc += p[k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = acc;
+}
+
+// Eq. 11: a_i = a_i / sqrt(sum of squares); untouched when the sum is 0.
+__global__ void k_div_norm(double* __restrict__ a, const u64* __restrict__ nnz, const double* __restrict__ ss) {
+    const u64 n = *nnz;
+    const double s = *ss;
+    if (!(s > 0.0)) return;
+    const double nrm = sqrt(s);
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = a[i] / nrm;
+}
+
+__global__ void k_copy_vec(const u64* __restrict__ r, const double* __restrict__ a, const u64* __restrict__ nnz,
+                           u64* __restrict__ r2, double* __restrict__ a2, u64* __restrict__ nnz2) {
+    const u64 n = *nnz;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        r2[i] = r[i];
+        a2[i] = a[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nnz2 = n;
+}
+
+// ---- generalized eigenproblem, one thread (m <= 32) ----
+#define GE_MAX 32
+
+// Cyclic Jacobi on the m x m symmetric matrix A (row-major, stride GE_MAX),
+// eigenvectors into V's columns, eigenvalues into w.  Same rotation rule,
+// sweep order and stopping rule as the CPU reference.
+__device__ void jacobi_dev(int m, double (*A)[GE_MAX], double (*V)[GE_MAX], double* w) {
+    for (int p = 0; p < m; ++p)
+        for (int q = 0; q < m; ++q) V[p][q] = (p == q) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, dg = 0.0;
+        for (int p = 0; p < m; ++p) {
+            dg += A[p][p] * A[p][p];
+            for (int q = p + 1; q < m; ++q) off += A[p][q] * A[p][q];
+        }
+        if (off <= 1e-30 * dg) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                double apq = A[p][q];
+                if (apq == 0.0) continue;
+                double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+                if (theta < 0.0) t = -t;
+                double c = 1.0 / sqrt(t * t + 1.0);
+                double s = t * c;
+                double tau = s / (1.0 + c);
+                A[p][p] = A[p][p] - t * apq;
+                A[q][q] = A[q][q] + t * apq;
+                A[p][q] = 0.0;
+                A[q][p] = 0.0;
+                for (int r = 0; r < m; ++r) {
+                    if (r == p || r == q) continue;
+                    double arp = A[r][p], arq = A[r][q];
+                    double nrp = arp - s * (arq + tau * arp);
+                    double nrq = arq + s * (arp - tau * arq);
+                    A[r][p] = nrp;
+                    A[p][r] = nrp;
+                    A[r][q] = nrq;
+                    A[q][r] = nrq;
+                }
+                for (int r = 0; r < m; ++r) {
+                    double vrp = V[r][p], vrq = V[r][q];
+                    V[r][p] = vrp - s * (vrq + tau * vrp);
+                    V[r][q] = vrq + s * (vrp - tau * vrq);
+                }
+            }
+    }
+    for (int p = 0; p < m; ++p) w[p] = A[p][p];
+}
+
+// Canonical orthogonalisation: S = U s U^T, keep s_k > 1e-10 max s,
+// X = U_k s_k^(-1/2), Jacobi on X^T T X, x = X y for the lowest eigenvalue,
+// sign fixed so that the largest |x_i| (lowest i on ties) is positive.
+__global__ void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S, double* lambda,
+                         double* x, double* energy_slot, int* status) {
+    __shared__ double A[GE_MAX][GE_MAX], U[GE_MAX][GE_MAX], X[GE_MAX][GE_MAX], TX[GE_MAX][GE_MAX];
+    __shared__ double sv[GE_MAX], lam[GE_MAX], xs[GE_MAX];
+    __shared__ int keep[GE_MAX];
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) A[i][j] = S[i * m + j];
+    jacobi_dev(m, A, U, sv);
+    double smax = 0.0;
+    for (int k = 0; k < m; ++k)
+        if (sv[k] > smax) smax = sv[k];
+    int r = 0;
+    for (int k = 0; k < m; ++k)
+        if (sv[k] > 1e-10 * smax) keep[r++] = k;
+    if (r == 0) {
+        *status = 1;
+        return;
+    }
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < r; ++c) X[i][c] = U[i][keep[c]] / sqrt(sv[keep[c]]);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < r; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += T[i * m + k] * X[k][c];
+            TX[i][c] = acc;
+        }
+    for (int a = 0; a < r; ++a)
+        for (int c = 0; c < r; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += X[k][a] * TX[k][c];
+            A[a][c] = acc;
+        }
+    for (int a = 0; a < r; ++a)
+        for (int c = a + 1; c < r; ++c) {
+            double v = 0.5 * (A[a][c] + A[c][a]);
+            A[a][c] = v;
+            A[c][a] = v;
+        }
+    jacobi_dev(r, A, U, lam);  // U now holds the eigenvectors y of X^T T X
+    int best = 0;
+    for (int k = 1; k < r; ++k)
+        if (lam[k] < lam[best]) best = k;
+    for (int i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int c = 0; c < r; ++c) acc += X[i][c] * U[c][best];
+        xs[i] = acc;
+    }
+    int imax = 0;
+    for (int i = 1; i < m; ++i)
+        if (fabs(xs[i]) > fabs(xs[imax])) imax = i;
+    bool neg = xs[imax] < 0.0;
+    for (int i = 0; i < m; ++i) x[i] = neg ? -xs[i] : xs[i];
+    *lambda = lam[best];
+    if (energy_slot) *energy_slot = lam[best];
+    *status = 0;
+}
+
+unsigned gsz(u64 cap) {
+    u64 g = (cap + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 16384) g = 16384;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
+                      double* out1, double* out2, bool ordered) {
+    if (ordered) {
+        hipLaunchKernelGGL(k_dot_dense_ordered, dim3(1), dim3(64), 0, P->stream, r, a, nnz, D, out1, out2);
+    } else {
+        double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
+        unsigned g = std::min<unsigned>(RGRID, gsz(cap));
+        hipLaunchKernelGGL(k_dot_dense_part, dim3(g), dim3(RB), 0, P->stream, r, a, nnz, D, part);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, out1, out2);
+    }
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,
+                       const double* ya, const u64* yn, double* out1, double* out2, bool ordered) {
+    if (ordered) {
+        hipLaunchKernelGGL(k_dot_sparse_ordered, dim3(1), dim3(64), 0, P->stream, xr, xa, xn, yr, ya, yn, out1, out2);
+    } else {
+        double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
+        unsigned g = std::min<unsigned>(RGRID, gsz(xcap));
+        hipLaunchKernelGGL(k_dot_sparse_part, dim3(g), dim3(RB), 0, P->stream, xr, xa, xn, yr, ya, yn, part);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, out1, out2);
+    }
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap,
+                         const double* coef, double sign) {
+    if (sign > 0)
+        hipLaunchKernelGGL(k_axpy_scatter<true>, dim3(gsz(cap)), dim3(256), 0, P->stream, D, r, a, nnz, coef);
+    else
+        hipLaunchKernelGGL(k_axpy_scatter<false>, dim3(gsz(cap)), dim3(256), 0, P->stream, D, r, a, nnz, coef);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap) {
+    hipLaunchKernelGGL(k_scatter_set, dim3(gsz(cap)), dim3(256), 0, P->stream, D, r, a, nnz);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered) {
+    double* part = (double*)P->ws_red.get((RGRID + 8) * sizeof(double));
+    double* ss = part + RGRID;
+    if (ordered) {
+        hipLaunchKernelGGL(k_sumsq_ordered, dim3(1), dim3(64), 0, P->stream, a, nnz, ss);
+    } else {
+        unsigned g = std::min<unsigned>(RGRID, gsz(cap));
+        hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(RB), 0, P->stream, a, nnz, part);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, ss, (double*)nullptr);
+    }
+    hipLaunchKernelGGL(k_div_norm, dim3(gsz(cap)), dim3(256), 0, P->stream, a, nnz, ss);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_copy_vec(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, u64* r2, double* a2,
+                     u64* nnz2) {
+    hipLaunchKernelGGL(k_copy_vec, dim3(gsz(cap)), dim3(256), 0, P->stream, r, a, nnz, r2, a2, nnz2);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
+                        double* energy_slot, int* status) {
+    hipLaunchKernelGGL(k_geneig, dim3(1), dim3(64), 0, P->stream, m, T, S, lambda, x, energy_slot, status);
+    SFCI_CHECK_HIP(hipGetLastError());
+}

@@ -1,0 +1,290 @@
+// Truncation to the M largest amplitudes (Sec. 2.1, Eqs. 10-11; the paper
+// sorts the whole intermediate vector, Sec. 3).  Here: an MSD radix select
+// over the 128-bit key K = bits(|c|) ++ (N_det - 1 - rank), which orders
+// entries by |c| descending and breaks exact ties by rank ascending, followed
+// by an order-preserving compaction that writes the kept entries by rank.
+// Every pass is a streaming read of the candidates (dense N_det array or a
+// rank-sorted list); no sort of the candidates is needed.
+#include <algorithm>
+
+#include "sfci_internal.h"
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+constexpr int DIG = 11;
+constexpr int NBIN = 1 << DIG;
+constexpr int CBLOCK = 256;
+constexpr int CITEMS = 16;
+constexpr u64 CCHUNK = (u64)CBLOCK * CITEMS;
+
+struct Geo {
+    int tb;    // total key bits = 63 + rank_bits
+    int ndig;  // ceil(tb / 11)
+    u64 ndet_m1;
+    int rank_bits;
+};
+
+__device__ __forceinline__ u128 sel_key(u64 rank, double c, const Geo& g) {
+    u64 P = (u64)__double_as_longlong(c) & 0x7FFFFFFFFFFFFFFFull;
+    u64 Q = g.ndet_m1 - rank;
+    return ((u128)P << g.rank_bits) | (u128)Q;
+}
+
+__device__ __forceinline__ int dig_lo(const Geo& g, int L) {
+    int lo = g.tb - DIG * (L + 1);
+    return lo < 0 ? 0 : lo;
+}
+
+struct DenseSrc {
+    const double* D;
+    u64 n;
+    __device__ __forceinline__ u64 size() const { return n; }
+    __device__ __forceinline__ void get(u64 i, u64& r, double& c) const { r = i; c = D[i]; }
+};
+
+struct ListSrc {
+    const u64* r;
+    const double* v;
+    const u64* cnt;
+    __device__ __forceinline__ u64 size() const { return *cnt; }
+    __device__ __forceinline__ void get(u64 i, u64& rr, double& c) const { rr = r[i]; c = v[i]; }
+};
+
+__device__ __forceinline__ bool sel_pred(const SelState& st, const Geo& g, u64 r, double c) {
+    if (c == 0.0) return false;
+    if (st.take_all) return true;
+    if (!st.done || st.level == 0) return false;  // M = 0: nothing is kept
+    u128 K = sel_key(r, c, g);
+    u128 pre = ((u128)st.pre_hi << 64) | st.pre_lo;
+    int sh = dig_lo(g, st.level - 1);
+    return (K >> sh) >= pre;
+}
+
+__global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
+    for (int t = threadIdx.x; t < NBIN; t += blockDim.x) st->hist[t] = 0;
+    if (threadIdx.x == 0) {
+        st->need = M;
+        st->pre_hi = 0;
+        st->pre_lo = 0;
+        st->level = 0;
+        st->done = (take_all || take_none) ? 1 : 0;
+        st->take_all = take_all;
+        st->total = 0;
+        st->count_out = 0;
+    }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict__ st, Geo g, int L) {
+    if (st->done) return;
+    __shared__ unsigned int h[NBIN];
+    __shared__ unsigned long long blk_total;
+    for (int t = threadIdx.x; t < NBIN; t += blockDim.x) h[t] = 0;
+    if (threadIdx.x == 0) blk_total = 0;
+    __syncthreads();
+    const u128 pre = ((u128)st->pre_hi << 64) | st->pre_lo;
+    const int lo = dig_lo(g, L);
+    const int hi_sh = g.tb - DIG * L;  // bits above the current digit
+    const u64 n = src.size();
+    u64 my_total = 0;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        u64 r;
+        double c;
+        src.get(i, r, c);
+        if (c == 0.0) continue;
+        ++my_total;
+        u128 K = sel_key(r, c, g);
+        if (L > 0 && (K >> hi_sh) != pre) continue;
+        unsigned d = (unsigned)((K >> lo) & (u128)(NBIN - 1));
+        atomicAdd(&h[d], 1u);
+    }
+    if (L == 0 && my_total) atomicAdd(&blk_total, (unsigned long long)my_total);
+    __syncthreads();
+    for (int t = threadIdx.x; t < NBIN; t += blockDim.x)
+        if (h[t]) atomicAdd((unsigned long long*)&st->hist[t], (unsigned long long)h[t]);
+    if (L == 0 && threadIdx.x == 0 && blk_total) atomicAdd((unsigned long long*)&st->total, blk_total);
+}
+
+__global__ void k_sel_pick(SelState* st, Geo g, int L, u64 M) {
+    if (threadIdx.x != 0) return;
+    if (st->done) return;
+    if (L == 0 && st->total <= M) {
+        st->take_all = 1;
+        st->done = 1;
+        for (int t = 0; t < NBIN; ++t) st->hist[t] = 0;
+        return;
+    }
+    u64 acc = 0;
+    int d = NBIN - 1;
+    for (; d > 0; --d) {
+        u64 h = st->hist[d];
+        if (acc + h >= st->need) break;
+        acc += h;
+    }
+    st->need -= acc;
+    u64 hd = st->hist[d];
+    int lo = dig_lo(g, L);
+    int width = (g.tb - DIG * L) - lo;
+    u128 pre = ((u128)st->pre_hi << 64) | st->pre_lo;
+    pre = (pre << width) | (u128)(unsigned)d;
+    st->pre_hi = (u64)(pre >> 64);
+    st->pre_lo = (u64)pre;
+    st->level = L + 1;
+    if (hd == st->need || L == g.ndig - 1) st->done = 1;
+    for (int t = 0; t < NBIN; ++t) st->hist[t] = 0;
+}
+
+template <class Src>
+__global__ __launch_bounds__(CBLOCK) void k_compact_count(Src src, const SelState* __restrict__ st, Geo g,
+                                                          u64* __restrict__ cnt) {
+    const u64 n = src.size();
+    const u64 base = (u64)blockIdx.x * CCHUNK;
+    if (base >= n) {  // grid sized for capacity; chunk beyond the live size
+        if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
+        return;
+    }
+    const SelState s = *st;
+    unsigned c = 0;
+    for (int k = 0; k < CITEMS; ++k) {
+        u64 i = base + (u64)k * CBLOCK + threadIdx.x;
+        if (i < n) {
+            u64 r;
+            double v;
+            src.get(i, r, v);
+            c += sel_pred(s, g, r, v) ? 1u : 0u;
+        }
+    }
+    __shared__ unsigned sh[CBLOCK / 64];
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int w = 0; w < CBLOCK / 64; ++w) t += sh[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+template <class Src, bool ZERO>
+__global__ __launch_bounds__(CBLOCK) void k_compact_write(Src src, const SelState* __restrict__ st, Geo g,
+                                                          const u64* __restrict__ off, u64* __restrict__ out_r,
+                                                          double* __restrict__ out_a, double* __restrict__ Dz) {
+    const u64 n = src.size();
+    const u64 base = (u64)blockIdx.x * CCHUNK;
+    if (base >= n) return;
+    const SelState s = *st;
+    __shared__ unsigned wtot[CBLOCK / 64];
+    u64 run = off[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < CITEMS; ++k) {
+        u64 i = base + (u64)k * CBLOCK + threadIdx.x;
+        u64 r = 0;
+        double v = 0.0;
+        bool p = false;
+        if (i < n) {
+            src.get(i, r, v);
+            p = sel_pred(s, g, r, v);
+            if (ZERO && v != 0.0) Dz[i] = 0.0;
+        }
+        u64 m = __ballot(p);
+        unsigned below = (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wtot[wave] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned wbase = 0, all = 0;
+        for (int w = 0; w < CBLOCK / 64; ++w) {
+            if (w < wave) wbase += wtot[w];
+            all += wtot[w];
+        }
+        if (p) {
+            u64 at = run + wbase + below;
+            out_r[at] = r;
+            out_a[at] = v;
+        }
+        run += all;
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_count(const u64* src, u64* dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+Geo make_geo(sfci_problem* P) {
+    Geo g;
+    g.rank_bits = P->kg.rank_bits;
+    g.tb = 63 + g.rank_bits;
+    g.ndig = (g.tb + DIG - 1) / DIG;
+    g.ndet_m1 = P->kg.ndet_m1;
+    return g;
+}
+
+template <class Src>
+void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_count_dev) {
+    Geo g = make_geo(P);
+    SelState* st = (SelState*)P->ws_sel.get(sizeof(SelState));
+    int take_all = (M == UINT64_MAX) ? 1 : 0;
+    int take_none = (M == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, P->stream, st, M, take_all, take_none);
+    unsigned hgrid = (unsigned)std::min<u64>((n_upper + 255) / 256, (u64)P->num_cu * 8);
+    if (hgrid < 1) hgrid = 1;
+    if (!take_all && !take_none) {
+        for (int L = 0; L < g.ndig; ++L) {
+            hipLaunchKernelGGL(k_sel_hist<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st, g, L);
+            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, P->stream, st, g, L, M);
+        }
+    }
+    u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
+    if (nblk < 1) nblk = 1;
+    u64* cnt = (u64*)P->ws_cnt.get(nblk * sizeof(u64));
+    hipLaunchKernelGGL(k_compact_count<Src>, dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, src, st, g, cnt);
+    exclusive_scan_u64(P, cnt, cnt, nblk, &st->count_out);
+    if (out_count_dev) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, P->stream, &st->count_out, out_count_dev);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+template <class Src>
+void run_write(sfci_problem* P, const Src& src, u64 n_upper, u64* out_rank, double* out_amp, bool zero_dense,
+               double* Dz) {
+    Geo g = make_geo(P);
+    SelState* st = (SelState*)P->ws_sel.p;
+    u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
+    if (nblk < 1) nblk = 1;
+    u64* cnt = (u64*)P->ws_cnt.p;
+    if (zero_dense)
+        hipLaunchKernelGGL((k_compact_write<Src, true>), dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, src, st, g,
+                           cnt, out_rank, out_amp, Dz);
+    else
+        hipLaunchKernelGGL((k_compact_write<Src, false>), dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, src, st,
+                           g, cnt, out_rank, out_amp, Dz);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void select_prepare(sfci_problem* P, const CandSrc& src, u64 M, u64* count_dev) {
+    if (src.dense) {
+        DenseSrc s{src.dense, P->Ndet};
+        run_prepare(P, s, P->Ndet, M, count_dev);
+    } else {
+        ListSrc s{src.lrank, src.lval, src.lcount};
+        run_prepare(P, s, src.lcap, M, count_dev);
+    }
+}
+
+void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* out_amp, bool zero_dense) {
+    if (src.dense) {
+        DenseSrc s{src.dense, P->Ndet};
+        run_write(P, s, P->Ndet, out_rank, out_amp, zero_dense, (double*)src.dense);
+    } else {
+        ListSrc s{src.lrank, src.lval, src.lcount};
+        run_write(P, s, src.lcap, out_rank, out_amp, false, nullptr);
+    }
+}
+
+void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, double* out_amp, u64* out_count_dev,
+                 bool zero_dense) {
+    select_prepare(P, src, M, out_count_dev);
+    select_write(P, src, out_rank, out_amp, zero_dense);
+}

@@ -1,0 +1,134 @@
+// Internal host-side declarations of libsfci (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sfci_device.h"
+
+#define SFCI_CHECK_HIP(expr)                                                       \
+    do {                                                                           \
+        hipError_t _e = (expr);                                                    \
+        if (_e != hipSuccess) throw sfci_error(-6, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct sfci_error {
+    int code;
+    std::string msg;
+    sfci_error(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void* get(size_t need);
+    void release();
+};
+
+// Top-M selection state (device resident): a radix select over the 128-bit
+// key K = (bits(|c|) << rank_bits) | (N_det - 1 - rank), 11-bit digits from
+// the top, so that larger K = larger |c|, then lower rank.
+struct SelState {
+    u64 need;       // entries still to take inside the current prefix
+    u64 pre_hi, pre_lo;
+    int level;      // digits fixed so far
+    int done;       // selection decided
+    int take_all;   // keep every nonzero entry
+    int pad;
+    u64 total;      // nonzero candidates (filled at level 0)
+    u64 count_out;  // entries written by the compaction
+    u64 hist[2048];
+};
+
+struct KeyGeom {
+    int rank_bits;  // bits of N_det - 1 (>= 1)
+    int ndig;       // number of 11-bit digits covering 63 + rank_bits bits
+    int pad_bits;   // left shift that aligns the key to ndig digits
+    u64 ndet_m1;
+};
+
+struct sfci_problem {
+    int n, na, nb;
+    u64 Na, Nb, Ndet;
+    KeyGeom kg;
+    hipStream_t stream;
+    int device;
+    double* d_h = nullptr;
+    double* d_g = nullptr;
+    u64* d_binom = nullptr;
+    double* d_D = nullptr;  // dense accumulator (N_det doubles), all zero between calls
+    int dense_state = 0;    // 0 untried, 1 allocated, -1 does not fit
+    int num_cu = 256;
+    DevBuf ws_sel, ws_cnt, ws_scan, ws_scan2, ws_scalar, ws_red;
+    DevBuf ws_tup_k, ws_tup_v, ws_tup_k2, ws_tup_v2, ws_seg_v, ws_seg_f, ws_src_cnt, ws_src_off, ws_hist;
+    DevBuf ws_list_r, ws_list_a;
+    DevBuf ws_lz[8];
+};
+
+// ---- launchers (sigma.hip) ----
+struct SigmaLaunch {
+    const u64* v_rank;
+    const double* v_amp;
+    const u64* v_nnz;  // device scalar
+    u64 cap;           // upper bound on nnz (grid sizing)
+};
+void launch_sigma_dense(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
+void launch_sigma_count(sfci_problem* P, const SigmaLaunch& v, u64 alo, u64 ahi, u64* counts);
+void launch_sigma_emit(sfci_problem* P, const SigmaLaunch& v, u64 alo, u64 ahi, const u64* offs, u64 key_base,
+                       u64* keys, double* vals);
+void launch_rank(sfci_problem* P, const u64* a, const u64* b, u64 cnt, u64* rank, int* bad);
+void launch_unrank(sfci_problem* P, const u64* rank, u64 cnt, u64* a, u64* b, int* bad);
+void launch_backward(sfci_problem* P, const SigmaLaunch& v, const double* sbar_dense, double* vbar, double* dh_raw,
+                     double* dg_raw);
+
+// ---- utilities (util.hip) ----
+void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);
+void launch_fill_u64(u64* p, u64 n, u64 val, hipStream_t s);
+// exclusive scan of n u64 counts into out (may alias); total -> *total_dev (device scalar)
+void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* total_dev);
+
+// ---- selection (select.hip) ----
+// Source of candidates: either a dense array (index = rank) or a list.
+struct CandSrc {
+    const double* dense;  // if non-null: D[0..Ndet)
+    const u64* lrank;     // else list
+    const double* lval;
+    const u64* lcount;    // device scalar
+    u64 lcap;
+};
+// Select the M largest (|c|, then lower rank) nonzero candidates and write them
+// by ascending rank to (out_rank, out_amp); *out_count_dev receives the count.
+// If zero_dense, the dense source is cleared to 0.0 in the same pass.
+// M == UINT64_MAX keeps all nonzero candidates.
+void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, double* out_amp, u64* out_count_dev,
+                 bool zero_dense);
+// Two-phase form: prepare (selection levels + counts; the count goes to
+// *count_dev), then write.  The state lives in the problem's workspace, so no
+// other selection may run in between.
+void select_prepare(sfci_problem* P, const CandSrc& src, u64 M, u64* count_dev);
+void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* out_amp, bool zero_dense);
+
+// ---- sort path (sortpath.hip) ----
+// sigma = H v by stable sort + in-order segmented sum; result sorted by rank,
+// zeros dropped, in (out_rank, out_amp) with *out_count_dev; returns false if
+// the result would exceed out_cap (then *out_count_dev = needed).
+void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_rank, double* out_amp,
+                  u64* out_count_dev, u64* emitted_dev);
+
+// ---- Lanczos vector ops (lanczos.hip) ----
+void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
+                      double* out1, double* out2, bool ordered);
+void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,
+                       const double* ya, const u64* yn, double* out1, double* out2, bool ordered);
+void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap,
+                         const double* coef, double sign);
+void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered);
+void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap);
+void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
+                        double* energy_slot, int* status);
+void launch_copy_vec(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, u64* r2, double* a2,
+                     u64* nnz2);
+
+int sfci_set_error(int code, const std::string& msg);

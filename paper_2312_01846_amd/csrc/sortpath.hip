@@ -1,0 +1,211 @@
+// Sort-and-merge deduplication of the intermediate elements (Sec. 2.2: the
+// paper sorts each bucket by determinant and merges equal determinants with a
+// linear scan; buckets are ranges of the hash, restricted to the spin-up part
+// of the string in Sec. 3).  On the GPU:
+//   * a pass covers a range of target alpha ranks (a contiguous rank range);
+//   * exact per-source tuple counts are scanned into emission offsets, so the
+//     tuples of every source land in one contiguous, source-ordered block;
+//   * a stable LSD radix sort by target keeps that order inside equal keys;
+//   * one thread per run of equal keys adds the values in order.
+// Every target therefore receives its contributions in ascending source
+// order: the result is bit-reproducible and independent of scheduling.
+#include <algorithm>
+#include <vector>
+
+#include "sfci_internal.h"
+
+namespace {
+
+constexpr int RS_BLOCK = 256;
+constexpr int RS_ITEMS = 16;
+constexpr u64 RS_TILE = (u64)RS_BLOCK * RS_ITEMS;
+constexpr int RS_BITS = 8;
+constexpr int RS_BINS = 1 << RS_BITS;
+
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const u64* __restrict__ keys, u64 n, int shift,
+                                                      u64* __restrict__ hist, u64 nblk) {
+    __shared__ unsigned h[RS_BINS];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const u64 base = (u64)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        u64 i = base + (u64)k * RS_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RS_BINS - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(u64)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const u64* __restrict__ keys, const double* __restrict__ vals,
+                                                         u64 n, int shift, const u64* __restrict__ offs, u64 nblk,
+                                                         u64* __restrict__ ko, double* __restrict__ vo) {
+    __shared__ u64 run[RS_BINS];
+    __shared__ unsigned wc[RS_BLOCK / 64][RS_BINS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    run[threadIdx.x] = offs[(u64)threadIdx.x * nblk + blockIdx.x];
+    for (int w = 0; w < RS_BLOCK / 64; ++w) wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const u64 base = (u64)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        u64 i = base + (u64)k * RS_BLOCK + threadIdx.x;
+        bool valid = i < n;
+        u64 key = valid ? keys[i] : 0;
+        double val = valid ? vals[i] : 0.0;
+        unsigned d = (unsigned)((key >> shift) & (RS_BINS - 1));
+        u64 peers = __ballot(valid);
+        for (int b = 0; b < RS_BITS; ++b) {
+            u64 m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        unsigned rank = (unsigned)__popcll(peers & ((1ull << lane) - 1ull));
+        if (valid && rank == 0) wc[wave][d] = (unsigned)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            u64 pos = run[d];
+            for (int w = 0; w < wave; ++w) pos += wc[w][d];
+            pos += rank;
+            ko[pos] = key;
+            vo[pos] = val;
+        }
+        __syncthreads();
+        {
+            unsigned add = 0;
+            for (int w = 0; w < RS_BLOCK / 64; ++w) {
+                add += wc[w][threadIdx.x];
+                wc[w][threadIdx.x] = 0;
+            }
+            run[threadIdx.x] += add;
+        }
+        __syncthreads();
+    }
+}
+
+// Run heads: sum each run of equal keys in order; flag nonzero sums.
+__global__ void k_seg_sum(const u64* __restrict__ keys, const double* __restrict__ vals, u64 n,
+                          double* __restrict__ seg, u64* __restrict__ flag) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        bool head = (i == 0) || (keys[i] != keys[i - 1]);
+        u64 f = 0;
+        if (head) {
+            double s = 0.0;
+            u64 k = keys[i];
+            for (u64 j = i; j < n && keys[j] == k; ++j) s += vals[j];
+            seg[i] = s;
+            f = (s != 0.0) ? 1 : 0;
+        }
+        flag[i] = f;
+    }
+}
+
+// Scatter flagged heads to out[base + exclusive-prefix(flag)].
+__global__ void k_seg_write(const u64* __restrict__ keys, const double* __restrict__ seg, const u64* __restrict__ flag,
+                            const u64* __restrict__ pos, u64 n, u64 key_base, const u64* __restrict__ out_base,
+                            u64 out_cap, u64* __restrict__ out_r, double* __restrict__ out_a) {
+    const u64 ob = *out_base;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        if (flag[i]) {
+            u64 at = ob + pos[i];
+            if (at < out_cap) {
+                out_r[at] = keys[i] + key_base;
+                out_a[at] = seg[i];
+            }
+        }
+    }
+}
+
+__global__ void k_add_scalar(u64* __restrict__ acc, const u64* __restrict__ add) {
+    if (threadIdx.x == 0) *acc += *add;
+}
+
+__global__ void k_set_scalar(u64* __restrict__ dst, const u64* __restrict__ src) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+unsigned g1(u64 n, u64 per = 256) {
+    u64 g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+int bits_for(u64 maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) ++b;
+    return b;
+}
+
+}  // namespace
+
+void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_rank, double* out_amp,
+                  u64* out_count_dev, u64* emitted_dev) {
+    const u64 cap_src = v.cap > 0 ? v.cap : 1;
+    u64* counts = (u64*)P->ws_src_cnt.get(cap_src * sizeof(u64));
+    u64* offs = (u64*)P->ws_src_off.get(cap_src * sizeof(u64));
+    u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));  // [0] pass total, [1] out running count
+    launch_fill_u64(scal, 8, 0, P->stream);
+    launch_fill_u64(counts, cap_src, 0, P->stream);
+
+    // Tuple buffer: sized to the whole job if it fits a quarter of free memory.
+    size_t freeb = 0, totb = 0;
+    SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+    u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + 2 * sizeof(u64);
+    u64 tup_cap = (u64)(freeb / 4) / per_tuple;
+    if (tup_cap < (1u << 20)) tup_cap = 1u << 20;
+
+    std::vector<std::pair<u64, u64>> todo;
+    todo.push_back({0, P->Na});
+    u64 emitted_total = 0;
+    while (!todo.empty()) {
+        auto [lo, hi] = todo.front();
+        todo.erase(todo.begin());
+        launch_sigma_count(P, v, lo, hi, counts);
+        exclusive_scan_u64(P, counts, offs, cap_src, &scal[0]);
+        u64 total = 0;
+        SFCI_CHECK_HIP(hipMemcpyAsync(&total, &scal[0], sizeof(u64), hipMemcpyDeviceToHost, P->stream));
+        SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+        if (total > tup_cap) {
+            if (hi - lo <= 1) throw sfci_error(-5, "sort path: one alpha row exceeds the tuple buffer");
+            u64 mid = lo + (hi - lo) / 2;
+            todo.insert(todo.begin(), {mid, hi});
+            todo.insert(todo.begin(), {lo, mid});
+            continue;
+        }
+        emitted_total += total;
+        if (total == 0) continue;
+        u64* k1 = (u64*)P->ws_tup_k.get(total * sizeof(u64));
+        double* v1 = (double*)P->ws_tup_v.get(total * sizeof(double));
+        u64* k2 = (u64*)P->ws_tup_k2.get(total * sizeof(u64));
+        double* v2 = (double*)P->ws_tup_v2.get(total * sizeof(double));
+        const u64 key_base = lo * P->Nb;
+        launch_sigma_emit(P, v, lo, hi, offs, key_base, k1, v1);
+        // stable LSD radix sort on the pass-local key
+        const int kbits = bits_for((hi - lo) * P->Nb - 1);
+        const u64 nblk = (total + RS_TILE - 1) / RS_TILE;
+        u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
+        for (int shift = 0; shift < kbits; shift += RS_BITS) {
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, total, shift, hist,
+                               nblk);
+            exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
+            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, total, shift,
+                               hist, nblk, k2, v2);
+            std::swap(k1, k2);
+            std::swap(v1, v2);
+        }
+        // in-order segmented sum and compaction of nonzero results
+        double* seg = (double*)P->ws_seg_v.get(total * sizeof(double));
+        u64* flag = (u64*)P->ws_seg_f.get(total * sizeof(u64));
+        hipLaunchKernelGGL(k_seg_sum, dim3(g1(total)), dim3(256), 0, P->stream, k1, v1, total, seg, flag);
+        u64* pos = (u64*)P->ws_scan2.get(total * sizeof(u64));
+        exclusive_scan_u64(P, flag, pos, total, &scal[2]);
+        hipLaunchKernelGGL(k_seg_write, dim3(g1(total)), dim3(256), 0, P->stream, k1, seg, flag, pos, total, key_base,
+                           &scal[1], out_cap, out_rank, out_amp);
+        hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, &scal[1], &scal[2]);
+        SFCI_CHECK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, P->stream, out_count_dev, &scal[1]);
+    if (emitted_dev) {
+        SFCI_CHECK_HIP(hipMemcpyAsync(&scal[3], &emitted_total, sizeof(u64), hipMemcpyHostToDevice, P->stream));
+        hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, emitted_dev, &scal[3]);
+    }
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+}

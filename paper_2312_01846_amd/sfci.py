@@ -1,0 +1,258 @@
+"""Python binding of libsfci (ctypes).  Argument marshalling only: every step
+of sigma = H v, truncation and the SFCI iteration runs in the HIP kernels of
+``libsfci.so``.  PyTorch provides device memory and the stream.
+
+If the library is missing or the GPU is absent, calls raise -- there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfci.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sfci.h")
+
+UINT64_MAX = (1 << 64) - 1
+
+SFCI_OK = 0
+STATUS = {0: "SFCI_OK", -1: "SFCI_E_ARG", -2: "SFCI_E_RANGE", -3: "SFCI_E_DUP", -4: "SFCI_E_CAPACITY",
+          -5: "SFCI_E_NOMEM", -6: "SFCI_E_DEVICE", -7: "SFCI_E_NOTSYM", -8: "SFCI_E_UNSUPPORTED"}
+DEDUP = {"auto": 0, "dense": 1, "sort": 2}
+
+
+class SfciError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Space(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("n_alpha", C.c_int32), ("n_beta", C.c_int32)]
+
+
+class SVec(C.Structure):
+    _fields_ = [("rank", C.c_void_p), ("amp", C.c_void_p), ("nnz", C.c_uint64), ("capacity", C.c_uint64)]
+
+
+class SigmaOpts(C.Structure):
+    _fields_ = [("M", C.c_uint64), ("dedup", C.c_int32), ("deterministic", C.c_int32)]
+
+
+class SigmaStats(C.Structure):
+    _fields_ = [("terms_enumerated", C.c_uint64), ("terms_emitted", C.c_uint64), ("candidates", C.c_uint64),
+                ("ms", C.c_double)]
+
+
+class LanczosOpts(C.Structure):
+    _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
+                ("dedup", C.c_int32)]
+
+
+class LanczosStats(C.Structure):
+    _fields_ = [("sigma_calls", C.c_uint64), ("terms_enumerated", C.c_uint64), ("terms_emitted", C.c_uint64),
+                ("sigma_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+_lib = None
+
+# Every function the header declares, with its ctypes signature.
+_SIGS = {
+    "sfci_space_size": (C.c_int, [C.POINTER(Space), C.POINTER(C.c_uint64)]),
+    "sfci_problem_create": (C.c_int, [C.POINTER(Space), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "sfci_problem_destroy": (C.c_int, [C.c_void_p]),
+    "sfci_rank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
+    "sfci_unrank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
+    "sfci_sigma": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SigmaOpts), C.POINTER(SVec),
+                             C.POINTER(SigmaStats)]),
+    "sfci_topm": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_uint64, C.c_int32, C.POINTER(SVec)]),
+    "sfci_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(LanczosOpts), C.c_void_p, C.POINTER(SVec),
+                               C.c_void_p, C.c_void_p, C.POINTER(LanczosStats)]),
+    "sfci_sigma_backward": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SVec), C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    "sfci_last_error": (C.c_char_p, []),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsfci.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2312_01846_amd.build`")
+        L = C.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SFCI_OK:
+        msg = load_library().sfci_last_error().decode(errors="replace")
+        raise SfciError(rc, msg)
+
+
+def space_size(n, na, nb) -> int:
+    out = C.c_uint64(0)
+    _check(load_library().sfci_space_size(C.byref(Space(n, na, nb)), C.byref(out)))
+    return int(out.value)
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libsfci needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _svec(ranks, amps, capacity=None):
+    n = int(ranks.numel())
+    return SVec(ranks.data_ptr() if n or capacity else None, amps.data_ptr() if n or capacity else None, n,
+                int(capacity if capacity is not None else n))
+
+
+class Problem:
+    """A (space, integrals) instance on the current GPU; integrals are host numpy arrays."""
+
+    def __init__(self, n, na, nb, h, g, stream=None):
+        torch = _torch()
+        self.n, self.na, self.nb = int(n), int(na), int(nb)
+        self.h = np.ascontiguousarray(h, dtype=np.float64).reshape(self.n, self.n)
+        self.g = np.ascontiguousarray(g, dtype=np.float64).reshape(self.n, self.n, self.n, self.n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n_det = space_size(self.n, self.na, self.nb)
+        self.tps = terms_per_source(self.n, self.na, self.nb)
+        handle = C.c_void_p(None)
+        _check(load_library().sfci_problem_create(C.byref(Space(self.n, self.na, self.nb)),
+                                                  self.h.ctypes.data_as(C.c_void_p), self.g.ctypes.data_as(C.c_void_p),
+                                                  C.c_void_p(self.stream.cuda_stream), C.byref(handle)))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sfci_problem_destroy(self._h)
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- Eq. 12 ----------------------------------------------------------------
+    def rank(self, a_bits, b_bits):
+        torch = _torch()
+        a = torch.as_tensor(np.asarray(a_bits, dtype=np.int64), device="cuda")
+        b = torch.as_tensor(np.asarray(b_bits, dtype=np.int64), device="cuda")
+        out = torch.empty_like(a)
+        _check(load_library().sfci_rank(self._h, a.data_ptr(), b.data_ptr(), a.numel(), out.data_ptr()))
+        return out
+
+    def unrank(self, ranks):
+        torch = _torch()
+        r = torch.as_tensor(ranks, device="cuda").to(torch.int64)
+        a = torch.empty_like(r)
+        b = torch.empty_like(r)
+        _check(load_library().sfci_unrank(self._h, r.data_ptr(), r.numel(), a.data_ptr(), b.data_ptr()))
+        return a, b
+
+    # -- sigma = H v, truncated ----------------------------------------------------
+    def sigma(self, ranks, amps, M=None, dedup="auto", deterministic=False, capacity=None):
+        """Returns (ranks int64, amps float64, stats dict) on the GPU."""
+        torch = _torch()
+        r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
+        a = torch.as_tensor(amps, device="cuda").to(torch.float64).contiguous()
+        Mv = UINT64_MAX if M is None else int(M)
+        cap = capacity
+        if cap is None:
+            cap = min(self.n_det, max(1, r.numel()) * self.tps)
+            if M is not None:
+                cap = min(cap, int(M))
+        opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0)
+        for _ in range(2):
+            o_r = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+            o_a = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+            out = SVec(o_r.data_ptr(), o_a.data_ptr(), 0, cap)
+            st = SigmaStats()
+            rc = load_library().sfci_sigma(self._h, C.byref(_svec(r, a)), C.byref(opts), C.byref(out), C.byref(st))
+            if rc == -4:
+                cap = int(out.nnz)
+                continue
+            _check(rc)
+            k = int(out.nnz)
+            stats = dict(terms_enumerated=st.terms_enumerated, terms_emitted=st.terms_emitted,
+                         candidates=st.candidates, ms=st.ms)
+            return o_r[:k], o_a[:k], stats
+        raise SfciError(-4, "capacity retry failed")
+
+    def topm(self, ranks, amps, M, normalise=False):
+        torch = _torch()
+        r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
+        a = torch.as_tensor(amps, device="cuda").to(torch.float64).contiguous()
+        cap = max(1, r.numel())
+        o_r = torch.empty(cap, dtype=torch.int64, device="cuda")
+        o_a = torch.empty(cap, dtype=torch.float64, device="cuda")
+        out = SVec(o_r.data_ptr(), o_a.data_ptr(), 0, cap)
+        Mv = UINT64_MAX if M is None else int(M)
+        _check(load_library().sfci_topm(self._h, C.byref(_svec(r, a)), Mv, 1 if normalise else 0, C.byref(out)))
+        k = int(out.nnz)
+        return o_r[:k], o_a[:k]
+
+    # -- the SFCI iteration ----------------------------------------------------
+    def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
+                want_psi=True, psi_capacity=None):
+        torch = _torch()
+        r = torch.as_tensor(ranks0, device="cuda").to(torch.int64).contiguous()
+        a = torch.as_tensor(amps0, device="cuda").to(torch.float64).contiguous()
+        nblk = n_iter // n_L
+        energies = np.zeros(nblk, dtype=np.float64)
+        T = np.zeros(nblk * n_L * n_L) if want_T else None
+        S = np.zeros(nblk * n_L * n_L) if want_T else None
+        Mv = UINT64_MAX if M is None else int(M)
+        opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup])
+        st = LanczosStats()
+        psi = None
+        if want_psi:
+            cap = psi_capacity or min(self.n_det, n_L * (Mv if M is not None else self.n_det))
+            p_r = torch.empty(cap, dtype=torch.int64, device="cuda")
+            p_a = torch.empty(cap, dtype=torch.float64, device="cuda")
+            psi = SVec(p_r.data_ptr(), p_a.data_ptr(), 0, cap)
+        rc = load_library().sfci_lanczos(self._h, C.byref(_svec(r, a)), C.byref(opts),
+                                         energies.ctypes.data_as(C.c_void_p), C.byref(psi) if psi else None,
+                                         T.ctypes.data_as(C.c_void_p) if want_T else None,
+                                         S.ctypes.data_as(C.c_void_p) if want_T else None, C.byref(st))
+        _check(rc)
+        out = dict(energies=energies, stats=dict(sigma_calls=st.sigma_calls, terms_enumerated=st.terms_enumerated,
+                                                 terms_emitted=st.terms_emitted, sigma_ms=st.sigma_ms,
+                                                 total_ms=st.total_ms))
+        if want_psi:
+            k = int(psi.nnz)
+            out["psi_rank"] = p_r[:k]
+            out["psi_amp"] = p_a[:k]
+        if want_T:
+            out["T"] = T.reshape(nblk, n_L, n_L)
+            out["S"] = S.reshape(nblk, n_L, n_L)
+        return out
+
+
+def terms_per_source(n, na, nb):
+    """(source, excitation) pairs per source: 1 + singles + doubles of both spins."""
+    sa, sb = na * (n - na), nb * (n - nb)
+    pa, qa = na * (na - 1) // 2, (n - na) * (n - na - 1) // 2
+    pb, qb = nb * (nb - 1) // 2, (n - nb) * (n - nb - 1) // 2
+    return 1 + sa + sb + pa * qa + pb * qb + sa * sb
+
+
+def declared_symbols(header: str = HEADER):
+    """Function names declared in include/sfci.h."""
+    import re
+
+    text = open(header).read()
+    return sorted(set(re.findall(r"\b(sfci_[a-z_]+)\s*\(", text)))
