@@ -72,6 +72,9 @@ __global__ void k_validate(const u64* __restrict__ r, u64 n, u64 ndet, int* __re
     }
 }
 
+// The fast-mode reductions keep their partial sums at the front of ws_red.
+constexpr u64 RAW_PAD = 2048;
+
 __global__ void k_set_u64(u64* p, u64 v) {
     if (threadIdx.x == 0) *p = v;
 }
@@ -539,8 +542,27 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
 
 sfci_status sfci_sigma_backward(sfci_problem* P, const sfci_svec* v, const sfci_svec* sbar, double* v_bar, double* dh,
                                 double* deri) {
-    (void)P; (void)v; (void)sbar; (void)v_bar; (void)dh; (void)deri;
-    return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "backward not built yet");
+    SFCI_GUARD_BEGIN
+    if (!P || !v || !sbar) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
+    if ((v->nnz && (!v->rank || !v->amp)) || (sbar->nnz && (!sbar->rank || !sbar->amp)))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL input arrays");
+    validate_vec(P, v->rank, v->nnz);
+    validate_vec(P, sbar->rank, sbar->nnz);
+    if (!ensure_dense(P))
+        return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "backward needs the dense array (N_det doubles)");
+    const int n = P->n;
+    const u64 n2 = (u64)n * n, n4 = n2 * n2;
+    u64* scal = (u64*)P->ws_lz[0].get(8 * sizeof(u64));
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, scal, (u64)v->nnz);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, scal + 1, (u64)sbar->nnz);
+    double* raw = (double*)P->ws_red.get((RAW_PAD + n2 + n4) * sizeof(double));
+    launch_scatter_set(P, P->d_D, sbar->rank, sbar->amp, scal + 1, std::max<u64>(1, sbar->nnz));
+    SigmaLaunch sl{v->rank, v->amp, scal, v->nnz};
+    launch_backward_dense(P, sl, P->d_D, v_bar, dh, deri, raw + RAW_PAD, raw + RAW_PAD + n2);
+    launch_scatter_zero(P, P->d_D, sbar->rank, scal + 1, std::max<u64>(1, sbar->nnz));
+    sync(P);
+    return SFCI_OK;
+    SFCI_GUARD_END
 }
 
 }  // extern "C"

@@ -159,6 +159,15 @@ struct AlphaRange {
     __device__ __forceinline__ bool in(u64 ra) const { return ra >= lo && ra < hi; }
 };
 
+// What a sink is told about each term besides target and element: the class
+// (0 diagonal, 1 alpha single, 2 beta single, 3 alpha-alpha double, 4
+// beta-beta double, 5 alpha-beta double), the orbitals (i->a, j->b; for a beta
+// single the orbitals are in i, a), the phase parity and the source strings.
+struct Term {
+    int cls, i, a, j, b, par;
+    u32 A, Bs;
+};
+
 // Number of (source, excitation) pairs visited per source.
 __host__ __device__ inline u64 terms_per_source(int n, int na, int nb) {
     u64 sa = (u64)na * (n - na), sb = (u64)nb * (n - nb);
@@ -168,9 +177,10 @@ __host__ __device__ inline u64 terms_per_source(int n, int na, int nb) {
 }
 
 // Walk every connected determinant of the source (R, c).  All 64 lanes of the
-// wave must call this together with the same arguments.  sink(ok, target, e, c)
-// is called wave-uniformly; ok is false for padding lanes and zero elements.
-template <bool FILTER, class Sink>
+// wave must call this together with the same arguments.  sink(ok, target, e,
+// c, term) is called wave-uniformly; ok is false for padding lanes and, unless
+// ALL is set, for elements that are exactly zero.
+template <bool FILTER, class Sink, bool ALL = false>
 __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomLds& B, WaveLds& W, u64 R,
                                  double c, const AlphaRange& rng, Sink& sink) {
     const int lane = lane_id();
@@ -221,9 +231,9 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
         double e = 0.0;
         if (lane == 0 && keepA) {
             e = diag_element(I, A, Bs);
-            ok = (e != 0.0);
+            ok = ALL || (e != 0.0);
         }
-        sink(ok, R, e, c);
+        sink(ok, R, e, c, Term{0, 0, 0, 0, 0, 0, A, Bs});
     }
     // (b) alpha singles, beta unchanged
     for (int t0 = 0; t0 < sA; t0 += 64) {
@@ -231,18 +241,20 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
         bool ok = false;
         double e = 0.0;
         u64 tgt = 0;
+        Term tm{1, 0, 0, 0, 0, 0, A, Bs};
         if (t < sA) {
             u64 rnb = W.aRankNb[t];
             u32 info = W.aInfo[t];
             if (!FILTER || rng.in(rnb / Nb)) {
                 int i = info & 255, a = (info >> 8) & 255;
                 e = single_element_nophase(I, A, Bs, i, a);
-                if ((info >> 16) & 1u) e = -e;
+                tm.i = i; tm.a = a; tm.par = (info >> 16) & 1;
+                if (tm.par) e = -e;
                 tgt = rnb + rB;
-                ok = (e != 0.0);
+                ok = ALL || (e != 0.0);
             }
         }
-        sink(ok, tgt, e, c);
+        sink(ok, tgt, e, c, tm);
     }
     // (c) beta singles, alpha unchanged
     for (int t0 = 0; t0 < sB; t0 += 64) {
@@ -250,15 +262,17 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
         bool ok = false;
         double e = 0.0;
         u64 tgt = 0;
+        Term tm{2, 0, 0, 0, 0, 0, A, Bs};
         if (t < sB && keepA) {
             u32 info = W.bInfo[t];
             int j = info & 255, b = (info >> 8) & 255;
             e = single_element_nophase(I, Bs, A, j, b);
-            if ((info >> 16) & 1u) e = -e;
+            tm.i = j; tm.a = b; tm.par = (info >> 16) & 1;
+            if (tm.par) e = -e;
             tgt = baseA + W.bRank[t];
-            ok = (e != 0.0);
+            ok = ALL || (e != 0.0);
         }
-        sink(ok, tgt, e, c);
+        sink(ok, tgt, e, c, tm);
     }
     // (d) alpha-alpha doubles: (i<j) x (a<b), pairing i->a, j->b
     {
@@ -270,6 +284,7 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
             bool ok = false;
             double e = 0.0;
             u64 tgt = 0;
+            Term tm{3, 0, 0, 0, 0, 0, A, Bs};
             if (t < tot) {
                 u32 po = W.pairOA[q], pv = W.pairVA[r];
                 int i = W.occA[po & 255], j = W.occA[po >> 8];
@@ -282,10 +297,11 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
                     e = (I.G(i, a, j, b) - I.G(i, b, j, a));
                     if (par) e = -e;
                     tgt = ra * Nb + rB;
-                    ok = (e != 0.0);
+                    ok = ALL || (e != 0.0);
+                    tm = Term{3, i, a, j, b, par, A, Bs};
                 }
             }
-            sink(ok, tgt, e, c);
+            sink(ok, tgt, e, c, tm);
             r += dr; q += dq;
             if (r >= QA) { r -= QA; q += 1; }
         }
@@ -300,6 +316,7 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
             bool ok = false;
             double e = 0.0;
             u64 tgt = 0;
+            Term tm{4, 0, 0, 0, 0, 0, A, Bs};
             if (t < tot && keepA) {
                 u32 po = W.pairOB[q], pv = W.pairVB[r];
                 int i = W.occB[po & 255], j = W.occB[po >> 8];
@@ -310,9 +327,10 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
                 e = (I.G(i, a, j, b) - I.G(i, b, j, a));
                 if (par) e = -e;
                 tgt = baseA + str_rank(B2, B);
-                ok = (e != 0.0);
+                ok = ALL || (e != 0.0);
+                tm = Term{4, i, a, j, b, par, A, Bs};
             }
-            sink(ok, tgt, e, c);
+            sink(ok, tgt, e, c, tm);
             r += dr; q += dq;
             if (r >= QB) { r -= QB; q += 1; }
         }
@@ -327,6 +345,7 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
             bool ok = false;
             double e = 0.0;
             u64 tgt = 0;
+            Term tm{5, 0, 0, 0, 0, 0, A, Bs};
             if (t < tot) {
                 u64 rnb = W.aRankNb[q];
                 if (!FILTER || rng.in(rnb / Nb)) {
@@ -334,12 +353,14 @@ __device__ void enumerate_source(const SpaceDev& sp, const Ints& I, const BinomL
                     int i = ai & 255, a = (ai >> 8) & 255;
                     int j = bi & 255, b = (bi >> 8) & 255;
                     e = I.G(i, a, j, b);
-                    if (((ai ^ bi) >> 16) & 1u) e = -e;
+                    int par = ((ai ^ bi) >> 16) & 1u;
+                    if (par) e = -e;
                     tgt = rnb + W.bRank[r];
-                    ok = (e != 0.0);
+                    ok = ALL || (e != 0.0);
+                    tm.i = i; tm.a = a; tm.j = j; tm.b = b; tm.par = par;
                 }
             }
-            sink(ok, tgt, e, c);
+            sink(ok, tgt, e, c, tm);
             r += dr; q += dq;
             if (r >= sB) { r -= sB; q += 1; }
         }

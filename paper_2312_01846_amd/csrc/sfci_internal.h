@@ -80,8 +80,11 @@ void launch_sigma_emit(sfci_problem* P, const SigmaLaunch& v, u64 alo, u64 ahi, 
                        u64* keys, double* vals);
 void launch_rank(sfci_problem* P, const u64* a, const u64* b, u64 cnt, u64* rank, int* bad);
 void launch_unrank(sfci_problem* P, const u64* rank, u64 cnt, u64* a, u64* b, int* bad);
-void launch_backward(sfci_problem* P, const SigmaLaunch& v, const double* sbar_dense, double* vbar, double* dh_raw,
-                     double* dg_raw);
+// Backward of sigma = H v (backward.hip).  The cotangent must already be
+// scattered into the zero dense array D.  Rh (n^2) and Rg (n^4) are scratch.
+void launch_backward_dense(sfci_problem* P, const SigmaLaunch& v, const double* D, double* vbar, double* dh, double* dg,
+                           double* Rh, double* Rg);
+void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nnz, u64 cap);
 
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);

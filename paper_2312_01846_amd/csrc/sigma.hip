@@ -18,7 +18,7 @@ struct SigmaParams {
 struct SinkDense {
     double* D;
     u64 cnt;
-    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c) {
+    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c, const Term&) {
         if (ok) {
             unsafeAtomicAdd(D + tgt, e * c);
             ++cnt;
@@ -28,7 +28,7 @@ struct SinkDense {
 
 struct SinkCount {
     u64 cnt;
-    __device__ __forceinline__ void operator()(bool ok, u64, double, double) { cnt += ok ? 1 : 0; }
+    __device__ __forceinline__ void operator()(bool ok, u64, double, double, const Term&) { cnt += ok ? 1 : 0; }
 };
 
 // Tuple emission at deterministic positions: within one source, lanes write
@@ -38,7 +38,7 @@ struct SinkEmit {
     double* vals;
     u64 pos;       // next slot of this source (wave-uniform)
     u64 key_base;  // subtracted from the rank to form the sort key
-    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c) {
+    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c, const Term&) {
         u64 m = __ballot(ok);
         if (ok) {
             u64 below = m & ((1ull << lane_id()) - 1ull);

@@ -205,6 +205,33 @@ class Problem:
         k = int(out.nnz)
         return o_r[:k], o_a[:k]
 
+    # -- backward of sigma = H(h, g) v -----------------------------------------------
+    def sigma_backward(self, v_rank, v_amp, s_rank, s_amp, want_vbar=True, want_dh=True, want_dg=True):
+        """vbar = H sbar on supp(v); dh, dg = gradients of sbar^T H v along symmetric perturbations."""
+        torch = _torch()
+        vr = torch.as_tensor(v_rank, device="cuda").to(torch.int64).contiguous()
+        va = torch.as_tensor(v_amp, device="cuda").to(torch.float64).contiguous()
+        sr = torch.as_tensor(s_rank, device="cuda").to(torch.int64).contiguous()
+        sa = torch.as_tensor(s_amp, device="cuda").to(torch.float64).contiguous()
+        n = self.n
+        vbar = torch.empty(max(1, vr.numel()), dtype=torch.float64, device="cuda") if want_vbar else None
+        dh = torch.empty((n, n), dtype=torch.float64, device="cuda") if want_dh else None
+        dg = torch.empty((n, n, n, n), dtype=torch.float64, device="cuda") if want_dg else None
+        _check(load_library().sfci_sigma_backward(self._h, C.byref(_svec(vr, va)), C.byref(_svec(sr, sa)),
+                                                  vbar.data_ptr() if vbar is not None else None,
+                                                  dh.data_ptr() if dh is not None else None,
+                                                  dg.data_ptr() if dg is not None else None))
+        return (vbar[:vr.numel()] if vbar is not None else None), dh, dg
+
+    def energy_gradients(self, psi_rank, psi_amp):
+        """E = <psi|H|psi>/<psi|psi> and its gradients dE/dh, dE/d(pq|rs) at fixed psi
+        (Hellmann-Feynman form): one backward call with sbar = psi/<psi|psi>."""
+        torch = _torch()
+        pa = torch.as_tensor(psi_amp, device="cuda").to(torch.float64)
+        nrm2 = torch.dot(pa, pa)
+        vbar, dh, dg = self.sigma_backward(psi_rank, pa, psi_rank, pa / nrm2)
+        return float(torch.dot(pa, vbar)), dh, dg
+
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
                 want_psi=True, psi_capacity=None):

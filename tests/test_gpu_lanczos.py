@@ -110,11 +110,33 @@ def test_c2_shape_golden(torch, S, name, det):
         assert out["energies"].tolist() == gd["energies"]
 
 
+def test_c1_full_config_deterministic(torch, S):
+    # The 12-site Hubbard workload itself: U = 4, M = 1e5, 60 sigma applications.
+    gd = _gold("c1_U4_M1e5_60")
+    h, g = synth.hubbard_ring(12, 1.0, 4.0)
+    P = S.Problem(12, 6, 6, h, g)
+    a, b = synth.neel_bits(12)
+    r0 = P.rank([a], [b]).cpu().numpy()
+    out = P.lanczos(r0, np.array([1.0]), M=100_000, n_L=10, n_iter=60, deterministic=True)
+    assert out["energies"].tolist() == gd["energies"]
+    assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
+
+
 @pytest.mark.parametrize("name", ["c4_inst31_M3e3_30", "c4_inst0_M1e4_30"])
-def test_c4_instance_golden(torch, S, name):
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_c4_instance_golden(torch, S, name, det):
     gd = _gold(name)
     j = int(name.split("_")[1].replace("inst", ""))
     lam, h, g = synth.bond_stretch_batch(20, 32, 40)[j]
     P = S.Problem(20, 4, 4, h, g)
-    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"])
-    assert np.all(np.abs(out["energies"] - np.array(gd["energies"])) < 1e-9)
+    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"],
+                    deterministic=det)
+    dE = np.abs(out["energies"] - np.array(gd["energies"]))
+    if det:
+        assert out["energies"].tolist() == gd["energies"]
+        assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
+    else:
+        # Closed-shell start with n_alpha = n_beta: spin-flip partners tie exactly,
+        # and FP64-atomic accumulation order decides which partner survives the
+        # truncation.  Both trajectories are valid; they stay close, not equal.
+        assert np.all(dE < 5e-3), dE
