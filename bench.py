@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--n_L", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
+                    help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
     return ap.parse_args()
 
 
@@ -102,16 +104,13 @@ def main():
     print(f"# building a start vector: {args.warmup} warm-up iterations at M={M}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     warm = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=M, n_L=args.n_L, n_iter=args.warmup,
-                     psi_capacity=min(P.n_det, args.n_L * M))
+                     psi_capacity=min(P.n_det, args.n_L * M), dedup=args.dedup)
     v_r, v_a = P.topm(warm["psi_rank"], warm["psi_amp"], M, normalise=True)
     torch.cuda.synchronize()
     print(f"# warm-up done in {time.perf_counter() - t0:.1f} s; start vector nnz={v_r.numel()}", file=sys.stderr,
           flush=True)
-    # one more untimed pass at full size (allocations, caches)
-    P.lanczos(v_r, v_a, M=M, n_L=args.n_L, n_iter=args.n_L, want_psi=False)
-    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    out = P.lanczos(v_r, v_a, M=M, n_L=args.n_L, n_iter=args.steps, want_psi=False)
+    out = P.lanczos(v_r, v_a, M=M, n_L=args.n_L, n_iter=args.steps, want_psi=False, dedup=args.dedup)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t1
     st = out["stats"]
@@ -144,7 +143,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {wl['desc']}, M={M}, N_L={args.n_L}, dense FP64-atomic dedup",
+            "workload": f"{args.workload}: {wl['desc']}, M={M}, N_L={args.n_L}, dedup={args.dedup}",
             "M": M,
             "n_L": args.n_L,
             "terms_per_step": terms / args.steps,
@@ -153,7 +152,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sigma_dense",
+            "kernel": "k_sigma_rowtile" if args.dedup == "dense" else "k_sigma_dense",
             "achieved": achieved / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",

@@ -1,6 +1,7 @@
 // C ABI of libsfci: problem lifecycle, sigma, truncation and the SFCI
 // iteration driver (Sec. 2.1).  All device work goes to the problem's stream.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -129,6 +130,15 @@ bool ensure_dense(sfci_problem* P) {
     return P->dense_state == 1;
 }
 
+// Dense-mode sigma into P->d_D: the target-owned tile kernel unless the
+// caller asks for the one-atomic-per-term kernel (or the tiles do not fit).
+void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted) {
+    if (dedup != SFCI_DEDUP_DENSE_ATOMIC && rowtile_available(P))
+        launch_sigma_rowtile(P, sl, P->d_D, emitted);
+    else
+        launch_sigma_dense(P, sl, P->d_D, emitted);
+}
+
 // Device-resident sparse vector with a device nnz (Lanczos basis storage).
 struct DVec {
     u64* r = nullptr;
@@ -248,11 +258,15 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     if (P->d_g) (void)hipFree(P->d_g);
     if (P->d_binom) (void)hipFree(P->d_binom);
     if (P->d_D) (void)hipFree(P->d_D);
+    rowtile_release(P);
     DevBuf* bufs[] = {&P->ws_sel,   &P->ws_cnt,   &P->ws_scan,  &P->ws_scan2,  &P->ws_scalar, &P->ws_red,
                       &P->ws_tup_k, &P->ws_tup_v, &P->ws_tup_k2, &P->ws_tup_v2, &P->ws_seg_v, &P->ws_seg_f,
                       &P->ws_src_cnt, &P->ws_src_off, &P->ws_hist, &P->ws_list_r, &P->ws_list_a};
     for (DevBuf* b : bufs) b->release();
     for (auto& b : P->ws_lz) b.release();
+    P->ws_rt_rows.release();
+    P->ws_rt_beta.release();
+    P->ws_rt_nbr.release();
     delete P;
     return SFCI_OK;
 }
@@ -290,7 +304,7 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     SFCI_GUARD_BEGIN
     if (!P || !v || !opts || !out) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
     if (v->nnz && (!v->rank || !v->amp)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL input arrays");
-    if (opts->dedup < 0 || opts->dedup > 2) return (sfci_status)sfci_set_error(SFCI_E_ARG, "bad dedup mode");
+    if (opts->dedup < 0 || opts->dedup > 3) return (sfci_status)sfci_set_error(SFCI_E_ARG, "bad dedup mode");
     validate_vec(P, v->rank, v->nnz);
     hipEvent_t e0, e1;
     SFCI_CHECK_HIP(hipEventCreate(&e0));
@@ -303,13 +317,13 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     const u64 tps = terms_per_source(P->n, P->na, P->nb);
     bool use_sort = opts->deterministic || opts->dedup == SFCI_DEDUP_SORT;
     if (!use_sort && !ensure_dense(P)) {
-        if (opts->dedup == SFCI_DEDUP_DENSE)
+        if (opts->dedup == SFCI_DEDUP_DENSE || opts->dedup == SFCI_DEDUP_DENSE_ATOMIC)
             return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "dense accumulator does not fit on the device");
         use_sort = true;
     }
     CandSrc src{};
     if (!use_sort) {
-        launch_sigma_dense(P, sl, P->d_D, (unsigned long long*)&scal[1]);
+        dense_sigma(P, sl, opts->dedup, (unsigned long long*)&scal[1]);
         src.dense = P->d_D;
     } else {
         u64 lcap = std::min<u64>(P->Ndet, std::max<u64>(1, v->nnz) * tps);
@@ -453,7 +467,7 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
                 tsig.end(P->stream);
                 launch_scatter_set(P, P->d_D, lr, la, sc + 33, lcap);
             } else {
-                launch_sigma_dense(P, sl, P->d_D, (unsigned long long*)(sc + 32));
+                dense_sigma(P, sl, o->dedup, (unsigned long long*)(sc + 32));
                 tsig.end(P->stream);
             }
             ++sigma_calls;

@@ -1,0 +1,627 @@
+// sigma = H v, dense mode, target-owned: one workgroup owns a tile of one
+// target alpha row (a contiguous rank range) in LDS and pulls every term that
+// lands in it, so no term goes through a global atomic.
+//
+// For a target alpha string A' the contributing source rows are A' itself,
+// its single and its double alpha excitations (Sec. 3: H couples determinants
+// up to double excitations).  With the alpha-major rank, a source row is a
+// contiguous slice of the sorted input vector, found through per-alpha-rank
+// row pointers.  Per source row and tile:
+//   * alpha double:   target (A', beta), one term per entry, element constant;
+//   * alpha single:   target (A', beta) plus (A', beta') for the beta singles
+//                     of each entry -- the alpha-beta doubles, most of the work;
+//   * identity:       diagonal, beta singles, beta-beta doubles of each entry.
+// The beta singles of every beta string are tabulated once per problem,
+// sorted by target rank with per-tile offsets, so a tile visits exactly the
+// singles that land in it.  Elements and phases are the same expressions as in
+// the source-side enumeration (same integrals, same order of additions).
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "sfci_internal.h"
+
+namespace {
+
+constexpr int RT_WAVES = 16;
+constexpr int RT_BLOCK = 64 * RT_WAVES;
+
+struct RTParams {
+    SpaceDev sp;
+    Ints I;
+    const u64* binom;
+    const u64* v_rank;
+    const double* v_amp;
+    const u32* v_beta;     // beta string of every input entry
+    const u64* rowbeg;     // per alpha rank: first input entry of that row
+    const u64* rowend;     // per alpha rank: one past the last (== rowbeg when empty)
+    const u32* rtb;        // per alpha rank, ntiles + 1 entry offsets: first entry with beta rank >= tile_lo[t]
+    const u64* T1;         // beta singles per beta rank, sorted: rank | j << 32 | b << 40 | par << 48
+    const uint16_t* toff;  // per beta rank, ntiles + 1 offsets into its T1 slice
+    const u64* tile_lo;    // ntiles + 1 rank boundaries
+    int ntiles;
+    int sB;                // beta singles per string
+    double* D;
+    unsigned* counter;
+    u64 n_items;           // N_alpha * ntiles
+    void* nbr_scratch;     // per workgroup: the nonempty source rows of the current item
+    u64 nbr_cap;           // records per workgroup
+    unsigned long long* emitted;
+};
+
+// One contributing source row of the current (target row, tile).
+struct NbrRec {
+    u32 As;       // source alpha string
+    u32 rAs;      // its rank
+    u32 rowb, rowe;
+    u32 e0, e1;   // its entries whose beta lies in the tile
+    double cst;   // alpha double: the element; alpha single: its alpha part
+    uint8_t type, i, a, j, b, par, pad0, pad1;
+};
+
+struct WaveScratch {
+    unsigned incl[64];
+    unsigned excl[64];
+    unsigned start[64];
+    u32 beta[64];
+    double c[64];
+    uint8_t occ[32], vir[32];
+};
+
+// Direct target (beta unchanged) of entry k of source row r: alpha double
+// (constant element), alpha single (alpha part + beta part), or the diagonal.
+__device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec& r, u32 beta) {
+    if (r.type == 2) return r.cst;
+    if (r.type == 1) {
+        double e = r.cst;
+        for (u32 m = beta; m; m &= m - 1u) {
+            int q = __builtin_ctz(m);
+            e += p.I.G(r.i, r.a, q, q);
+        }
+        return r.par ? -e : e;
+    }
+    return diag_element(p.I, r.As, beta);
+}
+
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(RTParams p) {
+    extern __shared__ double acc[];
+    __shared__ BinomLds sB;
+    __shared__ WaveScratch sw[RT_WAVES];
+    __shared__ uint8_t occA[32], virA[32];
+    __shared__ uint16_t pairNA[SFCI_MAX_PAIRS], pairVA[SFCI_MAX_PAIRS], pairNB[SFCI_MAX_PAIRS], pairVB[SFCI_MAX_PAIRS];
+    __shared__ unsigned s_item, s_nbr, s_nlist, s_next, s_next2, s_touched;
+
+    const int n = p.sp.n, na = p.sp.na, nb = p.sp.nb;
+    const int nva = n - na, nvb = n - nb;
+    const u64 Nb = p.sp.Nb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    WaveScratch& W = sw[wave];
+    NbrRec* list = (NbrRec*)p.nbr_scratch + (u64)blockIdx.x * p.nbr_cap;
+
+    load_binom(sB, p.binom);
+    const int PA = na * (na - 1) / 2, QA = nva * (nva - 1) / 2;
+    const int PB = nb * (nb - 1) / 2, QB = nvb * (nvb - 1) / 2;
+    for (int t = threadIdx.x; t < PA; t += RT_BLOCK) pairNA[t] = decode_pair(t, na);
+    for (int t = threadIdx.x; t < QA; t += RT_BLOCK) pairVA[t] = decode_pair(t, nva);
+    for (int t = threadIdx.x; t < PB; t += RT_BLOCK) pairNB[t] = decode_pair(t, nb);
+    for (int t = threadIdx.x; t < QB; t += RT_BLOCK) pairVB[t] = decode_pair(t, nvb);
+    const int sA = na * nva, sBn = p.sB;
+    const u64 n_nbr = 1 + (u64)sA + (u64)PA * QA;
+    const bool whole_rows = (p.ntiles == 1);
+    u64 my_terms = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(p.counter, 1u);
+            s_nbr = 0;
+            s_nlist = 0;
+            s_next = 0;
+            s_next2 = 0;
+            s_touched = 0;
+        }
+        __syncthreads();
+        const u64 item = s_item;
+        if (item >= p.n_items) break;
+        const u64 rAt = item / (u64)p.ntiles;
+        const int tile = (int)(item - rAt * (u64)p.ntiles);
+        const u64 tlo = p.tile_lo[tile], thi = p.tile_lo[tile + 1];
+        const int tsz = (int)(thi - tlo);
+        const u32 At = str_unrank(rAt, na, n, sB);
+        if (threadIdx.x < (unsigned)n) {
+            int q = threadIdx.x;
+            u32 below = (1u << q) - 1u;
+            if ((At >> q) & 1u) occA[__popc(At & below)] = (uint8_t)q;
+            else virA[q - __popc(At & below)] = (uint8_t)q;
+        }
+        for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
+        __syncthreads();
+
+        // Phase 1: the nonempty source rows, with their entry range in this tile.
+        for (;;) {
+            unsigned base = 0;
+            if (lane == 0) base = atomicAdd(&s_nbr, 64u);
+            base = __shfl(base, 0);
+            if ((u64)base >= n_nbr) break;
+            const u64 idx = (u64)base + lane;
+            NbrRec r;
+            r.type = 255;
+            if (idx < n_nbr) {
+                int i = 0, a = 0, j = 0, b = 0, type;
+                u32 As;
+                if (idx == 0) {
+                    type = 0;
+                    As = At;
+                } else if (idx <= (u64)sA) {
+                    int s = (int)idx - 1;
+                    a = occA[s / nva];  // created in the target
+                    i = virA[s % nva];  // annihilated from the source
+                    As = At ^ (1u << a) ^ (1u << i);
+                    type = 1;
+                } else {
+                    u64 d = idx - 1 - sA;
+                    int po = (int)(d / (u64)QA), pv = (int)(d - (u64)po * QA);
+                    unsigned pa = pairNA[po], pvv = pairVA[pv];
+                    a = occA[pa & 255];
+                    b = occA[pa >> 8];
+                    i = virA[pvv & 255];
+                    j = virA[pvv >> 8];
+                    As = At ^ (1u << a) ^ (1u << b) ^ (1u << i) ^ (1u << j);
+                    type = 2;
+                }
+                const u64 rAs = str_rank(As, sB);
+                const u64 rb = p.rowbeg[rAs], re = p.rowend[rAs];
+                if (re > rb) {
+                    const u32* tb = p.rtb + rAs * (u64)(p.ntiles + 1);
+                    r.As = As; r.rAs = (u32)rAs; r.rowb = (u32)rb; r.rowe = (u32)re;
+                    r.e0 = tb[tile]; r.e1 = tb[tile + 1];
+                    r.i = (uint8_t)i; r.a = (uint8_t)a; r.j = (uint8_t)j; r.b = (uint8_t)b;
+                    r.type = (uint8_t)type;
+                    r.par = 0;
+                    r.cst = 0.0;
+                    if (type == 2) {
+                        // alpha double, source-occupied i<j -> source-virtual a<b (pairing i->a, j->b)
+                        const u32 mid = As ^ (1u << i) ^ (1u << a);
+                        const int par = between_parity(As, i, a) ^ between_parity(mid, j, b);
+                        double e = (p.I.G(i, a, j, b) - p.I.G(i, b, j, a));
+                        if (par) e = -e;
+                        r.cst = e;
+                        if (e == 0.0 || r.e1 <= r.e0) r.type = 255;
+                    } else if (type == 1) {
+                        double e = p.I.H(i, a);
+                        for (u32 m = As & ~(1u << i); m; m &= m - 1u) {
+                            int k = __builtin_ctz(m);
+                            e += (p.I.G(i, a, k, k) - p.I.G(i, k, k, a));
+                        }
+                        r.cst = e;
+                        r.par = (uint8_t)between_parity(As, i, a);
+                    }
+                }
+            }
+            const bool keep = r.type != 255;
+            const u64 m = __ballot(keep);
+            unsigned slot0 = 0;
+            if (lane == 0 && m) slot0 = atomicAdd(&s_nlist, (unsigned)__popcll(m));
+            slot0 = __shfl(slot0, 0);
+            if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
+        }
+        __syncthreads();
+        const unsigned nlist = s_nlist;
+        if (nlist == 0) continue;  // nothing lands here: D stays zero
+        if (threadIdx.x == 0) s_touched = 1;
+
+        // Phase 2: direct targets (beta unchanged).  Short ranges: one thread
+        // per source row; long ranges: one wavefront, lanes over the entries.
+        for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
+            const NbrRec r = list[li];
+            if (r.e1 - r.e0 > 32) continue;
+            const u64 baseS = (u64)r.rAs * Nb + tlo;
+            for (u32 k = r.e0; k < r.e1; ++k) {
+                const double e = direct_element(p, r, p.v_beta[k]);
+                if (e != 0.0) {
+                    atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                    ++my_terms;
+                }
+            }
+        }
+        for (;;) {
+            unsigned li = 0;
+            if (lane == 0) li = atomicAdd(&s_next2, 1u);
+            li = __shfl(li, 0);
+            if (li >= nlist) break;
+            const NbrRec r = list[li];
+            if (r.e1 - r.e0 <= 32) continue;
+            const u64 baseS = (u64)r.rAs * Nb + tlo;
+            for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
+                const double e = direct_element(p, r, p.v_beta[k]);
+                if (e != 0.0) {
+                    atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                    ++my_terms;
+                }
+            }
+        }
+
+        // Phase 3: beta singles of the identity and alpha-single source rows
+        // (the alpha-beta doubles), and the identity row's beta-beta doubles.
+        for (;;) {
+            unsigned li = 0;
+            if (lane == 0) li = atomicAdd(&s_next, 1u);
+            li = __shfl(li, 0);
+            if (li >= nlist) break;
+            const NbrRec r = list[li];
+            const int T = r.type;
+            if (T == 2) continue;
+            const int I_ = r.i, A_ = r.a;
+            const u32 S = r.As;
+            const u64 baseS = (u64)r.rAs * Nb;
+            if (whole_rows) {
+                // lanes over the single-excitation index, entries in sequence:
+                // each step reads one contiguous table row
+                for (int s0 = 0; s0 < sBn; s0 += 64) {
+                    const int sidx = s0 + lane;
+                    if (sidx >= sBn) continue;
+                    for (u32 k = r.rowb; k < r.rowe; ++k) {
+                        const u64 rbeta = p.v_rank[k] - baseS;
+                        const u64 te = p.T1[rbeta * (u64)sBn + sidx];
+                        const u64 rt = te & 0xFFFFFFFFull;
+                        const int jj = (int)((te >> 32) & 255), bb = (int)((te >> 40) & 255);
+                        const int par_b = (int)((te >> 48) & 1);
+                        double e;
+                        if (T == 1) {
+                            e = p.I.G(I_, A_, jj, bb);
+                            if (r.par ^ par_b) e = -e;
+                        } else {
+                            e = single_element_nophase(p.I, p.v_beta[k], S, jj, bb);
+                            if (par_b) e = -e;
+                        }
+                        if (e != 0.0) {
+                            atomicAdd(&acc[rt - tlo], e * p.v_amp[k]);
+                            ++my_terms;
+                        }
+                    }
+                }
+            } else {
+                for (u64 k0 = r.rowb; k0 < r.rowe; k0 += 64) {
+                    const u64 k = k0 + lane;
+                    unsigned len = 0, st = 0;
+                    u32 beta = 0;
+                    double c = 0.0;
+                    if (k < r.rowe) {
+                        const u64 rbeta = p.v_rank[k] - baseS;
+                        const uint16_t* to = p.toff + rbeta * (u64)(p.ntiles + 1);
+                        const unsigned o0 = to[tile], o1 = to[tile + 1];
+                        len = o1 - o0;
+                        st = (unsigned)(rbeta * (u64)sBn) + o0;
+                        beta = p.v_beta[k];
+                        c = p.v_amp[k];
+                    }
+                    unsigned incl = len;
+                    for (int off = 1; off < 64; off <<= 1) {
+                        unsigned y = __shfl_up(incl, off);
+                        if (lane >= off) incl += y;
+                    }
+                    const unsigned total = __shfl(incl, 63);
+                    wave_sync();
+                    W.incl[lane] = incl;
+                    W.excl[lane] = incl - len;
+                    W.start[lane] = st;
+                    W.beta[lane] = beta;
+                    W.c[lane] = c;
+                    wave_sync();
+                    int x = 0;  // entry of item q; q only grows, so the search resumes
+                    for (unsigned q0 = 0; q0 < total; q0 += 64) {
+                        const unsigned q = q0 + lane;
+                        if (q < total) {
+                            while (W.incl[x] <= q) ++x;
+                            const u64 te = p.T1[W.start[x] + (q - W.excl[x])];
+                            const u64 rt = te & 0xFFFFFFFFull;
+                            const int jj = (int)((te >> 32) & 255), bb = (int)((te >> 40) & 255);
+                            const int par_b = (int)((te >> 48) & 1);
+                            double e;
+                            if (T == 1) {
+                                e = p.I.G(I_, A_, jj, bb);
+                                if (r.par ^ par_b) e = -e;
+                            } else {
+                                e = single_element_nophase(p.I, W.beta[x], S, jj, bb);
+                                if (par_b) e = -e;
+                            }
+                            if (e != 0.0) {
+                                atomicAdd(&acc[rt - tlo], e * W.c[x]);
+                                ++my_terms;
+                            }
+                        }
+                    }
+                }
+            }
+            if (T != 0) continue;
+            // identity row: beta-beta doubles of every entry
+            const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
+            const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
+            for (u64 k = r.rowb; k < r.rowe; ++k) {
+                const u32 beta = p.v_beta[k];
+                const double c = p.v_amp[k];
+                wave_sync();
+                if (lane < n) {
+                    u32 below = (1u << lane) - 1u;
+                    if ((beta >> lane) & 1u) W.occ[__popc(beta & below)] = (uint8_t)lane;
+                    else W.vir[lane - __popc(beta & below)] = (uint8_t)lane;
+                }
+                wave_sync();
+                const int tot = PB * QB;
+                int po = (QB > 0) ? lane / QB : 0, pv = (QB > 0) ? lane % QB : 0;
+                const int dq = (QB > 0) ? 64 / QB : 0, dr = (QB > 0) ? 64 % QB : 0;
+                for (int t0 = 0; t0 < tot; t0 += 64) {
+                    if (t0 + lane < tot) {
+                        const unsigned pa = pairNB[po], pvv = pairVB[pv];
+                        const int i2 = W.occ[pa & 255], j2 = W.occ[pa >> 8];
+                        const int a2 = W.vir[pvv & 255], b2 = W.vir[pvv >> 8];
+                        const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
+                        const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
+                        const int top = 31 - __clz((int)B2);
+                        if (top >= top_lo && top <= top_hi) {
+                            const u64 rt = str_rank(B2, sB);
+                            if (rt >= tlo && rt < thi) {
+                                const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
+                                double e = (p.I.G(i2, a2, j2, b2) - p.I.G(i2, b2, j2, a2));
+                                if (par) e = -e;
+                                if (e != 0.0) {
+                                    atomicAdd(&acc[rt - tlo], e * c);
+                                    ++my_terms;
+                                }
+                            }
+                        }
+                    }
+                    pv += dr;
+                    po += dq;
+                    if (pv >= QB) { pv -= QB; po += 1; }
+                }
+            }
+        }
+        __syncthreads();
+        if (s_touched) {
+            double* dst = p.D + rAt * Nb + tlo;
+            for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = acc[x];
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
+    if (lane == 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
+}
+
+// ---- per-problem tables ----
+// T1: for every beta string, its singles sorted by target rank; toff: per-tile
+// offsets into that sorted slice.  One wavefront per beta string; the sort is
+// a rank-by-counting over at most 256 distinct keys.
+__global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restrict__ binom, const u64* __restrict__ tile_lo,
+                                                 int ntiles, u64* __restrict__ T1, uint16_t* __restrict__ toff) {
+    __shared__ BinomLds sB;
+    __shared__ u64 key[SFCI_MAX_SINGLES];
+    __shared__ uint8_t occ[32], vir[32];
+    load_binom(sB, binom);
+    __syncthreads();
+    const int n = sp.n, nb = sp.nb, nvb = n - nb, sBn = nb * nvb;
+    const int lane = threadIdx.x;
+    for (u64 rb = blockIdx.x; rb < sp.Nb; rb += gridDim.x) {
+        const u32 beta = str_unrank(rb, nb, n, sB);
+        __syncthreads();
+        if (lane < n) {
+            u32 below = (1u << lane) - 1u;
+            if ((beta >> lane) & 1u) occ[__popc(beta & below)] = (uint8_t)lane;
+            else vir[lane - __popc(beta & below)] = (uint8_t)lane;
+        }
+        __syncthreads();
+        for (int t = lane; t < sBn; t += 64) {
+            int jj = occ[t / nvb], bb = vir[t % nvb];
+            u32 B2 = beta ^ (1u << jj) ^ (1u << bb);
+            u64 r = str_rank(B2, sB);
+            key[t] = r | ((u64)jj << 32) | ((u64)bb << 40) | ((u64)between_parity(beta, jj, bb) << 48);
+        }
+        __syncthreads();
+        for (int t = lane; t < sBn; t += 64) {
+            const u64 me = key[t] & 0xFFFFFFFFull;
+            int pos = 0;
+            for (int u = 0; u < sBn; ++u) pos += ((key[u] & 0xFFFFFFFFull) < me) ? 1 : 0;
+            T1[rb * (u64)sBn + pos] = key[t];
+        }
+        for (int t = lane; t <= ntiles; t += 64) {
+            const u64 lo = tile_lo[t];
+            int cnt = 0;
+            for (int u = 0; u < sBn; ++u) cnt += ((key[u] & 0xFFFFFFFFull) < lo) ? 1 : 0;
+            toff[rb * (u64)(ntiles + 1) + t] = (uint16_t)cnt;
+        }
+    }
+}
+
+// Row pointers of the sorted input (alpha-major ranks), the beta string of
+// every entry, and per (alpha row, tile) the first entry whose beta rank is in
+// that tile or above.  rowbeg/rowend/rtb must be zero-filled beforehand.
+__global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __restrict__ r, const u64* __restrict__ nnz_p,
+                       const u64* __restrict__ tile_lo, int ntiles, u64* __restrict__ rowbeg, u64* __restrict__ rowend,
+                       u32* __restrict__ rtb, u32* __restrict__ vbeta) {
+    __shared__ BinomLds sB;
+    load_binom(sB, binom);
+    __syncthreads();
+    const u64 nnz = *nnz_p;
+    const int nt1 = ntiles + 1;
+    for (u64 k = (u64)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (u64)gridDim.x * blockDim.x) {
+        const u64 R = r[k];
+        const u64 ra = R / sp.Nb;
+        const u64 rb = R - ra * sp.Nb;
+        vbeta[k] = str_unrank(rb, sp.nb, sp.n, sB);
+        int t = 0;
+        while (t + 1 < ntiles && tile_lo[t + 1] <= rb) ++t;
+        u32* tb = rtb + ra * (u64)nt1;
+        const bool first = (k == 0) || (r[k - 1] / sp.Nb != ra);
+        const bool last = (k + 1 == nnz) || (r[k + 1] / sp.Nb != ra);
+        int tprev = -1;
+        if (!first) {
+            const u64 rbp = r[k - 1] - ra * sp.Nb;
+            tprev = 0;
+            while (tprev + 1 < ntiles && tile_lo[tprev + 1] <= rbp) ++tprev;
+        }
+        for (int u = tprev + 1; u <= t; ++u) tb[u] = (u32)k;  // tiles that start at this entry
+        if (last)
+            for (int u = t + 1; u < nt1; ++u) tb[u] = (u32)(k + 1);
+        if (first) rowbeg[ra] = k;
+        if (last) rowend[ra] = k + 1;
+    }
+}
+
+u64 binom_u64(int a, int b) {
+    if (b < 0 || a < b) return 0;
+    u64 r = 1;
+    for (int i = 1; i <= b; ++i) r = r * (u64)(a - b + i) / (u64)i;
+    return r;
+}
+
+}  // namespace
+
+struct RowTileState {
+    bool ready = false;
+    int ntiles = 0;
+    int tile_max = 0;
+    size_t lds_bytes = 0;
+    std::vector<u64> tile_lo;
+    u64* d_tile_lo = nullptr;
+    u64* d_T1 = nullptr;
+    uint16_t* d_toff = nullptr;
+};
+
+static RowTileState* rt_state(sfci_problem* P) { return (RowTileState*)P->rowtile; }
+
+// Tiles: contiguous beta-rank ranges cut at top-orbital class boundaries
+// (strings whose highest occupied orbital is m have ranks in
+// [C(m, nb), C(m + 1, nb))), merged greedily from the top while they fit in
+// LDS; a class larger than the limit is cut into equal pieces.
+static void plan_tiles(sfci_problem* P, RowTileState* S, int tile_max) {
+    const int n = P->n, nb = P->nb;
+    std::vector<std::pair<u64, u64>> tiles;  // [lo, hi), collected from the top down
+    if (nb == 0) {
+        tiles.push_back({0, 1});
+    } else {
+        u64 cur_lo = P->Nb, cur_hi = P->Nb;  // open tile [cur_lo, cur_hi)
+        for (int m = n - 1; m >= nb - 1; --m) {
+            const u64 lo = binom_u64(m, nb), hi = binom_u64(m + 1, nb);  // class m
+            if (hi == lo) continue;
+            if (cur_hi - lo <= (u64)tile_max) {
+                cur_lo = lo;
+                continue;
+            }
+            if (cur_hi > cur_lo) tiles.push_back({cur_lo, cur_hi});
+            if (hi - lo <= (u64)tile_max) {
+                cur_hi = hi;
+                cur_lo = lo;
+            } else {
+                const u64 pieces = (hi - lo + tile_max - 1) / tile_max;
+                const u64 step = (hi - lo + pieces - 1) / pieces;
+                for (u64 top = hi; top > lo;) {
+                    const u64 bot = (top - lo > step) ? top - step : lo;
+                    tiles.push_back({bot, top});
+                    top = bot;
+                }
+                cur_hi = lo;
+                cur_lo = lo;
+            }
+        }
+        if (cur_hi > cur_lo) tiles.push_back({cur_lo, cur_hi});
+    }
+    std::reverse(tiles.begin(), tiles.end());
+    S->tile_lo.clear();
+    int mx = 0;
+    for (auto& t : tiles) {
+        S->tile_lo.push_back(t.first);
+        mx = std::max<int>(mx, (int)(t.second - t.first));
+    }
+    S->tile_lo.push_back(P->Nb);
+    S->ntiles = (int)tiles.size();
+    S->tile_max = mx;
+}
+
+bool rowtile_available(sfci_problem* P) {
+    if (P->n > 32 || P->nb * (P->n - P->nb) > SFCI_MAX_SINGLES) return false;
+    RowTileState* S = rt_state(P);
+    if (S && S->ready) return true;
+    if (!S) {
+        S = new RowTileState();
+        P->rowtile = S;
+    }
+    int maxlds = 0;
+    SFCI_CHECK_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
+    const size_t static_lds = sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + 64;
+    static_assert(sizeof(NbrRec) == 40, "neighbour record layout");
+    int tile_max = (int)(((size_t)maxlds - static_lds - 512) / sizeof(double));
+    if (tile_max < 1024) return false;
+    tile_max = std::min(tile_max, 16384);
+    if (const char* env = getenv("SFCI_TILE_MAX")) tile_max = std::max(1024, std::min(tile_max, atoi(env)));
+    plan_tiles(P, S, tile_max);
+    S->lds_bytes = (size_t)S->tile_max * sizeof(double);
+    const u64 sBn = (u64)P->nb * (P->n - P->nb);
+    SFCI_CHECK_HIP(hipMalloc(&S->d_tile_lo, S->tile_lo.size() * sizeof(u64)));
+    SFCI_CHECK_HIP(hipMemcpy(S->d_tile_lo, S->tile_lo.data(), S->tile_lo.size() * sizeof(u64), hipMemcpyHostToDevice));
+    SFCI_CHECK_HIP(hipMalloc(&S->d_T1, std::max<u64>(1, P->Nb * sBn) * sizeof(u64)));
+    SFCI_CHECK_HIP(hipMalloc(&S->d_toff, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
+    unsigned g = (unsigned)std::min<u64>(P->Nb, (u64)P->num_cu * 16);
+    hipLaunchKernelGGL(k_build_T1, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
+                       P->d_binom, S->d_tile_lo, S->ntiles, S->d_T1, S->d_toff);
+    SFCI_CHECK_HIP(hipGetLastError());
+    SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_sigma_rowtile, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)S->lds_bytes));
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    S->ready = true;
+    return true;
+}
+
+void rowtile_release(sfci_problem* P) {
+    RowTileState* S = rt_state(P);
+    if (!S) return;
+    if (S->d_tile_lo) (void)hipFree(S->d_tile_lo);
+    if (S->d_T1) (void)hipFree(S->d_T1);
+    if (S->d_toff) (void)hipFree(S->d_toff);
+    delete S;
+    P->rowtile = nullptr;
+}
+
+void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
+    RowTileState* S = rt_state(P);
+    const u64 cap = std::max<u64>(1, v.cap);
+    const u64 nt1 = (u64)S->ntiles + 1;
+    // rowbeg | rowend | counter(8 words) | rtb (u32 per row and tile boundary)
+    const u64 words = 2 * P->Na + 8 + (P->Na * nt1 + 1) / 2;
+    u64* rowbeg = (u64*)P->ws_rt_rows.get(words * sizeof(u64));
+    u64* rowend = rowbeg + P->Na;
+    unsigned* counter = (unsigned*)(rowend + P->Na);
+    u32* rtb = (u32*)(rowend + P->Na + 8);
+    u32* vbeta = (u32*)P->ws_rt_beta.get(cap * sizeof(u32));
+    launch_fill_u64(rowbeg, words, 0, P->stream);
+    unsigned g = (unsigned)std::min<u64>((cap + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_rows, dim3(g), dim3(256), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, P->d_binom,
+                       v.v_rank, v.v_nnz, S->d_tile_lo, S->ntiles, rowbeg, rowend, rtb, vbeta);
+    RTParams rp;
+    rp.sp = SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb};
+    rp.I = Ints{P->d_h, P->d_g, P->n};
+    rp.binom = P->d_binom;
+    rp.v_rank = v.v_rank;
+    rp.v_amp = v.v_amp;
+    rp.v_beta = vbeta;
+    rp.rowbeg = rowbeg;
+    rp.rowend = rowend;
+    rp.rtb = rtb;
+    rp.T1 = S->d_T1;
+    rp.toff = S->d_toff;
+    rp.tile_lo = S->d_tile_lo;
+    rp.ntiles = S->ntiles;
+    rp.sB = P->nb * (P->n - P->nb);
+    rp.D = D;
+    rp.counter = counter;
+    rp.emitted = emitted;
+    rp.n_items = P->Na * (u64)S->ntiles;
+    // as many workgroups as LDS allows on every CU
+    const int per_cu = std::max(1, (int)((160 * 1024) / (S->lds_bytes + 40 * 1024)));
+    const unsigned grid = (unsigned)std::min<u64>(rp.n_items, (u64)P->num_cu * per_cu);
+    const int na = P->na, nva = P->n - P->na;
+    rp.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
+    rp.nbr_scratch = P->ws_rt_nbr.get((u64)grid * rp.nbr_cap * sizeof(NbrRec));
+    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), S->lds_bytes, P->stream, rp);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+

@@ -65,6 +65,8 @@ struct sfci_problem {
     DevBuf ws_tup_k, ws_tup_v, ws_tup_k2, ws_tup_v2, ws_seg_v, ws_seg_f, ws_src_cnt, ws_src_off, ws_hist;
     DevBuf ws_list_r, ws_list_a;
     DevBuf ws_lz[8];
+    DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr;
+    void* rowtile = nullptr;  // tables of the target-owned dense kernel (rowtile.hip)
 };
 
 // ---- launchers (sigma.hip) ----
@@ -85,6 +87,11 @@ void launch_unrank(sfci_problem* P, const u64* rank, u64 cnt, u64* a, u64* b, in
 void launch_backward_dense(sfci_problem* P, const SigmaLaunch& v, const double* D, double* vbar, double* dh, double* dg,
                            double* Rh, double* Rg);
 void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nnz, u64 cap);
+
+// ---- target-owned dense sigma (rowtile.hip) ----
+bool rowtile_available(sfci_problem* P);  // builds the per-problem tables on first use
+void rowtile_release(sfci_problem* P);
+void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
 
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);

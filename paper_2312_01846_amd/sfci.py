@@ -21,7 +21,7 @@ UINT64_MAX = (1 << 64) - 1
 SFCI_OK = 0
 STATUS = {0: "SFCI_OK", -1: "SFCI_E_ARG", -2: "SFCI_E_RANGE", -3: "SFCI_E_DUP", -4: "SFCI_E_CAPACITY",
           -5: "SFCI_E_NOMEM", -6: "SFCI_E_DEVICE", -7: "SFCI_E_NOTSYM", -8: "SFCI_E_UNSUPPORTED"}
-DEDUP = {"auto": 0, "dense": 1, "sort": 2}
+DEDUP = {"auto": 0, "dense": 1, "sort": 2, "dense_atomic": 3}
 
 
 class SfciError(RuntimeError):

@@ -77,7 +77,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,n,na,nb,mk,nnz", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("mode", ["dense", "sort"])
+@pytest.mark.parametrize("mode", ["dense", "dense_atomic", "sort"])
 def test_sigma_matches_oracle(torch, S, orc, name, n, na, nb, mk, nnz, mode):
     h, g = mk()
     P, Po = _prob(S, orc, n, na, nb, h, g)
@@ -96,7 +96,7 @@ def test_sigma_matches_oracle(torch, S, orc, name, n, na, nb, mk, nnz, mode):
     assert st["candidates"] == len(orr)
 
 
-@pytest.mark.parametrize("mode", ["dense", "sort"])
+@pytest.mark.parametrize("mode", ["dense", "dense_atomic", "sort"])
 def test_sigma_truncated_support(torch, S, orc, mode):
     h, g = synth.molecule_like(10, 20, 5)
     P, Po = _prob(S, orc, 10, 4, 3, h, g)
@@ -146,6 +146,10 @@ def test_sampled_entries_large_space(torch, S, orc):
     gr, ga, st = P.sigma(kr.astype(np.int64), ka, dedup="dense")
     gr, ga = _np(gr).astype(np.uint64), _np(ga)
     assert st["terms_enumerated"] == len(kr) * 15436
+    # the one-atomic-per-term kernel gives the same support and values to rounding
+    ar, aa, _ = P.sigma(kr.astype(np.int64), ka, dedup="dense_atomic")
+    assert np.array_equal(_np(ar).astype(np.uint64), gr)
+    assert np.allclose(_np(aa), ga, rtol=1e-12, atol=1e-15)
     rng = np.random.default_rng(1)
     idx = rng.choice(len(gr), 60, replace=False)
     for i in idx:
