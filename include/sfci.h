@@ -72,9 +72,10 @@ typedef struct {
 
 /* Deduplication of the intermediate elements (Sec. 2.2 merge step). */
 enum {
-    SFCI_DEDUP_AUTO = 0,  /* dense if 8*N_det bytes fit the device, else sort */
-    SFCI_DEDUP_DENSE = 1, /* FP64 atomic accumulation into an N_det array (fast, order not fixed) */
-    SFCI_DEDUP_SORT = 2   /* stable radix sort + in-order segmented sum (deterministic) */
+    SFCI_DEDUP_AUTO = 0,         /* dense if 8*N_det bytes fit the device, else sort */
+    SFCI_DEDUP_DENSE = 1,        /* dense N_det array, target-owned tiles accumulated in LDS (order not fixed) */
+    SFCI_DEDUP_SORT = 2,         /* stable radix sort + in-order segmented sum (deterministic) */
+    SFCI_DEDUP_DENSE_ATOMIC = 3  /* dense N_det array, one FP64 global atomic per term (the first GPU path) */
 };
 
 typedef struct {
@@ -155,6 +156,40 @@ sfci_status sfci_lanczos(sfci_problem* prob, const sfci_svec* v0, const sfci_lan
  * Outputs are overwritten.  Asynchronous. */
 sfci_status sfci_sigma_backward(sfci_problem* prob, const sfci_svec* v, const sfci_svec* sbar, double* v_bar,
                                 double* dh, double* deri);
+
+/* ---- batched iteration (spec extension, not in the paper) ----
+ * Many instances (e.g. points along a bond-stretch curve) with uneven
+ * truncations M_k, and possibly different orbital counts, iterate together:
+ * each sigma application of all instances is one launch of the target-owned
+ * tile kernel, and after one eager block every iteration step is replayed
+ * from a captured hipGraph.  All problems must share one device and stream. */
+typedef struct sfci_batch sfci_batch;
+
+typedef struct {
+    double fwd_ms;              /* device time of the iteration (all blocks) */
+    double bwd_ms;              /* device time of the gradient pass */
+    double sigma_ms_per_step;   /* batched sigma launch, averaged over the eager steps 1..n_L-1 */
+    uint64_t terms_emitted;     /* nonzero-element terms over all sigma applications and instances */
+    uint64_t sigma_calls;       /* sigma applications per instance */
+    uint64_t psi_nnz_total;     /* entries of the final Psi over all instances */
+    int32_t graph_replayed_blocks;
+    int32_t batched_sigma;      /* 1: one launch per step served every instance */
+} sfci_batch_stats;
+
+/* probs: n_inst problem handles (kept, not owned). */
+sfci_status sfci_batch_create(int32_t n_inst, sfci_problem* const* probs, sfci_batch** out);
+sfci_status sfci_batch_destroy(sfci_batch* batch);
+
+/* The SFCI iteration (as sfci_lanczos) for every instance k from v0s[k]
+ * (device vectors) with truncation Ms[k]; opts->M is ignored.
+ * energies (host, n_inst * (n_iter/n_L)) receives the block energies,
+ * instance-major.  dh_all / deri_all (device, may be NULL) receive, per
+ * instance in order, dE/dh (n_k^2) and dE/d(pq|rs) (n_k^4) of
+ * E = <Psi|H|Psi>/<Psi|Psi> at the final untruncated Psi, symmetrised as in
+ * sfci_sigma_backward.  stats may be NULL. */
+sfci_status sfci_batch_lanczos(sfci_batch* batch, const sfci_svec* v0s, const uint64_t* Ms,
+                               const sfci_lanczos_opts* opts, double* energies, double* dh_all, double* deri_all,
+                               sfci_batch_stats* stats);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* sfci_last_error(void);

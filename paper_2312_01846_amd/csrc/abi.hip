@@ -87,7 +87,17 @@ unsigned g1(u64 n) {
     return (unsigned)g;
 }
 
-void sync(sfci_problem* P) { SFCI_CHECK_HIP(hipStreamSynchronize(P->stream)); }
+}  // namespace
+
+void sfci_sync(sfci_problem* P) { SFCI_CHECK_HIP(hipStreamSynchronize(P->stream)); }
+static void sync(sfci_problem* P) { sfci_sync(P); }
+
+void launch_set_u64(sfci_problem* P, u64* p, u64 v) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, p, v);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+namespace {
 
 u64 read_u64(sfci_problem* P, const u64* d) {
     u64 h = 0;
@@ -95,6 +105,8 @@ u64 read_u64(sfci_problem* P, const u64* d) {
     sync(P);
     return h;
 }
+
+}  // namespace
 
 void validate_vec(sfci_problem* P, const u64* r, u64 n) {
     if (n == 0) return;
@@ -139,13 +151,7 @@ void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned lon
         launch_sigma_dense(P, sl, P->d_D, emitted);
 }
 
-// Device-resident sparse vector with a device nnz (Lanczos basis storage).
-struct DVec {
-    u64* r = nullptr;
-    double* a = nullptr;
-    u64* nnz = nullptr;
-    u64 cap = 0;
-};
+namespace {
 
 struct EventTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -267,6 +273,7 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_rows.release();
     P->ws_rt_beta.release();
     P->ws_rt_nbr.release();
+    P->ws_rt_desc.release();
     delete P;
     return SFCI_OK;
 }

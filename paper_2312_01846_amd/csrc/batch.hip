@@ -1,0 +1,381 @@
+// Batched SFCI: many problem instances (points along a bond-stretch curve,
+// uneven truncations M_k, possibly different orbital counts) iterate
+// together.  Per sigma application the work of all instances is drained by
+// ONE launch of the target-owned tile kernel; the rest of an iteration (T/S
+// gathers, Eq. 10, truncation, Eq. 11) is issued per instance on the shared
+// stream.  After one eager block has sized and allocated every buffer, each
+// iteration step and the block end are captured into hipGraphs and replayed.
+// After the last block each instance's gradient of E = <Psi|H|Psi>/<Psi|Psi>
+// with respect to h and (pq|rs) is computed at fixed Psi.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sfci.h"
+#include "sfci_internal.h"
+
+struct sfci_batch {
+    int n = 0;
+    std::vector<sfci_problem*> P;
+    hipStream_t stream = nullptr;      // the problems' stream
+    hipStream_t own = nullptr;         // capture-capable stream used during a batched run
+    std::vector<DevBuf> descs;  // per iteration step j: the n instance descriptions
+    DevBuf prefix, counter, scratch;
+};
+
+namespace {
+
+struct Inst {
+    sfci_problem* P;
+    u64 M, cap, tps;
+    u64* Wr;
+    double* Wa;
+    u64* sc;       // [0..nL) nnz of w_j, [32] emitted, [33] list count, [34] psi count
+    double* T;     // one block: T then S (n_L x n_L each)
+    double* S;
+    double* x;
+    double* lam;
+    double* energies;  // n_blocks
+    int* blk;
+    int* status;
+    u64* psi_r;
+    double* psi_a;
+    double* sbar;
+    u64 lcap;
+    u64* lr;
+    double* la;
+    DVec W(int j) const { return DVec{Wr + (size_t)j * cap, Wa + (size_t)j * cap, sc + j, cap}; }
+};
+
+#define SFCI_GUARD_BEGIN try {
+#define SFCI_GUARD_END                                               \
+    }                                                                \
+    catch (const sfci_error& e) {                                    \
+        return (sfci_status)sfci_set_error(e.code, e.msg);           \
+    }                                                                \
+    catch (const std::exception& e) {                                \
+        return (sfci_status)sfci_set_error(SFCI_E_DEVICE, e.what()); \
+    }
+
+}  // namespace
+
+extern "C" {
+
+sfci_status sfci_batch_create(int32_t n_inst, sfci_problem* const* probs, sfci_batch** out) {
+    SFCI_GUARD_BEGIN
+    if (n_inst < 1 || !probs || !out) return (sfci_status)sfci_set_error(SFCI_E_ARG, "need n_inst >= 1 problems");
+    for (int k = 0; k < n_inst; ++k) {
+        if (!probs[k]) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL problem");
+        if (probs[k]->stream != probs[0]->stream || probs[k]->device != probs[0]->device)
+            return (sfci_status)sfci_set_error(SFCI_E_ARG, "batched problems must share one device and one stream");
+        for (int l = 0; l < k; ++l)
+            if (probs[l] == probs[k])
+                return (sfci_status)sfci_set_error(SFCI_E_ARG, "a problem appears twice (instances own their workspaces)");
+    }
+    sfci_batch* B = new sfci_batch();
+    B->n = n_inst;
+    B->P.assign(probs, probs + n_inst);
+    B->stream = probs[0]->stream;
+    SFCI_CHECK_HIP(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
+    *out = B;
+    return SFCI_OK;
+    SFCI_GUARD_END
+}
+
+sfci_status sfci_batch_destroy(sfci_batch* B) {
+    if (!B) return SFCI_OK;
+    (void)hipStreamSynchronize(B->stream);
+    for (auto& d : B->descs) d.release();
+    B->prefix.release();
+    B->counter.release();
+    B->scratch.release();
+    if (B->own) (void)hipStreamDestroy(B->own);
+    delete B;
+    return SFCI_OK;
+}
+
+sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64_t* Ms, const sfci_lanczos_opts* o,
+                               double* energies, double* dh_all, double* deri_all, sfci_batch_stats* stats) {
+    SFCI_GUARD_BEGIN
+    if (!B || !v0s || !Ms || !o || !energies) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
+    if (o->n_L < 1 || o->n_L > 32 || o->n_iter < o->n_L)
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
+    const int nL = o->n_L, nblk = o->n_iter / nL, n = B->n;
+    const bool det = o->deterministic != 0;
+    const bool use_graph = !det && (o->dedup != SFCI_DEDUP_DENSE_ATOMIC);
+    // Run on the batch's own stream (graph capture is not possible on the
+    // legacy default stream); the problems' stream is restored on exit.
+    SFCI_CHECK_HIP(hipStreamSynchronize(B->stream));
+    hipStream_t st = B->own;
+    struct Restore {
+        sfci_batch* B;
+        ~Restore() {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(B->own, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+                hipGraph_t g = nullptr;  // an error left a capture open: close and drop it
+                if (hipStreamEndCapture(B->own, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            }
+            (void)hipStreamSynchronize(B->own);
+            for (auto* P : B->P) P->stream = B->stream;
+        }
+    } restore{B};
+    for (auto* P : B->P) P->stream = st;
+    std::vector<Inst> I(n);
+    bool all_tiles = true;
+    for (int k = 0; k < n; ++k) {
+        sfci_problem* P = B->P[k];
+        if (v0s[k].nnz == 0) return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty start vector");
+        validate_vec(P, v0s[k].rank, v0s[k].nnz);
+        if (!ensure_dense(P))
+            return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "every instance needs its dense accumulator");
+        if (!det && o->dedup != SFCI_DEDUP_DENSE_ATOMIC && !rowtile_available(P)) all_tiles = false;
+        Inst& q = I[k];
+        q.P = P;
+        q.M = Ms[k];
+        q.cap = (Ms[k] == UINT64_MAX) ? P->Ndet : std::min<u64>(std::max<u64>(Ms[k], v0s[k].nnz), P->Ndet);
+        q.tps = terms_per_source(P->n, P->na, P->nb);
+        q.Wr = (u64*)P->ws_lz[1].get((size_t)nL * q.cap * sizeof(u64));
+        q.Wa = (double*)P->ws_lz[2].get((size_t)nL * q.cap * sizeof(double));
+        q.sc = (u64*)P->ws_lz[3].get(64 * sizeof(u64));
+        double* dbl = (double*)P->ws_lz[4].get((size_t)(2 * nL * nL + 64 + nblk) * sizeof(double));
+        q.T = dbl;
+        q.S = dbl + nL * nL;
+        q.x = q.S + nL * nL;
+        q.lam = q.x + 32;
+        q.energies = q.lam + 8;
+        int* ints = (int*)P->ws_lz[6].get(64 * sizeof(int));
+        q.blk = ints;
+        q.status = ints + 16;
+        const u64 pcap = std::min<u64>(P->Ndet, (u64)nL * q.cap);
+        q.psi_r = (u64*)P->ws_lz[5].get(pcap * sizeof(u64));
+        q.psi_a = (double*)P->ws_lz[7].get(2 * pcap * sizeof(double));
+        q.sbar = q.psi_a + pcap;
+        if (det) {
+            q.lcap = std::min<u64>(P->Ndet, q.cap * q.tps);
+            q.lr = (u64*)P->ws_list_r.get(q.lcap * sizeof(u64));
+            q.la = (double*)P->ws_list_a.get(q.lcap * sizeof(double));
+        }
+        launch_fill_u64(q.sc, 64, 0, st);
+        SFCI_CHECK_HIP(hipMemsetAsync(ints, 0, 64 * sizeof(int), st));
+        DVec w = q.W(0);
+        SFCI_CHECK_HIP(hipMemcpyAsync(w.r, v0s[k].rank, v0s[k].nnz * sizeof(u64), hipMemcpyDeviceToDevice, st));
+        SFCI_CHECK_HIP(hipMemcpyAsync(w.a, v0s[k].amp, v0s[k].nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+        launch_set_u64(P, w.nnz, v0s[k].nnz);
+        launch_normalise(P, w.a, w.nnz, q.cap, det);
+    }
+    const bool batched_sigma = !det && o->dedup != SFCI_DEDUP_DENSE_ATOMIC && all_tiles;
+
+    // one sigma application for every instance
+    B->descs.resize(nL);
+    std::vector<RowTileDesc> descs(n);
+    u64 total_items = 0, nbr_cap = 0;
+    size_t lds = 0;
+    auto sigma_all = [&](int j, bool upload) {
+        if (batched_sigma) {
+            std::vector<u64> pre(n + 1, 0);
+            for (int k = 0; k < n; ++k) {
+                DVec w = I[k].W(j);
+                descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
+                                           (unsigned long long*)(I[k].sc + 32));
+                pre[k + 1] = pre[k] + descs[k].n_items;
+                nbr_cap = std::max(nbr_cap, descs[k].nbr_cap);
+                lds = std::max(lds, descs[k].lds_bytes);
+            }
+            total_items = pre[n];
+            const size_t db = rowtile_desc_bytes();
+            char* d = (char*)B->descs[j].get((size_t)n * db);
+            u64* dpre = (u64*)B->prefix.get((size_t)(n + 1) * sizeof(u64));
+            unsigned* cnt = (unsigned*)B->counter.get(64);
+            const unsigned grid = rowtile_grid(B->P[0]->num_cu, lds, total_items);
+            void* scr = B->scratch.get(rowtile_scratch_bytes(grid, nbr_cap));
+            if (upload) {
+                std::vector<unsigned char> host((size_t)n * db);
+                for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, descs[k].raw, db);
+                SFCI_CHECK_HIP(hipMemcpyAsync(d, host.data(), host.size(), hipMemcpyHostToDevice, st));
+                SFCI_CHECK_HIP(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(u64), hipMemcpyHostToDevice, st));
+                SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host staging buffers go out of scope
+            }
+            rowtile_run(st, B->P[0]->num_cu, d, dpre, n, cnt, scr, nbr_cap, lds, total_items);
+        } else {
+            for (int k = 0; k < n; ++k) {
+                Inst& q = I[k];
+                DVec w = q.W(j);
+                SigmaLaunch sl{w.r, w.a, w.nnz, w.cap};
+                if (det) {
+                    sigma_sorted(q.P, sl, q.lcap, q.lr, q.la, q.sc + 33, q.sc + 32);
+                    launch_scatter_set(q.P, q.P->d_D, q.lr, q.la, q.sc + 33, q.lcap);
+                } else {
+                    dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32));
+                }
+            }
+        }
+    };
+    auto iteration_rest = [&](int j) {
+        for (int k = 0; k < n; ++k) {
+            Inst& q = I[k];
+            sfci_problem* P = q.P;
+            DVec wj = q.W(j);
+            for (int l = 0; l <= j; ++l) {
+                DVec wl = q.W(l);
+                launch_dot_dense(P, wl.r, wl.a, wl.nnz, q.cap, P->d_D, q.T + l * nL + j, q.T + j * nL + l, det);
+                launch_dot_sparse(P, wl.r, wl.a, wl.nnz, q.cap, wj.r, wj.a, wj.nnz, q.S + l * nL + j,
+                                  q.S + j * nL + l, det);
+            }
+            if (j + 1 < nL) {
+                launch_axpy_scatter(P, P->d_D, wj.r, wj.a, wj.nnz, q.cap, q.T + j * nL + j, -1.0);
+                if (j >= 1) {
+                    DVec wm = q.W(j - 1);
+                    launch_axpy_scatter(P, P->d_D, wm.r, wm.a, wm.nnz, q.cap, q.T + (j - 1) * nL + j, -1.0);
+                }
+                DVec wn = q.W(j + 1);
+                CandSrc src{};
+                src.dense = P->d_D;
+                select_topm(P, src, q.M, wn.r, wn.a, wn.nnz, true);
+                launch_normalise(P, wn.a, wn.nnz, q.cap, det);
+            } else {
+                launch_fill_f64(P->d_D, P->Ndet, 0.0, st);
+            }
+        }
+    };
+    auto block_end = [&](bool last) {
+        for (int k = 0; k < n; ++k) {
+            Inst& q = I[k];
+            sfci_problem* P = q.P;
+            launch_geneig_full(P, nL, q.T, q.S, q.lam, q.x, q.energies, q.status, q.blk);
+            for (int j = 0; j < nL; ++j) {
+                DVec wj = q.W(j);
+                launch_axpy_scatter(P, P->d_D, wj.r, wj.a, wj.nnz, q.cap, q.x + j, +1.0);
+            }
+            CandSrc src{};
+            src.dense = P->d_D;
+            if (!last) {
+                DVec w0 = q.W(0);
+                select_topm(P, src, q.M, w0.r, w0.a, w0.nnz, true);
+                launch_normalise(P, w0.a, w0.nnz, q.cap, det);
+            } else {
+                select_topm(P, src, UINT64_MAX, q.psi_r, q.psi_a, q.sc + 34, true);  // capacity n_L * cap suffices
+            }
+            launch_inc_int(P, q.blk);
+        }
+    };
+
+    hipEvent_t e0, e1, e2, es0, es1;
+    SFCI_CHECK_HIP(hipEventCreate(&e0));
+    SFCI_CHECK_HIP(hipEventCreate(&e1));
+    SFCI_CHECK_HIP(hipEventCreate(&e2));
+    SFCI_CHECK_HIP(hipEventCreate(&es0));
+    SFCI_CHECK_HIP(hipEventCreate(&es1));
+    SFCI_CHECK_HIP(hipEventRecord(e0, st));
+    double sigma_ms_eager = 0.0;
+    int sigma_eager = 0;
+    std::vector<hipGraphExec_t> gx;
+    hipGraphExec_t gend = nullptr;
+    for (int b = 0; b < nblk; ++b) {
+        const bool last = (b + 1 == nblk);
+        const bool replay = use_graph && b >= 1;
+        if (replay && gx.empty()) {
+            // capture every iteration step and the (non-final) block end once
+            for (int j = 0; j < nL; ++j) {
+                hipGraph_t g;
+                SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                sigma_all(j, false);
+                iteration_rest(j);
+                SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
+                hipGraphExec_t ex;
+                SFCI_CHECK_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+                SFCI_CHECK_HIP(hipGraphDestroy(g));
+                gx.push_back(ex);
+            }
+            hipGraph_t g;
+            SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            block_end(false);
+            SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
+            SFCI_CHECK_HIP(hipGraphInstantiate(&gend, g, nullptr, nullptr, 0));
+            SFCI_CHECK_HIP(hipGraphDestroy(g));
+        }
+        for (int j = 0; j < nL; ++j) {
+            if (replay) {
+                SFCI_CHECK_HIP(hipGraphLaunch(gx[j], st));
+            } else {
+                const bool timed = (b == 0);
+                if (timed) SFCI_CHECK_HIP(hipEventRecord(es0, st));
+                sigma_all(j, true);
+                if (timed) {
+                    SFCI_CHECK_HIP(hipEventRecord(es1, st));
+                    SFCI_CHECK_HIP(hipEventSynchronize(es1));
+                    float ms = 0.f;
+                    SFCI_CHECK_HIP(hipEventElapsedTime(&ms, es0, es1));
+                    if (j > 0) {  // step 0 starts from the (tiny) start vectors
+                        sigma_ms_eager += ms;
+                        ++sigma_eager;
+                    }
+                }
+                iteration_rest(j);
+            }
+        }
+        if (replay && !last) SFCI_CHECK_HIP(hipGraphLaunch(gend, st));
+        else block_end(last);
+    }
+    SFCI_CHECK_HIP(hipEventRecord(e1, st));
+    // gradients of each instance's Rayleigh quotient at the final Psi
+    if (dh_all || deri_all) {
+        u64 off_h = 0, off_g = 0;
+        for (int k = 0; k < n; ++k) {
+            Inst& q = I[k];
+            sfci_problem* P = q.P;
+            const u64 pcap = std::min<u64>(P->Ndet, (u64)nL * q.cap);
+            const u64 n2 = (u64)P->n * P->n, n4 = n2 * n2;
+            double* raw = (double*)P->ws_red.get((2048 + n2 + n4) * sizeof(double));
+            launch_div_by_sumsq(P, q.psi_a, q.sc + 34, pcap, q.sbar);
+            launch_scatter_set(P, P->d_D, q.psi_r, q.sbar, q.sc + 34, pcap);
+            launch_backward_dense(P, SigmaLaunch{q.psi_r, q.psi_a, q.sc + 34, pcap}, P->d_D, nullptr,
+                                  dh_all ? dh_all + off_h : nullptr, deri_all ? deri_all + off_g : nullptr,
+                                  raw + 2048, raw + 2048 + n2);
+            launch_scatter_zero(P, P->d_D, q.psi_r, q.sc + 34, pcap);
+            off_h += n2;
+            off_g += n4;
+        }
+    }
+    SFCI_CHECK_HIP(hipEventRecord(e2, st));
+    // results
+    std::vector<int> hstat(n);
+    std::vector<u64> hsc((size_t)n * 64);
+    for (int k = 0; k < n; ++k) {
+        SFCI_CHECK_HIP(hipMemcpyAsync(energies + (size_t)k * nblk, I[k].energies, nblk * sizeof(double),
+                                      hipMemcpyDeviceToHost, st));
+        SFCI_CHECK_HIP(hipMemcpyAsync(&hstat[k], I[k].status, sizeof(int), hipMemcpyDeviceToHost, st));
+        SFCI_CHECK_HIP(hipMemcpyAsync(&hsc[(size_t)k * 64], I[k].sc, 64 * sizeof(u64), hipMemcpyDeviceToHost, st));
+    }
+    SFCI_CHECK_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        float f = 0.f, bw = 0.f;
+        SFCI_CHECK_HIP(hipEventElapsedTime(&f, e0, e1));
+        SFCI_CHECK_HIP(hipEventElapsedTime(&bw, e1, e2));
+        stats->fwd_ms = f;
+        stats->bwd_ms = bw;
+        stats->sigma_ms_per_step = sigma_eager ? sigma_ms_eager / sigma_eager : 0.0;
+        u64 emitted = 0;
+        for (int k = 0; k < n; ++k) emitted += hsc[(size_t)k * 64 + 32];
+        stats->terms_emitted = emitted;
+        stats->sigma_calls = (u64)nblk * nL;
+        stats->graph_replayed_blocks = use_graph ? std::max(0, nblk - 1) : 0;
+        stats->batched_sigma = batched_sigma ? 1 : 0;
+        u64 psi_total = 0;
+        for (int k = 0; k < n; ++k) psi_total += hsc[(size_t)k * 64 + 34];
+        stats->psi_nnz_total = psi_total;
+    }
+    for (auto& ex : gx) (void)hipGraphExecDestroy(ex);
+    if (gend) (void)hipGraphExecDestroy(gend);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    (void)hipEventDestroy(es0);
+    (void)hipEventDestroy(es1);
+    for (int k = 0; k < n; ++k)
+        if (hstat[k]) return (sfci_status)sfci_set_error(SFCI_E_DEVICE, "generalized eigenproblem failed");
+    return SFCI_OK;
+    SFCI_GUARD_END
+}
+
+}  // extern "C"

@@ -243,7 +243,7 @@ __device__ void jacobi_dev(int m, double (*A)[GE_MAX], double (*V)[GE_MAX], doub
 // X = U_k s_k^(-1/2), Jacobi on X^T T X, x = X y for the lowest eigenvalue,
 // sign fixed so that the largest |x_i| (lowest i on ties) is positive.
 __global__ void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S, double* lambda,
-                         double* x, double* energy_slot, int* status) {
+                         double* x, double* energy_slot, const int* blk, int* status) {
     __shared__ double A[GE_MAX][GE_MAX], U[GE_MAX][GE_MAX], X[GE_MAX][GE_MAX], TX[GE_MAX][GE_MAX];
     __shared__ double sv[GE_MAX], lam[GE_MAX], xs[GE_MAX];
     __shared__ int keep[GE_MAX];
@@ -296,7 +296,7 @@ __global__ void k_geneig(int m, const double* __restrict__ T, const double* __re
     bool neg = xs[imax] < 0.0;
     for (int i = 0; i < m; ++i) x[i] = neg ? -xs[i] : xs[i];
     *lambda = lam[best];
-    if (energy_slot) *energy_slot = lam[best];
+    if (energy_slot) energy_slot[blk ? *blk : 0] = lam[best];
     *status = 0;
 }
 
@@ -370,7 +370,36 @@ void launch_copy_vec(sfci_problem* P, const u64* r, const double* a, const u64* 
 }
 
 void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
-                        double* energy_slot, int* status) {
-    hipLaunchKernelGGL(k_geneig, dim3(1), dim3(64), 0, P->stream, m, T, S, lambda, x, energy_slot, status);
+                        double* energy_slot, int* status, const int* blk) {
+    hipLaunchKernelGGL(k_geneig, dim3(1), dim3(64), 0, P->stream, m, T, S, lambda, x, energy_slot, blk, status);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+namespace {
+__global__ void k_inc_int(int* p) {
+    if (threadIdx.x == 0) *p += 1;
+}
+__global__ void k_scale_copy(const double* __restrict__ a, const u64* __restrict__ nnz, const double* __restrict__ ss,
+                             double* __restrict__ out) {
+    const u64 n = *nnz;
+    const double s = *ss;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+        out[i] = (s > 0.0) ? a[i] / s : 0.0;
+}
+}  // namespace
+
+void launch_inc_int(sfci_problem* P, int* p) {
+    hipLaunchKernelGGL(k_inc_int, dim3(1), dim3(64), 0, P->stream, p);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+// out = a / sum(a^2) (the cotangent of the Rayleigh quotient's numerator).
+void launch_div_by_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out) {
+    double* part = (double*)P->ws_red.get((RGRID + 8) * sizeof(double));
+    double* ss = part + RGRID + 1;
+    unsigned g = std::min<unsigned>(RGRID, gsz(cap));
+    hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(RB), 0, P->stream, a, nnz, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, ss, (double*)nullptr);
+    hipLaunchKernelGGL(k_scale_copy, dim3(gsz(cap)), dim3(256), 0, P->stream, a, nnz, ss, out);
     SFCI_CHECK_HIP(hipGetLastError());
 }

@@ -43,10 +43,6 @@ struct RTParams {
     int ntiles;
     int sB;                // beta singles per string
     double* D;
-    unsigned* counter;
-    u64 n_items;           // N_alpha * ntiles
-    void* nbr_scratch;     // per workgroup: the nonempty source rows of the current item
-    u64 nbr_cap;           // records per workgroup
     unsigned long long* emitted;
 };
 
@@ -84,37 +80,40 @@ __device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec
     return diag_element(p.I, r.As, beta);
 }
 
-__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(RTParams p) {
+// One launch serves one or many problem instances: item i belongs to the
+// instance whose [item_prefix[k], item_prefix[k+1]) holds it; a workgroup
+// reloads the instance description when consecutive items change instance.
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __restrict__ descs,
+                                                            const u64* __restrict__ item_prefix, int n_inst,
+                                                            unsigned* __restrict__ counter, void* nbr_scratch,
+                                                            u64 nbr_cap) {
     extern __shared__ double acc[];
     __shared__ BinomLds sB;
     __shared__ WaveScratch sw[RT_WAVES];
     __shared__ uint8_t occA[32], virA[32];
     __shared__ uint16_t pairNA[SFCI_MAX_PAIRS], pairVA[SFCI_MAX_PAIRS], pairNB[SFCI_MAX_PAIRS], pairVB[SFCI_MAX_PAIRS];
-    __shared__ unsigned s_item, s_nbr, s_nlist, s_next, s_next2, s_touched;
+    __shared__ unsigned s_nbr, s_nlist, s_next, s_next2, s_touched;
+    __shared__ u64 s_item;
+    __shared__ int s_inst, s_cur;
+    __shared__ RTParams p;
 
-    const int n = p.sp.n, na = p.sp.na, nb = p.sp.nb;
-    const int nva = n - na, nvb = n - nb;
-    const u64 Nb = p.sp.Nb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveScratch& W = sw[wave];
-    NbrRec* list = (NbrRec*)p.nbr_scratch + (u64)blockIdx.x * p.nbr_cap;
-
-    load_binom(sB, p.binom);
-    const int PA = na * (na - 1) / 2, QA = nva * (nva - 1) / 2;
-    const int PB = nb * (nb - 1) / 2, QB = nvb * (nvb - 1) / 2;
-    for (int t = threadIdx.x; t < PA; t += RT_BLOCK) pairNA[t] = decode_pair(t, na);
-    for (int t = threadIdx.x; t < QA; t += RT_BLOCK) pairVA[t] = decode_pair(t, nva);
-    for (int t = threadIdx.x; t < PB; t += RT_BLOCK) pairNB[t] = decode_pair(t, nb);
-    for (int t = threadIdx.x; t < QB; t += RT_BLOCK) pairVB[t] = decode_pair(t, nvb);
-    const int sA = na * nva, sBn = p.sB;
-    const u64 n_nbr = 1 + (u64)sA + (u64)PA * QA;
-    const bool whole_rows = (p.ntiles == 1);
+    NbrRec* list = (NbrRec*)nbr_scratch + (u64)blockIdx.x * nbr_cap;
+    const u64 total_items = item_prefix[n_inst];
+    load_binom(sB, descs[0].binom);  // the binomial table is the same for every instance
+    if (threadIdx.x == 0) s_cur = -1;
     u64 my_terms = 0;
 
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            s_item = atomicAdd(p.counter, 1u);
+            const u64 it = atomicAdd(counter, 1u);
+            int k = 0;
+            if (it < total_items)
+                while (k + 1 < n_inst && item_prefix[k + 1] <= it) ++k;
+            s_item = it < total_items ? it - item_prefix[k] : ~0ull;
+            s_inst = k;
             s_nbr = 0;
             s_nlist = 0;
             s_next = 0;
@@ -122,8 +121,33 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(RTParams p) {
             s_touched = 0;
         }
         __syncthreads();
+        if (s_item == ~0ull) break;
+        if (s_inst != s_cur) {
+            // new instance: flush the term count of the previous one, load the description
+            for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
+            if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
+            my_terms = 0;
+            __syncthreads();
+            const int words = (int)(sizeof(RTParams) / sizeof(u32));
+            for (int t = threadIdx.x; t < words; t += RT_BLOCK) ((u32*)&p)[t] = ((const u32*)&descs[s_inst])[t];
+            __syncthreads();
+            const int na_ = p.sp.na, nb_ = p.sp.nb, nva_ = p.sp.n - na_, nvb_ = p.sp.n - nb_;
+            for (int t = threadIdx.x; t < na_ * (na_ - 1) / 2; t += RT_BLOCK) pairNA[t] = decode_pair(t, na_);
+            for (int t = threadIdx.x; t < nva_ * (nva_ - 1) / 2; t += RT_BLOCK) pairVA[t] = decode_pair(t, nva_);
+            for (int t = threadIdx.x; t < nb_ * (nb_ - 1) / 2; t += RT_BLOCK) pairNB[t] = decode_pair(t, nb_);
+            for (int t = threadIdx.x; t < nvb_ * (nvb_ - 1) / 2; t += RT_BLOCK) pairVB[t] = decode_pair(t, nvb_);
+            if (threadIdx.x == 0) s_cur = s_inst;
+            __syncthreads();
+        }
+        const int n = p.sp.n, na = p.sp.na, nb = p.sp.nb;
+        const int nva = n - na, nvb = n - nb;
+        const u64 Nb = p.sp.Nb;
+        const int PA = na * (na - 1) / 2, QA = nva * (nva - 1) / 2;
+        const int PB = nb * (nb - 1) / 2, QB = nvb * (nvb - 1) / 2;
+        const int sA = na * nva, sBn = p.sB;
+        const u64 n_nbr = 1 + (u64)sA + (u64)PA * QA;
+        const bool whole_rows = (p.ntiles == 1);
         const u64 item = s_item;
-        if (item >= p.n_items) break;
         const u64 rAt = item / (u64)p.ntiles;
         const int tile = (int)(item - rAt * (u64)p.ntiles);
         const u64 tlo = p.tile_lo[tile], thi = p.tile_lo[tile + 1];
@@ -385,7 +409,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(RTParams p) {
         }
     }
     for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
-    if (lane == 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
+    if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
 }
 
 // ---- per-problem tables ----
@@ -581,22 +605,27 @@ void rowtile_release(sfci_problem* P) {
     P->rowtile = nullptr;
 }
 
-void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
+// Per-instance preparation on the instance's stream: row pointers, per-tile
+// entry offsets and beta strings of the input vector; returns the kernel's
+// description of this instance.  rowtile_available(P) must hold.
+RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
     RowTileState* S = rt_state(P);
     const u64 cap = std::max<u64>(1, v.cap);
     const u64 nt1 = (u64)S->ntiles + 1;
-    // rowbeg | rowend | counter(8 words) | rtb (u32 per row and tile boundary)
+    // rowbeg | rowend | 8 spare words | rtb (u32 per row and tile boundary)
     const u64 words = 2 * P->Na + 8 + (P->Na * nt1 + 1) / 2;
     u64* rowbeg = (u64*)P->ws_rt_rows.get(words * sizeof(u64));
     u64* rowend = rowbeg + P->Na;
-    unsigned* counter = (unsigned*)(rowend + P->Na);
     u32* rtb = (u32*)(rowend + P->Na + 8);
     u32* vbeta = (u32*)P->ws_rt_beta.get(cap * sizeof(u32));
     launch_fill_u64(rowbeg, words, 0, P->stream);
     unsigned g = (unsigned)std::min<u64>((cap + 255) / 256, 16384);
     hipLaunchKernelGGL(k_rows, dim3(g), dim3(256), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, P->d_binom,
                        v.v_rank, v.v_nnz, S->d_tile_lo, S->ntiles, rowbeg, rowend, rtb, vbeta);
-    RTParams rp;
+    SFCI_CHECK_HIP(hipGetLastError());
+    RowTileDesc out;
+    static_assert(sizeof(RTParams) <= sizeof(out.raw), "descriptor storage");
+    RTParams& rp = *(RTParams*)out.raw;
     rp.sp = SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb};
     rp.I = Ints{P->d_h, P->d_g, P->n};
     rp.binom = P->d_binom;
@@ -612,16 +641,44 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
     rp.ntiles = S->ntiles;
     rp.sB = P->nb * (P->n - P->nb);
     rp.D = D;
-    rp.counter = counter;
     rp.emitted = emitted;
-    rp.n_items = P->Na * (u64)S->ntiles;
-    // as many workgroups as LDS allows on every CU
-    const int per_cu = std::max(1, (int)((160 * 1024) / (S->lds_bytes + 40 * 1024)));
-    const unsigned grid = (unsigned)std::min<u64>(rp.n_items, (u64)P->num_cu * per_cu);
     const int na = P->na, nva = P->n - P->na;
-    rp.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
-    rp.nbr_scratch = P->ws_rt_nbr.get((u64)grid * rp.nbr_cap * sizeof(NbrRec));
-    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), S->lds_bytes, P->stream, rp);
+    out.n_items = P->Na * (u64)S->ntiles;
+    out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
+    out.lds_bytes = S->lds_bytes;
+    return out;
+}
+
+size_t rowtile_desc_bytes() { return sizeof(RTParams); }
+
+// One launch over n_inst instances whose descriptions (and the exclusive
+// prefix of their item counts, n_inst + 1 values) are already on the device.
+void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items) {
+    launch_fill_u64((u64*)d_counter, 1, 0, stream);
+    const int per_cu = std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
+    const unsigned grid = (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
+    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), lds_bytes, stream, (const RTParams*)d_descs,
+                       d_prefix, n_inst, d_counter, scratch, nbr_cap);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
+unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items) {
+    const int per_cu = std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
+    return (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
+}
+
+size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid * nbr_cap * sizeof(NbrRec); }
+
+void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
+    RowTileDesc d = rowtile_prepare(P, v, D, emitted);
+    // descriptor | prefix (2 words) | counter
+    char* buf = (char*)P->ws_rt_desc.get(sizeof(RTParams) + 64);
+    u64 prefix[2] = {0, d.n_items};
+    SFCI_CHECK_HIP(hipMemcpyAsync(buf, d.raw, sizeof(RTParams), hipMemcpyHostToDevice, P->stream));
+    SFCI_CHECK_HIP(hipMemcpyAsync(buf + sizeof(RTParams), prefix, sizeof(prefix), hipMemcpyHostToDevice, P->stream));
+    const unsigned grid = rowtile_grid(P->num_cu, d.lds_bytes, d.n_items);
+    void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
+    rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
+                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, d.lds_bytes, d.n_items);
+}

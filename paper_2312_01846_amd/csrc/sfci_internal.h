@@ -65,7 +65,7 @@ struct sfci_problem {
     DevBuf ws_tup_k, ws_tup_v, ws_tup_k2, ws_tup_v2, ws_seg_v, ws_seg_f, ws_src_cnt, ws_src_off, ws_hist;
     DevBuf ws_list_r, ws_list_a;
     DevBuf ws_lz[8];
-    DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr;
+    DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr, ws_rt_desc;
     void* rowtile = nullptr;  // tables of the target-owned dense kernel (rowtile.hip)
 };
 
@@ -92,6 +92,19 @@ void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nn
 bool rowtile_available(sfci_problem* P);  // builds the per-problem tables on first use
 void rowtile_release(sfci_problem* P);
 void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
+// Batched form: prepare each instance, put the descriptions on the device,
+// then one launch drains the items of all instances.
+struct RowTileDesc {
+    alignas(8) unsigned char raw[256];  // kernel-side description of one instance
+    u64 n_items, nbr_cap;
+    size_t lds_bytes;
+};
+RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
+size_t rowtile_desc_bytes();
+unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
+size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
+void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items);
 
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);
@@ -136,9 +149,27 @@ void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double*
                          const double* coef, double sign);
 void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered);
 void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap);
+// energy_slot[blk ? *blk : 0] receives lambda (blk: device block index, may be null)
 void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
-                        double* energy_slot, int* status);
+                        double* energy_slot, int* status, const int* blk = nullptr);
+void launch_inc_int(sfci_problem* P, int* p);
+void launch_div_by_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out);
 void launch_copy_vec(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, u64* r2, double* a2,
                      u64* nnz2);
 
 int sfci_set_error(int code, const std::string& msg);
+
+// ---- host helpers shared by the ABI files (abi.hip) ----
+void sfci_sync(sfci_problem* P);
+void launch_set_u64(sfci_problem* P, u64* p, u64 v);
+void validate_vec(sfci_problem* P, const u64* r, u64 n);  // throws on out-of-range or unsorted ranks
+bool ensure_dense(sfci_problem* P);                       // allocates the zeroed N_det accumulator if it fits
+void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted);
+
+// Device-resident sparse vector with a device nnz (Lanczos basis storage).
+struct DVec {
+    u64* r = nullptr;
+    double* a = nullptr;
+    u64* nnz = nullptr;
+    u64 cap = 0;
+};

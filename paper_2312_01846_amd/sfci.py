@@ -57,6 +57,12 @@ class LanczosStats(C.Structure):
                 ("sigma_ms", C.c_double), ("total_ms", C.c_double)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("fwd_ms", C.c_double), ("bwd_ms", C.c_double), ("sigma_ms_per_step", C.c_double),
+                ("terms_emitted", C.c_uint64), ("sigma_calls", C.c_uint64), ("psi_nnz_total", C.c_uint64),
+                ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32)]
+
+
 _lib = None
 
 # Every function the header declares, with its ctypes signature.
@@ -73,6 +79,10 @@ _SIGS = {
                                C.c_void_p, C.c_void_p, C.POINTER(LanczosStats)]),
     "sfci_sigma_backward": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SVec), C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "sfci_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "sfci_batch_destroy": (C.c_int, [C.c_void_p]),
+    "sfci_batch_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(C.c_uint64), C.POINTER(LanczosOpts),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchStats)]),
     "sfci_last_error": (C.c_char_p, []),
 }
 
@@ -266,6 +276,76 @@ class Problem:
         if want_T:
             out["T"] = T.reshape(nblk, n_L, n_L)
             out["S"] = S.reshape(nblk, n_L, n_L)
+        return out
+
+
+class Batch:
+    """Several Problems (one device, one stream) iterated together: one
+    target-owned tile launch per sigma step for all instances, later blocks
+    replayed from captured hipGraphs, Hellmann-Feynman gradients at the end."""
+
+    def __init__(self, problems):
+        _torch()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        handle = C.c_void_p(None)
+        _check(load_library().sfci_batch_create(len(self.problems), arr, C.byref(handle)))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().sfci_batch_destroy(self._h)
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True):
+        """starts: list of (ranks, amps); Ms: truncation per instance.  Returns
+        dict(energies (n_inst, n_blocks), dh [list of (n,n)], dg [list of (n,n,n,n)], stats)."""
+        torch = _torch()
+        n_inst = len(self.problems)
+        if len(starts) != n_inst or len(Ms) != n_inst:
+            raise ValueError("one start vector and one M per instance")
+        keep = []
+        vecs = (SVec * n_inst)()
+        for k, (r0, a0) in enumerate(starts):
+            r = torch.as_tensor(r0, device="cuda").to(torch.int64).contiguous()
+            a = torch.as_tensor(a0, device="cuda").to(torch.float64).contiguous()
+            keep.append((r, a))
+            vecs[k] = _svec(r, a)
+        Marr = (C.c_uint64 * n_inst)(*[UINT64_MAX if m is None else int(m) for m in Ms])
+        nblk = n_iter // n_L
+        energies = np.zeros(n_inst * nblk, dtype=np.float64)
+        dh_all = dg_all = None
+        if want_grad:
+            n2 = sum(p.n * p.n for p in self.problems)
+            n4 = sum(p.n ** 4 for p in self.problems)
+            dh_all = torch.empty(n2, dtype=torch.float64, device="cuda")
+            dg_all = torch.empty(n4, dtype=torch.float64, device="cuda")
+        opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup])
+        st = BatchStats()
+        rc = load_library().sfci_batch_lanczos(self._h, vecs, Marr, C.byref(opts),
+                                               energies.ctypes.data_as(C.c_void_p),
+                                               dh_all.data_ptr() if want_grad else None,
+                                               dg_all.data_ptr() if want_grad else None, C.byref(st))
+        _check(rc)
+        out = dict(energies=energies.reshape(n_inst, nblk),
+                   stats=dict(fwd_ms=st.fwd_ms, bwd_ms=st.bwd_ms, sigma_ms_per_step=st.sigma_ms_per_step,
+                              terms_emitted=st.terms_emitted, sigma_calls=st.sigma_calls,
+                              psi_nnz_total=st.psi_nnz_total, graph_replayed_blocks=st.graph_replayed_blocks,
+                              batched_sigma=st.batched_sigma))
+        if want_grad:
+            dh, dg, oh, og = [], [], 0, 0
+            for p in self.problems:
+                dh.append(dh_all[oh:oh + p.n * p.n].view(p.n, p.n))
+                dg.append(dg_all[og:og + p.n ** 4].view(p.n, p.n, p.n, p.n))
+                oh += p.n * p.n
+                og += p.n ** 4
+            out["dh"], out["dg"] = dh, dg
         return out
 
 

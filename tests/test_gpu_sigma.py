@@ -149,7 +149,10 @@ def test_sampled_entries_large_space(torch, S, orc):
     # the one-atomic-per-term kernel gives the same support and values to rounding
     ar, aa, _ = P.sigma(kr.astype(np.int64), ka, dedup="dense_atomic")
     assert np.array_equal(_np(ar).astype(np.uint64), gr)
-    assert np.allclose(_np(aa), ga, rtol=1e-12, atol=1e-15)
+    # A sum's rounding error is bounded by u * sum|terms|, not by the size of
+    # the (possibly cancelled) sum: compare against the vector's scale here and
+    # against the per-entry bound in the oracle samples below.
+    assert np.abs(_np(aa) - ga).max() <= 1e-12 * np.abs(ga).max()
     rng = np.random.default_rng(1)
     idx = rng.choice(len(gr), 60, replace=False)
     for i in idx:
