@@ -1,16 +1,19 @@
-"""Benchmark: sigma = H v throughput of the SFCI iteration on one MI355X.
+"""Benchmark of the SFCI hot path (sigma = H v with its Lanczos iteration) on one MI355X.
 
-A step is one truncated-Lanczos iteration (Sec. 2.1): sigma = H w_j (FP64
-atomic dedup into the dense N_det accumulator), the T and S gathers, the Eq. 10
-update, top-M selection and Eq. 11 normalisation.  Inputs are resident in HBM
-before timing starts: a warm-up run from the aufbau determinant produces a
-full-size (M entries) start vector.
+Default workload (c4batch): 32 bond-stretch instances of 8 electrons (4 alpha,
+4 beta) in 20 orbitals, N_det = C(20,4)^2 = 2.35e7 each, integrals
+h(lam) = h0 + lam h1, L(lam) = L0 + lam L1 with lam = j/31 (seeds 40-43, rank
+40), truncations M_j = round(10^(4 + 2 u_j)) (seed 44), 30 sigma applications
+per instance in blocks of N_L = 10, then dE/dh and dE/d(pq|rs) for every
+instance.  A step is one Lanczos iteration of all 32 instances (one batched
+sigma launch plus the per-instance vector operations); the timed region is
+`--steps` iterations plus the gradient pass.  The plain path (each instance
+alone: one FP64 atomic per term, no graphs, then the backward) is timed after
+it for the speedup and the energy comparison.
 
-Workload (default): 10 electrons (5 alpha, 5 beta) in 26 orbitals,
-N_det = C(26,5)^2 = 4.33e9, molecule-like synthetic integrals (seed 2, rank-52
-factorisation), M = 1e6 determinants per vector.
-
-Prints one JSON line.
+Other workloads: c2 (10 electrons in 26 orbitals, one instance, M = 1e6) and
+c4 (one 20-orbital instance).  Inputs are resident in HBM before timing
+starts.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -38,9 +41,12 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed Lanczos iterations (multiple of n_L)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed Lanczos iterations, a multiple of n_L (default 30 for c4batch, 10 otherwise)")
     ap.add_argument("--warmup", type=int, default=10, help="warm-up Lanczos iterations (multiple of n_L)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4batch", choices=sorted(WORKLOADS) + ["c4batch"])
+    ap.add_argument("--no-plain", action="store_true", help="c4batch: skip the plain-path comparison")
+    ap.add_argument("--n-inst", type=int, default=32)
     ap.add_argument("--M", type=float, default=1e6)
     ap.add_argument("--n_L", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -69,8 +75,8 @@ def cpu_baseline(h, g, n, na, nb, ranks, amps, target_s):
         take = min(len(ranks), int(take * max(2.0, target_s / 4 / max(elapsed, 1e-3))))
     terms = take * tps
     return dict(value=terms / elapsed, unit="terms/s", cores=1, kind="oracle",
-                sample=f"oracle sigma (generate + stable-sort merge) of the first {take} entries of the timed "
-                       f"start vector, {terms:.3g} terms, {elapsed:.1f} s on one host core")
+                sample=f"oracle sigma (generate + stable-sort merge) of the first {take} entries (by rank) of a vector of the timed "
+                       f"workload, {terms:.3g} terms, {elapsed:.1f} s on one host core")
 
 
 def _tps(n, na, nb):
@@ -85,12 +91,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a design note "
                                    "(alpha-rank-range slices), not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 30 if args.workload == "c4batch" else 10
     if args.steps % args.n_L or args.warmup % args.n_L:
         sys.exit("--steps and --warmup must be multiples of --n_L")
     import torch
 
     from paper_2312_01846_amd import sfci, synth
 
+    if args.workload == "c4batch":
+        return bench_batch(args, torch, sfci, synth)
     wl = WORKLOADS[args.workload]
     n, na, nb = wl["n"], wl["na"], wl["nb"]
     if args.workload == "c4":
@@ -153,6 +163,111 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": "k_sigma_rowtile" if args.dedup == "dense" else "k_sigma_dense",
+            "achieved": achieved / 1e9,
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK,
+            "traffic": None,
+            "sigma_kernel_ms_per_launch": st["sigma_ms"] / max(1, st["sigma_calls"]),
+            "alg_bytes_per_launch": alg_bytes / max(1, st["sigma_calls"]),
+            "sigma_terms_per_s_kernel": terms / sig_s if sig_s > 0 else 0.0,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+def bench_batch(args, torch, sfci, synth):
+    n, na, nb, rank = 20, 4, 4, 40
+    inst = synth.bond_stretch_batch(n, 32, rank)[:args.n_inst]
+    Ms = synth.batch_truncations(32)[:args.n_inst]
+    torch.cuda.set_device(0)
+    probs = [sfci.Problem(n, na, nb, h, g) for _, h, g in inst]
+    start = synth.spin_broken_start(na, nb)
+    r0 = probs[0].rank([s[0] for s in start], [s[1] for s in start]).cpu().numpy()
+    a0 = np.array([s[2] for s in start])
+    order = np.argsort(r0, kind="stable")
+    v0 = (r0[order], a0[order])
+    B = sfci.Batch(probs)
+    if args.warmup:
+        print(f"# warm-up: {args.warmup} batched iterations + gradients", file=sys.stderr, flush=True)
+        B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = out["stats"]
+    E = out["energies"]
+    print(f"# batched: {wall:.3f} s (fwd {st['fwd_ms']:.0f} ms, bwd {st['bwd_ms']:.0f} ms, sigma {st['sigma_ms']:.0f} ms)",
+          file=sys.stderr, flush=True)
+    plain = None
+    sample = None
+    if not args.no_plain:
+        t1 = time.perf_counter()
+        Ep = np.zeros(len(probs))
+        biggest = int(np.argmax(Ms))
+        for k, P in enumerate(probs):
+            o = P.lanczos(v0[0], v0[1], M=Ms[k], n_L=args.n_L, n_iter=args.steps, dedup="dense_atomic",
+                          psi_capacity=min(P.n_det, args.n_L * Ms[k]))
+            P.energy_gradients(o["psi_rank"], o["psi_amp"])
+            Ep[k] = o["energies"][-1]
+            if k == biggest:
+                sample = (o["psi_rank"], o["psi_amp"])
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t1
+        dE = np.abs(E[:, -1] - Ep)
+        plain = dict(seconds=t_plain, speedup=t_plain / wall, energy_max_abs_diff=float(dE.max()),
+                     path="each instance alone: FP64-atomic sigma, per-kernel launches, then the backward")
+        print(f"# plain: {t_plain:.3f} s, speedup {t_plain / wall:.2f}x, max |dE| {dE.max():.2e}", file=sys.stderr,
+              flush=True)
+    terms = st["terms_emitted"]
+    sig_s = st["sigma_ms"] / 1e3
+    alg_bytes = 16 * st["nnz_in_total"] + 16 * terms
+    achieved = alg_bytes / sig_s if sig_s > 0 else 0.0
+    cpu = None
+    if not args.no_cpu_baseline:
+        kb = int(np.argmax(Ms)) if sample is not None else 0
+        if sample is None:
+            o = probs[0].lanczos(v0[0], v0[1], M=Ms[0], n_L=args.n_L, n_iter=args.n_L)
+            sample = (o["psi_rank"], o["psi_amp"])
+        _, hs, gs = inst[kb]
+        cpu = cpu_baseline(hs, gs, n, na, nb, sample[0].cpu().numpy().astype(np.uint64), sample[1].cpu().numpy(),
+                           args.cpu_seconds)
+        cpu["sample"] += f" (instance {kb}, its final Psi)"
+    rec = {
+        "metric": "sigma terms/s (batched fwd+bwd)",
+        "value": terms / wall,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c4batch: {len(probs)} bond-stretch instances, 8e in 20 orbitals (4a,4b), N_det=2.35e7 each, "
+                        f"M log-uniform in [1e4,1e6] (seed 44), N_L={args.n_L}, {args.steps} sigma per instance "
+                        f"+ dE/dh, dE/d(pq|rs); start: aufbau + 0.1 alpha HOMO->LUMO",
+            "Ms": Ms,
+            "n_L": args.n_L,
+            "fwd_ms": st["fwd_ms"],
+            "bwd_ms": st["bwd_ms"],
+            "sigma_ms_total": st["sigma_ms"],
+            "terms_emitted": terms,
+            "psi_nnz_total": st["psi_nnz_total"],
+            "graph_replayed_blocks": st["graph_replayed_blocks"],
+            "final_energies": [float(x) for x in E[:, -1]],
+            "plain_path": plain,
+            "batched_speedup_vs_plain": plain["speedup"] if plain else None,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_sigma_rowtile",
             "achieved": achieved / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",

@@ -168,9 +168,10 @@ typedef struct sfci_batch sfci_batch;
 typedef struct {
     double fwd_ms;              /* device time of the iteration (all blocks) */
     double bwd_ms;              /* device time of the gradient pass */
-    double sigma_ms_per_step;   /* batched sigma launch, averaged over the eager steps 1..n_L-1 */
+    double sigma_ms;            /* sum over the sigma launches (events bracket each launch) */
     uint64_t terms_emitted;     /* nonzero-element terms over all sigma applications and instances */
-    uint64_t sigma_calls;       /* sigma applications per instance */
+    uint64_t nnz_in_total;      /* input entries over all sigma applications and instances */
+    uint64_t sigma_calls;       /* sigma applications per instance (= launches when batched_sigma) */
     uint64_t psi_nnz_total;     /* entries of the final Psi over all instances */
     int32_t graph_replayed_blocks;
     int32_t batched_sigma;      /* 1: one launch per step served every instance */

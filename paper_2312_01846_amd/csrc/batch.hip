@@ -31,7 +31,7 @@ struct Inst {
     u64 M, cap, tps;
     u64* Wr;
     double* Wa;
-    u64* sc;       // [0..nL) nnz of w_j, [32] emitted, [33] list count, [34] psi count
+    u64* sc;       // [0..nL) nnz of w_j, [32] emitted, [33] list count, [34] psi count, [35] sigma input entries
     double* T;     // one block: T then S (n_L x n_L each)
     double* S;
     double* x;
@@ -166,48 +166,60 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     }
     const bool batched_sigma = !det && o->dedup != SFCI_DEDUP_DENSE_ATOMIC && all_tiles;
 
-    // one sigma application for every instance
+    // One sigma application for every instance, in two parts: the per-instance
+    // preparation (row pointers, tile offsets, input-size bookkeeping) and the
+    // single tile launch that drains the work of all instances.
     B->descs.resize(nL);
     std::vector<RowTileDesc> descs(n);
     u64 total_items = 0, nbr_cap = 0;
     size_t lds = 0;
-    auto sigma_all = [&](int j, bool upload) {
+    char* d_desc = nullptr;
+    u64* d_pre = nullptr;
+    unsigned* d_cnt = nullptr;
+    void* d_scr = nullptr;
+    auto sigma_prepare = [&](int j, bool upload) {
+        for (int k = 0; k < n; ++k) launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);  // input entries
+        if (!batched_sigma) return;
+        std::vector<u64> pre(n + 1, 0);
+        for (int k = 0; k < n; ++k) {
+            DVec w = I[k].W(j);
+            descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
+                                       (unsigned long long*)(I[k].sc + 32));
+            pre[k + 1] = pre[k] + descs[k].n_items;
+            nbr_cap = std::max(nbr_cap, descs[k].nbr_cap);
+            lds = std::max(lds, descs[k].lds_bytes);
+        }
+        total_items = pre[n];
+        const size_t db = rowtile_desc_bytes();
+        d_desc = (char*)B->descs[j].get((size_t)n * db);
+        d_pre = (u64*)B->prefix.get((size_t)(n + 1) * sizeof(u64));
+        d_cnt = (unsigned*)B->counter.get(64);
+        d_scr = B->scratch.get(rowtile_scratch_bytes(rowtile_grid(B->P[0]->num_cu, lds, total_items), nbr_cap));
+        if (upload) {
+            std::vector<unsigned char> host((size_t)n * db);
+            for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, descs[k].raw, db);
+            SFCI_CHECK_HIP(hipMemcpyAsync(d_desc, host.data(), host.size(), hipMemcpyHostToDevice, st));
+            SFCI_CHECK_HIP(hipMemcpyAsync(d_pre, pre.data(), pre.size() * sizeof(u64), hipMemcpyHostToDevice, st));
+            SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host staging buffers go out of scope
+        }
+        launch_fill_u64((u64*)d_cnt, 1, 0, st);
+    };
+    auto sigma_launch = [&](int j) {
         if (batched_sigma) {
-            std::vector<u64> pre(n + 1, 0);
-            for (int k = 0; k < n; ++k) {
-                DVec w = I[k].W(j);
-                descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
-                                           (unsigned long long*)(I[k].sc + 32));
-                pre[k + 1] = pre[k] + descs[k].n_items;
-                nbr_cap = std::max(nbr_cap, descs[k].nbr_cap);
-                lds = std::max(lds, descs[k].lds_bytes);
-            }
-            total_items = pre[n];
-            const size_t db = rowtile_desc_bytes();
-            char* d = (char*)B->descs[j].get((size_t)n * db);
-            u64* dpre = (u64*)B->prefix.get((size_t)(n + 1) * sizeof(u64));
-            unsigned* cnt = (unsigned*)B->counter.get(64);
-            const unsigned grid = rowtile_grid(B->P[0]->num_cu, lds, total_items);
-            void* scr = B->scratch.get(rowtile_scratch_bytes(grid, nbr_cap));
-            if (upload) {
-                std::vector<unsigned char> host((size_t)n * db);
-                for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, descs[k].raw, db);
-                SFCI_CHECK_HIP(hipMemcpyAsync(d, host.data(), host.size(), hipMemcpyHostToDevice, st));
-                SFCI_CHECK_HIP(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(u64), hipMemcpyHostToDevice, st));
-                SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host staging buffers go out of scope
-            }
-            rowtile_run(st, B->P[0]->num_cu, d, dpre, n, cnt, scr, nbr_cap, lds, total_items);
-        } else {
-            for (int k = 0; k < n; ++k) {
-                Inst& q = I[k];
-                DVec w = q.W(j);
-                SigmaLaunch sl{w.r, w.a, w.nnz, w.cap};
-                if (det) {
-                    sigma_sorted(q.P, sl, q.lcap, q.lr, q.la, q.sc + 33, q.sc + 32);
-                    launch_scatter_set(q.P, q.P->d_D, q.lr, q.la, q.sc + 33, q.lcap);
-                } else {
-                    dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32));
-                }
+            // descriptions of step j (uploaded in the eager block; the
+            // remaining launch parameters are the same for every step)
+            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, lds, total_items, false);
+            return;
+        }
+        for (int k = 0; k < n; ++k) {
+            Inst& q = I[k];
+            DVec w = q.W(j);
+            SigmaLaunch sl{w.r, w.a, w.nnz, w.cap};
+            if (det) {
+                sigma_sorted(q.P, sl, q.lcap, q.lr, q.la, q.sc + 33, q.sc + 32);
+                launch_scatter_set(q.P, q.P->d_D, q.lr, q.la, q.sc + 33, q.lcap);
+            } else {
+                dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32));
             }
         }
     };
@@ -260,59 +272,64 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         }
     };
 
-    hipEvent_t e0, e1, e2, es0, es1;
-    SFCI_CHECK_HIP(hipEventCreate(&e0));
-    SFCI_CHECK_HIP(hipEventCreate(&e1));
-    SFCI_CHECK_HIP(hipEventCreate(&e2));
-    SFCI_CHECK_HIP(hipEventCreate(&es0));
-    SFCI_CHECK_HIP(hipEventCreate(&es1));
-    SFCI_CHECK_HIP(hipEventRecord(e0, st));
-    double sigma_ms_eager = 0.0;
-    int sigma_eager = 0;
-    std::vector<hipGraphExec_t> gx;
+    // events: whole run, gradients, and one pair around every sigma launch
+    const int n_sig = nblk * nL;
+    std::vector<hipEvent_t> ev(3 + 2 * (size_t)n_sig, nullptr);
+    struct EvFree {
+        std::vector<hipEvent_t>& v;
+        ~EvFree() {
+            for (auto e : v)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } ev_free{ev};
+    for (auto& e : ev) SFCI_CHECK_HIP(hipEventCreate(&e));
+    hipEvent_t e0 = ev[0], e1 = ev[1], e2 = ev[2];
+    std::vector<hipGraphExec_t> gprep, grest;
     hipGraphExec_t gend = nullptr;
+    struct GraphFree {
+        std::vector<hipGraphExec_t>& a;
+        std::vector<hipGraphExec_t>& b;
+        hipGraphExec_t& c;
+        ~GraphFree() {
+            for (auto x : a) (void)hipGraphExecDestroy(x);
+            for (auto x : b) (void)hipGraphExecDestroy(x);
+            if (c) (void)hipGraphExecDestroy(c);
+        }
+    } graph_free{gprep, grest, gend};
+    auto capture = [&](auto&& body) {
+        hipGraph_t g;
+        SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        body();
+        SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
+        hipGraphExec_t ex;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        SFCI_CHECK_HIP(e);
+        return ex;
+    };
+    SFCI_CHECK_HIP(hipEventRecord(e0, st));
+    int sig = 0;
     for (int b = 0; b < nblk; ++b) {
         const bool last = (b + 1 == nblk);
         const bool replay = use_graph && b >= 1;
-        if (replay && gx.empty()) {
-            // capture every iteration step and the (non-final) block end once
+        if (replay && gprep.empty()) {
+            // capture the preparation and the remainder of every iteration
+            // step, and the (non-final) block end, once; the sigma launch
+            // itself stays outside the graphs so that events bracket it
             for (int j = 0; j < nL; ++j) {
-                hipGraph_t g;
-                SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                sigma_all(j, false);
-                iteration_rest(j);
-                SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
-                hipGraphExec_t ex;
-                SFCI_CHECK_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-                SFCI_CHECK_HIP(hipGraphDestroy(g));
-                gx.push_back(ex);
+                gprep.push_back(capture([&] { sigma_prepare(j, false); }));
+                grest.push_back(capture([&] { iteration_rest(j); }));
             }
-            hipGraph_t g;
-            SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            block_end(false);
-            SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
-            SFCI_CHECK_HIP(hipGraphInstantiate(&gend, g, nullptr, nullptr, 0));
-            SFCI_CHECK_HIP(hipGraphDestroy(g));
+            gend = capture([&] { block_end(false); });
         }
-        for (int j = 0; j < nL; ++j) {
-            if (replay) {
-                SFCI_CHECK_HIP(hipGraphLaunch(gx[j], st));
-            } else {
-                const bool timed = (b == 0);
-                if (timed) SFCI_CHECK_HIP(hipEventRecord(es0, st));
-                sigma_all(j, true);
-                if (timed) {
-                    SFCI_CHECK_HIP(hipEventRecord(es1, st));
-                    SFCI_CHECK_HIP(hipEventSynchronize(es1));
-                    float ms = 0.f;
-                    SFCI_CHECK_HIP(hipEventElapsedTime(&ms, es0, es1));
-                    if (j > 0) {  // step 0 starts from the (tiny) start vectors
-                        sigma_ms_eager += ms;
-                        ++sigma_eager;
-                    }
-                }
-                iteration_rest(j);
-            }
+        for (int j = 0; j < nL; ++j, ++sig) {
+            if (replay) SFCI_CHECK_HIP(hipGraphLaunch(gprep[j], st));
+            else sigma_prepare(j, true);
+            SFCI_CHECK_HIP(hipEventRecord(ev[3 + 2 * sig], st));
+            sigma_launch(j);
+            SFCI_CHECK_HIP(hipEventRecord(ev[4 + 2 * sig], st));
+            if (replay) SFCI_CHECK_HIP(hipGraphLaunch(grest[j], st));
+            else iteration_rest(j);
         }
         if (replay && !last) SFCI_CHECK_HIP(hipGraphLaunch(gend, st));
         else block_end(last);
@@ -354,24 +371,26 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         SFCI_CHECK_HIP(hipEventElapsedTime(&bw, e1, e2));
         stats->fwd_ms = f;
         stats->bwd_ms = bw;
-        stats->sigma_ms_per_step = sigma_eager ? sigma_ms_eager / sigma_eager : 0.0;
-        u64 emitted = 0;
-        for (int k = 0; k < n; ++k) emitted += hsc[(size_t)k * 64 + 32];
+        double sms = 0.0;
+        for (int i = 0; i < n_sig; ++i) {
+            float ms = 0.f;
+            SFCI_CHECK_HIP(hipEventElapsedTime(&ms, ev[3 + 2 * i], ev[4 + 2 * i]));
+            sms += ms;
+        }
+        stats->sigma_ms = sms;
+        u64 emitted = 0, nin = 0, psi_total = 0;
+        for (int k = 0; k < n; ++k) {
+            emitted += hsc[(size_t)k * 64 + 32];
+            psi_total += hsc[(size_t)k * 64 + 34];
+            nin += hsc[(size_t)k * 64 + 35];
+        }
         stats->terms_emitted = emitted;
-        stats->sigma_calls = (u64)nblk * nL;
+        stats->nnz_in_total = nin;
+        stats->sigma_calls = (u64)n_sig;
+        stats->psi_nnz_total = psi_total;
         stats->graph_replayed_blocks = use_graph ? std::max(0, nblk - 1) : 0;
         stats->batched_sigma = batched_sigma ? 1 : 0;
-        u64 psi_total = 0;
-        for (int k = 0; k < n; ++k) psi_total += hsc[(size_t)k * 64 + 34];
-        stats->psi_nnz_total = psi_total;
     }
-    for (auto& ex : gx) (void)hipGraphExecDestroy(ex);
-    if (gend) (void)hipGraphExecDestroy(gend);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
-    (void)hipEventDestroy(es0);
-    (void)hipEventDestroy(es1);
     for (int k = 0; k < n; ++k)
         if (hstat[k]) return (sfci_status)sfci_set_error(SFCI_E_DEVICE, "generalized eigenproblem failed");
     return SFCI_OK;

@@ -379,6 +379,9 @@ namespace {
 __global__ void k_inc_int(int* p) {
     if (threadIdx.x == 0) *p += 1;
 }
+__global__ void k_add_u64(u64* dst, const u64* src) {
+    if (threadIdx.x == 0) *dst += *src;
+}
 __global__ void k_scale_copy(const double* __restrict__ a, const u64* __restrict__ nnz, const double* __restrict__ ss,
                              double* __restrict__ out) {
     const u64 n = *nnz;
@@ -390,6 +393,11 @@ __global__ void k_scale_copy(const double* __restrict__ a, const u64* __restrict
 
 void launch_inc_int(sfci_problem* P, int* p) {
     hipLaunchKernelGGL(k_inc_int, dim3(1), dim3(64), 0, P->stream, p);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_add_u64(sfci_problem* P, u64* dst, const u64* src) {
+    hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, P->stream, dst, src);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 

@@ -65,6 +65,15 @@ struct WaveScratch {
     uint8_t occ[32], vir[32];
 };
 
+// Entries of the identity row per beta-beta-double work unit.
+constexpr unsigned RT_BB_CHUNK = 4;
+// Input entries whose table reads are issued together in the beta-single loop.
+constexpr int RT_UNROLL = 4;
+
+__device__ __forceinline__ u32 rl32(u32 v, int l) { return (u32)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ u64 rl64(u64 v, int l) { return ((u64)rl32((u32)(v >> 32), l) << 32) | rl32((u32)v, l); }
+__device__ __forceinline__ double rlf64(double v, int l) { return __longlong_as_double((long long)rl64((u64)__double_as_longlong(v), l)); }
+
 // Direct target (beta unchanged) of entry k of source row r: alpha double
 // (constant element), alpha single (alpha part + beta part), or the diagonal.
 __device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec& r, u32 beta) {
@@ -92,7 +101,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
     __shared__ WaveScratch sw[RT_WAVES];
     __shared__ uint8_t occA[32], virA[32];
     __shared__ uint16_t pairNA[SFCI_MAX_PAIRS], pairVA[SFCI_MAX_PAIRS], pairNB[SFCI_MAX_PAIRS], pairVB[SFCI_MAX_PAIRS];
-    __shared__ unsigned s_nbr, s_nlist, s_next, s_next2, s_touched;
+    __shared__ unsigned s_nbr, s_nlist, s_next, s_next2, s_touched, s_idb, s_ide;
     __shared__ u64 s_item;
     __shared__ int s_inst, s_cur;
     __shared__ RTParams p;
@@ -119,6 +128,8 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
             s_next = 0;
             s_next2 = 0;
             s_touched = 0;
+            s_idb = 0;
+            s_ide = 0;
         }
         __syncthreads();
         if (s_item == ~0ull) break;
@@ -196,6 +207,10 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                 }
                 const u64 rAs = str_rank(As, sB);
                 const u64 rb = p.rowbeg[rAs], re = p.rowend[rAs];
+                if (type == 0) {
+                    s_idb = (u32)rb;  // the identity row: all its entries feed the beta-beta doubles
+                    s_ide = (u32)re;
+                }
                 if (re > rb) {
                     const u32* tb = p.rtb + rAs * (u64)(p.ntiles + 1);
                     r.As = As; r.rAs = (u32)rAs; r.rowb = (u32)rb; r.rowe = (u32)re;
@@ -267,12 +282,63 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
         }
 
         // Phase 3: beta singles of the identity and alpha-single source rows
-        // (the alpha-beta doubles), and the identity row's beta-beta doubles.
+        // (the alpha-beta doubles), one list row per work unit; then the
+        // identity row's beta-beta doubles, RT_BB_CHUNK entries per unit, so
+        // that every wavefront shares the largest single-row job.
+        const u32 idb = s_idb, ide = s_ide;
+        const unsigned n_bb = (PB > 0 && QB > 0) ? (ide - idb + RT_BB_CHUNK - 1) / RT_BB_CHUNK : 0u;
+        const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
+        const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
         for (;;) {
             unsigned li = 0;
             if (lane == 0) li = atomicAdd(&s_next, 1u);
             li = __shfl(li, 0);
-            if (li >= nlist) break;
+            if (li >= nlist + n_bb) break;
+            if (li >= nlist) {
+                // beta-beta doubles of identity-row entries [k0, k1)
+                const u32 k0 = idb + (li - nlist) * RT_BB_CHUNK;
+                const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
+                for (u32 k = k0; k < k1; ++k) {
+                    const u32 beta = p.v_beta[k];
+                    const double c = p.v_amp[k];
+                    wave_sync();
+                    if (lane < n) {
+                        u32 below = (1u << lane) - 1u;
+                        if ((beta >> lane) & 1u) W.occ[__popc(beta & below)] = (uint8_t)lane;
+                        else W.vir[lane - __popc(beta & below)] = (uint8_t)lane;
+                    }
+                    wave_sync();
+                    const int tot = PB * QB;
+                    int po = lane / QB, pv = lane % QB;
+                    const int dq = 64 / QB, dr = 64 % QB;
+                    for (int t0 = 0; t0 < tot; t0 += 64) {
+                        if (t0 + lane < tot) {
+                            const unsigned pa = pairNB[po], pvv = pairVB[pv];
+                            const int i2 = W.occ[pa & 255], j2 = W.occ[pa >> 8];
+                            const int a2 = W.vir[pvv & 255], b2 = W.vir[pvv >> 8];
+                            const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
+                            const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
+                            const int top = 31 - __clz((int)B2);
+                            if (top >= top_lo && top <= top_hi) {
+                                const u64 rt = str_rank(B2, sB);
+                                if (rt >= tlo && rt < thi) {
+                                    const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
+                                    double e = (p.I.G(i2, a2, j2, b2) - p.I.G(i2, b2, j2, a2));
+                                    if (par) e = -e;
+                                    if (e != 0.0) {
+                                        atomicAdd(&acc[rt - tlo], e * c);
+                                        ++my_terms;
+                                    }
+                                }
+                            }
+                        }
+                        pv += dr;
+                        po += dq;
+                        if (pv >= QB) { pv -= QB; po += 1; }
+                    }
+                }
+                continue;
+            }
             const NbrRec r = list[li];
             const int T = r.type;
             if (T == 2) continue;
@@ -280,28 +346,63 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
             const u32 S = r.As;
             const u64 baseS = (u64)r.rAs * Nb;
             if (whole_rows) {
-                // lanes over the single-excitation index, entries in sequence:
-                // each step reads one contiguous table row
+                // lanes over the single-excitation index; 64 entries at a time
+                // are loaded one per lane and taken in turn (readlane), with
+                // RT_UNROLL table reads in flight
                 for (int s0 = 0; s0 < sBn; s0 += 64) {
                     const int sidx = s0 + lane;
-                    if (sidx >= sBn) continue;
-                    for (u32 k = r.rowb; k < r.rowe; ++k) {
-                        const u64 rbeta = p.v_rank[k] - baseS;
-                        const u64 te = p.T1[rbeta * (u64)sBn + sidx];
-                        const u64 rt = te & 0xFFFFFFFFull;
-                        const int jj = (int)((te >> 32) & 255), bb = (int)((te >> 40) & 255);
-                        const int par_b = (int)((te >> 48) & 1);
-                        double e;
-                        if (T == 1) {
-                            e = p.I.G(I_, A_, jj, bb);
-                            if (r.par ^ par_b) e = -e;
-                        } else {
-                            e = single_element_nophase(p.I, p.v_beta[k], S, jj, bb);
-                            if (par_b) e = -e;
+                    const bool act = sidx < sBn;
+                    for (u32 kb = r.rowb; kb < r.rowe; kb += 64) {
+                        const u32 kk = kb + lane;
+                        u64 rk = 0;
+                        double ck = 0.0;
+                        u32 bk = 0;
+                        if (kk < r.rowe) {
+                            rk = p.v_rank[kk];
+                            ck = p.v_amp[kk];
+                            if (T == 0) bk = p.v_beta[kk];
                         }
-                        if (e != 0.0) {
-                            atomicAdd(&acc[rt - tlo], e * p.v_amp[k]);
-                            ++my_terms;
+                        const int cnt = (int)min(64u, r.rowe - kb);
+                        for (int q = 0; q < cnt; q += RT_UNROLL) {
+                            u64 te[RT_UNROLL];
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                te[u] = 0;
+                                if (q + u < cnt) {
+                                    const u64 rbeta = rl64(rk, q + u) - baseS;
+                                    if (act) te[u] = p.T1[rbeta * (u64)sBn + sidx];
+                                }
+                            }
+                            double e[RT_UNROLL];
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                const int jj = (int)((te[u] >> 32) & 255), bb = (int)((te[u] >> 40) & 255);
+                                const int par_b = (int)((te[u] >> 48) & 1);
+                                double x = 0.0;
+                                if (q + u < cnt) {
+                                    const u32 bq = (T == 0) ? rl32(bk, q + u) : 0u;
+                                    if (act) {
+                                        if (T == 1) {
+                                            x = p.I.G(I_, A_, jj, bb);
+                                            if (r.par ^ par_b) x = -x;
+                                        } else {
+                                            x = single_element_nophase(p.I, bq, S, jj, bb);
+                                            if (par_b) x = -x;
+                                        }
+                                    }
+                                }
+                                e[u] = x;
+                            }
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                if (q + u < cnt) {
+                                    const double c = rlf64(ck, q + u);
+                                    if (e[u] != 0.0) {
+                                        atomicAdd(&acc[(te[u] & 0xFFFFFFFFull) - tlo], e[u] * c);
+                                        ++my_terms;
+                                    }
+                                }
+                            }
                         }
                     }
                 }
@@ -356,49 +457,6 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                             }
                         }
                     }
-                }
-            }
-            if (T != 0) continue;
-            // identity row: beta-beta doubles of every entry
-            const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
-            const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
-            for (u64 k = r.rowb; k < r.rowe; ++k) {
-                const u32 beta = p.v_beta[k];
-                const double c = p.v_amp[k];
-                wave_sync();
-                if (lane < n) {
-                    u32 below = (1u << lane) - 1u;
-                    if ((beta >> lane) & 1u) W.occ[__popc(beta & below)] = (uint8_t)lane;
-                    else W.vir[lane - __popc(beta & below)] = (uint8_t)lane;
-                }
-                wave_sync();
-                const int tot = PB * QB;
-                int po = (QB > 0) ? lane / QB : 0, pv = (QB > 0) ? lane % QB : 0;
-                const int dq = (QB > 0) ? 64 / QB : 0, dr = (QB > 0) ? 64 % QB : 0;
-                for (int t0 = 0; t0 < tot; t0 += 64) {
-                    if (t0 + lane < tot) {
-                        const unsigned pa = pairNB[po], pvv = pairVB[pv];
-                        const int i2 = W.occ[pa & 255], j2 = W.occ[pa >> 8];
-                        const int a2 = W.vir[pvv & 255], b2 = W.vir[pvv >> 8];
-                        const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
-                        const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
-                        const int top = 31 - __clz((int)B2);
-                        if (top >= top_lo && top <= top_hi) {
-                            const u64 rt = str_rank(B2, sB);
-                            if (rt >= tlo && rt < thi) {
-                                const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
-                                double e = (p.I.G(i2, a2, j2, b2) - p.I.G(i2, b2, j2, a2));
-                                if (par) e = -e;
-                                if (e != 0.0) {
-                                    atomicAdd(&acc[rt - tlo], e * c);
-                                    ++my_terms;
-                                }
-                            }
-                        }
-                    }
-                    pv += dr;
-                    po += dq;
-                    if (pv >= QB) { pv -= QB; po += 1; }
                 }
             }
         }
@@ -654,8 +712,9 @@ size_t rowtile_desc_bytes() { return sizeof(RTParams); }
 // One launch over n_inst instances whose descriptions (and the exclusive
 // prefix of their item counts, n_inst + 1 values) are already on the device.
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
-                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items) {
-    launch_fill_u64((u64*)d_counter, 1, 0, stream);
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items,
+                 bool fill_counter) {
+    if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
     const int per_cu = std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
     const unsigned grid = (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
     hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), lds_bytes, stream, (const RTParams*)d_descs,

@@ -103,8 +103,10 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
 size_t rowtile_desc_bytes();
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
+// fill_counter = false: the caller has already zeroed *d_counter on the stream.
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
-                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items);
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items,
+                 bool fill_counter = true);
 
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);
@@ -153,6 +155,7 @@ void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* 
 void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
                         double* energy_slot, int* status, const int* blk = nullptr);
 void launch_inc_int(sfci_problem* P, int* p);
+void launch_add_u64(sfci_problem* P, u64* dst, const u64* src);  // *dst += *src
 void launch_div_by_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out);
 void launch_copy_vec(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, u64* r2, double* a2,
                      u64* nnz2);

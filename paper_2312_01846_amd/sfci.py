@@ -58,8 +58,9 @@ class LanczosStats(C.Structure):
 
 
 class BatchStats(C.Structure):
-    _fields_ = [("fwd_ms", C.c_double), ("bwd_ms", C.c_double), ("sigma_ms_per_step", C.c_double),
-                ("terms_emitted", C.c_uint64), ("sigma_calls", C.c_uint64), ("psi_nnz_total", C.c_uint64),
+    _fields_ = [("fwd_ms", C.c_double), ("bwd_ms", C.c_double), ("sigma_ms", C.c_double),
+                ("terms_emitted", C.c_uint64), ("nnz_in_total", C.c_uint64), ("sigma_calls", C.c_uint64),
+                ("psi_nnz_total", C.c_uint64),
                 ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32)]
 
 
@@ -334,8 +335,9 @@ class Batch:
                                                dg_all.data_ptr() if want_grad else None, C.byref(st))
         _check(rc)
         out = dict(energies=energies.reshape(n_inst, nblk),
-                   stats=dict(fwd_ms=st.fwd_ms, bwd_ms=st.bwd_ms, sigma_ms_per_step=st.sigma_ms_per_step,
-                              terms_emitted=st.terms_emitted, sigma_calls=st.sigma_calls,
+                   stats=dict(fwd_ms=st.fwd_ms, bwd_ms=st.bwd_ms, sigma_ms=st.sigma_ms,
+                              terms_emitted=st.terms_emitted, nnz_in_total=st.nnz_in_total,
+                              sigma_calls=st.sigma_calls,
                               psi_nnz_total=st.psi_nnz_total, graph_replayed_blocks=st.graph_replayed_blocks,
                               batched_sigma=st.batched_sigma))
         if want_grad:

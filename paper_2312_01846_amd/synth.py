@@ -132,6 +132,22 @@ def aufbau_bits(n_elec: int) -> int:
     return (1 << n_elec) - 1
 
 
+def spin_broken_start(na: int, nb: int, weight: float = 0.1) -> list[tuple[int, int, float]]:
+    """Start vector without alpha/beta exchange symmetry, as (alpha bits,
+    beta bits, amplitude) triples: the aufbau determinant plus `weight` times
+    its alpha-only HOMO -> LUMO excitation.
+
+    With n_alpha = n_beta, a start vector that is symmetric under exchanging
+    the alpha and beta strings keeps every iterate symmetric, so the two
+    partners of each exchanged pair carry equal amplitudes and the top-M cut
+    through such a pair is decided by the last bit of rounding.  This start
+    gives the partners different amplitudes throughout.
+    """
+    a0, b0 = aufbau_bits(na), aufbau_bits(nb)
+    a1 = (a0 & ~(1 << (na - 1))) | (1 << na)
+    return [(a0, b0, 1.0), (a1, b0, float(weight))]
+
+
 def neel_bits(n_sites: int) -> tuple[int, int]:
     """Neel determinant: alpha on even sites, beta on odd sites."""
     a = sum(1 << p for p in range(0, n_sites, 2))

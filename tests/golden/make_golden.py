@@ -34,20 +34,21 @@ def case_defs():
     def mol(n, na, nb, rank, seed):
         def b():
             h, g = synth.molecule_like(n, rank, seed)
-            return n, na, nb, h, g, synth.aufbau_bits(na), synth.aufbau_bits(nb)
+            return n, na, nb, h, g, [(synth.aufbau_bits(na), synth.aufbau_bits(nb), 1.0)]
         return b
 
     def hub(L, U):
         def b():
             h, g = synth.hubbard_ring(L, 1.0, U)
             a, bb = synth.neel_bits(L)
-            return L, L // 2, L // 2, h, g, a, bb
+            return L, L // 2, L // 2, h, g, [(a, bb, 1.0)]
         return b
 
-    def c4(j):
+    def c4(j, broken=False):
         def b():
             lam, h, g = synth.bond_stretch_batch(20, 32, 40)[j]
-            return 20, 4, 4, h, g, synth.aufbau_bits(4), synth.aufbau_bits(4)
+            start = synth.spin_broken_start(4, 4) if broken else [(synth.aufbau_bits(4), synth.aufbau_bits(4), 1.0)]
+            return 20, 4, 4, h, g, start
         return b
 
     return {
@@ -59,16 +60,20 @@ def case_defs():
         "c2_M1e4_30": (mol(26, 5, 5, 52, 2), 10_000, 10, 30),
         "c4_inst0_M1e4_30": (c4(0), 10_000, 10, 30),
         "c4_inst31_M3e3_30": (c4(31), 3_000, 10, 30),
+        "c4sb_inst31_M3e3_30": (c4(31, True), 3_000, 10, 30),
+        "c4sb_inst12_M1e4_30": (c4(12, True), 10_000, 10, 30),
     }
 
 
 def run(name):
     build, M, nL, nit = case_defs()[name]
-    n, na, nb, h, g, a0, b0 = build()
+    n, na, nb, h, g, start = build()
     P = oracle.Problem(n, na, nb, h, g)
-    r0 = P.rank([a0], [b0])
+    r0 = P.rank([s[0] for s in start], [s[1] for s in start])
+    a0 = np.array([s[2] for s in start])
+    order = np.argsort(r0, kind="stable")
     t = time.time()
-    out = P.lanczos(r0, np.array([1.0]), M, nL, nit)
+    out = P.lanczos(r0[order], a0[order], M, nL, nit)
     dt = time.time() - t
     return dict(energies=[float(x) for x in out["energies"]], psi_nnz=int(len(out["psi_rank"])),
                 psi_support_sha=_support_digest(out["psi_rank"]), M=M, n_L=nL, n_iter=nit, oracle_seconds=dt)
