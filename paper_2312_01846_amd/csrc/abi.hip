@@ -260,10 +260,13 @@ sfci_status sfci_problem_create(const sfci_space* sp, const double* h, const dou
 sfci_status sfci_problem_destroy(sfci_problem* P) {
     if (!P) return SFCI_OK;
     (void)hipStreamSynchronize(P->stream);
-    if (P->d_h) (void)hipFree(P->d_h);
-    if (P->d_g) (void)hipFree(P->d_g);
-    if (P->d_binom) (void)hipFree(P->d_binom);
-    if (P->d_D) (void)hipFree(P->d_D);
+    if (P->swapped) sfci_problem_destroy(P->swapped);
+    if (!P->borrowed) {
+        if (P->d_h) (void)hipFree(P->d_h);
+        if (P->d_g) (void)hipFree(P->d_g);
+        if (P->d_binom) (void)hipFree(P->d_binom);
+        if (P->d_D) (void)hipFree(P->d_D);
+    }
     rowtile_release(P);
     DevBuf* bufs[] = {&P->ws_sel,   &P->ws_cnt,   &P->ws_scan,  &P->ws_scan2,  &P->ws_scalar, &P->ws_red,
                       &P->ws_tup_k, &P->ws_tup_v, &P->ws_tup_k2, &P->ws_tup_v2, &P->ws_seg_v, &P->ws_seg_f,
@@ -274,6 +277,7 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_beta.release();
     P->ws_rt_nbr.release();
     P->ws_rt_desc.release();
+    P->grad_ws.release();
     delete P;
     return SFCI_OK;
 }
@@ -577,8 +581,28 @@ sfci_status sfci_sigma_backward(sfci_problem* P, const sfci_svec* v, const sfci_
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, scal, (u64)v->nnz);
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, scal + 1, (u64)sbar->nnz);
     double* raw = (double*)P->ws_red.get((RAW_PAD + n2 + n4) * sizeof(double));
-    launch_scatter_set(P, P->d_D, sbar->rank, sbar->amp, scal + 1, std::max<u64>(1, sbar->nnz));
     SigmaLaunch sl{v->rank, v->amp, scal, v->nnz};
+    if (!v_bar && v->nnz && sbar->nnz && rowtile_grad_available(P)) {
+        // integral gradients only: the target-owned tile passes
+        GradJob J{};
+        J.P = P;
+        J.v = sl;
+        J.s_rank = sbar->rank;
+        J.s_amp = sbar->amp;
+        J.s_nnz = scal + 1;
+        J.s_cap = sbar->nnz;
+        J.Rh = raw + RAW_PAD;
+        J.Rg = raw + RAW_PAD + n2;
+        J.dh = dh;
+        J.dg = deri;
+        J.vt_rank = (u64*)P->ws_list_r.get(v->nnz * sizeof(u64));
+        J.vt_amp = (double*)P->ws_list_a.get(v->nnz * sizeof(double));
+        J.vt_nnz = scal + 2;
+        rowtile_gradients(P->stream, 1, &J, P->grad_ws);
+        sync(P);
+        return SFCI_OK;
+    }
+    launch_scatter_set(P, P->d_D, sbar->rank, sbar->amp, scal + 1, std::max<u64>(1, sbar->nnz));
     launch_backward_dense(P, sl, P->d_D, v_bar, dh, deri, raw + RAW_PAD, raw + RAW_PAD + n2);
     launch_scatter_zero(P, P->d_D, sbar->rank, scal + 1, std::max<u64>(1, sbar->nnz));
     sync(P);

@@ -161,6 +161,13 @@ void launch_backward_dense(sfci_problem* P, const SigmaLaunch& v, const double* 
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
+void launch_symmetrise(sfci_problem* P, const double* Rh, const double* Rg, double* dh, double* dg) {
+    const u64 n2 = (u64)P->n * P->n, n4 = n2 * n2;
+    if (!dh && !dg) return;
+    hipLaunchKernelGGL(k_symmetrise, dim3(gsz(n4)), dim3(256), 0, P->stream, P->n, Rh, Rg, dh, dg);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
 void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nnz, u64 cap) {
     hipLaunchKernelGGL(k_scatter_zero, dim3(gsz(cap)), dim3(256), 0, P->stream, D, r, nnz);
     SFCI_CHECK_HIP(hipGetLastError());

@@ -22,6 +22,7 @@ struct sfci_batch {
     hipStream_t own = nullptr;         // capture-capable stream used during a batched run
     std::vector<DevBuf> descs;  // per iteration step j: the n instance descriptions
     DevBuf prefix, counter, scratch;
+    RowTileGradWs grad_ws;
 };
 
 namespace {
@@ -31,7 +32,7 @@ struct Inst {
     u64 M, cap, tps;
     u64* Wr;
     double* Wa;
-    u64* sc;       // [0..nL) nnz of w_j, [32] emitted, [33] list count, [34] psi count, [35] sigma input entries
+    u64* sc;       // [0..nL) nnz of w_j, [32] emitted, [33] list count, [34] psi count, [35] sigma input entries, [36] transposed Psi count
     double* T;     // one block: T then S (n_L x n_L each)
     double* S;
     double* x;
@@ -90,6 +91,7 @@ sfci_status sfci_batch_destroy(sfci_batch* B) {
     B->prefix.release();
     B->counter.release();
     B->scratch.release();
+    B->grad_ws.release();
     if (B->own) (void)hipStreamDestroy(B->own);
     delete B;
     return SFCI_OK;
@@ -335,8 +337,12 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         else block_end(last);
     }
     SFCI_CHECK_HIP(hipEventRecord(e1, st));
-    // gradients of each instance's Rayleigh quotient at the final Psi
+    // gradients of each instance's Rayleigh quotient at the final Psi:
+    // sbar = Psi / <Psi|Psi>, v = Psi
     if (dh_all || deri_all) {
+        bool tiles = !det;
+        for (int k = 0; k < n && tiles; ++k) tiles = rowtile_grad_available(I[k].P);
+        std::vector<GradJob> jobs;
         u64 off_h = 0, off_g = 0;
         for (int k = 0; k < n; ++k) {
             Inst& q = I[k];
@@ -344,15 +350,35 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             const u64 pcap = std::min<u64>(P->Ndet, (u64)nL * q.cap);
             const u64 n2 = (u64)P->n * P->n, n4 = n2 * n2;
             double* raw = (double*)P->ws_red.get((2048 + n2 + n4) * sizeof(double));
+            double* dh = dh_all ? dh_all + off_h : nullptr;
+            double* dg = deri_all ? deri_all + off_g : nullptr;
             launch_div_by_sumsq(P, q.psi_a, q.sc + 34, pcap, q.sbar);
-            launch_scatter_set(P, P->d_D, q.psi_r, q.sbar, q.sc + 34, pcap);
-            launch_backward_dense(P, SigmaLaunch{q.psi_r, q.psi_a, q.sc + 34, pcap}, P->d_D, nullptr,
-                                  dh_all ? dh_all + off_h : nullptr, deri_all ? deri_all + off_g : nullptr,
-                                  raw + 2048, raw + 2048 + n2);
-            launch_scatter_zero(P, P->d_D, q.psi_r, q.sc + 34, pcap);
+            const SigmaLaunch psi{q.psi_r, q.psi_a, q.sc + 34, pcap};
+            if (tiles) {
+                GradJob J{};
+                J.P = P;
+                J.v = psi;
+                J.s_rank = q.psi_r;
+                J.s_amp = q.sbar;
+                J.s_nnz = q.sc + 34;
+                J.s_cap = pcap;
+                J.Rh = raw + 2048;
+                J.Rg = raw + 2048 + n2;
+                J.dh = dh;
+                J.dg = dg;
+                J.vt_rank = (u64*)P->ws_list_r.get(pcap * sizeof(u64));
+                J.vt_amp = (double*)P->ws_list_a.get(pcap * sizeof(double));
+                J.vt_nnz = q.sc + 36;
+                jobs.push_back(J);
+            } else {
+                launch_scatter_set(P, P->d_D, q.psi_r, q.sbar, q.sc + 34, pcap);
+                launch_backward_dense(P, psi, P->d_D, nullptr, dh, dg, raw + 2048, raw + 2048 + n2);
+                launch_scatter_zero(P, P->d_D, q.psi_r, q.sc + 34, pcap);
+            }
             off_h += n2;
             off_g += n4;
         }
+        if (tiles) rowtile_gradients(st, n, jobs.data(), B->grad_ws);
     }
     SFCI_CHECK_HIP(hipEventRecord(e2, st));
     // results

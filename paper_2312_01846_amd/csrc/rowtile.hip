@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "sfci_internal.h"
@@ -42,8 +43,10 @@ struct RTParams {
     const u64* tile_lo;    // ntiles + 1 rank boundaries
     int ntiles;
     int sB;                // beta singles per string
-    double* D;
+    double* D;                   // sigma: the output; gradient passes: the dense cotangent
     unsigned long long* emitted;
+    double* Rh;                  // gradient passes: raw dL/dh (n*n) and dL/d(pq|rs) (n^4)
+    double* Rg;
 };
 
 // One contributing source row of the current (target row, tile).
@@ -89,13 +92,31 @@ __device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec
     return diag_element(p.I, r.As, beta);
 }
 
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// Work modes of the row-tile kernel.
+//   RT_SIGMA: sigma = H v into the zero tile, written to D.
+//   RT_GRAD_A: gradient of L = sbar^T H v along the integrals for the terms
+//     that leave beta unchanged or are alpha-beta doubles: the diagonal, alpha
+//     singles, alpha-alpha doubles and alpha-beta doubles.  The tile holds sbar.
+//   RT_GRAD_B: the same for the rest (beta singles, beta-beta doubles), run on
+//     the spin-exchanged problem with the transposed vectors, where they are
+//     alpha singles and alpha-alpha doubles (identity row skipped).
+// A beta excitation's phase and element do not involve the alpha string
+// beyond its occupations, so exchanging the spins maps those terms exactly.
+enum { RT_SIGMA = 0, RT_GRAD_A = 1, RT_GRAD_B = 2 };
+
 // One launch serves one or many problem instances: item i belongs to the
 // instance whose [item_prefix[k], item_prefix[k+1]) holds it; a workgroup
 // reloads the instance description when consecutive items change instance.
-__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __restrict__ descs,
-                                                            const u64* __restrict__ item_prefix, int n_inst,
-                                                            unsigned* __restrict__ counter, void* nbr_scratch,
-                                                            u64 nbr_cap) {
+template <int MODE>
+__device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
+                                             int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
+                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
+    constexpr bool GRAD = MODE != RT_SIGMA;
     extern __shared__ double acc[];
     __shared__ BinomLds sB;
     __shared__ WaveScratch sw[RT_WAVES];
@@ -111,6 +132,12 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
     NbrRec* list = (NbrRec*)nbr_scratch + (u64)blockIdx.x * nbr_cap;
     const u64 total_items = item_prefix[n_inst];
     load_binom(sB, descs[0].binom);  // the binomial table is the same for every instance
+    // gradient passes: per wavefront, an n^2 slab of (j, b) weights (first
+    // pass only) and 32 per-orbital weights, after the tile; zero between uses
+    double* const wslab = acc + slab_off + (u32)wave * (slab_n2 + 32);
+    double* const wo = wslab + slab_n2;
+    if (GRAD)
+        for (u32 t = threadIdx.x; t < (u32)RT_WAVES * (slab_n2 + 32); t += RT_BLOCK) acc[slab_off + t] = 0.0;
     if (threadIdx.x == 0) s_cur = -1;
     u64 my_terms = 0;
 
@@ -170,7 +197,12 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
             if ((At >> q) & 1u) occA[__popc(At & below)] = (uint8_t)q;
             else virA[q - __popc(At & below)] = (uint8_t)q;
         }
-        for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
+        if (GRAD) {
+            const double* src = p.D + rAt * Nb + tlo;
+            for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = src[x];
+        } else {
+            for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
+        }
         __syncthreads();
 
         // Phase 1: the nonempty source rows, with their entry range in this tile.
@@ -223,18 +255,29 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                         // alpha double, source-occupied i<j -> source-virtual a<b (pairing i->a, j->b)
                         const u32 mid = As ^ (1u << i) ^ (1u << a);
                         const int par = between_parity(As, i, a) ^ between_parity(mid, j, b);
-                        double e = (p.I.G(i, a, j, b) - p.I.G(i, b, j, a));
-                        if (par) e = -e;
-                        r.cst = e;
-                        if (e == 0.0 || r.e1 <= r.e0) r.type = 255;
-                    } else if (type == 1) {
-                        double e = p.I.H(i, a);
-                        for (u32 m = As & ~(1u << i); m; m &= m - 1u) {
-                            int k = __builtin_ctz(m);
-                            e += (p.I.G(i, a, k, k) - p.I.G(i, k, k, a));
+                        r.par = (uint8_t)par;
+                        if (!GRAD) {
+                            double e = (p.I.G(i, a, j, b) - p.I.G(i, b, j, a));
+                            if (par) e = -e;
+                            r.cst = e;
+                            if (e == 0.0) r.type = 255;
                         }
-                        r.cst = e;
+                        // (a gradient pass keeps zero elements: their derivative need not vanish)
+                        if (r.e1 <= r.e0) r.type = 255;
+                    } else if (type == 1) {
+                        if (!GRAD) {
+                            double e = p.I.H(i, a);
+                            for (u32 m = As & ~(1u << i); m; m &= m - 1u) {
+                                int k = __builtin_ctz(m);
+                                e += (p.I.G(i, a, k, k) - p.I.G(i, k, k, a));
+                            }
+                            r.cst = e;
+                        }
                         r.par = (uint8_t)between_parity(As, i, a);
+                        if (MODE == RT_GRAD_B && r.e1 <= r.e0) r.type = 255;  // direct targets only
+                    } else if (GRAD) {
+                        // identity row: the diagonal in the first pass, nothing in the second
+                        if (MODE == RT_GRAD_B || r.e1 <= r.e0) r.type = 255;
                     }
                 }
             }
@@ -252,32 +295,131 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
 
         // Phase 2: direct targets (beta unchanged).  Short ranges: one thread
         // per source row; long ranges: one wavefront, lanes over the entries.
-        for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
-            const NbrRec r = list[li];
-            if (r.e1 - r.e0 > 32) continue;
-            const u64 baseS = (u64)r.rAs * Nb + tlo;
-            for (u32 k = r.e0; k < r.e1; ++k) {
-                const double e = direct_element(p, r, p.v_beta[k]);
-                if (e != 0.0) {
-                    atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
-                    ++my_terms;
+        if (!GRAD) {
+            for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
+                const NbrRec r = list[li];
+                if (r.e1 - r.e0 > 32) continue;
+                const u64 baseS = (u64)r.rAs * Nb + tlo;
+                for (u32 k = r.e0; k < r.e1; ++k) {
+                    const double e = direct_element(p, r, p.v_beta[k]);
+                    if (e != 0.0) {
+                        atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                        ++my_terms;
+                    }
                 }
             }
-        }
-        for (;;) {
-            unsigned li = 0;
-            if (lane == 0) li = atomicAdd(&s_next2, 1u);
-            li = __shfl(li, 0);
-            if (li >= nlist) break;
-            const NbrRec r = list[li];
-            if (r.e1 - r.e0 <= 32) continue;
-            const u64 baseS = (u64)r.rAs * Nb + tlo;
-            for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                const double e = direct_element(p, r, p.v_beta[k]);
-                if (e != 0.0) {
-                    atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
-                    ++my_terms;
+            for (;;) {
+                unsigned li = 0;
+                if (lane == 0) li = atomicAdd(&s_next2, 1u);
+                li = __shfl(li, 0);
+                if (li >= nlist) break;
+                const NbrRec r = list[li];
+                if (r.e1 - r.e0 <= 32) continue;
+                const u64 baseS = (u64)r.rAs * Nb + tlo;
+                for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
+                    const double e = direct_element(p, r, p.v_beta[k]);
+                    if (e != 0.0) {
+                        atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                        ++my_terms;
+                    }
                 }
+            }
+        } else {
+            // Gradient: every direct term of a source row shares the row's
+            // integrals up to the beta occupations, so the row reduces to
+            //   W = sum_k sbar(target_k) v_k,  O_q = same over entries with q occupied,
+            // and (identity row) P_pq over entries with p and q occupied.
+            const u32 n2 = (u32)n * n;
+            auto gi = [&](int a_, int b_, int c_, int d_) { return (((u32)a_ * n + b_) * n + c_) * n + d_; };
+            for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
+                const NbrRec r = list[li];
+                if (r.type != 2 || r.e1 - r.e0 > 32) continue;
+                const u64 baseS = (u64)r.rAs * Nb + tlo;
+                double w = 0.0;
+                for (u32 k = r.e0; k < r.e1; ++k) w += acc[p.v_rank[k] - baseS] * p.v_amp[k];
+                if (w != 0.0) {
+                    if (r.par) w = -w;
+                    atomicAdd(p.Rg + gi(r.i, r.a, r.j, r.b), w);
+                    atomicAdd(p.Rg + gi(r.i, r.b, r.j, r.a), -w);
+                }
+            }
+            double* slab = wslab;
+            for (;;) {
+                unsigned li = 0;
+                if (lane == 0) li = atomicAdd(&s_next2, 1u);
+                li = __shfl(li, 0);
+                if (li >= nlist) break;
+                const NbrRec r = list[li];
+                const int T = r.type;
+                if (T == 2 && r.e1 - r.e0 <= 32) continue;
+                if (r.e1 <= r.e0) continue;
+                const u64 baseS = (u64)r.rAs * Nb + tlo;
+                double wl = 0.0;
+                for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
+                    const double sb = acc[p.v_rank[k] - baseS];
+                    if (sb == 0.0) continue;
+                    const double w = sb * p.v_amp[k];
+                    wl += w;
+                    if (T != 2) {
+                        const u32 beta = p.v_beta[k];
+                        for (u32 m = beta; m; m &= m - 1u) {
+                            const int q = __builtin_ctz(m);
+                            atomicAdd(&wo[q], w);
+                            if (T == 0)
+                                for (u32 m2 = m & (m - 1u); m2; m2 &= m2 - 1u) atomicAdd(&slab[q * n + __builtin_ctz(m2)], w);
+                        }
+                    }
+                }
+                const double Wr = wave_sum(wl);
+                wave_sync();
+                if (T == 2) {
+                    if (lane == 0 && Wr != 0.0) {
+                        const double w = r.par ? -Wr : Wr;
+                        atomicAdd(p.Rg + gi(r.i, r.a, r.j, r.b), w);
+                        atomicAdd(p.Rg + gi(r.i, r.b, r.j, r.a), -w);
+                    }
+                } else if (T == 1) {
+                    // alpha single i -> a: h_ia + sum_{k in As\i} [(ia|kk) - (ik|ka)] + sum_{q in beta} (ia|qq)
+                    const int i = r.i, a = r.a;
+                    const double sg = r.par ? -1.0 : 1.0;
+                    if (lane < n) {
+                        const int q = lane;
+                        const bool spect = q != i && ((r.As >> q) & 1u);
+                        const double add = sg * (wo[q] + (spect ? Wr : 0.0));
+                        wo[q] = 0.0;
+                        if (add != 0.0) atomicAdd(p.Rg + gi(i, a, q, q), add);
+                        if (spect && Wr != 0.0) atomicAdd(p.Rg + gi(i, q, q, a), -sg * Wr);
+                    }
+                    if (lane == 0 && Wr != 0.0) atomicAdd(p.Rh + i * n + a, sg * Wr);
+                } else {
+                    // diagonal: sum_{p in A, B} h_pp + same-spin pairs [(pp|qq) - (pq|qp)] + alpha-beta (pp|qq)
+                    const u32 A = r.As;
+                    if (lane < n) {
+                        const int q = lane;
+                        const double oq = wo[q];
+                        wo[q] = 0.0;
+                        const double dh = oq + (((A >> q) & 1u) ? Wr : 0.0);
+                        if (dh != 0.0) atomicAdd(p.Rh + q * n + q, dh);
+                        if (oq != 0.0)
+                            for (u32 m = A; m; m &= m - 1u) atomicAdd(p.Rg + gi(__builtin_ctz(m), __builtin_ctz(m), q, q), oq);
+                        if (((A >> q) & 1u) && Wr != 0.0)
+                            for (u32 m = A & ~((2u << q) - 1u); m; m &= m - 1u) {
+                                const int q2 = __builtin_ctz(m);
+                                atomicAdd(p.Rg + gi(q, q, q2, q2), Wr);
+                                atomicAdd(p.Rg + gi(q, q2, q2, q), -Wr);
+                            }
+                    }
+                    for (u32 t = lane; t < n2; t += 64) {
+                        const double v = slab[t];
+                        if (v != 0.0) {
+                            const int q = (int)(t / n), q2 = (int)(t - (u32)q * n);
+                            atomicAdd(p.Rg + gi(q, q, q2, q2), v);
+                            atomicAdd(p.Rg + gi(q, q2, q2, q), -v);
+                            slab[t] = 0.0;
+                        }
+                    }
+                }
+                wave_sync();
             }
         }
 
@@ -286,15 +428,16 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
         // identity row's beta-beta doubles, RT_BB_CHUNK entries per unit, so
         // that every wavefront shares the largest single-row job.
         const u32 idb = s_idb, ide = s_ide;
-        const unsigned n_bb = (PB > 0 && QB > 0) ? (ide - idb + RT_BB_CHUNK - 1) / RT_BB_CHUNK : 0u;
+        const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + RT_BB_CHUNK - 1) / RT_BB_CHUNK : 0u;
+        const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : nlist + n_bb;
         const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
         const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
         for (;;) {
             unsigned li = 0;
             if (lane == 0) li = atomicAdd(&s_next, 1u);
             li = __shfl(li, 0);
-            if (li >= nlist + n_bb) break;
-            if (li >= nlist) {
+            if (li >= n_units) break;
+            if (!GRAD && li >= nlist) {
                 // beta-beta doubles of identity-row entries [k0, k1)
                 const u32 k0 = idb + (li - nlist) * RT_BB_CHUNK;
                 const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
@@ -341,8 +484,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
             }
             const NbrRec r = list[li];
             const int T = r.type;
-            if (T == 2) continue;
+            if (T == 2 || (GRAD && T == 0)) continue;
             const int I_ = r.i, A_ = r.a;
+            double* slab = wslab;  // gradient: this row's (j, b) weights
             const u32 S = r.As;
             const u64 baseS = (u64)r.rAs * Nb;
             if (whole_rows) {
@@ -372,6 +516,25 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                                     const u64 rbeta = rl64(rk, q + u) - baseS;
                                     if (act) te[u] = p.T1[rbeta * (u64)sBn + sidx];
                                 }
+                            }
+                            if (GRAD) {
+                                // alpha-beta double (ia|jb): weight sbar(target) v(source) with both phases
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) {
+                                    if (q + u < cnt) {
+                                        const double c = rlf64(ck, q + u);
+                                        if (act) {
+                                            const double sb = acc[(te[u] & 0xFFFFFFFFull) - tlo];
+                                            if (sb != 0.0) {
+                                                const int jj = (int)((te[u] >> 32) & 255), bb = (int)((te[u] >> 40) & 255);
+                                                double x = sb * c;
+                                                if (r.par ^ (int)((te[u] >> 48) & 1)) x = -x;
+                                                atomicAdd(&slab[jj * n + bb], x);
+                                            }
+                                        }
+                                    }
+                                }
+                                continue;
                             }
                             double e[RT_UNROLL];
 #pragma unroll
@@ -443,6 +606,15 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                             const u64 rt = te & 0xFFFFFFFFull;
                             const int jj = (int)((te >> 32) & 255), bb = (int)((te >> 40) & 255);
                             const int par_b = (int)((te >> 48) & 1);
+                            if (GRAD) {
+                                const double sb = acc[rt - tlo];
+                                if (sb != 0.0) {
+                                    double w = sb * W.c[x];
+                                    if (r.par ^ par_b) w = -w;
+                                    atomicAdd(&slab[jj * n + bb], w);
+                                }
+                                continue;
+                            }
                             double e;
                             if (T == 1) {
                                 e = p.I.G(I_, A_, jj, bb);
@@ -459,15 +631,52 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                     }
                 }
             }
+            if (GRAD) {
+                // flush this row's (j, b) weights into dL/d(ia|jb)
+                wave_sync();
+                const u32 n2 = (u32)n * n;
+                double* Rrow = p.Rg + ((u32)I_ * n + A_) * n2;
+                for (u32 t = lane; t < n2; t += 64) {
+                    const double v = slab[t];
+                    if (v != 0.0) {
+                        atomicAdd(Rrow + t, v);
+                        slab[t] = 0.0;
+                    }
+                }
+                wave_sync();
+            }
         }
         __syncthreads();
-        if (s_touched) {
+        if (!GRAD && s_touched) {
             double* dst = p.D + rAt * Nb + tlo;
             for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = acc[x];
         }
     }
     for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
     if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
+}
+
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __restrict__ descs,
+                                                            const u64* __restrict__ item_prefix, int n_inst,
+                                                            unsigned* __restrict__ counter, void* nbr_scratch,
+                                                            u64 nbr_cap) {
+    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, 0u, 0u);
+}
+
+// Integral gradients, first pass (alpha-side and alpha-beta terms).
+__global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a(const RTParams* __restrict__ descs,
+                                                             const u64* __restrict__ item_prefix, int n_inst,
+                                                             unsigned* __restrict__ counter, void* nbr_scratch,
+                                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
+    rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2);
+}
+
+// Integral gradients, second pass (beta-side terms on the spin-exchanged problem).
+__global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __restrict__ descs,
+                                                             const u64* __restrict__ item_prefix, int n_inst,
+                                                             unsigned* __restrict__ counter, void* nbr_scratch,
+                                                             u64 nbr_cap, unsigned slab_off) {
+    rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u);
 }
 
 // ---- per-problem tables ----
@@ -700,6 +909,8 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.sB = P->nb * (P->n - P->nb);
     rp.D = D;
     rp.emitted = emitted;
+    rp.Rh = nullptr;
+    rp.Rg = nullptr;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
@@ -740,4 +951,162 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
     void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
     rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
                 (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, d.lds_bytes, d.n_items);
+}
+
+// ---- integral gradients through the tiles ----
+namespace {
+
+// D[rank with alpha and beta exchanged] = a (or 0): rank = r_a * N_b + r_b
+// becomes r_b * N_a + r_a.
+__global__ void k_scatter_tr(double* __restrict__ D, const u64* __restrict__ r, const double* __restrict__ a,
+                             const u64* __restrict__ nnz, u64 Na, u64 Nb) {
+    const u64 n = *nnz;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        const u64 R = r[i];
+        const u64 ra = R / Nb, rb = R - ra * Nb;
+        D[rb * Na + ra] = a ? a[i] : 0.0;
+    }
+}
+
+size_t rt_static_lds() {
+    return sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + sizeof(RTParams) + 64;
+}
+
+unsigned g256(u64 n) { return (unsigned)std::max<u64>(1, std::min<u64>((n + 255) / 256, 16384)); }
+
+}  // namespace
+
+// The alpha/beta-exchanged shadow of P (created on first use).
+static sfci_problem* rowtile_swapped(sfci_problem* P) {
+    if (!P->swapped) {
+        auto* Q = new sfci_problem();
+        Q->n = P->n;
+        Q->na = P->nb;
+        Q->nb = P->na;
+        Q->Na = P->Nb;
+        Q->Nb = P->Na;
+        Q->Ndet = P->Ndet;
+        Q->kg = P->kg;
+        Q->device = P->device;
+        Q->num_cu = P->num_cu;
+        Q->borrowed = true;
+        P->swapped = Q;
+    }
+    sfci_problem* Q = P->swapped;
+    Q->stream = P->stream;
+    Q->d_h = P->d_h;
+    Q->d_g = P->d_g;
+    Q->d_binom = P->d_binom;
+    Q->d_D = P->d_D;
+    Q->dense_state = P->dense_state;
+    return Q;
+}
+
+bool rowtile_grad_available(sfci_problem* P) {
+    if (!P->d_D || !rowtile_available(P)) return false;
+    sfci_problem* Q = rowtile_swapped(P);
+    if (!rowtile_available(Q)) return false;
+    int maxlds = 0;
+    SFCI_CHECK_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
+    const size_t n2 = (size_t)P->n * P->n;
+    const size_t need_a = rt_state(P)->lds_bytes + RT_WAVES * (n2 + 32) * sizeof(double);
+    const size_t need_b = rt_state(Q)->lds_bytes + RT_WAVES * 32 * sizeof(double);
+    return std::max(need_a, need_b) + rt_static_lds() <= (size_t)maxlds;
+}
+
+namespace {
+
+// One launch of a gradient pass over all jobs' descriptions.
+void grad_pass(hipStream_t st, int pass, std::vector<RowTileDesc>& d, unsigned slab_n2, int num_cu,
+               RowTileGradWs& ws) {
+    const int n = (int)d.size();
+    std::vector<u64> pre(n + 1, 0);
+    u64 nbr_cap = 0;
+    size_t tile_bytes = 0;
+    for (int k = 0; k < n; ++k) {
+        pre[k + 1] = pre[k] + d[k].n_items;
+        nbr_cap = std::max(nbr_cap, d[k].nbr_cap);
+        tile_bytes = std::max(tile_bytes, d[k].lds_bytes);
+    }
+    tile_bytes = (tile_bytes + 15) & ~(size_t)15;
+    const unsigned slab_off = (unsigned)(tile_bytes / sizeof(double));
+    const size_t lds = tile_bytes + (size_t)RT_WAVES * (slab_n2 + 32) * sizeof(double);
+    const size_t db = sizeof(RTParams);
+    char* dd = (char*)ws.desc.get((size_t)n * db);
+    u64* dpre = (u64*)ws.prefix.get((size_t)(n + 1) * sizeof(u64));
+    unsigned* cnt = (unsigned*)ws.counter.get(64);
+    std::vector<unsigned char> host((size_t)n * db);
+    for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, d[k].raw, db);
+    SFCI_CHECK_HIP(hipMemcpyAsync(dd, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    SFCI_CHECK_HIP(hipMemcpyAsync(dpre, pre.data(), pre.size() * sizeof(u64), hipMemcpyHostToDevice, st));
+    launch_fill_u64((u64*)cnt, 1, 0, st);
+    const unsigned grid = rowtile_grid(num_cu, lds, pre[n]);
+    void* scr = ws.scratch.get(rowtile_scratch_bytes(grid, nbr_cap));
+    if (pass == 0) {
+        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_grad_rowtile_a, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+        hipLaunchKernelGGL(k_grad_rowtile_a, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt,
+                           scr, nbr_cap, slab_off, slab_n2);
+    } else {
+        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_grad_rowtile_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds));
+        hipLaunchKernelGGL(k_grad_rowtile_b, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt,
+                           scr, nbr_cap, slab_off);
+    }
+    SFCI_CHECK_HIP(hipGetLastError());
+    SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host staging buffer goes out of scope
+}
+
+}  // namespace
+
+void rowtile_gradients(hipStream_t st, int n_jobs, const GradJob* jobs, RowTileGradWs& ws) {
+    std::vector<RowTileDesc> d(n_jobs);
+    unsigned slab_n2 = 0;
+    int num_cu = 256;
+    // first pass: sbar dense in D, the sources are v
+    for (int k = 0; k < n_jobs; ++k) {
+        const GradJob& J = jobs[k];
+        sfci_problem* P = J.P;
+        if (P->stream != st) throw sfci_error(-1, "gradient jobs must run on the given stream");
+        const u64 n2 = (u64)P->n * P->n;
+        launch_fill_f64(J.Rh, n2, 0.0, st);
+        launch_fill_f64(J.Rg, n2 * n2, 0.0, st);
+        launch_scatter_set(P, P->d_D, J.s_rank, J.s_amp, J.s_nnz, J.s_cap);
+        d[k] = rowtile_prepare(P, J.v, P->d_D, nullptr);
+        RTParams& rp = *(RTParams*)d[k].raw;
+        rp.Rh = J.Rh;
+        rp.Rg = J.Rg;
+        slab_n2 = std::max(slab_n2, (unsigned)n2);
+        num_cu = P->num_cu;
+    }
+    grad_pass(st, 0, d, slab_n2, num_cu, ws);
+    // second pass: the spin-exchanged problem, transposed sbar and v
+    for (int k = 0; k < n_jobs; ++k) {
+        const GradJob& J = jobs[k];
+        sfci_problem* P = J.P;
+        launch_scatter_zero(P, P->d_D, J.s_rank, J.s_nnz, J.s_cap);
+        hipLaunchKernelGGL(k_scatter_tr, dim3(g256(J.v.cap)), dim3(256), 0, st, P->d_D, J.v.v_rank, J.v.v_amp,
+                           J.v.v_nnz, P->Na, P->Nb);
+        SFCI_CHECK_HIP(hipGetLastError());
+        CandSrc src{};
+        src.dense = P->d_D;
+        select_topm(P, src, UINT64_MAX, J.vt_rank, J.vt_amp, J.vt_nnz, true);  // sorted, and D back to zero
+        hipLaunchKernelGGL(k_scatter_tr, dim3(g256(J.s_cap)), dim3(256), 0, st, P->d_D, J.s_rank, J.s_amp, J.s_nnz,
+                           P->Na, P->Nb);
+        SFCI_CHECK_HIP(hipGetLastError());
+        sfci_problem* Q = rowtile_swapped(P);
+        d[k] = rowtile_prepare(Q, SigmaLaunch{J.vt_rank, J.vt_amp, J.vt_nnz, J.v.cap}, P->d_D, nullptr);
+        RTParams& rp = *(RTParams*)d[k].raw;
+        rp.Rh = J.Rh;
+        rp.Rg = J.Rg;
+    }
+    grad_pass(st, 1, d, 0u, num_cu, ws);
+    for (int k = 0; k < n_jobs; ++k) {
+        const GradJob& J = jobs[k];
+        sfci_problem* P = J.P;
+        hipLaunchKernelGGL(k_scatter_tr, dim3(g256(J.s_cap)), dim3(256), 0, st, P->d_D, J.s_rank,
+                           (const double*)nullptr, J.s_nnz, P->Na, P->Nb);
+        SFCI_CHECK_HIP(hipGetLastError());
+        launch_symmetrise(P, J.Rh, J.Rg, J.dh, J.dg);
+    }
 }

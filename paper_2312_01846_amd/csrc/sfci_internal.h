@@ -27,6 +27,12 @@ struct DevBuf {
     void release();
 };
 
+// Launch buffers of the gradient passes through the target-owned tiles.
+struct RowTileGradWs {
+    DevBuf desc, prefix, counter, scratch;
+    void release() { desc.release(); prefix.release(); counter.release(); scratch.release(); }
+};
+
 // Top-M selection state (device resident): a radix select over the 128-bit
 // key K = (bits(|c|) << rank_bits) | (N_det - 1 - rank), 11-bit digits from
 // the top, so that larger K = larger |c|, then lower rank.
@@ -67,6 +73,11 @@ struct sfci_problem {
     DevBuf ws_lz[8];
     DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr, ws_rt_desc;
     void* rowtile = nullptr;  // tables of the target-owned dense kernel (rowtile.hip)
+    // The same space with alpha and beta exchanged (gradient second pass):
+    // shares this problem's integrals, binomial table and dense array.
+    sfci_problem* swapped = nullptr;
+    RowTileGradWs grad_ws;
+    bool borrowed = false;  // true for such a shadow: d_h, d_g, d_binom, d_D belong to another problem
 };
 
 // ---- launchers (sigma.hip) ----
@@ -107,6 +118,28 @@ size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
                  unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items,
                  bool fill_counter = true);
+
+// Integral gradients through the target-owned tiles: for each job,
+// L = s^T H(h, g) v with s and v sparse (ascending unique ranks).  Raw
+// gradients accumulate into Rh (n^2) and Rg (n^4), which the call zeroes
+// first, and are then symmetrised into dh / dg (either may be NULL).  The
+// dense array of every problem must be zero on entry; it is zero on exit.
+// vt_* is scratch for the transposed v (capacity v.cap).
+struct GradJob {
+    sfci_problem* P;
+    SigmaLaunch v;
+    const u64* s_rank;
+    const double* s_amp;
+    const u64* s_nnz;
+    u64 s_cap;
+    double *Rh, *Rg, *dh, *dg;
+    u64* vt_rank;
+    double* vt_amp;
+    u64* vt_nnz;
+};
+bool rowtile_grad_available(sfci_problem* P);
+void rowtile_gradients(hipStream_t st, int n_jobs, const GradJob* jobs, RowTileGradWs& ws);
+void launch_symmetrise(sfci_problem* P, const double* Rh, const double* Rg, double* dh, double* dg);
 
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);
