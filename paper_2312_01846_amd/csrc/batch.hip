@@ -174,7 +174,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     B->descs.resize(nL);
     std::vector<RowTileDesc> descs(n);
     u64 total_items = 0, nbr_cap = 0;
-    size_t lds = 0;
+    RowTileGeom geom{};
     char* d_desc = nullptr;
     u64* d_pre = nullptr;
     unsigned* d_cnt = nullptr;
@@ -189,14 +189,14 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
                                        (unsigned long long*)(I[k].sc + 32));
             pre[k + 1] = pre[k] + descs[k].n_items;
             nbr_cap = std::max(nbr_cap, descs[k].nbr_cap);
-            lds = std::max(lds, descs[k].lds_bytes);
         }
         total_items = pre[n];
+        geom = rowtile_geom(descs.data(), n);
         const size_t db = rowtile_desc_bytes();
         d_desc = (char*)B->descs[j].get((size_t)n * db);
         d_pre = (u64*)B->prefix.get((size_t)(n + 1) * sizeof(u64));
         d_cnt = (unsigned*)B->counter.get(64);
-        d_scr = B->scratch.get(rowtile_scratch_bytes(rowtile_grid(B->P[0]->num_cu, lds, total_items), nbr_cap));
+        d_scr = B->scratch.get(rowtile_scratch_bytes(rowtile_grid(B->P[0]->num_cu, geom.lds, total_items), nbr_cap));
         if (upload) {
             std::vector<unsigned char> host((size_t)n * db);
             for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, descs[k].raw, db);
@@ -210,7 +210,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         if (batched_sigma) {
             // descriptions of step j (uploaded in the eager block; the
             // remaining launch parameters are the same for every step)
-            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, lds, total_items, false);
+            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, geom, total_items, false);
             return;
         }
         for (int k = 0; k < n; ++k) {

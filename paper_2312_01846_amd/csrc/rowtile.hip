@@ -35,6 +35,7 @@ struct RTParams {
     const u64* v_rank;
     const double* v_amp;
     const u32* v_beta;     // beta string of every input entry
+    const u32* v_rb;       // beta rank of every input entry (the rank within its alpha row)
     const u64* rowbeg;     // per alpha rank: first input entry of that row
     const u64* rowend;     // per alpha rank: one past the last (== rowbeg when empty)
     const u32* rtb;        // per alpha rank, ntiles + 1 entry offsets: first entry with beta rank >= tile_lo[t]
@@ -299,11 +300,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
                 const NbrRec r = list[li];
                 if (r.e1 - r.e0 > 32) continue;
-                const u64 baseS = (u64)r.rAs * Nb + tlo;
                 for (u32 k = r.e0; k < r.e1; ++k) {
-                    const double e = direct_element(p, r, p.v_beta[k]);
+                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k]);
                     if (e != 0.0) {
-                        atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                        atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
                         ++my_terms;
                     }
                 }
@@ -315,11 +315,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (li >= nlist) break;
                 const NbrRec r = list[li];
                 if (r.e1 - r.e0 <= 32) continue;
-                const u64 baseS = (u64)r.rAs * Nb + tlo;
                 for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                    const double e = direct_element(p, r, p.v_beta[k]);
+                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k]);
                     if (e != 0.0) {
-                        atomicAdd(&acc[p.v_rank[k] - baseS], e * p.v_amp[k]);
+                        atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
                         ++my_terms;
                     }
                 }
@@ -334,9 +333,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
                 const NbrRec r = list[li];
                 if (r.type != 2 || r.e1 - r.e0 > 32) continue;
-                const u64 baseS = (u64)r.rAs * Nb + tlo;
                 double w = 0.0;
-                for (u32 k = r.e0; k < r.e1; ++k) w += acc[p.v_rank[k] - baseS] * p.v_amp[k];
+                for (u32 k = r.e0; k < r.e1; ++k) w += acc[p.v_rb[k] - tlo] * p.v_amp[k];
                 if (w != 0.0) {
                     if (r.par) w = -w;
                     atomicAdd(p.Rg + gi(r.i, r.a, r.j, r.b), w);
@@ -353,10 +351,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const int T = r.type;
                 if (T == 2 && r.e1 - r.e0 <= 32) continue;
                 if (r.e1 <= r.e0) continue;
-                const u64 baseS = (u64)r.rAs * Nb + tlo;
                 double wl = 0.0;
                 for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                    const double sb = acc[p.v_rank[k] - baseS];
+                    const double sb = acc[p.v_rb[k] - tlo];
                     if (sb == 0.0) continue;
                     const double w = sb * p.v_amp[k];
                     wl += w;
@@ -486,9 +483,17 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             const int T = r.type;
             if (T == 2 || (GRAD && T == 0)) continue;
             const int I_ = r.i, A_ = r.a;
-            double* slab = wslab;  // gradient: this row's (j, b) weights
+            double* slab = wslab;  // gradient: this row's (j, b) weights; sigma: the (ia|..) slab
             const u32 S = r.As;
-            const u64 baseS = (u64)r.rAs * Nb;
+            const bool gs = !GRAD && T == 1 && slab_n2 != 0;
+            if (gs) {
+                // stage (ia|jb) for all j, b of this source row's alpha single
+                const u32 n2 = (u32)n * n;
+                const double* Gia = p.I.g + ((u32)I_ * n + A_) * n2;
+                wave_sync();
+                for (u32 t = lane; t < n2; t += 64) slab[t] = Gia[t];
+                wave_sync();
+            }
             if (whole_rows) {
                 // lanes over the single-excitation index; 64 entries at a time
                 // are loaded one per lane and taken in turn (readlane), with
@@ -498,11 +503,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     const bool act = sidx < sBn;
                     for (u32 kb = r.rowb; kb < r.rowe; kb += 64) {
                         const u32 kk = kb + lane;
-                        u64 rk = 0;
+                        u32 rk = 0;
                         double ck = 0.0;
                         u32 bk = 0;
                         if (kk < r.rowe) {
-                            rk = p.v_rank[kk];
+                            rk = p.v_rb[kk];
                             ck = p.v_amp[kk];
                             if (T == 0) bk = p.v_beta[kk];
                         }
@@ -513,7 +518,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             for (int u = 0; u < RT_UNROLL; ++u) {
                                 te[u] = 0;
                                 if (q + u < cnt) {
-                                    const u64 rbeta = rl64(rk, q + u) - baseS;
+                                    const u64 rbeta = rl32(rk, q + u);
                                     if (act) te[u] = p.T1[rbeta * (u64)sBn + sidx];
                                 }
                             }
@@ -546,7 +551,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                     const u32 bq = (T == 0) ? rl32(bk, q + u) : 0u;
                                     if (act) {
                                         if (T == 1) {
-                                            x = p.I.G(I_, A_, jj, bb);
+                                            x = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                             if (r.par ^ par_b) x = -x;
                                         } else {
                                             x = single_element_nophase(p.I, bq, S, jj, bb);
@@ -576,7 +581,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     u32 beta = 0;
                     double c = 0.0;
                     if (k < r.rowe) {
-                        const u64 rbeta = p.v_rank[k] - baseS;
+                        const u64 rbeta = p.v_rb[k];
                         const uint16_t* to = p.toff + rbeta * (u64)(p.ntiles + 1);
                         const unsigned o0 = to[tile], o1 = to[tile + 1];
                         len = o1 - o0;
@@ -617,7 +622,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             }
                             double e;
                             if (T == 1) {
-                                e = p.I.G(I_, A_, jj, bb);
+                                e = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                 if (r.par ^ par_b) e = -e;
                             } else {
                                 e = single_element_nophase(p.I, W.beta[x], S, jj, bb);
@@ -656,11 +661,13 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
 }
 
+// slab_n2 > 0: every wavefront stages the (ia|jb) slab of its alpha-single
+// source row in LDS at slab_off + wave * (slab_n2 + 32) doubles.
 __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __restrict__ descs,
                                                             const u64* __restrict__ item_prefix, int n_inst,
                                                             unsigned* __restrict__ counter, void* nbr_scratch,
-                                                            u64 nbr_cap) {
-    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, 0u, 0u);
+                                                            u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
+    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2);
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
@@ -728,7 +735,7 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
 // that tile or above.  rowbeg/rowend/rtb must be zero-filled beforehand.
 __global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __restrict__ r, const u64* __restrict__ nnz_p,
                        const u64* __restrict__ tile_lo, int ntiles, u64* __restrict__ rowbeg, u64* __restrict__ rowend,
-                       u32* __restrict__ rtb, u32* __restrict__ vbeta) {
+                       u32* __restrict__ rtb, u32* __restrict__ vbeta, u32* __restrict__ vrb) {
     __shared__ BinomLds sB;
     load_binom(sB, binom);
     __syncthreads();
@@ -739,6 +746,7 @@ __global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __
         const u64 ra = R / sp.Nb;
         const u64 rb = R - ra * sp.Nb;
         vbeta[k] = str_unrank(rb, sp.nb, sp.n, sB);
+        vrb[k] = (u32)rb;
         int t = 0;
         while (t + 1 < ntiles && tile_lo[t + 1] <= rb) ++t;
         u32* tb = rtb + ra * (u64)nt1;
@@ -767,8 +775,13 @@ u64 binom_u64(int a, int b) {
 
 }  // namespace
 
+static size_t rt_static_lds() {
+    return sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + sizeof(RTParams) + 64;
+}
+
 struct RowTileState {
     bool ready = false;
+    int maxlds = 0;
     int ntiles = 0;
     int tile_max = 0;
     size_t lds_bytes = 0;
@@ -838,7 +851,7 @@ bool rowtile_available(sfci_problem* P) {
     }
     int maxlds = 0;
     SFCI_CHECK_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
-    const size_t static_lds = sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + 64;
+    const size_t static_lds = rt_static_lds();
     static_assert(sizeof(NbrRec) == 40, "neighbour record layout");
     int tile_max = (int)(((size_t)maxlds - static_lds - 512) / sizeof(double));
     if (tile_max < 1024) return false;
@@ -855,8 +868,10 @@ bool rowtile_available(sfci_problem* P) {
     hipLaunchKernelGGL(k_build_T1, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
                        P->d_binom, S->d_tile_lo, S->ntiles, S->d_T1, S->d_toff);
     SFCI_CHECK_HIP(hipGetLastError());
-    SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_sigma_rowtile, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)S->lds_bytes));
+    S->maxlds = maxlds;
+    const int dyn_max = maxlds - (int)rt_static_lds();
+    for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b})
+        SFCI_CHECK_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_max));
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
     S->ready = true;
     return true;
@@ -884,11 +899,12 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     u64* rowbeg = (u64*)P->ws_rt_rows.get(words * sizeof(u64));
     u64* rowend = rowbeg + P->Na;
     u32* rtb = (u32*)(rowend + P->Na + 8);
-    u32* vbeta = (u32*)P->ws_rt_beta.get(cap * sizeof(u32));
+    u32* vbeta = (u32*)P->ws_rt_beta.get(2 * cap * sizeof(u32));
+    u32* vrb = vbeta + cap;
     launch_fill_u64(rowbeg, words, 0, P->stream);
     unsigned g = (unsigned)std::min<u64>((cap + 255) / 256, 16384);
     hipLaunchKernelGGL(k_rows, dim3(g), dim3(256), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, P->d_binom,
-                       v.v_rank, v.v_nnz, S->d_tile_lo, S->ntiles, rowbeg, rowend, rtb, vbeta);
+                       v.v_rank, v.v_nnz, S->d_tile_lo, S->ntiles, rowbeg, rowend, rtb, vbeta, vrb);
     SFCI_CHECK_HIP(hipGetLastError());
     RowTileDesc out;
     static_assert(sizeof(RTParams) <= sizeof(out.raw), "descriptor storage");
@@ -899,6 +915,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.v_rank = v.v_rank;
     rp.v_amp = v.v_amp;
     rp.v_beta = vbeta;
+    rp.v_rb = vrb;
     rp.rowbeg = rowbeg;
     rp.rowend = rowend;
     rp.rtb = rtb;
@@ -915,6 +932,8 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
     out.lds_bytes = S->lds_bytes;
+    out.n2 = (unsigned)(P->n * P->n);
+    out.max_lds = S->maxlds;
     return out;
 }
 
@@ -922,14 +941,29 @@ size_t rowtile_desc_bytes() { return sizeof(RTParams); }
 
 // One launch over n_inst instances whose descriptions (and the exclusive
 // prefix of their item counts, n_inst + 1 values) are already on the device.
+RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
+    size_t tile = 0;
+    unsigned n2 = 0;
+    int maxlds = 1 << 30;
+    for (int k = 0; k < n_inst; ++k) {
+        tile = std::max(tile, d[k].lds_bytes);
+        n2 = std::max(n2, d[k].n2);
+        maxlds = std::min(maxlds, d[k].max_lds);
+    }
+    tile = (tile + 15) & ~(size_t)15;
+    RowTileGeom g{tile, 0u, 0u};
+    const size_t with = tile + (size_t)RT_WAVES * (n2 + 32) * sizeof(double);
+    if (with + rt_static_lds() <= (size_t)maxlds) g = RowTileGeom{with, (unsigned)(tile / sizeof(double)), n2};
+    return g;
+}
+
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
-                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items,
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
                  bool fill_counter) {
     if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
-    const int per_cu = std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
-    const unsigned grid = (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
-    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), lds_bytes, stream, (const RTParams*)d_descs,
-                       d_prefix, n_inst, d_counter, scratch, nbr_cap);
+    const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items);
+    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream, (const RTParams*)d_descs,
+                       d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
@@ -947,10 +981,11 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
     u64 prefix[2] = {0, d.n_items};
     SFCI_CHECK_HIP(hipMemcpyAsync(buf, d.raw, sizeof(RTParams), hipMemcpyHostToDevice, P->stream));
     SFCI_CHECK_HIP(hipMemcpyAsync(buf + sizeof(RTParams), prefix, sizeof(prefix), hipMemcpyHostToDevice, P->stream));
-    const unsigned grid = rowtile_grid(P->num_cu, d.lds_bytes, d.n_items);
+    const RowTileGeom geom = rowtile_geom(&d, 1);
+    const unsigned grid = rowtile_grid(P->num_cu, geom.lds, d.n_items);
     void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
     rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
-                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, d.lds_bytes, d.n_items);
+                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items);
 }
 
 // ---- integral gradients through the tiles ----
@@ -968,9 +1003,6 @@ __global__ void k_scatter_tr(double* __restrict__ D, const u64* __restrict__ r, 
     }
 }
 
-size_t rt_static_lds() {
-    return sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + sizeof(RTParams) + 64;
-}
 
 unsigned g256(u64 n) { return (unsigned)std::max<u64>(1, std::min<u64>((n + 255) / 256, 16384)); }
 

@@ -108,15 +108,25 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
 struct RowTileDesc {
     alignas(8) unsigned char raw[256];  // kernel-side description of one instance
     u64 n_items, nbr_cap;
-    size_t lds_bytes;
+    size_t lds_bytes;  // the tile
+    unsigned n2;       // n^2 of the instance
+    int max_lds;       // LDS per workgroup on the device
 };
+// Launch geometry for a set of descriptions: dynamic LDS, and where the
+// per-wavefront integral slabs start (slab_n2 = 0: no slabs, the kernel
+// reads the integrals from global memory).
+struct RowTileGeom {
+    size_t lds;
+    unsigned slab_off, slab_n2;
+};
+RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
 size_t rowtile_desc_bytes();
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 // fill_counter = false: the caller has already zeroed *d_counter on the stream.
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
-                 unsigned* d_counter, void* scratch, u64 nbr_cap, size_t lds_bytes, u64 total_items,
+                 unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
                  bool fill_counter = true);
 
 // Integral gradients through the target-owned tiles: for each job,
