@@ -39,7 +39,7 @@ struct RTParams {
     const u64* rowbeg;     // per alpha rank: first input entry of that row
     const u64* rowend;     // per alpha rank: one past the last (== rowbeg when empty)
     const u32* rtb;        // per alpha rank, ntiles + 1 entry offsets: first entry with beta rank >= tile_lo[t]
-    const u64* T1;         // beta singles per beta rank, sorted: rank | j << 32 | b << 40 | par << 48
+    const u32* T1;         // beta singles per beta rank, sorted by target: rank | j << 21 | b << 26 | par << 31
     const uint16_t* toff;  // per beta rank, ntiles + 1 offsets into its T1 slice
     const u64* tile_lo;    // ntiles + 1 rank boundaries
     int ntiles;
@@ -48,6 +48,7 @@ struct RTParams {
     unsigned long long* emitted;
     double* Rh;                  // gradient passes: raw dL/dh (n*n) and dL/d(pq|rs) (n^4)
     double* Rg;
+    const double* K2;            // n^2: (pp|qq) - (pq|qp)
 };
 
 // One contributing source row of the current (target row, tile).
@@ -69,8 +70,15 @@ struct WaveScratch {
     uint8_t occ[32], vir[32];
 };
 
-// Entries of the identity row per beta-beta-double work unit.
+// Packed beta single (T1 entry): target beta rank, j (annihilated), b (created), phase.
+__device__ __forceinline__ u32 t1_rank(u32 t) { return t & 0x1FFFFFu; }
+__device__ __forceinline__ int t1_j(u32 t) { return (int)((t >> 21) & 31u); }
+__device__ __forceinline__ int t1_b(u32 t) { return (int)((t >> 26) & 31u); }
+__device__ __forceinline__ int t1_par(u32 t) { return (int)(t >> 31); }
+
+// Entries of the identity row per beta-beta-double and per beta-single work unit.
 constexpr unsigned RT_BB_CHUNK = 4;
+constexpr unsigned RT_B1_CHUNK = 16;
 // Input entries whose table reads are issued together in the beta-single loop.
 constexpr int RT_UNROLL = 4;
 
@@ -80,17 +88,42 @@ __device__ __forceinline__ double rlf64(double v, int l) { return __longlong_as_
 
 // Direct target (beta unchanged) of entry k of source row r: alpha double
 // (constant element), alpha single (alpha part + beta part), or the diagonal.
-__device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec& r, u32 beta) {
+// itab (LDS): K2[n^2] = (pp|qq) - (pq|qp) and J[n^2] = (pp|qq), hd[32] = h_pp
+// (per instance), then EA = sum of h_pp over the item's target alpha string.
+// The diagonal is summed in the same order as the reference formula (alpha
+// h_pp, beta h_pp, alpha pairs, beta pairs, alpha-beta), so its bits match.
+// gq: this wavefront's (ia|qq), q = 0..n-1, for its alpha-single row (or NULL).
+__device__ __forceinline__ double direct_element(const RTParams& p, const NbrRec& r, u32 beta, const double* itab,
+                                                 const double* gq) {
     if (r.type == 2) return r.cst;
+    const int n = p.sp.n;
     if (r.type == 1) {
         double e = r.cst;
         for (u32 m = beta; m; m &= m - 1u) {
             int q = __builtin_ctz(m);
-            e += p.I.G(r.i, r.a, q, q);
+            e += gq ? gq[q] : p.I.G(r.i, r.a, q, q);
         }
         return r.par ? -e : e;
     }
-    return diag_element(p.I, r.As, beta);
+    const double* K2 = itab;
+    const double* J = itab + n * n;
+    const double* hd = J + n * n;
+    const u32 A = r.As;
+    double e = hd[32];
+    for (u32 m = beta; m; m &= m - 1u) e += hd[__builtin_ctz(m)];
+    for (u32 m = A; m; m &= m - 1u) {
+        const int q = __builtin_ctz(m);
+        for (u32 m2 = m & (m - 1u); m2; m2 &= m2 - 1u) e += K2[q * n + __builtin_ctz(m2)];
+    }
+    for (u32 m = beta; m; m &= m - 1u) {
+        const int q = __builtin_ctz(m);
+        for (u32 m2 = m & (m - 1u); m2; m2 &= m2 - 1u) e += K2[q * n + __builtin_ctz(m2)];
+    }
+    for (u32 m = A; m; m &= m - 1u) {
+        const double* Jq = J + __builtin_ctz(m) * n;
+        for (u32 m2 = beta; m2; m2 &= m2 - 1u) e += Jq[__builtin_ctz(m2)];
+    }
+    return e;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -116,9 +149,10 @@ enum { RT_SIGMA = 0, RT_GRAD_A = 1, RT_GRAD_B = 2 };
 template <int MODE>
 __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
                                              int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
-                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
+                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off) {
     constexpr bool GRAD = MODE != RT_SIGMA;
     extern __shared__ double acc[];
+    double* const itab = acc + itab_off;  // sigma: per-item element tables
     __shared__ BinomLds sB;
     __shared__ WaveScratch sw[RT_WAVES];
     __shared__ uint8_t occA[32], virA[32];
@@ -175,6 +209,15 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (int t = threadIdx.x; t < nva_ * (nva_ - 1) / 2; t += RT_BLOCK) pairVA[t] = decode_pair(t, nva_);
             for (int t = threadIdx.x; t < nb_ * (nb_ - 1) / 2; t += RT_BLOCK) pairNB[t] = decode_pair(t, nb_);
             for (int t = threadIdx.x; t < nvb_ * (nvb_ - 1) / 2; t += RT_BLOCK) pairVB[t] = decode_pair(t, nvb_);
+            if (!GRAD) {
+                const int n_ = p.sp.n, n2_ = n_ * n_;
+                for (int t = threadIdx.x; t < n2_; t += RT_BLOCK) {
+                    const int q = t / n_, q2 = t - q * n_;
+                    itab[t] = p.K2[t];
+                    itab[n2_ + t] = p.I.G(q, q, q2, q2);
+                }
+                for (int t = threadIdx.x; t < n_; t += RT_BLOCK) itab[2 * n2_ + t] = p.I.H(t, t);
+            }
             if (threadIdx.x == 0) s_cur = s_inst;
             __syncthreads();
         }
@@ -289,6 +332,12 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             slot0 = __shfl(slot0, 0);
             if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
         }
+        if (!GRAD && threadIdx.x == RT_BLOCK - 1) {
+            // the alpha h_pp of the diagonal, summed from zero in ascending order
+            double x = 0.0;
+            for (u32 m = At; m; m &= m - 1u) x += p.I.H(__builtin_ctz(m), __builtin_ctz(m));
+            itab[2 * n * n + 32] = x;
+        }
         __syncthreads();
         const unsigned nlist = s_nlist;
         if (nlist == 0) continue;  // nothing lands here: D stays zero
@@ -301,7 +350,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const NbrRec r = list[li];
                 if (r.e1 - r.e0 > 32) continue;
                 for (u32 k = r.e0; k < r.e1; ++k) {
-                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k]);
+                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k], itab, nullptr);
                     if (e != 0.0) {
                         atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
                         ++my_terms;
@@ -315,8 +364,16 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (li >= nlist) break;
                 const NbrRec r = list[li];
                 if (r.e1 - r.e0 <= 32) continue;
+                const double* gq = nullptr;
+                if (r.type == 1) {
+                    // this row's (ia|qq), q = 0..n-1
+                    wave_sync();
+                    if (lane < n) wo[lane] = p.I.G(r.i, r.a, lane, lane);
+                    wave_sync();
+                    gq = wo;
+                }
                 for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k]);
+                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k], itab, gq);
                     if (e != 0.0) {
                         atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
                         ++my_terms;
@@ -425,8 +482,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         // identity row's beta-beta doubles, RT_BB_CHUNK entries per unit, so
         // that every wavefront shares the largest single-row job.
         const u32 idb = s_idb, ide = s_ide;
+        const unsigned n_b1 = (!GRAD && ide > idb) ? (ide - idb + RT_B1_CHUNK - 1) / RT_B1_CHUNK : 0u;
         const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + RT_BB_CHUNK - 1) / RT_BB_CHUNK : 0u;
-        const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : nlist + n_bb;
+        const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : nlist + n_b1 + n_bb;
         const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
         const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
         for (;;) {
@@ -434,9 +492,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             if (lane == 0) li = atomicAdd(&s_next, 1u);
             li = __shfl(li, 0);
             if (li >= n_units) break;
-            if (!GRAD && li >= nlist) {
+            if (!GRAD && li >= nlist + n_b1) {
                 // beta-beta doubles of identity-row entries [k0, k1)
-                const u32 k0 = idb + (li - nlist) * RT_BB_CHUNK;
+                const u32 k0 = idb + (li - nlist - n_b1) * RT_BB_CHUNK;
                 const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
                 for (u32 k = k0; k < k1; ++k) {
                     const u32 beta = p.v_beta[k];
@@ -479,12 +537,26 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 }
                 continue;
             }
-            const NbrRec r = list[li];
+            NbrRec r;
+            if (!GRAD && li >= nlist) {
+                // beta singles of identity-row entries, RT_B1_CHUNK per unit
+                const u32 k0 = idb + (li - nlist) * RT_B1_CHUNK;
+                r.As = At;
+                r.rAs = (u32)rAt;
+                r.rowb = k0;
+                r.rowe = min(ide, k0 + RT_B1_CHUNK);
+                r.e0 = r.e1 = 0;
+                r.cst = 0.0;
+                r.type = 0;
+                r.i = r.a = r.j = r.b = 0;
+                r.par = 0;
+            } else {
+                r = list[li];
+                if (r.type != 1) continue;  // alpha doubles: direct only; the identity row: chunks above
+            }
             const int T = r.type;
-            if (T == 2 || (GRAD && T == 0)) continue;
             const int I_ = r.i, A_ = r.a;
             double* slab = wslab;  // gradient: this row's (j, b) weights; sigma: the (ia|..) slab
-            const u32 S = r.As;
             const bool gs = !GRAD && T == 1 && slab_n2 != 0;
             if (gs) {
                 // stage (ia|jb) for all j, b of this source row's alpha single
@@ -513,7 +585,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         }
                         const int cnt = (int)min(64u, r.rowe - kb);
                         for (int q = 0; q < cnt; q += RT_UNROLL) {
-                            u64 te[RT_UNROLL];
+                            u32 te[RT_UNROLL];
 #pragma unroll
                             for (int u = 0; u < RT_UNROLL; ++u) {
                                 te[u] = 0;
@@ -529,11 +601,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                     if (q + u < cnt) {
                                         const double c = rlf64(ck, q + u);
                                         if (act) {
-                                            const double sb = acc[(te[u] & 0xFFFFFFFFull) - tlo];
+                                            const double sb = acc[t1_rank(te[u]) - tlo];
                                             if (sb != 0.0) {
-                                                const int jj = (int)((te[u] >> 32) & 255), bb = (int)((te[u] >> 40) & 255);
+                                                const int jj = t1_j(te[u]), bb = t1_b(te[u]);
                                                 double x = sb * c;
-                                                if (r.par ^ (int)((te[u] >> 48) & 1)) x = -x;
+                                                if (r.par ^ t1_par(te[u])) x = -x;
                                                 atomicAdd(&slab[jj * n + bb], x);
                                             }
                                         }
@@ -544,8 +616,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             double e[RT_UNROLL];
 #pragma unroll
                             for (int u = 0; u < RT_UNROLL; ++u) {
-                                const int jj = (int)((te[u] >> 32) & 255), bb = (int)((te[u] >> 40) & 255);
-                                const int par_b = (int)((te[u] >> 48) & 1);
+                                const int jj = t1_j(te[u]), bb = t1_b(te[u]);
+                                const int par_b = t1_par(te[u]);
                                 double x = 0.0;
                                 if (q + u < cnt) {
                                     const u32 bq = (T == 0) ? rl32(bk, q + u) : 0u;
@@ -554,7 +626,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                             x = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                             if (r.par ^ par_b) x = -x;
                                         } else {
-                                            x = single_element_nophase(p.I, bq, S, jj, bb);
+                                            x = single_element_nophase(p.I, bq, At, jj, bb);
                                             if (par_b) x = -x;
                                         }
                                     }
@@ -566,7 +638,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 if (q + u < cnt) {
                                     const double c = rlf64(ck, q + u);
                                     if (e[u] != 0.0) {
-                                        atomicAdd(&acc[(te[u] & 0xFFFFFFFFull) - tlo], e[u] * c);
+                                        atomicAdd(&acc[t1_rank(te[u]) - tlo], e[u] * c);
                                         ++my_terms;
                                     }
                                 }
@@ -607,10 +679,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         const unsigned q = q0 + lane;
                         if (q < total) {
                             while (W.incl[x] <= q) ++x;
-                            const u64 te = p.T1[W.start[x] + (q - W.excl[x])];
-                            const u64 rt = te & 0xFFFFFFFFull;
-                            const int jj = (int)((te >> 32) & 255), bb = (int)((te >> 40) & 255);
-                            const int par_b = (int)((te >> 48) & 1);
+                            const u32 te = p.T1[W.start[x] + (q - W.excl[x])];
+                            const u32 rt = t1_rank(te);
+                            const int jj = t1_j(te), bb = t1_b(te);
+                            const int par_b = t1_par(te);
                             if (GRAD) {
                                 const double sb = acc[rt - tlo];
                                 if (sb != 0.0) {
@@ -625,7 +697,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 e = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                 if (r.par ^ par_b) e = -e;
                             } else {
-                                e = single_element_nophase(p.I, W.beta[x], S, jj, bb);
+                                e = single_element_nophase(p.I, W.beta[x], At, jj, bb);
                                 if (par_b) e = -e;
                             }
                             if (e != 0.0) {
@@ -666,8 +738,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
 __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __restrict__ descs,
                                                             const u64* __restrict__ item_prefix, int n_inst,
                                                             unsigned* __restrict__ counter, void* nbr_scratch,
-                                                            u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
-    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2);
+                                                            u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
+                                                            unsigned itab_off) {
+    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, itab_off);
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
@@ -675,7 +748,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a(const RTParams* __r
                                                              const u64* __restrict__ item_prefix, int n_inst,
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
-    rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2);
+    rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, 0u);
 }
 
 // Integral gradients, second pass (beta-side terms on the spin-exchanged problem).
@@ -683,7 +756,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
                                                              const u64* __restrict__ item_prefix, int n_inst,
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off) {
-    rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u);
+    rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u, 0u);
 }
 
 // ---- per-problem tables ----
@@ -691,7 +764,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
 // offsets into that sorted slice.  One wavefront per beta string; the sort is
 // a rank-by-counting over at most 256 distinct keys.
 __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restrict__ binom, const u64* __restrict__ tile_lo,
-                                                 int ntiles, u64* __restrict__ T1, uint16_t* __restrict__ toff) {
+                                                 int ntiles, u32* __restrict__ T1, uint16_t* __restrict__ toff) {
     __shared__ BinomLds sB;
     __shared__ u64 key[SFCI_MAX_SINGLES];
     __shared__ uint8_t occ[32], vir[32];
@@ -719,7 +792,9 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
             const u64 me = key[t] & 0xFFFFFFFFull;
             int pos = 0;
             for (int u = 0; u < sBn; ++u) pos += ((key[u] & 0xFFFFFFFFull) < me) ? 1 : 0;
-            T1[rb * (u64)sBn + pos] = key[t];
+            const u64 kt = key[t];
+            T1[rb * (u64)sBn + pos] = (u32)(kt & 0xFFFFFFFFull) | ((u32)((kt >> 32) & 31) << 21) |
+                                      ((u32)((kt >> 40) & 31) << 26) | ((u32)((kt >> 48) & 1) << 31);
         }
         for (int t = lane; t <= ntiles; t += 64) {
             const u64 lo = tile_lo[t];
@@ -727,6 +802,16 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
             for (int u = 0; u < sBn; ++u) cnt += ((key[u] & 0xFFFFFFFFull) < lo) ? 1 : 0;
             toff[rb * (u64)(ntiles + 1) + t] = (uint16_t)cnt;
         }
+    }
+}
+
+// K2[p][q] = (pp|qq) - (pq|qp), rounded exactly as in the diagonal element.
+__global__ void k_build_K(int n, const double* __restrict__ g, double* __restrict__ K) {
+    const u64 n2 = (u64)n * n, t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    auto G = [&](int a, int b, int c, int d) { return g[(((u64)a * n + b) * n + c) * n + d]; };
+    if (t < n2) {
+        const int p = (int)(t / n), q = (int)(t % n);
+        K[t] = (G(p, p, q, q) - G(p, q, q, p));
     }
 }
 
@@ -775,6 +860,8 @@ u64 binom_u64(int a, int b) {
 
 }  // namespace
 
+static unsigned rt_itab_doubles(unsigned n2) { return (2 * n2 + 40 + 1) & ~1u; }
+
 static size_t rt_static_lds() {
     return sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + sizeof(RTParams) + 64;
 }
@@ -787,7 +874,8 @@ struct RowTileState {
     size_t lds_bytes = 0;
     std::vector<u64> tile_lo;
     u64* d_tile_lo = nullptr;
-    u64* d_T1 = nullptr;
+    u32* d_T1 = nullptr;
+    double* d_K = nullptr;  // (pp|qq) - (pq|qp), n^2
     uint16_t* d_toff = nullptr;
 };
 
@@ -842,7 +930,8 @@ static void plan_tiles(sfci_problem* P, RowTileState* S, int tile_max) {
 }
 
 bool rowtile_available(sfci_problem* P) {
-    if (P->n > 32 || P->nb * (P->n - P->nb) > SFCI_MAX_SINGLES) return false;
+    // the packed single-excitation table holds a target beta rank in 21 bits
+    if (P->n > 32 || P->nb * (P->n - P->nb) > SFCI_MAX_SINGLES || P->Nb >= (1ull << 21)) return false;
     RowTileState* S = rt_state(P);
     if (S && S->ready) return true;
     if (!S) {
@@ -853,7 +942,9 @@ bool rowtile_available(sfci_problem* P) {
     SFCI_CHECK_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
     const size_t static_lds = rt_static_lds();
     static_assert(sizeof(NbrRec) == 40, "neighbour record layout");
-    int tile_max = (int)(((size_t)maxlds - static_lds - 512) / sizeof(double));
+    // room for the element tables and the per-wavefront 32-double areas
+    const size_t reserve = (rt_itab_doubles((unsigned)(P->n * P->n)) + RT_WAVES * 32) * sizeof(double);
+    int tile_max = (int)(((size_t)maxlds - static_lds - reserve - 512) / sizeof(double));
     if (tile_max < 1024) return false;
     tile_max = std::min(tile_max, 16384);
     if (const char* env = getenv("SFCI_TILE_MAX")) tile_max = std::max(1024, std::min(tile_max, atoi(env)));
@@ -862,11 +953,15 @@ bool rowtile_available(sfci_problem* P) {
     const u64 sBn = (u64)P->nb * (P->n - P->nb);
     SFCI_CHECK_HIP(hipMalloc(&S->d_tile_lo, S->tile_lo.size() * sizeof(u64)));
     SFCI_CHECK_HIP(hipMemcpy(S->d_tile_lo, S->tile_lo.data(), S->tile_lo.size() * sizeof(u64), hipMemcpyHostToDevice));
-    SFCI_CHECK_HIP(hipMalloc(&S->d_T1, std::max<u64>(1, P->Nb * sBn) * sizeof(u64)));
+    SFCI_CHECK_HIP(hipMalloc(&S->d_T1, std::max<u64>(1, P->Nb * sBn) * sizeof(u32)));
     SFCI_CHECK_HIP(hipMalloc(&S->d_toff, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
     unsigned g = (unsigned)std::min<u64>(P->Nb, (u64)P->num_cu * 16);
     hipLaunchKernelGGL(k_build_T1, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
                        P->d_binom, S->d_tile_lo, S->ntiles, S->d_T1, S->d_toff);
+    SFCI_CHECK_HIP(hipGetLastError());
+    const u64 nK = (u64)P->n * P->n;
+    SFCI_CHECK_HIP(hipMalloc(&S->d_K, nK * sizeof(double)));
+    hipLaunchKernelGGL(k_build_K, dim3((unsigned)((nK + 255) / 256)), dim3(256), 0, P->stream, P->n, P->d_g, S->d_K);
     SFCI_CHECK_HIP(hipGetLastError());
     S->maxlds = maxlds;
     const int dyn_max = maxlds - (int)rt_static_lds();
@@ -882,6 +977,7 @@ void rowtile_release(sfci_problem* P) {
     if (!S) return;
     if (S->d_tile_lo) (void)hipFree(S->d_tile_lo);
     if (S->d_T1) (void)hipFree(S->d_T1);
+    if (S->d_K) (void)hipFree(S->d_K);
     if (S->d_toff) (void)hipFree(S->d_toff);
     delete S;
     P->rowtile = nullptr;
@@ -928,6 +1024,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.emitted = emitted;
     rp.Rh = nullptr;
     rp.Rg = nullptr;
+    rp.K2 = S->d_K;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
@@ -950,10 +1047,14 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
         n2 = std::max(n2, d[k].n2);
         maxlds = std::min(maxlds, d[k].max_lds);
     }
+    // [tile | element tables: 2 n^2 + 40 | per wavefront: (ia|jb) slab (optional) + 32]
     tile = (tile + 15) & ~(size_t)15;
-    RowTileGeom g{tile, 0u, 0u};
-    const size_t with = tile + (size_t)RT_WAVES * (n2 + 32) * sizeof(double);
-    if (with + rt_static_lds() <= (size_t)maxlds) g = RowTileGeom{with, (unsigned)(tile / sizeof(double)), n2};
+    const unsigned itab_off = (unsigned)(tile / sizeof(double));
+    const unsigned slab_off = itab_off + rt_itab_doubles(n2);
+    const size_t base = (size_t)slab_off * sizeof(double);
+    RowTileGeom g{base + (size_t)RT_WAVES * 32 * sizeof(double), slab_off, 0u, itab_off};
+    const size_t with = base + (size_t)RT_WAVES * (n2 + 32) * sizeof(double);
+    if (with + rt_static_lds() <= (size_t)maxlds) g.lds = with, g.slab_n2 = n2;
     return g;
 }
 
@@ -963,7 +1064,7 @@ void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64*
     if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
     const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items);
     hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream, (const RTParams*)d_descs,
-                       d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2);
+                       d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 

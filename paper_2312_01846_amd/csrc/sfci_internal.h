@@ -118,6 +118,7 @@ struct RowTileDesc {
 struct RowTileGeom {
     size_t lds;
     unsigned slab_off, slab_n2;
+    unsigned itab_off;  // per-item element tables
 };
 RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
