@@ -189,115 +189,161 @@ __global__ void k_copy_vec(const u64* __restrict__ r, const double* __restrict__
     if (blockIdx.x == 0 && threadIdx.x == 0) *nnz2 = n;
 }
 
-// ---- generalized eigenproblem, one thread (m <= 32) ----
+// ---- generalized eigenproblem, one wavefront (m <= 32) ----
 #define GE_MAX 32
 
 // Cyclic Jacobi on the m x m symmetric matrix A (row-major, stride GE_MAX),
 // eigenvectors into V's columns, eigenvalues into w.  Same rotation rule,
-// sweep order and stopping rule as the CPU reference.
-__device__ void jacobi_dev(int m, double (*A)[GE_MAX], double (*V)[GE_MAX], double* w) {
-    for (int p = 0; p < m; ++p)
-        for (int q = 0; q < m; ++q) V[p][q] = (p == q) ? 1.0 : 0.0;
+// sweep order and stopping rule as the CPU reference.  Lane r updates row r
+// of every rotation; the rows are independent, so the results are the same
+// bits as a sequential sweep.
+__device__ void jacobi_dev(int m, double (*A)[GE_MAX], double (*V)[GE_MAX], double* w, int* flag) {
+    const int r = threadIdx.x;
+    if (r < m)
+        for (int q = 0; q < m; ++q) V[r][q] = (r == q) ? 1.0 : 0.0;
+    wave_sync();
     for (int sweep = 0; sweep < 64; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int p = 0; p < m; ++p) {
-            dg += A[p][p] * A[p][p];
-            for (int q = p + 1; q < m; ++q) off += A[p][q] * A[p][q];
+        if (r == 0) {
+            double off = 0.0, dg = 0.0;
+            for (int p = 0; p < m; ++p) {
+                dg += A[p][p] * A[p][p];
+                for (int q = p + 1; q < m; ++q) off += A[p][q] * A[p][q];
+            }
+            *flag = (off <= 1e-30 * dg) ? 1 : 0;
         }
-        if (off <= 1e-30 * dg) break;
+        wave_sync();
+        if (*flag) break;
         for (int p = 0; p < m; ++p)
             for (int q = p + 1; q < m; ++q) {
-                double apq = A[p][q];
+                const double apq = A[p][q];
                 if (apq == 0.0) continue;
-                double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                const double app = A[p][p], aqq = A[q][q];
+                const double theta = (aqq - app) / (2.0 * apq);
                 double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
                 if (theta < 0.0) t = -t;
-                double c = 1.0 / sqrt(t * t + 1.0);
-                double s = t * c;
-                double tau = s / (1.0 + c);
-                A[p][p] = A[p][p] - t * apq;
-                A[q][q] = A[q][q] + t * apq;
-                A[p][q] = 0.0;
-                A[q][p] = 0.0;
-                for (int r = 0; r < m; ++r) {
-                    if (r == p || r == q) continue;
-                    double arp = A[r][p], arq = A[r][q];
-                    double nrp = arp - s * (arq + tau * arp);
-                    double nrq = arq + s * (arp - tau * arq);
+                const double c = 1.0 / sqrt(t * t + 1.0);
+                const double s = t * c;
+                const double tau = s / (1.0 + c);
+                const bool row = r < m && r != p && r != q;
+                double arp = 0.0, arq = 0.0, vrp = 0.0, vrq = 0.0;
+                if (row) {
+                    arp = A[r][p];
+                    arq = A[r][q];
+                }
+                if (r < m) {
+                    vrp = V[r][p];
+                    vrq = V[r][q];
+                }
+                wave_sync();  // every read of this rotation before any write
+                if (r == 0) {
+                    A[p][p] = app - t * apq;
+                    A[q][q] = aqq + t * apq;
+                    A[p][q] = 0.0;
+                    A[q][p] = 0.0;
+                }
+                if (row) {
+                    const double nrp = arp - s * (arq + tau * arp);
+                    const double nrq = arq + s * (arp - tau * arq);
                     A[r][p] = nrp;
                     A[p][r] = nrp;
                     A[r][q] = nrq;
                     A[q][r] = nrq;
                 }
-                for (int r = 0; r < m; ++r) {
-                    double vrp = V[r][p], vrq = V[r][q];
+                if (r < m) {
                     V[r][p] = vrp - s * (vrq + tau * vrp);
                     V[r][q] = vrq + s * (vrp - tau * vrq);
                 }
+                wave_sync();
             }
     }
-    for (int p = 0; p < m; ++p) w[p] = A[p][p];
+    if (r < m) w[r] = A[r][r];
+    wave_sync();
 }
 
 // Canonical orthogonalisation: S = U s U^T, keep s_k > 1e-10 max s,
 // X = U_k s_k^(-1/2), Jacobi on X^T T X, x = X y for the lowest eigenvalue,
 // sign fixed so that the largest |x_i| (lowest i on ties) is positive.
-__global__ void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S, double* lambda,
-                         double* x, double* energy_slot, const int* blk, int* status) {
+// One wavefront; every sum keeps the reference's order.
+__global__ __launch_bounds__(64) void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S,
+                                               double* lambda, double* x, double* energy_slot, const int* blk,
+                                               int* status) {
     __shared__ double A[GE_MAX][GE_MAX], U[GE_MAX][GE_MAX], X[GE_MAX][GE_MAX], TX[GE_MAX][GE_MAX];
     __shared__ double sv[GE_MAX], lam[GE_MAX], xs[GE_MAX];
     __shared__ int keep[GE_MAX];
-    if (threadIdx.x != 0) return;
-    for (int i = 0; i < m; ++i)
+    __shared__ int s_r, s_best, s_flag;
+    const int i = threadIdx.x;
+    if (i < m)
         for (int j = 0; j < m; ++j) A[i][j] = S[i * m + j];
-    jacobi_dev(m, A, U, sv);
-    double smax = 0.0;
-    for (int k = 0; k < m; ++k)
-        if (sv[k] > smax) smax = sv[k];
-    int r = 0;
-    for (int k = 0; k < m; ++k)
-        if (sv[k] > 1e-10 * smax) keep[r++] = k;
+    wave_sync();
+    jacobi_dev(m, A, U, sv, &s_flag);
+    if (i == 0) {
+        double smax = 0.0;
+        for (int k = 0; k < m; ++k)
+            if (sv[k] > smax) smax = sv[k];
+        int r = 0;
+        for (int k = 0; k < m; ++k)
+            if (sv[k] > 1e-10 * smax) keep[r++] = k;
+        s_r = r;
+    }
+    wave_sync();
+    const int r = s_r;
     if (r == 0) {
-        *status = 1;
+        if (i == 0) *status = 1;
         return;
     }
-    for (int i = 0; i < m; ++i)
+    if (i < m)
         for (int c = 0; c < r; ++c) X[i][c] = U[i][keep[c]] / sqrt(sv[keep[c]]);
-    for (int i = 0; i < m; ++i)
+    wave_sync();
+    if (i < m)
         for (int c = 0; c < r; ++c) {
             double acc = 0.0;
             for (int k = 0; k < m; ++k) acc += T[i * m + k] * X[k][c];
             TX[i][c] = acc;
         }
-    for (int a = 0; a < r; ++a)
+    wave_sync();
+    if (i < r)
         for (int c = 0; c < r; ++c) {
             double acc = 0.0;
-            for (int k = 0; k < m; ++k) acc += X[k][a] * TX[k][c];
-            A[a][c] = acc;
+            for (int k = 0; k < m; ++k) acc += X[k][i] * TX[k][c];
+            A[i][c] = acc;
         }
-    for (int a = 0; a < r; ++a)
-        for (int c = a + 1; c < r; ++c) {
-            double v = 0.5 * (A[a][c] + A[c][a]);
-            A[a][c] = v;
-            A[c][a] = v;
+    wave_sync();
+    if (i < r)
+        for (int c = i + 1; c < r; ++c) {
+            const double v = 0.5 * (A[i][c] + A[c][i]);
+            A[i][c] = v;
+            A[c][i] = v;
         }
-    jacobi_dev(r, A, U, lam);  // U now holds the eigenvectors y of X^T T X
-    int best = 0;
-    for (int k = 1; k < r; ++k)
-        if (lam[k] < lam[best]) best = k;
-    for (int i = 0; i < m; ++i) {
+    wave_sync();
+    jacobi_dev(r, A, U, lam, &s_flag);  // U now holds the eigenvectors y of X^T T X
+    if (i == 0) {
+        int best = 0;
+        for (int k = 1; k < r; ++k)
+            if (lam[k] < lam[best]) best = k;
+        s_best = best;
+    }
+    wave_sync();
+    const int best = s_best;
+    if (i < m) {
         double acc = 0.0;
         for (int c = 0; c < r; ++c) acc += X[i][c] * U[c][best];
         xs[i] = acc;
     }
-    int imax = 0;
-    for (int i = 1; i < m; ++i)
-        if (fabs(xs[i]) > fabs(xs[imax])) imax = i;
-    bool neg = xs[imax] < 0.0;
-    for (int i = 0; i < m; ++i) x[i] = neg ? -xs[i] : xs[i];
-    *lambda = lam[best];
-    if (energy_slot) energy_slot[blk ? *blk : 0] = lam[best];
-    *status = 0;
+    wave_sync();
+    if (i == 0) {
+        int imax = 0;
+        for (int k = 1; k < m; ++k)
+            if (fabs(xs[k]) > fabs(xs[imax])) imax = k;
+        s_flag = xs[imax] < 0.0 ? 1 : 0;
+    }
+    wave_sync();
+    const bool neg = s_flag != 0;
+    if (i < m) x[i] = neg ? -xs[i] : xs[i];
+    if (i == 0) {
+        *lambda = lam[best];
+        if (energy_slot) energy_slot[blk ? *blk : 0] = lam[best];
+        *status = 0;
+    }
 }
 
 unsigned gsz(u64 cap) {

@@ -107,33 +107,74 @@ __global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict_
     if (L == 0 && threadIdx.x == 0 && blk_total) atomicAdd((unsigned long long*)&st->total, blk_total);
 }
 
-__global__ void k_sel_pick(SelState* st, Geo g, int L, u64 M) {
-    if (threadIdx.x != 0) return;
-    if (st->done) return;
+// Pick the digit of level L: the largest d >= 1 whose bins d.. hold at least
+// `need` entries (else 0), as a block-wide suffix scan over the histogram.
+constexpr int PICK_T = 256;
+constexpr int PICK_PER = NBIN / PICK_T;
+__global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L, u64 M) {
+    __shared__ u64 part[PICK_T];
+    __shared__ int s_d;
+    __shared__ u64 s_acc;
+    const int t = threadIdx.x;
+    if (st->done) return;  // uniform: nobody writes it before every thread has read it
+    const u64 need = st->need;
     if (L == 0 && st->total <= M) {
-        st->take_all = 1;
-        st->done = 1;
-        for (int t = 0; t < NBIN; ++t) st->hist[t] = 0;
+        __syncthreads();
+        for (int b = t; b < NBIN; b += PICK_T) st->hist[b] = 0;
+        if (t == 0) {
+            st->take_all = 1;
+            st->done = 1;
+        }
         return;
     }
-    u64 acc = 0;
-    int d = NBIN - 1;
-    for (; d > 0; --d) {
-        u64 h = st->hist[d];
-        if (acc + h >= st->need) break;
-        acc += h;
+    u64 h[PICK_PER];
+    u64 mine = 0;
+    for (int k = 0; k < PICK_PER; ++k) {
+        h[k] = st->hist[t * PICK_PER + k];
+        mine += h[k];
     }
-    st->need -= acc;
-    u64 hd = st->hist[d];
-    int lo = dig_lo(g, L);
-    int width = (g.tb - DIG * L) - lo;
-    u128 pre = ((u128)st->pre_hi << 64) | st->pre_lo;
-    pre = (pre << width) | (u128)(unsigned)d;
-    st->pre_hi = (u64)(pre >> 64);
-    st->pre_lo = (u64)pre;
-    st->level = L + 1;
-    if (hd == st->need || L == g.ndig - 1) st->done = 1;
-    for (int t = 0; t < NBIN; ++t) st->hist[t] = 0;
+    part[t] = mine;
+    if (t == 0) {
+        s_d = 0;
+        s_acc = 0;
+    }
+    __syncthreads();
+    // exclusive suffix sum over threads (bins above this thread's block)
+    u64 above = 0;
+    for (int u = t + 1; u < PICK_T; ++u) above += part[u];
+    u64 incl = above;  // entries in bins > current bin
+    for (int k = PICK_PER - 1; k >= 0; --k) {
+        const int b = t * PICK_PER + k;
+        const u64 hi = incl;  // bins > b
+        incl += h[k];         // bins >= b
+        if (b >= 1 && incl >= need && hi < need) {
+            s_d = b;
+            s_acc = hi;
+        }
+    }
+    __syncthreads();
+    int d = s_d;
+    u64 acc = s_acc;
+    if (d == 0) {
+        // no bin >= 1 reaches `need`: the digit is 0, with everything above it taken
+        acc = 0;
+        for (int u = 0; u < PICK_T; ++u) acc += part[u];
+        acc -= st->hist[0];
+    }
+    const u64 hd = st->hist[d];
+    __syncthreads();
+    for (int b = t; b < NBIN; b += PICK_T) st->hist[b] = 0;
+    if (t == 0) {
+        st->need = need - acc;
+        const int lo = dig_lo(g, L);
+        const int width = (g.tb - DIG * L) - lo;
+        u128 pre = ((u128)st->pre_hi << 64) | st->pre_lo;
+        pre = (pre << width) | (u128)(unsigned)d;
+        st->pre_hi = (u64)(pre >> 64);
+        st->pre_lo = (u64)pre;
+        st->level = L + 1;
+        if (hd == st->need || L == g.ndig - 1) st->done = 1;
+    }
 }
 
 template <class Src>
@@ -232,7 +273,7 @@ void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_c
     if (!take_all && !take_none) {
         for (int L = 0; L < g.ndig; ++L) {
             hipLaunchKernelGGL(k_sel_hist<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st, g, L);
-            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, P->stream, st, g, L, M);
+            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_T), 0, P->stream, st, g, L, M);
         }
     }
     u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
