@@ -183,7 +183,7 @@ def bench_batch(args, torch, sfci, synth):
     Ms = synth.batch_truncations(32)[:args.n_inst]
     torch.cuda.set_device(0)
     probs = [sfci.Problem(n, na, nb, h, g) for _, h, g in inst]
-    start = synth.spin_broken_start(na, nb)
+    start = synth.perturbed_start(n, na, nb)
     r0 = probs[0].rank([s[0] for s in start], [s[1] for s in start]).cpu().numpy()
     a0 = np.array([s[2] for s in start])
     order = np.argsort(r0, kind="stable")
@@ -218,6 +218,7 @@ def bench_batch(args, torch, sfci, synth):
         t_plain = time.perf_counter() - t1
         dE = np.abs(E[:, -1] - Ep)
         plain = dict(seconds=t_plain, speedup=t_plain / wall, energy_max_abs_diff=float(dE.max()),
+                     energy_abs_diff=[float(x) for x in dE],
                      path="each instance alone: FP64-atomic sigma, per-kernel launches, then the backward")
         print(f"# plain: {t_plain:.3f} s, speedup {t_plain / wall:.2f}x, max |dE| {dE.max():.2e}", file=sys.stderr,
               flush=True)
@@ -251,7 +252,7 @@ def bench_batch(args, torch, sfci, synth):
         "config": {
             "workload": f"c4batch: {len(probs)} bond-stretch instances, 8e in 20 orbitals (4a,4b), N_det=2.35e7 each, "
                         f"M log-uniform in [1e4,1e6] (seed 44), N_L={args.n_L}, {args.steps} sigma per instance "
-                        f"+ dE/dh, dE/d(pq|rs); start: aufbau + 0.1 alpha HOMO->LUMO",
+                        f"+ dE/dh, dE/d(pq|rs); start: aufbau + 0.1 N(0,1) on its singles (seed 7)",
             "Ms": Ms,
             "n_L": args.n_L,
             "fwd_ms": st["fwd_ms"],

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "sfci_internal.h"
@@ -49,6 +50,11 @@ struct RTParams {
     double* Rh;                  // gradient passes: raw dL/dh (n*n) and dL/d(pq|rs) (n^4)
     double* Rg;
     const double* K2;            // n^2: (pp|qq) - (pq|qp)
+    const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
+    const u32* T2r;              // beta-beta doubles per beta rank, sorted: target rank (NULL: not tabulated)
+    const double* T2v;           //   and the signed element
+    const uint16_t* toff2;       //   per beta rank, ntiles + 1 offsets
+    int PQ;                      //   doubles per beta string
 };
 
 // One contributing source row of the current (target row, tile).
@@ -77,10 +83,16 @@ __device__ __forceinline__ int t1_b(u32 t) { return (int)((t >> 26) & 31u); }
 __device__ __forceinline__ int t1_par(u32 t) { return (int)(t >> 31); }
 
 // Entries of the identity row per beta-beta-double and per beta-single work unit.
-constexpr unsigned RT_BB_CHUNK = 4;
+constexpr unsigned RT_BB_CHUNK = 16;
 constexpr unsigned RT_B1_CHUNK = 16;
 // Input entries whose table reads are issued together in the beta-single loop.
 constexpr int RT_UNROLL = 4;
+
+// Global-memory view of a device pointer (plain global loads, not flat ones).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gl(const T* q) {
+    return (const __attribute__((address_space(1))) T*)q;
+}
 
 __device__ __forceinline__ u32 rl32(u32 v, int l) { return (u32)__builtin_amdgcn_readlane((int)v, l); }
 __device__ __forceinline__ u64 rl64(u64 v, int l) { return ((u64)rl32((u32)(v >> 32), l) << 32) | rl32((u32)v, l); }
@@ -496,6 +508,28 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 // beta-beta doubles of identity-row entries [k0, k1)
                 const u32 k0 = idb + (li - nlist - n_b1) * RT_BB_CHUNK;
                 const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
+                if (p.PQ) {
+                    // tabulated: the doubles of each entry's beta string that land in this tile
+                    const auto rbg = gl(p.v_rb);
+                    const auto ampg = gl(p.v_amp);
+                    const auto t2r = gl(p.T2r);
+                    const auto t2v = gl(p.T2v);
+                    const auto to2 = gl(p.toff2);
+                    for (u32 k = k0; k < k1; ++k) {
+                        const u64 rb = rbg[k];
+                        const double c = ampg[k];
+                        const u64 base = rb * (u64)p.PQ;
+                        const u32 o0 = to2[rb * (u64)(p.ntiles + 1) + tile], o1 = to2[rb * (u64)(p.ntiles + 1) + tile + 1];
+                        for (u32 t = o0 + lane; t < o1; t += 64) {
+                            const double e = t2v[base + t];
+                            if (e != 0.0) {
+                                atomicAdd(&acc[t2r[base + t] - tlo], e * c);
+                                ++my_terms;
+                            }
+                        }
+                    }
+                    continue;
+                }
                 for (u32 k = k0; k < k1; ++k) {
                     const u32 beta = p.v_beta[k];
                     const double c = p.v_amp[k];
@@ -566,10 +600,16 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 for (u32 t = lane; t < n2; t += 64) slab[t] = Gia[t];
                 wave_sync();
             }
-            if (whole_rows) {
-                // lanes over the single-excitation index; 64 entries at a time
-                // are loaded one per lane and taken in turn (readlane), with
-                // RT_UNROLL table reads in flight
+            if (whole_rows && T == 1) {
+                // Alpha-beta doubles, the bulk of the work.  Lanes over the
+                // single-excitation index; 64 entries at a time are loaded one
+                // per lane and taken in turn (readlane), RT_UNROLL table reads
+                // in flight.  Global-address-space loads keep the table reads
+                // independent of the LDS traffic.
+                const auto T1g = gl(p.T1);
+                const auto rbg = gl(p.v_rb);
+                const auto ampg = gl(p.v_amp);
+                const int par_a = r.par;
                 for (int s0 = 0; s0 < sBn; s0 += 64) {
                     const int sidx = s0 + lane;
                     const bool act = sidx < sBn;
@@ -577,72 +617,96 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         const u32 kk = kb + lane;
                         u32 rk = 0;
                         double ck = 0.0;
-                        u32 bk = 0;
                         if (kk < r.rowe) {
-                            rk = p.v_rb[kk];
-                            ck = p.v_amp[kk];
-                            if (T == 0) bk = p.v_beta[kk];
+                            rk = rbg[kk];
+                            ck = ampg[kk];
                         }
                         const int cnt = (int)min(64u, r.rowe - kb);
-                        for (int q = 0; q < cnt; q += RT_UNROLL) {
-                            u32 te[RT_UNROLL];
+                        // the element's integral comes from the staged LDS slab (GS) or from global memory
+                        auto sweep = [&](auto GS) {
+                            constexpr bool kGS = decltype(GS)::value;
+                            auto element = [&](u32 te) -> double {
+                                return kGS ? slab[t1_j(te) * n + t1_b(te)] : p.I.G(I_, A_, t1_j(te), t1_b(te));
+                            };
+                            // sign of both phases applied to x by flipping its sign bit
+                            auto signed_ = [&](double x, u32 te) {
+                                return __longlong_as_double(__double_as_longlong(x) ^
+                                                            ((long long)(par_a ^ t1_par(te)) << 63));
+                            };
+                            int q = 0;
+                            for (; q + RT_UNROLL <= cnt; q += RT_UNROLL) {
+                                if (!act) continue;
+                                u32 te[RT_UNROLL];
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
-                                te[u] = 0;
-                                if (q + u < cnt) {
-                                    const u64 rbeta = rl32(rk, q + u);
-                                    if (act) te[u] = p.T1[rbeta * (u64)sBn + sidx];
-                                }
-                            }
-                            if (GRAD) {
-                                // alpha-beta double (ia|jb): weight sbar(target) v(source) with both phases
+                                for (int u = 0; u < RT_UNROLL; ++u) te[u] = T1g[rl32(rk, q + u) * (u32)sBn + sidx];
+                                if (GRAD) {
+                                    // weight sbar(target) v(source) with both phases, into the (j, b) slab
+                                    double sb[RT_UNROLL];
 #pragma unroll
-                                for (int u = 0; u < RT_UNROLL; ++u) {
-                                    if (q + u < cnt) {
+                                    for (int u = 0; u < RT_UNROLL; ++u) sb[u] = acc[t1_rank(te[u]) - tlo];
+#pragma unroll
+                                    for (int u = 0; u < RT_UNROLL; ++u) {
                                         const double c = rlf64(ck, q + u);
-                                        if (act) {
-                                            const double sb = acc[t1_rank(te[u]) - tlo];
-                                            if (sb != 0.0) {
-                                                const int jj = t1_j(te[u]), bb = t1_b(te[u]);
-                                                double x = sb * c;
-                                                if (r.par ^ t1_par(te[u])) x = -x;
-                                                atomicAdd(&slab[jj * n + bb], x);
-                                            }
-                                        }
+                                        if (sb[u] != 0.0) atomicAdd(&slab[t1_j(te[u]) * n + t1_b(te[u])], signed_(sb[u] * c, te[u]));
                                     }
-                                }
-                                continue;
-                            }
-                            double e[RT_UNROLL];
+                                } else {
+                                    // all element reads first, then the accumulations (adding an exact
+                                    // zero leaves a slot unchanged, so zero elements need no branch)
+                                    double x[RT_UNROLL];
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
-                                const int jj = t1_j(te[u]), bb = t1_b(te[u]);
-                                const int par_b = t1_par(te[u]);
-                                double x = 0.0;
-                                if (q + u < cnt) {
-                                    const u32 bq = (T == 0) ? rl32(bk, q + u) : 0u;
-                                    if (act) {
-                                        if (T == 1) {
-                                            x = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
-                                            if (r.par ^ par_b) x = -x;
-                                        } else {
-                                            x = single_element_nophase(p.I, bq, At, jj, bb);
-                                            if (par_b) x = -x;
-                                        }
-                                    }
-                                }
-                                e[u] = x;
-                            }
+                                    for (int u = 0; u < RT_UNROLL; ++u) x[u] = element(te[u]);
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
-                                if (q + u < cnt) {
-                                    const double c = rlf64(ck, q + u);
-                                    if (e[u] != 0.0) {
-                                        atomicAdd(&acc[t1_rank(te[u]) - tlo], e[u] * c);
-                                        ++my_terms;
+                                    for (int u = 0; u < RT_UNROLL; ++u) {
+                                        const double c = rlf64(ck, q + u);
+                                        atomicAdd(&acc[t1_rank(te[u]) - tlo], signed_(x[u], te[u]) * c);
+                                        my_terms += (x[u] != 0.0) ? 1u : 0u;
                                     }
                                 }
                             }
+                            for (; q < cnt; ++q) {
+                                if (!act) continue;
+                                const u32 te = T1g[rl32(rk, q) * (u32)sBn + sidx];
+                                const double c = rlf64(ck, q);
+                                if (GRAD) {
+                                    const double sb = acc[t1_rank(te) - tlo];
+                                    if (sb != 0.0) atomicAdd(&slab[t1_j(te) * n + t1_b(te)], signed_(sb * c, te));
+                                } else {
+                                    const double x = element(te);
+                                    atomicAdd(&acc[t1_rank(te) - tlo], signed_(x, te) * c);
+                                    my_terms += (x != 0.0) ? 1u : 0u;
+                                }
+                            }
+                        };
+                        if (gs || GRAD) sweep(std::true_type{});
+                        else sweep(std::false_type{});
+                    }
+                }
+            } else if (whole_rows) {
+                // identity-row beta singles (sigma only): lanes over the
+                // single-excitation index, entries in turn
+                const auto T1g = gl(p.T1);
+                const auto rbg = gl(p.v_rb);
+                const auto ampg = gl(p.v_amp);
+                const auto betag = gl(p.v_beta);
+                for (int s0 = 0; s0 < sBn; s0 += 64) {
+                    const int sidx = s0 + lane;
+                    if (sidx >= sBn) continue;
+                    const auto tsg = gl(p.TS);
+                    for (u32 k = r.rowb; k < r.rowe; ++k) {
+                        const u32 ti = rbg[k] * (u32)sBn + sidx;
+                        const u32 te = T1g[ti];
+                        // tabulated beta part, then the alpha part in ascending order
+                        double x = tsg[ti];
+                        const int jj = t1_j(te), bb = t1_b(te);
+                        for (u32 m = At; m; m &= m - 1u) {
+                            const int kq = __builtin_ctz(m);
+                            x += p.I.G(jj, bb, kq, kq);
+                        }
+                        (void)betag;
+                        if (t1_par(te)) x = -x;
+                        if (x != 0.0) {
+                            atomicAdd(&acc[t1_rank(te) - tlo], x * ampg[k]);
+                            ++my_terms;
                         }
                     }
                 }
@@ -697,7 +761,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 e = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                 if (r.par ^ par_b) e = -e;
                             } else {
-                                e = single_element_nophase(p.I, W.beta[x], At, jj, bb);
+                                e = p.TS[W.start[x] + (q - W.excl[x])];
+                                for (u32 m = At; m; m &= m - 1u) {
+                                    const int kq = __builtin_ctz(m);
+                                    e += p.I.G(jj, bb, kq, kq);
+                                }
                                 if (par_b) e = -e;
                             }
                             if (e != 0.0) {
@@ -763,8 +831,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
 // T1: for every beta string, its singles sorted by target rank; toff: per-tile
 // offsets into that sorted slice.  One wavefront per beta string; the sort is
 // a rank-by-counting over at most 256 distinct keys.
-__global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restrict__ binom, const u64* __restrict__ tile_lo,
-                                                 int ntiles, u32* __restrict__ T1, uint16_t* __restrict__ toff) {
+__global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restrict__ binom, Ints I,
+                                                 const u64* __restrict__ tile_lo, int ntiles, u32* __restrict__ T1,
+                                                 double* __restrict__ TS, uint16_t* __restrict__ toff) {
     __shared__ BinomLds sB;
     __shared__ u64 key[SFCI_MAX_SINGLES];
     __shared__ uint8_t occ[32], vir[32];
@@ -793,14 +862,98 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
             int pos = 0;
             for (int u = 0; u < sBn; ++u) pos += ((key[u] & 0xFFFFFFFFull) < me) ? 1 : 0;
             const u64 kt = key[t];
-            T1[rb * (u64)sBn + pos] = (u32)(kt & 0xFFFFFFFFull) | ((u32)((kt >> 32) & 31) << 21) |
-                                      ((u32)((kt >> 40) & 31) << 26) | ((u32)((kt >> 48) & 1) << 31);
+            const int jj = (int)((kt >> 32) & 31), bb = (int)((kt >> 40) & 31);
+            T1[rb * (u64)sBn + pos] = (u32)(kt & 0xFFFFFFFFull) | ((u32)jj << 21) | ((u32)bb << 26) |
+                                      ((u32)((kt >> 48) & 1) << 31);
+            // h_jb + sum_{k in beta, k != j} [(jb|kk) - (jk|kb)]: the leading part of the
+            // single-excitation element, in the reference's order (the alpha part follows)
+            double e = I.H(jj, bb);
+            for (u32 m = beta & ~(1u << jj); m; m &= m - 1u) {
+                const int k = __builtin_ctz(m);
+                e += (I.G(jj, bb, k, k) - I.G(jj, k, k, bb));
+            }
+            TS[rb * (u64)sBn + pos] = e;
         }
         for (int t = lane; t <= ntiles; t += 64) {
             const u64 lo = tile_lo[t];
             int cnt = 0;
             for (int u = 0; u < sBn; ++u) cnt += ((key[u] & 0xFFFFFFFFull) < lo) ? 1 : 0;
             toff[rb * (u64)(ntiles + 1) + t] = (uint16_t)cnt;
+        }
+    }
+}
+
+// T2: for every beta string, its beta-beta doubles (occupied i < j -> virtual
+// a < b, pairing i -> a, j -> b) sorted by target rank, with the signed
+// element +-[(ia|jb) - (ib|ja)]; toff2: per-tile offsets.  One workgroup per
+// string, bitonic sort of (rank, index) keys in LDS; at most RT_T2_MAX doubles.
+constexpr int RT_T2_MAX = 4096;
+__global__ __launch_bounds__(256) void k_build_T2(SpaceDev sp, const u64* __restrict__ binom, Ints I,
+                                                  const u64* __restrict__ tile_lo, int ntiles, int PQ,
+                                                  u32* __restrict__ T2r, double* __restrict__ T2v,
+                                                  uint16_t* __restrict__ toff2) {
+    __shared__ BinomLds sB;
+    __shared__ u64 key[RT_T2_MAX];
+    __shared__ double val[RT_T2_MAX];
+    __shared__ uint8_t occ[32], vir[32];
+    load_binom(sB, binom);
+    const int n = sp.n, nb = sp.nb, nvb = n - nb, QB = nvb * (nvb - 1) / 2;
+    int P2 = 1;
+    while (P2 < PQ) P2 <<= 1;
+    for (u64 rb = blockIdx.x; rb < sp.Nb; rb += gridDim.x) {
+        __syncthreads();
+        const u32 beta = str_unrank(rb, nb, n, sB);
+        if (threadIdx.x < (unsigned)n) {
+            const int q = threadIdx.x;
+            const u32 below = (1u << q) - 1u;
+            if ((beta >> q) & 1u) occ[__popc(beta & below)] = (uint8_t)q;
+            else vir[q - __popc(beta & below)] = (uint8_t)q;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < P2; t += blockDim.x) {
+            if (t >= PQ) {
+                key[t] = ~0ull;
+                continue;
+            }
+            const unsigned pa = decode_pair(t / QB, nb), pv = decode_pair(t % QB, nvb);
+            const int i2 = occ[pa & 255], j2 = occ[pa >> 8], a2 = vir[pv & 255], b2 = vir[pv >> 8];
+            const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
+            const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
+            const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
+            double e = (I.G(i2, a2, j2, b2) - I.G(i2, b2, j2, a2));
+            if (par) e = -e;
+            key[t] = (str_rank(B2, sB) << 12) | (u64)t;
+            val[t] = e;
+        }
+        __syncthreads();
+        for (int k = 2; k <= P2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = threadIdx.x; t < P2; t += blockDim.x) {
+                    const int u = t ^ j;
+                    if (u > t) {
+                        const u64 a = key[t], b = key[u];
+                        const bool up = (t & k) == 0;
+                        if ((a > b) == up) {
+                            key[t] = b;
+                            key[u] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int t = threadIdx.x; t < PQ; t += blockDim.x) {
+            T2r[rb * (u64)PQ + t] = (u32)(key[t] >> 12);
+            T2v[rb * (u64)PQ + t] = val[key[t] & 4095];
+        }
+        for (int t = threadIdx.x; t <= ntiles; t += blockDim.x) {
+            const u64 lo = tile_lo[t];
+            int a = 0, b = PQ;  // first entry with rank >= lo
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if ((key[mid] >> 12) < lo) a = mid + 1;
+                else b = mid;
+            }
+            toff2[rb * (u64)(ntiles + 1) + t] = (uint16_t)a;
         }
     }
 }
@@ -875,6 +1028,11 @@ struct RowTileState {
     std::vector<u64> tile_lo;
     u64* d_tile_lo = nullptr;
     u32* d_T1 = nullptr;
+    double* d_TS = nullptr;
+    u32* d_T2r = nullptr;
+    double* d_T2v = nullptr;
+    uint16_t* d_toff2 = nullptr;
+    int PQ = 0;
     double* d_K = nullptr;  // (pp|qq) - (pq|qp), n^2
     uint16_t* d_toff = nullptr;
 };
@@ -956,9 +1114,29 @@ bool rowtile_available(sfci_problem* P) {
     SFCI_CHECK_HIP(hipMalloc(&S->d_T1, std::max<u64>(1, P->Nb * sBn) * sizeof(u32)));
     SFCI_CHECK_HIP(hipMalloc(&S->d_toff, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
     unsigned g = (unsigned)std::min<u64>(P->Nb, (u64)P->num_cu * 16);
+    SFCI_CHECK_HIP(hipMalloc(&S->d_TS, std::max<u64>(1, P->Nb * sBn) * sizeof(double)));
     hipLaunchKernelGGL(k_build_T1, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
-                       P->d_binom, S->d_tile_lo, S->ntiles, S->d_T1, S->d_toff);
+                       P->d_binom, Ints{P->d_h, P->d_g, P->n}, S->d_tile_lo, S->ntiles, S->d_T1, S->d_TS, S->d_toff);
     SFCI_CHECK_HIP(hipGetLastError());
+    {
+        // beta-beta doubles table, when it is small enough per string and fits in memory
+        const int nvb = P->n - P->nb;
+        const int PQ = (P->nb * (P->nb - 1) / 2) * (nvb * (nvb - 1) / 2);
+        size_t fr = 0, tot = 0;
+        SFCI_CHECK_HIP(hipMemGetInfo(&fr, &tot));
+        const u64 bytes = P->Nb * (u64)PQ * 12 + P->Nb * (u64)(S->ntiles + 1) * 2;
+        if (PQ > 0 && PQ <= RT_T2_MAX && bytes < fr / 8) {
+            SFCI_CHECK_HIP(hipMalloc(&S->d_T2r, P->Nb * (u64)PQ * sizeof(u32)));
+            SFCI_CHECK_HIP(hipMalloc(&S->d_T2v, P->Nb * (u64)PQ * sizeof(double)));
+            SFCI_CHECK_HIP(hipMalloc(&S->d_toff2, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
+            const unsigned g2 = (unsigned)std::min<u64>(P->Nb, (u64)P->num_cu * 8);
+            hipLaunchKernelGGL(k_build_T2, dim3(g2), dim3(256), 0, P->stream,
+                               SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, P->d_binom, Ints{P->d_h, P->d_g, P->n},
+                               S->d_tile_lo, S->ntiles, PQ, S->d_T2r, S->d_T2v, S->d_toff2);
+            SFCI_CHECK_HIP(hipGetLastError());
+            S->PQ = PQ;
+        }
+    }
     const u64 nK = (u64)P->n * P->n;
     SFCI_CHECK_HIP(hipMalloc(&S->d_K, nK * sizeof(double)));
     hipLaunchKernelGGL(k_build_K, dim3((unsigned)((nK + 255) / 256)), dim3(256), 0, P->stream, P->n, P->d_g, S->d_K);
@@ -977,6 +1155,10 @@ void rowtile_release(sfci_problem* P) {
     if (!S) return;
     if (S->d_tile_lo) (void)hipFree(S->d_tile_lo);
     if (S->d_T1) (void)hipFree(S->d_T1);
+    if (S->d_TS) (void)hipFree(S->d_TS);
+    if (S->d_T2r) (void)hipFree(S->d_T2r);
+    if (S->d_T2v) (void)hipFree(S->d_T2v);
+    if (S->d_toff2) (void)hipFree(S->d_toff2);
     if (S->d_K) (void)hipFree(S->d_K);
     if (S->d_toff) (void)hipFree(S->d_toff);
     delete S;
@@ -1025,6 +1207,11 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.Rh = nullptr;
     rp.Rg = nullptr;
     rp.K2 = S->d_K;
+    rp.TS = S->d_TS;
+    rp.T2r = S->d_T2r;
+    rp.T2v = S->d_T2v;
+    rp.toff2 = S->d_toff2;
+    rp.PQ = S->PQ;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);

@@ -71,9 +71,12 @@ struct Ints {
     const double* __restrict__ h;  // n*n
     const double* __restrict__ g;  // n^4, (pq|rs) at ((p*n+q)*n+r)*n+s
     int n;
-    __device__ __forceinline__ double H(int p, int q) const { return h[p * n + q]; }
+    // h and g live in device global memory: read them as such (not through flat addressing)
+    __device__ __forceinline__ double H(int p, int q) const {
+        return ((const __attribute__((address_space(1))) double*)h)[p * n + q];
+    }
     __device__ __forceinline__ double G(int p, int q, int r, int s) const {
-        return g[((p * n + q) * n + r) * n + s];
+        return ((const __attribute__((address_space(1))) double*)g)[((p * n + q) * n + r) * n + s];
     }
 };
 

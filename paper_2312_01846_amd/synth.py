@@ -132,20 +132,30 @@ def aufbau_bits(n_elec: int) -> int:
     return (1 << n_elec) - 1
 
 
-def spin_broken_start(na: int, nb: int, weight: float = 0.1) -> list[tuple[int, int, float]]:
-    """Start vector without alpha/beta exchange symmetry, as (alpha bits,
-    beta bits, amplitude) triples: the aufbau determinant plus `weight` times
-    its alpha-only HOMO -> LUMO excitation.
+def perturbed_start(n: int, na: int, nb: int, seed: int = 7, weight: float = 0.1) -> list[tuple[int, int, float]]:
+    """Start vector as (alpha bits, beta bits, amplitude) triples: the aufbau
+    determinant with amplitude 1 plus every single excitation of it, alpha
+    singles then beta singles (occupied i ascending, virtual a ascending),
+    with amplitudes weight * N(0, 1) drawn in that order from one seed.
 
-    With n_alpha = n_beta, a start vector that is symmetric under exchanging
-    the alpha and beta strings keeps every iterate symmetric, so the two
-    partners of each exchanged pair carry equal amplitudes and the top-M cut
-    through such a pair is decided by the last bit of rounding.  This start
-    gives the partners different amplitudes throughout.
+    With n_alpha = n_beta the Hamiltonian commutes with exchanging the alpha
+    and beta strings.  A start vector that is symmetric (or antisymmetric)
+    under that exchange keeps every iterate so, and the two partners of an
+    exchanged pair then carry amplitudes of equal magnitude: the top-M cut
+    through such a pair is decided by the last bit of rounding.  Independent
+    random amplitudes on both spins give both the exchange-symmetric and the
+    antisymmetric part of the vector the same support, so the partners differ.
     """
+    rng = np.random.default_rng(seed)
     a0, b0 = aufbau_bits(na), aufbau_bits(nb)
-    a1 = (a0 & ~(1 << (na - 1))) | (1 << na)
-    return [(a0, b0, 1.0), (a1, b0, float(weight))]
+    out = [(a0, b0, 1.0)]
+    for i in range(na):
+        for a in range(na, n):
+            out.append((a0 ^ (1 << i) ^ (1 << a), b0, float(weight * rng.normal())))
+    for i in range(nb):
+        for a in range(nb, n):
+            out.append((a0, b0 ^ (1 << i) ^ (1 << a), float(weight * rng.normal())))
+    return out
 
 
 def neel_bits(n_sites: int) -> tuple[int, int]:

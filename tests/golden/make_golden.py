@@ -30,11 +30,13 @@ def _support_digest(r):
 
 
 def case_defs():
-    """name -> (builder of (n, na, nb, h, g, start alpha bits, start beta bits), M, n_L, n_iter)."""
-    def mol(n, na, nb, rank, seed):
+    """name -> (builder of (n, na, nb, h, g, start as (alpha bits, beta bits, amplitude) triples), M, n_L, n_iter)."""
+    def mol(n, na, nb, rank, seed, perturbed=False):
         def b():
             h, g = synth.molecule_like(n, rank, seed)
-            return n, na, nb, h, g, [(synth.aufbau_bits(na), synth.aufbau_bits(nb), 1.0)]
+            start = (synth.perturbed_start(n, na, nb) if perturbed
+                     else [(synth.aufbau_bits(na), synth.aufbau_bits(nb), 1.0)])
+            return n, na, nb, h, g, start
         return b
 
     def hub(L, U):
@@ -47,7 +49,7 @@ def case_defs():
     def c4(j, broken=False):
         def b():
             lam, h, g = synth.bond_stretch_batch(20, 32, 40)[j]
-            start = synth.spin_broken_start(4, 4) if broken else [(synth.aufbau_bits(4), synth.aufbau_bits(4), 1.0)]
+            start = synth.perturbed_start(20, 4, 4) if broken else [(synth.aufbau_bits(4), synth.aufbau_bits(4), 1.0)]
             return 20, 4, 4, h, g, start
         return b
 
@@ -60,8 +62,10 @@ def case_defs():
         "c2_M1e4_30": (mol(26, 5, 5, 52, 2), 10_000, 10, 30),
         "c4_inst0_M1e4_30": (c4(0), 10_000, 10, 30),
         "c4_inst31_M3e3_30": (c4(31), 3_000, 10, 30),
-        "c4sb_inst31_M3e3_30": (c4(31, True), 3_000, 10, 30),
-        "c4sb_inst12_M1e4_30": (c4(12, True), 10_000, 10, 30),
+        "c0p_M300_30": (mol(8, 3, 3, 16, 0, True), 300, 10, 30),
+        "c2p_M2e3_20": (mol(26, 5, 5, 52, 2, True), 2_000, 10, 20),
+        "c4p_inst31_M3e3_30": (c4(31, True), 3_000, 10, 30),
+        "c4p_inst15_M1e4_30": (c4(15, True), 10_938, 10, 30),
     }
 
 

@@ -63,6 +63,14 @@ def _c0(S):
 AUFBAU = (np.array([0], dtype=np.int64), np.array([1.0]))
 
 
+def _perturbed(P):
+    st = synth.perturbed_start(P.n, P.na, P.nb)
+    r0 = P.rank([t[0] for t in st], [t[1] for t in st]).cpu().numpy()
+    a0 = np.array([t[2] for t in st])
+    o = np.argsort(r0, kind="stable")
+    return r0[o], a0[o]
+
+
 def _euler(dh, dg, h, g):
     # E is linear in (h, g): E = sum h * dE/dh + sum g * dE/dg at fixed Psi.
     return float((_np(dh) * h).sum() + (_np(dg) * g).sum())
@@ -95,13 +103,15 @@ def test_batch_deterministic_matches_goldens(torch, S):
 
 def test_batch_fast_mixed_sizes(torch, S, orc):
     # 8 and 20 orbitals in one tile launch; the untruncated 8-orbital run is
-    # plain Lanczos and must match the oracle, the truncated ones their goldens.
-    gc0, g31 = _gold("c0_M300_30"), _gold("c4_inst31_M3e3_30")
+    # plain Lanczos and must match the oracle, the truncated 8-orbital run
+    # (perturbed start, no exact ties) its golden.
+    gc0, g31 = _gold("c0p_M300_30"), _gold("c4_inst31_M3e3_30")
     Pa, hc, ec = _c0(S)
     Pb, _, _ = _c0(S)
     P31, h31, e31 = _c4(S, 31)
     B = S.Batch([Pa, P31, Pb])
-    out = B.lanczos([AUFBAU] * 3, [None, g31["M"], gc0["M"]], n_L=10, n_iter=30, deterministic=False)
+    out = B.lanczos([AUFBAU, AUFBAU, _perturbed(Pb)], [None, g31["M"], gc0["M"]], n_L=10, n_iter=30,
+                    deterministic=False)
     st = out["stats"]
     assert st["batched_sigma"] == 1 and st["graph_replayed_blocks"] == 2 and st["sigma_calls"] == 30
     ref = orc.Problem(8, 3, 3, hc, ec).lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), None, 10, 30)
@@ -128,6 +138,26 @@ def test_batch_fast_gradients_match_oracle(torch, S, orc):
     _, oh, og = Po.backward(r, a, r, a / float(a @ a))
     assert np.allclose(_np(out["dh"][0]), oh, rtol=1e-6, atol=1e-9)
     assert np.allclose(_np(out["dg"][0]), og, rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_batch_perturbed_start_goldens(torch, S, det):
+    # Start vectors without the alpha/beta exchange symmetry: no exact ties at
+    # the top-M cut, so the fast batched path (tile launch, graph replay) must
+    # match the oracle's energies at equal M to 1e-9 Ha.
+    g31, g15 = _gold("c4p_inst31_M3e3_30"), _gold("c4p_inst15_M1e4_30")
+    P31, _, _ = _c4(S, 31)
+    P15, _, _ = _c4(S, 15)
+    B = S.Batch([P31, P15])
+    out = B.lanczos([_perturbed(P31), _perturbed(P15)], [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=det,
+                    want_grad=False)
+    E = out["energies"]
+    if det:
+        assert E[0].tolist() == g31["energies"] and E[1].tolist() == g15["energies"]
+    else:
+        assert out["stats"]["batched_sigma"] == 1 and out["stats"]["graph_replayed_blocks"] == 2
+        assert np.all(np.abs(E[0] - np.array(g31["energies"])) < 1e-9)
+        assert np.all(np.abs(E[1] - np.array(g15["energies"])) < 1e-9)
 
 
 def test_batch_repeat_and_shrink(torch, S):

