@@ -114,7 +114,7 @@ def main():
     print(f"# building a start vector: {args.warmup} warm-up iterations at M={M}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     warm = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=M, n_L=args.n_L, n_iter=args.warmup,
-                     psi_capacity=min(P.n_det, args.n_L * M), dedup=args.dedup)
+                     psi_capacity=min(P.n_det, args.n_L * (M + sfci.TIE_SLACK)), dedup=args.dedup)
     v_r, v_a = P.topm(warm["psi_rank"], warm["psi_amp"], M, normalise=True)
     torch.cuda.synchronize()
     print(f"# warm-up done in {time.perf_counter() - t0:.1f} s; start vector nnz={v_r.numel()}", file=sys.stderr,
@@ -209,7 +209,7 @@ def bench_batch(args, torch, sfci, synth):
         biggest = int(np.argmax(Ms))
         for k, P in enumerate(probs):
             o = P.lanczos(v0[0], v0[1], M=Ms[k], n_L=args.n_L, n_iter=args.steps, dedup="dense_atomic",
-                          psi_capacity=min(P.n_det, args.n_L * Ms[k]))
+                          psi_capacity=min(P.n_det, args.n_L * (Ms[k] + sfci.TIE_SLACK)))
             P.energy_gradients(o["psi_rank"], o["psi_amp"])
             Ep[k] = o["energies"][-1]
             if k == biggest:

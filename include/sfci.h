@@ -70,6 +70,16 @@ typedef struct {
     uint64_t capacity; /* entries allocated */
 } sfci_svec;
 
+/* Truncation to M (Sec. 2.1 keeps the largest entries; the paper is silent on
+ * ties).  Entries are ordered by |c| descending, rank ascending, and the first
+ * M kept; every further entry whose |c| is >= (1 - 2^-36) times the M-th |c|
+ * is kept too, so partners of equal magnitude in exact arithmetic (e.g.
+ * alpha/beta-exchanged determinants when n_alpha = n_beta) are not split by
+ * rounding -- unless that adds more than SFCI_TIE_SLACK entries, in which case
+ * exactly M are kept.  A truncated vector therefore holds at most
+ * M + SFCI_TIE_SLACK entries; size outputs accordingly. */
+#define SFCI_TIE_SLACK 256
+
 /* Deduplication of the intermediate elements (Sec. 2.2 merge step). */
 enum {
     SFCI_DEDUP_AUTO = 0,         /* dense if 8*N_det bytes fit the device, else sort */
@@ -79,7 +89,7 @@ enum {
 };
 
 typedef struct {
-    uint64_t M;        /* keep the M largest |sigma_k| (ties: lower rank first); UINT64_MAX = all */
+    uint64_t M;        /* keep the M largest |sigma_k| (ties: see SFCI_TIE_SLACK); UINT64_MAX = all */
     int32_t dedup;     /* SFCI_DEDUP_* */
     int32_t deterministic; /* 1: sort dedup and ordered reductions, bit-reproducible */
 } sfci_sigma_opts;
@@ -117,12 +127,12 @@ sfci_status sfci_sigma(sfci_problem* prob, const sfci_svec* v, const sfci_sigma_
                        sfci_sigma_stats* stats);
 
 /* Truncation alone (Eqs. 10-11 without the division): the M largest |amp| of v
- * (ties by lower rank), by ascending rank, into out.  Zero amplitudes are dropped.
+ * (ties: see SFCI_TIE_SLACK), by ascending rank, into out.  Zero amplitudes are dropped.
  * normalise != 0 divides the kept amplitudes by their 2-norm (Eq. 11). */
 sfci_status sfci_topm(sfci_problem* prob, const sfci_svec* v, uint64_t M, int32_t normalise, sfci_svec* out);
 
 typedef struct {
-    uint64_t M;            /* N_d of Sec. 2.1: entries kept per basis vector; UINT64_MAX = all */
+    uint64_t M;            /* N_d of Sec. 2.1: entries kept per basis vector (at most M + SFCI_TIE_SLACK); UINT64_MAX = all */
     int32_t n_L;           /* basis vectors per block (N_L), 1..32 */
     int32_t n_iter;        /* sigma applications; n_iter / n_L blocks are run */
     int32_t deterministic; /* 1: sort dedup and ordered reductions */

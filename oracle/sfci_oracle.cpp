@@ -506,6 +506,15 @@ extern "C" double orc_sigma_entry(int n, int na, int nb, const double* h, const 
 // Truncation (Eqs. 10-11): order the nonzero entries by |c| descending, ties
 // by rank ascending; keep the first min(M, nnz); return them by ascending
 // rank.  M < 0 keeps all.  In/out may alias.  Returns the kept count.
+// Truncation reading (the paper keeps "the largest" entries and is silent on
+// ties): order the nonzero entries by |c| descending, rank ascending, and take
+// the first M.  Entries whose magnitude lies within a relative 2^-36 of the
+// M-th one are kept as well, so that partners of equal magnitude in exact
+// arithmetic (e.g. alpha/beta-exchanged determinants when n_alpha = n_beta)
+// are never split by a rounding difference -- unless that would add more than
+// ORC_TIE_SLACK entries, in which case exactly M are kept.
+static const i64 ORC_TIE_SLACK = 256;
+
 extern "C" i64 orc_topm(i64 nnz, const u64* rank, const double* amp, i64 M, u64* out_rank, double* out_amp) {
     std::vector<std::pair<u64, double>> e;
     for (i64 t = 0; t < nnz; ++t)
@@ -516,7 +525,14 @@ extern "C" i64 orc_topm(i64 nnz, const u64* rank, const double* amp, i64 M, u64*
             if (ax != ay) return ax > ay;
             return x.first < y.first;
         });
-        e.resize((size_t)M);
+        i64 keep = M;
+        if (M > 0) {
+            const double thr = std::fabs(e[(size_t)M - 1].second) * (1.0 - 1.0 / 68719476736.0);  // 1 - 2^-36
+            i64 k = M;
+            while (k < (i64)e.size() && std::fabs(e[(size_t)k].second) >= thr) ++k;
+            if (k - M <= ORC_TIE_SLACK) keep = k;
+        }
+        e.resize((size_t)keep);
     }
     std::sort(e.begin(), e.end());
     for (size_t t = 0; t < e.size(); ++t) { out_rank[t] = e[t].first; out_amp[t] = e[t].second; }

@@ -420,7 +420,9 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
     if (!dense_ok)
         return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED,
                                            "the iteration needs the dense accumulator (N_det doubles) on the device");
-    const u64 cap = (o->M == UINT64_MAX) ? P->Ndet : std::min<u64>(std::max<u64>(o->M, v0->nnz), P->Ndet);
+    // a truncated vector holds at most M + SFCI_TIE_SLACK entries
+    const u64 cap = (o->M >= P->Ndet) ? P->Ndet
+                                      : std::min<u64>(std::max<u64>(o->M + SFCI_TIE_SLACK, v0->nnz), P->Ndet);
     const u64 tps = terms_per_source(P->n, P->na, P->nb);
     // basis storage
     u64* Wr = (u64*)P->ws_lz[1].get((size_t)nL * cap * sizeof(u64));

@@ -135,7 +135,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         Inst& q = I[k];
         q.P = P;
         q.M = Ms[k];
-        q.cap = (Ms[k] == UINT64_MAX) ? P->Ndet : std::min<u64>(std::max<u64>(Ms[k], v0s[k].nnz), P->Ndet);
+        q.cap = (Ms[k] >= P->Ndet) ? P->Ndet
+                                   : std::min<u64>(std::max<u64>(Ms[k] + SFCI_TIE_SLACK, v0s[k].nnz), P->Ndet);
         q.tps = terms_per_source(P->n, P->na, P->nb);
         q.Wr = (u64*)P->ws_lz[1].get((size_t)nL * q.cap * sizeof(u64));
         q.Wa = (double*)P->ws_lz[2].get((size_t)nL * q.cap * sizeof(double));

@@ -51,10 +51,7 @@ struct RTParams {
     double* Rg;
     const double* K2;            // n^2: (pp|qq) - (pq|qp)
     const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
-    const u32* T2r;              // beta-beta doubles per beta rank, sorted: target rank (NULL: not tabulated)
-    const double* T2v;           //   and the signed element
-    const uint16_t* toff2;       //   per beta rank, ntiles + 1 offsets
-    int PQ;                      //   doubles per beta string
+    const double* K4;            // [(i<j), (a<b)] pair-indexed (ia|jb) - (ib|ja), pair (x<y) -> y(y-1)/2 + x
 };
 
 // One contributing source row of the current (target row, tile).
@@ -83,7 +80,7 @@ __device__ __forceinline__ int t1_b(u32 t) { return (int)((t >> 26) & 31u); }
 __device__ __forceinline__ int t1_par(u32 t) { return (int)(t >> 31); }
 
 // Entries of the identity row per beta-beta-double and per beta-single work unit.
-constexpr unsigned RT_BB_CHUNK = 16;
+constexpr unsigned RT_BB_CHUNK = 4;
 constexpr unsigned RT_B1_CHUNK = 16;
 // Input entries whose table reads are issued together in the beta-single loop.
 constexpr int RT_UNROLL = 4;
@@ -508,28 +505,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 // beta-beta doubles of identity-row entries [k0, k1)
                 const u32 k0 = idb + (li - nlist - n_b1) * RT_BB_CHUNK;
                 const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
-                if (p.PQ) {
-                    // tabulated: the doubles of each entry's beta string that land in this tile
-                    const auto rbg = gl(p.v_rb);
-                    const auto ampg = gl(p.v_amp);
-                    const auto t2r = gl(p.T2r);
-                    const auto t2v = gl(p.T2v);
-                    const auto to2 = gl(p.toff2);
-                    for (u32 k = k0; k < k1; ++k) {
-                        const u64 rb = rbg[k];
-                        const double c = ampg[k];
-                        const u64 base = rb * (u64)p.PQ;
-                        const u32 o0 = to2[rb * (u64)(p.ntiles + 1) + tile], o1 = to2[rb * (u64)(p.ntiles + 1) + tile + 1];
-                        for (u32 t = o0 + lane; t < o1; t += 64) {
-                            const double e = t2v[base + t];
-                            if (e != 0.0) {
-                                atomicAdd(&acc[t2r[base + t] - tlo], e * c);
-                                ++my_terms;
-                            }
-                        }
-                    }
-                    continue;
-                }
+                const auto K4g = gl(p.K4);
+                const int np2 = n * (n - 1) / 2;
                 for (u32 k = k0; k < k1; ++k) {
                     const u32 beta = p.v_beta[k];
                     const double c = p.v_amp[k];
@@ -555,7 +532,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 const u64 rt = str_rank(B2, sB);
                                 if (rt >= tlo && rt < thi) {
                                     const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
-                                    double e = (p.I.G(i2, a2, j2, b2) - p.I.G(i2, b2, j2, a2));
+                                    // (i2 a2|j2 b2) - (i2 b2|j2 a2), tabulated by orbital pairs
+                                    double e = K4g[(u32)(j2 * (j2 - 1) / 2 + i2) * (u32)np2 + (u32)(b2 * (b2 - 1) / 2 + a2)];
                                     if (par) e = -e;
                                     if (e != 0.0) {
                                         atomicAdd(&acc[rt - tlo], e * c);
@@ -883,79 +861,19 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
     }
 }
 
-// T2: for every beta string, its beta-beta doubles (occupied i < j -> virtual
-// a < b, pairing i -> a, j -> b) sorted by target rank, with the signed
-// element +-[(ia|jb) - (ib|ja)]; toff2: per-tile offsets.  One workgroup per
-// string, bitonic sort of (rank, index) keys in LDS; at most RT_T2_MAX doubles.
-constexpr int RT_T2_MAX = 4096;
-__global__ __launch_bounds__(256) void k_build_T2(SpaceDev sp, const u64* __restrict__ binom, Ints I,
-                                                  const u64* __restrict__ tile_lo, int ntiles, int PQ,
-                                                  u32* __restrict__ T2r, double* __restrict__ T2v,
-                                                  uint16_t* __restrict__ toff2) {
-    __shared__ BinomLds sB;
-    __shared__ u64 key[RT_T2_MAX];
-    __shared__ double val[RT_T2_MAX];
-    __shared__ uint8_t occ[32], vir[32];
-    load_binom(sB, binom);
-    const int n = sp.n, nb = sp.nb, nvb = n - nb, QB = nvb * (nvb - 1) / 2;
-    int P2 = 1;
-    while (P2 < PQ) P2 <<= 1;
-    for (u64 rb = blockIdx.x; rb < sp.Nb; rb += gridDim.x) {
-        __syncthreads();
-        const u32 beta = str_unrank(rb, nb, n, sB);
-        if (threadIdx.x < (unsigned)n) {
-            const int q = threadIdx.x;
-            const u32 below = (1u << q) - 1u;
-            if ((beta >> q) & 1u) occ[__popc(beta & below)] = (uint8_t)q;
-            else vir[q - __popc(beta & below)] = (uint8_t)q;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < P2; t += blockDim.x) {
-            if (t >= PQ) {
-                key[t] = ~0ull;
-                continue;
-            }
-            const unsigned pa = decode_pair(t / QB, nb), pv = decode_pair(t % QB, nvb);
-            const int i2 = occ[pa & 255], j2 = occ[pa >> 8], a2 = vir[pv & 255], b2 = vir[pv >> 8];
-            const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
-            const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
-            const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
-            double e = (I.G(i2, a2, j2, b2) - I.G(i2, b2, j2, a2));
-            if (par) e = -e;
-            key[t] = (str_rank(B2, sB) << 12) | (u64)t;
-            val[t] = e;
-        }
-        __syncthreads();
-        for (int k = 2; k <= P2; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int t = threadIdx.x; t < P2; t += blockDim.x) {
-                    const int u = t ^ j;
-                    if (u > t) {
-                        const u64 a = key[t], b = key[u];
-                        const bool up = (t & k) == 0;
-                        if ((a > b) == up) {
-                            key[t] = b;
-                            key[u] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        for (int t = threadIdx.x; t < PQ; t += blockDim.x) {
-            T2r[rb * (u64)PQ + t] = (u32)(key[t] >> 12);
-            T2v[rb * (u64)PQ + t] = val[key[t] & 4095];
-        }
-        for (int t = threadIdx.x; t <= ntiles; t += blockDim.x) {
-            const u64 lo = tile_lo[t];
-            int a = 0, b = PQ;  // first entry with rank >= lo
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if ((key[mid] >> 12) < lo) a = mid + 1;
-                else b = mid;
-            }
-            toff2[rb * (u64)(ntiles + 1) + t] = (uint16_t)a;
-        }
-    }
+// K4[(i<j), (a<b)] = (ia|jb) - (ib|ja), rounded exactly as in the double's element.
+__global__ void k_build_K4(int n, const double* __restrict__ g, double* __restrict__ K4) {
+    const u64 np2 = (u64)n * (n - 1) / 2, t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np2 * np2) return;
+    const u64 po = t / np2, pv = t % np2;
+    int j = 1;
+    while ((u64)(j * (j + 1) / 2) <= po) ++j;  // occupied pair (i, j): po = j(j-1)/2 + i
+    const int i = (int)(po - (u64)(j * (j - 1) / 2));
+    int b = 1;
+    while ((u64)(b * (b + 1) / 2) <= pv) ++b;
+    const int a = (int)(pv - (u64)(b * (b - 1) / 2));
+    auto G = [&](int p, int q, int r, int s_) { return g[(((u64)p * n + q) * n + r) * n + s_]; };
+    K4[t] = (G(i, a, j, b) - G(i, b, j, a));
 }
 
 // K2[p][q] = (pp|qq) - (pq|qp), rounded exactly as in the diagonal element.
@@ -1029,10 +947,7 @@ struct RowTileState {
     u64* d_tile_lo = nullptr;
     u32* d_T1 = nullptr;
     double* d_TS = nullptr;
-    u32* d_T2r = nullptr;
-    double* d_T2v = nullptr;
-    uint16_t* d_toff2 = nullptr;
-    int PQ = 0;
+    double* d_K4 = nullptr;
     double* d_K = nullptr;  // (pp|qq) - (pq|qp), n^2
     uint16_t* d_toff = nullptr;
 };
@@ -1119,23 +1034,12 @@ bool rowtile_available(sfci_problem* P) {
                        P->d_binom, Ints{P->d_h, P->d_g, P->n}, S->d_tile_lo, S->ntiles, S->d_T1, S->d_TS, S->d_toff);
     SFCI_CHECK_HIP(hipGetLastError());
     {
-        // beta-beta doubles table, when it is small enough per string and fits in memory
-        const int nvb = P->n - P->nb;
-        const int PQ = (P->nb * (P->nb - 1) / 2) * (nvb * (nvb - 1) / 2);
-        size_t fr = 0, tot = 0;
-        SFCI_CHECK_HIP(hipMemGetInfo(&fr, &tot));
-        const u64 bytes = P->Nb * (u64)PQ * 12 + P->Nb * (u64)(S->ntiles + 1) * 2;
-        if (PQ > 0 && PQ <= RT_T2_MAX && bytes < fr / 8) {
-            SFCI_CHECK_HIP(hipMalloc(&S->d_T2r, P->Nb * (u64)PQ * sizeof(u32)));
-            SFCI_CHECK_HIP(hipMalloc(&S->d_T2v, P->Nb * (u64)PQ * sizeof(double)));
-            SFCI_CHECK_HIP(hipMalloc(&S->d_toff2, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
-            const unsigned g2 = (unsigned)std::min<u64>(P->Nb, (u64)P->num_cu * 8);
-            hipLaunchKernelGGL(k_build_T2, dim3(g2), dim3(256), 0, P->stream,
-                               SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, P->d_binom, Ints{P->d_h, P->d_g, P->n},
-                               S->d_tile_lo, S->ntiles, PQ, S->d_T2r, S->d_T2v, S->d_toff2);
-            SFCI_CHECK_HIP(hipGetLastError());
-            S->PQ = PQ;
-        }
+        // same-spin double elements by orbital pairs
+        const u64 np2 = (u64)P->n * (P->n - 1) / 2;
+        SFCI_CHECK_HIP(hipMalloc(&S->d_K4, std::max<u64>(1, np2 * np2) * sizeof(double)));
+        hipLaunchKernelGGL(k_build_K4, dim3((unsigned)std::max<u64>(1, (np2 * np2 + 255) / 256)), dim3(256), 0,
+                           P->stream, P->n, P->d_g, S->d_K4);
+        SFCI_CHECK_HIP(hipGetLastError());
     }
     const u64 nK = (u64)P->n * P->n;
     SFCI_CHECK_HIP(hipMalloc(&S->d_K, nK * sizeof(double)));
@@ -1156,9 +1060,7 @@ void rowtile_release(sfci_problem* P) {
     if (S->d_tile_lo) (void)hipFree(S->d_tile_lo);
     if (S->d_T1) (void)hipFree(S->d_T1);
     if (S->d_TS) (void)hipFree(S->d_TS);
-    if (S->d_T2r) (void)hipFree(S->d_T2r);
-    if (S->d_T2v) (void)hipFree(S->d_T2v);
-    if (S->d_toff2) (void)hipFree(S->d_toff2);
+    if (S->d_K4) (void)hipFree(S->d_K4);
     if (S->d_K) (void)hipFree(S->d_K);
     if (S->d_toff) (void)hipFree(S->d_toff);
     delete S;
@@ -1208,10 +1110,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.Rg = nullptr;
     rp.K2 = S->d_K;
     rp.TS = S->d_TS;
-    rp.T2r = S->d_T2r;
-    rp.T2v = S->d_T2v;
-    rp.toff2 = S->d_toff2;
-    rp.PQ = S->PQ;
+    rp.K4 = S->d_K4;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);

@@ -7,6 +7,7 @@
 // rank-sorted list); no sort of the candidates is needed.
 #include <algorithm>
 
+#include "../../include/sfci.h"
 #include "sfci_internal.h"
 
 namespace {
@@ -52,10 +53,13 @@ struct ListSrc {
     __device__ __forceinline__ void get(u64 i, u64& rr, double& c) const { rr = r[i]; c = v[i]; }
 };
 
+__device__ __forceinline__ u64 abs_bits(double c) { return (u64)__double_as_longlong(c) & 0x7FFFFFFFFFFFFFFFull; }
+
 __device__ __forceinline__ bool sel_pred(const SelState& st, const Geo& g, u64 r, double c) {
     if (c == 0.0) return false;
     if (st.take_all) return true;
     if (!st.done || st.level == 0) return false;  // M = 0: nothing is kept
+    if (st.use_thr) return abs_bits(c) >= st.thr_bits;
     u128 K = sel_key(r, c, g);
     u128 pre = ((u128)st.pre_hi << 64) | st.pre_lo;
     int sh = dig_lo(g, st.level - 1);
@@ -73,7 +77,58 @@ __global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
         st->take_all = take_all;
         st->total = 0;
         st->count_out = 0;
+        st->cmin = ~0ull;
+        st->thr_bits = 0;
+        st->count_thr = 0;
+        st->use_thr = 0;
     }
+}
+
+// Ties at the cut: the smallest |c| among the M selected (exact rule) ...
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_min(Src src, SelState* __restrict__ st, Geo g) {
+    const SelState s = *st;
+    if (s.take_all || !s.done || s.level == 0) return;
+    const u64 n = src.size();
+    u64 m = ~0ull;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        u64 r;
+        double c;
+        src.get(i, r, c);
+        if (sel_pred(s, g, r, c)) m = min(m, abs_bits(c));
+    }
+    for (int off = 32; off >= 1; off >>= 1) m = min(m, (u64)__shfl_xor((long long)m, off));
+    if ((threadIdx.x & 63) == 0 && m != ~0ull) atomicMin((unsigned long long*)&st->cmin, (unsigned long long)m);
+}
+
+// ... the threshold cmin * (1 - 2^-36) ...
+__global__ void k_sel_thr(SelState* st) {
+    if (threadIdx.x != 0 || st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
+    const double thr = __longlong_as_double((long long)st->cmin) * (1.0 - 1.0 / 68719476736.0);
+    st->thr_bits = abs_bits(thr);
+}
+
+// ... how many nonzero candidates reach it ...
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_count_thr(Src src, SelState* __restrict__ st) {
+    if (st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
+    const u64 thr = st->thr_bits;
+    const u64 n = src.size();
+    unsigned long long c_ = 0;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        u64 r;
+        double c;
+        src.get(i, r, c);
+        c_ += (c != 0.0 && abs_bits(c) >= thr) ? 1ull : 0ull;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c_ += (unsigned long long)__shfl_xor((long long)c_, off);
+    if ((threadIdx.x & 63) == 0 && c_) atomicAdd((unsigned long long*)&st->count_thr, c_);
+}
+
+// ... and whether they are kept (at most SFCI_TIE_SLACK beyond M).
+__global__ void k_sel_mode(SelState* st, u64 M) {
+    if (threadIdx.x != 0 || st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
+    st->use_thr = (st->count_thr <= M + (u64)SFCI_TIE_SLACK) ? 1 : 0;
 }
 
 template <class Src>
@@ -275,6 +330,10 @@ void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_c
             hipLaunchKernelGGL(k_sel_hist<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st, g, L);
             hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_T), 0, P->stream, st, g, L, M);
         }
+        hipLaunchKernelGGL(k_sel_min<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st, g);
+        hipLaunchKernelGGL(k_sel_thr, dim3(1), dim3(64), 0, P->stream, st);
+        hipLaunchKernelGGL(k_sel_count_thr<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st);
+        hipLaunchKernelGGL(k_sel_mode, dim3(1), dim3(64), 0, P->stream, st, M);
     }
     u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
     if (nblk < 1) nblk = 1;

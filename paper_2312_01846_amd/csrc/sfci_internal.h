@@ -45,6 +45,11 @@ struct SelState {
     int pad;
     u64 total;      // nonzero candidates (filled at level 0)
     u64 count_out;  // entries written by the compaction
+    u64 cmin;       // bits of the smallest |c| among the M selected
+    u64 thr_bits;   // bits of cmin * (1 - 2^-36)
+    u64 count_thr;  // nonzero candidates with |c| >= that
+    int use_thr;    // keep every |c| >= thr (count_thr <= M + SFCI_TIE_SLACK)
+    int pad2;
     u64 hist[2048];
 };
 

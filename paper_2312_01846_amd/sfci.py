@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsfci.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sfci.h")
 
 UINT64_MAX = (1 << 64) - 1
+TIE_SLACK = 256  # SFCI_TIE_SLACK: a truncated vector holds at most M + TIE_SLACK entries
 
 SFCI_OK = 0
 STATUS = {0: "SFCI_OK", -1: "SFCI_E_ARG", -2: "SFCI_E_RANGE", -3: "SFCI_E_DUP", -4: "SFCI_E_CAPACITY",
@@ -185,7 +186,7 @@ class Problem:
         if cap is None:
             cap = min(self.n_det, max(1, r.numel()) * self.tps)
             if M is not None:
-                cap = min(cap, int(M))
+                cap = min(cap, int(M) + TIE_SLACK)
         opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0)
         for _ in range(2):
             o_r = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
@@ -258,7 +259,7 @@ class Problem:
         st = LanczosStats()
         psi = None
         if want_psi:
-            cap = psi_capacity or min(self.n_det, n_L * (Mv if M is not None else self.n_det))
+            cap = psi_capacity or min(self.n_det, n_L * (Mv + TIE_SLACK if M is not None else self.n_det))
             p_r = torch.empty(cap, dtype=torch.int64, device="cuda")
             p_a = torch.empty(cap, dtype=torch.float64, device="cuda")
             psi = SVec(p_r.data_ptr(), p_a.data_ptr(), 0, cap)

@@ -3,10 +3,12 @@
 Every value stored here comes from ``oracle`` run on the seeded inputs of
 ``paper_2312_01846_amd.synth``; nothing is taken from the HIP path.  Usage:
 
-    python tests/golden/make_golden.py [case ...]
+    python tests/golden/make_golden.py [--out FILE] [case ...]
+    python tests/golden/make_golden.py --merge FILE ...
 
-Without arguments all cases are (re)computed; existing entries for other
-cases are kept.
+Without case names all cases are (re)computed; existing entries for other
+cases are kept.  --out writes to another file (for parallel runs), --merge
+copies such files into the golden file.
 """
 import hashlib
 import json
@@ -83,13 +85,24 @@ def run(name):
                 psi_support_sha=_support_digest(out["psi_rank"]), M=M, n_L=nL, n_iter=nit, oracle_seconds=dt)
 
 
-def main(names):
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
-    for nm in names or list(case_defs()):
+def main(argv):
+    """[--out FILE] [case ...]: compute into FILE (default: the golden file);
+    --merge FILE ...: copy the cases of each FILE into the golden file."""
+    out = OUT
+    if argv[:1] == ["--merge"]:
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+        for f in argv[1:]:
+            data.update(json.load(open(f)))
+        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+        return
+    if argv[:1] == ["--out"]:
+        out, argv = argv[1], argv[2:]
+    data = json.load(open(out)) if os.path.exists(out) else {}
+    for nm in argv or list(case_defs()):
         print("running", nm, flush=True)
         data[nm] = run(nm)
         print(nm, data[nm], flush=True)
-        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+        json.dump(data, open(out, "w"), indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":

@@ -73,15 +73,18 @@ def _perturbed(P):
     return r0[o], a0[o]
 
 
-def test_c0_truncated_golden(torch, S):
-    # Closed-shell aufbau start (n_alpha = n_beta): exact alpha/beta exchange
-    # ties at the top-M cut, which only the deterministic mode resolves as the
-    # oracle does (the fast mode's accumulation order may pick the partner).
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_c0_truncated_golden(torch, S, det):
+    # Closed-shell aufbau start (n_alpha = n_beta): alpha/beta-exchanged
+    # partners have equal magnitudes and straddle the cut; the truncation keeps
+    # such near-ties together, so the fast mode also matches the oracle.
     gd = _gold("c0_M300_30")
     P, _, _ = _c0(S)
-    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=300, n_L=10, n_iter=30, deterministic=True)
-    assert out["energies"].tolist() == gd["energies"]
-    assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
+    out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=300, n_L=10, n_iter=30, deterministic=det)
+    assert np.all(np.abs(out["energies"] - np.array(gd["energies"])) < 1e-9)
+    if det:
+        assert out["energies"].tolist() == gd["energies"]
+        assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
 
 
 @pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
@@ -119,10 +122,10 @@ def test_c1_U4_truncated_golden_deterministic(torch, S):
     assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
 
 
-@pytest.mark.parametrize("name,det", [("c2_M2e3_20", True), ("c2p_M2e3_20", True), ("c2p_M2e3_20", False)])
+@pytest.mark.parametrize("name,det", [("c2_M2e3_20", True), ("c2_M2e3_20", False), ("c2p_M2e3_20", True),
+                                      ("c2p_M2e3_20", False)])
 def test_c2_shape_golden(torch, S, name, det):
-    # 26 orbitals, multi-tile rows.  The fast mode is checked from the
-    # perturbed start (no exact exchange ties at the cut).
+    # 26 orbitals, multi-tile rows, from the aufbau and the perturbed start.
     gd = _gold(name)
     h, g = synth.molecule_like(26, 52, 2)
     P = S.Problem(26, 5, 5, h, g)
@@ -159,7 +162,5 @@ def test_c4_instance_golden(torch, S, name, det):
         assert out["energies"].tolist() == gd["energies"]
         assert _sha(out["psi_rank"].cpu().numpy()) == gd["psi_support_sha"]
     else:
-        # Closed-shell start with n_alpha = n_beta: spin-flip partners tie exactly,
-        # and FP64-atomic accumulation order decides which partner survives the
-        # truncation.  Both trajectories are valid; they stay close, not equal.
-        assert np.all(dE < 5e-3), dE
+        # closed-shell start: exchange partners tie at the cut and are kept together
+        assert np.all(dE < 1e-9), dE

@@ -127,6 +127,14 @@ def test_topm_bit_exact_with_ties(torch, S, orc):
         gr, ga = P.topm(ranks.astype(np.int64), amps, M)
         assert np.array_equal(_np(gr).astype(np.uint64), kr), M
         assert np.array_equal(_np(ga), ka), M
+    # partners one ulp apart straddling the cut are kept together, as in the oracle
+    near = amps.copy()
+    near[[300, 301, 302]] = [9.0, 9.0 * (1 + 2.0 ** -52), 9.0 * (1 - 2.0 ** -50)]
+    for M in [1, 2, 4, 5]:  # these 3 lead, then the 3 entries of 7.0
+        kr, ka = orc.topm(ranks, near, M)
+        gr, ga = P.topm(ranks.astype(np.int64), near, M)
+        assert np.array_equal(_np(gr).astype(np.uint64), kr), M
+        assert np.array_equal(_np(ga), ka), M
     # normalised form equals the oracle's Eq. 11 division
     kr, ka = orc.topm(ranks, amps, 3000)
     kan, _ = orc.normalize(ka)

@@ -148,9 +148,34 @@ def test_topm_matches_full_sort_and_ties(orc):
         kr, ka = orc.topm(ranks, amps, M)
         keys = sorted([(-abs(x), int(r), x) for r, x in zip(ranks, amps) if x != 0.0])
         keep = keys if M is None else keys[:M]
+        if M is not None and 0 < M < len(keys):
+            # plus everything within a relative 2^-36 of the M-th magnitude, if that adds <= 256
+            thr = -keep[-1][0] * (1.0 - 2.0 ** -36)
+            extra = [k for k in keys[M:] if -k[0] >= thr]
+            if len(extra) <= 256:
+                keep = keep + extra
         want = sorted((r, x) for _, r, x in keep)
         assert [int(x) for x in kr] == [r for r, _ in want]
         assert np.array_equal(ka, np.array([x for _, x in want]))
+    # the 60 planted ties of magnitude 0.25 are split only when more than 256 would have to be added
+    many = amps.copy()
+    many[:400] = 0.5
+    kr, _ = orc.topm(ranks, many, 100)
+    assert len(kr) == 100
+    above = int(np.sum(np.abs(amps) > 0.25))
+    kr, _ = orc.topm(ranks, amps, above + 5)  # the M-th entry is one of the 0.25 ties: all 60 are kept
+    assert len(kr) == above + 60
+    assert np.sum(np.abs(amps[np.isin(ranks, kr)]) == 0.25) == 60
+
+
+def test_topm_keeps_near_ties(orc):
+    # partners equal up to rounding are kept together; a real gap still cuts
+    ranks = np.arange(10, dtype=np.uint64)
+    amps = np.array([1.0, 0.9, 0.8, 0.7, 0.7 * (1 + 2.0 ** -52), 0.6, 0.5, 0.4, 0.3, 0.2])
+    kr, ka = orc.topm(ranks, amps, 4)
+    assert kr.tolist() == [0, 1, 2, 3, 4]
+    kr, ka = orc.topm(ranks, amps, 3)
+    assert kr.tolist() == [0, 1, 2]
 
 
 def test_normalize(orc):
