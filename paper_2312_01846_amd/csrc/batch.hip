@@ -23,6 +23,10 @@ struct sfci_batch {
     std::vector<DevBuf> descs;  // per iteration step j: the n instance descriptions
     DevBuf prefix, counter, scratch;
     RowTileGradWs grad_ws;
+    // per-instance chains run on these streams (forked from and joined to `own`)
+    std::vector<hipStream_t> aux;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -79,6 +83,14 @@ sfci_status sfci_batch_create(int32_t n_inst, sfci_problem* const* probs, sfci_b
     B->P.assign(probs, probs + n_inst);
     B->stream = probs[0]->stream;
     SFCI_CHECK_HIP(hipStreamCreateWithFlags(&B->own, hipStreamNonBlocking));
+    const int S = std::min(n_inst, 4);
+    B->aux.assign(S, nullptr);
+    B->ev_join.assign(S, nullptr);
+    for (int s = 0; s < S; ++s) {
+        SFCI_CHECK_HIP(hipStreamCreateWithFlags(&B->aux[s], hipStreamNonBlocking));
+        SFCI_CHECK_HIP(hipEventCreateWithFlags(&B->ev_join[s], hipEventDisableTiming));
+    }
+    SFCI_CHECK_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
     *out = B;
     return SFCI_OK;
     SFCI_GUARD_END
@@ -92,6 +104,11 @@ sfci_status sfci_batch_destroy(sfci_batch* B) {
     B->counter.release();
     B->scratch.release();
     B->grad_ws.release();
+    for (auto s : B->aux)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto e : B->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
     if (B->own) (void)hipStreamDestroy(B->own);
     delete B;
     return SFCI_OK;
@@ -180,14 +197,42 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     u64* d_pre = nullptr;
     unsigned* d_cnt = nullptr;
     void* d_scr = nullptr;
-    auto sigma_prepare = [&](int j, bool upload) {
-        for (int k = 0; k < n; ++k) launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);  // input entries
-        if (!batched_sigma) return;
-        std::vector<u64> pre(n + 1, 0);
+    // Per-instance work fans out over the auxiliary streams (instance k on
+    // aux[k % S]) and joins back to st, so that the small kernels of
+    // different instances overlap; under capture this becomes parallel graph
+    // branches.  The deterministic mode stays on st (its sort path
+    // synchronises the stream of the instance).
+    const int S = det ? 1 : (int)B->aux.size();
+    auto fan = [&](auto&& body) {
+        if (S <= 1) {
+            for (int k = 0; k < n; ++k) body(k);
+            return;
+        }
+        SFCI_CHECK_HIP(hipEventRecord(B->ev_fork, st));
+        for (int s = 0; s < S; ++s) SFCI_CHECK_HIP(hipStreamWaitEvent(B->aux[s], B->ev_fork, 0));
         for (int k = 0; k < n; ++k) {
+            I[k].P->stream = B->aux[k % S];
+            body(k);
+            I[k].P->stream = st;
+        }
+        for (int s = 0; s < S; ++s) {
+            SFCI_CHECK_HIP(hipEventRecord(B->ev_join[s], B->aux[s]));
+            SFCI_CHECK_HIP(hipStreamWaitEvent(st, B->ev_join[s], 0));
+        }
+    };
+    auto sigma_prepare = [&](int j, bool upload) {
+        if (!batched_sigma) {
+            for (int k = 0; k < n; ++k) launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);  // input entries
+            return;
+        }
+        std::vector<u64> pre(n + 1, 0);
+        fan([&](int k) {
+            launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);
             DVec w = I[k].W(j);
             descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
                                        (unsigned long long*)(I[k].sc + 32));
+        });
+        for (int k = 0; k < n; ++k) {
             pre[k + 1] = pre[k] + descs[k].n_items;
             nbr_cap = std::max(nbr_cap, descs[k].nbr_cap);
         }
@@ -227,7 +272,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         }
     };
     auto iteration_rest = [&](int j) {
-        for (int k = 0; k < n; ++k) {
+        fan([&](int k) {
             Inst& q = I[k];
             sfci_problem* P = q.P;
             DVec wj = q.W(j);
@@ -249,12 +294,12 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
                 select_topm(P, src, q.M, wn.r, wn.a, wn.nnz, true);
                 launch_normalise(P, wn.a, wn.nnz, q.cap, det);
             } else {
-                launch_fill_f64(P->d_D, P->Ndet, 0.0, st);
+                launch_fill_f64(P->d_D, P->Ndet, 0.0, P->stream);
             }
-        }
+        });
     };
     auto block_end = [&](bool last) {
-        for (int k = 0; k < n; ++k) {
+        fan([&](int k) {
             Inst& q = I[k];
             sfci_problem* P = q.P;
             launch_geneig_full(P, nL, q.T, q.S, q.lam, q.x, q.energies, q.status, q.blk);
@@ -272,7 +317,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
                 select_topm(P, src, UINT64_MAX, q.psi_r, q.psi_a, q.sc + 34, true);  // capacity n_L * cap suffices
             }
             launch_inc_int(P, q.blk);
-        }
+        });
     };
 
     // events: whole run, gradients, and one pair around every sigma launch
