@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+# value: sigma terms per second of the whole job; the roofline fraction and the
+# batched-vs-plain speedup with its energy agreement ride along in the record
+METRIC = "\u03c3 terms/s and HBM-roofline fraction; batched fwd+bwd speedup vs plain @1e-9 Ha"
 
 WORKLOADS = {
     "c2": dict(n=26, na=5, nb=5, rank=52, seed=2,
@@ -54,6 +57,33 @@ def parse():
     ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sigma_rowtile_c4batch_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_sigma_rowtile launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith(" "):
+            k, _, v = line.partition(":")
+            kv[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2312_01846_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("rowtile.hip", "sfci_device.h"))
+    if kv.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return dict(total=float(kv["traffic_bytes_per_launch"]), fetch=float(kv["fetch_bytes_per_launch"]),
+                    write=float(kv["write_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(h, g, n, na, nb, ranks, amps, target_s):
@@ -140,7 +170,7 @@ def main():
         cpu = cpu_baseline(h, g, n, na, nb, v_r.cpu().numpy().astype(np.uint64), v_a.cpu().numpy(),
                            args.cpu_seconds)
     rec = {
-        "metric": "sigma terms/s",
+        "metric": METRIC,
         "value": value,
         "unit": "terms/s",
         "n_gpus": 1,
@@ -236,8 +266,9 @@ def bench_batch(args, torch, sfci, synth):
         cpu = cpu_baseline(hs, gs, n, na, nb, sample[0].cpu().numpy().astype(np.uint64), sample[1].cpu().numpy(),
                            args.cpu_seconds)
         cpu["sample"] += f" (instance {kb}, its final Psi)"
+    traffic = measured_traffic()
     rec = {
-        "metric": "sigma terms/s (batched fwd+bwd)",
+        "metric": METRIC,
         "value": terms / wall,
         "unit": "terms/s",
         "n_gpus": 1,
@@ -273,7 +304,9 @@ def bench_batch(args, torch, sfci, synth):
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK,
-            "traffic": None,
+            "traffic": traffic["total"] / 1e9 if traffic else None,
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_fetch_write_GB": [traffic["fetch"] / 1e9, traffic["write"] / 1e9] if traffic else None,
             "sigma_kernel_ms_per_launch": st["sigma_ms"] / max(1, st["sigma_calls"]),
             "alg_bytes_per_launch": alg_bytes / max(1, st["sigma_calls"]),
             "sigma_terms_per_s_kernel": terms / sig_s if sig_s > 0 else 0.0,
