@@ -137,6 +137,8 @@ typedef struct {
     int32_t n_iter;        /* sigma applications; n_iter / n_L blocks are run */
     int32_t deterministic; /* 1: sort dedup and ordered reductions */
     int32_t dedup;         /* SFCI_DEDUP_* (ignored when deterministic) */
+    double screen_eps;     /* Sec. 3: entries of H w_j with |c| < eps are dropped before T, Eq. 10
+                              and the truncation (the paper uses 5e-5); 0 = off */
 } sfci_lanczos_opts;
 
 typedef struct {

@@ -67,7 +67,7 @@ def lib():
         L.orc_geneig.restype = i32; L.orc_geneig.argtypes = [i32, f64p, f64p, C.POINTER(dbl), f64p]
         L.orc_lanczos.restype = i64
         L.orc_lanczos.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp, vp,
-                                  vp, i64]
+                                  vp, i64, dbl]
         for nm in ("orc_backward_explicit", "orc_backward_sc"):
             f = getattr(L, nm)
             f.restype = i32
@@ -159,19 +159,21 @@ class Problem:
         v = lib().orc_sigma_entry(*self._a(), len(ranks), _u64(ranks), _f64(amps), int(target), C.byref(ab))
         return v, ab.value
 
-    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False):
+    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0):
         M = -1 if M is None else int(M)
         nblk = n_iter // n_L
         en = np.zeros(nblk, dtype=np.float64)
         T = np.zeros(nblk * n_L * n_L, dtype=np.float64)
         S = np.zeros(nblk * n_L * n_L, dtype=np.float64)
         r0, a0 = _u64(ranks0), _f64(amps0)
-        need = lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), None, None, 0)
+        need = lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), None, None, 0,
+                                 float(eps))
         if need < 0:
             raise RuntimeError("oracle lanczos failed")
         pr = np.empty(need, dtype=np.uint64)
         pa = np.empty(need, dtype=np.float64)
-        lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa), need)
+        lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa), need,
+                          float(eps))
         out = dict(energies=en, psi_rank=pr, psi_amp=pa)
         if want_T:
             out["T"] = T.reshape(nblk, n_L, n_L)

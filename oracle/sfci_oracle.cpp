@@ -715,9 +715,12 @@ static SVec lanczos_update(const SVec& y, double a, const SVec& x, double b, con
 // n_iter sigma applications are run (n_iter / N_L blocks).  energies[b]
 // receives each block's lambda.  The final Psi (before truncation) is
 // written to psi_* when psi_cap suffices; returns its size, or -1.
+// eps > 0: the screening of Sec. 3 -- entries of the merged H w_j with
+// amplitude below eps are not taken into v, so T, the Eq. 10 update and the
+// candidates all see the screened vector.
 extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
                            const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
-                           double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap) {
+                           double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps) {
     Space S = make_space(n, na, nb, h, g);
     SVec w0;
     w0.r.assign(r0, r0 + nnz0);
@@ -731,6 +734,12 @@ extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double*
         std::vector<double> T(nL * nL, 0.0), Sm(nL * nL, 0.0);
         for (int j = 0; j < nL; ++j) {
             SVec y = sigma_full(S, w[j]);
+            if (eps > 0.0) {
+                SVec ys;
+                for (size_t t = 0; t < y.r.size(); ++t)
+                    if (!(std::fabs(y.a[t]) < eps)) { ys.r.push_back(y.r[t]); ys.a.push_back(y.a[t]); }
+                y = ys;
+            }
             for (int l = 0; l <= j; ++l) {
                 double t = sdot(w[l], y);
                 T[l * nL + j] = t; T[j * nL + l] = t;

@@ -144,11 +144,13 @@ bool ensure_dense(sfci_problem* P) {
 
 // Dense-mode sigma into P->d_D: the target-owned tile kernel unless the
 // caller asks for the one-atomic-per-term kernel (or the tiles do not fit).
-void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted) {
-    if (dedup != SFCI_DEDUP_DENSE_ATOMIC && rowtile_available(P))
-        launch_sigma_rowtile(P, sl, P->d_D, emitted);
-    else
+void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted, double eps) {
+    if (dedup != SFCI_DEDUP_DENSE_ATOMIC && rowtile_available(P)) {
+        launch_sigma_rowtile(P, sl, P->d_D, emitted, eps);
+    } else {
         launch_sigma_dense(P, sl, P->d_D, emitted);
+        if (eps > 0.0) launch_screen(P, P->d_D, P->Ndet, eps);
+    }
 }
 
 namespace {
@@ -270,7 +272,8 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     rowtile_release(P);
     DevBuf* bufs[] = {&P->ws_sel,   &P->ws_cnt,   &P->ws_scan,  &P->ws_scan2,  &P->ws_scalar, &P->ws_red,
                       &P->ws_tup_k, &P->ws_tup_v, &P->ws_tup_k2, &P->ws_tup_v2, &P->ws_seg_v, &P->ws_seg_f,
-                      &P->ws_src_cnt, &P->ws_src_off, &P->ws_hist, &P->ws_list_r, &P->ws_list_a};
+                      &P->ws_src_cnt, &P->ws_src_off, &P->ws_hist, &P->ws_list_r, &P->ws_list_a,
+                      &P->ws_sel2,    &P->ws_cand_r, &P->ws_cand_a};
     for (DevBuf* b : bufs) b->release();
     for (auto& b : P->ws_lz) b.release();
     P->ws_rt_rows.release();
@@ -479,8 +482,9 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
                 sigma_sorted(P, sl, lcap, lr, la, sc + 33, sc + 32);
                 tsig.end(P->stream);
                 launch_scatter_set(P, P->d_D, lr, la, sc + 33, lcap);
+                if (o->screen_eps > 0.0) launch_screen(P, P->d_D, P->Ndet, o->screen_eps);
             } else {
-                dense_sigma(P, sl, o->dedup, (unsigned long long*)(sc + 32));
+                dense_sigma(P, sl, o->dedup, (unsigned long long*)(sc + 32), o->screen_eps);
                 tsig.end(P->stream);
             }
             ++sigma_calls;

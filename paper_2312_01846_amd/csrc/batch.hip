@@ -230,7 +230,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);
             DVec w = I[k].W(j);
             descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
-                                       (unsigned long long*)(I[k].sc + 32));
+                                       (unsigned long long*)(I[k].sc + 32), o->screen_eps);
         });
         for (int k = 0; k < n; ++k) {
             pre[k + 1] = pre[k] + descs[k].n_items;
@@ -266,8 +266,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             if (det) {
                 sigma_sorted(q.P, sl, q.lcap, q.lr, q.la, q.sc + 33, q.sc + 32);
                 launch_scatter_set(q.P, q.P->d_D, q.lr, q.la, q.sc + 33, q.lcap);
+                if (o->screen_eps > 0.0) launch_screen(q.P, q.P->d_D, q.P->Ndet, o->screen_eps);
             } else {
-                dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32));
+                dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32), o->screen_eps);
             }
         }
     };

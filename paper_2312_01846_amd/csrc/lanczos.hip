@@ -425,6 +425,12 @@ namespace {
 __global__ void k_inc_int(int* p) {
     if (threadIdx.x == 0) *p += 1;
 }
+__global__ void k_screen(double* __restrict__ D, u64 n, double eps) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        const double v = D[i];
+        if (v != 0.0 && fabs(v) < eps) D[i] = 0.0;
+    }
+}
 __global__ void k_add_u64(u64* dst, const u64* src) {
     if (threadIdx.x == 0) *dst += *src;
 }
@@ -439,6 +445,11 @@ __global__ void k_scale_copy(const double* __restrict__ a, const u64* __restrict
 
 void launch_inc_int(sfci_problem* P, int* p) {
     hipLaunchKernelGGL(k_inc_int, dim3(1), dim3(64), 0, P->stream, p);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_screen(sfci_problem* P, double* D, u64 n, double eps) {
+    hipLaunchKernelGGL(k_screen, dim3(gsz(n)), dim3(256), 0, P->stream, D, n, eps);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 

@@ -52,6 +52,7 @@ struct RTParams {
     const double* K2;            // n^2: (pp|qq) - (pq|qp)
     const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
     const double* K4;            // [(i<j), (a<b)] pair-indexed (ia|jb) - (ib|ja), pair (x<y) -> y(y-1)/2 + x
+    double eps;                  // sigma: screening threshold (Sec. 3), 0 = off
 };
 
 // One contributing source row of the current (target row, tile).
@@ -772,7 +773,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         __syncthreads();
         if (!GRAD && s_touched) {
             double* dst = p.D + rAt * Nb + tlo;
-            for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = acc[x];
+            const double eps = p.eps;
+            if (eps > 0.0)
+                for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = (fabs(acc[x]) < eps) ? 0.0 : acc[x];
+            else
+                for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = acc[x];
         }
     }
     for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
@@ -1070,7 +1075,7 @@ void rowtile_release(sfci_problem* P) {
 // Per-instance preparation on the instance's stream: row pointers, per-tile
 // entry offsets and beta strings of the input vector; returns the kernel's
 // description of this instance.  rowtile_available(P) must hold.
-RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
+RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps) {
     RowTileState* S = rt_state(P);
     const u64 cap = std::max<u64>(1, v.cap);
     const u64 nt1 = (u64)S->ntiles + 1;
@@ -1111,6 +1116,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.K2 = S->d_K;
     rp.TS = S->d_TS;
     rp.K4 = S->d_K4;
+    rp.eps = eps;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
@@ -1161,8 +1167,8 @@ unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items) {
 
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid * nbr_cap * sizeof(NbrRec); }
 
-void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted) {
-    RowTileDesc d = rowtile_prepare(P, v, D, emitted);
+void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps) {
+    RowTileDesc d = rowtile_prepare(P, v, D, emitted, eps);
     // descriptor | prefix (2 words) | counter
     char* buf = (char*)P->ws_rt_desc.get(sizeof(RTParams) + 64);
     u64 prefix[2] = {0, d.n_items};

@@ -57,6 +57,7 @@ __device__ __forceinline__ u64 abs_bits(double c) { return (u64)__double_as_long
 
 __device__ __forceinline__ bool sel_pred(const SelState& st, const Geo& g, u64 r, double c) {
     if (c == 0.0) return false;
+    if (st.cand) return abs_bits(c) >= st.cand_bits;
     if (st.take_all) return true;
     if (!st.done || st.level == 0) return false;  // M = 0: nothing is kept
     if (st.use_thr) return abs_bits(c) >= st.thr_bits;
@@ -81,7 +82,30 @@ __global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
         st->thr_bits = 0;
         st->count_thr = 0;
         st->use_thr = 0;
+        st->cand = 0;
+        st->cand_bits = 0;
+        st->count_cand = 0;
     }
+}
+
+// Dense sources: after the level-0 pick (the top key digit is the exponent
+// field of |c|), every entry that can still be kept -- including the tie rule's
+// reach just below the M-th magnitude -- has |c| >= 2^e (1 - 2^-36), e the
+// binade of the M-th |c|.  Those candidates are compacted into a list and the
+// rest of the selection runs on the list.
+__global__ void k_sel_cand_bound(SelState* st) {
+    if (threadIdx.x != 0) return;
+    u64 b;
+    if (st->take_all) {
+        b = 1;  // every nonzero entry
+    } else if (st->level == 0) {
+        b = ~0ull;  // M = 0: nothing
+    } else {
+        const u64 d0 = st->pre_lo & (u64)(NBIN - 1);
+        b = d0 == 0 ? 1 : abs_bits(__longlong_as_double((long long)(d0 << 52)) * (1.0 - 1.0 / 68719476736.0));
+    }
+    st->cand_bits = b;
+    st->cand = 1;
 }
 
 // Ties at the cut: the smallest |c| among the M selected (exact rule) ...
@@ -317,9 +341,9 @@ Geo make_geo(sfci_problem* P) {
 }
 
 template <class Src>
-void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_count_dev) {
+void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_count_dev, SelState* st = nullptr) {
     Geo g = make_geo(P);
-    SelState* st = (SelState*)P->ws_sel.get(sizeof(SelState));
+    if (!st) st = (SelState*)P->ws_sel.get(sizeof(SelState));
     int take_all = (M == UINT64_MAX) ? 1 : 0;
     int take_none = (M == 0) ? 1 : 0;
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, P->stream, st, M, take_all, take_none);
@@ -346,9 +370,9 @@ void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_c
 
 template <class Src>
 void run_write(sfci_problem* P, const Src& src, u64 n_upper, u64* out_rank, double* out_amp, bool zero_dense,
-               double* Dz) {
+               double* Dz, SelState* st = nullptr) {
     Geo g = make_geo(P);
-    SelState* st = (SelState*)P->ws_sel.p;
+    if (!st) st = (SelState*)P->ws_sel.p;
     u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
     if (nblk < 1) nblk = 1;
     u64* cnt = (u64*)P->ws_cnt.p;
@@ -385,6 +409,34 @@ void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* ou
 
 void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, double* out_amp, u64* out_count_dev,
                  bool zero_dense) {
-    select_prepare(P, src, M, out_count_dev);
-    select_write(P, src, out_rank, out_amp, zero_dense);
+    if (!src.dense || !zero_dense || M == UINT64_MAX || M == 0) {
+        select_prepare(P, src, M, out_count_dev);
+        select_write(P, src, out_rank, out_amp, zero_dense);
+        return;
+    }
+    // Dense source, truncation to M: one histogram pass for the binade of the
+    // M-th |c|, one pass to count and one to compact the candidates into a
+    // rank-ordered list (zeroing the dense array), then the full selection on
+    // the list.
+    Geo g = make_geo(P);
+    SelState* st = (SelState*)P->ws_sel.get(sizeof(SelState));
+    SelState* st2 = (SelState*)P->ws_sel2.get(sizeof(SelState));
+    u64* cr = (u64*)P->ws_cand_r.get(P->Ndet * sizeof(u64));
+    double* ca = (double*)P->ws_cand_a.get(P->Ndet * sizeof(double));
+    DenseSrc ds{src.dense, P->Ndet};
+    const unsigned hgrid = (unsigned)std::max<u64>(1, std::min<u64>((P->Ndet + 255) / 256, (u64)P->num_cu * 8));
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, P->stream, st, M, 0, 0);
+    hipLaunchKernelGGL(k_sel_hist<DenseSrc>, dim3(hgrid), dim3(256), 0, P->stream, ds, st, g, 0);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_T), 0, P->stream, st, g, 0, M);
+    hipLaunchKernelGGL(k_sel_cand_bound, dim3(1), dim3(64), 0, P->stream, st);
+    const u64 nblk = std::max<u64>(1, (P->Ndet + CCHUNK - 1) / CCHUNK);
+    u64* cnt = (u64*)P->ws_cnt.get(nblk * sizeof(u64));
+    hipLaunchKernelGGL(k_compact_count<DenseSrc>, dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, ds, st, g, cnt);
+    exclusive_scan_u64(P, cnt, cnt, nblk, &st->count_cand);
+    hipLaunchKernelGGL((k_compact_write<DenseSrc, true>), dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, ds, st, g,
+                       cnt, cr, ca, (double*)src.dense);
+    SFCI_CHECK_HIP(hipGetLastError());
+    ListSrc ls{cr, ca, &st->count_cand};
+    run_prepare(P, ls, P->Ndet, M, out_count_dev, st2);
+    run_write(P, ls, P->Ndet, out_rank, out_amp, false, nullptr, st2);
 }

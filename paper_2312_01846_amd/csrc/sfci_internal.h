@@ -49,7 +49,9 @@ struct SelState {
     u64 thr_bits;   // bits of cmin * (1 - 2^-36)
     u64 count_thr;  // nonzero candidates with |c| >= that
     int use_thr;    // keep every |c| >= thr (count_thr <= M + SFCI_TIE_SLACK)
-    int pad2;
+    int cand;       // compaction predicate: |c| >= cand_bits instead of the selection
+    u64 cand_bits;  // dense sources: bits of the candidate bound (binade of the M-th |c|, less 2^-36)
+    u64 count_cand; // candidates compacted into the list
     u64 hist[2048];
 };
 
@@ -75,6 +77,7 @@ struct sfci_problem {
     DevBuf ws_sel, ws_cnt, ws_scan, ws_scan2, ws_scalar, ws_red;
     DevBuf ws_tup_k, ws_tup_v, ws_tup_k2, ws_tup_v2, ws_seg_v, ws_seg_f, ws_src_cnt, ws_src_off, ws_hist;
     DevBuf ws_list_r, ws_list_a;
+    DevBuf ws_sel2, ws_cand_r, ws_cand_a;  // top-M of a dense source: candidate list and its selection state
     DevBuf ws_lz[8];
     DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr, ws_rt_desc;
     void* rowtile = nullptr;  // tables of the target-owned dense kernel (rowtile.hip)
@@ -107,7 +110,9 @@ void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nn
 // ---- target-owned dense sigma (rowtile.hip) ----
 bool rowtile_available(sfci_problem* P);  // builds the per-problem tables on first use
 void rowtile_release(sfci_problem* P);
-void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
+// eps > 0: accumulated entries with |c| < eps are written as zero (screening, Sec. 3).
+void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
+                          double eps = 0.0);
 // Batched form: prepare each instance, put the descriptions on the device,
 // then one launch drains the items of all instances.
 struct RowTileDesc {
@@ -126,7 +131,8 @@ struct RowTileGeom {
     unsigned itab_off;  // per-item element tables
 };
 RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
-RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted);
+RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
+                            double eps = 0.0);
 size_t rowtile_desc_bytes();
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
@@ -216,7 +222,9 @@ void sfci_sync(sfci_problem* P);
 void launch_set_u64(sfci_problem* P, u64* p, u64 v);
 void validate_vec(sfci_problem* P, const u64* r, u64 n);  // throws on out-of-range or unsorted ranks
 bool ensure_dense(sfci_problem* P);                       // allocates the zeroed N_det accumulator if it fits
-void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted);
+void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted, double eps = 0.0);
+// Screening (Sec. 3): D[i] = 0 where 0 < |D[i]| < eps.
+void launch_screen(sfci_problem* P, double* D, u64 n, double eps);
 
 // Device-resident sparse vector with a device nnz (Lanczos basis storage).
 struct DVec {

@@ -50,7 +50,7 @@ class SigmaStats(C.Structure):
 
 class LanczosOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
-                ("dedup", C.c_int32)]
+                ("dedup", C.c_int32), ("screen_eps", C.c_double)]
 
 
 class LanczosStats(C.Structure):
@@ -246,7 +246,7 @@ class Problem:
 
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
-                want_psi=True, psi_capacity=None):
+                want_psi=True, psi_capacity=None, screen_eps=0.0):
         torch = _torch()
         r = torch.as_tensor(ranks0, device="cuda").to(torch.int64).contiguous()
         a = torch.as_tensor(amps0, device="cuda").to(torch.float64).contiguous()
@@ -255,7 +255,7 @@ class Problem:
         T = np.zeros(nblk * n_L * n_L) if want_T else None
         S = np.zeros(nblk * n_L * n_L) if want_T else None
         Mv = UINT64_MAX if M is None else int(M)
-        opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup])
+        opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps))
         st = LanczosStats()
         psi = None
         if want_psi:
@@ -305,7 +305,8 @@ class Batch:
         except Exception:
             pass
 
-    def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True):
+    def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True,
+                screen_eps=0.0):
         """starts: list of (ranks, amps); Ms: truncation per instance.  Returns
         dict(energies (n_inst, n_blocks), dh [list of (n,n)], dg [list of (n,n,n,n)], stats)."""
         torch = _torch()
@@ -328,7 +329,7 @@ class Batch:
             n4 = sum(p.n ** 4 for p in self.problems)
             dh_all = torch.empty(n2, dtype=torch.float64, device="cuda")
             dg_all = torch.empty(n4, dtype=torch.float64, device="cuda")
-        opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup])
+        opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps))
         st = BatchStats()
         rc = load_library().sfci_batch_lanczos(self._h, vecs, Marr, C.byref(opts),
                                                energies.ctypes.data_as(C.c_void_p),

@@ -183,3 +183,21 @@ def test_batch_rejects_bad_arguments(torch, S):
     B = S.Batch([P])
     with pytest.raises(S.SfciError):
         B.lanczos([AUFBAU], [100], n_L=10, n_iter=5)
+
+
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_batch_screening_matches_oracle(torch, S, orc, det):
+    Pa, hc, ec = _c0(S)
+    P31, h31, e31 = _c4(S, 31)
+    B = S.Batch([Pa, P31])
+    out = B.lanczos([AUFBAU, _perturbed(P31)], [300, 2000], n_L=10, n_iter=20, deterministic=det, want_grad=False,
+                    screen_eps=5e-5)
+    ref = orc.Problem(8, 3, 3, hc, ec).lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20,
+                                               eps=5e-5)
+    if det:
+        assert np.array_equal(out["energies"][0], ref["energies"])
+    else:
+        assert np.all(np.abs(out["energies"][0] - ref["energies"]) < 1e-9)
+    # the 20-orbital instance against its own single-instance run
+    single = P31.lanczos(*_perturbed(P31), M=2000, n_L=10, n_iter=20, deterministic=det, screen_eps=5e-5)
+    assert np.all(np.abs(out["energies"][1] - single["energies"]) < 1e-9)

@@ -164,3 +164,22 @@ def test_c4_instance_golden(torch, S, name, det):
     else:
         # closed-shell start: exchange partners tie at the cut and are kept together
         assert np.all(dE < 1e-9), dE
+
+
+@pytest.mark.parametrize("mode", ["deterministic", "dense", "dense_atomic"])
+def test_screening_matches_oracle(torch, S, orc, mode):
+    # Sec. 3 screening at the paper's eps = 5e-5 (and a coarse 2e-3 that
+    # removes many entries): same energies as the oracle's screened iteration,
+    # bit for bit in deterministic mode.
+    P, h, g = _c0(S)
+    Po = orc.Problem(8, 3, 3, h, g)
+    for eps in (5e-5, 2e-3):
+        ref = Po.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30, eps=eps)
+        out = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=300, n_L=10, n_iter=30,
+                        deterministic=(mode == "deterministic"), dedup="auto" if mode == "deterministic" else mode,
+                        screen_eps=eps)
+        if mode == "deterministic":
+            assert np.array_equal(out["energies"], ref["energies"]), eps
+            assert np.array_equal(out["psi_rank"].cpu().numpy().astype(np.uint64), ref["psi_rank"])
+        else:
+            assert np.all(np.abs(out["energies"] - ref["energies"]) < 1e-9), eps

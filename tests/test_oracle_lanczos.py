@@ -119,5 +119,49 @@ def test_truncated_blocks_are_variational(orc):
 def test_truncated_vectors_have_M_entries(orc):
     P, _ = _dense_case(orc)
     out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 50, 10, 10)
-    assert len(out["psi_rank"]) <= 10 * 50
+    assert len(out["psi_rank"]) <= 10 * (50 + 256)  # each vector: M plus kept near-ties at the cut
     assert np.all(np.diff(out["psi_rank"].astype(np.int64)) > 0)
+
+
+def test_screening_matches_manual_block(orc):
+    # Sec. 3 screening: entries of H w_j below eps do not enter v.  First block
+    # with N_L = 2, no truncation, rebuilt from the oracle's sigma (pinned
+    # elsewhere) with the screen applied by hand.
+    P, _ = _dense_case(orc)
+    eps = 0.05
+    out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), None, 2, 2, want_T=True, eps=eps)
+
+    def screened_sigma(r, a):
+        sr, sa = P.sigma(r, a)
+        keep = ~(np.abs(sa) < eps)
+        return sr[keep], sa[keep]
+
+    def dot(x, y):
+        _, ix, iy = np.intersect1d(x[0], y[0], return_indices=True)
+        return float(x[1][ix] @ y[1][iy])
+
+    w0 = (np.array([0], dtype=np.uint64), np.array([1.0]))
+    y0 = screened_sigma(*w0)
+    t00 = dot(w0, y0)
+    u = dict(zip(y0[0].tolist(), y0[1].tolist()))
+    u[0] = u.get(0, 0.0) - t00
+    ur = np.array(sorted(k for k, v in u.items() if v != 0.0), dtype=np.uint64)
+    ua = np.array([u[int(k)] for k in ur])
+    w1 = (ur, ua / np.sqrt(ua @ ua))
+    y1 = screened_sigma(*w1)
+    T = out["T"][0]
+    assert abs(T[0, 0] - t00) < 1e-12
+    assert abs(T[0, 1] - dot(w0, y1)) < 1e-12 and abs(T[1, 1] - dot(w1, y1)) < 1e-12
+    # screening made a difference here
+    plain = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), None, 2, 2, want_T=True)
+    assert abs(plain["T"][0][1, 1] - T[1, 1]) > 1e-6
+
+
+def test_screening_tiny_eps_is_identity(orc):
+    P, _ = _dense_case(orc)
+    a = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30, want_T=True)
+    b = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30, want_T=True, eps=1e-300)
+    assert np.array_equal(a["energies"], b["energies"]) and np.array_equal(a["T"], b["T"])
+    # the paper's setting leaves the energy nearly unchanged on this case
+    c = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30, eps=5e-5)
+    assert abs(c["energies"][-1] - a["energies"][-1]) < 1e-3
