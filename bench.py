@@ -56,7 +56,19 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run three 1 GiB device-to-device copies (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    n = 1 << 27  # 2^27 doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied 3 x {n * 8} bytes", flush=True)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sigma_rowtile_c4batch_traffic.md")
@@ -127,6 +139,8 @@ def main():
         sys.exit("--steps and --warmup must be multiples of --n_L")
     import torch
 
+    if args.copy_probe:
+        return copy_probe(torch)
     from paper_2312_01846_amd import sfci, synth
 
     if args.workload == "c4batch":

@@ -139,6 +139,8 @@ typedef struct {
     int32_t dedup;         /* SFCI_DEDUP_* (ignored when deterministic) */
     double screen_eps;     /* Sec. 3: entries of H w_j with |c| < eps are dropped before T, Eq. 10
                               and the truncation (the paper uses 5e-5); 0 = off */
+    int32_t no_dense;      /* 1: keep every vector as a rank list and never allocate the N_det array
+                              (sort path, alpha-range passes); implied when 8 N_det bytes do not fit */
 } sfci_lanczos_opts;
 
 typedef struct {

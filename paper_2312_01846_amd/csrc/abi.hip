@@ -155,37 +155,6 @@ void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned lon
 
 namespace {
 
-struct EventTimer {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    bool on = false;
-    void begin(hipStream_t s) {
-        if (!on) return;
-        hipEvent_t a, b;
-        SFCI_CHECK_HIP(hipEventCreate(&a));
-        SFCI_CHECK_HIP(hipEventCreate(&b));
-        SFCI_CHECK_HIP(hipEventRecord(a, s));
-        ev.push_back({a, b});
-    }
-    void end(hipStream_t s) {
-        if (!on) return;
-        SFCI_CHECK_HIP(hipEventRecord(ev.back().second, s));
-    }
-    double total_ms() {
-        double t = 0.0;
-        for (auto& p : ev) {
-            float ms = 0.f;
-            SFCI_CHECK_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-            t += ms;
-        }
-        return t;
-    }
-    ~EventTimer() {
-        for (auto& p : ev) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
-        }
-    }
-};
 
 }  // namespace
 
@@ -281,6 +250,7 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_nbr.release();
     P->ws_rt_desc.release();
     P->grad_ws.release();
+    P->list_ws.release();
     delete P;
     return SFCI_OK;
 }
@@ -335,20 +305,34 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
             return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "dense accumulator does not fit on the device");
         use_sort = true;
     }
-    CandSrc src{};
-    if (!use_sort) {
-        dense_sigma(P, sl, opts->dedup, (unsigned long long*)&scal[1]);
-        src.dense = P->d_D;
-    } else {
-        u64 lcap = std::min<u64>(P->Ndet, std::max<u64>(1, v->nnz) * tps);
-        u64* lr = (u64*)P->ws_list_r.get(lcap * sizeof(u64));
-        double* la = (double*)P->ws_list_a.get(lcap * sizeof(double));
-        sigma_sorted(P, sl, lcap, lr, la, &scal[3], &scal[1]);
-        src.lrank = lr;
-        src.lval = la;
-        src.lcount = &scal[3];
-        src.lcap = lcap;
+    if (use_sort) {
+        // sort path: alpha-range passes into a running top-M candidate list,
+        // no N_det array and no full-length sigma list
+        u64 distinct = 0;
+        const u64 need = sigma_list_topm(P, sl, opts->M, out->rank, out->amp,
+                                         (out->rank && out->amp) ? out->capacity : 0, &scal[1], &distinct);
+        SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
+        const u64 emitted = read_u64(P, &scal[1]);
+        out->nnz = need;
+        sfci_status rc = SFCI_OK;
+        if (need > out->capacity || (need && (!out->rank || !out->amp)))
+            rc = (sfci_status)sfci_set_error(SFCI_E_CAPACITY, "output capacity " + std::to_string(out->capacity) +
+                                                                   " < " + std::to_string(need));
+        if (stats) {
+            float ms = 0.f;
+            SFCI_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            stats->ms = ms;
+            stats->terms_enumerated = v->nnz * tps;
+            stats->terms_emitted = emitted;
+            stats->candidates = distinct;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
     }
+    CandSrc src{};
+    dense_sigma(P, sl, opts->dedup, (unsigned long long*)&scal[1]);
+    src.dense = P->d_D;
     select_prepare(P, src, opts->M, &scal[2]);
     u64 hs[4];
     SFCI_CHECK_HIP(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, P->stream));
@@ -356,12 +340,12 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     const u64 need = hs[2];
     sfci_status rc = SFCI_OK;
     if (need > out->capacity || (need && (!out->rank || !out->amp))) {
-        if (!use_sort) launch_fill_f64(P->d_D, P->Ndet, 0.0, P->stream);
+        launch_fill_f64(P->d_D, P->Ndet, 0.0, P->stream);
         out->nnz = need;
         rc = (sfci_status)sfci_set_error(SFCI_E_CAPACITY, "output capacity " + std::to_string(out->capacity) +
                                                                " < " + std::to_string(need));
     } else {
-        select_write(P, src, out->rank, out->amp, !use_sort);
+        select_write(P, src, out->rank, out->amp, true);
         out->nnz = need;
     }
     SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
@@ -419,10 +403,7 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
     const int nL = o->n_L;
     const int nblk = o->n_iter / nL;
     const bool det = o->deterministic != 0;
-    const bool dense_ok = ensure_dense(P);
-    if (!dense_ok)
-        return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED,
-                                           "the iteration needs the dense accumulator (N_det doubles) on the device");
+    const bool list_mode = o->no_dense != 0 || !ensure_dense(P);
     // a truncated vector holds at most M + SFCI_TIE_SLACK entries
     const u64 cap = (o->M >= P->Ndet) ? P->Ndet
                                       : std::min<u64>(std::max<u64>(o->M + SFCI_TIE_SLACK, v0->nnz), P->Ndet);
@@ -446,7 +427,7 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
     u64 lcap = 0;
     u64 *lr = nullptr;
     double* la = nullptr;
-    if (det) {
+    if (det && !list_mode) {
         lcap = std::min<u64>(P->Ndet, cap * tps);
         lr = (u64*)P->ws_list_r.get(lcap * sizeof(u64));
         la = (double*)P->ws_list_a.get(lcap * sizeof(double));
@@ -467,9 +448,13 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
         launch_normalise(P, w.a, w.nnz, cap, det);
     }
     u64 sigma_calls = 0;
-    std::vector<u64> nnz_log;  // host-side record for the enumerated-term count (read at the end)
     u64* nnz_hist = (u64*)P->ws_lz[7].get((size_t)(nblk * nL + 1) * sizeof(u64));
-    for (int b = 0; b < nblk; ++b) {
+    u64 psi_n = 0;
+    if (list_mode) {
+        ListBasis LB{cap, Wr, Wa, sc, Td, Sd, xd, lam, energies_d, status, nnz_hist};
+        lanczos_list(P, o, LB, psi_out, &psi_n, &sigma_calls, tsig);
+    }
+    for (int b = 0; b < (list_mode ? 0 : nblk); ++b) {
         double* T = Td + (size_t)b * nL * nL;
         double* S = Sd + (size_t)b * nL * nL;
         for (int j = 0; j < nL; ++j) {
@@ -524,8 +509,15 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
         }
     }
     // Final Psi (untruncated) into psi_out when it fits.
-    u64 psi_n = read_u64(P, sc + 34);
     sfci_status rc = SFCI_OK;
+    if (list_mode) {
+        if (psi_out) {
+            if (psi_n > psi_out->capacity || (psi_n && (!psi_out->rank || !psi_out->amp)))
+                rc = (sfci_status)sfci_set_error(SFCI_E_CAPACITY, "psi_out capacity too small");
+            psi_out->nnz = psi_n;
+        }
+    } else {
+    psi_n = read_u64(P, sc + 34);
     CandSrc src{};
     src.dense = P->d_D;
     if (psi_out) {
@@ -539,6 +531,7 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
         }
     } else {
         launch_fill_f64(P->d_D, P->Ndet, 0.0, P->stream);
+    }
     }
     SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
     SFCI_CHECK_HIP(hipMemcpyAsync(energies, energies_d, nblk * sizeof(double), hipMemcpyDeviceToHost, P->stream));

@@ -120,6 +120,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     if (!B || !v0s || !Ms || !o || !energies) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
     if (o->n_L < 1 || o->n_L > 32 || o->n_iter < o->n_L)
         return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
+    if (o->no_dense)
+        return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "the batched iteration keeps dense accumulators");
     const int nL = o->n_L, nblk = o->n_iter / nL, n = B->n;
     const bool det = o->deterministic != 0;
     const bool use_graph = !det && (o->dedup != SFCI_DEDUP_DENSE_ATOMIC);

@@ -39,14 +39,22 @@ __device__ __forceinline__ double y_at(const u64* __restrict__ yr, const double*
     return (lo < yn && yr[lo] == key) ? ya[lo] : 0.0;
 }
 
+// y value paired with entry i of x: D[x_rank[i]] (dense) or Y[i] (already
+// gathered, GATHERED): the products and their order are the same either way.
+template <bool GATHERED>
+__device__ __forceinline__ double y_of(const u64* __restrict__ r, const double* __restrict__ D, u64 i) {
+    return GATHERED ? D[i] : D[r[i]];
+}
+
 // partial[b] = sum over a grid-stride slice of x_amp[i] * D[x_rank[i]]
+template <bool GATHERED>
 __global__ __launch_bounds__(RB) void k_dot_dense_part(const u64* __restrict__ r, const double* __restrict__ a,
                                                        const u64* __restrict__ nnz, const double* __restrict__ D,
                                                        double* __restrict__ part) {
     __shared__ double sh[RB];
     const u64 n = *nnz;
     double s = 0.0;
-    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += a[i] * D[r[i]];
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += a[i] * y_of<GATHERED>(r, D, i);
     double b = block_sum(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
@@ -79,6 +87,7 @@ __global__ __launch_bounds__(RB) void k_dot_final(const double* __restrict__ par
 
 // Ordered sums: one wavefront; products of 64 consecutive entries are formed in
 // parallel, then added one by one in index order.
+template <bool GATHERED>
 __global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict__ r, const double* __restrict__ a,
                                                           const u64* __restrict__ nnz, const double* __restrict__ D,
                                                           double* out1, double* out2) {
@@ -87,7 +96,7 @@ __global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict_
     double acc = 0.0;
     for (u64 base = 0; base < n; base += 64) {
         u64 i = base + threadIdx.x;
-        p[threadIdx.x] = (i < n) ? a[i] * D[r[i]] : 0.0;
+        p[threadIdx.x] = (i < n) ? a[i] * y_of<GATHERED>(r, D, i) : 0.0;
         __syncthreads();
         u64 cnt = (n - base < 64) ? (n - base) : 64;
         for (u64 k = 0; k < cnt; ++k) acc += p[k];
@@ -355,17 +364,30 @@ unsigned gsz(u64 cap) {
 
 }  // namespace
 
-void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
-                      double* out1, double* out2, bool ordered) {
+namespace {
+template <bool GATHERED>
+void dot_dense_impl(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
+                    double* out1, double* out2, bool ordered) {
     if (ordered) {
-        hipLaunchKernelGGL(k_dot_dense_ordered, dim3(1), dim3(64), 0, P->stream, r, a, nnz, D, out1, out2);
+        hipLaunchKernelGGL(k_dot_dense_ordered<GATHERED>, dim3(1), dim3(64), 0, P->stream, r, a, nnz, D, out1, out2);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(cap));
-        hipLaunchKernelGGL(k_dot_dense_part, dim3(g), dim3(RB), 0, P->stream, r, a, nnz, D, part);
+        hipLaunchKernelGGL(k_dot_dense_part<GATHERED>, dim3(g), dim3(RB), 0, P->stream, r, a, nnz, D, part);
         hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, out1, out2);
     }
     SFCI_CHECK_HIP(hipGetLastError());
+}
+}  // namespace
+
+void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
+                      double* out1, double* out2, bool ordered) {
+    dot_dense_impl<false>(P, r, a, nnz, cap, D, out1, out2, ordered);
+}
+
+void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 cap, const double* Y, double* out1,
+                         double* out2, bool ordered) {
+    dot_dense_impl<true>(P, nullptr, a, nnz, cap, Y, out1, out2, ordered);
 }
 
 void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,

@@ -4,7 +4,10 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
+#include "../../include/sfci.h"
 #include "sfci_device.h"
 
 #define SFCI_CHECK_HIP(expr)                                                       \
@@ -62,6 +65,14 @@ struct KeyGeom {
     u64 ndet_m1;
 };
 
+// Buffers of the list-based iteration and sigma (listlz.hip).
+struct ListWs {
+    DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a;
+    void release() {
+        for (DevBuf* b : {&scal, &pr, &pa, &mark, &Rr, &Ra, &R2r, &R2a, &yg, &taken, &psi_r, &psi_a}) b->release();
+    }
+};
+
 struct sfci_problem {
     int n, na, nb;
     u64 Na, Nb, Ndet;
@@ -85,6 +96,7 @@ struct sfci_problem {
     // shares this problem's integrals, binomial table and dense array.
     sfci_problem* swapped = nullptr;
     RowTileGradWs grad_ws;
+    ListWs list_ws;
     bool borrowed = false;  // true for such a shadow: d_h, d_g, d_binom, d_D belong to another problem
 };
 
@@ -194,12 +206,40 @@ void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* ou
 // sigma = H v by stable sort + in-order segmented sum; result sorted by rank,
 // zeros dropped, in (out_rank, out_amp) with *out_count_dev; returns false if
 // the result would exceed out_cap (then *out_count_dev = needed).
+// eps > 0 drops sums with |sum| < eps (screening, Sec. 3).
 void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_rank, double* out_amp,
-                  u64* out_count_dev, u64* emitted_dev);
+                  u64* out_count_dev, u64* emitted_dev, double eps = 0.0);
+// Pass-by-pass form: a pass covers a range [alo, ahi) of target alpha ranks
+// (ascending, disjoint).  Before a pass's reduction the sink says where its
+// entries go (appended at out[*base_dev ...], *base_dev advanced by their
+// number); after it, the sink may consume them.  tup_cap = 0: sized from free
+// memory.  Returns the number of passes run.
+struct SortPassOut {
+    u64* r;
+    double* a;
+    u64 cap;
+    u64* base_dev;
+};
+struct SortPassSink {
+    virtual SortPassOut begin(u64 alo, u64 ahi, u64 tuples) = 0;
+    virtual void end(u64 alo, u64 ahi) = 0;
+    virtual ~SortPassSink() = default;
+};
+u64 sort_tuple_cap(sfci_problem* P);
+u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
+                        double eps);
+void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2, u64 n, int kbits, u64** k_out,
+                      double** v_out);
+int key_bits(u64 maxval);
+void segmented_sum_append(sfci_problem* P, const u64* keys, const double* vals, u64 n, u64 key_base, double eps,
+                          u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a);
 
 // ---- Lanczos vector ops (lanczos.hip) ----
 void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
                       double* out1, double* out2, bool ordered);
+// The same sum with Y[i] (the y value already gathered for entry i) in place of D[r[i]].
+void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 cap, const double* Y, double* out1,
+                         double* out2, bool ordered);
 void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,
                        const double* ya, const u64* yn, double* out1, double* out2, bool ordered);
 void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap,
@@ -225,6 +265,60 @@ bool ensure_dense(sfci_problem* P);                       // allocates the zeroe
 void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned long long* emitted, double eps = 0.0);
 // Screening (Sec. 3): D[i] = 0 where 0 < |D[i]| < eps.
 void launch_screen(sfci_problem* P, double* D, u64 n, double eps);
+
+// Device time of a sequence of bracketed regions on a stream (HIP events).
+struct EventTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    bool on = false;
+    void begin(hipStream_t s) {
+        if (!on) return;
+        hipEvent_t a, b;
+        SFCI_CHECK_HIP(hipEventCreate(&a));
+        SFCI_CHECK_HIP(hipEventCreate(&b));
+        SFCI_CHECK_HIP(hipEventRecord(a, s));
+        ev.push_back({a, b});
+    }
+    void end(hipStream_t s) {
+        if (!on) return;
+        SFCI_CHECK_HIP(hipEventRecord(ev.back().second, s));
+    }
+    double total_ms() {
+        double t = 0.0;
+        for (auto& p : ev) {
+            float ms = 0.f;
+            SFCI_CHECK_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+            t += ms;
+        }
+        return t;
+    }
+    ~EventTimer() {
+        for (auto& p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    }
+};
+
+// ---- list-based iteration and truncated sigma without an N_det array (listlz.hip) ----
+// sigma = H v through the sort path's passes; the top-M (tie rule) sorted by
+// rank into out when it fits out_cap.  Returns the selected count;
+// *distinct_host (may be NULL) receives the number of distinct nonzero entries.
+u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
+                    u64* emitted_dev, u64* distinct_host);
+// The basis and the per-block outputs the iteration writes (device).
+struct ListBasis {
+    u64 cap;        // entries per basis vector
+    u64* Wr;        // n_L x cap ranks
+    double* Wa;     // n_L x cap amplitudes
+    u64* sc;        // [0, n_L) nnz per vector, [32] emitted-term counter
+    double *Td, *Sd, *xd, *lam, *energies_d;
+    int* status_d;
+    u64* nnz_hist;  // nnz of each sigma input, block after block
+};
+// w_0 must already hold the normalised start vector.  *psi_n_out receives the
+// last Psi's length; it is copied to psi_out when it fits.
+void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& B, sfci_svec* psi_out, u64* psi_n_out,
+                  u64* sigma_calls, EventTimer& tsig);
 
 // Device-resident sparse vector with a device nnz (Lanczos basis storage).
 struct DVec {

@@ -80,9 +80,10 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const u64* __restrict__
     }
 }
 
-// Run heads: sum each run of equal keys in order; flag nonzero sums.
+// Run heads: sum each run of equal keys in order; flag nonzero sums (and,
+// with eps > 0, only those with |sum| >= eps: the screening of Sec. 3).
 __global__ void k_seg_sum(const u64* __restrict__ keys, const double* __restrict__ vals, u64 n,
-                          double* __restrict__ seg, u64* __restrict__ flag) {
+                          double* __restrict__ seg, u64* __restrict__ flag, double eps) {
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
         bool head = (i == 0) || (keys[i] != keys[i - 1]);
         u64 f = 0;
@@ -91,7 +92,7 @@ __global__ void k_seg_sum(const u64* __restrict__ keys, const double* __restrict
             u64 k = keys[i];
             for (u64 j = i; j < n && keys[j] == k; ++j) s += vals[j];
             seg[i] = s;
-            f = (s != 0.0) ? 1 : 0;
+            f = (s != 0.0 && !(fabs(s) < eps)) ? 1 : 0;
         }
         flag[i] = f;
     }
@@ -136,25 +137,76 @@ int bits_for(u64 maxval) {
 
 }  // namespace
 
-void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_rank, double* out_amp,
-                  u64* out_count_dev, u64* emitted_dev) {
+// Stable LSD radix sort of (keys, vals) on the low kbits of the key; the
+// result ends in (*k_out, *v_out), which is one of the two buffer pairs.
+void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2, u64 n, int kbits, u64** k_out,
+                      double** v_out) {
+    if (n > 0) {
+        const u64 nblk = (n + RS_TILE - 1) / RS_TILE;
+        u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
+        for (int shift = 0; shift < kbits; shift += RS_BITS) {
+            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
+                               nblk);
+            exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
+            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
+                               hist, nblk, k2, v2);
+            std::swap(k1, k2);
+            std::swap(v1, v2);
+        }
+        SFCI_CHECK_HIP(hipGetLastError());
+    }
+    *k_out = k1;
+    *v_out = v1;
+}
+
+int key_bits(u64 maxval) { return bits_for(maxval); }
+
+// Sum runs of equal keys of a key-sorted list in order and append the nonzero
+// sums (key + key_base, sum) at out[*out_base + ...]; *out_base += their
+// number.  eps > 0 drops sums with |sum| < eps.
+void segmented_sum_append(sfci_problem* P, const u64* keys, const double* vals, u64 n, u64 key_base, double eps,
+                          u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a) {
+    if (n == 0) return;
+    u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));
+    double* seg = (double*)P->ws_seg_v.get(n * sizeof(double));
+    u64* flag = (u64*)P->ws_seg_f.get(n * sizeof(u64));
+    hipLaunchKernelGGL(k_seg_sum, dim3(g1(n)), dim3(256), 0, P->stream, keys, vals, n, seg, flag, eps);
+    u64* pos = (u64*)P->ws_scan2.get(n * sizeof(u64));
+    exclusive_scan_u64(P, flag, pos, n, &scal[2]);
+    hipLaunchKernelGGL(k_seg_write, dim3(g1(n)), dim3(256), 0, P->stream, keys, seg, flag, pos, n, key_base,
+                       out_base_dev, out_cap, out_r, out_a);
+    hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, out_base_dev, &scal[2]);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+u64 sort_tuple_cap(sfci_problem* P) {
+    // Tuple buffer: a quarter of free memory (7 words per tuple over the
+    // emission, sort and reduction buffers).  SFCI_SORT_TUPLE_CAP lowers it.
+    size_t freeb = 0, totb = 0;
+    SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+    const u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + 2 * sizeof(u64);
+    u64 cap = (u64)(freeb / 4) / per_tuple;
+    if (const char* env = getenv("SFCI_SORT_TUPLE_CAP")) {
+        long long e = atoll(env);
+        if (e > 0) cap = std::min<u64>(cap, (u64)e);
+    }
+    if (cap < 4096) cap = 4096;
+    return cap;
+}
+
+u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
+                        double eps) {
     const u64 cap_src = v.cap > 0 ? v.cap : 1;
     u64* counts = (u64*)P->ws_src_cnt.get(cap_src * sizeof(u64));
     u64* offs = (u64*)P->ws_src_off.get(cap_src * sizeof(u64));
-    u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));  // [0] pass total, [1] out running count
+    u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));  // [0] pass total, [2] segment count, [3] emitted
     launch_fill_u64(scal, 8, 0, P->stream);
     launch_fill_u64(counts, cap_src, 0, P->stream);
-
-    // Tuple buffer: sized to the whole job if it fits a quarter of free memory.
-    size_t freeb = 0, totb = 0;
-    SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
-    u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + 2 * sizeof(u64);
-    u64 tup_cap = (u64)(freeb / 4) / per_tuple;
-    if (tup_cap < (1u << 20)) tup_cap = 1u << 20;
+    if (tup_cap == 0) tup_cap = sort_tuple_cap(P);
 
     std::vector<std::pair<u64, u64>> todo;
     todo.push_back({0, P->Na});
-    u64 emitted_total = 0;
+    u64 emitted_total = 0, passes = 0;
     while (!todo.empty()) {
         auto [lo, hi] = todo.front();
         todo.erase(todo.begin());
@@ -172,40 +224,46 @@ void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_r
         }
         emitted_total += total;
         if (total == 0) continue;
+        ++passes;
         u64* k1 = (u64*)P->ws_tup_k.get(total * sizeof(u64));
         double* v1 = (double*)P->ws_tup_v.get(total * sizeof(double));
         u64* k2 = (u64*)P->ws_tup_k2.get(total * sizeof(u64));
         double* v2 = (double*)P->ws_tup_v2.get(total * sizeof(double));
         const u64 key_base = lo * P->Nb;
         launch_sigma_emit(P, v, lo, hi, offs, key_base, k1, v1);
-        // stable LSD radix sort on the pass-local key
-        const int kbits = bits_for((hi - lo) * P->Nb - 1);
-        const u64 nblk = (total + RS_TILE - 1) / RS_TILE;
-        u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
-        for (int shift = 0; shift < kbits; shift += RS_BITS) {
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, total, shift, hist,
-                               nblk);
-            exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
-            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, total, shift,
-                               hist, nblk, k2, v2);
-            std::swap(k1, k2);
-            std::swap(v1, v2);
-        }
-        // in-order segmented sum and compaction of nonzero results
-        double* seg = (double*)P->ws_seg_v.get(total * sizeof(double));
-        u64* flag = (u64*)P->ws_seg_f.get(total * sizeof(u64));
-        hipLaunchKernelGGL(k_seg_sum, dim3(g1(total)), dim3(256), 0, P->stream, k1, v1, total, seg, flag);
-        u64* pos = (u64*)P->ws_scan2.get(total * sizeof(u64));
-        exclusive_scan_u64(P, flag, pos, total, &scal[2]);
-        hipLaunchKernelGGL(k_seg_write, dim3(g1(total)), dim3(256), 0, P->stream, k1, seg, flag, pos, total, key_base,
-                           &scal[1], out_cap, out_rank, out_amp);
-        hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, &scal[1], &scal[2]);
-        SFCI_CHECK_HIP(hipGetLastError());
+        u64* ks;
+        double* vs;
+        radix_sort_pairs(P, k1, v1, k2, v2, total, bits_for((hi - lo) * P->Nb - 1), &ks, &vs);
+        SortPassOut out = sink.begin(lo, hi, total);
+        segmented_sum_append(P, ks, vs, total, key_base, eps, out.base_dev, out.cap, out.r, out.a);
+        sink.end(lo, hi);
     }
-    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, P->stream, out_count_dev, &scal[1]);
     if (emitted_dev) {
         SFCI_CHECK_HIP(hipMemcpyAsync(&scal[3], &emitted_total, sizeof(u64), hipMemcpyHostToDevice, P->stream));
         hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, emitted_dev, &scal[3]);
     }
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    return passes;
+}
+
+namespace {
+// Every pass appends to one rank-ordered list.
+struct AppendSink : SortPassSink {
+    u64 *r, *count_dev;
+    double* a;
+    u64 cap;
+    SortPassOut begin(u64, u64, u64) override { return SortPassOut{r, a, cap, count_dev}; }
+    void end(u64, u64) override {}
+};
+}  // namespace
+
+void sigma_sorted(sfci_problem* P, const SigmaLaunch& v, u64 out_cap, u64* out_rank, double* out_amp,
+                  u64* out_count_dev, u64* emitted_dev, double eps) {
+    launch_fill_u64(out_count_dev, 1, 0, P->stream);
+    AppendSink sink;
+    sink.r = out_rank;
+    sink.a = out_amp;
+    sink.cap = out_cap;
+    sink.count_dev = out_count_dev;
+    sigma_sorted_passes(P, v, sink, emitted_dev, 0, eps);
 }

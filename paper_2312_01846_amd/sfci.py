@@ -50,7 +50,7 @@ class SigmaStats(C.Structure):
 
 class LanczosOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
-                ("dedup", C.c_int32), ("screen_eps", C.c_double)]
+                ("dedup", C.c_int32), ("screen_eps", C.c_double), ("no_dense", C.c_int32)]
 
 
 class LanczosStats(C.Structure):
@@ -246,7 +246,7 @@ class Problem:
 
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
-                want_psi=True, psi_capacity=None, screen_eps=0.0):
+                want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False):
         torch = _torch()
         r = torch.as_tensor(ranks0, device="cuda").to(torch.int64).contiguous()
         a = torch.as_tensor(amps0, device="cuda").to(torch.float64).contiguous()
@@ -255,7 +255,8 @@ class Problem:
         T = np.zeros(nblk * n_L * n_L) if want_T else None
         S = np.zeros(nblk * n_L * n_L) if want_T else None
         Mv = UINT64_MAX if M is None else int(M)
-        opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps))
+        opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps),
+                           1 if no_dense else 0)
         st = LanczosStats()
         psi = None
         if want_psi:
