@@ -251,6 +251,7 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_desc.release();
     P->grad_ws.release();
     P->list_ws.release();
+    P->rowpass_ws.release();
     delete P;
     return SFCI_OK;
 }

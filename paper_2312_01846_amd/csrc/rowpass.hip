@@ -1,0 +1,481 @@
+// Target-row-driven emission for the sort path (Sec. 2.2's sort-and-merge
+// with buckets that are ranges of the spin-up rank, Sec. 3).
+//
+// A source determinant (A, B) reaches target alpha rows A' that are A itself,
+// an alpha single of A, or an alpha double of A; the relation is symmetric,
+// so the source rows that feed a target row are found by exciting the target
+// string.  Per sigma application:
+//   1. row pointers of the input (entries are rank-sorted, so each source
+//      alpha row is one contiguous range);
+//   2. per target row, the exact number of tuples it receives: each nonempty
+//      neighbouring source row contributes (entries) x (beta options of its
+//      relation: all beta singles and doubles plus the diagonal for the row
+//      itself, the unchanged beta string and all beta singles for an alpha
+//      single, the unchanged beta string for an alpha double);
+//   3. the host cuts the rows into passes of at most the tuple buffer;
+//   4. per pass: the (target row, source row) pairs, sorted by source row
+//      inside each target row, with their tuple offsets; then every entry of
+//      every pair emits its tuples at fixed positions.
+// Inside a target, contributions therefore sit in ascending source row and,
+// within a row, ascending entry order, i.e. ascending source rank; the stable
+// radix sort by target keeps that order and the in-order segmented sum adds
+// in it.  Every option is emitted, exact-zero elements included (adding an
+// exact zero leaves a sum's bits unchanged), so the counts are closed-form and
+// no pass ever re-enumerates a source it does not feed.  Elements use the
+// same expressions, in the same order, as the source-driven enumeration.
+#include <algorithm>
+#include <vector>
+
+#include "sfci_internal.h"
+
+namespace {
+
+constexpr int RP_WPB = 4;
+constexpr int RP_BLOCK = 64 * RP_WPB;
+constexpr u32 RP_IDENT = 0, RP_SINGLE = 1, RP_DOUBLE = 2;
+
+struct RPPair {
+    u64 tup_off;    // pass-local index of the pair's first tuple
+    u32 src_row;    // source alpha rank
+    u32 tgt_local;  // target alpha rank minus the pass's first row
+    u32 beg, ne;    // the source row's entries
+    u32 info;       // type | i << 2 | a << 7 | j << 12 | b << 17 | phase << 22 (source frame)
+    u32 pad;
+    double e2;      // alpha-alpha double: element with its phase
+};
+
+struct RPConst {
+    SpaceDev sp;
+    Ints I;
+    const u64* binom;
+    const u64* v_rank;
+    const double* v_amp;
+    const u64* v_nnz;
+    const u32* row_beg;
+    const u32* row_end;
+    int sA, sB, PA, QA, PB, QB;
+    u64 c_id, c_s;  // tuples per entry of an identity pair / a single pair
+};
+
+__device__ __forceinline__ u64 wave_sum(u64 x) {
+    for (int off = 32; off >= 1; off >>= 1) x += (u64)__shfl_xor((long long)x, off);
+    return x;
+}
+
+// exclusive prefix over the wave; *total receives the sum
+__device__ __forceinline__ u64 wave_excl_scan(u64 v, u64* total) {
+    const int lane = lane_id();
+    u64 x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        u64 y = (u64)__shfl_up((long long)x, off);
+        if (lane >= off) x += y;
+    }
+    *total = (u64)__shfl((long long)x, 63);
+    return x - v;
+}
+
+// Occupied / virtual orbital lists of a string (lanes < n write).
+__device__ __forceinline__ void fill_lists(u32 S, int n, uint8_t* occ, uint8_t* vir) {
+    const int lane = lane_id();
+    if (lane < n) {
+        const u32 below = (1u << lane) - 1u;
+        if ((S >> lane) & 1u) occ[__popc(S & below)] = (uint8_t)lane;
+        else vir[lane - __popc(S & below)] = (uint8_t)lane;
+    }
+}
+
+// Neighbour t of target string At: t = 0 itself, then its single
+// excitations, then its double excitations (pair tables pO, pV).
+__device__ __forceinline__ u32 neighbour(int t, u32 At, const uint8_t* occ, const uint8_t* vir,
+                                         const uint16_t* pO, const uint16_t* pV, int nv, int sA, int QA,
+                                         u32* type) {
+    if (t == 0) {
+        *type = RP_IDENT;
+        return At;
+    }
+    if (t <= sA) {
+        const int idx = t - 1;
+        *type = RP_SINGLE;
+        return At ^ (1u << occ[idx / nv]) ^ (1u << vir[idx % nv]);
+    }
+    const int idx = t - 1 - sA;
+    const u32 po = pO[idx / QA], pv = pV[idx % QA];
+    *type = RP_DOUBLE;
+    return At ^ (1u << occ[po & 255]) ^ (1u << occ[po >> 8]) ^ (1u << vir[pv & 255]) ^ (1u << vir[pv >> 8]);
+}
+
+__device__ __forceinline__ u64 tuples_per_entry(const RPConst& c, u32 type) {
+    return type == RP_IDENT ? c.c_id : (type == RP_SINGLE ? c.c_s : 1ull);
+}
+
+__global__ void k_fill_u32(u32* p, u64 n) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_rp_rowptr(const u64* __restrict__ v_rank, const u64* __restrict__ v_nnz, u64 Nb,
+                            u32* __restrict__ beg, u32* __restrict__ end) {
+    const u64 n = *v_nnz;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        const u64 ra = v_rank[i] / Nb;
+        if (i == 0 || v_rank[i - 1] / Nb != ra) beg[ra] = (u32)i;
+        if (i + 1 == n || v_rank[i + 1] / Nb != ra) end[ra] = (u32)(i + 1);
+    }
+}
+
+// Per target row: tuples received and nonempty neighbouring source rows.
+__global__ __launch_bounds__(RP_BLOCK) void k_rp_count(RPConst c, u64* __restrict__ cnt, u32* __restrict__ npair) {
+    __shared__ BinomLds B;
+    __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
+    __shared__ uint8_t occ[RP_WPB][32], vir[RP_WPB][32];
+    load_binom(B, c.binom);
+    const int n = c.sp.n, na = c.sp.na, nva = n - na;
+    for (int t = threadIdx.x; t < c.PA; t += blockDim.x) pO[t] = decode_pair(t, na);
+    for (int t = threadIdx.x; t < c.QA; t += blockDim.x) pV[t] = decode_pair(t, nva);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int K = 1 + c.sA + c.PA * c.QA;
+    for (u64 r = (u64)blockIdx.x * RP_WPB + wave; r < c.sp.Na; r += (u64)gridDim.x * RP_WPB) {
+        const u32 At = str_unrank(r, na, n, B);
+        wave_sync();
+        fill_lists(At, n, occ[wave], vir[wave]);
+        wave_sync();
+        u64 s = 0, k = 0;
+        for (int t = lane; t < K; t += 64) {
+            u32 type;
+            const u32 As = neighbour(t, At, occ[wave], vir[wave], pO, pV, nva, c.sA, c.QA, &type);
+            const u64 rs = str_rank(As, B);
+            const u32 ne = c.row_end[rs] - c.row_beg[rs];
+            if (ne) {
+                s += (u64)ne * tuples_per_entry(c, type);
+                ++k;
+            }
+        }
+        s = wave_sum(s);
+        k = wave_sum(k);
+        if (lane == 0) {
+            cnt[r] = s;
+            npair[r] = (u32)k;
+        }
+    }
+}
+
+// Pairs of the target rows [lo, hi): one wavefront per row collects the
+// nonempty neighbours, sorts them by source rank (bitonic, in LDS) and writes
+// the records with their tuple offsets.
+__global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, const u64* __restrict__ tup_pre,
+                                                 const u64* __restrict__ pair_pre, RPPair* __restrict__ pairs) {
+    extern __shared__ u64 keys[];
+    __shared__ BinomLds B;
+    __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
+    __shared__ uint8_t occ[32], vir[32];
+    load_binom(B, c.binom);
+    const int n = c.sp.n, na = c.sp.na, nva = n - na;
+    for (int t = threadIdx.x; t < c.PA; t += blockDim.x) pO[t] = decode_pair(t, na);
+    for (int t = threadIdx.x; t < c.QA; t += blockDim.x) pV[t] = decode_pair(t, nva);
+    __syncthreads();
+    const int lane = lane_id();
+    const int K = 1 + c.sA + c.PA * c.QA;
+    const u64 Nb = c.sp.Nb;
+    for (u64 r = lo + blockIdx.x; r < hi; r += gridDim.x) {
+        const u32 At = str_unrank(r, na, n, B);
+        wave_sync();
+        fill_lists(At, n, occ, vir);
+        wave_sync();
+        u32 k = 0;
+        for (int t0 = 0; t0 < K; t0 += 64) {
+            const int t = t0 + lane;
+            bool ok = false;
+            u64 key = 0;
+            if (t < K) {
+                u32 type;
+                const u32 As = neighbour(t, At, occ, vir, pO, pV, nva, c.sA, c.QA, &type);
+                const u64 rs = str_rank(As, B);
+                ok = c.row_end[rs] != c.row_beg[rs];
+                key = (rs << 16) | (u64)t;
+            }
+            const u64 m = __ballot(ok);
+            if (ok) keys[k + (u32)__popcll(m & ((1ull << lane) - 1ull))] = key;
+            k += (u32)__popcll(m);
+        }
+        u32 N = 1;
+        while (N < k) N <<= 1;
+        for (u32 t = k + lane; t < N; t += 64) keys[t] = ~0ull;
+        wave_sync();
+        for (u32 size = 2; size <= N; size <<= 1) {
+            for (u32 stride = size >> 1; stride > 0; stride >>= 1) {
+                for (u32 t = lane; t < N / 2; t += 64) {
+                    const u32 i = 2 * t - (t & (stride - 1));
+                    const u32 j = i + stride;
+                    const bool up = (i & size) == 0;
+                    const u64 x = keys[i], y = keys[j];
+                    if ((x > y) == up) {
+                        keys[i] = y;
+                        keys[j] = x;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        const u64 tbase = tup_pre[r] - tup_pre[lo];
+        const u64 pbase = pair_pre[r] - pair_pre[lo];
+        u64 run = 0;
+        for (u32 q0 = 0; q0 < k; q0 += 64) {
+            const u32 q = q0 + lane;
+            u64 cntq = 0;
+            RPPair pr{};
+            if (q < k) {
+                const u64 key = keys[q];
+                const u64 rs = key >> 16;
+                const int t = (int)(key & 0xffff);
+                u32 type;
+                const u32 As = neighbour(t, At, occ, vir, pO, pV, nva, c.sA, c.QA, &type);
+                pr.src_row = (u32)rs;
+                pr.tgt_local = (u32)(r - lo);
+                pr.beg = c.row_beg[rs];
+                pr.ne = c.row_end[rs] - pr.beg;
+                u32 info = type;
+                if (type == RP_SINGLE) {
+                    // source A = As moves i -> a to reach At
+                    const int i = __builtin_ctz(As & ~At), a = __builtin_ctz(At & ~As);
+                    info |= (u32)i << 2 | (u32)a << 7 | (u32)between_parity(As, i, a) << 22;
+                } else if (type == RP_DOUBLE) {
+                    const u32 d1 = As & ~At, d2 = At & ~As;
+                    const int i = __builtin_ctz(d1), j = __builtin_ctz(d1 & (d1 - 1u));
+                    const int a = __builtin_ctz(d2), b = __builtin_ctz(d2 & (d2 - 1u));
+                    const u32 mid = As ^ (1u << i) ^ (1u << a);
+                    const int par = between_parity(As, i, a) ^ between_parity(mid, j, b);
+                    double e = (c.I.G(i, a, j, b) - c.I.G(i, b, j, a));
+                    if (par) e = -e;
+                    pr.e2 = e;
+                    info |= (u32)i << 2 | (u32)a << 7 | (u32)j << 12 | (u32)b << 17 | (u32)par << 22;
+                }
+                pr.info = info;
+                cntq = (u64)pr.ne * tuples_per_entry(c, type);
+            }
+            u64 tot;
+            const u64 pre = wave_excl_scan(cntq, &tot);
+            if (q < k) {
+                pr.tup_off = tbase + run + pre;
+                pairs[pbase + q] = pr;
+            }
+            run += tot;
+        }
+        (void)Nb;
+        wave_sync();
+    }
+}
+
+// Emission: every wavefront owns the entries whose first tuple falls in its
+// share of the pass's tuples.  Alpha-alpha pairs: a lane per entry; the other
+// pairs: the wavefront walks one entry's beta options across its lanes.
+__global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* __restrict__ pairs, u64 npairs,
+                                                      u64 total, u64* __restrict__ keys, double* __restrict__ vals,
+                                                      unsigned long long* __restrict__ nonzero) {
+    __shared__ BinomLds B;
+    __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
+    __shared__ uint8_t occ[RP_WPB][32], vir[RP_WPB][32];
+    load_binom(B, c.binom);
+    const int n = c.sp.n, na = c.sp.na, nb = c.sp.nb, nvb = n - nb;
+    for (int t = threadIdx.x; t < c.PB; t += blockDim.x) pO[t] = decode_pair(t, nb);
+    for (int t = threadIdx.x; t < c.QB; t += blockDim.x) pV[t] = decode_pair(t, nvb);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const u64 gw = (u64)blockIdx.x * RP_WPB + wave, NW = (u64)gridDim.x * RP_WPB;
+    const u64 T0 = (u64)(((unsigned __int128)total * gw) / NW);
+    const u64 T1 = (u64)(((unsigned __int128)total * (gw + 1)) / NW);
+    u64 nz = 0;
+    if (T0 < T1 && npairs > 0) {
+        // last pair whose first tuple is <= T0
+        u64 lo = 0, hi = npairs;
+        while (hi - lo > 1) {
+            const u64 mid = lo + ((hi - lo) >> 1);
+            if (pairs[mid].tup_off <= T0) lo = mid;
+            else hi = mid;
+        }
+        const u64 Nb = c.sp.Nb;
+        for (u64 p = lo; p < npairs; ++p) {
+            const RPPair pr = pairs[p];
+            if (pr.tup_off >= T1) break;
+            const u32 type = pr.info & 3u;
+            const u64 cp = tuples_per_entry(c, type);
+            // entries whose first tuple lies in [T0, T1)
+            u64 e0 = (pr.tup_off >= T0) ? 0 : (T0 - pr.tup_off + cp - 1) / cp;
+            u64 e1 = (T1 - pr.tup_off + cp - 1) / cp;
+            if (e1 > pr.ne) e1 = pr.ne;
+            if (e0 >= e1) continue;
+            const u64 tgt_base = (u64)pr.tgt_local * Nb;
+            if (type == RP_DOUBLE) {
+                for (u64 e = e0 + lane; e < e1; e += 64) {
+                    const u64 s = pr.beg + e;
+                    const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
+                    const u64 at = pr.tup_off + e;
+                    keys[at] = tgt_base + rB;
+                    vals[at] = pr.e2 * c.v_amp[s];
+                    nz += (pr.e2 != 0.0) ? 1 : 0;
+                }
+                continue;
+            }
+            const u32 A = str_unrank(pr.src_row, na, n, B);
+            const int i = (pr.info >> 2) & 31, a = (pr.info >> 7) & 31, pa = (pr.info >> 22) & 1;
+            for (u64 e = e0; e < e1; ++e) {
+                const u64 s = pr.beg + e;
+                const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
+                const double amp = c.v_amp[s];
+                const u32 Bs = str_unrank(rB, nb, n, B);
+                wave_sync();
+                fill_lists(Bs, n, occ[wave], vir[wave]);
+                wave_sync();
+                const u64 base = pr.tup_off + e * cp;
+                for (u64 o = lane; o < cp; o += 64) {
+                    double el;
+                    u64 tb;
+                    if (type == RP_SINGLE) {
+                        if (o == 0) {
+                            el = single_element_nophase(c.I, A, Bs, i, a);
+                            if (pa) el = -el;
+                            tb = rB;
+                        } else {
+                            const int idx = (int)o - 1;
+                            const int jj = occ[wave][idx / nvb], bb = vir[wave][idx % nvb];
+                            const u32 B2 = Bs ^ (1u << jj) ^ (1u << bb);
+                            el = c.I.G(i, a, jj, bb);
+                            if (pa ^ between_parity(Bs, jj, bb)) el = -el;
+                            tb = str_rank(B2, B);
+                        }
+                    } else if (o == 0) {
+                        el = diag_element(c.I, A, Bs);
+                        tb = rB;
+                    } else if ((int)o <= c.sB) {
+                        const int idx = (int)o - 1;
+                        const int jj = occ[wave][idx / nvb], bb = vir[wave][idx % nvb];
+                        const u32 B2 = Bs ^ (1u << jj) ^ (1u << bb);
+                        el = single_element_nophase(c.I, Bs, A, jj, bb);
+                        if (between_parity(Bs, jj, bb)) el = -el;
+                        tb = str_rank(B2, B);
+                    } else {
+                        const int idx = (int)o - 1 - c.sB;
+                        const u32 po = pO[idx / c.QB], pv = pV[idx % c.QB];
+                        const int ii = occ[wave][po & 255], jj = occ[wave][po >> 8];
+                        const int aa = vir[wave][pv & 255], bb = vir[wave][pv >> 8];
+                        const u32 mid = Bs ^ (1u << ii) ^ (1u << aa);
+                        const u32 B2 = mid ^ (1u << jj) ^ (1u << bb);
+                        const int par = between_parity(Bs, ii, aa) ^ between_parity(mid, jj, bb);
+                        el = (c.I.G(ii, aa, jj, bb) - c.I.G(ii, bb, jj, aa));
+                        if (par) el = -el;
+                        tb = str_rank(B2, B);
+                    }
+                    keys[base + o] = tgt_base + tb;
+                    vals[base + o] = el * amp;
+                    nz += (el != 0.0) ? 1 : 0;
+                }
+            }
+        }
+    }
+    nz = wave_sum(nz);
+    if (lane == 0 && nz) atomicAdd(nonzero, (unsigned long long)nz);
+}
+
+unsigned g1(u64 n) {
+    u64 g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
+                  double eps) {
+    if (v.cap >= (1ull << 32)) throw sfci_error(-8, "sort path: more than 2^32 input entries");
+    const int n = P->n, na = P->na, nb = P->nb;
+    const u64 Na = P->Na, Nb = P->Nb;
+    RPConst c;
+    c.sp = SpaceDev{n, na, nb, Na, Nb};
+    c.I = Ints{P->d_h, P->d_g, n};
+    c.binom = P->d_binom;
+    c.v_rank = v.v_rank;
+    c.v_amp = v.v_amp;
+    c.v_nnz = v.v_nnz;
+    c.sA = na * (n - na);
+    c.sB = nb * (n - nb);
+    c.PA = na * (na - 1) / 2;
+    c.QA = (n - na) * (n - na - 1) / 2;
+    c.PB = nb * (nb - 1) / 2;
+    c.QB = (n - nb) * (n - nb - 1) / 2;
+    c.c_id = 1 + (u64)c.sB + (u64)c.PB * c.QB;
+    c.c_s = 1 + (u64)c.sB;
+    const int K = 1 + c.sA + c.PA * c.QA;
+    if (K > 65536) throw sfci_error(-8, "sort path: more than 65536 alpha neighbours per string");
+    u32 Kp2 = 1;
+    while (Kp2 < (u32)K) Kp2 <<= 1;
+    if ((size_t)Kp2 * sizeof(u64) > 128 * 1024) throw sfci_error(-8, "sort path: neighbour list exceeds LDS");
+    if ((size_t)Kp2 * sizeof(u64) > 48 * 1024)
+        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_rp_pairs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(Kp2 * sizeof(u64))));
+    if (tup_cap == 0) tup_cap = sort_tuple_cap(P);
+
+    RowPassWs& ws = P->rowpass_ws;
+    u32* beg = (u32*)ws.beg.get(Na * sizeof(u32));
+    u32* end = (u32*)ws.end.get(Na * sizeof(u32));
+    u64* cnt = (u64*)ws.cnt.get(Na * sizeof(u64));
+    u32* np = (u32*)ws.npair.get(Na * sizeof(u32));
+    u64* tpre = (u64*)ws.tup_pre.get((Na + 1) * sizeof(u64));
+    u64* ppre = (u64*)ws.pair_pre.get((Na + 1) * sizeof(u64));
+    unsigned long long* nz = (unsigned long long*)ws.scal.get(8 * sizeof(u64));
+    c.row_beg = beg;
+    c.row_end = end;
+    hipLaunchKernelGGL(k_fill_u32, dim3(g1(Na)), dim3(256), 0, P->stream, beg, Na);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g1(Na)), dim3(256), 0, P->stream, end, Na);
+    launch_fill_u64((u64*)nz, 1, 0, P->stream);
+    hipLaunchKernelGGL(k_rp_rowptr, dim3(g1(v.cap)), dim3(256), 0, P->stream, v.v_rank, v.v_nnz, Nb, beg, end);
+    const unsigned cgrid = (unsigned)std::max<u64>(1, std::min<u64>((Na + RP_WPB - 1) / RP_WPB, (u64)P->num_cu * 16));
+    hipLaunchKernelGGL(k_rp_count, dim3(cgrid), dim3(RP_BLOCK), 0, P->stream, c, cnt, np);
+    SFCI_CHECK_HIP(hipGetLastError());
+    std::vector<u64> hc(Na), htp(Na + 1), hpp(Na + 1);
+    std::vector<u32> hn(Na);
+    SFCI_CHECK_HIP(hipMemcpyAsync(hc.data(), cnt, Na * sizeof(u64), hipMemcpyDeviceToHost, P->stream));
+    SFCI_CHECK_HIP(hipMemcpyAsync(hn.data(), np, Na * sizeof(u32), hipMemcpyDeviceToHost, P->stream));
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    htp[0] = hpp[0] = 0;
+    for (u64 r = 0; r < Na; ++r) {
+        htp[r + 1] = htp[r] + hc[r];
+        hpp[r + 1] = hpp[r] + hn[r];
+    }
+    SFCI_CHECK_HIP(hipMemcpyAsync(tpre, htp.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
+    SFCI_CHECK_HIP(hipMemcpyAsync(ppre, hpp.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
+
+    const u64 pair_cap = 1ull << 26;
+    const unsigned egrid = (unsigned)P->num_cu * 8;
+    u64 passes = 0;
+    u64 lo = 0;
+    while (lo < Na) {
+        if (hc[lo] > tup_cap) throw sfci_error(-5, "sort path: one alpha row exceeds the tuple buffer");
+        u64 hi = lo + 1;
+        while (hi < Na && htp[hi + 1] - htp[lo] <= tup_cap && hpp[hi + 1] - hpp[lo] <= pair_cap) ++hi;
+        const u64 tuples = htp[hi] - htp[lo], npairs = hpp[hi] - hpp[lo];
+        if (tuples > 0) {
+            ++passes;
+            RPPair* pairs = (RPPair*)ws.pairs.get(npairs * sizeof(RPPair));
+            const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 32);
+            hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(64), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
+                               ppre, pairs);
+            u64* k1 = (u64*)P->ws_tup_k.get(tuples * sizeof(u64));
+            double* v1 = (double*)P->ws_tup_v.get(tuples * sizeof(double));
+            u64* k2 = (u64*)P->ws_tup_k2.get(tuples * sizeof(u64));
+            double* v2 = (double*)P->ws_tup_v2.get(tuples * sizeof(double));
+            hipLaunchKernelGGL(k_rp_emit, dim3(egrid), dim3(RP_BLOCK), 0, P->stream, c, (const RPPair*)pairs, npairs,
+                               tuples, k1, v1, nz);
+            SFCI_CHECK_HIP(hipGetLastError());
+            u64* ks;
+            double* vs;
+            radix_sort_pairs(P, k1, v1, k2, v2, tuples, key_bits((hi - lo) * Nb - 1), &ks, &vs);
+            SortPassOut out = sink.begin(lo, hi, tuples);
+            segmented_sum_append(P, ks, vs, tuples, lo * Nb, eps, out.base_dev, out.cap, out.r, out.a);
+            sink.end(lo, hi);
+        }
+        lo = hi;
+    }
+    if (emitted_dev) launch_add_u64(P, emitted_dev, (const u64*)nz);
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    return passes;
+}

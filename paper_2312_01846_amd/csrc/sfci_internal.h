@@ -65,6 +65,14 @@ struct KeyGeom {
     u64 ndet_m1;
 };
 
+// Buffers of the target-row-driven sort-path emission (rowpass.hip).
+struct RowPassWs {
+    DevBuf beg, end, cnt, npair, tup_pre, pair_pre, pairs, scal;
+    void release() {
+        for (DevBuf* b : {&beg, &end, &cnt, &npair, &tup_pre, &pair_pre, &pairs, &scal}) b->release();
+    }
+};
+
 // Buffers of the list-based iteration and sigma (listlz.hip).
 struct ListWs {
     DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a;
@@ -97,6 +105,7 @@ struct sfci_problem {
     sfci_problem* swapped = nullptr;
     RowTileGradWs grad_ws;
     ListWs list_ws;
+    RowPassWs rowpass_ws;
     bool borrowed = false;  // true for such a shadow: d_h, d_g, d_binom, d_D belong to another problem
 };
 
@@ -228,6 +237,11 @@ struct SortPassSink {
 u64 sort_tuple_cap(sfci_problem* P);
 u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
                         double eps);
+// The same passes with target-row-driven emission (rowpass.hip): per-row
+// tuple counts once per call, then per pass only the (target row, source
+// row) pairs that land in it.
+u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
+                  double eps);
 void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2, u64 n, int kbits, u64** k_out,
                       double** v_out);
 int key_bits(u64 maxval);

@@ -196,6 +196,8 @@ u64 sort_tuple_cap(sfci_problem* P) {
 
 u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
                         double eps) {
+    const char* how = getenv("SFCI_SORT_EMIT");
+    if (!how || std::string(how) != "source") return sigma_rowpass(P, v, sink, emitted_dev, tup_cap, eps);
     const u64 cap_src = v.cap > 0 ? v.cap : 1;
     u64* counts = (u64*)P->ws_src_cnt.get(cap_src * sizeof(u64));
     u64* offs = (u64*)P->ws_src_off.get(cap_src * sizeof(u64));

@@ -159,3 +159,30 @@ def test_sigma_topm_in_passes_matches_oracle(torch, S, orc, monkeypatch, M):
     assert st["candidates"] == int(np.count_nonzero(fa))
 
 
+
+
+@pytest.mark.parametrize("case", ["c0", "hubbard", "n20", "n26"])
+def test_row_emission_equals_source_emission(torch, S, monkeypatch, case):
+    # target-row-driven passes (per-row counts, sorted pair lists, exact-zero
+    # elements emitted) against the source-driven passes: identical sigma,
+    # identical count of nonzero elements
+    if case == "c0":
+        h, g = synth.molecule_like(8, 16, 0)
+        P = S.Problem(8, 3, 3, h, g)
+    elif case == "hubbard":
+        h, g = synth.hubbard_ring(12, 1.0, 4.0)
+        P = S.Problem(12, 6, 6, h, g)
+    elif case == "n20":
+        _, h, g = synth.bond_stretch_batch(20, 32, 40)[9]
+        P = S.Problem(20, 4, 4, h, g)
+    else:
+        h, g = synth.molecule_like(26, 52, 2)
+        P = S.Problem(26, 5, 5, h, g)
+    r0, a0 = _perturbed(P)
+    monkeypatch.setenv("SFCI_SORT_TUPLE_CAP", str(1 << 20))
+    r1, a1, s1 = P.sigma(r0, a0, deterministic=True)
+    monkeypatch.setenv("SFCI_SORT_EMIT", "source")
+    r2, a2, s2 = P.sigma(r0, a0, deterministic=True)
+    assert np.array_equal(_np(r1), _np(r2))
+    assert np.array_equal(_np(a1), _np(a2))
+    assert s1["terms_emitted"] == s2["terms_emitted"]
