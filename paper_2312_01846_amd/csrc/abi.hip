@@ -241,7 +241,7 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     rowtile_release(P);
     DevBuf* bufs[] = {&P->ws_sel,   &P->ws_cnt,   &P->ws_scan,  &P->ws_scan2,  &P->ws_scalar, &P->ws_red,
                       &P->ws_tup_k, &P->ws_tup_v, &P->ws_tup_k2, &P->ws_tup_v2, &P->ws_seg_v, &P->ws_seg_f,
-                      &P->ws_src_cnt, &P->ws_src_off, &P->ws_hist, &P->ws_list_r, &P->ws_list_a,
+                      &P->ws_src_cnt, &P->ws_src_off, &P->ws_hist, &P->ws_list_r, &P->ws_list_a, &P->ws_prod,
                       &P->ws_sel2,    &P->ws_cand_r, &P->ws_cand_a};
     for (DevBuf* b : bufs) b->release();
     for (auto& b : P->ws_lz) b.release();

@@ -87,20 +87,29 @@ __global__ __launch_bounds__(RB) void k_dot_final(const double* __restrict__ par
 
 // Ordered sums: one wavefront; products of 64 consecutive entries are formed in
 // parallel, then added one by one in index order.
+// acc += p_base, p_base+1, ..., in index order: the 64 products of a chunk
+// are formed by the lanes and staged in LDS, then lane 0 adds them one by
+// one (its acc is the result).
+__device__ __forceinline__ double add_chunk_in_order(double acc, double p, int cnt, double* stage) {
+    stage[threadIdx.x & 63] = p;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < cnt; ++k) acc += stage[k];
+    __syncthreads();
+    return acc;
+}
+
 template <bool GATHERED>
 __global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict__ r, const double* __restrict__ a,
                                                           const u64* __restrict__ nnz, const double* __restrict__ D,
                                                           double* out1, double* out2) {
-    __shared__ double p[64];
+    __shared__ double stage[64];
     const u64 n = *nnz;
     double acc = 0.0;
     for (u64 base = 0; base < n; base += 64) {
-        u64 i = base + threadIdx.x;
-        p[threadIdx.x] = (i < n) ? a[i] * y_of<GATHERED>(r, D, i) : 0.0;
-        __syncthreads();
-        u64 cnt = (n - base < 64) ? (n - base) : 64;
-        for (u64 k = 0; k < cnt; ++k) acc += p[k];
-        __syncthreads();
+        const u64 i = base + threadIdx.x;
+        const double p = (i < n) ? a[i] * y_of<GATHERED>(r, D, i) : 0.0;
+        acc = add_chunk_in_order(acc, p, (int)((n - base < 64) ? (n - base) : 64), stage);
     }
     if (threadIdx.x == 0) {
         *out1 = acc;
@@ -108,24 +117,29 @@ __global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict_
     }
 }
 
-__global__ __launch_bounds__(64) void k_dot_sparse_ordered(const u64* __restrict__ xr, const double* __restrict__ xa,
-                                                           const u64* __restrict__ xn, const u64* __restrict__ yr,
-                                                           const double* __restrict__ ya, const u64* __restrict__ yn,
-                                                           double* out1, double* out2) {
-    __shared__ double p[64];
-    __shared__ int hit[64];
+// Sparse-sparse products x_i * y(rank_i) (0 where y has no entry), formed
+// in parallel; the ordered sum below then adds them in index order.  Adding
+// +0 for a missing entry changes nothing: the running sum starts at +0 and
+// round-to-nearest never turns it into -0.
+__global__ __launch_bounds__(RB) void k_sparse_products(const u64* __restrict__ xr, const double* __restrict__ xa,
+                                                        const u64* __restrict__ xn, const u64* __restrict__ yr,
+                                                        const double* __restrict__ ya, const u64* __restrict__ yn,
+                                                        double* __restrict__ prod) {
     const u64 n = *xn, m = *yn;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) {
+        const double yv = y_at(yr, ya, m, xr[i]);
+        prod[i] = (yv != 0.0) ? xa[i] * yv : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_sum_ordered(const double* __restrict__ prod, const u64* __restrict__ nnz,
+                                                    double* out1, double* out2) {
+    __shared__ double stage[64];
+    const u64 n = *nnz;
     double acc = 0.0;
     for (u64 base = 0; base < n; base += 64) {
-        u64 i = base + threadIdx.x;
-        double yv = (i < n) ? y_at(yr, ya, m, xr[i]) : 0.0;
-        p[threadIdx.x] = (yv != 0.0) ? xa[i] * yv : 0.0;
-        hit[threadIdx.x] = (yv != 0.0);
-        __syncthreads();
-        u64 cnt = (n - base < 64) ? (n - base) : 64;
-        for (u64 k = 0; k < cnt; ++k)
-            if (hit[k]) acc += p[k];
-        __syncthreads();
+        const u64 i = base + threadIdx.x;
+        acc = add_chunk_in_order(acc, (i < n) ? prod[i] : 0.0, (int)((n - base < 64) ? (n - base) : 64), stage);
     }
     if (threadIdx.x == 0) {
         *out1 = acc;
@@ -165,16 +179,13 @@ __global__ __launch_bounds__(RB) void k_sumsq_part(const double* __restrict__ a,
 
 __global__ __launch_bounds__(64) void k_sumsq_ordered(const double* __restrict__ a, const u64* __restrict__ nnz,
                                                       double* out) {
-    __shared__ double p[64];
+    __shared__ double stage[64];
     const u64 n = *nnz;
     double acc = 0.0;
     for (u64 base = 0; base < n; base += 64) {
-        u64 i = base + threadIdx.x;
-        p[threadIdx.x] = (i < n) ? a[i] * a[i] : 0.0;
-        __syncthreads();
-        u64 cnt = (n - base < 64) ? (n - base) : 64;
-        for (u64 k = 0; k < cnt; ++k) acc += p[k];
-        __syncthreads();
+        const u64 i = base + threadIdx.x;
+        const double p = (i < n) ? a[i] * a[i] : 0.0;
+        acc = add_chunk_in_order(acc, p, (int)((n - base < 64) ? (n - base) : 64), stage);
     }
     if (threadIdx.x == 0) *out = acc;
 }
@@ -393,7 +404,9 @@ void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 c
 void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,
                        const double* ya, const u64* yn, double* out1, double* out2, bool ordered) {
     if (ordered) {
-        hipLaunchKernelGGL(k_dot_sparse_ordered, dim3(1), dim3(64), 0, P->stream, xr, xa, xn, yr, ya, yn, out1, out2);
+        double* prod = (double*)P->ws_prod.get(std::max<u64>(1, xcap) * sizeof(double));
+        hipLaunchKernelGGL(k_sparse_products, dim3(gsz(xcap)), dim3(RB), 0, P->stream, xr, xa, xn, yr, ya, yn, prod);
+        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, P->stream, (const double*)prod, xn, out1, out2);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(xcap));

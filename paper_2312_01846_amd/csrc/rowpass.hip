@@ -269,7 +269,7 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
 // share of the pass's tuples.  Alpha-alpha pairs: a lane per entry; the other
 // pairs: the wavefront walks one entry's beta options across its lanes.
 __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* __restrict__ pairs, u64 npairs,
-                                                      u64 total, u64* __restrict__ keys, double* __restrict__ vals,
+                                                      u64 total, u32* __restrict__ keys, double* __restrict__ vals,
                                                       unsigned long long* __restrict__ nonzero) {
     __shared__ BinomLds B;
     __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
                     const u64 s = pr.beg + e;
                     const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
                     const u64 at = pr.tup_off + e;
-                    keys[at] = tgt_base + rB;
+                    keys[at] = (u32)(tgt_base + rB);
                     vals[at] = pr.e2 * c.v_amp[s];
                     nz += (pr.e2 != 0.0) ? 1 : 0;
                 }
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
                         if (par) el = -el;
                         tb = str_rank(B2, B);
                     }
-                    keys[base + o] = tgt_base + tb;
+                    keys[base + o] = (u32)(tgt_base + tb);
                     vals[base + o] = el * amp;
                     nz += (el != 0.0) ? 1 : 0;
                 }
@@ -445,13 +445,17 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
     SFCI_CHECK_HIP(hipMemcpyAsync(ppre, hpp.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
 
     const u64 pair_cap = 1ull << 26;
+    // pass-local keys (target row within the pass) * N_beta + beta rank fit 32 bits
+    const u64 rows_cap = (1ull << 32) / Nb;
     const unsigned egrid = (unsigned)P->num_cu * 8;
     u64 passes = 0;
     u64 lo = 0;
     while (lo < Na) {
         if (hc[lo] > tup_cap) throw sfci_error(-5, "sort path: one alpha row exceeds the tuple buffer");
         u64 hi = lo + 1;
-        while (hi < Na && htp[hi + 1] - htp[lo] <= tup_cap && hpp[hi + 1] - hpp[lo] <= pair_cap) ++hi;
+        while (hi < Na && htp[hi + 1] - htp[lo] <= tup_cap && hpp[hi + 1] - hpp[lo] <= pair_cap &&
+               hi + 1 - lo <= rows_cap)
+            ++hi;
         const u64 tuples = htp[hi] - htp[lo], npairs = hpp[hi] - hpp[lo];
         if (tuples > 0) {
             ++passes;
@@ -459,14 +463,14 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
             const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 32);
             hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(64), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
                                ppre, pairs);
-            u64* k1 = (u64*)P->ws_tup_k.get(tuples * sizeof(u64));
+            u32* k1 = (u32*)P->ws_tup_k.get(tuples * sizeof(u32));
             double* v1 = (double*)P->ws_tup_v.get(tuples * sizeof(double));
-            u64* k2 = (u64*)P->ws_tup_k2.get(tuples * sizeof(u64));
+            u32* k2 = (u32*)P->ws_tup_k2.get(tuples * sizeof(u32));
             double* v2 = (double*)P->ws_tup_v2.get(tuples * sizeof(double));
             hipLaunchKernelGGL(k_rp_emit, dim3(egrid), dim3(RP_BLOCK), 0, P->stream, c, (const RPPair*)pairs, npairs,
                                tuples, k1, v1, nz);
             SFCI_CHECK_HIP(hipGetLastError());
-            u64* ks;
+            u32* ks;
             double* vs;
             radix_sort_pairs(P, k1, v1, k2, v2, tuples, key_bits((hi - lo) * Nb - 1), &ks, &vs);
             SortPassOut out = sink.begin(lo, hi, tuples);

@@ -95,7 +95,7 @@ struct sfci_problem {
     int num_cu = 256;
     DevBuf ws_sel, ws_cnt, ws_scan, ws_scan2, ws_scalar, ws_red;
     DevBuf ws_tup_k, ws_tup_v, ws_tup_k2, ws_tup_v2, ws_seg_v, ws_seg_f, ws_src_cnt, ws_src_off, ws_hist;
-    DevBuf ws_list_r, ws_list_a;
+    DevBuf ws_list_r, ws_list_a, ws_prod;
     DevBuf ws_sel2, ws_cand_r, ws_cand_a;  // top-M of a dense source: candidate list and its selection state
     DevBuf ws_lz[8];
     DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr, ws_rt_desc;
@@ -242,10 +242,13 @@ u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sin
 // row) pairs that land in it.
 u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
                   double eps);
-void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2, u64 n, int kbits, u64** k_out,
+// K = u64 or u32.
+template <class K>
+void radix_sort_pairs(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, int kbits, K** k_out,
                       double** v_out);
 int key_bits(u64 maxval);
-void segmented_sum_append(sfci_problem* P, const u64* keys, const double* vals, u64 n, u64 key_base, double eps,
+template <class K>
+void segmented_sum_append(sfci_problem* P, const K* keys, const double* vals, u64 n, u64 key_base, double eps,
                           u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a);
 
 // ---- Lanczos vector ops (lanczos.hip) ----

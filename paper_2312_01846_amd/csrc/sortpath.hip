@@ -22,7 +22,8 @@ constexpr u64 RS_TILE = (u64)RS_BLOCK * RS_ITEMS;
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
 
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const u64* __restrict__ keys, u64 n, int shift,
+template <class K>
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys, u64 n, int shift,
                                                       u64* __restrict__ hist, u64 nblk) {
     __shared__ unsigned h[RS_BINS];
     h[threadIdx.x] = 0;
@@ -36,9 +37,10 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const u64* __restrict__ ke
     hist[(u64)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const u64* __restrict__ keys, const double* __restrict__ vals,
+template <class K>
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ keys, const double* __restrict__ vals,
                                                          u64 n, int shift, const u64* __restrict__ offs, u64 nblk,
-                                                         u64* __restrict__ ko, double* __restrict__ vo) {
+                                                         K* __restrict__ ko, double* __restrict__ vo) {
     __shared__ u64 run[RS_BINS];
     __shared__ unsigned wc[RS_BLOCK / 64][RS_BINS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const u64* __restrict__
     for (int k = 0; k < RS_ITEMS; ++k) {
         u64 i = base + (u64)k * RS_BLOCK + threadIdx.x;
         bool valid = i < n;
-        u64 key = valid ? keys[i] : 0;
+        K key = valid ? keys[i] : (K)0;
         double val = valid ? vals[i] : 0.0;
         unsigned d = (unsigned)((key >> shift) & (RS_BINS - 1));
         u64 peers = __ballot(valid);
@@ -80,26 +82,81 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const u64* __restrict__
     }
 }
 
-// Run heads: sum each run of equal keys in order; flag nonzero sums (and,
-// with eps > 0, only those with |sum| >= eps: the screening of Sec. 3).
-__global__ void k_seg_sum(const u64* __restrict__ keys, const double* __restrict__ vals, u64 n,
-                          double* __restrict__ seg, u64* __restrict__ flag, double eps) {
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
-        bool head = (i == 0) || (keys[i] != keys[i - 1]);
-        u64 f = 0;
-        if (head) {
-            double s = 0.0;
-            u64 k = keys[i];
-            for (u64 j = i; j < n && keys[j] == k; ++j) s += vals[j];
-            seg[i] = s;
-            f = (s != 0.0 && !(fabs(s) < eps)) ? 1 : 0;
+// In-order sums of the runs of equal keys.  Each wavefront owns the runs
+// whose first element lies in its span of SEG_SPAN positions: it walks the
+// keys 64 at a time and adds every run's values one by one in index order
+// (a run that crosses the span's end is finished by its owner), so the sums
+// round exactly as a sequential loop does.  flag[i] = 1 for the first
+// element of a run whose sum is nonzero (and, with eps > 0, has |sum| >= eps:
+// the screening of Sec. 3), else 0; seg[i] holds that sum.
+constexpr u64 SEG_SPAN = 2048;
+
+__device__ __forceinline__ u64 keep_flag(double s, double eps) { return (s != 0.0 && !(fabs(s) < eps)) ? 1 : 0; }
+
+template <class K>
+__global__ __launch_bounds__(256) void k_seg_sum(const K* __restrict__ keys, const double* __restrict__ vals, u64 n,
+                                                 double* __restrict__ seg, u64* __restrict__ flag, double eps) {
+    __shared__ double sv[4][64];
+    __shared__ int stop_flag[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u64 nw = ((u64)gridDim.x * blockDim.x) >> 6;
+    for (u64 w = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * SEG_SPAN < n; w += nw) {
+        const u64 a = w * SEG_SPAN, b = min(n, a + SEG_SPAN);
+        // the lanes find the run heads of each 64-entry chunk and stage its
+        // values; lane 0 adds them in order, head to head
+        bool in_run = false;
+        u64 head = 0;
+        double acc = 0.0;
+        for (u64 base = a; base < n; base += 64) {
+            const u64 i = base + lane;
+            const bool valid = i < n;
+            const bool is_head = valid && (i == 0 || keys[i - 1] != keys[i]);
+            if (valid && i < b && !is_head) flag[i] = 0;
+            sv[wave][lane] = valid ? vals[i] : 0.0;
+            const u64 hm = __ballot(is_head);
+            wave_sync();
+            if (lane == 0) {
+                const int cnt = (int)min((u64)64, n - base);
+                int stop = 0, t = 0;
+                while (t < cnt) {
+                    const u64 rest = hm >> t;
+                    int h = rest ? t + (int)__builtin_ctzll(rest) : cnt;
+                    if (h > cnt) h = cnt;
+                    if (in_run)
+                        for (int q = t; q < h; ++q) acc += sv[wave][q];
+                    if (h >= cnt) break;
+                    if (in_run) {
+                        seg[head] = acc;
+                        flag[head] = keep_flag(acc, eps);
+                    }
+                    if (base + h >= b) {
+                        in_run = false;
+                        stop = 1;
+                        break;
+                    }
+                    in_run = true;
+                    head = base + h;
+                    acc = 0.0;
+                    acc += sv[wave][h];
+                    t = h + 1;
+                }
+                stop_flag[wave] = stop;
+            }
+            wave_sync();
+            const int stop = stop_flag[wave];
+            wave_sync();
+            if (stop) break;
         }
-        flag[i] = f;
+        if (lane == 0 && in_run) {
+            seg[head] = acc;
+            flag[head] = keep_flag(acc, eps);
+        }
     }
 }
 
 // Scatter flagged heads to out[base + exclusive-prefix(flag)].
-__global__ void k_seg_write(const u64* __restrict__ keys, const double* __restrict__ seg, const u64* __restrict__ flag,
+template <class K>
+__global__ void k_seg_write(const K* __restrict__ keys, const double* __restrict__ seg, const u64* __restrict__ flag,
                             const u64* __restrict__ pos, u64 n, u64 key_base, const u64* __restrict__ out_base,
                             u64 out_cap, u64* __restrict__ out_r, double* __restrict__ out_a) {
     const u64 ob = *out_base;
@@ -107,7 +164,7 @@ __global__ void k_seg_write(const u64* __restrict__ keys, const double* __restri
         if (flag[i]) {
             u64 at = ob + pos[i];
             if (at < out_cap) {
-                out_r[at] = keys[i] + key_base;
+                out_r[at] = (u64)keys[i] + key_base;
                 out_a[at] = seg[i];
             }
         }
@@ -139,16 +196,17 @@ int bits_for(u64 maxval) {
 
 // Stable LSD radix sort of (keys, vals) on the low kbits of the key; the
 // result ends in (*k_out, *v_out), which is one of the two buffer pairs.
-void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2, u64 n, int kbits, u64** k_out,
+template <class K>
+void radix_sort_pairs(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, int kbits, K** k_out,
                       double** v_out) {
     if (n > 0) {
         const u64 nblk = (n + RS_TILE - 1) / RS_TILE;
         u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
         for (int shift = 0; shift < kbits; shift += RS_BITS) {
-            hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
+            hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
                                nblk);
             exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
-            hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
+            hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
                                hist, nblk, k2, v2);
             std::swap(k1, k2);
             std::swap(v1, v2);
@@ -158,26 +216,35 @@ void radix_sort_pairs(sfci_problem* P, u64* k1, double* v1, u64* k2, double* v2,
     *k_out = k1;
     *v_out = v1;
 }
+template void radix_sort_pairs<u64>(sfci_problem*, u64*, double*, u64*, double*, u64, int, u64**, double**);
+template void radix_sort_pairs<u32>(sfci_problem*, u32*, double*, u32*, double*, u64, int, u32**, double**);
 
 int key_bits(u64 maxval) { return bits_for(maxval); }
 
 // Sum runs of equal keys of a key-sorted list in order and append the nonzero
 // sums (key + key_base, sum) at out[*out_base + ...]; *out_base += their
 // number.  eps > 0 drops sums with |sum| < eps.
-void segmented_sum_append(sfci_problem* P, const u64* keys, const double* vals, u64 n, u64 key_base, double eps,
+template <class K>
+void segmented_sum_append(sfci_problem* P, const K* keys, const double* vals, u64 n, u64 key_base, double eps,
                           u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a) {
     if (n == 0) return;
     u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));
     double* seg = (double*)P->ws_seg_v.get(n * sizeof(double));
     u64* flag = (u64*)P->ws_seg_f.get(n * sizeof(u64));
-    hipLaunchKernelGGL(k_seg_sum, dim3(g1(n)), dim3(256), 0, P->stream, keys, vals, n, seg, flag, eps);
+    const u64 spans = (n + SEG_SPAN - 1) / SEG_SPAN;
+    const unsigned sgrid = (unsigned)std::min<u64>((spans + 3) / 4, (u64)P->num_cu * 32);
+    hipLaunchKernelGGL(k_seg_sum<K>, dim3(sgrid), dim3(256), 0, P->stream, keys, vals, n, seg, flag, eps);
     u64* pos = (u64*)P->ws_scan2.get(n * sizeof(u64));
     exclusive_scan_u64(P, flag, pos, n, &scal[2]);
-    hipLaunchKernelGGL(k_seg_write, dim3(g1(n)), dim3(256), 0, P->stream, keys, seg, flag, pos, n, key_base,
+    hipLaunchKernelGGL(k_seg_write<K>, dim3(g1(n)), dim3(256), 0, P->stream, keys, seg, flag, pos, n, key_base,
                        out_base_dev, out_cap, out_r, out_a);
     hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, out_base_dev, &scal[2]);
     SFCI_CHECK_HIP(hipGetLastError());
 }
+template void segmented_sum_append<u64>(sfci_problem*, const u64*, const double*, u64, u64, double, u64*, u64, u64*,
+                                        double*);
+template void segmented_sum_append<u32>(sfci_problem*, const u32*, const double*, u64, u64, double, u64*, u64, u64*,
+                                        double*);
 
 u64 sort_tuple_cap(sfci_problem* P) {
     // Tuple buffer: a quarter of free memory (7 words per tuple over the

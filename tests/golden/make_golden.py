@@ -68,6 +68,9 @@ def case_defs():
         "c2p_M2e3_20": (mol(26, 5, 5, 52, 2, True), 2_000, 10, 20),
         "c4p_inst31_M3e3_30": (c4(31, True), 3_000, 10, 30),
         "c4p_inst15_M1e4_30": (c4(15, True), 10_938, 10, 30),
+        # 12 electrons in 28 orbitals (1.42e11 determinants): the list iteration's shape
+        "c3_M1e3_10": (mol(28, 6, 6, 56, 3), 1_000, 5, 10),
+        "c3p_M1e3_10": (mol(28, 6, 6, 56, 3, True), 1_000, 5, 10),
     }
 
 

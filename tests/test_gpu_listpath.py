@@ -76,6 +76,10 @@ def _case(S, name):
         h, g = synth.molecule_like(26, 52, 2)
         P = S.Problem(26, 5, 5, h, g)
         return P, (_perturbed(P) if name.startswith("c2p") else AUFBAU), 1 << 23
+    if name.startswith("c3"):
+        h, g = synth.molecule_like(28, 56, 3)
+        P = S.Problem(28, 6, 6, h, g)
+        return P, (_perturbed(P) if name.startswith("c3p") else AUFBAU), 1 << 23
     j = int(name.split("_")[1].replace("inst", ""))
     _, h, g = synth.bond_stretch_batch(20, 32, 40)[j]
     P = S.Problem(20, 4, 4, h, g)
@@ -83,8 +87,10 @@ def _case(S, name):
 
 
 @pytest.mark.parametrize("name", ["c0_M300_30", "c0p_M300_30", "c1_U4_M2e3_20", "c2_M2e3_20", "c2p_M2e3_20",
-                                  "c4_inst31_M3e3_30"])
+                                  "c4_inst31_M3e3_30", "c3_M1e3_10", "c3p_M1e3_10"])
 def test_list_iteration_matches_goldens(torch, S, monkeypatch, name):
+    # c3*: 12 electrons in 28 orbitals, 1.42e11 determinants -- the N_det
+    # array (1.14 TB) cannot exist, so this is the only way the space runs
     gd = _gold(name)
     P, start, tup_cap = _case(S, name)
     monkeypatch.setenv("SFCI_SORT_TUPLE_CAP", str(tup_cap))
