@@ -204,6 +204,61 @@ __global__ __launch_bounds__(LB) void k_scaled_concat(const u64* __restrict__ Wr
     }
 }
 
+// Order-preserving compaction of a dense slice: block b counts the nonzero
+// entries of its DC_CHUNK slots, then writes them (rank = rank_base + slot)
+// at out[*out_base + off[b] + ...] in slot order and zeroes the slots read.
+constexpr int DC_ITEMS = 16;
+constexpr u64 DC_CHUNK = (u64)LB * DC_ITEMS;
+
+__global__ __launch_bounds__(LB) void k_dense_count(const double* __restrict__ D, u64 n, u64* __restrict__ cnt) {
+    __shared__ unsigned wsum[LB / 64];
+    const u64 base = (u64)blockIdx.x * DC_CHUNK;
+    unsigned c = 0;
+    for (int k = 0; k < DC_ITEMS; ++k) {
+        const u64 i = base + (u64)k * LB + threadIdx.x;
+        c += (i < n && D[i] != 0.0) ? 1u : 0u;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int w = 0; w < LB / 64; ++w) t += wsum[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(LB) void k_dense_write(double* __restrict__ D, u64 n, const u64* __restrict__ off,
+                                                    u64 rank_base, const u64* __restrict__ out_base,
+                                                    u64* __restrict__ out_r, double* __restrict__ out_a) {
+    __shared__ unsigned wtot[LB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u64 base = (u64)blockIdx.x * DC_CHUNK;
+    u64 run = *out_base + off[blockIdx.x];
+    for (int k = 0; k < DC_ITEMS; ++k) {
+        const u64 i = base + (u64)k * LB + threadIdx.x;
+        double v = 0.0;
+        if (i < n) v = D[i];
+        const bool p = v != 0.0;
+        if (p) D[i] = 0.0;
+        const u64 m = __ballot(p);
+        if (lane == 0) wtot[wave] = (unsigned)__popcll(m);
+        __syncthreads();
+        unsigned wbase = 0, all = 0;
+        for (int w = 0; w < LB / 64; ++w) {
+            if (w < wave) wbase += wtot[w];
+            all += wtot[w];
+        }
+        if (p) {
+            const u64 at = run + wbase + (u64)__popcll(m & ((1ull << lane) - 1ull));
+            out_r[at] = rank_base + i;
+            out_a[at] = v;
+        }
+        run += all;
+        __syncthreads();
+    }
+}
+
 unsigned grid_for(u64 n, unsigned max_blocks = 4096) {
     u64 g = (n + LB - 1) / LB;
     if (g < 1) g = 1;
@@ -383,6 +438,49 @@ u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank,
     return need;
 }
 
+// Dense passes: sigma through the target-owned tile kernel, a range of
+// target alpha rows at a time, into a zeroed slice of rows x N_beta doubles;
+// each slice is compacted (rank order, zeroing it) into the sink.
+u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, double eps) {
+    ListWs& ws = P->list_ws;
+    size_t freeb = 0, totb = 0;
+    SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+    const u64 slice_bytes = std::min<u64>((u64)(freeb + ws.dpass.bytes) / 4, 32ull << 30);
+    u64 rows = std::max<u64>(1, std::min<u64>(P->Na, slice_bytes / (8 * P->Nb)));
+    if (const char* env = getenv("SFCI_LIST_PASS_ROWS")) {
+        long long e = atoll(env);
+        if (e > 0) rows = std::min<u64>(rows, (u64)e);
+    }
+    const u64 slots = rows * P->Nb;
+    if (ws.dpass.bytes < slots * sizeof(double)) {
+        ws.dpass.get(slots * sizeof(double));
+        launch_fill_f64((double*)ws.dpass.p, ws.dpass.bytes / sizeof(double), 0.0, P->stream);
+    }
+    double* Dp = (double*)ws.dpass.p;
+    u64* sc = (u64*)ws.scal2.get(8 * sizeof(u64));  // [0] pass count
+    const RowTileDesc all = rowtile_prepare(P, v, Dp, (unsigned long long*)emitted_dev, eps);
+    u64 passes = 0;
+    for (u64 lo = 0; lo < P->Na; lo += rows) {
+        const u64 hi = std::min<u64>(P->Na, lo + rows);
+        const u64 n = (hi - lo) * P->Nb;
+        launch_sigma_rowtile_rows(P, all, lo, hi, Dp);
+        const u64 nblk = (n + DC_CHUNK - 1) / DC_CHUNK;
+        u64* cnt = (u64*)ws.dcnt.get(nblk * sizeof(u64));
+        hipLaunchKernelGGL(k_dense_count, dim3((unsigned)nblk), dim3(LB), 0, P->stream, (const double*)Dp, n, cnt);
+        exclusive_scan_u64(P, cnt, cnt, nblk, &sc[0]);
+        const u64 total = read_dev(P, &sc[0]);
+        ++passes;
+        SortPassOut out = sink.begin(lo, hi, std::max<u64>(1, total));
+        if (total > out.cap) throw sfci_error(-5, "dense pass: output buffer too small");
+        hipLaunchKernelGGL(k_dense_write, dim3((unsigned)nblk), dim3(LB), 0, P->stream, Dp, n, (const u64*)cnt,
+                           lo * P->Nb, (const u64*)out.base_dev, out.r, out.a);
+        launch_add_u64(P, out.base_dev, &sc[0]);
+        SFCI_CHECK_HIP(hipGetLastError());
+        sink.end(lo, hi);
+    }
+    return passes;
+}
+
 void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& Bs, sfci_svec* psi_out,
                   u64* psi_n_out, u64* sigma_calls, EventTimer& tsig) {
     const int nL = o->n_L;
@@ -404,6 +502,8 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
     auto Wrj = [&](int j) { return Wr + (size_t)j * cap; };
     auto Waj = [&](int j) { return Wa + (size_t)j * cap; };
     const u64 tup_cap = sort_tuple_cap(P);
+    // without the ordered-sum requirement, sigma goes through the tile kernel in row passes
+    const bool dense_passes = !det && rowtile_available(P);
 
     // Top-M of a candidate list into w_dst (rank order, normalised).
     auto select_into = [&](const CandSrc& src, int dst, bool sorted_src) {
@@ -437,7 +537,10 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
             sink.bounds = ls + 8;
             sink.pcount = ls + 2;
             tsig.begin(P->stream);
-            sigma_sorted_passes(P, sl, sink, sc + 32, tup_cap, o->screen_eps);
+            if (dense_passes)
+                sigma_dense_passes(P, sl, sink, sc + 32, o->screen_eps);
+            else
+                sigma_sorted_passes(P, sl, sink, sc + 32, tup_cap, o->screen_eps);
             tsig.end(P->stream);
             ++*sigma_calls;
             for (int l = 0; l <= j; ++l) {

@@ -53,6 +53,8 @@ struct RTParams {
     const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
     const double* K4;            // [(i<j), (a<b)] pair-indexed (ia|jb) - (ib|ja), pair (x<y) -> y(y-1)/2 + x
     double eps;                  // sigma: screening threshold (Sec. 3), 0 = off
+    u64 item_base;               // items of this description start at this global item
+    u64 row_base;                // D holds target rows from this alpha rank on
 };
 
 // One contributing source row of the current (target row, tile).
@@ -239,7 +241,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         const int sA = na * nva, sBn = p.sB;
         const u64 n_nbr = 1 + (u64)sA + (u64)PA * QA;
         const bool whole_rows = (p.ntiles == 1);
-        const u64 item = s_item;
+        const u64 item = s_item + p.item_base;
         const u64 rAt = item / (u64)p.ntiles;
         const int tile = (int)(item - rAt * (u64)p.ntiles);
         const u64 tlo = p.tile_lo[tile], thi = p.tile_lo[tile + 1];
@@ -252,7 +254,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             else virA[q - __popc(At & below)] = (uint8_t)q;
         }
         if (GRAD) {
-            const double* src = p.D + rAt * Nb + tlo;
+            const double* src = p.D + (rAt - p.row_base) * Nb + tlo;
             for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = src[x];
         } else {
             for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
@@ -772,7 +774,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         }
         __syncthreads();
         if (!GRAD && s_touched) {
-            double* dst = p.D + rAt * Nb + tlo;
+            double* dst = p.D + (rAt - p.row_base) * Nb + tlo;
             const double eps = p.eps;
             if (eps > 0.0)
                 for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = (fabs(acc[x]) < eps) ? 0.0 : acc[x];
@@ -1117,6 +1119,8 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.TS = S->d_TS;
     rp.K4 = S->d_K4;
     rp.eps = eps;
+    rp.item_base = 0;
+    rp.row_base = 0;
     const int na = P->na, nva = P->n - P->na;
     out.n_items = P->Na * (u64)S->ntiles;
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
@@ -1179,6 +1183,26 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
     void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
     rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
                 (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items);
+}
+
+void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, double* Dp) {
+    RowTileDesc d = all;
+    RTParams& rp = *(RTParams*)d.raw;
+    rp.item_base = lo * (u64)rp.ntiles;
+    rp.row_base = lo;
+    rp.D = Dp;
+    d.n_items = (hi - lo) * (u64)rp.ntiles;
+    char* buf = (char*)P->ws_rt_desc.get(sizeof(RTParams) + 64);
+    u64 prefix[2] = {0, d.n_items};
+    SFCI_CHECK_HIP(hipMemcpyAsync(buf, d.raw, sizeof(RTParams), hipMemcpyHostToDevice, P->stream));
+    SFCI_CHECK_HIP(hipMemcpyAsync(buf + sizeof(RTParams), prefix, sizeof(prefix), hipMemcpyHostToDevice, P->stream));
+    const RowTileGeom geom = rowtile_geom(&d, 1);
+    const unsigned grid = rowtile_grid(P->num_cu, geom.lds, d.n_items);
+    void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
+    rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
+                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items);
+    // the host buffers above are copied before this returns
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
 }
 
 // ---- integral gradients through the tiles ----

@@ -75,9 +75,11 @@ struct RowPassWs {
 
 // Buffers of the list-based iteration and sigma (listlz.hip).
 struct ListWs {
-    DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a;
+    DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a, dpass, dcnt, scal2;
     void release() {
-        for (DevBuf* b : {&scal, &pr, &pa, &mark, &Rr, &Ra, &R2r, &R2a, &yg, &taken, &psi_r, &psi_a}) b->release();
+        for (DevBuf* b : {&scal, &pr, &pa, &mark, &Rr, &Ra, &R2r, &R2a, &yg, &taken, &psi_r, &psi_a, &dpass, &dcnt,
+                          &scal2})
+            b->release();
     }
 };
 
@@ -155,6 +157,10 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
                             double eps = 0.0);
 size_t rowtile_desc_bytes();
+// Target alpha rows [lo, hi) of a prepared description only, written into
+// Dp[rank - lo * N_beta] (touched tiles are overwritten, the rest is left
+// as it is: Dp must be zero there).  Synchronises the stream.
+void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, double* Dp);
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 // fill_counter = false: the caller has already zeroed *d_counter on the stream.
