@@ -11,9 +11,11 @@ sigma launch plus the per-instance vector operations); the timed region is
 alone: one FP64 atomic per term, no graphs, then the backward) is timed after
 it for the speedup and the energy comparison.
 
-Other workloads: c2 (10 electrons in 26 orbitals, one instance, M = 1e6) and
-c4 (one 20-orbital instance).  Inputs are resident in HBM before timing
-starts.  Prints one JSON line.
+Other workloads: c2 (10 electrons in 26 orbitals, one instance, M = 1e6), c3
+(12 electrons in 28 orbitals, 1.42e11 determinants, run with --M 1e7: the
+list iteration, since the 1.14 TB N_det array cannot exist) and c4 (one
+20-orbital instance).  Inputs are resident in HBM before timing starts.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -36,6 +38,9 @@ METRIC = "\u03c3 terms/s and HBM-roofline fraction; batched fwd+bwd speedup vs p
 WORKLOADS = {
     "c2": dict(n=26, na=5, nb=5, rank=52, seed=2,
                desc="10e in 26 orbitals (5a,5b), N_det=4.33e9, molecule-like integrals seed 2"),
+    "c3": dict(n=28, na=6, nb=6, rank=56, seed=3,
+               desc="12e in 28 orbitals (6a,6b), N_det=1.42e11 (no N_det array: list iteration, sigma in "
+                    "slices of target rows), molecule-like integrals seed 3"),
     "c4": dict(n=20, na=4, nb=4, rank=40, seed=None,
                desc="8e in 20 orbitals (4a,4b), N_det=2.35e7, bond-stretch instance lambda=0"),
 }
@@ -56,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
+    ap.add_argument("--det", action="store_true",
+                    help="single-problem workloads: deterministic mode (sort dedup, ordered sums)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run three 1 GiB device-to-device copies (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -158,13 +165,15 @@ def main():
     print(f"# building a start vector: {args.warmup} warm-up iterations at M={M}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     warm = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=M, n_L=args.n_L, n_iter=args.warmup,
-                     psi_capacity=min(P.n_det, args.n_L * (M + sfci.TIE_SLACK)), dedup=args.dedup)
+                     psi_capacity=min(P.n_det, args.n_L * (M + sfci.TIE_SLACK)), dedup=args.dedup,
+                     deterministic=args.det)
     v_r, v_a = P.topm(warm["psi_rank"], warm["psi_amp"], M, normalise=True)
     torch.cuda.synchronize()
     print(f"# warm-up done in {time.perf_counter() - t0:.1f} s; start vector nnz={v_r.numel()}", file=sys.stderr,
           flush=True)
     t1 = time.perf_counter()
-    out = P.lanczos(v_r, v_a, M=M, n_L=args.n_L, n_iter=args.steps, want_psi=False, dedup=args.dedup)
+    out = P.lanczos(v_r, v_a, M=M, n_L=args.n_L, n_iter=args.steps, want_psi=False, dedup=args.dedup,
+                    deterministic=args.det)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t1
     st = out["stats"]
@@ -197,7 +206,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {wl['desc']}, M={M}, N_L={args.n_L}, dedup={args.dedup}",
+            "workload": f"{args.workload}: {wl['desc']}, M={M}, N_L={args.n_L}, "
+                        + ("deterministic (sort dedup)" if args.det else f"dedup={args.dedup}"),
             "M": M,
             "n_L": args.n_L,
             "terms_per_step": terms / args.steps,
@@ -206,7 +216,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_sigma_rowtile" if args.dedup == "dense" else "k_sigma_dense",
+            "kernel": ("k_rs_scatter" if args.det else
+                       "k_sigma_rowtile" if args.dedup == "dense" else "k_sigma_dense"),
             "achieved": achieved / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
