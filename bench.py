@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="c4batch: keep the tile kernel's default work sizes")
     ap.add_argument("--det", action="store_true",
                     help="single-problem workloads: deterministic mode (sort dedup, ordered sums)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -246,7 +248,10 @@ def bench_batch(args, torch, sfci, synth):
     B = sfci.Batch(probs)
     if args.warmup:
         print(f"# warm-up: {args.warmup} batched iterations + gradients", file=sys.stderr, flush=True)
-        B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.warmup)
+        # the warm-up also tunes the tile kernel's work sizes (kept by the batch)
+        wout = B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.warmup, autotune=not args.no_autotune)
+        tune = wout["stats"]["tune"]
+        print(f"# tuned work sizes: {tune}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.steps)
@@ -317,6 +322,7 @@ def bench_batch(args, torch, sfci, synth):
             "terms_emitted": terms,
             "psi_nnz_total": st["psi_nnz_total"],
             "graph_replayed_blocks": st["graph_replayed_blocks"],
+            "tile_work_sizes": st["tune"],
             "final_energies": [float(x) for x in E[:, -1]],
             "plain_path": plain,
             "batched_speedup_vs_plain": plain["speedup"] if plain else None,

@@ -141,6 +141,9 @@ typedef struct {
                               and the truncation (the paper uses 5e-5); 0 = off */
     int32_t no_dense;      /* 1: keep every vector as a rank list and never allocate the N_det array
                               (sort path, alpha-range passes); implied when 8 N_det bytes do not fit */
+    int32_t autotune;      /* batched fast mode: 1 = choose the tile kernel's work sizes (beta singles and
+                              beta-beta doubles per work unit, workgroups per CU) by timing candidates on the
+                              last eager sigma step, once per batch; later calls reuse the choice */
 } sfci_lanczos_opts;
 
 typedef struct {
@@ -189,6 +192,12 @@ typedef struct {
     uint64_t psi_nnz_total;     /* entries of the final Psi over all instances */
     int32_t graph_replayed_blocks;
     int32_t batched_sigma;      /* 1: one launch per step served every instance */
+    int32_t tune_trials;        /* candidate launches timed by this call (0: none, or the batch's earlier choice) */
+    uint32_t tune_b1_chunk;     /* work sizes the sigma launches used (0 = built-in default) */
+    uint32_t tune_bb_chunk;
+    uint32_t tune_per_cu;
+    double tune_default_ms;     /* trial time of the default sizes and of the chosen ones (when tuned) */
+    double tune_best_ms;
 } sfci_batch_stats;
 
 /* probs: n_inst problem handles (kept, not owned). */

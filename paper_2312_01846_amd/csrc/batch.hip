@@ -27,6 +27,9 @@ struct sfci_batch {
     std::vector<hipStream_t> aux;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
+    // work sizes of the sigma tile launches (chosen by autotuning, kept across calls)
+    RowTileTune tune;
+    bool tuned = false;
 };
 
 namespace {
@@ -52,6 +55,9 @@ struct Inst {
     double* la;
     DVec W(int j) const { return DVec{Wr + (size_t)j * cap, Wa + (size_t)j * cap, sc + j, cap}; }
 };
+
+// Largest workgroups-per-CU multiple a tuning candidate may ask for.
+constexpr unsigned kTuneMaxPerCu = 4;
 
 #define SFCI_GUARD_BEGIN try {
 #define SFCI_GUARD_END                                               \
@@ -187,6 +193,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         launch_normalise(P, w.a, w.nnz, q.cap, det);
     }
     const bool batched_sigma = !det && o->dedup != SFCI_DEDUP_DENSE_ATOMIC && all_tiles;
+    const bool autotune = o->autotune != 0 && batched_sigma;
+    int tune_trials = 0;
+    double tune_default_ms = 0.0, tune_best_ms = 0.0;
 
     // One sigma application for every instance, in two parts: the per-instance
     // preparation (row pointers, tile offsets, input-size bookkeeping) and the
@@ -244,7 +253,10 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         d_desc = (char*)B->descs[j].get((size_t)n * db);
         d_pre = (u64*)B->prefix.get((size_t)(n + 1) * sizeof(u64));
         d_cnt = (unsigned*)B->counter.get(64);
-        d_scr = B->scratch.get(rowtile_scratch_bytes(rowtile_grid(B->P[0]->num_cu, geom.lds, total_items), nbr_cap));
+        // room for the largest grid a tuning candidate may use
+        const unsigned gmax = std::max(rowtile_grid(B->P[0]->num_cu, geom.lds, total_items),
+                                       rowtile_grid(B->P[0]->num_cu, geom.lds, total_items, kTuneMaxPerCu));
+        d_scr = B->scratch.get(rowtile_scratch_bytes(gmax, nbr_cap));
         if (upload) {
             std::vector<unsigned char> host((size_t)n * db);
             for (int k = 0; k < n; ++k) std::memcpy(host.data() + (size_t)k * db, descs[k].raw, db);
@@ -258,7 +270,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         if (batched_sigma) {
             // descriptions of step j (uploaded in the eager block; the
             // remaining launch parameters are the same for every step)
-            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, geom, total_items, false);
+            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, geom, total_items, false,
+                        B->tune);
             return;
         }
         for (int k = 0; k < n; ++k) {
@@ -273,6 +286,54 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
                 dense_sigma(q.P, sl, o->dedup, (unsigned long long*)(q.sc + 32), o->screen_eps);
             }
         }
+    };
+    // Autotuning: the sigma of step j (inputs prepared, counter zeroed) is
+    // launched once per candidate work-size set, each bracketed by events;
+    // every launch overwrites the same touched tiles, so the real launch that
+    // follows leaves the state it would have without the trials.  The term
+    // counters are saved and restored around them.  Coordinate descent:
+    // beta singles per unit, then beta-beta doubles per unit, then the grid.
+    auto tune_on_step = [&](int j) {
+        (void)j;
+        for (int k = 0; k < n; ++k)
+            SFCI_CHECK_HIP(hipMemcpyAsync(I[k].sc + 40, I[k].sc + 32, sizeof(u64), hipMemcpyDeviceToDevice, st));
+        const unsigned auto_per_cu =
+            std::max(1u, rowtile_grid(1, geom.lds, ~0ull));  // workgroups per CU the default grid uses
+        auto trial = [&](const RowTileTune& t) {
+            hipEvent_t a, z;
+            SFCI_CHECK_HIP(hipEventCreate(&a));
+            SFCI_CHECK_HIP(hipEventCreate(&z));
+            SFCI_CHECK_HIP(hipEventRecord(a, st));
+            rowtile_run(st, B->P[0]->num_cu, B->descs[j].p, d_pre, n, d_cnt, d_scr, nbr_cap, geom, total_items, true,
+                        t);
+            SFCI_CHECK_HIP(hipEventRecord(z, st));
+            SFCI_CHECK_HIP(hipEventSynchronize(z));
+            float ms = 0.f;
+            SFCI_CHECK_HIP(hipEventElapsedTime(&ms, a, z));
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(z);
+            ++tune_trials;
+            return (double)ms;
+        };
+        RowTileTune best{16, 4, auto_per_cu};
+        double best_ms = trial(best);
+        tune_default_ms = best_ms;
+        auto consider = [&](RowTileTune t) {
+            const double ms = trial(t);
+            if (ms < best_ms) best_ms = ms, best = t;
+        };
+        const RowTileTune b0 = best;
+        for (unsigned c : {8u, 32u}) consider(RowTileTune{c, b0.bb_chunk, b0.per_cu});
+        const RowTileTune b1 = best;
+        for (unsigned c : {2u, 8u}) consider(RowTileTune{b1.b1_chunk, c, b1.per_cu});
+        const RowTileTune b2 = best;
+        if (2 * auto_per_cu <= kTuneMaxPerCu) consider(RowTileTune{b2.b1_chunk, b2.bb_chunk, 2 * auto_per_cu});
+        tune_best_ms = best_ms;
+        B->tune = best;
+        B->tuned = true;
+        for (int k = 0; k < n; ++k)
+            SFCI_CHECK_HIP(hipMemcpyAsync(I[k].sc + 32, I[k].sc + 40, sizeof(u64), hipMemcpyDeviceToDevice, st));
+        launch_fill_u64((u64*)d_cnt, 1, 0, st);  // the real launch starts from item 0
     };
     auto iteration_rest = [&](int j) {
         fan([&](int k) {
@@ -376,6 +437,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         for (int j = 0; j < nL; ++j, ++sig) {
             if (replay) SFCI_CHECK_HIP(hipGraphLaunch(gprep[j], st));
             else sigma_prepare(j, true);
+            if (autotune && !B->tuned && b == 0 && j == nL - 1) tune_on_step(j);
             SFCI_CHECK_HIP(hipEventRecord(ev[3 + 2 * sig], st));
             sigma_launch(j);
             SFCI_CHECK_HIP(hipEventRecord(ev[4 + 2 * sig], st));
@@ -465,6 +527,12 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         stats->psi_nnz_total = psi_total;
         stats->graph_replayed_blocks = use_graph ? std::max(0, nblk - 1) : 0;
         stats->batched_sigma = batched_sigma ? 1 : 0;
+        stats->tune_trials = tune_trials;
+        stats->tune_b1_chunk = batched_sigma ? B->tune.b1_chunk : 0u;
+        stats->tune_bb_chunk = batched_sigma ? B->tune.bb_chunk : 0u;
+        stats->tune_per_cu = batched_sigma ? B->tune.per_cu : 0u;
+        stats->tune_default_ms = tune_default_ms;
+        stats->tune_best_ms = tune_best_ms;
     }
     for (int k = 0; k < n; ++k)
         if (hstat[k]) return (sfci_status)sfci_set_error(SFCI_E_DEVICE, "generalized eigenproblem failed");

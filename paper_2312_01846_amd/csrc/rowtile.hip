@@ -83,6 +83,8 @@ __device__ __forceinline__ int t1_b(u32 t) { return (int)((t >> 26) & 31u); }
 __device__ __forceinline__ int t1_par(u32 t) { return (int)(t >> 31); }
 
 // Entries of the identity row per beta-beta-double and per beta-single work unit.
+// Default work per unit of the identity row's beta-beta doubles and beta
+// singles (entries per unit); a launch may choose others (autotuning).
 constexpr unsigned RT_BB_CHUNK = 4;
 constexpr unsigned RT_B1_CHUNK = 16;
 // Input entries whose table reads are issued together in the beta-single loop.
@@ -161,7 +163,8 @@ enum { RT_SIGMA = 0, RT_GRAD_A = 1, RT_GRAD_B = 2 };
 template <int MODE>
 __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
                                              int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
-                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off) {
+                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off,
+                                             unsigned b1_chunk, unsigned bb_chunk) {
     constexpr bool GRAD = MODE != RT_SIGMA;
     extern __shared__ double acc[];
     double* const itab = acc + itab_off;  // sigma: per-item element tables
@@ -491,11 +494,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
 
         // Phase 3: beta singles of the identity and alpha-single source rows
         // (the alpha-beta doubles), one list row per work unit; then the
-        // identity row's beta-beta doubles, RT_BB_CHUNK entries per unit, so
+        // identity row's beta-beta doubles, bb_chunk entries per unit, so
         // that every wavefront shares the largest single-row job.
         const u32 idb = s_idb, ide = s_ide;
-        const unsigned n_b1 = (!GRAD && ide > idb) ? (ide - idb + RT_B1_CHUNK - 1) / RT_B1_CHUNK : 0u;
-        const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + RT_BB_CHUNK - 1) / RT_BB_CHUNK : 0u;
+        const unsigned n_b1 = (!GRAD && ide > idb) ? (ide - idb + b1_chunk - 1) / b1_chunk : 0u;
+        const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + bb_chunk - 1) / bb_chunk : 0u;
         const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : nlist + n_b1 + n_bb;
         const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
         const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
@@ -506,8 +509,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             if (li >= n_units) break;
             if (!GRAD && li >= nlist + n_b1) {
                 // beta-beta doubles of identity-row entries [k0, k1)
-                const u32 k0 = idb + (li - nlist - n_b1) * RT_BB_CHUNK;
-                const u32 k1 = min(ide, k0 + RT_BB_CHUNK);
+                const u32 k0 = idb + (li - nlist - n_b1) * bb_chunk;
+                const u32 k1 = min(ide, k0 + bb_chunk);
                 const auto K4g = gl(p.K4);
                 const int np2 = n * (n - 1) / 2;
                 for (u32 k = k0; k < k1; ++k) {
@@ -554,12 +557,12 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             }
             NbrRec r;
             if (!GRAD && li >= nlist) {
-                // beta singles of identity-row entries, RT_B1_CHUNK per unit
-                const u32 k0 = idb + (li - nlist) * RT_B1_CHUNK;
+                // beta singles of identity-row entries, b1_chunk per unit
+                const u32 k0 = idb + (li - nlist) * b1_chunk;
                 r.As = At;
                 r.rAs = (u32)rAt;
                 r.rowb = k0;
-                r.rowe = min(ide, k0 + RT_B1_CHUNK);
+                r.rowe = min(ide, k0 + b1_chunk);
                 r.e0 = r.e1 = 0;
                 r.cst = 0.0;
                 r.type = 0;
@@ -792,8 +795,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                                                             const u64* __restrict__ item_prefix, int n_inst,
                                                             unsigned* __restrict__ counter, void* nbr_scratch,
                                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
-                                                            unsigned itab_off) {
-    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, itab_off);
+                                                            unsigned itab_off, unsigned b1_chunk, unsigned bb_chunk) {
+    rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, itab_off,
+                           b1_chunk, bb_chunk);
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
@@ -801,7 +805,8 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a(const RTParams* __r
                                                              const u64* __restrict__ item_prefix, int n_inst,
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
-    rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, 0u);
+    rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, 0u,
+                            RT_B1_CHUNK, RT_BB_CHUNK);
 }
 
 // Integral gradients, second pass (beta-side terms on the spin-exchanged problem).
@@ -809,7 +814,8 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
                                                              const u64* __restrict__ item_prefix, int n_inst,
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off) {
-    rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u, 0u);
+    rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u, 0u, RT_B1_CHUNK,
+                            RT_BB_CHUNK);
 }
 
 // ---- per-problem tables ----
@@ -1156,16 +1162,18 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
 
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
                  unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
-                 bool fill_counter) {
+                 bool fill_counter, const RowTileTune& tune) {
     if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
-    const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items);
+    const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items, tune.per_cu);
     hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream, (const RTParams*)d_descs,
-                       d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off);
+                       d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off,
+                       tune.b1_chunk ? tune.b1_chunk : RT_B1_CHUNK, tune.bb_chunk ? tune.bb_chunk : RT_BB_CHUNK);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
-unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items) {
-    const int per_cu = std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
+unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned per_cu_override) {
+    const int per_cu = per_cu_override ? (int)per_cu_override
+                                       : std::max(1, (int)((160 * 1024) / (lds_bytes + 40 * 1024)));
     return (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
 }
 

@@ -154,6 +154,12 @@ struct RowTileGeom {
     unsigned itab_off;  // per-item element tables
 };
 RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
+// Launch-time work sizes of the sigma tile kernel (0 = the built-in default):
+// identity-row beta singles and beta-beta doubles per work unit (entries),
+// and workgroups per compute unit in the grid.
+struct RowTileTune {
+    unsigned b1_chunk = 0, bb_chunk = 0, per_cu = 0;
+};
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
                             double eps = 0.0);
 size_t rowtile_desc_bytes();
@@ -161,12 +167,12 @@ size_t rowtile_desc_bytes();
 // Dp[rank - lo * N_beta] (touched tiles are overwritten, the rest is left
 // as it is: Dp must be zero there).  Synchronises the stream.
 void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, double* Dp);
-unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items);
+unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned per_cu_override = 0);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 // fill_counter = false: the caller has already zeroed *d_counter on the stream.
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
                  unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
-                 bool fill_counter = true);
+                 bool fill_counter = true, const RowTileTune& tune = RowTileTune{});
 
 // Integral gradients through the target-owned tiles: for each job,
 // L = s^T H(h, g) v with s and v sparse (ascending unique ranks).  Raw

@@ -50,7 +50,8 @@ class SigmaStats(C.Structure):
 
 class LanczosOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
-                ("dedup", C.c_int32), ("screen_eps", C.c_double), ("no_dense", C.c_int32)]
+                ("dedup", C.c_int32), ("screen_eps", C.c_double), ("no_dense", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class LanczosStats(C.Structure):
@@ -62,7 +63,9 @@ class BatchStats(C.Structure):
     _fields_ = [("fwd_ms", C.c_double), ("bwd_ms", C.c_double), ("sigma_ms", C.c_double),
                 ("terms_emitted", C.c_uint64), ("nnz_in_total", C.c_uint64), ("sigma_calls", C.c_uint64),
                 ("psi_nnz_total", C.c_uint64),
-                ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32)]
+                ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32), ("tune_trials", C.c_int32),
+                ("tune_b1_chunk", C.c_uint32), ("tune_bb_chunk", C.c_uint32), ("tune_per_cu", C.c_uint32),
+                ("tune_default_ms", C.c_double), ("tune_best_ms", C.c_double)]
 
 
 _lib = None
@@ -307,7 +310,7 @@ class Batch:
             pass
 
     def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True,
-                screen_eps=0.0):
+                screen_eps=0.0, autotune=False):
         """starts: list of (ranks, amps); Ms: truncation per instance.  Returns
         dict(energies (n_inst, n_blocks), dh [list of (n,n)], dg [list of (n,n,n,n)], stats)."""
         torch = _torch()
@@ -330,7 +333,8 @@ class Batch:
             n4 = sum(p.n ** 4 for p in self.problems)
             dh_all = torch.empty(n2, dtype=torch.float64, device="cuda")
             dg_all = torch.empty(n4, dtype=torch.float64, device="cuda")
-        opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps))
+        opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps), 0,
+                           1 if autotune else 0)
         st = BatchStats()
         rc = load_library().sfci_batch_lanczos(self._h, vecs, Marr, C.byref(opts),
                                                energies.ctypes.data_as(C.c_void_p),
@@ -342,7 +346,10 @@ class Batch:
                               terms_emitted=st.terms_emitted, nnz_in_total=st.nnz_in_total,
                               sigma_calls=st.sigma_calls,
                               psi_nnz_total=st.psi_nnz_total, graph_replayed_blocks=st.graph_replayed_blocks,
-                              batched_sigma=st.batched_sigma))
+                              batched_sigma=st.batched_sigma, tune_trials=st.tune_trials,
+                              tune=dict(b1_chunk=st.tune_b1_chunk, bb_chunk=st.tune_bb_chunk,
+                                        per_cu=st.tune_per_cu, default_ms=st.tune_default_ms,
+                                        best_ms=st.tune_best_ms)))
         if want_grad:
             dh, dg, oh, og = [], [], 0, 0
             for p in self.problems:

@@ -201,3 +201,30 @@ def test_batch_screening_matches_oracle(torch, S, orc, det):
     # the 20-orbital instance against its own single-instance run
     single = P31.lanczos(*_perturbed(P31), M=2000, n_L=10, n_iter=20, deterministic=det, screen_eps=5e-5)
     assert np.all(np.abs(out["energies"][1] - single["energies"]) < 1e-9)
+
+
+def test_batch_autotune_keeps_energies(torch, S):
+    # The tuned work sizes (beta singles / beta-beta doubles per unit,
+    # workgroups per CU) only change the order of the tile accumulation:
+    # energies stay within 1e-9 Ha of the oracle; the choice comes from the
+    # candidate sets and a second call reuses it without new trials.
+    g31, g15 = _gold("c4p_inst31_M3e3_30"), _gold("c4p_inst15_M1e4_30")
+    P31, _, _ = _c4(S, 31)
+    P15, _, _ = _c4(S, 15)
+    B = S.Batch([P31, P15])
+    starts = [_perturbed(P31), _perturbed(P15)]
+    out = B.lanczos(starts, [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=False, want_grad=False,
+                    autotune=True)
+    st = out["stats"]
+    t = st["tune"]
+    assert st["tune_trials"] in (5, 6)
+    assert t["b1_chunk"] in (8, 16, 32) and t["bb_chunk"] in (2, 4, 8) and t["per_cu"] >= 1
+    assert 0 < t["best_ms"] <= t["default_ms"]
+    for k, g in enumerate((g31, g15)):
+        assert np.all(np.abs(out["energies"][k] - np.array(g["energies"])) < 1e-9)
+    again = B.lanczos(starts, [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=False, want_grad=False,
+                      autotune=True)
+    assert again["stats"]["tune_trials"] == 0
+    assert again["stats"]["tune"]["b1_chunk"] == t["b1_chunk"] and again["stats"]["tune"]["bb_chunk"] == t["bb_chunk"]
+    for k, g in enumerate((g31, g15)):
+        assert np.all(np.abs(again["energies"][k] - np.array(g["energies"])) < 1e-9)
