@@ -68,6 +68,9 @@ def lib():
         L.orc_lanczos.restype = i64
         L.orc_lanczos.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp, vp,
                                   vp, i64, dbl]
+        L.orc_pt2.restype = i32
+        L.orc_pt2.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, C.POINTER(dbl), C.POINTER(dbl),
+                              C.POINTER(u64)]
         for nm in ("orc_backward_explicit", "orc_backward_sc"):
             f = getattr(L, nm)
             f.restype = i32
@@ -179,6 +182,14 @@ class Problem:
             out["T"] = T.reshape(nblk, n_L, n_L)
             out["S"] = S.reshape(nblk, n_L, n_L)
         return out
+
+    def pt2(self, ranks, amps):
+        """Second-order Epstein-Nesbet correction of Psi: (E0, E2, number of external determinants)."""
+        e0, e2, ne = C.c_double(0.0), C.c_double(0.0), C.c_uint64(0)
+        rc = lib().orc_pt2(*self._a(), len(ranks), _u64(ranks), _f64(amps), C.byref(e0), C.byref(e2), C.byref(ne))
+        if rc != 0:
+            raise ValueError("invalid input vector")
+        return e0.value, e2.value, int(ne.value)
 
     def backward(self, v_rank, v_amp, s_rank, s_amp, explicit=False):
         n = self.n

@@ -807,6 +807,51 @@ static void sym8(int n, const double* G, double* out) {
                 }
 }
 
+// Second-order Epstein-Nesbet correction of a variational vector Psi, the
+// perturbative correction the paper names for future work (its comparison
+// with ASCI in the results).  Standard partitioning, H0 = diagonal of H:
+//   E0 = <Psi|H|Psi> / <Psi|Psi>,
+//   E2 = [ sum over k outside supp(Psi) of (H Psi)_k^2 / (E0 - H_kk) ] / <Psi|Psi>.
+// H Psi comes from the merge of orc_sigma; every sum runs over ascending rank
+// (E0's numerator over the entries of H Psi inside supp(Psi)); H_kk is the
+// diagonal element above.  *n_ext = number of external determinants with
+// (H Psi)_k != 0.  Returns 0, or -1 on bad input.
+extern "C" int orc_pt2(int n, int na, int nb, const double* h, const double* g, i64 nnz, const u64* rank,
+                       const double* amp, double* e0, double* e2, u64* n_ext) {
+    Space S = make_space(n, na, nb, h, g);
+    for (i64 t = 0; t < nnz; ++t) {
+        if (rank[t] >= S.Ndet) return -1;
+        if (t > 0 && rank[t] <= rank[t - 1]) return -1;
+    }
+    std::vector<Acc> y = sigma_merged(S, nnz, rank, amp);
+    double num = 0.0, den = 0.0;
+    for (i64 t = 0; t < nnz; ++t) den += amp[t] * amp[t];
+    // <Psi|H Psi>: walk both rank-sorted lists together
+    i64 t = 0;
+    for (const Acc& e : y) {
+        while (t < nnz && rank[t] < e.r) ++t;
+        if (t < nnz && rank[t] == e.r) num += amp[t] * e.v;
+    }
+    const double E0 = num / den;
+    std::vector<int> oa, va, ob, vb;
+    double s = 0.0;
+    u64 cnt = 0;
+    t = 0;
+    for (const Acc& e : y) {
+        while (t < nnz && rank[t] < e.r) ++t;
+        if ((t < nnz && rank[t] == e.r) || e.v == 0.0) continue;
+        occ_virt(orc_str_unrank(e.r / S.Nb, na), n, oa, va);
+        occ_virt(orc_str_unrank(e.r % S.Nb, nb), n, ob, vb);
+        const double hkk = diag_element(S, oa, ob);
+        s += (e.v * e.v) / (E0 - hkk);
+        ++cnt;
+    }
+    *e0 = E0;
+    *e2 = s / den;
+    *n_ext = cnt;
+    return 0;
+}
+
 extern "C" int orc_backward_explicit(int n, int na, int nb, const double* h, const double* g, i64 nnz_v,
                                      const u64* rv, const double* av, i64 nnz_s, const u64* rs, const double* as,
                                      double* vbar, double* dh, double* dg) {
