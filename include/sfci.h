@@ -174,6 +174,21 @@ sfci_status sfci_lanczos(sfci_problem* prob, const sfci_svec* v0, const sfci_lan
 sfci_status sfci_sigma_backward(sfci_problem* prob, const sfci_svec* v, const sfci_svec* sbar, double* v_bar,
                                 double* dh, double* deri);
 
+/* Second-order Epstein-Nesbet correction of a variational vector Psi (device
+ * vector, strictly ascending ranks, not necessarily normalised): the
+ * perturbative correction the paper names for future work (the F2 discussion
+ * in its results).  Diagonal partitioning:
+ *   *e0 = <Psi|H|Psi> / <Psi|Psi>,
+ *   *e2 = sum over determinants k outside supp(Psi) of (H Psi)_k^2 / (*e0 - H_kk),
+ *         divided by <Psi|Psi>;
+ *   *n_external (may be NULL) = number of those k with (H Psi)_k != 0.
+ * deterministic != 0: H Psi from the sort path and every sum in ascending
+ * rank (bit-reproducible); else the dense tile kernel and tree reductions.
+ * Needs the full H Psi as a list on the device (distinct entries x 16 B).
+ * Synchronises.  SFCI_E_ARG for an empty or zero-norm Psi. */
+sfci_status sfci_pt2(sfci_problem* prob, const sfci_svec* psi, int32_t deterministic, double* e0, double* e2,
+                     uint64_t* n_external);
+
 /* ---- batched iteration (spec extension, not in the paper) ----
  * Many instances (e.g. points along a bond-stretch curve) with uneven
  * truncations M_k, and possibly different orbital counts, iterate together:

@@ -177,6 +177,16 @@ __global__ __launch_bounds__(RB) void k_sumsq_part(const double* __restrict__ a,
     if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
+__global__ __launch_bounds__(RB) void k_sum_part(const double* __restrict__ x, const u64* __restrict__ nnz,
+                                                 double* __restrict__ part) {
+    __shared__ double sh[RB];
+    const u64 n = *nnz;
+    double s = 0.0;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += x[i];
+    double b = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
 __global__ __launch_bounds__(64) void k_sumsq_ordered(const double* __restrict__ a, const u64* __restrict__ nnz,
                                                       double* out) {
     __shared__ double stage[64];
@@ -399,6 +409,30 @@ void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64*
 void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 cap, const double* Y, double* out1,
                          double* out2, bool ordered) {
     dot_dense_impl<true>(P, nullptr, a, nnz, cap, Y, out1, out2, ordered);
+}
+
+void launch_sum(sfci_problem* P, const double* x, const u64* nnz, u64 cap, double* out, bool ordered) {
+    if (ordered) {
+        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, P->stream, x, nnz, out, (double*)nullptr);
+    } else {
+        double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
+        unsigned g = std::min<unsigned>(RGRID, gsz(cap));
+        hipLaunchKernelGGL(k_sum_part, dim3(g), dim3(RB), 0, P->stream, x, nnz, part);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, out, (double*)nullptr);
+    }
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out, bool ordered) {
+    if (ordered) {
+        hipLaunchKernelGGL(k_sumsq_ordered, dim3(1), dim3(64), 0, P->stream, a, nnz, out);
+    } else {
+        double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
+        unsigned g = std::min<unsigned>(RGRID, gsz(cap));
+        hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(RB), 0, P->stream, a, nnz, part);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, out, (double*)nullptr);
+    }
+    SFCI_CHECK_HIP(hipGetLastError());
 }
 
 void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,

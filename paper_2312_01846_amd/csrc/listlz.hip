@@ -481,6 +481,26 @@ u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink
     return passes;
 }
 
+u64 sigma_list_full(sfci_problem* P, const SigmaLaunch& v, u64* emitted_dev, u64** r, double** a) {
+    ListWs& ws = P->list_ws;
+    u64* ls = (u64*)ws.scal.get(128 * sizeof(u64));
+    launch_fill_u64(ls, 128, 0, P->stream);
+    ListCands C{P, ws, UINT64_MAX, 0, 0, ls, ls + 1, (int*)(ls + 3)};
+    C.reset();
+    ListPassSink sink;
+    sink.P = P;
+    sink.cands = &C;
+    sink.bounds = ls + 8;
+    sink.pcount = ls + 2;
+    sigma_sorted_passes(P, v, sink, emitted_dev, 0, 0.0);
+    check_overflow(P, (const int*)(ls + 3));
+    const u64 n = read_dev(P, C.Rn);
+    sort_by_rank(P, C.Rr(), C.Ra(), n);
+    *r = C.Rr();
+    *a = C.Ra();
+    return n;
+}
+
 void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& Bs, sfci_svec* psi_out,
                   u64* psi_n_out, u64* sigma_calls, EventTimer& tsig) {
     const int nL = o->n_L;

@@ -1,0 +1,146 @@
+// Second-order Epstein-Nesbet correction of a variational vector Psi: the
+// perturbative correction the paper leaves for future work (its comparison
+// of the F2 result with ASCI and that method's Epstein-Nesbet correction).
+// Standard partitioning with the diagonal of H as the zeroth-order operator:
+//   E0 = <Psi|H|Psi> / <Psi|Psi>,
+//   E2 = [ sum over k outside supp(Psi) of (H Psi)_k^2 / (E0 - H_kk) ] / <Psi|Psi>.
+// The same sigma machinery produces H Psi as a rank-sorted list; one pass
+// forms E0's products on supp(Psi) (binary search in Psi), one the external
+// terms with H_kk in the diagonal element's fixed addition order.  The
+// deterministic option (sort-path sigma, every sum strictly in rank order)
+// gives the bits of a sequential evaluation; otherwise the dense tile kernel
+// and tree reductions.
+#include <algorithm>
+
+#include "sfci_internal.h"
+
+namespace {
+
+constexpr int PB = 256;
+
+__device__ __forceinline__ bool find_rank(const u64* __restrict__ r, u64 n, u64 key, u64* pos) {
+    u64 lo = 0, hi = n;
+    while (lo < hi) {
+        const u64 mid = lo + ((hi - lo) >> 1);
+        if (r[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    *pos = lo;
+    return lo < n && r[lo] == key;
+}
+
+// prod[i] = Psi(rank of y_i) * y_i on supp(Psi), else 0
+__global__ __launch_bounds__(PB) void k_pt2_inner(const u64* __restrict__ yr, const double* __restrict__ ya,
+                                                  const u64* __restrict__ ny, const u64* __restrict__ pr,
+                                                  const double* __restrict__ pa, u64 np, double* __restrict__ prod) {
+    const u64 n = *ny;
+    for (u64 i = (u64)blockIdx.x * PB + threadIdx.x; i < n; i += (u64)gridDim.x * PB) {
+        u64 pos;
+        prod[i] = find_rank(pr, np, yr[i], &pos) ? pa[pos] * ya[i] : 0.0;
+    }
+}
+
+__global__ void k_pt2_e0(const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ e0) {
+    if (threadIdx.x == 0) *e0 = *num / *den;
+}
+
+// prod[i] = y_i^2 / (E0 - H_kk) outside supp(Psi), else 0; counts the external entries
+__global__ __launch_bounds__(PB) void k_pt2_outer(SpaceDev sp, Ints I, const u64* __restrict__ binom,
+                                                  const u64* __restrict__ yr, const double* __restrict__ ya,
+                                                  const u64* __restrict__ ny, const u64* __restrict__ pr, u64 np,
+                                                  const double* __restrict__ e0p, double* __restrict__ prod,
+                                                  unsigned long long* __restrict__ n_ext) {
+    __shared__ BinomLds B;
+    load_binom(B, binom);
+    __syncthreads();
+    const u64 n = *ny;
+    const double E0 = *e0p;
+    unsigned long long cnt = 0;
+    for (u64 i = (u64)blockIdx.x * PB + threadIdx.x; i < n; i += (u64)gridDim.x * PB) {
+        u64 pos;
+        const double y = ya[i];
+        double t = 0.0;
+        if (y != 0.0 && !find_rank(pr, np, yr[i], &pos)) {
+            const u64 ra = yr[i] / sp.Nb;
+            const u32 A = str_unrank(ra, sp.na, sp.n, B);
+            const u32 Bs = str_unrank(yr[i] - ra * sp.Nb, sp.nb, sp.n, B);
+            const double hkk = diag_element(I, A, Bs);
+            t = (y * y) / (E0 - hkk);
+            ++cnt;
+        }
+        prod[i] = t;
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(n_ext, cnt);
+}
+
+unsigned grid_of(u64 n) {
+    u64 g = (n + PB - 1) / PB;
+    return (unsigned)std::max<u64>(1, std::min<u64>(g, 16384));
+}
+
+}  // namespace
+
+// H Psi as a rank-sorted list: the sort path (deterministic, or when the
+// N_det array does not fit) or the dense tile kernel compacted in rank order.
+static u64 sigma_full_list(sfci_problem* P, const SigmaLaunch& sl, bool det, u64* emitted, u64** yr, double** ya,
+                           u64* cnt_dev) {
+    if (det || !ensure_dense(P)) {
+        const u64 n = sigma_list_full(P, sl, emitted, yr, ya);
+        launch_set_u64(P, cnt_dev, n);
+        return n;
+    }
+    dense_sigma(P, sl, SFCI_DEDUP_DENSE, (unsigned long long*)emitted);
+    CandSrc src{};
+    src.dense = P->d_D;
+    select_prepare(P, src, UINT64_MAX, cnt_dev);
+    u64 n = 0;
+    SFCI_CHECK_HIP(hipMemcpyAsync(&n, cnt_dev, sizeof(u64), hipMemcpyDeviceToHost, P->stream));
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    *yr = (u64*)P->ws_list_r.get(std::max<u64>(1, n) * sizeof(u64));
+    *ya = (double*)P->ws_list_a.get(std::max<u64>(1, n) * sizeof(double));
+    select_write(P, src, *yr, *ya, true);  // rank order; zeroes the accumulator
+    return n;
+}
+
+extern "C" sfci_status sfci_pt2(sfci_problem* P, const sfci_svec* psi, int32_t deterministic, double* e0,
+                                double* e2, uint64_t* n_external) {
+    try {
+        if (!P || !psi || !e0 || !e2) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
+        if (psi->nnz == 0 || !psi->rank || !psi->amp)
+            return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty vector");
+        validate_vec(P, psi->rank, psi->nnz);
+        const bool det = deterministic != 0;
+        u64* sc = (u64*)P->ws_lz[0].get(16 * sizeof(u64));  // [0] nnz(Psi) [1] emitted [2] |y| [3] n_ext
+        double* sd = (double*)(sc + 8);                     // [0] num [1] den [2] E0 [3] sum
+        launch_fill_u64(sc, 16, 0, P->stream);
+        launch_set_u64(P, sc, psi->nnz);
+        const SigmaLaunch sl{psi->rank, psi->amp, sc, psi->nnz};
+        u64* yr;
+        double* ya;
+        const u64 ny = sigma_full_list(P, sl, det, sc + 1, &yr, &ya, sc + 2);
+        double* prod = (double*)P->ws_prod.get(std::max<u64>(1, ny) * sizeof(double));
+        hipLaunchKernelGGL(k_pt2_inner, dim3(grid_of(ny)), dim3(PB), 0, P->stream, yr, ya, sc + 2, psi->rank,
+                           psi->amp, (u64)psi->nnz, prod);
+        launch_sum(P, prod, sc + 2, std::max<u64>(1, ny), sd + 0, det);
+        launch_sumsq(P, psi->amp, sc, psi->nnz, sd + 1, det);
+        hipLaunchKernelGGL(k_pt2_e0, dim3(1), dim3(64), 0, P->stream, sd + 0, sd + 1, sd + 2);
+        hipLaunchKernelGGL(k_pt2_outer, dim3(grid_of(ny)), dim3(PB), 0, P->stream,
+                           SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb}, Ints{P->d_h, P->d_g, P->n}, P->d_binom, yr,
+                           ya, sc + 2, psi->rank, (u64)psi->nnz, sd + 2, prod, (unsigned long long*)(sc + 3));
+        launch_sum(P, prod, sc + 2, std::max<u64>(1, ny), sd + 3, det);
+        SFCI_CHECK_HIP(hipGetLastError());
+        double hd[4];
+        u64 hc[4];
+        SFCI_CHECK_HIP(hipMemcpyAsync(hd, sd, sizeof(hd), hipMemcpyDeviceToHost, P->stream));
+        SFCI_CHECK_HIP(hipMemcpyAsync(hc, sc, sizeof(hc), hipMemcpyDeviceToHost, P->stream));
+        SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+        if (!(hd[1] > 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "Psi has zero norm");
+        *e0 = hd[2];
+        *e2 = hd[3] / hd[1];
+        if (n_external) *n_external = hc[3];
+        return SFCI_OK;
+    } catch (const sfci_error& e) {
+        return (sfci_status)sfci_set_error(e.code, e.msg);
+    }
+}

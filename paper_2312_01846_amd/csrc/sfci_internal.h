@@ -269,6 +269,9 @@ void launch_dot_dense(sfci_problem* P, const u64* r, const double* a, const u64*
 // The same sum with Y[i] (the y value already gathered for entry i) in place of D[r[i]].
 void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 cap, const double* Y, double* out1,
                          double* out2, bool ordered);
+// sum of x[0..*nnz) (ordered: strictly in index order) and sum of squares
+void launch_sum(sfci_problem* P, const double* x, const u64* nnz, u64 cap, double* out, bool ordered);
+void launch_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out, bool ordered);
 void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u64* xn, u64 xcap, const u64* yr,
                        const double* ya, const u64* yn, double* out1, double* out2, bool ordered);
 void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap,
@@ -334,6 +337,9 @@ struct EventTimer {
 // *distinct_host (may be NULL) receives the number of distinct nonzero entries.
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
                     u64* emitted_dev, u64* distinct_host);
+// sigma = H v in full through the sort path's passes, no N_det array: the
+// nonzero entries sorted by rank in list_ws.Rr / Ra; returns their number.
+u64 sigma_list_full(sfci_problem* P, const SigmaLaunch& v, u64* emitted_dev, u64** r, double** a);
 // The basis and the per-block outputs the iteration writes (device).
 struct ListBasis {
     u64 cap;        // entries per basis vector

@@ -84,6 +84,8 @@ _SIGS = {
                                C.c_void_p, C.c_void_p, C.POINTER(LanczosStats)]),
     "sfci_sigma_backward": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SVec), C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "sfci_pt2": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                           C.POINTER(C.c_uint64)]),
     "sfci_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "sfci_batch_destroy": (C.c_int, [C.c_void_p]),
     "sfci_batch_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(C.c_uint64), C.POINTER(LanczosOpts),
@@ -221,6 +223,16 @@ class Problem:
         return o_r[:k], o_a[:k]
 
     # -- backward of sigma = H(h, g) v -----------------------------------------------
+    def pt2(self, ranks, amps, deterministic=False):
+        """Second-order Epstein-Nesbet correction of Psi: (E0, E2, number of external determinants)."""
+        torch = _torch()
+        r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
+        a = torch.as_tensor(amps, device="cuda").to(torch.float64).contiguous()
+        e0, e2, ne = C.c_double(0.0), C.c_double(0.0), C.c_uint64(0)
+        _check(load_library().sfci_pt2(self._h, C.byref(_svec(r, a)), 1 if deterministic else 0, C.byref(e0),
+                                       C.byref(e2), C.byref(ne)))
+        return e0.value, e2.value, int(ne.value)
+
     def sigma_backward(self, v_rank, v_amp, s_rank, s_amp, want_vbar=True, want_dh=True, want_dg=True):
         """vbar = H sbar on supp(v); dh, dg = gradients of sbar^T H v along symmetric perturbations."""
         torch = _torch()
