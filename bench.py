@@ -63,6 +63,8 @@ def parse():
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c4batch: keep the tile kernel's default work sizes")
+    ap.add_argument("--pt2", action="store_true",
+                    help="single-problem workloads: also time the Epstein-Nesbet correction of the start vector")
     ap.add_argument("--det", action="store_true",
                     help="single-problem workloads: deterministic mode (sort dedup, ordered sums)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -190,6 +192,17 @@ def main():
     alg_bytes = 16 * nnz_in_total + 16 * terms
     sig_s = st["sigma_ms"] / 1e3
     achieved = alg_bytes / sig_s if sig_s > 0 else 0.0
+    pt2 = None
+    if args.pt2:
+        # second-order Epstein-Nesbet correction of the (truncated, normalised) start vector
+        pt2 = dict(input_nnz=int(v_r.numel()))
+        for mode, det in (("fast", False), ("deterministic", True)):
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            e0, e2, ne = P.pt2(v_r, v_a, deterministic=det)
+            pt2[mode] = dict(ms=(time.perf_counter() - t2) * 1e3, e0=e0, e2=e2, n_external=ne,
+                             sigma_terms_per_s=int(v_r.numel()) * tps / (time.perf_counter() - t2))
+        print(f"# pt2: {pt2}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(h, g, n, na, nb, v_r.cpu().numpy().astype(np.uint64), v_a.cpu().numpy(),
@@ -214,6 +227,7 @@ def main():
             "n_L": args.n_L,
             "terms_per_step": terms / args.steps,
             "energies": [float(x) for x in out["energies"]],
+            "pt2": pt2,
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -321,10 +321,10 @@ struct ListCands {
     }
     // Cut the list back to its K best once it has grown past 2K.
     void maybe_cut() {
-        if (K == UINT64_MAX) return;
         check_overflow(P, overflow);
         const u64 n = read_dev(P, Rn);
-        n_upper = n;
+        n_upper = n;  // the actual length (the appends' bound counts every pass entry)
+        if (K == UINT64_MAX) return;
         if (n <= 2 * K + SFCI_TIE_SLACK) return;
         u64* r2 = (u64*)ws.R2r.get(n * sizeof(u64));
         double* a2 = (double*)ws.R2a.get(n * sizeof(double));
