@@ -93,8 +93,15 @@ __global__ __launch_bounds__(RB) void k_dot_final(const double* __restrict__ par
 __device__ __forceinline__ double add_chunk_in_order(double acc, double p, int cnt, double* stage) {
     stage[threadIdx.x & 63] = p;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        for (int k = 0; k < cnt; ++k) acc += stage[k];
+    if ((threadIdx.x & 63) == 0) {
+        if (cnt == 64) {
+            // a full chunk: a fixed-length chain, so the LDS reads run ahead of the adds
+#pragma unroll
+            for (int k = 0; k < 64; ++k) acc += stage[k];
+        } else {
+            for (int k = 0; k < cnt; ++k) acc += stage[k];
+        }
+    }
     __syncthreads();
     return acc;
 }
@@ -137,9 +144,12 @@ __global__ __launch_bounds__(64) void k_sum_ordered(const double* __restrict__ p
     __shared__ double stage[64];
     const u64 n = *nnz;
     double acc = 0.0;
+    double nxt = (threadIdx.x < n) ? prod[threadIdx.x] : 0.0;
     for (u64 base = 0; base < n; base += 64) {
-        const u64 i = base + threadIdx.x;
-        acc = add_chunk_in_order(acc, (i < n) ? prod[i] : 0.0, (int)((n - base < 64) ? (n - base) : 64), stage);
+        const double cur = nxt;
+        const u64 i2 = base + 64 + threadIdx.x;  // the next chunk's load is in flight during this chunk's adds
+        nxt = (i2 < n) ? prod[i2] : 0.0;
+        acc = add_chunk_in_order(acc, cur, (int)((n - base < 64) ? (n - base) : 64), stage);
     }
     if (threadIdx.x == 0) {
         *out1 = acc;

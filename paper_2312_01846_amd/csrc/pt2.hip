@@ -5,8 +5,9 @@
 //   E0 = <Psi|H|Psi> / <Psi|Psi>,
 //   E2 = [ sum over k outside supp(Psi) of (H Psi)_k^2 / (E0 - H_kk) ] / <Psi|Psi>.
 // The same sigma machinery produces H Psi as a rank-sorted list; one pass
-// forms E0's products on supp(Psi) (binary search in Psi), one the external
-// terms with H_kk in the diagonal element's fixed addition order.  The
+// forms E0's products over supp(Psi) (each Psi rank searched in H Psi), one
+// the external terms (each H Psi rank searched in Psi) with H_kk in the
+// diagonal element's fixed addition order.  The
 // deterministic option (sort-path sigma, every sum strictly in rank order)
 // gives the bits of a sequential evaluation; otherwise the dense tile kernel
 // and tree reductions.
@@ -29,14 +30,16 @@ __device__ __forceinline__ bool find_rank(const u64* __restrict__ r, u64 n, u64 
     return lo < n && r[lo] == key;
 }
 
-// prod[i] = Psi(rank of y_i) * y_i on supp(Psi), else 0
+// prod[t] = Psi_t * y(rank of Psi_t) (0 where H Psi has no entry): the
+// products of <Psi|H Psi> in ascending rank (skipping the zero products of
+// entries outside supp(Psi) leaves the ordered sum's bits unchanged)
 __global__ __launch_bounds__(PB) void k_pt2_inner(const u64* __restrict__ yr, const double* __restrict__ ya,
                                                   const u64* __restrict__ ny, const u64* __restrict__ pr,
                                                   const double* __restrict__ pa, u64 np, double* __restrict__ prod) {
     const u64 n = *ny;
-    for (u64 i = (u64)blockIdx.x * PB + threadIdx.x; i < n; i += (u64)gridDim.x * PB) {
+    for (u64 t = (u64)blockIdx.x * PB + threadIdx.x; t < np; t += (u64)gridDim.x * PB) {
         u64 pos;
-        prod[i] = find_rank(pr, np, yr[i], &pos) ? pa[pos] * ya[i] : 0.0;
+        prod[t] = find_rank(yr, n, pr[t], &pos) ? pa[t] * ya[pos] : 0.0;
     }
 }
 
@@ -119,10 +122,10 @@ extern "C" sfci_status sfci_pt2(sfci_problem* P, const sfci_svec* psi, int32_t d
         u64* yr;
         double* ya;
         const u64 ny = sigma_full_list(P, sl, det, sc + 1, &yr, &ya, sc + 2);
-        double* prod = (double*)P->ws_prod.get(std::max<u64>(1, ny) * sizeof(double));
-        hipLaunchKernelGGL(k_pt2_inner, dim3(grid_of(ny)), dim3(PB), 0, P->stream, yr, ya, sc + 2, psi->rank,
+        double* prod = (double*)P->ws_prod.get(std::max<u64>(std::max<u64>(1, ny), psi->nnz) * sizeof(double));
+        hipLaunchKernelGGL(k_pt2_inner, dim3(grid_of(psi->nnz)), dim3(PB), 0, P->stream, yr, ya, sc + 2, psi->rank,
                            psi->amp, (u64)psi->nnz, prod);
-        launch_sum(P, prod, sc + 2, std::max<u64>(1, ny), sd + 0, det);
+        launch_sum(P, prod, sc, psi->nnz, sd + 0, det);
         launch_sumsq(P, psi->amp, sc, psi->nnz, sd + 1, det);
         hipLaunchKernelGGL(k_pt2_e0, dim3(1), dim3(64), 0, P->stream, sd + 0, sd + 1, sd + 2);
         hipLaunchKernelGGL(k_pt2_outer, dim3(grid_of(ny)), dim3(PB), 0, P->stream,
