@@ -68,6 +68,9 @@ def lib():
         L.orc_lanczos.restype = i64
         L.orc_lanczos.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp, vp,
                                   vp, i64, dbl]
+        L.orc_lanczos_roots.restype = i64
+        L.orc_lanczos_roots.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp,
+                                        vp, vp, i64, dbl, i32, vp, vp, vp]
         L.orc_pt2.restype = i32
         L.orc_pt2.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, C.POINTER(dbl), C.POINTER(dbl),
                               C.POINTER(u64)]
@@ -162,21 +165,31 @@ class Problem:
         v = lib().orc_sigma_entry(*self._a(), len(ranks), _u64(ranks), _f64(amps), int(target), C.byref(ab))
         return v, ab.value
 
-    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0):
+    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0, roots=None):
+        """roots: list of (ranks, amps) of previously found eigenvectors to project out."""
         M = -1 if M is None else int(M)
         nblk = n_iter // n_L
         en = np.zeros(nblk, dtype=np.float64)
         T = np.zeros(nblk * n_L * n_L, dtype=np.float64)
         S = np.zeros(nblk * n_L * n_L, dtype=np.float64)
         r0, a0 = _u64(ranks0), _f64(amps0)
-        need = lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), None, None, 0,
-                                 float(eps))
+        roots = roots or []
+        off = np.zeros(len(roots) + 1, dtype=np.int64)
+        for i, (rr, _) in enumerate(roots):
+            off[i + 1] = off[i] + len(rr)
+        rcat = _u64(np.concatenate([np.asarray(rr, dtype=np.uint64) for rr, _ in roots]) if roots
+                    else np.zeros(1, dtype=np.uint64))
+        acat = _f64(np.concatenate([np.asarray(aa, dtype=np.float64) for _, aa in roots]) if roots
+                    else np.zeros(1))
+        args = (float(eps), len(roots), _ptr(off), _ptr(rcat), _ptr(acat))
+        need = lib().orc_lanczos_roots(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), None,
+                                       None, 0, *args)
         if need < 0:
             raise RuntimeError("oracle lanczos failed")
         pr = np.empty(need, dtype=np.uint64)
         pa = np.empty(need, dtype=np.float64)
-        lib().orc_lanczos(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa), need,
-                          float(eps))
+        lib().orc_lanczos_roots(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa),
+                                need, *args)
         out = dict(energies=en, psi_rank=pr, psi_amp=pa)
         if want_T:
             out["T"] = T.reshape(nblk, n_L, n_L)

@@ -715,17 +715,72 @@ static SVec lanczos_update(const SVec& y, double a, const SVec& x, double b, con
 // n_iter sigma applications are run (n_iter / N_L blocks).  energies[b]
 // receives each block's lambda.  The final Psi (before truncation) is
 // written to psi_* when psi_cap suffices; returns its size, or -1.
+// y <- y - c x entrywise over the union of supports (missing = 0), each entry
+// rounded as y_k - (c * x_k).
+static SVec axpy_union(const SVec& y, double c, const SVec& x) {
+    SVec out;
+    size_t i = 0, j = 0;
+    while (i < y.r.size() || j < x.r.size()) {
+        if (j == x.r.size() || (i < y.r.size() && y.r[i] < x.r[j])) {
+            out.r.push_back(y.r[i]); out.a.push_back(y.a[i]); ++i;
+        } else if (i == y.r.size() || x.r[j] < y.r[i]) {
+            const double prod = c * x.a[j];
+            out.r.push_back(x.r[j]); out.a.push_back(0.0 - prod); ++j;
+        } else {
+            const double prod = c * x.a[j];
+            out.r.push_back(y.r[i]); out.a.push_back(y.a[i] - prod); ++i; ++j;
+        }
+    }
+    return out;
+}
+
+// Projection onto the complement of the previously found eigenvectors
+// (Sec. 4: excited states by projecting the found eigenvectors out of the
+// effective Hamiltonian): P y = y - sum_i Psi_i <Psi_i|y> / <Psi_i|Psi_i>,
+// the roots taken in order.
+struct Roots {
+    std::vector<SVec> v;    // Psi_i
+    std::vector<SVec> hv;   // H Psi_i
+    std::vector<double> q;  // <Psi_i|Psi_i>
+};
+
+static SVec project(const Roots& R, SVec y) {
+    for (size_t i = 0; i < R.v.size(); ++i) {
+        const double d = sdot(R.v[i], y) / R.q[i];
+        y = axpy_union(y, d, R.v[i]);
+    }
+    return y;
+}
+
 // eps > 0: the screening of Sec. 3 -- entries of the merged H w_j with
 // amplitude below eps are not taken into v, so T, the Eq. 10 update and the
 // candidates all see the screened vector.
-extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
-                           const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
-                           double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps) {
+// n_roots > 0: the iteration runs on P H P (P as above) from the projected,
+// truncated start vector, for the next excited state: every sigma becomes
+//   y = screen(H w) - sum_i c_i H Psi_i  (c_i = <Psi_i|w>/<Psi_i|Psi_i>),  then y = P y,
+// and the block-end Psi is projected before its truncation.  Root i is
+// (root_r, root_a)[root_off[i] .. root_off[i+1]), ranks ascending.
+extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
+                                 const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
+                                 double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
+                                 int n_roots, const i64* root_off, const u64* root_r, const double* root_a) {
     Space S = make_space(n, na, nb, h, g);
+    Roots R;
+    for (int i = 0; i < n_roots; ++i) {
+        SVec x;
+        x.r.assign(root_r + root_off[i], root_r + root_off[i + 1]);
+        x.a.assign(root_a + root_off[i], root_a + root_off[i + 1]);
+        double q = 0.0;
+        for (double v : x.a) q += v * v;
+        R.hv.push_back(sigma_full(S, x));
+        R.q.push_back(q);
+        R.v.push_back(x);
+    }
     SVec w0;
     w0.r.assign(r0, r0 + nnz0);
     w0.a.assign(a0, a0 + nnz0);
-    orc_normalize((i64)w0.a.size(), w0.a.data());
+    if (n_roots > 0) w0 = topm_normalize(project(R, w0), M);
+    else orc_normalize((i64)w0.a.size(), w0.a.data());
     int nblocks = n_iter / nL;
     SVec psi;
     for (int blk = 0; blk < nblocks; ++blk) {
@@ -739,6 +794,14 @@ extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double*
                 for (size_t t = 0; t < y.r.size(); ++t)
                     if (!(std::fabs(y.a[t]) < eps)) { ys.r.push_back(y.r[t]); ys.a.push_back(y.a[t]); }
                 y = ys;
+            }
+            if (n_roots > 0) {
+                // H P w = H w - sum_i c_i H Psi_i, then P
+                for (int i = 0; i < n_roots; ++i) {
+                    const double c = sdot(R.v[i], w[j]) / R.q[i];
+                    y = axpy_union(y, c, R.hv[i]);
+                }
+                y = project(R, y);
             }
             for (int l = 0; l <= j; ++l) {
                 double t = sdot(w[l], y);
@@ -772,6 +835,12 @@ extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double*
         psi.r.clear(); psi.a.clear();
         for (size_t t = 0; t < all.size(); ++t)
             if (acc[t] != 0.0) { psi.r.push_back(all[t]); psi.a.push_back(acc[t]); }
+        if (n_roots > 0) {
+            SVec pp = project(R, psi), nz;
+            for (size_t t = 0; t < pp.r.size(); ++t)
+                if (pp.a[t] != 0.0) { nz.r.push_back(pp.r[t]); nz.a.push_back(pp.a[t]); }
+            psi = nz;
+        }
         w0 = topm_normalize(psi, M);
     }
     if ((i64)psi.r.size() <= psi_cap && psi_rank && psi_amp) {
@@ -779,6 +848,13 @@ extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double*
         std::copy(psi.a.begin(), psi.a.end(), psi_amp);
     }
     return (i64)psi.r.size();
+}
+
+extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
+                           const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
+                           double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps) {
+    return orc_lanczos_roots(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
+                             psi_cap, eps, 0, nullptr, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -165,3 +165,41 @@ def test_screening_tiny_eps_is_identity(orc):
     # the paper's setting leaves the energy nearly unchanged on this case
     c = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30, eps=5e-5)
     assert abs(c["energies"][-1] - a["energies"][-1]) < 1e-3
+
+
+def _dense_setup(orc, n, na, nb, seed):
+    h, g = synth.molecule_like(n, 2 * n, seed)
+    P = orc.Problem(n, na, nb, h, g)
+    H = P.dense_H()
+    w, V = np.linalg.eigh(H)
+    return P, w, V
+
+
+def test_excited_state_by_projection_converges_to_next_eigenvalue(orc):
+    # Sec. 4: project the found eigenvectors out of the effective Hamiltonian.
+    # From a start that breaks every symmetry but S_z, the untruncated
+    # iteration with the exact ground state projected out converges to the
+    # second eigenvalue of the dense H, with two roots to the third.
+    P, w, V = _dense_setup(orc, 6, 2, 2, 21)
+    N = P.n_det
+    rng = np.random.default_rng(3)
+    r0 = np.arange(N, dtype=np.uint64)
+    a0 = rng.standard_normal(N)
+    root0 = (r0, V[:, 0])
+    out = P.lanczos(r0, a0, None, 10, 80, roots=[root0])
+    assert abs(out["energies"][-1] - w[1]) < 1e-8
+    out2 = P.lanczos(r0, a0, None, 10, 80, roots=[root0, (r0, V[:, 1])])
+    assert abs(out2["energies"][-1] - w[2]) < 1e-8
+    # the final Psi is orthogonal to the roots
+    psi = np.zeros(N)
+    psi[out2["psi_rank"].astype(np.int64)] = out2["psi_amp"]
+    assert abs(psi @ V[:, 0]) < 1e-10 * np.linalg.norm(psi)
+    assert abs(psi @ V[:, 1]) < 1e-10 * np.linalg.norm(psi)
+
+
+def test_no_roots_is_the_plain_iteration(orc):
+    h, g = synth.molecule_like(8, 16, 0)
+    P = orc.Problem(8, 3, 3, h, g)
+    a = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20)
+    b = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20, roots=[])
+    assert np.array_equal(a["energies"], b["energies"]) and np.array_equal(a["psi_amp"], b["psi_amp"])
