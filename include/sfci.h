@@ -164,6 +164,22 @@ typedef struct {
 sfci_status sfci_lanczos(sfci_problem* prob, const sfci_svec* v0, const sfci_lanczos_opts* opts, double* energies,
                          sfci_svec* psi_out, double* T_out, double* S_out, sfci_lanczos_stats* stats);
 
+/* Excited states (Sec. 4: project the previously found eigenvectors out of
+ * the effective Hamiltonian): the iteration of sfci_lanczos on P H P with
+ * P y = y - sum_i Psi_i <Psi_i|y> / <Psi_i|Psi_i>, roots[0..n_roots) the found
+ * eigenvectors (device vectors, ascending ranks, any norm, applied in order).
+ * Each sigma becomes H w - sum_i c_i H Psi_i (c_i = <Psi_i|w>/<Psi_i|Psi_i>,
+ * H Psi_i computed once) followed by P; the start vector is projected and
+ * truncated to M; the block-end Psi is projected before its truncation, and
+ * psi_out receives the projected Psi.  energies: the lowest eigenvalue of each
+ * block's (T, S), i.e. the next state.  n_roots = 0 is sfci_lanczos.  Needs
+ * the dense accumulator (SFCI_E_UNSUPPORTED with no_dense or when it does not
+ * fit); at most SFCI_MAX_ROOTS roots. */
+#define SFCI_MAX_ROOTS 8
+sfci_status sfci_lanczos_roots(sfci_problem* prob, const sfci_svec* v0, const sfci_lanczos_opts* opts,
+                               const sfci_svec* roots, int32_t n_roots, double* energies, sfci_svec* psi_out,
+                               double* T_out, double* S_out, sfci_lanczos_stats* stats);
+
 /* Backward of sigma = H(h, eri) v for a cotangent sbar (device vectors):
  *   v_bar[i] = sum_k H_ki sbar_k for the entries i of v (device, nnz(v) doubles, may be NULL),
  *   dh  = sym(gamma),  gamma_pq = sum_ki sbar_k v_i <k|E_pq|i>      (device n*n, may be NULL),

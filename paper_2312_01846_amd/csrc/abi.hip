@@ -251,6 +251,12 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_desc.release();
     P->grad_ws.release();
     P->list_ws.release();
+    for (int i = 0; i < SFCI_MAX_ROOTS; ++i) {
+        P->ws_hroot_r[i].release();
+        P->ws_hroot_a[i].release();
+    }
+    P->ws_roots_sc.release();
+    P->ws_roots_cnt.release();
     P->rowpass_ws.release();
     delete P;
     return SFCI_OK;
@@ -395,8 +401,27 @@ sfci_status sfci_topm(sfci_problem* P, const sfci_svec* v, uint64_t M, int32_t n
 
 sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczos_opts* o, double* energies,
                          sfci_svec* psi_out, double* T_out, double* S_out, sfci_lanczos_stats* stats) {
+    return sfci_lanczos_roots(P, v0, o, nullptr, 0, energies, psi_out, T_out, S_out, stats);
+}
+
+namespace {
+__global__ void k_div_scalar(const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ out) {
+    if (threadIdx.x == 0) *out = *num / *den;
+}
+}  // namespace
+
+sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_lanczos_opts* o,
+                               const sfci_svec* roots, int32_t n_roots, double* energies, sfci_svec* psi_out,
+                               double* T_out, double* S_out, sfci_lanczos_stats* stats) {
     SFCI_GUARD_BEGIN
     if (!P || !v0 || !o || !energies) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
+    if (n_roots < 0 || n_roots > SFCI_MAX_ROOTS || (n_roots > 0 && !roots))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 0 <= n_roots <= SFCI_MAX_ROOTS root vectors");
+    for (int i = 0; i < n_roots; ++i) {
+        if (roots[i].nnz == 0 || !roots[i].rank || !roots[i].amp)
+            return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty root vector");
+        validate_vec(P, roots[i].rank, roots[i].nnz);
+    }
     if (o->n_L < 1 || o->n_L > 32 || o->n_iter < o->n_L)
         return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
     if (v0->nnz == 0) return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty start vector");
@@ -405,6 +430,8 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
     const int nblk = o->n_iter / nL;
     const bool det = o->deterministic != 0;
     const bool list_mode = o->no_dense != 0 || !ensure_dense(P);
+    if (list_mode && n_roots > 0)
+        return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "projected roots need the dense accumulator");
     // a truncated vector holds at most M + SFCI_TIE_SLACK entries
     const u64 cap = (o->M >= P->Ndet) ? P->Ndet
                                       : std::min<u64>(std::max<u64>(o->M + SFCI_TIE_SLACK, v0->nnz), P->Ndet);
@@ -440,12 +467,52 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
     SFCI_CHECK_HIP(hipEventCreate(&e0));
     SFCI_CHECK_HIP(hipEventCreate(&e1));
     SFCI_CHECK_HIP(hipEventRecord(e0, P->stream));
-    // w_0 = v0 / |v0|
-    {
+    // Projected roots (excited states, Sec. 4): <Psi_i|Psi_i> and H Psi_i once;
+    // per root scalars: [0] q, [1] c or d numerator, [2] c or d.
+    double* rsc = (double*)P->ws_roots_sc.get((size_t)(3 * SFCI_MAX_ROOTS + 8) * sizeof(double));
+    u64* rcnt = (u64*)P->ws_roots_cnt.get((size_t)(2 * SFCI_MAX_ROOTS + 8) * sizeof(u64));
+    std::vector<u64> hcap(n_roots, 0);
+    for (int i = 0; i < n_roots; ++i) {
+        launch_set_u64(P, rcnt + i, roots[i].nnz);
+        launch_sumsq(P, roots[i].amp, rcnt + i, roots[i].nnz, rsc + 3 * i, det);
+        u64 *yr;
+        double* ya;
+        const SigmaLaunch rl{roots[i].rank, roots[i].amp, rcnt + i, roots[i].nnz};
+        const u64 ny = sigma_full_list(P, rl, det, sc + 40, &yr, &ya, rcnt + SFCI_MAX_ROOTS + i);
+        hcap[i] = std::max<u64>(1, ny);
+        u64* hr = (u64*)P->ws_hroot_r[i].get(hcap[i] * sizeof(u64));
+        double* ha = (double*)P->ws_hroot_a[i].get(hcap[i] * sizeof(double));
+        if (ny) {
+            SFCI_CHECK_HIP(hipMemcpyAsync(hr, yr, ny * sizeof(u64), hipMemcpyDeviceToDevice, P->stream));
+            SFCI_CHECK_HIP(hipMemcpyAsync(ha, ya, ny * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+        }
+    }
+    // D <- P D: D -= (<Psi_i|D>/q_i) Psi_i, roots in order
+    auto project_dense = [&]() {
+        for (int i = 0; i < n_roots; ++i) {
+            launch_dot_dense(P, roots[i].rank, roots[i].amp, rcnt + i, roots[i].nnz, P->d_D, rsc + 3 * i + 1,
+                             nullptr, det);
+            hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, P->stream, rsc + 3 * i + 1, rsc + 3 * i,
+                               rsc + 3 * i + 2);
+            launch_axpy_scatter(P, P->d_D, roots[i].rank, roots[i].amp, rcnt + i, roots[i].nnz, rsc + 3 * i + 2,
+                                -1.0);
+        }
+    };
+    // w_0 = v0 / |v0| (with roots: the projected start, truncated to M)
+    if (n_roots == 0) {
         DVec w = W(0);
         SFCI_CHECK_HIP(hipMemcpyAsync(w.r, v0->rank, v0->nnz * sizeof(u64), hipMemcpyDeviceToDevice, P->stream));
         SFCI_CHECK_HIP(hipMemcpyAsync(w.a, v0->amp, v0->nnz * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
         hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, w.nnz, (u64)v0->nnz);
+        launch_normalise(P, w.a, w.nnz, cap, det);
+    } else {
+        DVec w = W(0);
+        launch_set_u64(P, rcnt + 2 * SFCI_MAX_ROOTS, v0->nnz);
+        launch_scatter_set(P, P->d_D, v0->rank, v0->amp, rcnt + 2 * SFCI_MAX_ROOTS, v0->nnz);
+        project_dense();
+        CandSrc src{};
+        src.dense = P->d_D;
+        select_topm(P, src, o->M, w.r, w.a, w.nnz, true);
         launch_normalise(P, w.a, w.nnz, cap, det);
     }
     u64 sigma_calls = 0;
@@ -473,6 +540,18 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
                 dense_sigma(P, sl, o->dedup, (unsigned long long*)(sc + 32), o->screen_eps);
                 tsig.end(P->stream);
             }
+            if (n_roots > 0) {
+                // H P w_j = H w_j - sum_i c_i H Psi_i, c_i = <Psi_i|w_j>/q_i; then P
+                for (int i = 0; i < n_roots; ++i) {
+                    launch_dot_sparse(P, roots[i].rank, roots[i].amp, rcnt + i, roots[i].nnz, wj.r, wj.a, wj.nnz,
+                                      rsc + 3 * i + 1, nullptr, det);
+                    hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, P->stream, rsc + 3 * i + 1, rsc + 3 * i,
+                                       rsc + 3 * i + 2);
+                    launch_axpy_scatter(P, P->d_D, (const u64*)P->ws_hroot_r[i].p, (const double*)P->ws_hroot_a[i].p,
+                                        rcnt + SFCI_MAX_ROOTS + i, hcap[i], rsc + 3 * i + 2, -1.0);
+                }
+                project_dense();
+            }
             ++sigma_calls;
             for (int l = 0; l <= j; ++l) {
                 DVec wl = W(l);
@@ -499,6 +578,7 @@ sfci_status sfci_lanczos(sfci_problem* P, const sfci_svec* v0, const sfci_lanczo
             DVec wj = W(j);
             launch_axpy_scatter(P, P->d_D, wj.r, wj.a, wj.nnz, cap, xd + j, +1.0);
         }
+        if (n_roots > 0) project_dense();
         CandSrc src{};
         src.dense = P->d_D;
         if (b + 1 < nblk) {

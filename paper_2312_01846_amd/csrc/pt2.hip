@@ -86,8 +86,8 @@ unsigned grid_of(u64 n) {
 
 // H Psi as a rank-sorted list: the sort path (deterministic, or when the
 // N_det array does not fit) or the dense tile kernel compacted in rank order.
-static u64 sigma_full_list(sfci_problem* P, const SigmaLaunch& sl, bool det, u64* emitted, u64** yr, double** ya,
-                           u64* cnt_dev) {
+u64 sigma_full_list(sfci_problem* P, const SigmaLaunch& sl, bool det, u64* emitted, u64** yr, double** ya,
+                    u64* cnt_dev) {
     if (det || !ensure_dense(P)) {
         const u64 n = sigma_list_full(P, sl, emitted, yr, ya);
         launch_set_u64(P, cnt_dev, n);

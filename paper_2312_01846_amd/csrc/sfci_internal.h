@@ -108,6 +108,8 @@ struct sfci_problem {
     RowTileGradWs grad_ws;
     ListWs list_ws;
     RowPassWs rowpass_ws;
+    // projected roots of the excited-state iteration: H Psi_i lists and scalars
+    DevBuf ws_hroot_r[SFCI_MAX_ROOTS], ws_hroot_a[SFCI_MAX_ROOTS], ws_roots_sc, ws_roots_cnt;
     bool borrowed = false;  // true for such a shadow: d_h, d_g, d_binom, d_D belong to another problem
 };
 
@@ -340,6 +342,13 @@ u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank,
 // sigma = H v in full through the sort path's passes, no N_det array: the
 // nonzero entries sorted by rank in list_ws.Rr / Ra; returns their number.
 u64 sigma_list_full(sfci_problem* P, const SigmaLaunch& v, u64* emitted_dev, u64** r, double** a);
+// H v in full as a rank-sorted list (zeros dropped): the sort path when
+// deterministic or when the N_det array does not fit, else the dense tile
+// kernel compacted in rank order (the accumulator is zero again afterwards).
+// The list lives in the problem's workspace until the next such call;
+// *cnt_dev receives its length, which is also returned.
+u64 sigma_full_list(sfci_problem* P, const SigmaLaunch& sl, bool det, u64* emitted, u64** yr, double** ya,
+                    u64* cnt_dev);
 // The basis and the per-block outputs the iteration writes (device).
 struct ListBasis {
     u64 cap;        // entries per basis vector

@@ -82,6 +82,9 @@ _SIGS = {
     "sfci_topm": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_uint64, C.c_int32, C.POINTER(SVec)]),
     "sfci_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(LanczosOpts), C.c_void_p, C.POINTER(SVec),
                                C.c_void_p, C.c_void_p, C.POINTER(LanczosStats)]),
+    "sfci_lanczos_roots": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(LanczosOpts), C.POINTER(SVec),
+                                     C.c_int32, C.c_void_p, C.POINTER(SVec), C.c_void_p, C.c_void_p,
+                                     C.POINTER(LanczosStats)]),
     "sfci_sigma_backward": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SVec), C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
     "sfci_pt2": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -261,7 +264,9 @@ class Problem:
 
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
-                want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False):
+                want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False, roots=None):
+        """roots: list of (ranks, amps) of previously found eigenvectors projected out
+        of the effective Hamiltonian (the iteration then finds the next state)."""
         torch = _torch()
         r = torch.as_tensor(ranks0, device="cuda").to(torch.int64).contiguous()
         a = torch.as_tensor(amps0, device="cuda").to(torch.float64).contiguous()
@@ -279,10 +284,20 @@ class Problem:
             p_r = torch.empty(cap, dtype=torch.int64, device="cuda")
             p_a = torch.empty(cap, dtype=torch.float64, device="cuda")
             psi = SVec(p_r.data_ptr(), p_a.data_ptr(), 0, cap)
-        rc = load_library().sfci_lanczos(self._h, C.byref(_svec(r, a)), C.byref(opts),
-                                         energies.ctypes.data_as(C.c_void_p), C.byref(psi) if psi else None,
-                                         T.ctypes.data_as(C.c_void_p) if want_T else None,
-                                         S.ctypes.data_as(C.c_void_p) if want_T else None, C.byref(st))
+        keep = []
+        rvecs = None
+        if roots:
+            rvecs = (SVec * len(roots))()
+            for i, (rr, ra) in enumerate(roots):
+                tr = torch.as_tensor(rr, device="cuda").to(torch.int64).contiguous()
+                ta = torch.as_tensor(ra, device="cuda").to(torch.float64).contiguous()
+                keep.append((tr, ta))
+                rvecs[i] = _svec(tr, ta)
+        rc = load_library().sfci_lanczos_roots(self._h, C.byref(_svec(r, a)), C.byref(opts), rvecs,
+                                               len(roots) if roots else 0, energies.ctypes.data_as(C.c_void_p),
+                                               C.byref(psi) if psi else None,
+                                               T.ctypes.data_as(C.c_void_p) if want_T else None,
+                                               S.ctypes.data_as(C.c_void_p) if want_T else None, C.byref(st))
         _check(rc)
         out = dict(energies=energies, stats=dict(sigma_calls=st.sigma_calls, terms_enumerated=st.terms_enumerated,
                                                  terms_emitted=st.terms_emitted, sigma_ms=st.sigma_ms,

@@ -74,7 +74,33 @@ def case_defs():
     }
 
 
+def excited_defs():
+    """name -> (ground-state case whose truncated Psi is the projected root, M, n_L, n_iter of the excited run)."""
+    return {"x4p_inst31_M3e3_20": ("c4p_inst31_M3e3_30", 3_000, 10, 20)}
+
+
+def run_excited(name):
+    base, M, nL, nit = excited_defs()[name]
+    build, Mg, nLg, nitg = case_defs()[base]
+    n, na, nb, h, g, start = build()
+    P = oracle.Problem(n, na, nb, h, g)
+    r0 = P.rank([s[0] for s in start], [s[1] for s in start])
+    a0 = np.array([s[2] for s in start])
+    order = np.argsort(r0, kind="stable")
+    ground = P.lanczos(r0[order], a0[order], Mg, nLg, nitg)
+    rr, ra = oracle.topm(ground["psi_rank"], ground["psi_amp"], Mg)
+    ra, _ = oracle.normalize(ra)
+    t = time.time()
+    out = P.lanczos(r0[order], a0[order], M, nL, nit, roots=[(rr, ra)])
+    dt = time.time() - t
+    return dict(energies=[float(x) for x in out["energies"]], psi_nnz=int(len(out["psi_rank"])),
+                psi_support_sha=_support_digest(out["psi_rank"]), M=M, n_L=nL, n_iter=nit, root_case=base,
+                ground_energy=float(ground["energies"][-1]), oracle_seconds=dt)
+
+
 def run(name):
+    if name in excited_defs():
+        return run_excited(name)
     build, M, nL, nit = case_defs()[name]
     n, na, nb, h, g, start = build()
     P = oracle.Problem(n, na, nb, h, g)
@@ -101,7 +127,7 @@ def main(argv):
     if argv[:1] == ["--out"]:
         out, argv = argv[1], argv[2:]
     data = json.load(open(out)) if os.path.exists(out) else {}
-    for nm in argv or list(case_defs()):
+    for nm in argv or list(case_defs()) + list(excited_defs()):
         print("running", nm, flush=True)
         data[nm] = run(nm)
         print(nm, data[nm], flush=True)
