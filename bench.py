@@ -65,6 +65,8 @@ def parse():
                     help="c4batch: keep the tile kernel's default work sizes")
     ap.add_argument("--pt2", action="store_true",
                     help="single-problem workloads: also time the Epstein-Nesbet correction of the start vector")
+    ap.add_argument("--excited", action="store_true",
+                    help="single-problem workloads: also time the iteration with the start vector projected out")
     ap.add_argument("--det", action="store_true",
                     help="single-problem workloads: deterministic mode (sort dedup, ordered sums)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -203,6 +205,18 @@ def main():
             pt2[mode] = dict(ms=(time.perf_counter() - t2) * 1e3, e0=e0, e2=e2, n_external=ne,
                              sigma_terms_per_s=int(v_r.numel()) * tps / (time.perf_counter() - t2))
         print(f"# pt2: {pt2}", file=sys.stderr, flush=True)
+    excited = None
+    if args.excited:
+        # the next state: the same iteration with the (truncated) start vector projected out
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        xo = P.lanczos(np.array([0], dtype=np.int64), np.array([1.0]), M=M, n_L=args.n_L, n_iter=args.steps,
+                       want_psi=False, dedup=args.dedup, deterministic=args.det, roots=[(v_r, v_a)])
+        torch.cuda.synchronize()
+        xs = time.perf_counter() - t3
+        excited = dict(ms_per_step=xs * 1e3 / args.steps, energies=[float(x) for x in xo["energies"]],
+                       ground_ms_per_step=wall * 1e3 / args.steps)
+        print(f"# excited: {excited}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(h, g, n, na, nb, v_r.cpu().numpy().astype(np.uint64), v_a.cpu().numpy(),
@@ -228,6 +242,7 @@ def main():
             "terms_per_step": terms / args.steps,
             "energies": [float(x) for x in out["energies"]],
             "pt2": pt2,
+            "excited": excited,
             "parallelism": "single GPU",
         },
         "roofline": {
