@@ -55,6 +55,8 @@ struct RTParams {
     double eps;                  // sigma: screening threshold (Sec. 3), 0 = off
     u64 item_base;               // items of this description start at this global item
     u64 row_base;                // D holds target rows from this alpha rank on
+    u32 tile_chunk;              // consecutive tiles of one row per work unit
+    u32 pad_chunk;
 };
 
 // One contributing source row of the current (target row, tile).
@@ -173,13 +175,19 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     __shared__ uint8_t occA[32], virA[32];
     __shared__ uint16_t pairNA[SFCI_MAX_PAIRS], pairVA[SFCI_MAX_PAIRS], pairNB[SFCI_MAX_PAIRS], pairVB[SFCI_MAX_PAIRS];
     __shared__ unsigned s_nbr, s_nlist, s_next, s_next2, s_touched, s_idb, s_ide;
-    __shared__ u64 s_item;
+    __shared__ u64 s_item, s_left;  // current item (row * ntiles + tile); tiles of its row still to do
     __shared__ int s_inst, s_cur;
+    // sigma with several tiles per row: the row's neighbour records, kept
+    // across its tiles (tile-independent parts; entry ranges refreshed per tile)
+    __shared__ u64 s_cache_row;
+    __shared__ int s_cache_inst;
+    __shared__ unsigned s_nrow;
     __shared__ RTParams p;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     WaveScratch& W = sw[wave];
-    NbrRec* list = (NbrRec*)nbr_scratch + (u64)blockIdx.x * nbr_cap;
+    NbrRec* list = (NbrRec*)nbr_scratch + (u64)blockIdx.x * 2 * nbr_cap;
+    NbrRec* rowlist = list + nbr_cap;
     const u64 total_items = item_prefix[n_inst];
     load_binom(sB, descs[0].binom);  // the binomial table is the same for every instance
     // gradient passes: per wavefront, an n^2 slab of (j, b) weights (first
@@ -188,18 +196,43 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     double* const wo = wslab + slab_n2;
     if (GRAD)
         for (u32 t = threadIdx.x; t < (u32)RT_WAVES * (slab_n2 + 32); t += RT_BLOCK) acc[slab_off + t] = 0.0;
-    if (threadIdx.x == 0) s_cur = -1;
+    if (threadIdx.x == 0) {
+        s_cur = -1;
+        s_left = 0;
+        s_cache_row = ~0ull;
+        s_cache_inst = -1;
+        s_nrow = 0;
+    }
     u64 my_terms = 0;
 
+    // The counter hands out target rows (item_prefix counts rows per
+    // instance); a workgroup then takes the row's tiles one after another.
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            const u64 it = atomicAdd(counter, 1u);
-            int k = 0;
-            if (it < total_items)
-                while (k + 1 < n_inst && item_prefix[k + 1] <= it) ++k;
-            s_item = it < total_items ? it - item_prefix[k] : ~0ull;
-            s_inst = k;
+            if (s_left > 0) {
+                s_item += 1;
+                s_left -= 1;
+            } else {
+                const u64 it = atomicAdd(counter, 1u);
+                int k = 0;
+                if (it < total_items)
+                    while (k + 1 < n_inst && item_prefix[k + 1] <= it) ++k;
+                s_item = ~0ull;
+                s_left = 0;
+                if (it < total_items) {
+                    // unit -> (row, chunk of tile_chunk tiles)
+                    const u64 nt = (u64)descs[k].ntiles, C = (u64)descs[k].tile_chunk;
+                    const u64 nch = (nt + C - 1) / C;
+                    const u64 u = it - item_prefix[k];
+                    const u64 row = u / nch, ch = u - row * nch;
+                    s_item = row * nt + ch * C;
+                    s_left = min(C, nt - ch * C) - 1;
+                }
+                s_inst = k;
+                s_nrow = 0;  // a new row: its records are built afresh
+                s_cache_row = ~0ull;
+            }
             s_nbr = 0;
             s_nlist = 0;
             s_next = 0;
@@ -265,7 +298,36 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         __syncthreads();
 
         // Phase 1: the nonempty source rows, with their entry range in this tile.
+        const bool multi = !GRAD && p.ntiles > 1;
+        const bool cached = multi && s_cache_row == rAt && s_cache_inst == s_inst;
+        if (cached) {
+            // the row's records from its first tile: refresh the entry ranges
+            const unsigned nrow = s_nrow;
+            for (unsigned b0 = 0; b0 < nrow; b0 += RT_BLOCK) {
+                const unsigned t = b0 + threadIdx.x;
+                NbrRec r;
+                r.type = 255;
+                if (t < nrow) {
+                    r = rowlist[t];
+                    const u32* tb = p.rtb + (u64)r.rAs * (u64)(p.ntiles + 1);
+                    r.e0 = tb[tile];
+                    r.e1 = tb[tile + 1];
+                    if (r.type == 0) {
+                        s_idb = r.rowb;
+                        s_ide = r.rowe;
+                    }
+                    if (r.type == 2 && r.e1 <= r.e0) r.type = 255;
+                }
+                const bool keep = r.type != 255;
+                const u64 m = __ballot(keep);
+                unsigned slot0 = 0;
+                if (lane == 0 && m) slot0 = atomicAdd(&s_nlist, (unsigned)__popcll(m));
+                slot0 = __shfl(slot0, 0);
+                if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
+            }
+        }
         for (;;) {
+            if (cached) break;
             unsigned base = 0;
             if (lane == 0) base = atomicAdd(&s_nbr, 64u);
             base = __shfl(base, 0);
@@ -273,6 +335,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             const u64 idx = (u64)base + lane;
             NbrRec r;
             r.type = 255;
+            bool row_ok = false;  // nonempty source row with a usable element (tile aside)
             if (idx < n_nbr) {
                 int i = 0, a = 0, j = 0, b = 0, type;
                 u32 As;
@@ -303,6 +366,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     s_ide = (u32)re;
                 }
                 if (re > rb) {
+                    row_ok = true;
                     const u32* tb = p.rtb + rAs * (u64)(p.ntiles + 1);
                     r.As = As; r.rAs = (u32)rAs; r.rowb = (u32)rb; r.rowe = (u32)re;
                     r.e0 = tb[tile]; r.e1 = tb[tile + 1];
@@ -319,7 +383,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             double e = (p.I.G(i, a, j, b) - p.I.G(i, b, j, a));
                             if (par) e = -e;
                             r.cst = e;
-                            if (e == 0.0) r.type = 255;
+                            if (e == 0.0) {
+                                r.type = 255;
+                                row_ok = false;
+                            }
                         }
                         // (a gradient pass keeps zero elements: their derivative need not vanish)
                         if (r.e1 <= r.e0) r.type = 255;
@@ -340,12 +407,32 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     }
                 }
             }
+            if (multi) {
+                // keep every record that survives the row-level filters for the row's later tiles
+                // (in sigma mode only alpha doubles are ever dropped for a tile alone)
+                const u64 mr = __ballot(row_ok);
+                unsigned rs0 = 0;
+                if (lane == 0 && mr) rs0 = atomicAdd(&s_nrow, (unsigned)__popcll(mr));
+                rs0 = __shfl(rs0, 0);
+                if (row_ok) {
+                    NbrRec rr = r;
+                    if (rr.type == 255) rr.type = 2;
+                    rowlist[rs0 + __popcll(mr & ((1ull << lane) - 1ull))] = rr;
+                }
+            }
             const bool keep = r.type != 255;
             const u64 m = __ballot(keep);
             unsigned slot0 = 0;
             if (lane == 0 && m) slot0 = atomicAdd(&s_nlist, (unsigned)__popcll(m));
             slot0 = __shfl(slot0, 0);
             if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
+        }
+        if (multi && !cached) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_cache_row = rAt;
+                s_cache_inst = s_inst;
+            }
         }
         if (!GRAD && threadIdx.x == RT_BLOCK - 1) {
             // the alpha h_pp of the diagonal, summed from zero in ascending order
@@ -946,8 +1033,20 @@ u64 binom_u64(int a, int b) {
 
 static unsigned rt_itab_doubles(unsigned n2) { return (2 * n2 + 40 + 1) & ~1u; }
 
+// The tile kernels' static LDS, as compiled (the largest of the three), so
+// that static + dynamic LDS never exceeds what a workgroup may hold.
 static size_t rt_static_lds() {
-    return sizeof(BinomLds) + RT_WAVES * sizeof(WaveScratch) + 64 + 4 * SFCI_MAX_PAIRS * 2 + sizeof(RTParams) + 64;
+    static size_t cached = 0;
+    if (cached == 0) {
+        size_t mx = 0;
+        for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b}) {
+            hipFuncAttributes attr{};
+            SFCI_CHECK_HIP(hipFuncGetAttributes(&attr, f));
+            mx = std::max(mx, (size_t)attr.sharedSizeBytes);
+        }
+        cached = mx + 64;  // a cache line of margin
+    }
+    return cached;
 }
 
 struct RowTileState {
@@ -1128,7 +1227,14 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.item_base = 0;
     rp.row_base = 0;
     const int na = P->na, nva = P->n - P->na;
-    out.n_items = P->Na * (u64)S->ntiles;
+    // work units: chunks of up to tile_chunk consecutive tiles of one target
+    // row (a workgroup walks a chunk's tiles in turn, reusing the row's
+    // neighbour records); SFCI_TILE_CHUNK overrides the default
+    unsigned chunk = 2;  // measured at 28 orbitals: 1, 2, 4, 7, 28 tiles -> 9.8, 9.0, 9.3, 10.7, 21.8 s
+    if (const char* env = getenv("SFCI_TILE_CHUNK")) chunk = (unsigned)std::max(1, atoi(env));
+    rp.tile_chunk = std::min<unsigned>(chunk, (unsigned)S->ntiles);
+    rp.pad_chunk = 0;
+    out.n_items = P->Na * (u64)((S->ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
     out.lds_bytes = S->lds_bytes;
     out.n2 = (unsigned)(P->n * P->n);
@@ -1177,7 +1283,7 @@ unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned pe
     return (unsigned)std::min<u64>(std::max<u64>(1, total_items), (u64)num_cu * per_cu);
 }
 
-size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid * nbr_cap * sizeof(NbrRec); }
+size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid * 2 * nbr_cap * sizeof(NbrRec); }
 
 void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps) {
     RowTileDesc d = rowtile_prepare(P, v, D, emitted, eps);
@@ -1199,7 +1305,7 @@ void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, 
     rp.item_base = lo * (u64)rp.ntiles;
     rp.row_base = lo;
     rp.D = Dp;
-    d.n_items = (hi - lo) * (u64)rp.ntiles;
+    d.n_items = (hi - lo) * (u64)((rp.ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     char* buf = (char*)P->ws_rt_desc.get(sizeof(RTParams) + 64);
     u64 prefix[2] = {0, d.n_items};
     SFCI_CHECK_HIP(hipMemcpyAsync(buf, d.raw, sizeof(RTParams), hipMemcpyHostToDevice, P->stream));
