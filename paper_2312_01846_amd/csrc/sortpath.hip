@@ -37,48 +37,101 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys
     hist[(u64)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// One stable LSD pass.  Wavefront w of a block ranks the contiguous quarter
+// [w * RS_TILE/4, (w+1) * RS_TILE/4) of the block's tile on its own (64
+// entries at a time, digit peers from ballots, running per-digit counts in
+// its own LDS row: no block barrier), the block then orders the tile by digit
+// in LDS (wavefront order = tile order, so the pass is stable) and writes
+// every digit's run to its global slot as one contiguous stretch.  offs holds
+// the exclusive prefix of the (digit, block) counts, digit-major.
 template <class K>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ keys, const double* __restrict__ vals,
                                                          u64 n, int shift, const u64* __restrict__ offs, u64 nblk,
                                                          K* __restrict__ ko, double* __restrict__ vo) {
-    __shared__ u64 run[RS_BINS];
-    __shared__ unsigned wc[RS_BLOCK / 64][RS_BINS];
+    constexpr int NW = RS_BLOCK / 64;
+    constexpr int PER_WAVE = RS_TILE / NW;  // entries per wavefront
+    __shared__ K sk[RS_TILE];
+    __shared__ double sv[RS_TILE];
+    __shared__ u64 gstart[RS_BINS];
+    __shared__ unsigned lstart[RS_BINS];
+    __shared__ unsigned wcnt[NW][RS_BINS];
+    __shared__ unsigned wsum[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[(u64)threadIdx.x * nblk + blockIdx.x];
-    for (int w = 0; w < RS_BLOCK / 64; ++w) wc[w][threadIdx.x] = 0;
-    __syncthreads();
     const u64 base = (u64)blockIdx.x * RS_TILE;
-    for (int k = 0; k < RS_ITEMS; ++k) {
-        u64 i = base + (u64)k * RS_BLOCK + threadIdx.x;
-        bool valid = i < n;
-        K key = valid ? keys[i] : (K)0;
-        double val = valid ? vals[i] : 0.0;
-        unsigned d = (unsigned)((key >> shift) & (RS_BINS - 1));
+    for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
+    {
+        // this block's count of digit d from the scanned offsets, and the
+        // block-local start of every digit
+        const unsigned d = threadIdx.x;
+        const u64 at = (u64)d * nblk + blockIdx.x;
+        const u64 g = offs[at];
+        const u64 nx = (at + 1 < (u64)RS_BINS * nblk) ? offs[at + 1] : n;
+        gstart[d] = g;
+        const unsigned cnt = (unsigned)(nx - g);
+        unsigned x = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        unsigned before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        lstart[d] = before + x - cnt;
+    }
+    // ranks inside this wavefront's quarter
+    K key[PER_WAVE / 64];
+    double val[PER_WAVE / 64];
+    unsigned dig[PER_WAVE / 64], loc[PER_WAVE / 64];
+    const u64 wbase = base + (u64)wave * PER_WAVE;
+#pragma unroll
+    for (int k = 0; k < PER_WAVE / 64; ++k) {
+        const u64 i = wbase + (u64)k * 64 + lane;
+        const bool valid = i < n;
+        key[k] = valid ? keys[i] : (K)0;
+        val[k] = valid ? vals[i] : 0.0;
+        const unsigned d = (unsigned)((key[k] >> shift) & (RS_BINS - 1));
+        dig[k] = valid ? d : 0xffffffffu;
         u64 peers = __ballot(valid);
         for (int b = 0; b < RS_BITS; ++b) {
-            u64 m = __ballot((d >> b) & 1u);
+            const u64 m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
-        unsigned rank = (unsigned)__popcll(peers & ((1ull << lane) - 1ull));
-        if (valid && rank == 0) wc[wave][d] = (unsigned)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            u64 pos = run[d];
-            for (int w = 0; w < wave; ++w) pos += wc[w][d];
-            pos += rank;
-            ko[pos] = key;
-            vo[pos] = val;
+        const unsigned rank = (unsigned)__popcll(peers & ((1ull << lane) - 1ull));
+        loc[k] = valid ? wcnt[wave][d] + rank : 0u;
+        wave_sync();
+        if (valid && rank == 0) wcnt[wave][d] += (unsigned)__popcll(peers);
+        wave_sync();
+    }
+    __syncthreads();
+    {
+        // wcnt[w][d] becomes the tile position of wavefront w's first digit-d
+        // entry: lower wavefronts first, then this one's order
+        const unsigned d = threadIdx.x;
+        unsigned run = lstart[d];
+        for (int w = 0; w < NW; ++w) {
+            const unsigned c = wcnt[w][d];
+            wcnt[w][d] = run;
+            run += c;
         }
-        __syncthreads();
-        {
-            unsigned add = 0;
-            for (int w = 0; w < RS_BLOCK / 64; ++w) {
-                add += wc[w][threadIdx.x];
-                wc[w][threadIdx.x] = 0;
-            }
-            run[threadIdx.x] += add;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER_WAVE / 64; ++k) {
+        const unsigned d = dig[k];
+        if (d == 0xffffffffu) continue;
+        const unsigned pos = wcnt[wave][d] + loc[k];
+        sk[pos] = key[k];
+        sv[pos] = val[k];
+    }
+    __syncthreads();
+    const u64 cnt = (n - base < RS_TILE) ? (n - base) : RS_TILE;
+    for (u64 t = threadIdx.x; t < cnt; t += RS_BLOCK) {
+        const K kk = sk[t];
+        const unsigned d = (unsigned)((kk >> shift) & (RS_BINS - 1));
+        const u64 gpos = gstart[d] + (t - lstart[d]);
+        ko[gpos] = kk;
+        vo[gpos] = sv[t];
     }
 }
 
