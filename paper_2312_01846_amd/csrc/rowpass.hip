@@ -431,18 +431,21 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
     const unsigned cgrid = (unsigned)std::max<u64>(1, std::min<u64>((Na + RP_WPB - 1) / RP_WPB, (u64)P->num_cu * 16));
     hipLaunchKernelGGL(k_rp_count, dim3(cgrid), dim3(RP_BLOCK), 0, P->stream, c, cnt, np);
     SFCI_CHECK_HIP(hipGetLastError());
-    std::vector<u64> hc(Na), htp(Na + 1), hpp(Na + 1);
+    std::vector<u64> hc(Na), htp(Na + 1), hpp(Na + 1), htt(Na + 1);
     std::vector<u32> hn(Na);
     SFCI_CHECK_HIP(hipMemcpyAsync(hc.data(), cnt, Na * sizeof(u64), hipMemcpyDeviceToHost, P->stream));
     SFCI_CHECK_HIP(hipMemcpyAsync(hn.data(), np, Na * sizeof(u32), hipMemcpyDeviceToHost, P->stream));
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
-    htp[0] = hpp[0] = 0;
+    htp[0] = hpp[0] = htt[0] = 0;
     for (u64 r = 0; r < Na; ++r) {
         htp[r + 1] = htp[r] + hc[r];
         hpp[r + 1] = hpp[r] + hn[r];
+        htt[r + 1] = htt[r] + (hc[r] + SFCI_SORT_TILE - 1) / SFCI_SORT_TILE;
     }
+    u64* ttile = (u64*)ws.tile_pre.get((Na + 1) * sizeof(u64));
     SFCI_CHECK_HIP(hipMemcpyAsync(tpre, htp.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
     SFCI_CHECK_HIP(hipMemcpyAsync(ppre, hpp.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
+    SFCI_CHECK_HIP(hipMemcpyAsync(ttile, htt.data(), (Na + 1) * sizeof(u64), hipMemcpyHostToDevice, P->stream));
 
     const u64 pair_cap = 1ull << 26;
     // pass-local keys (target row within the pass) * N_beta + beta rank fit 32 bits
@@ -472,7 +475,10 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
             SFCI_CHECK_HIP(hipGetLastError());
             u32* ks;
             double* vs;
-            radix_sort_pairs(P, k1, v1, k2, v2, tuples, key_bits((hi - lo) * Nb - 1), &ks, &vs);
+            // tuples sit grouped by target row: only the beta rank is sorted
+            const u64 ntiles = htt[hi] - htt[lo];
+            u32* tile_row = (u32*)ws.tile_row.get(ntiles * sizeof(u32));
+            radix_sort_rows(P, k1, v1, k2, v2, tuples, tpre, ttile, lo, hi, ntiles, tile_row, &ks, &vs);
             SortPassOut out = sink.begin(lo, hi, tuples);
             segmented_sum_append(P, ks, vs, tuples, lo * Nb, eps, out.base_dev, out.cap, out.r, out.a);
             sink.end(lo, hi);

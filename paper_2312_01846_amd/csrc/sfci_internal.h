@@ -67,9 +67,10 @@ struct KeyGeom {
 
 // Buffers of the target-row-driven sort-path emission (rowpass.hip).
 struct RowPassWs {
-    DevBuf beg, end, cnt, npair, tup_pre, pair_pre, pairs, scal;
+    DevBuf beg, end, cnt, npair, tup_pre, pair_pre, pairs, scal, tile_pre, tile_row;
     void release() {
-        for (DevBuf* b : {&beg, &end, &cnt, &npair, &tup_pre, &pair_pre, &pairs, &scal}) b->release();
+        for (DevBuf* b : {&beg, &end, &cnt, &npair, &tup_pre, &pair_pre, &pairs, &scal, &tile_pre, &tile_row})
+            b->release();
     }
 };
 
@@ -261,6 +262,15 @@ template <class K>
 void radix_sort_pairs(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, int kbits, K** k_out,
                       double** v_out);
 int key_bits(u64 maxval);
+// Entries per radix-sort tile.
+constexpr u64 SFCI_SORT_TILE = 4096;
+// Stable sort of pass-local keys (target row - lo) * N_beta + beta rank whose
+// entries are already grouped by target row in ascending row order: only the
+// beta rank is sorted, inside each row.  tpre / ttile hold the entries and the
+// tiles (ceil(entries / SFCI_SORT_TILE)) before every row of the space,
+// ntiles = ttile[hi] - ttile[lo]; tile_row has room for ntiles entries.
+void radix_sort_rows(sfci_problem* P, u32* k1, double* v1, u32* k2, double* v2, u64 n, const u64* tpre,
+                     const u64* ttile, u64 lo, u64 hi, u64 ntiles, u32* tile_row, u32** k_out, double** v_out);
 template <class K>
 void segmented_sum_append(sfci_problem* P, const K* keys, const double* vals, u64 n, u64 key_base, double eps,
                           u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a);

@@ -22,19 +22,72 @@ constexpr u64 RS_TILE = (u64)RS_BLOCK * RS_ITEMS;
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
 
+static_assert(RS_TILE == SFCI_SORT_TILE, "sort tile");
+
+// Where block b's tile lies.  Plain sort: tiles of RS_TILE entries, the
+// (digit, block) counts digit-major over all blocks.  Row-segmented sort
+// (the input is already grouped by target row, rows in ascending order):
+// tiles never cross a row, every row's counts are laid out digit-major over
+// the row's own tiles, rows one after another, so one exclusive scan gives
+// every (row, digit, tile) its output position; the digits are those of the
+// key minus the row's first key, i.e. of the beta rank alone.
+struct SortTiles {
+    const u32* tile_row;  // nullptr: plain sort; else each tile's target row
+    const u64* tpre;      // entries before each row (rows of the whole space)
+    const u64* ttile;     // tiles before each row
+    u64 lo;               // the pass's first row
+    u64 Nb;               // keys per row
+};
+
+struct TileInfo {
+    u64 base, len;  // the tile's entries
+    u64 hb, hs;     // count of digit d at hist[hb + d * hs]
+    u64 kbase;      // subtracted from the keys before the digits are taken
+};
+
+__device__ __forceinline__ TileInfo tile_info(const SortTiles& st, u64 n, u64 nblk, u64 b) {
+    TileInfo t;
+    if (!st.tile_row) {
+        t.base = b * RS_TILE;
+        t.len = (n - t.base < RS_TILE) ? (n - t.base) : RS_TILE;
+        t.hb = b;
+        t.hs = nblk;
+        t.kbase = 0;
+        return t;
+    }
+    const u64 R = st.tile_row[b];
+    const u64 t0 = st.ttile[R] - st.ttile[st.lo];
+    const u64 it = b - t0;
+    const u64 rlen = st.tpre[R + 1] - st.tpre[R];
+    t.base = st.tpre[R] - st.tpre[st.lo] + it * RS_TILE;
+    t.len = (rlen - it * RS_TILE < RS_TILE) ? (rlen - it * RS_TILE) : RS_TILE;
+    t.hb = t0 * RS_BINS + it;
+    t.hs = st.ttile[R + 1] - st.ttile[R];
+    t.kbase = (R - st.lo) * st.Nb;
+    return t;
+}
+
 template <class K>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys, u64 n, int shift,
-                                                      u64* __restrict__ hist, u64 nblk) {
+                                                      u64* __restrict__ hist, u64 nblk, SortTiles st) {
     __shared__ unsigned h[RS_BINS];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const u64 base = (u64)blockIdx.x * RS_TILE;
+    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x);
+    const K kb = (K)ti.kbase;
     for (int k = 0; k < RS_ITEMS; ++k) {
-        u64 i = base + (u64)k * RS_BLOCK + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RS_BINS - 1)], 1u);
+        const u64 i = (u64)k * RS_BLOCK + threadIdx.x;
+        if (i < ti.len) atomicAdd(&h[((keys[ti.base + i] - kb) >> shift) & (RS_BINS - 1)], 1u);
     }
     __syncthreads();
-    hist[(u64)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    hist[ti.hb + (u64)threadIdx.x * ti.hs] = h[threadIdx.x];
+}
+
+// Rows [lo, hi) of the pass: every tile records its row.
+__global__ void k_rs_tile_rows(const u64* __restrict__ ttile, u64 lo, u64 hi, u32* __restrict__ tile_row) {
+    const u64 r = lo + (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= hi) return;
+    for (u64 t = ttile[r]; t < ttile[r + 1]; ++t) tile_row[t - ttile[lo]] = (u32)r;
 }
 
 // One stable LSD pass.  Wavefront w of a block ranks the contiguous quarter
@@ -43,11 +96,12 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys
 // its own LDS row: no block barrier), the block then orders the tile by digit
 // in LDS (wavefront order = tile order, so the pass is stable) and writes
 // every digit's run to its global slot as one contiguous stretch.  offs holds
-// the exclusive prefix of the (digit, block) counts, digit-major.
+// the exclusive prefix of the counts in the layout tile_info describes.
 template <class K>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ keys, const double* __restrict__ vals,
                                                          u64 n, int shift, const u64* __restrict__ offs, u64 nblk,
-                                                         K* __restrict__ ko, double* __restrict__ vo) {
+                                                         SortTiles st, K* __restrict__ ko,
+                                                         double* __restrict__ vo) {
     constexpr int NW = RS_BLOCK / 64;
     constexpr int PER_WAVE = RS_TILE / NW;  // entries per wavefront
     __shared__ K sk[RS_TILE];
@@ -57,40 +111,23 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
     __shared__ unsigned wcnt[NW][RS_BINS];
     __shared__ unsigned wsum[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const u64 base = (u64)blockIdx.x * RS_TILE;
+    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x);
+    const K kb = (K)ti.kbase;
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
-    {
-        // this block's count of digit d from the scanned offsets, and the
-        // block-local start of every digit
-        const unsigned d = threadIdx.x;
-        const u64 at = (u64)d * nblk + blockIdx.x;
-        const u64 g = offs[at];
-        const u64 nx = (at + 1 < (u64)RS_BINS * nblk) ? offs[at + 1] : n;
-        gstart[d] = g;
-        const unsigned cnt = (unsigned)(nx - g);
-        unsigned x = cnt;
-        for (int off = 1; off < 64; off <<= 1) {
-            const unsigned y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        unsigned before = 0;
-        for (int w = 0; w < wave; ++w) before += wsum[w];
-        lstart[d] = before + x - cnt;
-    }
+    gstart[threadIdx.x] = offs[ti.hb + (u64)threadIdx.x * ti.hs];
+    __syncthreads();
     // ranks inside this wavefront's quarter
     K key[PER_WAVE / 64];
     double val[PER_WAVE / 64];
     unsigned dig[PER_WAVE / 64], loc[PER_WAVE / 64];
-    const u64 wbase = base + (u64)wave * PER_WAVE;
+    const u64 wbase = (u64)wave * PER_WAVE;
 #pragma unroll
     for (int k = 0; k < PER_WAVE / 64; ++k) {
         const u64 i = wbase + (u64)k * 64 + lane;
-        const bool valid = i < n;
-        key[k] = valid ? keys[i] : (K)0;
-        val[k] = valid ? vals[i] : 0.0;
-        const unsigned d = (unsigned)((key[k] >> shift) & (RS_BINS - 1));
+        const bool valid = i < ti.len;
+        key[k] = valid ? keys[ti.base + i] : (K)0;
+        val[k] = valid ? vals[ti.base + i] : 0.0;
+        const unsigned d = (unsigned)(((key[k] - kb) >> shift) & (RS_BINS - 1));
         dig[k] = valid ? d : 0xffffffffu;
         u64 peers = __ballot(valid);
         for (int b = 0; b < RS_BITS; ++b) {
@@ -105,10 +142,22 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
     }
     __syncthreads();
     {
-        // wcnt[w][d] becomes the tile position of wavefront w's first digit-d
-        // entry: lower wavefronts first, then this one's order
+        // block-local start of every digit, then wcnt[w][d] becomes the tile
+        // position of wavefront w's first digit-d entry: lower wavefronts
+        // first, then this one's order
         const unsigned d = threadIdx.x;
-        unsigned run = lstart[d];
+        unsigned cnt = 0;
+        for (int w = 0; w < NW; ++w) cnt += wcnt[w][d];
+        unsigned x = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        unsigned run = x - cnt;
+        for (int w = 0; w < wave; ++w) run += wsum[w];
+        lstart[d] = run;
         for (int w = 0; w < NW; ++w) {
             const unsigned c = wcnt[w][d];
             wcnt[w][d] = run;
@@ -125,10 +174,9 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
         sv[pos] = val[k];
     }
     __syncthreads();
-    const u64 cnt = (n - base < RS_TILE) ? (n - base) : RS_TILE;
-    for (u64 t = threadIdx.x; t < cnt; t += RS_BLOCK) {
+    for (u64 t = threadIdx.x; t < ti.len; t += RS_BLOCK) {
         const K kk = sk[t];
-        const unsigned d = (unsigned)((kk >> shift) & (RS_BINS - 1));
+        const unsigned d = (unsigned)(((kk - kb) >> shift) & (RS_BINS - 1));
         const u64 gpos = gstart[d] + (t - lstart[d]);
         ko[gpos] = kk;
         vo[gpos] = sv[t];
@@ -250,29 +298,47 @@ int bits_for(u64 maxval) {
 // Stable LSD radix sort of (keys, vals) on the low kbits of the key; the
 // result ends in (*k_out, *v_out), which is one of the two buffer pairs.
 template <class K>
-void radix_sort_pairs(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, int kbits, K** k_out,
-                      double** v_out) {
-    if (n > 0) {
-        const u64 nblk = (n + RS_TILE - 1) / RS_TILE;
-        u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
-        for (int shift = 0; shift < kbits; shift += RS_BITS) {
-            hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
-                               nblk);
-            exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
-            hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
-                               hist, nblk, k2, v2);
-            std::swap(k1, k2);
-            std::swap(v1, v2);
-        }
-        SFCI_CHECK_HIP(hipGetLastError());
+void radix_passes(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, u64 nblk, int kbits,
+                  const SortTiles& st, K** k_out, double** v_out) {
+    u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
+    for (int shift = 0; shift < kbits; shift += RS_BITS) {
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
+                           nblk, st);
+        exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
+                           hist, nblk, st, k2, v2);
+        std::swap(k1, k2);
+        std::swap(v1, v2);
     }
+    SFCI_CHECK_HIP(hipGetLastError());
     *k_out = k1;
     *v_out = v1;
+}
+
+template <class K>
+void radix_sort_pairs(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, int kbits, K** k_out,
+                      double** v_out) {
+    *k_out = k1;
+    *v_out = v1;
+    if (n == 0) return;
+    radix_passes(P, k1, v1, k2, v2, n, (n + RS_TILE - 1) / RS_TILE, kbits, SortTiles{}, k_out, v_out);
 }
 template void radix_sort_pairs<u64>(sfci_problem*, u64*, double*, u64*, double*, u64, int, u64**, double**);
 template void radix_sort_pairs<u32>(sfci_problem*, u32*, double*, u32*, double*, u64, int, u32**, double**);
 
 int key_bits(u64 maxval) { return bits_for(maxval); }
+
+void radix_sort_rows(sfci_problem* P, u32* k1, double* v1, u32* k2, double* v2, u64 n, const u64* tpre,
+                     const u64* ttile, u64 lo, u64 hi, u64 ntiles, u32* tile_row, u32** k_out, double** v_out) {
+    *k_out = k1;
+    *v_out = v1;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_rs_tile_rows, dim3((unsigned)((hi - lo + 255) / 256)), dim3(256), 0, P->stream, ttile, lo,
+                       hi, tile_row);
+    const SortTiles st{tile_row, tpre, ttile, lo, P->Nb};
+    radix_passes(P, k1, v1, k2, v2, n, ntiles, bits_for(P->Nb - 1), st, k_out, v_out);
+}
+
 
 // Sum runs of equal keys of a key-sorted list in order and append the nonzero
 // sums (key + key_base, sum) at out[*out_base + ...]; *out_base += their
