@@ -24,8 +24,9 @@ constexpr int RS_BINS = 1 << RS_BITS;
 
 static_assert(RS_TILE == SFCI_SORT_TILE, "sort tile");
 
-// Where block b's tile lies.  Plain sort: tiles of RS_TILE entries, the
-// (digit, block) counts digit-major over all blocks.  Row-segmented sort
+// Where block b's tile lies (a pass's digits take nbins <= RS_BINS values).
+// Plain sort: tiles of RS_TILE entries, the (digit, block) counts
+// digit-major over all blocks.  Row-segmented sort
 // (the input is already grouped by target row, rows in ascending order):
 // tiles never cross a row, every row's counts are laid out digit-major over
 // the row's own tiles, rows one after another, so one exclusive scan gives
@@ -45,7 +46,7 @@ struct TileInfo {
     u64 kbase;      // subtracted from the keys before the digits are taken
 };
 
-__device__ __forceinline__ TileInfo tile_info(const SortTiles& st, u64 n, u64 nblk, u64 b) {
+__device__ __forceinline__ TileInfo tile_info(const SortTiles& st, u64 n, u64 nblk, u64 b, u64 nbins) {
     TileInfo t;
     if (!st.tile_row) {
         t.base = b * RS_TILE;
@@ -61,26 +62,28 @@ __device__ __forceinline__ TileInfo tile_info(const SortTiles& st, u64 n, u64 nb
     const u64 rlen = st.tpre[R + 1] - st.tpre[R];
     t.base = st.tpre[R] - st.tpre[st.lo] + it * RS_TILE;
     t.len = (rlen - it * RS_TILE < RS_TILE) ? (rlen - it * RS_TILE) : RS_TILE;
-    t.hb = t0 * RS_BINS + it;
+    t.hb = t0 * nbins + it;
     t.hs = st.ttile[R + 1] - st.ttile[R];
     t.kbase = (R - st.lo) * st.Nb;
     return t;
 }
 
 template <class K>
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys, u64 n, int shift,
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const K* __restrict__ keys, u64 n, int shift, int bits,
                                                       u64* __restrict__ hist, u64 nblk, SortTiles st) {
     __shared__ unsigned h[RS_BINS];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x);
+    const u64 nbins = 1ull << bits;
+    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x, nbins);
     const K kb = (K)ti.kbase;
+    const K mask = (K)(nbins - 1);
     for (int k = 0; k < RS_ITEMS; ++k) {
         const u64 i = (u64)k * RS_BLOCK + threadIdx.x;
-        if (i < ti.len) atomicAdd(&h[((keys[ti.base + i] - kb) >> shift) & (RS_BINS - 1)], 1u);
+        if (i < ti.len) atomicAdd(&h[((keys[ti.base + i] - kb) >> shift) & mask], 1u);
     }
     __syncthreads();
-    hist[ti.hb + (u64)threadIdx.x * ti.hs] = h[threadIdx.x];
+    if (threadIdx.x < nbins) hist[ti.hb + (u64)threadIdx.x * ti.hs] = h[threadIdx.x];
 }
 
 // Rows [lo, hi) of the pass: every tile records its row.
@@ -99,7 +102,8 @@ __global__ void k_rs_tile_rows(const u64* __restrict__ ttile, u64 lo, u64 hi, u3
 // the exclusive prefix of the counts in the layout tile_info describes.
 template <class K>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ keys, const double* __restrict__ vals,
-                                                         u64 n, int shift, const u64* __restrict__ offs, u64 nblk,
+                                                         u64 n, int shift, int bits, const u64* __restrict__ offs,
+                                                         u64 nblk,
                                                          SortTiles st, K* __restrict__ ko,
                                                          double* __restrict__ vo) {
     constexpr int NW = RS_BLOCK / 64;
@@ -111,10 +115,12 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
     __shared__ unsigned wcnt[NW][RS_BINS];
     __shared__ unsigned wsum[NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x);
+    const u64 nbins = 1ull << bits;
+    const TileInfo ti = tile_info(st, n, nblk, blockIdx.x, nbins);
     const K kb = (K)ti.kbase;
+    const K mask = (K)(nbins - 1);
     for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
-    gstart[threadIdx.x] = offs[ti.hb + (u64)threadIdx.x * ti.hs];
+    gstart[threadIdx.x] = (threadIdx.x < nbins) ? offs[ti.hb + (u64)threadIdx.x * ti.hs] : 0;
     __syncthreads();
     // ranks inside this wavefront's quarter
     K key[PER_WAVE / 64];
@@ -127,10 +133,10 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
         const bool valid = i < ti.len;
         key[k] = valid ? keys[ti.base + i] : (K)0;
         val[k] = valid ? vals[ti.base + i] : 0.0;
-        const unsigned d = (unsigned)(((key[k] - kb) >> shift) & (RS_BINS - 1));
+        const unsigned d = (unsigned)(((key[k] - kb) >> shift) & mask);
         dig[k] = valid ? d : 0xffffffffu;
         u64 peers = __ballot(valid);
-        for (int b = 0; b < RS_BITS; ++b) {
+        for (int b = 0; b < bits; ++b) {
             const u64 m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
     __syncthreads();
     for (u64 t = threadIdx.x; t < ti.len; t += RS_BLOCK) {
         const K kk = sk[t];
-        const unsigned d = (unsigned)(((kk - kb) >> shift) & (RS_BINS - 1));
+        const unsigned d = (unsigned)(((kk - kb) >> shift) & mask);
         const u64 gpos = gstart[d] + (t - lstart[d]);
         ko[gpos] = kk;
         vo[gpos] = sv[t];
@@ -300,13 +306,19 @@ int bits_for(u64 maxval) {
 template <class K>
 void radix_passes(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, u64 nblk, int kbits,
                   const SortTiles& st, K** k_out, double** v_out) {
+    // the key bits split evenly over the fewest passes of at most RS_BITS:
+    // longer digit runs per tile and fewer counts to scan than full digits
+    const int npass = (kbits + RS_BITS - 1) / RS_BITS;
     u64* hist = (u64*)P->ws_hist.get((u64)RS_BINS * nblk * sizeof(u64));
-    for (int shift = 0; shift < kbits; shift += RS_BITS) {
-        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, hist,
-                           nblk, st);
-        exclusive_scan_u64(P, hist, hist, (u64)RS_BINS * nblk, nullptr);
+    for (int p = 0, shift = 0; p < npass; ++p) {
+        const int bits = (kbits - shift + (npass - p) - 1) / (npass - p);
+        const u64 nbins = 1ull << bits;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, bits,
+                           hist, nblk, st);
+        exclusive_scan_u64(P, hist, hist, nbins * nblk, nullptr);
         hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
-                           hist, nblk, st, k2, v2);
+                           bits, hist, nblk, st, k2, v2);
+        shift += bits;
         std::swap(k1, k2);
         std::swap(v1, v2);
     }

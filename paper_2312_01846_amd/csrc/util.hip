@@ -14,69 +14,100 @@ __global__ void k_fill_u64(u64* __restrict__ p, u64 n, u64 v) {
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr u64 SCAN_TILE = (u64)SCAN_BLOCK * SCAN_ITEMS;
+constexpr int TOP_BLOCK = 1024;
 
-// Block-wide inclusive scan of one value per thread (256 threads).
-__device__ u64 block_incl_scan(u64 x, u64* sh) {
-    const int t = threadIdx.x;
-    sh[t] = x;
-    __syncthreads();
-    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-        u64 y = (t >= off) ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += y;
-        __syncthreads();
+__device__ __forceinline__ u64 shfl_up_u64(u64 x, int off) { return (u64)__shfl_up((long long)x, off); }
+__device__ __forceinline__ u64 shfl_xor_u64(u64 x, int off) { return (u64)__shfl_xor((long long)x, off); }
+
+// Exclusive scan of one value per thread over a block of NT threads (wavefront
+// scans, then the wavefront totals); *total receives the block's sum.  sh
+// holds NT / 64 entries.
+template <int NT>
+__device__ __forceinline__ u64 block_excl_scan(u64 x, u64* sh, u64* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u64 inc = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const u64 y = shfl_up_u64(inc, off);
+        if (lane >= off) inc += y;
     }
-    u64 r = sh[t];
+    if (lane == 63) sh[w] = inc;
     __syncthreads();
-    return r;
+    u64 pre = 0, tot = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+        const u64 v = sh[k];
+        if (k < w) pre += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - x;
 }
 
-__global__ void k_scan_reduce(const u64* __restrict__ in, u64 n, u64* __restrict__ bsum) {
-    __shared__ u64 sh[SCAN_BLOCK];
-    u64 base = (u64)blockIdx.x * SCAN_TILE;
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const u64* __restrict__ in, u64 n, u64* __restrict__ bsum) {
+    __shared__ u64 sh[SCAN_BLOCK / 64];
+    const u64 base = (u64)blockIdx.x * SCAN_TILE;
     u64 s = 0;
+#pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        u64 i = base + (u64)threadIdx.x * SCAN_ITEMS + k;
+        const u64 i = base + (u64)k * SCAN_BLOCK + threadIdx.x;
         if (i < n) s += in[i];
     }
-    u64 inc = block_incl_scan(s, sh);
-    if (threadIdx.x == SCAN_BLOCK - 1) bsum[blockIdx.x] = inc;
+    for (int off = 32; off >= 1; off >>= 1) s += shfl_xor_u64(s, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 t = 0;
+        for (int k = 0; k < SCAN_BLOCK / 64; ++k) t += sh[k];
+        bsum[blockIdx.x] = t;
+    }
 }
 
 // Single block: exclusive scan of nb block sums in place, total to *total.
-__global__ void k_scan_top(u64* __restrict__ bsum, u64 nb, u64* __restrict__ total) {
-    __shared__ u64 sh[SCAN_BLOCK];
-    __shared__ u64 tot;
+__global__ __launch_bounds__(TOP_BLOCK) void k_scan_top(u64* __restrict__ bsum, u64 nb, u64* __restrict__ total) {
+    __shared__ u64 sh[TOP_BLOCK / 64];
     u64 carry = 0;
-    for (u64 base = 0; base < nb; base += SCAN_BLOCK) {
-        u64 i = base + threadIdx.x;
-        u64 x = (i < nb) ? bsum[i] : 0;
-        u64 inc = block_incl_scan(x, sh);
-        if (i < nb) bsum[i] = carry + inc - x;
-        if (threadIdx.x == SCAN_BLOCK - 1) tot = inc;
-        __syncthreads();
+    for (u64 base = 0; base < nb; base += TOP_BLOCK) {
+        const u64 i = base + threadIdx.x;
+        const u64 x = (i < nb) ? bsum[i] : 0;
+        u64 tot;
+        const u64 ex = block_excl_scan<TOP_BLOCK>(x, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
         carry += tot;
-        __syncthreads();
     }
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ void k_scan_down(const u64* __restrict__ in, u64 n, const u64* __restrict__ boff, u64* __restrict__ out) {
-    __shared__ u64 sh[SCAN_BLOCK];
-    u64 base = (u64)blockIdx.x * SCAN_TILE;
+// Each thread scans SCAN_ITEMS consecutive counts.  in and out may be the
+// same array (every thread reads its own counts before writing them).
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const u64* in, u64 n, const u64* __restrict__ boff,
+                                                          u64* out) {
+    __shared__ u64 sh[SCAN_BLOCK / 64];
+    const u64 first = (u64)blockIdx.x * SCAN_TILE + (u64)threadIdx.x * SCAN_ITEMS;
+    const bool full = (u64)(blockIdx.x + 1) * SCAN_TILE <= n;
     u64 v[SCAN_ITEMS];
     u64 s = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        u64 i = base + (u64)threadIdx.x * SCAN_ITEMS + k;
-        v[k] = (i < n) ? in[i] : 0;
-        s += v[k];
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = in[first + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = (first + k < n) ? in[first + k] : 0;
     }
-    u64 inc = block_incl_scan(s, sh);
-    u64 run = boff[blockIdx.x] + inc - s;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        u64 i = base + (u64)threadIdx.x * SCAN_ITEMS + k;
-        if (i < n) out[i] = run;
-        run += v[k];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+    u64 tot;
+    u64 run = boff[blockIdx.x] + block_excl_scan<SCAN_BLOCK>(s, sh, &tot);
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            out[first + k] = run;
+            run += v[k];
+        }
+    } else {
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (first + k < n) out[first + k] = run;
+            run += v[k];
+        }
     }
 }
 
@@ -106,7 +137,7 @@ void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* to
     if (nb < 1) nb = 1;
     u64* bsum = (u64*)P->ws_scan.get(nb * sizeof(u64));
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, P->stream, bsum, nb, total_dev);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_BLOCK), 0, P->stream, bsum, nb, total_dev);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum, out);
     SFCI_CHECK_HIP(hipGetLastError());
 }
