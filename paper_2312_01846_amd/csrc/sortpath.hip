@@ -190,89 +190,117 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
 }
 
 // In-order sums of the runs of equal keys.  Each wavefront owns the runs
-// whose first element lies in its span of SEG_SPAN positions: it walks the
-// keys 64 at a time and adds every run's values one by one in index order
-// (a run that crosses the span's end is finished by its owner), so the sums
-// round exactly as a sequential loop does.  flag[i] = 1 for the first
-// element of a run whose sum is nonzero (and, with eps > 0, has |sum| >= eps:
-// the screening of Sec. 3), else 0; seg[i] holds that sum.
-constexpr u64 SEG_SPAN = 2048;
+// whose first element lies in its span of SEG_SPAN positions.  It stages the
+// span's values in LDS and lists the run heads, then its lanes take the runs
+// in turn (run j to lane j mod 64) and each adds its run's values one by one
+// in index order from a zero start, so every sum rounds exactly as a
+// sequential loop does; the last run, which may cross the span's end, is
+// finished by the whole wavefront staging 64 values at a time.  Sums that are nonzero (and, with eps > 0, have |sum| >= eps:
+// the screening of Sec. 3) are written in head order, with key + key_base, to
+// the span's own stretch of the staging arrays; span_cnt receives their number.
+constexpr int SEG_SPAN = 1024;
+constexpr int SEG_WAVES = 4;
 
-__device__ __forceinline__ u64 keep_flag(double s, double eps) { return (s != 0.0 && !(fabs(s) < eps)) ? 1 : 0; }
+__device__ __forceinline__ bool keep_sum(double s, double eps) { return s != 0.0 && !(fabs(s) < eps); }
 
 template <class K>
-__global__ __launch_bounds__(256) void k_seg_sum(const K* __restrict__ keys, const double* __restrict__ vals, u64 n,
-                                                 double* __restrict__ seg, u64* __restrict__ flag, double eps) {
-    __shared__ double sv[4][64];
-    __shared__ int stop_flag[4];
+__global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_runs(const K* __restrict__ keys,
+                                                             const double* __restrict__ vals, u64 n, u64 key_base,
+                                                             double eps, u64* __restrict__ stage_r,
+                                                             double* __restrict__ stage_a,
+                                                             u64* __restrict__ span_cnt) {
+    __shared__ double sv[SEG_WAVES][SEG_SPAN];
+    __shared__ uint16_t hpos[SEG_WAVES][SEG_SPAN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const u64 nw = ((u64)gridDim.x * blockDim.x) >> 6;
-    for (u64 w = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * SEG_SPAN < n; w += nw) {
-        const u64 a = w * SEG_SPAN, b = min(n, a + SEG_SPAN);
-        // the lanes find the run heads of each 64-entry chunk and stage its
-        // values; lane 0 adds them in order, head to head
-        bool in_run = false;
-        u64 head = 0;
-        double acc = 0.0;
-        for (u64 base = a; base < n; base += 64) {
-            const u64 i = base + lane;
-            const bool valid = i < n;
+    const u64 lt = (1ull << lane) - 1ull;
+    const u64 nspans = (n + SEG_SPAN - 1) / SEG_SPAN;
+    const u64 nw = (u64)gridDim.x * SEG_WAVES;
+    for (u64 w = (u64)blockIdx.x * SEG_WAVES + wave; w < nspans; w += nw) {
+        const u64 a = w * SEG_SPAN;
+        const int len = (int)min((u64)SEG_SPAN, n - a);
+        int H = 0;
+        for (int c = 0; c < SEG_SPAN; c += 64) {
+            const int q = c + lane;
+            const u64 i = a + q;
+            const bool valid = q < len;
             const bool is_head = valid && (i == 0 || keys[i - 1] != keys[i]);
-            if (valid && i < b && !is_head) flag[i] = 0;
-            sv[wave][lane] = valid ? vals[i] : 0.0;
-            const u64 hm = __ballot(is_head);
-            wave_sync();
-            if (lane == 0) {
-                const int cnt = (int)min((u64)64, n - base);
-                int stop = 0, t = 0;
-                while (t < cnt) {
-                    const u64 rest = hm >> t;
-                    int h = rest ? t + (int)__builtin_ctzll(rest) : cnt;
-                    if (h > cnt) h = cnt;
-                    if (in_run)
-                        for (int q = t; q < h; ++q) acc += sv[wave][q];
-                    if (h >= cnt) break;
-                    if (in_run) {
-                        seg[head] = acc;
-                        flag[head] = keep_flag(acc, eps);
-                    }
-                    if (base + h >= b) {
-                        in_run = false;
-                        stop = 1;
-                        break;
-                    }
-                    in_run = true;
-                    head = base + h;
-                    acc = 0.0;
-                    acc += sv[wave][h];
-                    t = h + 1;
-                }
-                stop_flag[wave] = stop;
+            sv[wave][q] = valid ? vals[i] : 0.0;
+            const u64 m = __ballot(is_head);
+            if (is_head) hpos[wave][H + __popcll(m & lt)] = (uint16_t)q;
+            H += __popcll(m);
+        }
+        wave_sync();
+        if (H == 0) {
+            if (lane == 0) span_cnt[w] = 0;
+            continue;
+        }
+        // every run but the last ends inside the span
+        const int e_last = len;
+        u64 kept = 0;
+        double part = 0.0;  // the last run's sum over its in-span part
+        for (int r0 = 0; r0 < H; r0 += 64) {
+            const int j = r0 + lane;
+            double acc = 0.0;
+            bool keep = false;
+            K key = 0;
+            if (j < H) {
+                const int s0 = hpos[wave][j];
+                const int e = (j + 1 < H) ? (int)hpos[wave][j + 1] : e_last;
+                for (int q = s0; q < e; ++q) acc += sv[wave][q];
+                key = keys[a + s0];
+                if (j + 1 < H) keep = keep_sum(acc, eps);
+                else part = acc;
             }
-            wave_sync();
-            const int stop = stop_flag[wave];
-            wave_sync();
-            if (stop) break;
+            const u64 m = __ballot(keep);
+            if (keep) {
+                const u64 at = a + kept + (u64)__popcll(m & lt);
+                stage_r[at] = (u64)key + key_base;
+                stage_a[at] = acc;
+            }
+            kept += (u64)__popcll(m);
         }
-        if (lane == 0 && in_run) {
-            seg[head] = acc;
-            flag[head] = keep_flag(acc, eps);
+        // the last run continues past the span while the keys stay equal: the
+        // wavefront stages 64 values at a time, lane 0 goes on adding in order
+        double acc = __shfl(part, (H - 1) & 63);
+        const K hk = keys[a + hpos[wave][H - 1]];
+        wave_sync();
+        for (u64 base = a + len; base < n; base += 64) {
+            const u64 i = base + lane;
+            const bool same = i < n && keys[i] == hk;
+            const u64 diff = __ballot(!same);
+            const int cnt = diff ? (int)__builtin_ctzll(diff) : 64;
+            sv[wave][lane] = (lane < cnt) ? vals[i] : 0.0;
+            wave_sync();
+            if (lane == 0)
+                for (int q = 0; q < cnt; ++q) acc += sv[wave][q];
+            wave_sync();
+            if (diff) break;
         }
+        if (lane == 0 && keep_sum(acc, eps)) {
+            stage_r[a + kept] = (u64)hk + key_base;
+            stage_a[a + kept] = acc;
+            ++kept;
+        }
+        if (lane == 0) span_cnt[w] = kept;
+        wave_sync();
     }
 }
 
-// Scatter flagged heads to out[base + exclusive-prefix(flag)].
-template <class K>
-__global__ void k_seg_write(const K* __restrict__ keys, const double* __restrict__ seg, const u64* __restrict__ flag,
-                            const u64* __restrict__ pos, u64 n, u64 key_base, const u64* __restrict__ out_base,
-                            u64 out_cap, u64* __restrict__ out_r, double* __restrict__ out_a) {
+// Move every span's kept sums to out[*out_base + span offset + ...] (entries
+// past out_cap are dropped; the caller sees the total).
+__global__ __launch_bounds__(256) void k_seg_copy(const u64* __restrict__ stage_r, const double* __restrict__ stage_a,
+                                                  const u64* __restrict__ span_cnt, const u64* __restrict__ span_off,
+                                                  u64 nspans, const u64* __restrict__ out_base, u64 out_cap,
+                                                  u64* __restrict__ out_r, double* __restrict__ out_a) {
+    const int lane = threadIdx.x & 63;
     const u64 ob = *out_base;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
-        if (flag[i]) {
-            u64 at = ob + pos[i];
-            if (at < out_cap) {
-                out_r[at] = (u64)keys[i] + key_base;
-                out_a[at] = seg[i];
+    const u64 nw = ((u64)gridDim.x * blockDim.x) >> 6;
+    for (u64 w = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nspans; w += nw) {
+        const u64 c = span_cnt[w], o = ob + span_off[w], a = w * SEG_SPAN;
+        for (u64 t = lane; t < c; t += 64) {
+            if (o + t < out_cap) {
+                out_r[o + t] = stage_r[a + t];
+                out_a[o + t] = stage_a[a + t];
             }
         }
     }
@@ -360,14 +388,18 @@ void segmented_sum_append(sfci_problem* P, const K* keys, const double* vals, u6
                           u64* out_base_dev, u64 out_cap, u64* out_r, double* out_a) {
     if (n == 0) return;
     u64* scal = (u64*)P->ws_scalar.get(8 * sizeof(u64));
-    double* seg = (double*)P->ws_seg_v.get(n * sizeof(double));
-    u64* flag = (u64*)P->ws_seg_f.get(n * sizeof(u64));
-    const u64 spans = (n + SEG_SPAN - 1) / SEG_SPAN;
-    const unsigned sgrid = (unsigned)std::min<u64>((spans + 3) / 4, (u64)P->num_cu * 32);
-    hipLaunchKernelGGL(k_seg_sum<K>, dim3(sgrid), dim3(256), 0, P->stream, keys, vals, n, seg, flag, eps);
-    u64* pos = (u64*)P->ws_scan2.get(n * sizeof(u64));
-    exclusive_scan_u64(P, flag, pos, n, &scal[2]);
-    hipLaunchKernelGGL(k_seg_write<K>, dim3(g1(n)), dim3(256), 0, P->stream, keys, seg, flag, pos, n, key_base,
+    double* stage_a = (double*)P->ws_seg_v.get(n * sizeof(double));
+    u64* stage_r = (u64*)P->ws_seg_f.get(n * sizeof(u64));
+    const u64 nspans = (n + SEG_SPAN - 1) / SEG_SPAN;
+    u64* cnt = (u64*)P->ws_scan2.get(2 * nspans * sizeof(u64));
+    u64* off = cnt + nspans;
+    const unsigned sgrid =
+        (unsigned)std::max<u64>(1, std::min<u64>((nspans + SEG_WAVES - 1) / SEG_WAVES, (u64)P->num_cu * 16));
+    hipLaunchKernelGGL(k_seg_runs<K>, dim3(sgrid), dim3(64 * SEG_WAVES), 0, P->stream, keys, vals, n, key_base, eps,
+                       stage_r, stage_a, cnt);
+    exclusive_scan_u64(P, cnt, off, nspans, &scal[2]);
+    const unsigned cgrid = (unsigned)std::max<u64>(1, std::min<u64>((nspans + 3) / 4, (u64)P->num_cu * 16));
+    hipLaunchKernelGGL(k_seg_copy, dim3(cgrid), dim3(256), 0, P->stream, stage_r, stage_a, cnt, off, nspans,
                        out_base_dev, out_cap, out_r, out_a);
     hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, P->stream, out_base_dev, &scal[2]);
     SFCI_CHECK_HIP(hipGetLastError());
@@ -378,11 +410,11 @@ template void segmented_sum_append<u32>(sfci_problem*, const u32*, const double*
                                         double*);
 
 u64 sort_tuple_cap(sfci_problem* P) {
-    // Tuple buffer: a quarter of free memory (7 words per tuple over the
+    // Tuple buffer: a quarter of free memory (6 words per tuple over the
     // emission, sort and reduction buffers).  SFCI_SORT_TUPLE_CAP lowers it.
     size_t freeb = 0, totb = 0;
     SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
-    const u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + 2 * sizeof(u64);
+    const u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + sizeof(u64);
     u64 cap = (u64)(freeb / 4) / per_tuple;
     if (const char* env = getenv("SFCI_SORT_TUPLE_CAP")) {
         long long e = atoll(env);
