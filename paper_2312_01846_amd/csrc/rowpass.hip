@@ -55,6 +55,9 @@ struct RPConst {
     const u32* row_end;
     int sA, sB, PA, QA, PB, QB;
     u64 c_id, c_s;  // tuples per entry of an identity pair / a single pair
+    // beta singles of every beta string (target rank | j << 21 | b << 26 |
+    // phase << 31), or nullptr: then they are enumerated and ranked per entry
+    const u32* T1;
 };
 
 __device__ __forceinline__ u64 wave_sum(u64 x) {
@@ -317,6 +320,41 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
             }
             const u32 A = str_unrank(pr.src_row, na, n, B);
             const int i = (pr.info >> 2) & 31, a = (pr.info >> 7) & 31, pa = (pr.info >> 22) & 1;
+            if (type == RP_SINGLE && c.T1) {
+                // beta unchanged: a lane per entry
+                for (u64 e = e0 + lane; e < e1; e += 64) {
+                    const u64 s = pr.beg + e;
+                    const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
+                    const u32 Bs = str_unrank(rB, nb, n, B);
+                    double el = single_element_nophase(c.I, A, Bs, i, a);
+                    if (pa) el = -el;
+                    const u64 at = pr.tup_off + e * cp;
+                    keys[at] = (u32)(tgt_base + rB);
+                    vals[at] = el * c.v_amp[s];
+                    nz += (el != 0.0) ? 1 : 0;
+                }
+                // alpha-beta doubles: lanes over (entry, beta single), the
+                // single's target, orbitals and phase from the table.  An
+                // entry's targets are distinct, so the order of its options
+                // does not matter to any sum.
+                const u32 sBn = (u32)c.sB;
+                const u32 nf = (u32)(e1 - e0) * sBn;
+                const __attribute__((address_space(1))) double* gia =
+                    (const __attribute__((address_space(1))) double*)c.I.g + (u64)(i * n + a) * n * n;
+                for (u32 f = lane; f < nf; f += 64) {
+                    const u32 de = f / sBn, o = f - de * sBn;
+                    const u64 s = pr.beg + e0 + de;
+                    const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
+                    const u32 t = c.T1[rB * sBn + o];
+                    double el = gia[((t >> 21) & 31u) * n + ((t >> 26) & 31u)];
+                    if (pa ^ (int)(t >> 31)) el = -el;
+                    const u64 at = pr.tup_off + (e0 + de) * cp + 1 + o;
+                    keys[at] = (u32)(tgt_base + (t & 0x1FFFFFu));
+                    vals[at] = el * c.v_amp[s];
+                    nz += (el != 0.0) ? 1 : 0;
+                }
+                continue;
+            }
             for (u64 e = e0; e < e1; ++e) {
                 const u64 s = pr.beg + e;
                 const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
@@ -404,6 +442,7 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
     c.QB = (n - nb) * (n - nb - 1) / 2;
     c.c_id = 1 + (u64)c.sB + (u64)c.PB * c.QB;
     c.c_s = 1 + (u64)c.sB;
+    c.T1 = rowtile_T1(P);
     const int K = 1 + c.sA + c.PA * c.QA;
     if (K > 65536) throw sfci_error(-8, "sort path: more than 65536 alpha neighbours per string");
     u32 Kp2 = 1;

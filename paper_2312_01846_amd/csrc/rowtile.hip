@@ -1114,6 +1114,12 @@ static void plan_tiles(sfci_problem* P, RowTileState* S, int tile_max) {
     S->tile_max = mx;
 }
 
+const u32* rowtile_T1(sfci_problem* P) {
+    const char* env = getenv("SFCI_RP_NO_T1");
+    if (env && env[0] == '1') return nullptr;
+    return rowtile_available(P) ? rt_state(P)->d_T1 : nullptr;
+}
+
 bool rowtile_available(sfci_problem* P) {
     // the packed single-excitation table holds a target beta rank in 21 bits
     if (P->n > 32 || P->nb * (P->n - P->nb) > SFCI_MAX_SINGLES || P->Nb >= (1ull << 21)) return false;

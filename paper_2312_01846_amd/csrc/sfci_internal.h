@@ -135,6 +135,9 @@ void launch_scatter_zero(sfci_problem* P, double* D, const u64* r, const u64* nn
 
 // ---- target-owned dense sigma (rowtile.hip) ----
 bool rowtile_available(sfci_problem* P);  // builds the per-problem tables on first use
+// The packed beta singles of every beta string (sorted by target rank), or
+// nullptr where the tables cannot be built (or SFCI_RP_NO_T1=1).
+const u32* rowtile_T1(sfci_problem* P);
 void rowtile_release(sfci_problem* P);
 // eps > 0: accumulated entries with |c| < eps are written as zero (screening, Sec. 3).
 void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,

@@ -19,6 +19,7 @@ namespace {
 constexpr int RS_BLOCK = 256;
 constexpr int RS_ITEMS = 16;
 constexpr u64 RS_TILE = (u64)RS_BLOCK * RS_ITEMS;
+constexpr int RS_SBLOCK = 512;  // threads of the scatter kernel
 constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
 
@@ -93,36 +94,41 @@ __global__ void k_rs_tile_rows(const u64* __restrict__ ttile, u64 lo, u64 hi, u3
     for (u64 t = ttile[r]; t < ttile[r + 1]; ++t) tile_row[t - ttile[lo]] = (u32)r;
 }
 
-// One stable LSD pass.  Wavefront w of a block ranks the contiguous quarter
-// [w * RS_TILE/4, (w+1) * RS_TILE/4) of the block's tile on its own (64
-// entries at a time, digit peers from ballots, running per-digit counts in
-// its own LDS row: no block barrier), the block then orders the tile by digit
-// in LDS (wavefront order = tile order, so the pass is stable) and writes
-// every digit's run to its global slot as one contiguous stretch.  offs holds
-// the exclusive prefix of the counts in the layout tile_info describes.
+// One stable LSD pass (RS_SBLOCK threads).  Wavefront w of a block ranks the
+// contiguous share [w * PER_WAVE, (w+1) * PER_WAVE) of the block's tile on
+// its own (64 entries at a time, digit peers from ballots, running per-digit
+// counts in its own LDS row: no block barrier), the block then orders the tile
+// by digit in LDS (wavefront order = tile order, so the pass is stable) and
+// writes every digit's run to its global slot as one contiguous stretch.  offs
+// holds the exclusive prefix of the counts in the layout tile_info describes.
+// Eight wavefronts per block keep more loads in flight than the LDS share of
+// a four-wavefront block would allow.
 template <class K>
-__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ keys, const double* __restrict__ vals,
-                                                         u64 n, int shift, int bits, const u64* __restrict__ offs,
-                                                         u64 nblk,
-                                                         SortTiles st, K* __restrict__ ko,
-                                                         double* __restrict__ vo) {
-    constexpr int NW = RS_BLOCK / 64;
+__global__ __launch_bounds__(RS_SBLOCK) void k_rs_scatter(const K* __restrict__ keys,
+                                                          const double* __restrict__ vals, u64 n, int shift,
+                                                          int bits, const u64* __restrict__ offs, u64 nblk,
+                                                          SortTiles st, K* __restrict__ ko,
+                                                          double* __restrict__ vo) {
+    constexpr int NW = RS_SBLOCK / 64;
+    constexpr int DW = RS_BINS / 64;        // wavefronts holding one digit per lane
     constexpr int PER_WAVE = RS_TILE / NW;  // entries per wavefront
+    static_assert(RS_SBLOCK >= RS_BINS && RS_TILE % RS_SBLOCK == 0, "scatter block");
     __shared__ K sk[RS_TILE];
     __shared__ double sv[RS_TILE];
     __shared__ u64 gstart[RS_BINS];
     __shared__ unsigned lstart[RS_BINS];
-    __shared__ unsigned wcnt[NW][RS_BINS];
-    __shared__ unsigned wsum[NW];
+    __shared__ uint16_t wcnt[NW][RS_BINS];  // counts, then tile positions (< RS_TILE)
+    __shared__ unsigned wsum[DW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const u64 nbins = 1ull << bits;
     const TileInfo ti = tile_info(st, n, nblk, blockIdx.x, nbins);
     const K kb = (K)ti.kbase;
     const K mask = (K)(nbins - 1);
-    for (int w = 0; w < NW; ++w) wcnt[w][threadIdx.x] = 0;
-    gstart[threadIdx.x] = (threadIdx.x < nbins) ? offs[ti.hb + (u64)threadIdx.x * ti.hs] : 0;
+    for (int q = threadIdx.x; q < NW * RS_BINS; q += RS_SBLOCK) (&wcnt[0][0])[q] = 0;
+    if (threadIdx.x < RS_BINS)
+        gstart[threadIdx.x] = (threadIdx.x < nbins) ? offs[ti.hb + (u64)threadIdx.x * ti.hs] : 0;
     __syncthreads();
-    // ranks inside this wavefront's quarter
+    // ranks inside this wavefront's share
     K key[PER_WAVE / 64];
     double val[PER_WAVE / 64];
     unsigned dig[PER_WAVE / 64], loc[PER_WAVE / 64];
@@ -133,6 +139,11 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
         const bool valid = i < ti.len;
         key[k] = valid ? keys[ti.base + i] : (K)0;
         val[k] = valid ? vals[ti.base + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER_WAVE / 64; ++k) {
+        const u64 i = wbase + (u64)k * 64 + lane;
+        const bool valid = i < ti.len;
         const unsigned d = (unsigned)(((key[k] - kb) >> shift) & mask);
         dig[k] = valid ? d : 0xffffffffu;
         u64 peers = __ballot(valid);
@@ -141,32 +152,34 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const unsigned rank = (unsigned)__popcll(peers & ((1ull << lane) - 1ull));
-        loc[k] = valid ? wcnt[wave][d] + rank : 0u;
+        loc[k] = valid ? (unsigned)wcnt[wave][d] + rank : 0u;
         wave_sync();
-        if (valid && rank == 0) wcnt[wave][d] += (unsigned)__popcll(peers);
+        if (valid && rank == 0) wcnt[wave][d] = (uint16_t)(wcnt[wave][d] + __popcll(peers));
         wave_sync();
     }
     __syncthreads();
-    {
-        // block-local start of every digit, then wcnt[w][d] becomes the tile
-        // position of wavefront w's first digit-d entry: lower wavefronts
-        // first, then this one's order
-        const unsigned d = threadIdx.x;
-        unsigned cnt = 0;
+    // block-local start of every digit (the first DW wavefronts, a digit per
+    // lane), then wcnt[w][d] becomes the tile position of wavefront w's first
+    // digit-d entry: lower wavefronts first, then this one's order
+    const unsigned d = threadIdx.x;
+    unsigned cnt = 0, x = 0;
+    if (wave < DW) {
         for (int w = 0; w < NW; ++w) cnt += wcnt[w][d];
-        unsigned x = cnt;
+        x = cnt;
         for (int off = 1; off < 64; off <<= 1) {
             const unsigned y = __shfl_up(x, off);
             if (lane >= off) x += y;
         }
         if (lane == 63) wsum[wave] = x;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (wave < DW) {
         unsigned run = x - cnt;
         for (int w = 0; w < wave; ++w) run += wsum[w];
         lstart[d] = run;
         for (int w = 0; w < NW; ++w) {
             const unsigned c = wcnt[w][d];
-            wcnt[w][d] = run;
+            wcnt[w][d] = (uint16_t)run;
             run += c;
         }
     }
@@ -180,7 +193,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const K* __restrict__ k
         sv[pos] = val[k];
     }
     __syncthreads();
-    for (u64 t = threadIdx.x; t < ti.len; t += RS_BLOCK) {
+    for (u64 t = threadIdx.x; t < ti.len; t += RS_SBLOCK) {
         const K kk = sk[t];
         const unsigned d = (unsigned)(((kk - kb) >> shift) & mask);
         const u64 gpos = gstart[d] + (t - lstart[d]);
@@ -344,7 +357,7 @@ void radix_passes(sfci_problem* P, K* k1, double* v1, K* k2, double* v2, u64 n, 
         hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, n, shift, bits,
                            hist, nblk, st);
         exclusive_scan_u64(P, hist, hist, nbins * nblk, nullptr);
-        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_BLOCK), 0, P->stream, k1, v1, n, shift,
+        hipLaunchKernelGGL(k_rs_scatter<K>, dim3((unsigned)nblk), dim3(RS_SBLOCK), 0, P->stream, k1, v1, n, shift,
                            bits, hist, nblk, st, k2, v2);
         shift += bits;
         std::swap(k1, k2);
