@@ -14,8 +14,9 @@
 //      single, the unchanged beta string for an alpha double);
 //   3. the host cuts the rows into passes of at most the tuple buffer;
 //   4. per pass: the (target row, source row) pairs, sorted by source row
-//      inside each target row, with their tuple offsets; then every entry of
-//      every pair emits its tuples at fixed positions.
+//      inside each target row, with their tuple offsets; an alpha-double pair
+//      (most pairs, one tuple per entry) writes its tuples right there, every
+//      entry of the other pairs emits its tuples at fixed positions after.
 // Inside a target, contributions therefore sit in ascending source row and,
 // within a row, ascending entry order, i.e. ascending source rank; the stable
 // radix sort by target keeps that order and the in-order segmented sum adds
@@ -125,7 +126,9 @@ __global__ void k_rp_rowptr(const u64* __restrict__ v_rank, const u64* __restric
     }
 }
 
-// Per target row: tuples received and nonempty neighbouring source rows.
+// Per target row: tuples received and the nonempty neighbouring source rows
+// that are the row itself or an alpha single of it (the pair records the
+// emission kernel walks).
 __global__ __launch_bounds__(RP_BLOCK) void k_rp_count(RPConst c, u64* __restrict__ cnt, u32* __restrict__ npair) {
     __shared__ BinomLds B;
     __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_count(RPConst c, u64* __restric
             const u32 ne = c.row_end[rs] - c.row_beg[rs];
             if (ne) {
                 s += (u64)ne * tuples_per_entry(c, type);
-                ++k;
+                if (type != RP_DOUBLE) ++k;  // alpha doubles are emitted with the pairs
             }
         }
         s = wave_sum(s);
@@ -163,10 +166,14 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_count(RPConst c, u64* __restric
 }
 
 // Pairs of the target rows [lo, hi): one wavefront per row collects the
-// nonempty neighbours, sorts them by source rank (bitonic, in LDS) and writes
-// the records with their tuple offsets.
+// nonempty neighbours, sorts them by source rank (bitonic, in LDS) and assigns
+// their tuple offsets.  An alpha-double pair has one tuple per entry with one
+// element: its lane writes those tuples at once.  The other pairs are written
+// as records for the emission kernel.
 __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, const u64* __restrict__ tup_pre,
-                                                 const u64* __restrict__ pair_pre, RPPair* __restrict__ pairs) {
+                                                 const u64* __restrict__ pair_pre, RPPair* __restrict__ pairs,
+                                                 u32* __restrict__ tkeys, double* __restrict__ tvals,
+                                                 unsigned long long* __restrict__ nonzero) {
     extern __shared__ u64 keys[];
     __shared__ BinomLds B;
     __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
@@ -179,6 +186,7 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
     const int lane = lane_id();
     const int K = 1 + c.sA + c.PA * c.QA;
     const u64 Nb = c.sp.Nb;
+    u64 nz = 0;
     for (u64 r = lo + blockIdx.x; r < hi; r += gridDim.x) {
         const u32 At = str_unrank(r, na, n, B);
         wave_sync();
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
         }
         const u64 tbase = tup_pre[r] - tup_pre[lo];
         const u64 pbase = pair_pre[r] - pair_pre[lo];
-        u64 run = 0;
+        u64 run = 0, prun = 0;
         for (u32 q0 = 0; q0 < k; q0 += 64) {
             const u32 q = q0 + lane;
             u64 cntq = 0;
@@ -257,20 +265,53 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
             }
             u64 tot;
             const u64 pre = wave_excl_scan(cntq, &tot);
-            if (q < k) {
-                pr.tup_off = tbase + run + pre;
-                pairs[pbase + q] = pr;
+            const bool dbl = q < k && (pr.info & 3u) == RP_DOUBLE;
+            const bool rec = q < k && !dbl;
+            const u64 mrec = __ballot(rec);
+            const u64 at = tbase + run + pre;
+            if (rec) {
+                pr.tup_off = at;
+                pairs[pbase + prun + (u64)__popcll(mrec & ((1ull << lane) - 1ull))] = pr;
             }
+            // alpha-double tuples of this batch: lanes over the flattened
+            // (pair, entry) list, each lane's pair found by a binary search
+            // over the lanes' prefix counts
+            const u64 dne = dbl ? pr.ne : 0;
+            if (dbl && pr.e2 != 0.0) nz += dne;
+            u64 dtot;
+            const u64 dpre = wave_excl_scan(dne, &dtot);
+            const u64 src_base = (u64)pr.src_row * Nb - (u64)pr.tgt_local * Nb;  // rank shift, mod 2^64
+            for (u64 f0 = 0; f0 < dtot; f0 += 64) {
+                const u64 f = f0 + lane;
+                int L = 0;
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const u64 v = (u64)__shfl((long long)dpre, L + step);
+                    if (v <= f) L += step;
+                }
+                const u64 e = f - (u64)__shfl((long long)dpre, L);
+                const u64 s = (u64)__shfl((long long)pr.beg, L) + e;
+                const u64 o = (u64)__shfl((long long)at, L) + e;
+                const u64 sb = (u64)__shfl((long long)src_base, L);
+                const double e2 = __shfl(pr.e2, L);
+                if (f < dtot) {
+                    tkeys[o] = (u32)(c.v_rank[s] - sb);
+                    tvals[o] = e2 * c.v_amp[s];
+                }
+            }
+            prun += (u64)__popcll(mrec);
             run += tot;
         }
-        (void)Nb;
         wave_sync();
     }
+    nz = wave_sum(nz);
+    if (lane == 0 && nz) atomicAdd(nonzero, (unsigned long long)nz);
 }
 
-// Emission: every wavefront owns the entries whose first tuple falls in its
-// share of the pass's tuples.  Alpha-alpha pairs: a lane per entry; the other
-// pairs: the wavefront walks one entry's beta options across its lanes.
+// Emission of the identity and alpha-single pairs (alpha-double tuples are
+// written with the pairs): every wavefront owns the entries whose first tuple
+// falls in its share of the pass's tuples and walks an entry's beta options
+// across its lanes (alpha singles with the beta-single table: lanes over
+// (entry, option) of the pair).
 __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* __restrict__ pairs, u64 npairs,
                                                       u64 total, u32* __restrict__ keys, double* __restrict__ vals,
                                                       unsigned long long* __restrict__ nonzero) {
@@ -307,17 +348,6 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
             if (e1 > pr.ne) e1 = pr.ne;
             if (e0 >= e1) continue;
             const u64 tgt_base = (u64)pr.tgt_local * Nb;
-            if (type == RP_DOUBLE) {
-                for (u64 e = e0 + lane; e < e1; e += 64) {
-                    const u64 s = pr.beg + e;
-                    const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
-                    const u64 at = pr.tup_off + e;
-                    keys[at] = (u32)(tgt_base + rB);
-                    vals[at] = pr.e2 * c.v_amp[s];
-                    nz += (pr.e2 != 0.0) ? 1 : 0;
-                }
-                continue;
-            }
             const u32 A = str_unrank(pr.src_row, na, n, B);
             const int i = (pr.info >> 2) & 31, a = (pr.info >> 7) & 31, pa = (pr.info >> 22) & 1;
             if (type == RP_SINGLE && c.T1) {
@@ -501,16 +531,17 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
         const u64 tuples = htp[hi] - htp[lo], npairs = hpp[hi] - hpp[lo];
         if (tuples > 0) {
             ++passes;
-            RPPair* pairs = (RPPair*)ws.pairs.get(npairs * sizeof(RPPair));
-            const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 32);
-            hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(64), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
-                               ppre, pairs);
+            RPPair* pairs = (RPPair*)ws.pairs.get(std::max<u64>(1, npairs) * sizeof(RPPair));
             u32* k1 = (u32*)P->ws_tup_k.get(tuples * sizeof(u32));
             double* v1 = (double*)P->ws_tup_v.get(tuples * sizeof(double));
             u32* k2 = (u32*)P->ws_tup_k2.get(tuples * sizeof(u32));
             double* v2 = (double*)P->ws_tup_v2.get(tuples * sizeof(double));
-            hipLaunchKernelGGL(k_rp_emit, dim3(egrid), dim3(RP_BLOCK), 0, P->stream, c, (const RPPair*)pairs, npairs,
-                               tuples, k1, v1, nz);
+            const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 32);
+            hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(64), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
+                               ppre, pairs, k1, v1, nz);
+            if (npairs > 0)
+                hipLaunchKernelGGL(k_rp_emit, dim3(egrid), dim3(RP_BLOCK), 0, P->stream, c, (const RPPair*)pairs,
+                                   npairs, tuples, k1, v1, nz);
             SFCI_CHECK_HIP(hipGetLastError());
             u32* ks;
             double* vs;
