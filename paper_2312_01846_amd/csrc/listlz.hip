@@ -22,6 +22,7 @@
 // order the dense scatters do.  The deterministic option therefore gives the
 // dense deterministic iteration's numbers bit for bit.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "sfci_internal.h"
@@ -438,6 +439,24 @@ u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank,
     return need;
 }
 
+// Which passes sigma takes in fast mode.  The tile kernel pays a fixed cost
+// per (target row, tile) item (its neighbour records) plus ~2.2e-11 s per term;
+// the sort path ~4.2e-11 s per term and nothing per item (measured at 28
+// orbitals, M = 1e6 and 1e7: the item cost is ~1.2e-7 s).  The tile kernel is
+// taken once terms exceed ~5 700 per item.  SFCI_LIST_SIGMA=tile|sort forces
+// one kind.
+constexpr double kSortTermsPerTileItem = 5700.0;
+
+bool list_sigma_tiles(sfci_problem* P, u64 nnz) {
+    if (!rowtile_available(P)) return false;
+    if (const char* env = getenv("SFCI_LIST_SIGMA")) {
+        if (!strcmp(env, "tile")) return true;
+        if (!strcmp(env, "sort")) return false;
+    }
+    const double terms = (double)nnz * (double)terms_per_source(P->n, P->na, P->nb);
+    return terms > kSortTermsPerTileItem * (double)P->Na * (double)rowtile_ntiles(P);
+}
+
 // Dense passes: sigma through the target-owned tile kernel, a range of
 // target alpha rows at a time, into a zeroed slice of rows x N_beta doubles;
 // each slice is compacted (rank order, zeroing it) into the sink.
@@ -522,8 +541,8 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
     auto Wrj = [&](int j) { return Wr + (size_t)j * cap; };
     auto Waj = [&](int j) { return Wa + (size_t)j * cap; };
     const u64 tup_cap = sort_tuple_cap(P);
-    // without the ordered-sum requirement, sigma goes through the tile kernel in row passes
-    const bool dense_passes = !det && rowtile_available(P);
+    // without the ordered-sum requirement, sigma may go through the tile kernel in row passes
+    const bool tiles_ok = !det && rowtile_available(P);
 
     // Top-M of a candidate list into w_dst (rank order, normalised).
     auto select_into = [&](const CandSrc& src, int dst, bool sorted_src) {
@@ -556,6 +575,7 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
             sink.Y = Y;
             sink.bounds = ls + 8;
             sink.pcount = ls + 2;
+            const bool dense_passes = tiles_ok && list_sigma_tiles(P, read_dev(P, Wn(j)));
             tsig.begin(P->stream);
             if (dense_passes)
                 sigma_dense_passes(P, sl, sink, sc + 32, o->screen_eps);

@@ -1114,6 +1114,8 @@ static void plan_tiles(sfci_problem* P, RowTileState* S, int tile_max) {
     S->tile_max = mx;
 }
 
+int rowtile_ntiles(sfci_problem* P) { return rowtile_available(P) ? rt_state(P)->ntiles : 0; }
+
 const u32* rowtile_T1(sfci_problem* P) {
     const char* env = getenv("SFCI_RP_NO_T1");
     if (env && env[0] == '1') return nullptr;

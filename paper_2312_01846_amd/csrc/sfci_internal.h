@@ -138,6 +138,8 @@ bool rowtile_available(sfci_problem* P);  // builds the per-problem tables on fi
 // The packed beta singles of every beta string (sorted by target rank), or
 // nullptr where the tables cannot be built (or SFCI_RP_NO_T1=1).
 const u32* rowtile_T1(sfci_problem* P);
+// Beta-rank tiles per target row of the tile kernel (0 where it is unavailable).
+int rowtile_ntiles(sfci_problem* P);
 void rowtile_release(sfci_problem* P);
 // eps > 0: accumulated entries with |c| < eps are written as zero (screening, Sec. 3).
 void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
