@@ -85,40 +85,66 @@ __global__ __launch_bounds__(RB) void k_dot_final(const double* __restrict__ par
     }
 }
 
-// Ordered sums: one wavefront; products of 64 consecutive entries are formed in
-// parallel, then added one by one in index order.
-// acc += p_base, p_base+1, ..., in index order: the 64 products of a chunk
-// are formed by the lanes and staged in LDS, then lane 0 adds them one by
-// one (its acc is the result).
-__device__ __forceinline__ double add_chunk_in_order(double acc, double p, int cnt, double* stage) {
-    stage[threadIdx.x & 63] = p;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        if (cnt == 64) {
-            // a full chunk: a fixed-length chain, so the LDS reads run ahead of the adds
-#pragma unroll
-            for (int k = 0; k < 64; ++k) acc += stage[k];
-        } else {
-            for (int k = 0; k < cnt; ++k) acc += stage[k];
-        }
+// Ordered sums: acc = ((0 + t_0) + t_1) + ... strictly in index order, t_i
+// the term of entry i (x_i; a_i * D[r_i]; a_i * Y_i; a_i * a_i).  One
+// wavefront streams the terms: while lane 0 adds a group of OS_DEPTH chunks of
+// 64 terms from LDS, the next group's loads are in flight, so the global
+// latency hides behind the add chain (wavefront-scope syncs only: a block
+// barrier would wait for those loads).
+enum { OS_SUM = 0, OS_DOT = 1, OS_DOT_GATHERED = 2, OS_SUMSQ = 3 };
+constexpr int OS_DEPTH = 8;
+
+template <int MODE>
+__device__ __forceinline__ void os_load(const u64* __restrict__ r, const double* __restrict__ a,
+                                        const double* __restrict__ D, u64 i, u64 n, double& x, double& y) {
+    x = 0.0;
+    y = 0.0;
+    if (i < n) {
+        x = a[i];
+        if (MODE == OS_DOT) y = D[r[i]];
+        if (MODE == OS_DOT_GATHERED) y = D[i];
     }
-    __syncthreads();
-    return acc;
 }
 
-template <bool GATHERED>
-__global__ __launch_bounds__(64) void k_dot_dense_ordered(const u64* __restrict__ r, const double* __restrict__ a,
-                                                          const u64* __restrict__ nnz, const double* __restrict__ D,
-                                                          double* out1, double* out2) {
-    __shared__ double stage[64];
+template <int MODE>
+__device__ __forceinline__ double os_term(double x, double y) {
+    if (MODE == OS_SUM) return x;
+    if (MODE == OS_SUMSQ) return x * x;
+    return x * y;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void k_ordered(const u64* __restrict__ r, const double* __restrict__ a,
+                                                const u64* __restrict__ nnz, const double* __restrict__ D,
+                                                double* out1, double* out2) {
+    constexpr int G = 64 * OS_DEPTH;
+    __shared__ double stage[G];
     const u64 n = *nnz;
+    const int lane = threadIdx.x;
+    double x[OS_DEPTH], y[OS_DEPTH];
+#pragma unroll
+    for (int k = 0; k < OS_DEPTH; ++k) os_load<MODE>(r, a, D, (u64)k * 64 + lane, n, x[k], y[k]);
     double acc = 0.0;
-    for (u64 base = 0; base < n; base += 64) {
-        const u64 i = base + threadIdx.x;
-        const double p = (i < n) ? a[i] * y_of<GATHERED>(r, D, i) : 0.0;
-        acc = add_chunk_in_order(acc, p, (int)((n - base < 64) ? (n - base) : 64), stage);
+    for (u64 base = 0; base < n; base += G) {
+#pragma unroll
+        for (int k = 0; k < OS_DEPTH; ++k) stage[k * 64 + lane] = os_term<MODE>(x[k], y[k]);
+#pragma unroll
+        for (int k = 0; k < OS_DEPTH; ++k) os_load<MODE>(r, a, D, base + G + (u64)k * 64 + lane, n, x[k], y[k]);
+        wave_sync();
+        if (lane == 0) {
+            if (n - base >= (u64)G) {
+                for (int q = 0; q < G; q += 64) {
+#pragma unroll
+                    for (int k = 0; k < 64; ++k) acc += stage[q + k];
+                }
+            } else {
+                const int cnt = (int)(n - base);
+                for (int q = 0; q < cnt; ++q) acc += stage[q];
+            }
+        }
+        wave_sync();
     }
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         *out1 = acc;
         if (out2) *out2 = acc;
     }
@@ -136,24 +162,6 @@ __global__ __launch_bounds__(RB) void k_sparse_products(const u64* __restrict__ 
     for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) {
         const double yv = y_at(yr, ya, m, xr[i]);
         prod[i] = (yv != 0.0) ? xa[i] * yv : 0.0;
-    }
-}
-
-__global__ __launch_bounds__(64) void k_sum_ordered(const double* __restrict__ prod, const u64* __restrict__ nnz,
-                                                    double* out1, double* out2) {
-    __shared__ double stage[64];
-    const u64 n = *nnz;
-    double acc = 0.0;
-    double nxt = (threadIdx.x < n) ? prod[threadIdx.x] : 0.0;
-    for (u64 base = 0; base < n; base += 64) {
-        const double cur = nxt;
-        const u64 i2 = base + 64 + threadIdx.x;  // the next chunk's load is in flight during this chunk's adds
-        nxt = (i2 < n) ? prod[i2] : 0.0;
-        acc = add_chunk_in_order(acc, cur, (int)((n - base < 64) ? (n - base) : 64), stage);
-    }
-    if (threadIdx.x == 0) {
-        *out1 = acc;
-        if (out2) *out2 = acc;
     }
 }
 
@@ -195,19 +203,6 @@ __global__ __launch_bounds__(RB) void k_sum_part(const double* __restrict__ x, c
     for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)gridDim.x * RB) s += x[i];
     double b = block_sum(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = b;
-}
-
-__global__ __launch_bounds__(64) void k_sumsq_ordered(const double* __restrict__ a, const u64* __restrict__ nnz,
-                                                      double* out) {
-    __shared__ double stage[64];
-    const u64 n = *nnz;
-    double acc = 0.0;
-    for (u64 base = 0; base < n; base += 64) {
-        const u64 i = base + threadIdx.x;
-        const double p = (i < n) ? a[i] * a[i] : 0.0;
-        acc = add_chunk_in_order(acc, p, (int)((n - base < 64) ? (n - base) : 64), stage);
-    }
-    if (threadIdx.x == 0) *out = acc;
 }
 
 // Eq. 11: a_i = a_i / sqrt(sum of squares); untouched when the sum is 0.
@@ -400,7 +395,8 @@ template <bool GATHERED>
 void dot_dense_impl(sfci_problem* P, const u64* r, const double* a, const u64* nnz, u64 cap, const double* D,
                     double* out1, double* out2, bool ordered) {
     if (ordered) {
-        hipLaunchKernelGGL(k_dot_dense_ordered<GATHERED>, dim3(1), dim3(64), 0, P->stream, r, a, nnz, D, out1, out2);
+        hipLaunchKernelGGL(k_ordered<GATHERED ? OS_DOT_GATHERED : OS_DOT>, dim3(1), dim3(64), 0, P->stream, r, a, nnz,
+                           D, out1, out2);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(cap));
@@ -423,7 +419,8 @@ void launch_dot_gathered(sfci_problem* P, const double* a, const u64* nnz, u64 c
 
 void launch_sum(sfci_problem* P, const double* x, const u64* nnz, u64 cap, double* out, bool ordered) {
     if (ordered) {
-        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, P->stream, x, nnz, out, (double*)nullptr);
+        hipLaunchKernelGGL(k_ordered<OS_SUM>, dim3(1), dim3(64), 0, P->stream, (const u64*)nullptr, x, nnz,
+                           (const double*)nullptr, out, (double*)nullptr);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(cap));
@@ -435,7 +432,8 @@ void launch_sum(sfci_problem* P, const double* x, const u64* nnz, u64 cap, doubl
 
 void launch_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 cap, double* out, bool ordered) {
     if (ordered) {
-        hipLaunchKernelGGL(k_sumsq_ordered, dim3(1), dim3(64), 0, P->stream, a, nnz, out);
+        hipLaunchKernelGGL(k_ordered<OS_SUMSQ>, dim3(1), dim3(64), 0, P->stream, (const u64*)nullptr, a, nnz,
+                           (const double*)nullptr, out, (double*)nullptr);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(cap));
@@ -450,7 +448,8 @@ void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u
     if (ordered) {
         double* prod = (double*)P->ws_prod.get(std::max<u64>(1, xcap) * sizeof(double));
         hipLaunchKernelGGL(k_sparse_products, dim3(gsz(xcap)), dim3(RB), 0, P->stream, xr, xa, xn, yr, ya, yn, prod);
-        hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, P->stream, (const double*)prod, xn, out1, out2);
+        hipLaunchKernelGGL(k_ordered<OS_SUM>, dim3(1), dim3(64), 0, P->stream, (const u64*)nullptr,
+                           (const double*)prod, xn, (const double*)nullptr, out1, out2);
     } else {
         double* part = (double*)P->ws_red.get(RGRID * sizeof(double));
         unsigned g = std::min<unsigned>(RGRID, gsz(xcap));
@@ -478,7 +477,8 @@ void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool 
     double* part = (double*)P->ws_red.get((RGRID + 8) * sizeof(double));
     double* ss = part + RGRID;
     if (ordered) {
-        hipLaunchKernelGGL(k_sumsq_ordered, dim3(1), dim3(64), 0, P->stream, a, nnz, ss);
+        hipLaunchKernelGGL(k_ordered<OS_SUMSQ>, dim3(1), dim3(64), 0, P->stream, (const u64*)nullptr, a, nnz,
+                           (const double*)nullptr, ss, (double*)nullptr);
     } else {
         unsigned g = std::min<unsigned>(RGRID, gsz(cap));
         hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(RB), 0, P->stream, a, nnz, part);
