@@ -165,36 +165,43 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_count(RPConst c, u64* __restric
     }
 }
 
-// Pairs of the target rows [lo, hi): one wavefront per row collects the
-// nonempty neighbours, sorts them by source rank (bitonic, in LDS) and assigns
-// their tuple offsets.  An alpha-double pair has one tuple per entry with one
-// element: its lane writes those tuples at once.  The other pairs are written
-// as records for the emission kernel.
-__global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, const u64* __restrict__ tup_pre,
-                                                 const u64* __restrict__ pair_pre, RPPair* __restrict__ pairs,
-                                                 u32* __restrict__ tkeys, double* __restrict__ tvals,
-                                                 unsigned long long* __restrict__ nonzero) {
+// Pairs of the target rows [lo, hi): a block of RPP_WAVES wavefronts per row
+// collects the nonempty neighbours (in any order: they are sorted next),
+// sorts them by source rank (bitonic, in LDS) and assigns their tuple offsets
+// in that order.  An alpha-double pair has one tuple per entry with one
+// element: its wavefront writes those tuples at once, lanes over the flattened
+// (pair, entry) list.  The other pairs are written as records for the
+// emission kernel.
+constexpr int RPP_WAVES = 4;
+constexpr int RPP_BLOCK = 64 * RPP_WAVES;
+
+__global__ __launch_bounds__(RPP_BLOCK) void k_rp_pairs(RPConst c, u64 lo, u64 hi, const u64* __restrict__ tup_pre,
+                                                        const u64* __restrict__ pair_pre, RPPair* __restrict__ pairs,
+                                                        u32* __restrict__ tkeys, double* __restrict__ tvals,
+                                                        unsigned long long* __restrict__ nonzero) {
     extern __shared__ u64 keys[];
     __shared__ BinomLds B;
     __shared__ uint16_t pO[SFCI_MAX_PAIRS], pV[SFCI_MAX_PAIRS];
     __shared__ uint8_t occ[32], vir[32];
+    __shared__ unsigned kcount;
+    __shared__ u64 wtot[RPP_WAVES], wrec[RPP_WAVES];
     load_binom(B, c.binom);
     const int n = c.sp.n, na = c.sp.na, nva = n - na;
     for (int t = threadIdx.x; t < c.PA; t += blockDim.x) pO[t] = decode_pair(t, na);
     for (int t = threadIdx.x; t < c.QA; t += blockDim.x) pV[t] = decode_pair(t, nva);
     __syncthreads();
-    const int lane = lane_id();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const u64 lt = (1ull << lane) - 1ull;
     const int K = 1 + c.sA + c.PA * c.QA;
     const u64 Nb = c.sp.Nb;
     u64 nz = 0;
     for (u64 r = lo + blockIdx.x; r < hi; r += gridDim.x) {
         const u32 At = str_unrank(r, na, n, B);
-        wave_sync();
-        fill_lists(At, n, occ, vir);
-        wave_sync();
-        u32 k = 0;
-        for (int t0 = 0; t0 < K; t0 += 64) {
-            const int t = t0 + lane;
+        if (wave == 0) fill_lists(At, n, occ, vir);
+        if (threadIdx.x == 0) kcount = 0;
+        __syncthreads();
+        for (int t0 = 0; t0 < K; t0 += RPP_BLOCK) {
+            const int t = t0 + (int)threadIdx.x;
             bool ok = false;
             u64 key = 0;
             if (t < K) {
@@ -205,16 +212,20 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
                 key = (rs << 16) | (u64)t;
             }
             const u64 m = __ballot(ok);
-            if (ok) keys[k + (u32)__popcll(m & ((1ull << lane) - 1ull))] = key;
-            k += (u32)__popcll(m);
+            unsigned at = 0;
+            if (lane == 0 && m) at = atomicAdd(&kcount, (unsigned)__popcll(m));
+            at = (unsigned)__shfl((int)at, 0);
+            if (ok) keys[at + (unsigned)__popcll(m & lt)] = key;
         }
+        __syncthreads();
+        const u32 k = kcount;
         u32 N = 1;
         while (N < k) N <<= 1;
-        for (u32 t = k + lane; t < N; t += 64) keys[t] = ~0ull;
-        wave_sync();
+        for (u32 t = k + threadIdx.x; t < N; t += RPP_BLOCK) keys[t] = ~0ull;
+        __syncthreads();
         for (u32 size = 2; size <= N; size <<= 1) {
             for (u32 stride = size >> 1; stride > 0; stride >>= 1) {
-                for (u32 t = lane; t < N / 2; t += 64) {
+                for (u32 t = threadIdx.x; t < N / 2; t += RPP_BLOCK) {
                     const u32 i = 2 * t - (t & (stride - 1));
                     const u32 j = i + stride;
                     const bool up = (i & size) == 0;
@@ -224,14 +235,14 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
                         keys[j] = x;
                     }
                 }
-                wave_sync();
+                __syncthreads();
             }
         }
         const u64 tbase = tup_pre[r] - tup_pre[lo];
         const u64 pbase = pair_pre[r] - pair_pre[lo];
         u64 run = 0, prun = 0;
-        for (u32 q0 = 0; q0 < k; q0 += 64) {
-            const u32 q = q0 + lane;
+        for (u32 q0 = 0; q0 < k; q0 += RPP_BLOCK) {
+            const u32 q = q0 + threadIdx.x;
             u64 cntq = 0;
             RPPair pr{};
             if (q < k) {
@@ -263,17 +274,33 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
                 pr.info = info;
                 cntq = (u64)pr.ne * tuples_per_entry(c, type);
             }
-            u64 tot;
-            const u64 pre = wave_excl_scan(cntq, &tot);
+            // tuple offsets and record slots in ascending q over the block
+            u64 wt;
+            const u64 pre = wave_excl_scan(cntq, &wt);
             const bool dbl = q < k && (pr.info & 3u) == RP_DOUBLE;
             const bool rec = q < k && !dbl;
             const u64 mrec = __ballot(rec);
-            const u64 at = tbase + run + pre;
+            if (lane == 0) {
+                wtot[wave] = wt;
+                wrec[wave] = (u64)__popcll(mrec);
+            }
+            __syncthreads();
+            u64 before = 0, rbefore = 0, tot = 0, rtot = 0;
+            for (int w = 0; w < RPP_WAVES; ++w) {
+                if (w < wave) {
+                    before += wtot[w];
+                    rbefore += wrec[w];
+                }
+                tot += wtot[w];
+                rtot += wrec[w];
+            }
+            __syncthreads();
+            const u64 at = tbase + run + before + pre;
             if (rec) {
                 pr.tup_off = at;
-                pairs[pbase + prun + (u64)__popcll(mrec & ((1ull << lane) - 1ull))] = pr;
+                pairs[pbase + prun + rbefore + (u64)__popcll(mrec & lt)] = pr;
             }
-            // alpha-double tuples of this batch: lanes over the flattened
+            // this wavefront's alpha-double tuples: lanes over the flattened
             // (pair, entry) list, each lane's pair found by a binary search
             // over the lanes' prefix counts
             const u64 dne = dbl ? pr.ne : 0;
@@ -298,10 +325,10 @@ __global__ __launch_bounds__(64) void k_rp_pairs(RPConst c, u64 lo, u64 hi, cons
                     tvals[o] = e2 * c.v_amp[s];
                 }
             }
-            prun += (u64)__popcll(mrec);
             run += tot;
+            prun += rtot;
         }
-        wave_sync();
+        __syncthreads();
     }
     nz = wave_sum(nz);
     if (lane == 0 && nz) atomicAdd(nonzero, (unsigned long long)nz);
@@ -536,8 +563,8 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
             double* v1 = (double*)P->ws_tup_v.get(tuples * sizeof(double));
             u32* k2 = (u32*)P->ws_tup_k2.get(tuples * sizeof(u32));
             double* v2 = (double*)P->ws_tup_v2.get(tuples * sizeof(double));
-            const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 32);
-            hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(64), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
+            const unsigned pgrid = (unsigned)std::min<u64>(hi - lo, (u64)P->num_cu * 16);
+            hipLaunchKernelGGL(k_rp_pairs, dim3(pgrid), dim3(RPP_BLOCK), Kp2 * sizeof(u64), P->stream, c, lo, hi, tpre,
                                ppre, pairs, k1, v1, nz);
             if (npairs > 0)
                 hipLaunchKernelGGL(k_rp_emit, dim3(egrid), dim3(RP_BLOCK), 0, P->stream, c, (const RPPair*)pairs,
