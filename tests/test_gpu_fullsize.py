@@ -98,3 +98,73 @@ def test_benchmark_workload_full_size(torch, S, orc):
             continue
         v, _ = Po.sigma_entry(kr, ka, int(t))
         assert v == 0.0
+
+
+@pytest.fixture(scope="module")
+def c3_problem(S):
+    # 12 electrons in 28 orbitals (1.42e11 determinants), the molecule-like
+    # integrals of the 28-orbital benchmark workload; no N_det array
+    h, g = synth.molecule_like(28, 56, 3)
+    return S.Problem(28, 6, 6, h, g), h, g
+
+
+def _c3_start(P):
+    st = synth.perturbed_start(P.n, P.na, P.nb)
+    r0 = P.rank([t[0] for t in st], [t[1] for t in st]).cpu().numpy()
+    a0 = np.array([t[2] for t in st])
+    o = np.argsort(r0, kind="stable")
+    return r0[o], a0[o]
+
+
+def test_28_orbitals_M1e6_tile_and_sort_sigma_agree(torch, S, c3_problem, monkeypatch):
+    # the list iteration at M = 1e6: sigma through the tile kernel in row
+    # slices (the kernel the 28-orbital benchmark times at M = 1e7) and through
+    # the sort path (the per-sigma choice at this M) give the same energies
+    P, _, _ = c3_problem
+    start = _c3_start(P)
+    E = {}
+    for kind in ("tile", "sort"):
+        monkeypatch.setenv("SFCI_LIST_SIGMA", kind)
+        E[kind] = P.lanczos(*start, M=1_000_000, n_L=5, n_iter=5, want_psi=False)["energies"]
+    assert abs(E["tile"][-1] - E["sort"][-1]) < 1e-9, E
+
+
+def test_28_orbitals_sigma_topm_sampled(torch, S, orc, c3_problem):
+    # top-M of sigma of a ~1e6-entry vector (2.5e10 terms) through the sort
+    # path: sampled kept entries recomputed one by one by the oracle, and
+    # sampled neighbours of the kept support that were not kept must not beat
+    # the M-th magnitude
+    P, h, g = c3_problem
+    start = _c3_start(P)
+    run = P.lanczos(*start, M=1_000_000, n_L=2, n_iter=2, deterministic=True)
+    vr, va = P.topm(run["psi_rank"], run["psi_amp"], 1_000_000, normalise=True)
+    kr, ka = _np(vr).astype(np.uint64), _np(va)
+    assert len(kr) > 5e5
+    M = 1_000_000
+    gr, ga, st = P.sigma(kr.astype(np.int64), ka, M=M, deterministic=True)
+    gr, ga = _np(gr).astype(np.uint64), _np(ga)
+    assert st["terms_enumerated"] == len(kr) * P.tps
+    assert M <= len(gr) <= M + S.TIE_SLACK
+    assert np.all(np.diff(gr.astype(np.int64)) > 0)
+    Po = orc.Problem(28, 6, 6, h, g)
+    rng = np.random.default_rng(3)
+    # the oracle's entry sums the same products in the same ascending source
+    # order, each element evaluated from the target's side: equal to rounding
+    for i in rng.choice(len(gr), 16, replace=False):
+        v, ab = Po.sigma_entry(kr, ka, int(gr[i]))
+        assert abs(ga[i] - v) <= 1e-12 * ab, (int(gr[i]), ga[i], v, ab)
+    cut = np.sort(np.abs(ga))[::-1][M - 1]
+    # neighbours of kept entries (the connected determinants of a kept
+    # target) are sigma entries of the same vector; those outside the kept
+    # set lie at or below the cut, to rounding
+    kept = set(gr.tolist())
+    probes = 0
+    for i in rng.choice(len(gr), 40, replace=False):
+        nr, _, _ = P.sigma(np.array([int(gr[i])], dtype=np.int64), np.array([1.0]))
+        for t in _np(nr)[rng.choice(len(nr), 3, replace=False)]:
+            if int(t) in kept:
+                continue
+            v, ab = Po.sigma_entry(kr, ka, int(t))
+            assert abs(v) <= cut + 1e-12 * ab, (int(t), v, cut)
+            probes += 1
+    assert probes > 0
