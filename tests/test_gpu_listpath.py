@@ -174,8 +174,6 @@ def test_sigma_topm_in_passes_matches_oracle(torch, S, orc, monkeypatch, M):
     assert st["candidates"] == int(np.count_nonzero(fa))
 
 
-
-
 @pytest.mark.parametrize("case", ["c0", "hubbard", "n20", "n26"])
 def test_row_emission_equals_source_emission(torch, S, monkeypatch, case):
     # target-row-driven passes (per-row counts, sorted pair lists, exact-zero
@@ -196,8 +194,13 @@ def test_row_emission_equals_source_emission(torch, S, monkeypatch, case):
     r0, a0 = _perturbed(P)
     monkeypatch.setenv("SFCI_SORT_TUPLE_CAP", str(1 << 20))
     r1, a1, s1 = P.sigma(r0, a0, deterministic=True)
+    # without the beta-single table the alpha-single pairs rank every option
+    monkeypatch.setenv("SFCI_RP_NO_T1", "1")
+    r3, a3, s3 = P.sigma(r0, a0, deterministic=True)
+    monkeypatch.delenv("SFCI_RP_NO_T1")
     monkeypatch.setenv("SFCI_SORT_EMIT", "source")
     r2, a2, s2 = P.sigma(r0, a0, deterministic=True)
-    assert np.array_equal(_np(r1), _np(r2))
-    assert np.array_equal(_np(a1), _np(a2))
-    assert s1["terms_emitted"] == s2["terms_emitted"]
+    for r, a, s in ((r2, a2, s2), (r3, a3, s3)):
+        assert np.array_equal(_np(r1), _np(r))
+        assert np.array_equal(_np(a1), _np(a))
+        assert s1["terms_emitted"] == s["terms_emitted"]
