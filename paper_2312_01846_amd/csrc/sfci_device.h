@@ -144,14 +144,6 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// Value of v held by lane k (k wave-uniform), through scalar registers.
-__device__ __forceinline__ double readlane_f64(double v, int k) {
-    const long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), k);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Pair index -> (x, y), 0 <= x < y < k, in lexicographic order.
 __device__ __forceinline__ uint16_t decode_pair(int idx, int k) {
     int x = 0;
