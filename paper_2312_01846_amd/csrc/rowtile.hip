@@ -70,7 +70,6 @@ struct NbrRec {
 };
 
 struct WaveScratch {
-    unsigned incl[64];
     unsigned excl[64];
     unsigned start[64];
     u32 beta[64];
@@ -803,17 +802,22 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     }
                     const unsigned total = __shfl(incl, 63);
                     wave_sync();
-                    W.incl[lane] = incl;
                     W.excl[lane] = incl - len;
                     W.start[lane] = st;
                     W.beta[lane] = beta;
                     W.c[lane] = c;
                     wave_sync();
-                    int x = 0;  // entry of item q; q only grows, so the search resumes
+                    const unsigned excl = incl - len;
                     for (unsigned q0 = 0; q0 < total; q0 += 64) {
                         const unsigned q = q0 + lane;
+                        // entry of item q: the last lane whose first item is <= q
+                        // (a lane with no items shares its first item with the next)
+                        int x = 0;
+                        for (int step = 32; step >= 1; step >>= 1) {
+                            const unsigned v = (unsigned)__shfl((int)excl, x + step);
+                            if (v <= q) x += step;
+                        }
                         if (q < total) {
-                            while (W.incl[x] <= q) ++x;
                             const u32 te = p.T1[W.start[x] + (q - W.excl[x])];
                             const u32 rt = t1_rank(te);
                             const int jj = t1_j(te), bb = t1_b(te);
