@@ -52,6 +52,9 @@ struct RTParams {
     const double* K2;            // n^2: (pp|qq) - (pq|qp)
     const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
     const double* K4;            // [(i<j), (a<b)] pair-indexed (ia|jb) - (ib|ja), pair (x<y) -> y(y-1)/2 + x
+    const u32* T2r;              // per beta rank, its beta-beta doubles: target beta rank
+    const double* T2e;           //   and element with both phases, (ia|jb) - (ib|ja) signed
+                                 // (rows of one tile with a small table only; else nullptr)
     double eps;                  // sigma: screening threshold (Sec. 3), 0 = off
     u64 item_base;               // items of this description start at this global item
     u64 row_base;                // D holds target rows from this alpha rank on
@@ -599,6 +602,39 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const u32 k1 = min(ide, k0 + bb_chunk);
                 const auto K4g = gl(p.K4);
                 const int np2 = n * (n - 1) / 2;
+                if (p.T2r) {
+                    // tabulated target rank and signed element per double;
+                    // RT_UNROLL groups of 64 doubles have their loads in flight
+                    const auto T2rg = gl(p.T2r);
+                    const auto T2eg = gl(p.T2e);
+                    const u32 tot = (u32)(PB * QB);
+                    for (u32 k = k0; k < k1; ++k) {
+                        const u64 base = (u64)p.v_rb[k] * tot;
+                        const double c = p.v_amp[k];
+                        for (u32 t0 = 0; t0 < tot; t0 += 64 * RT_UNROLL) {
+                            u32 rt[RT_UNROLL];
+                            double e[RT_UNROLL];
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                const u32 t = t0 + (u32)u * 64 + lane;
+                                rt[u] = 0xFFFFFFFFu;
+                                e[u] = 0.0;
+                                if (t < tot) {
+                                    rt[u] = T2rg[base + t];
+                                    e[u] = T2eg[base + t];
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                if (rt[u] >= tlo && rt[u] < thi && e[u] != 0.0) {
+                                    atomicAdd(&acc[rt[u] - tlo], e[u] * c);
+                                    ++my_terms;
+                                }
+                            }
+                        }
+                    }
+                    continue;
+                }
                 for (u32 k = k0; k < k1; ++k) {
                     const u32 beta = p.v_beta[k];
                     const double c = p.v_amp[k];
@@ -758,25 +794,38 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const auto rbg = gl(p.v_rb);
                 const auto ampg = gl(p.v_amp);
                 const auto betag = gl(p.v_beta);
+                (void)betag;
                 for (int s0 = 0; s0 < sBn; s0 += 64) {
                     const int sidx = s0 + lane;
                     if (sidx >= sBn) continue;
                     const auto tsg = gl(p.TS);
-                    for (u32 k = r.rowb; k < r.rowe; ++k) {
-                        const u32 ti = rbg[k] * (u32)sBn + sidx;
-                        const u32 te = T1g[ti];
-                        // tabulated beta part, then the alpha part in ascending order
-                        double x = tsg[ti];
-                        const int jj = t1_j(te), bb = t1_b(te);
+                    // RT_UNROLL entries at a time, their loads in flight together;
+                    // each element adds its tabulated beta part, then the alpha
+                    // part in ascending orbital order
+                    for (u32 k0 = r.rowb; k0 < r.rowe; k0 += RT_UNROLL) {
+                        u32 te[RT_UNROLL];
+                        double x[RT_UNROLL], c[RT_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            const u32 k = min(k0 + (u32)u, r.rowe - 1u);
+                            const u32 ti = rbg[k] * (u32)sBn + sidx;
+                            te[u] = T1g[ti];
+                            x[u] = tsg[ti];
+                            c[u] = (k0 + (u32)u < r.rowe) ? ampg[k] : 0.0;
+                        }
                         for (u32 m = At; m; m &= m - 1u) {
                             const int kq = __builtin_ctz(m);
-                            x += p.I.G(jj, bb, kq, kq);
+#pragma unroll
+                            for (int u = 0; u < RT_UNROLL; ++u) x[u] += p.I.G(t1_j(te[u]), t1_b(te[u]), kq, kq);
                         }
-                        (void)betag;
-                        if (t1_par(te)) x = -x;
-                        if (x != 0.0) {
-                            atomicAdd(&acc[t1_rank(te) - tlo], x * ampg[k]);
-                            ++my_terms;
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            if (k0 + (u32)u >= r.rowe) continue;
+                            if (t1_par(te[u])) x[u] = -x[u];
+                            if (x[u] != 0.0) {
+                                atomicAdd(&acc[t1_rank(te[u]) - tlo], x[u] * c[u]);
+                                ++my_terms;
+                            }
                         }
                     }
                 }
@@ -965,6 +1014,47 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
     }
 }
 
+// T2: for every beta string, its beta-beta doubles (i < j occupied -> a < b
+// virtual, pairs in lexicographic order): the target rank, and the element
+// (ia|jb) - (ib|ja) from the pair-indexed table with both phases applied.
+// One wavefront per beta string.
+__global__ __launch_bounds__(64) void k_build_T2(SpaceDev sp, const u64* __restrict__ binom,
+                                                 const double* __restrict__ K4, u32* __restrict__ T2r,
+                                                 double* __restrict__ T2e) {
+    __shared__ BinomLds sB;
+    __shared__ uint8_t occ[32], vir[32];
+    load_binom(sB, binom);
+    __syncthreads();
+    const int n = sp.n, nb = sp.nb, nvb = n - nb;
+    const int QB = nvb * (nvb - 1) / 2, tot = (nb * (nb - 1) / 2) * QB;
+    const u32 np2 = (u32)(n * (n - 1) / 2);
+    const int lane = threadIdx.x;
+    for (u64 rb = blockIdx.x; rb < sp.Nb; rb += gridDim.x) {
+        const u32 beta = str_unrank(rb, nb, n, sB);
+        __syncthreads();
+        if (lane < n) {
+            const u32 below = (1u << lane) - 1u;
+            if ((beta >> lane) & 1u) occ[__popc(beta & below)] = (uint8_t)lane;
+            else vir[lane - __popc(beta & below)] = (uint8_t)lane;
+        }
+        __syncthreads();
+        for (int t = lane; t < tot; t += 64) {
+            const uint16_t pa = decode_pair(t / QB, nb), pv = decode_pair(t % QB, nvb);
+            const int i2 = occ[pa & 255], j2 = occ[pa >> 8];
+            const int a2 = vir[pv & 255], b2 = vir[pv >> 8];
+            const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
+            const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
+            const u64 rt = str_rank(B2, sB);
+            const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
+            const u32 k4 = (u32)(j2 * (j2 - 1) / 2 + i2) * np2 + (u32)(b2 * (b2 - 1) / 2 + a2);
+            double e = K4[k4];
+            if (par) e = -e;
+            T2r[rb * (u64)tot + t] = (u32)rt;
+            T2e[rb * (u64)tot + t] = e;
+        }
+    }
+}
+
 // K4[(i<j), (a<b)] = (ia|jb) - (ib|ja), rounded exactly as in the double's element.
 __global__ void k_build_K4(int n, const double* __restrict__ g, double* __restrict__ K4) {
     const u64 np2 = (u64)n * (n - 1) / 2, t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1064,6 +1154,8 @@ struct RowTileState {
     u32* d_T1 = nullptr;
     double* d_TS = nullptr;
     double* d_K4 = nullptr;
+    u32* d_T2r = nullptr;  // beta-beta doubles per beta string (rows of one tile only):
+    double* d_T2e = nullptr;  // target rank, signed element
     double* d_K = nullptr;  // (pp|qq) - (pq|qp), n^2
     uint16_t* d_toff = nullptr;
 };
@@ -1165,6 +1257,20 @@ bool rowtile_available(sfci_problem* P) {
                            P->stream, P->n, P->d_g, S->d_K4);
         SFCI_CHECK_HIP(hipGetLastError());
     }
+    {
+        // beta-beta doubles per beta string, when a target row is one tile
+        // (each double lands in it) and the table is small
+        const u64 tot = (u64)(P->nb * (P->nb - 1) / 2) * (u64)((P->n - P->nb) * (P->n - P->nb - 1) / 2);
+        const u64 bytes = P->Nb * tot * (sizeof(u32) + sizeof(double));
+        const char* env = getenv("SFCI_NO_T2");
+        if (S->ntiles == 1 && tot > 0 && bytes <= (1ull << 30) && !(env && env[0] == '1')) {
+            SFCI_CHECK_HIP(hipMalloc(&S->d_T2r, P->Nb * tot * sizeof(u32)));
+            SFCI_CHECK_HIP(hipMalloc(&S->d_T2e, P->Nb * tot * sizeof(double)));
+            hipLaunchKernelGGL(k_build_T2, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
+                               P->d_binom, (const double*)S->d_K4, S->d_T2r, S->d_T2e);
+            SFCI_CHECK_HIP(hipGetLastError());
+        }
+    }
     const u64 nK = (u64)P->n * P->n;
     SFCI_CHECK_HIP(hipMalloc(&S->d_K, nK * sizeof(double)));
     hipLaunchKernelGGL(k_build_K, dim3((unsigned)((nK + 255) / 256)), dim3(256), 0, P->stream, P->n, P->d_g, S->d_K);
@@ -1185,6 +1291,8 @@ void rowtile_release(sfci_problem* P) {
     if (S->d_T1) (void)hipFree(S->d_T1);
     if (S->d_TS) (void)hipFree(S->d_TS);
     if (S->d_K4) (void)hipFree(S->d_K4);
+    if (S->d_T2r) (void)hipFree(S->d_T2r);
+    if (S->d_T2e) (void)hipFree(S->d_T2e);
     if (S->d_K) (void)hipFree(S->d_K);
     if (S->d_toff) (void)hipFree(S->d_toff);
     delete S;
@@ -1235,6 +1343,8 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.K2 = S->d_K;
     rp.TS = S->d_TS;
     rp.K4 = S->d_K4;
+    rp.T2r = S->d_T2r;
+    rp.T2e = S->d_T2e;
     rp.eps = eps;
     rp.item_base = 0;
     rp.row_base = 0;
