@@ -453,11 +453,25 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
                 const NbrRec r = list[li];
                 if (r.e1 - r.e0 > 32) continue;
-                for (u32 k = r.e0; k < r.e1; ++k) {
-                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k], itab, nullptr);
-                    if (e != 0.0) {
-                        atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
-                        ++my_terms;
+                // RT_UNROLL entries at a time, their loads in flight together
+                for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
+                    u32 rb[RT_UNROLL], bt[RT_UNROLL];
+                    double c[RT_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        const u32 k = min(k0 + (u32)u, r.e1 - 1u);
+                        rb[u] = p.v_rb[k];
+                        c[u] = p.v_amp[k];
+                        bt[u] = (r.type == 2) ? 0u : p.v_beta[k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        if (k0 + (u32)u >= r.e1) continue;
+                        const double e = (r.type == 2) ? r.cst : direct_element(p, r, bt[u], itab, nullptr);
+                        if (e != 0.0) {
+                            atomicAdd(&acc[rb[u] - tlo], e * c[u]);
+                            ++my_terms;
+                        }
                     }
                 }
             }
@@ -476,11 +490,30 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     wave_sync();
                     gq = wo;
                 }
-                for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                    const double e = (r.type == 2) ? r.cst : direct_element(p, r, p.v_beta[k], itab, gq);
-                    if (e != 0.0) {
-                        atomicAdd(&acc[p.v_rb[k] - tlo], e * p.v_amp[k]);
-                        ++my_terms;
+                // RT_UNROLL chunks of 64 entries at a time, their loads in flight together
+                for (u32 k0 = r.e0; k0 < r.e1; k0 += 64 * RT_UNROLL) {
+                    u32 rb[RT_UNROLL], bt[RT_UNROLL];
+                    double c[RT_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        const u32 k = k0 + (u32)u * 64 + lane;
+                        rb[u] = 0;
+                        bt[u] = 0;
+                        c[u] = 0.0;
+                        if (k < r.e1) {
+                            rb[u] = p.v_rb[k];
+                            c[u] = p.v_amp[k];
+                            if (r.type != 2) bt[u] = p.v_beta[k];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        if (k0 + (u32)u * 64 + lane >= r.e1) continue;
+                        const double e = (r.type == 2) ? r.cst : direct_element(p, r, bt[u], itab, gq);
+                        if (e != 0.0) {
+                            atomicAdd(&acc[rb[u] - tlo], e * c[u]);
+                            ++my_terms;
+                        }
                     }
                 }
             }
