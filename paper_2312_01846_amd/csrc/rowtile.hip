@@ -773,11 +773,22 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                                             ((long long)(par_a ^ t1_par(te)) << 63));
                             };
                             int q = 0;
+                            // the next group's table reads are issued before this group's accumulations
+                            u32 te_next[RT_UNROLL];
+                            if (act && RT_UNROLL <= cnt) {
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) te_next[u] = T1g[rl32(rk, u) * (u32)sBn + sidx];
+                            }
                             for (; q + RT_UNROLL <= cnt; q += RT_UNROLL) {
                                 if (!act) continue;
                                 u32 te[RT_UNROLL];
 #pragma unroll
-                                for (int u = 0; u < RT_UNROLL; ++u) te[u] = T1g[rl32(rk, q + u) * (u32)sBn + sidx];
+                                for (int u = 0; u < RT_UNROLL; ++u) te[u] = te_next[u];
+                                if (q + 2 * RT_UNROLL <= cnt) {
+#pragma unroll
+                                    for (int u = 0; u < RT_UNROLL; ++u)
+                                        te_next[u] = T1g[rl32(rk, q + RT_UNROLL + u) * (u32)sBn + sidx];
+                                }
                                 if (GRAD) {
                                     // weight sbar(target) v(source) with both phases, into the (j, b) slab
                                     double sb[RT_UNROLL];
