@@ -143,7 +143,7 @@ def _tps(n, na, nb):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a design note "
+        print(json.dumps({"error": "this library runs on one GPU; sharding across GPUs is a design note "
                                    "(alpha-rank-range slices), not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.steps is None:

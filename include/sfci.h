@@ -205,7 +205,7 @@ sfci_status sfci_sigma_backward(sfci_problem* prob, const sfci_svec* v, const sf
 sfci_status sfci_pt2(sfci_problem* prob, const sfci_svec* psi, int32_t deterministic, double* e0, double* e2,
                      uint64_t* n_external);
 
-/* ---- batched iteration (spec extension, not in the paper) ----
+/* ---- batched iteration (an extension, not in the paper) ----
  * Many instances (e.g. points along a bond-stretch curve) with uneven
  * truncations M_k, and possibly different orbital counts, iterate together:
  * each sigma application of all instances is one launch of the target-owned

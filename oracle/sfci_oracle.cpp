@@ -858,7 +858,7 @@ extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Backward of sigma = H(h, g) v for a cotangent sbar (spec extension,
+// Backward of sigma = H(h, g) v for a cotangent sbar (an extension,
 // not in the paper).  With L = sbar^T H v:
 //   vbar_i = sum_k H_ki sbar_k                 for i in supp(v)
 //   gamma_pq = sum_ki sbar_k v_i <k| sum_s a+_ps a_qs |i>
