@@ -528,7 +528,20 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const NbrRec r = list[li];
                 if (r.type != 2 || r.e1 - r.e0 > 32) continue;
                 double w = 0.0;
-                for (u32 k = r.e0; k < r.e1; ++k) w += acc[p.v_rb[k] - tlo] * p.v_amp[k];
+                // RT_UNROLL entries' loads in flight together; the sum keeps entry order
+                for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
+                    u32 rb[RT_UNROLL];
+                    double c[RT_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        const u32 k = min(k0 + (u32)u, r.e1 - 1u);
+                        rb[u] = p.v_rb[k];
+                        c[u] = p.v_amp[k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u)
+                        if (k0 + (u32)u < r.e1) w += acc[rb[u] - tlo] * c[u];
+                }
                 if (w != 0.0) {
                     if (r.par) w = -w;
                     atomicAdd(p.Rg + gi(r.i, r.a, r.j, r.b), w);
@@ -546,18 +559,37 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (T == 2 && r.e1 - r.e0 <= 32) continue;
                 if (r.e1 <= r.e0) continue;
                 double wl = 0.0;
-                for (u32 k = r.e0 + lane; k < r.e1; k += 64) {
-                    const double sb = acc[p.v_rb[k] - tlo];
-                    if (sb == 0.0) continue;
-                    const double w = sb * p.v_amp[k];
-                    wl += w;
-                    if (T != 2) {
-                        const u32 beta = p.v_beta[k];
-                        for (u32 m = beta; m; m &= m - 1u) {
-                            const int q = __builtin_ctz(m);
-                            atomicAdd(&wo[q], w);
-                            if (T == 0)
-                                for (u32 m2 = m & (m - 1u); m2; m2 &= m2 - 1u) atomicAdd(&slab[q * n + __builtin_ctz(m2)], w);
+                // RT_UNROLL chunks of 64 entries: their loads in flight together
+                for (u32 k0 = r.e0; k0 < r.e1; k0 += 64 * RT_UNROLL) {
+                    u32 rb[RT_UNROLL], bt[RT_UNROLL];
+                    double c[RT_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        const u32 k = k0 + (u32)u * 64 + lane;
+                        rb[u] = 0;
+                        bt[u] = 0;
+                        c[u] = 0.0;
+                        if (k < r.e1) {
+                            rb[u] = p.v_rb[k];
+                            c[u] = p.v_amp[k];
+                            if (T != 2) bt[u] = p.v_beta[k];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < RT_UNROLL; ++u) {
+                        if (k0 + (u32)u * 64 + lane >= r.e1) continue;
+                        const double sb = acc[rb[u] - tlo];
+                        if (sb == 0.0) continue;
+                        const double w = sb * c[u];
+                        wl += w;
+                        if (T != 2) {
+                            for (u32 m = bt[u]; m; m &= m - 1u) {
+                                const int q = __builtin_ctz(m);
+                                atomicAdd(&wo[q], w);
+                                if (T == 0)
+                                    for (u32 m2 = m & (m - 1u); m2; m2 &= m2 - 1u)
+                                        atomicAdd(&slab[q * n + __builtin_ctz(m2)], w);
+                            }
                         }
                     }
                 }
