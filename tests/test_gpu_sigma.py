@@ -202,3 +202,25 @@ def test_error_paths(torch, S, orc):
     sr, sa, _ = P.sigma(np.array([0], dtype=np.int64), np.array([1.0]))
     o1r, o1a = orc.Problem(8, 3, 3, h, g).sigma(np.array([0], dtype=np.uint64), np.array([1.0]))
     assert np.array_equal(_np(sr).astype(np.uint64), o1r)
+
+
+@pytest.mark.parametrize("n,na,nb", [(7, 3, 0), (7, 0, 3), (6, 2, 6), (6, 6, 2)],
+                         ids=["no_beta", "no_alpha", "beta_full", "alpha_full"])
+@pytest.mark.parametrize("mode", ["sort", "dense", "dense_atomic"])
+def test_sigma_degenerate_spin_spaces(torch, S, orc, n, na, nb, mode):
+    # one spin with a single string (N = 1 rows or columns): the row passes
+    # sort 0 bits (N_beta = 1) or hold one alpha row; tables have no singles
+    h, g = synth.molecule_like(n, 2 * n, 4)
+    P, Po = _prob(S, orc, n, na, nb, h, g)
+    nd = P.n_det
+    k = max(1, nd // 3)
+    rng = np.random.default_rng(7)
+    r = np.sort(rng.choice(nd, size=k, replace=False)).astype(np.uint64)
+    a = rng.standard_normal(k)
+    gr, ga, _ = P.sigma(r.astype(np.int64), a, dedup=mode, deterministic=(mode == "sort"))
+    orr, oa = Po.sigma(r, a)
+    assert np.array_equal(_np(gr).astype(np.uint64), orr)
+    if mode == "sort":
+        assert np.array_equal(_np(ga), oa)
+    else:
+        assert np.allclose(_np(ga), oa, rtol=0, atol=1e-12 * max(1.0, np.abs(oa).max()))
