@@ -307,17 +307,21 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     SigmaLaunch sl{v->rank, v->amp, scal, v->nnz};
     const u64 tps = terms_per_source(P->n, P->na, P->nb);
     bool use_sort = opts->deterministic || opts->dedup == SFCI_DEDUP_SORT;
+    bool list_tiles = false;  // no N_det array, fast: the tile kernel's slices may serve
     if (!use_sort && !ensure_dense(P)) {
         if (opts->dedup == SFCI_DEDUP_DENSE || opts->dedup == SFCI_DEDUP_DENSE_ATOMIC)
             return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "dense accumulator does not fit on the device");
         use_sort = true;
+        list_tiles = true;
     }
     if (use_sort) {
-        // sort path: alpha-range passes into a running top-M candidate list,
-        // no N_det array and no full-length sigma list
+        // alpha-range passes (sort path, or tile-kernel slices in fast mode)
+        // into a running top-M candidate list, no N_det array and no
+        // full-length sigma list
         u64 distinct = 0;
         const u64 need = sigma_list_topm(P, sl, opts->M, out->rank, out->amp,
-                                         (out->rank && out->amp) ? out->capacity : 0, &scal[1], &distinct);
+                                         (out->rank && out->amp) ? out->capacity : 0, &scal[1], &distinct,
+                                         list_tiles);
         SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
         const u64 emitted = read_u64(P, &scal[1]);
         out->nnz = need;

@@ -407,8 +407,10 @@ void sort_by_rank(sfci_problem* P, u64* r, double* a, u64 n) {
 
 }  // namespace
 
+u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, double eps);
+
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
-                    u64* emitted_dev, u64* distinct_host) {
+                    u64* emitted_dev, u64* distinct_host, bool tiles_ok) {
     ListWs& ws = P->list_ws;
     u64* ls = (u64*)ws.scal.get(128 * sizeof(u64));  // [0] Rn [1] bound [2] pass count [3] overflow [4] distinct [8..) bounds
     launch_fill_u64(ls, 128, 0, P->stream);
@@ -420,7 +422,10 @@ u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank,
     sink.bounds = ls + 8;
     sink.pcount = ls + 2;
     sink.distinct = ls + 4;
-    sigma_sorted_passes(P, v, sink, emitted_dev, 0, 0.0);
+    if (tiles_ok && list_sigma_tiles(P, read_dev(P, v.v_nnz)))
+        sigma_dense_passes(P, v, sink, emitted_dev, 0.0);
+    else
+        sigma_sorted_passes(P, v, sink, emitted_dev, 0, 0.0);
     check_overflow(P, (const int*)(ls + 3));
     C.n_upper = read_dev(P, C.Rn);
     CandSrc src{};

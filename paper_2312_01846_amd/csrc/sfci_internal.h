@@ -349,11 +349,16 @@ struct EventTimer {
 };
 
 // ---- list-based iteration and truncated sigma without an N_det array (listlz.hip) ----
-// sigma = H v through the sort path's passes; the top-M (tie rule) sorted by
-// rank into out when it fits out_cap.  Returns the selected count;
-// *distinct_host (may be NULL) receives the number of distinct nonzero entries.
+// sigma = H v in passes of target alpha rows (the sort path's, or with
+// tiles_ok the tile kernel's slices when the per-sigma cost rule picks them);
+// the top-M (tie rule) sorted by rank into out when it fits out_cap.  Returns
+// the selected count; *distinct_host (may be NULL) receives the number of
+// distinct nonzero entries.
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
-                    u64* emitted_dev, u64* distinct_host);
+                    u64* emitted_dev, u64* distinct_host, bool tiles_ok);
+// Fast mode's per-sigma choice between the tile kernel's slices (true) and
+// the sort path, from the input's size (SFCI_LIST_SIGMA=tile|sort forces one).
+bool list_sigma_tiles(sfci_problem* P, u64 nnz);
 // sigma = H v in full through the sort path's passes, no N_det array: the
 // nonzero entries sorted by rank in list_ws.Rr / Ra; returns their number.
 u64 sigma_list_full(sfci_problem* P, const SigmaLaunch& v, u64* emitted_dev, u64** r, double** a);

@@ -168,3 +168,40 @@ def test_28_orbitals_sigma_topm_sampled(torch, S, orc, c3_problem):
             assert abs(v) <= cut + 1e-12 * ab, (int(t), v, cut)
             probes += 1
     assert probes > 0
+
+
+def test_28_orbitals_M1e7_tile_sigma_sampled(torch, S, orc, c3_problem, monkeypatch):
+    # the size the 28-orbital benchmark times: sigma of a 1e7-entry vector
+    # (2.5e11 terms) through the tile kernel in row slices, top-M kept; sampled
+    # kept entries recomputed one by one by the oracle, sampled unkept
+    # neighbours of kept targets at or below the M-th magnitude
+    P, h, g = c3_problem
+    M = 10_000_000
+    r1, a1, _ = P.sigma(*_c3_start(P), M=M)
+    r2, a2, _ = P.sigma(r1, a1, M=M)
+    assert r2.numel() >= M
+    monkeypatch.setenv("SFCI_LIST_SIGMA", "tile")
+    gr, ga, st = P.sigma(r2, a2, M=M)
+    kr, ka = _np(r2).astype(np.uint64), _np(a2)
+    gr, ga = _np(gr).astype(np.uint64), _np(ga)
+    assert st["terms_enumerated"] == len(kr) * P.tps
+    assert M <= len(gr) <= M + S.TIE_SLACK
+    assert np.all(np.diff(gr.astype(np.int64)) > 0)
+    Po = orc.Problem(28, 6, 6, h, g)
+    rng = np.random.default_rng(11)
+    for i in rng.choice(len(gr), 16, replace=False):
+        v, ab = Po.sigma_entry(kr, ka, int(gr[i]))
+        assert abs(ga[i] - v) <= 1e-12 * ab, (int(gr[i]), ga[i], v, ab)
+    cut = np.sort(np.abs(ga))[::-1][M - 1]
+    probes = 0
+    for i in rng.choice(len(gr), 20, replace=False):
+        nr, _, _ = P.sigma(np.array([int(gr[i])], dtype=np.int64), np.array([1.0]))
+        for t in _np(nr)[rng.choice(len(nr), 3, replace=False)]:
+            t = int(t)
+            pos = np.searchsorted(gr, np.uint64(t))
+            if pos < len(gr) and int(gr[pos]) == t:
+                continue
+            v, ab = Po.sigma_entry(kr, ka, t)
+            assert abs(v) <= cut + 1e-12 * ab, (t, v, cut)
+            probes += 1
+    assert probes > 0
