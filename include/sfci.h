@@ -121,6 +121,9 @@ sfci_status sfci_unrank(sfci_problem* prob, const uint64_t* rank, uint64_t count
 
 /* sigma = H v, then the M largest entries (Eqs. 10-11 order, not normalised),
  * written to out sorted by rank.  v must be strictly ascending with ranks < N_det.
+ * When the N_det accumulator does not fit the device, sigma is formed in
+ * passes of target alpha rows into a running top-M candidate list (the sort
+ * path; in fast mode the tile kernel's row slices once the input is large).
  * On SFCI_E_CAPACITY, out->nnz is set to the size needed and nothing is written.
  * stats may be NULL.  Synchronises the stream (returns out->nnz). */
 sfci_status sfci_sigma(sfci_problem* prob, const sfci_svec* v, const sfci_sigma_opts* opts, sfci_svec* out,
