@@ -398,17 +398,41 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
                 const u32 nf = (u32)(e1 - e0) * sBn;
                 const __attribute__((address_space(1))) double* gia =
                     (const __attribute__((address_space(1))) double*)c.I.g + (u64)(i * n + a) * n * n;
-                for (u32 f = lane; f < nf; f += 64) {
-                    const u32 de = f / sBn, o = f - de * sBn;
-                    const u64 s = pr.beg + e0 + de;
-                    const u64 rB = c.v_rank[s] - (u64)pr.src_row * Nb;
-                    const u32 t = c.T1[rB * sBn + o];
-                    double el = gia[((t >> 21) & 31u) * n + ((t >> 26) & 31u)];
-                    if (pa ^ (int)(t >> 31)) el = -el;
-                    const u64 at = pr.tup_off + (e0 + de) * cp + 1 + o;
-                    keys[at] = (u32)(tgt_base + (t & 0x1FFFFFu));
-                    vals[at] = el * c.v_amp[s];
-                    nz += (el != 0.0) ? 1 : 0;
+                // four groups of 64 options at a time: each level of the
+                // dependent loads (entry rank, table entry, integral) is in
+                // flight for all four groups together
+                constexpr int EU = 4;
+                for (u32 f0 = 0; f0 < nf; f0 += 64 * EU) {
+                    u64 s[EU], at[EU];
+                    u32 o[EU], t[EU];
+                    double am[EU], el[EU];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        const u32 f = min(f0 + (u32)u * 64 + lane, nf - 1u);
+                        const u32 de = f / sBn;
+                        o[u] = f - de * sBn;
+                        s[u] = pr.beg + e0 + de;
+                        at[u] = pr.tup_off + (e0 + de) * cp + 1 + o[u];
+                    }
+                    u64 rB[EU];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        rB[u] = c.v_rank[s[u]] - (u64)pr.src_row * Nb;
+                        am[u] = c.v_amp[s[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) t[u] = c.T1[rB[u] * sBn + o[u]];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) el[u] = gia[((t[u] >> 21) & 31u) * n + ((t[u] >> 26) & 31u)];
+#pragma unroll
+                    for (int u = 0; u < EU; ++u) {
+                        if (f0 + (u32)u * 64 + lane >= nf) continue;
+                        double e = el[u];
+                        if (pa ^ (int)(t[u] >> 31)) e = -e;
+                        keys[at[u]] = (u32)(tgt_base + (t[u] & 0x1FFFFFu));
+                        vals[at[u]] = e * am[u];
+                        nz += (e != 0.0) ? 1 : 0;
+                    }
                 }
                 continue;
             }
