@@ -308,21 +308,40 @@ __global__ __launch_bounds__(RPP_BLOCK) void k_rp_pairs(RPConst c, u64 lo, u64 h
             u64 dtot;
             const u64 dpre = wave_excl_scan(dne, &dtot);
             const u64 src_base = (u64)pr.src_row * Nb - (u64)pr.tgt_local * Nb;  // rank shift, mod 2^64
-            for (u64 f0 = 0; f0 < dtot; f0 += 64) {
-                const u64 f = f0 + lane;
-                int L = 0;
-                for (int step = 32; step >= 1; step >>= 1) {
-                    const u64 v = (u64)__shfl((long long)dpre, L + step);
-                    if (v <= f) L += step;
+            // four groups of 64 at a time: the lane searches first, then all
+            // the groups' loads together
+            constexpr int DU = 4;
+            for (u64 f0 = 0; f0 < dtot; f0 += 64 * DU) {
+                u64 s[DU], o[DU], sb[DU];
+                double e2[DU];
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const u64 f = f0 + (u64)u * 64 + lane;
+                    int L = 0;
+                    for (int step = 32; step >= 1; step >>= 1) {
+                        const u64 v = (u64)__shfl((long long)dpre, L + step);
+                        if (v <= f) L += step;
+                    }
+                    const u64 e = f - (u64)__shfl((long long)dpre, L);
+                    s[u] = (u64)__shfl((long long)pr.beg, L) + e;
+                    o[u] = (u64)__shfl((long long)at, L) + e;
+                    sb[u] = (u64)__shfl((long long)src_base, L);
+                    e2[u] = __shfl(pr.e2, L);
                 }
-                const u64 e = f - (u64)__shfl((long long)dpre, L);
-                const u64 s = (u64)__shfl((long long)pr.beg, L) + e;
-                const u64 o = (u64)__shfl((long long)at, L) + e;
-                const u64 sb = (u64)__shfl((long long)src_base, L);
-                const double e2 = __shfl(pr.e2, L);
-                if (f < dtot) {
-                    tkeys[o] = (u32)(c.v_rank[s] - sb);
-                    tvals[o] = e2 * c.v_amp[s];
+                u64 rk[DU];
+                double am[DU];
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const bool ok = f0 + (u64)u * 64 + lane < dtot;
+                    rk[u] = ok ? c.v_rank[s[u]] : 0;
+                    am[u] = ok ? c.v_amp[s[u]] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    if (f0 + (u64)u * 64 + lane < dtot) {
+                        tkeys[o[u]] = (u32)(rk[u] - sb[u]);
+                        tvals[o[u]] = e2[u] * am[u];
+                    }
                 }
             }
             run += tot;
