@@ -262,7 +262,16 @@ __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_runs(const K* __restrict
             if (j < H) {
                 const int s0 = hpos[wave][j];
                 const int e = (j + 1 < H) ? (int)hpos[wave][j + 1] : e_last;
-                for (int q = s0; q < e; ++q) acc += sv[wave][q];
+                // four values read ahead, added one by one in index order
+                int q = s0;
+                for (; q + 4 <= e; q += 4) {
+                    const double x0 = sv[wave][q], x1 = sv[wave][q + 1], x2 = sv[wave][q + 2], x3 = sv[wave][q + 3];
+                    acc += x0;
+                    acc += x1;
+                    acc += x2;
+                    acc += x3;
+                }
+                for (; q < e; ++q) acc += sv[wave][q];
                 key = keys[a + s0];
                 if (j + 1 < H) keep = keep_sum(acc, eps);
                 else part = acc;
@@ -287,8 +296,17 @@ __global__ __launch_bounds__(64 * SEG_WAVES) void k_seg_runs(const K* __restrict
             const int cnt = diff ? (int)__builtin_ctzll(diff) : 64;
             sv[wave][lane] = (lane < cnt) ? vals[i] : 0.0;
             wave_sync();
-            if (lane == 0)
-                for (int q = 0; q < cnt; ++q) acc += sv[wave][q];
+            if (lane == 0) {
+                int q = 0;
+                for (; q + 4 <= cnt; q += 4) {
+                    const double x0 = sv[wave][q], x1 = sv[wave][q + 1], x2 = sv[wave][q + 2], x3 = sv[wave][q + 3];
+                    acc += x0;
+                    acc += x1;
+                    acc += x2;
+                    acc += x3;
+                }
+                for (; q < cnt; ++q) acc += sv[wave][q];
+            }
             wave_sync();
             if (diff) break;
         }
