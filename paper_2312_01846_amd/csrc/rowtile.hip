@@ -933,17 +933,32 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     W.c[lane] = c;
                     wave_sync();
                     const unsigned excl = incl - len;
-                    for (unsigned q0 = 0; q0 < total; q0 += 64) {
-                        const unsigned q = q0 + lane;
-                        // entry of item q: the last lane whose first item is <= q
-                        // (a lane with no items shares its first item with the next)
-                        int x = 0;
-                        for (int step = 32; step >= 1; step >>= 1) {
-                            const unsigned v = (unsigned)__shfl((int)excl, x + step);
-                            if (v <= q) x += step;
+                    // two groups of 64 items at a time: both table reads in flight together
+                    for (unsigned q00 = 0; q00 < total; q00 += 128) {
+                        unsigned qg[2];
+                        int xg[2];
+                        u32 tg[2];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            qg[u] = q00 + (unsigned)u * 64 + lane;
+                            // entry of item q: the last lane whose first item is <= q
+                            // (a lane with no items shares its first item with the next)
+                            int x = 0;
+                            for (int step = 32; step >= 1; step >>= 1) {
+                                const unsigned v = (unsigned)__shfl((int)excl, x + step);
+                                if (v <= qg[u]) x += step;
+                            }
+                            xg[u] = x;
                         }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+                            tg[u] = (qg[u] < total) ? p.T1[W.start[xg[u]] + (qg[u] - W.excl[xg[u]])] : 0u;
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                        const unsigned q = qg[u];
+                        const int x = xg[u];
                         if (q < total) {
-                            const u32 te = p.T1[W.start[x] + (q - W.excl[x])];
+                            const u32 te = tg[u];
                             const u32 rt = t1_rank(te);
                             const int jj = t1_j(te), bb = t1_b(te);
                             const int par_b = t1_par(te);
@@ -972,6 +987,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 atomicAdd(&acc[rt - tlo], e * W.c[x]);
                                 ++my_terms;
                             }
+                        }
                         }
                     }
                 }
