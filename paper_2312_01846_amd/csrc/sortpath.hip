@@ -3,10 +3,12 @@
 // linear scan; buckets are ranges of the hash, restricted to the spin-up part
 // of the string in Sec. 3).  On the GPU:
 //   * a pass covers a range of target alpha ranks (a contiguous rank range);
-//   * exact per-source tuple counts are scanned into emission offsets, so the
-//     tuples of every source land in one contiguous, source-ordered block;
-//   * a stable LSD radix sort by target keeps that order inside equal keys;
-//   * one thread per run of equal keys adds the values in order.
+//   * tuples are emitted at fixed offsets so that the contributions to every
+//     target sit in ascending source order (target-row-driven emission, or the
+//     source-driven one kept as a cross-check);
+//   * a stable LSD radix sort by target keeps that order inside equal keys
+//     (with row-grouped tuples only the beta rank is sorted, inside each row);
+//   * each run of equal keys is added in index order by one lane.
 // Every target therefore receives its contributions in ascending source
 // order: the result is bit-reproducible and independent of scheduling.
 #include <algorithm>
