@@ -1,8 +1,10 @@
 // The SFCI iteration (Sec. 2.1) without a dense N_det array: every vector is
-// a rank-sorted (rank, amplitude) list and sigma = H w_j comes from the sort
-// path one alpha-rank range at a time (Sec. 2.2's buckets, restricted to the
-// spin-up string as in Sec. 3).  This is what runs when 8 N_det bytes do not
-// fit the device (12 electrons in 28 orbitals: 1.14 TB).
+// a rank-sorted (rank, amplitude) list and sigma = H w_j comes one alpha-rank
+// range at a time (Sec. 2.2's buckets, restricted to the spin-up string as in
+// Sec. 3) from the sort path, or in fast mode from the tile kernel in row
+// slices when the input is large enough (list_sigma_tiles).  This is what runs
+// when 8 N_det bytes do not fit the device (12 electrons in 28 orbitals:
+// 1.14 TB).
 //
 // Per sigma application, each pass's reduced entries y (ascending ranks of
 // one alpha range) are consumed at once:
