@@ -205,3 +205,44 @@ def test_28_orbitals_M1e7_tile_sigma_sampled(torch, S, orc, c3_problem, monkeypa
             assert abs(v) <= cut + 1e-12 * ab, (t, v, cut)
             probes += 1
     assert probes > 0
+
+
+def test_26_orbitals_M1e7_dense_sigma_sampled(torch, S, orc):
+    # 10 electrons in 26 orbitals (4.33e9 determinants): the dense accumulator
+    # (34.6 GB) and one tile-kernel launch per sigma, as the 26-orbital
+    # workload runs; sigma of a 1e7-entry vector (1.5e11 terms), top-M kept,
+    # sampled against the oracle entry by entry
+    h, g = synth.molecule_like(26, 52, 2)
+    P = S.Problem(26, 5, 5, h, g)
+    st = synth.perturbed_start(26, 5, 5)
+    r0 = P.rank([t[0] for t in st], [t[1] for t in st]).cpu().numpy()
+    a0 = np.array([t[2] for t in st])
+    o = np.argsort(r0, kind="stable")
+    M = 10_000_000
+    r1, a1, _ = P.sigma(r0[o], a0[o], M=M)
+    r2, a2, _ = P.sigma(r1, a1, M=M)
+    assert r2.numel() >= M
+    gr, ga, st2 = P.sigma(r2, a2, M=M, dedup="dense")
+    kr, ka = _np(r2).astype(np.uint64), _np(a2)
+    gr, ga = _np(gr).astype(np.uint64), _np(ga)
+    assert st2["terms_enumerated"] == len(kr) * P.tps
+    assert M <= len(gr) <= M + S.TIE_SLACK
+    assert np.all(np.diff(gr.astype(np.int64)) > 0)
+    Po = orc.Problem(26, 5, 5, h, g)
+    rng = np.random.default_rng(5)
+    for i in rng.choice(len(gr), 16, replace=False):
+        v, ab = Po.sigma_entry(kr, ka, int(gr[i]))
+        assert abs(ga[i] - v) <= 1e-12 * ab, (int(gr[i]), ga[i], v, ab)
+    cut = np.sort(np.abs(ga))[::-1][M - 1]
+    probes = 0
+    for i in rng.choice(len(gr), 20, replace=False):
+        nr, _, _ = P.sigma(np.array([int(gr[i])], dtype=np.int64), np.array([1.0]))
+        for t in _np(nr)[rng.choice(len(nr), 3, replace=False)]:
+            t = int(t)
+            pos = np.searchsorted(gr, np.uint64(t))
+            if pos < len(gr) and int(gr[pos]) == t:
+                continue
+            v, ab = Po.sigma_entry(kr, ka, t)
+            assert abs(v) <= cut + 1e-12 * ab, (t, v, cut)
+            probes += 1
+    assert probes > 0
