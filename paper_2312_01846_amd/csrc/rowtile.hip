@@ -73,10 +73,6 @@ struct NbrRec {
 };
 
 struct WaveScratch {
-    unsigned excl[64];
-    unsigned start[64];
-    u32 beta[64];
-    double c[64];
     uint8_t occ[32], vir[32];
 };
 
@@ -926,18 +922,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         if (lane >= off) incl += y;
                     }
                     const unsigned total = __shfl(incl, 63);
-                    wave_sync();
-                    W.excl[lane] = incl - len;
-                    W.start[lane] = st;
-                    W.beta[lane] = beta;
-                    W.c[lane] = c;
-                    wave_sync();
+                    (void)beta;
                     const unsigned excl = incl - len;
                     // two groups of 64 items at a time: both table reads in flight together
                     for (unsigned q00 = 0; q00 < total; q00 += 128) {
-                        unsigned qg[2];
+                        unsigned qg[2], ig[2];
                         int xg[2];
                         u32 tg[2];
+                        double cg[2];
 #pragma unroll
                         for (int u = 0; u < 2; ++u) {
                             qg[u] = q00 + (unsigned)u * 64 + lane;
@@ -949,14 +941,16 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 if (v <= qg[u]) x += step;
                             }
                             xg[u] = x;
+                            // the item's table index and its entry's amplitude, from lane x
+                            ig[u] = (unsigned)__shfl((int)st, x) + (qg[u] - (unsigned)__shfl((int)excl, x));
+                            cg[u] = __shfl(c, x);
                         }
 #pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            tg[u] = (qg[u] < total) ? p.T1[W.start[xg[u]] + (qg[u] - W.excl[xg[u]])] : 0u;
+                        for (int u = 0; u < 2; ++u) tg[u] = (qg[u] < total) ? p.T1[ig[u]] : 0u;
 #pragma unroll
                         for (int u = 0; u < 2; ++u) {
                         const unsigned q = qg[u];
-                        const int x = xg[u];
+                        const double cx = cg[u];
                         if (q < total) {
                             const u32 te = tg[u];
                             const u32 rt = t1_rank(te);
@@ -965,7 +959,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             if (GRAD) {
                                 const double sb = acc[rt - tlo];
                                 if (sb != 0.0) {
-                                    double w = sb * W.c[x];
+                                    double w = sb * cx;
                                     if (r.par ^ par_b) w = -w;
                                     atomicAdd(&slab[jj * n + bb], w);
                                 }
@@ -976,7 +970,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 e = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
                                 if (r.par ^ par_b) e = -e;
                             } else {
-                                e = p.TS[W.start[x] + (q - W.excl[x])];
+                                e = p.TS[ig[u]];
                                 for (u32 m = At; m; m &= m - 1u) {
                                     const int kq = __builtin_ctz(m);
                                     e += p.I.G(jj, bb, kq, kq);
@@ -984,7 +978,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 if (par_b) e = -e;
                             }
                             if (e != 0.0) {
-                                atomicAdd(&acc[rt - tlo], e * W.c[x]);
+                                atomicAdd(&acc[rt - tlo], e * cx);
                                 ++my_terms;
                             }
                         }
