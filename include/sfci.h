@@ -70,13 +70,17 @@ typedef struct {
     uint64_t capacity; /* entries allocated */
 } sfci_svec;
 
-/* Truncation to M (Sec. 2.1 keeps the largest entries; the paper is silent on
- * ties).  Entries are ordered by |c| descending, rank ascending, and the first
- * M kept; every further entry whose |c| is >= (1 - 2^-36) times the M-th |c|
- * is kept too, so partners of equal magnitude in exact arithmetic (e.g.
+/* Truncation to M (Sec. 2.1, Eqs. 10-11: each basis vector keeps N_d = M
+ * entries, the largest in magnitude).  Nonzero entries are ordered by |c|
+ * descending and exact ties by rank ascending (the paper leaves ties open);
+ * the first min(M, nonzero) are kept.  This is the default everywhere.
+ *
+ * tie_band = 1 in the options switches on an extension that is not the
+ * paper's rule: every further entry whose |c| is >= (1 - 2^-36) times the M-th
+ * |c| is kept too, so partners of equal magnitude in exact arithmetic (e.g.
  * alpha/beta-exchanged determinants when n_alpha = n_beta) are not split by
- * rounding -- unless that adds more than SFCI_TIE_SLACK entries, in which case
- * exactly M are kept.  A truncated vector therefore holds at most
+ * rounding -- unless that adds more than SFCI_TIE_SLACK entries, in which
+ * case exactly M are kept.  With the band a truncated vector holds at most
  * M + SFCI_TIE_SLACK entries; size outputs accordingly. */
 #define SFCI_TIE_SLACK 256
 
@@ -92,6 +96,10 @@ typedef struct {
     uint64_t M;        /* keep the M largest |sigma_k| (ties: see SFCI_TIE_SLACK); UINT64_MAX = all */
     int32_t dedup;     /* SFCI_DEDUP_* */
     int32_t deterministic; /* 1: sort dedup and ordered reductions, bit-reproducible */
+    double screen_eps; /* Sec. 3: merged entries with |sigma_k| < screen_eps are dropped before the
+                          truncation (the paper uses 5e-5); 0 = off */
+    int32_t tie_band;  /* 1: the truncation extension described at SFCI_TIE_SLACK; 0 = the paper's rule */
+    int32_t reserved;  /* must be 0 */
 } sfci_sigma_opts;
 
 typedef struct {
@@ -131,8 +139,10 @@ sfci_status sfci_sigma(sfci_problem* prob, const sfci_svec* v, const sfci_sigma_
 
 /* Truncation alone (Eqs. 10-11 without the division): the M largest |amp| of v
  * (ties: see SFCI_TIE_SLACK), by ascending rank, into out.  Zero amplitudes are dropped.
- * normalise != 0 divides the kept amplitudes by their 2-norm (Eq. 11). */
-sfci_status sfci_topm(sfci_problem* prob, const sfci_svec* v, uint64_t M, int32_t normalise, sfci_svec* out);
+ * normalise != 0 divides the kept amplitudes by their 2-norm (Eq. 11).
+ * tie_band: as in sfci_sigma_opts. */
+sfci_status sfci_topm(sfci_problem* prob, const sfci_svec* v, uint64_t M, int32_t normalise, int32_t tie_band,
+                      sfci_svec* out);
 
 typedef struct {
     uint64_t M;            /* N_d of Sec. 2.1: entries kept per basis vector (at most M + SFCI_TIE_SLACK); UINT64_MAX = all */
@@ -147,6 +157,11 @@ typedef struct {
     int32_t autotune;      /* batched fast mode: 1 = choose the tile kernel's work sizes (beta singles and
                               beta-beta doubles per work unit, workgroups per CU) by timing candidates on the
                               last eager sigma step, once per batch; later calls reuse the choice */
+    double conv_eps;       /* Sec. 2.1 halting: > 0 stops after block n >= 1 once E(n-1) - E(n) < conv_eps
+                              (the signed change, as the paper writes it); 0 = run n_iter / n_L blocks.
+                              Not available in the batched call (SFCI_E_UNSUPPORTED there). */
+    int32_t tie_band;      /* 1: the truncation extension described at SFCI_TIE_SLACK; 0 = the paper's rule */
+    int32_t reserved;      /* must be 0 */
 } sfci_lanczos_opts;
 
 typedef struct {
@@ -155,11 +170,14 @@ typedef struct {
     uint64_t terms_emitted;    /* of those, with a nonzero element */
     double sigma_ms;           /* summed device time of the sigma expansion kernels (HIP events) */
     double total_ms;           /* device time of the whole call */
+    int32_t blocks_run;        /* blocks run (fewer than n_iter / n_L when conv_eps halted the run) */
+    int32_t reserved;
 } sfci_lanczos_stats;
 
 /* The SFCI iteration of Sec. 2.1 from start vector v0 (normalised internally).
  * energies[b] (host, n_iter/n_L entries) receives each block's lowest
- * generalized eigenvalue of (T, S).  psi_out (device, may be NULL) receives the
+ * generalized eigenvalue of (T, S); blocks not run (conv_eps halting) get
+ * NaN.  psi_out (device, may be NULL) receives the
  * last block's Psi = sum_j x_j w_j before truncation; SFCI_E_CAPACITY (with
  * psi_out->nnz = needed) if it does not fit, energies still valid.
  * T_out/S_out (host, may be NULL) receive each block's n_L x n_L matrices,
@@ -207,6 +225,21 @@ sfci_status sfci_sigma_backward(sfci_problem* prob, const sfci_svec* v, const sf
  * Synchronises.  SFCI_E_ARG for an empty or zero-norm Psi. */
 sfci_status sfci_pt2(sfci_problem* prob, const sfci_svec* psi, int32_t deterministic, double* e0, double* e2,
                      uint64_t* n_external);
+
+/* The energy of a vector and its integral gradients at fixed Psi (device
+ * vector, strictly ascending ranks, any nonzero norm):
+ *   *energy (host) = <Psi|H|Psi> / <Psi|Psi>   (Sec. 2.1, Eq. 9);
+ *   dh (device n*n, may be NULL) and deri (device n^4, may be NULL) = the
+ *   gradients of that quotient along symmetric perturbations of h and eri
+ *   (an extension, not in the paper), i.e. sfci_sigma_backward with v = Psi
+ *   and sbar = Psi / <Psi|Psi>; at an eigenvector these are the energy's
+ *   Hellmann-Feynman derivatives.
+ * deterministic != 0: H Psi from the sort path and the energy's sums in
+ * ascending rank (bit-reproducible); else the dense tile kernel and tree
+ * reductions.  The gradients need the dense array (SFCI_E_UNSUPPORTED when
+ * it does not fit).  Synchronises.  SFCI_E_ARG for an empty or zero-norm Psi. */
+sfci_status sfci_energy_gradients(sfci_problem* prob, const sfci_svec* psi, int32_t deterministic, double* energy,
+                                  double* dh, double* deri);
 
 /* ---- batched iteration (an extension, not in the paper) ----
  * Many instances (e.g. points along a bond-stretch curve) with uneven

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sfci_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
+CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-Wall"]
 
 
 def build(force: bool = True) -> str:
@@ -62,6 +62,7 @@ def lib():
         L.orc_sigma_entry.restype = dbl
         L.orc_sigma_entry.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, u64, C.POINTER(dbl)]
         L.orc_topm.restype = i64; L.orc_topm.argtypes = [i64, u64p, f64p, i64, u64p, f64p]
+        L.orc_topm_band.restype = i64; L.orc_topm_band.argtypes = [i64, u64p, f64p, i64, u64p, f64p, i32]
         L.orc_normalize.restype = dbl; L.orc_normalize.argtypes = [i64, f64p]
         L.orc_jacobi.restype = None; L.orc_jacobi.argtypes = [i32, f64p, f64p, f64p]
         L.orc_geneig.restype = i32; L.orc_geneig.argtypes = [i32, f64p, f64p, C.POINTER(dbl), f64p]
@@ -71,6 +72,11 @@ def lib():
         L.orc_lanczos_roots.restype = i64
         L.orc_lanczos_roots.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp,
                                         vp, vp, i64, dbl, i32, vp, vp, vp]
+        L.orc_lanczos_ex.restype = i64
+        L.orc_lanczos_ex.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp,
+                                     vp, vp, i64, dbl, i32, vp, vp, vp, i32, dbl, C.POINTER(i32), vp]
+        L.orc_set_threads.restype = None; L.orc_set_threads.argtypes = [i32]
+        L.orc_get_threads.restype = i32; L.orc_get_threads.argtypes = []
         L.orc_pt2.restype = i32
         L.orc_pt2.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, C.POINTER(dbl), C.POINTER(dbl),
                               C.POINTER(u64)]
@@ -165,8 +171,12 @@ class Problem:
         v = lib().orc_sigma_entry(*self._a(), len(ranks), _u64(ranks), _f64(amps), int(target), C.byref(ab))
         return v, ab.value
 
-    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0, roots=None):
-        """roots: list of (ranks, amps) of previously found eigenvectors to project out."""
+    def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0, roots=None, tie_band=False,
+                conv_eps=0.0):
+        """roots: list of (ranks, amps) of previously found eigenvectors to project out.
+        tie_band: the truncation extension of orc_topm_band (default: the paper's rule).
+        conv_eps > 0: halt after block n >= 1 once E(n-1) - E(n) < conv_eps; the
+        result's "blocks_run" says how many blocks ran (energies beyond it stay 0)."""
         M = -1 if M is None else int(M)
         nblk = n_iter // n_L
         en = np.zeros(nblk, dtype=np.float64)
@@ -181,16 +191,27 @@ class Problem:
                     else np.zeros(1, dtype=np.uint64))
         acat = _f64(np.concatenate([np.asarray(aa, dtype=np.float64) for _, aa in roots]) if roots
                     else np.zeros(1))
-        args = (float(eps), len(roots), _ptr(off), _ptr(rcat), _ptr(acat))
-        need = lib().orc_lanczos_roots(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), None,
-                                       None, 0, *args)
+        nrun = C.c_int(0)
+        bnnz = np.zeros(nblk * n_L, dtype=np.int64)
+        args = (float(eps), len(roots), _ptr(off), _ptr(rcat), _ptr(acat), 1 if tie_band else 0, float(conv_eps),
+                C.byref(nrun), _ptr(bnnz))
+        # Psi holds at most n_L truncated vectors (or the whole space): one run
+        # fills it; a second run happens only if that bound is too small
+        cap = self.n_det if M < 0 else min(self.n_det, n_L * (M + (256 if tie_band else 0)))
+        pr = np.empty(max(cap, 1), dtype=np.uint64)
+        pa = np.empty(max(cap, 1), dtype=np.float64)
+        need = lib().orc_lanczos_ex(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, _ptr(T), _ptr(S), _ptr(pr),
+                                    _ptr(pa), cap, *args)
         if need < 0:
             raise RuntimeError("oracle lanczos failed")
-        pr = np.empty(need, dtype=np.uint64)
-        pa = np.empty(need, dtype=np.float64)
-        lib().orc_lanczos_roots(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa),
-                                need, *args)
-        out = dict(energies=en, psi_rank=pr, psi_amp=pa)
+        if need > cap:
+            pr = np.empty(need, dtype=np.uint64)
+            pa = np.empty(need, dtype=np.float64)
+            lib().orc_lanczos_ex(*self._a(), r0.size, r0, a0, M, n_L, n_iter, en, None, None, _ptr(pr), _ptr(pa),
+                                 need, *args)
+        pr, pa = pr[:need].copy(), pa[:need].copy()
+        out = dict(energies=en, psi_rank=pr, psi_amp=pa, blocks_run=int(nrun.value),
+                   basis_nnz=bnnz.reshape(nblk, n_L))
         if want_T:
             out["T"] = T.reshape(nblk, n_L, n_L)
             out["S"] = S.reshape(nblk, n_L, n_L)
@@ -217,6 +238,16 @@ class Problem:
 
 
 # free functions ---------------------------------------------------------------
+def set_threads(t):
+    """Threads of the oracle's sigma (Sec. 2.2's parallel form: per-thread
+    buckets, per-bucket stable sort and merge) and of its truncation sort.
+    Every result has the same bits for any thread count."""
+    lib().orc_set_threads(int(t))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())
+
 def binom(a, b):
     return int(lib().orc_binom(int(a), int(b)))
 
@@ -239,11 +270,11 @@ def space_size(n, na, nb):
     return int(lib().orc_space_size(n, na, nb))
 
 
-def topm(ranks, amps, M):
+def topm(ranks, amps, M, tie_band=False):
     r, a = _u64(ranks), _f64(amps)
     orank = np.empty(r.size, dtype=np.uint64)
     oamp = np.empty(r.size, dtype=np.float64)
-    k = lib().orc_topm(r.size, r, a, -1 if M is None else int(M), orank, oamp)
+    k = lib().orc_topm_band(r.size, r, a, -1 if M is None else int(M), orank, oamp, 1 if tie_band else 0)
     return orank[:k].copy(), oamp[:k].copy()
 
 

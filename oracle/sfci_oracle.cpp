@@ -33,6 +33,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <parallel/algorithm>
 #include <vector>
 
 typedef uint64_t u64;
@@ -407,11 +408,40 @@ extern "C" i64 orc_source_terms(int n, int na, int nb, const double* h, const do
 // Returns the number of output entries, or -(needed) when cap is too small
 // (the output arrays may then be NULL), or -1 on bad input.
 struct Acc { u64 r; double v, a; };
+typedef std::pair<u64, double> Tup;
 
-static std::vector<Acc> sigma_merged(const Space& S, i64 nnz, const u64* rank, const double* amp) {
+static void stable_sort_by_target(std::vector<Tup>& tup) {
+    std::stable_sort(tup.begin(), tup.end(), [](const Tup& x, const Tup& y) { return x.first < y.first; });
+}
+
+// Merge a chunk of intermediate elements, sorted by target (equal targets in
+// source order), into the running merged list: one addition at a time.
+static void merge_chunk(std::vector<Acc>& run, const std::vector<Tup>& tup) {
+    std::vector<Acc> next;
+    next.reserve(run.size() + tup.size());
+    size_t x = 0, y = 0;
+    while (x < run.size() || y < tup.size()) {
+        if (y == tup.size() || (x < run.size() && run[x].r < tup[y].first)) {
+            next.push_back(run[x++]);
+            continue;
+        }
+        Acc cur;
+        if (x < run.size() && run[x].r == tup[y].first) cur = run[x++];
+        else { cur.r = tup[y].first; cur.v = 0.0; cur.a = 0.0; }
+        while (y < tup.size() && tup[y].first == cur.r) {
+            cur.v += tup[y].second;
+            cur.a += std::fabs(tup[y].second);
+            ++y;
+        }
+        next.push_back(cur);
+    }
+    run.swap(next);
+}
+
+static std::vector<Acc> sigma_merged_seq(const Space& S, i64 nnz, const u64* rank, const double* amp) {
     const int na = S.na, nb = S.nb;
     std::vector<Acc> run;       // merged so far, ascending rank
-    std::vector<std::pair<u64, double>> tup;
+    std::vector<Tup> tup;
     const size_t chunk_cap = (size_t)1 << 25;
     i64 t = 0;
     while (t < nnz) {
@@ -425,32 +455,69 @@ static std::vector<Acc> sigma_merged(const Space& S, i64 nnz, const u64* rank, c
             });
             ++t;
         }
-        std::stable_sort(tup.begin(), tup.end(),
-                         [](const std::pair<u64, double>& x, const std::pair<u64, double>& y) {
-                             return x.first < y.first;
-                         });
-        // Merge the sorted chunk into the running list, one addition at a time.
-        std::vector<Acc> next;
-        next.reserve(run.size() + tup.size());
-        size_t x = 0, y = 0;
-        while (x < run.size() || y < tup.size()) {
-            if (y == tup.size() || (x < run.size() && run[x].r < tup[y].first)) {
-                next.push_back(run[x++]);
-                continue;
-            }
-            Acc cur;
-            if (x < run.size() && run[x].r == tup[y].first) cur = run[x++];
-            else { cur.r = tup[y].first; cur.v = 0.0; cur.a = 0.0; }
-            while (y < tup.size() && tup[y].first == cur.r) {
-                cur.v += tup[y].second;
-                cur.a += std::fabs(tup[y].second);
-                ++y;
-            }
-            next.push_back(cur);
-        }
-        run.swap(next);
+        stable_sort_by_target(tup);
+        merge_chunk(run, tup);
     }
     return run;
+}
+
+// The same two steps in the paper's shared-memory parallel form (Sec. 2.2):
+// each of T threads generates the intermediate elements of its own segment
+// of the input into thread-local buckets (bucket = an equal range of the
+// determinant rank, the hash-range split); then every bucket is merged on its
+// own by one thread, its threads' parts taken in thread order.  The paper
+// sorts a bucket with introsort; here the sort is stable, so that every target
+// still receives its contributions in ascending source order and the result
+// has the bits of the sequential form above (tested).
+static int g_threads = 1;
+
+extern "C" void orc_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+extern "C" int orc_get_threads(void) { return g_threads; }
+
+static std::vector<Acc> sigma_merged_buckets(const Space& S, i64 nnz, const u64* rank, const double* amp, int T) {
+    const int na = S.na, nb = S.nb, n = S.n;
+    const int NB = 16 * T;
+    const u64 width = S.Ndet / (u64)NB + 1;
+    const i64 sa = (i64)na * (n - na), sb = (i64)nb * (n - nb);
+    const i64 per_src = 1 + sa + sb + sa * sb + (i64)(na * (na - 1) / 2) * ((n - na) * (n - na - 1) / 2) +
+                        (i64)(nb * (nb - 1) / 2) * ((n - nb) * (n - nb - 1) / 2);
+    const i64 chunk_src = std::max<i64>(1, ((i64)1 << 24) * T / per_src);
+    std::vector<std::vector<Acc>> run(NB);
+    std::vector<std::vector<std::vector<Tup>>> loc(T, std::vector<std::vector<Tup>>(NB));
+    for (i64 t0 = 0; t0 < nnz; t0 += chunk_src) {
+        const i64 t1 = std::min(nnz, t0 + chunk_src);
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+        for (int k = 0; k < T; ++k) {
+            for (auto& b : loc[k]) b.clear();
+            const i64 lo = t0 + (t1 - t0) * k / T, hi = t0 + (t1 - t0) * (k + 1) / T;
+            for (i64 t = lo; t < hi; ++t) {
+                u64 A = orc_str_unrank(rank[t] / S.Nb, na), B = orc_str_unrank(rank[t] % S.Nb, nb);
+                double vi = amp[t];
+                sc_terms(S, A, B, [&](u64 A2, u64 B2, double e) {
+                    const u64 R = orc_str_rank(A2) * S.Nb + orc_str_rank(B2);
+                    loc[k][R / width].push_back({R, e * vi});
+                });
+            }
+        }
+#pragma omp parallel for num_threads(T) schedule(dynamic, 1)
+        for (int b = 0; b < NB; ++b) {
+            std::vector<Tup> tup;
+            for (int k = 0; k < T; ++k) tup.insert(tup.end(), loc[k][b].begin(), loc[k][b].end());
+            stable_sort_by_target(tup);
+            merge_chunk(run[b], tup);
+        }
+    }
+    std::vector<Acc> out;
+    size_t tot = 0;
+    for (auto& r : run) tot += r.size();
+    out.reserve(tot);
+    for (auto& r : run) out.insert(out.end(), r.begin(), r.end());
+    return out;
+}
+
+static std::vector<Acc> sigma_merged(const Space& S, i64 nnz, const u64* rank, const double* amp) {
+    if (g_threads > 1) return sigma_merged_buckets(S, nnz, rank, amp, g_threads);
+    return sigma_merged_seq(S, nnz, rank, amp);
 }
 
 extern "C" i64 orc_sigma(int n, int na, int nb, const double* h, const double* g, i64 nnz,
@@ -503,30 +570,35 @@ extern "C" double orc_sigma_entry(int n, int na, int nb, const double* h, const 
 }
 
 // ---------------------------------------------------------------------------
-// Truncation (Eqs. 10-11): order the nonzero entries by |c| descending, ties
-// by rank ascending; keep the first min(M, nnz); return them by ascending
-// rank.  M < 0 keeps all.  In/out may alias.  Returns the kept count.
-// Truncation reading (the paper keeps "the largest" entries and is silent on
-// ties): order the nonzero entries by |c| descending, rank ascending, and take
-// the first M.  Entries whose magnitude lies within a relative 2^-36 of the
-// M-th one are kept as well, so that partners of equal magnitude in exact
-// arithmetic (e.g. alpha/beta-exchanged determinants when n_alpha = n_beta)
-// are never split by a rounding difference -- unless that would add more than
+// Truncation (Sec. 2.1, Eqs. 10-11): each basis vector keeps at most N_d = M
+// entries, the largest in magnitude.  The nonzero entries are ordered by |c|
+// descending; the paper leaves exact ties open, and they go to the lower rank.
+// The first min(M, nnz) are kept and returned by ascending rank.  M < 0 keeps
+// all.  In/out may alias.  Returns the kept count.
+//
+// band != 0 switches on an extension that is not the paper's rule: after the
+// first M, every further entry whose |c| is at least (1 - 2^-36) times the
+// M-th |c| is kept as well (so partners that are equal in exact arithmetic are
+// never split by a rounding difference), unless that adds more than
 // ORC_TIE_SLACK entries, in which case exactly M are kept.
 static const i64 ORC_TIE_SLACK = 256;
 
-extern "C" i64 orc_topm(i64 nnz, const u64* rank, const double* amp, i64 M, u64* out_rank, double* out_amp) {
+extern "C" i64 orc_topm_band(i64 nnz, const u64* rank, const double* amp, i64 M, u64* out_rank, double* out_amp,
+                             int band) {
     std::vector<std::pair<u64, double>> e;
     for (i64 t = 0; t < nnz; ++t)
         if (amp[t] != 0.0) e.push_back({rank[t], amp[t]});
     if (M >= 0 && (i64)e.size() > M) {
-        std::sort(e.begin(), e.end(), [](const std::pair<u64, double>& x, const std::pair<u64, double>& y) {
+        // a total order (ranks are unique), so any correct sort gives the same sequence
+        auto by_mag = [](const std::pair<u64, double>& x, const std::pair<u64, double>& y) {
             double ax = std::fabs(x.second), ay = std::fabs(y.second);
             if (ax != ay) return ax > ay;
             return x.first < y.first;
-        });
+        };
+        if (g_threads > 1) __gnu_parallel::sort(e.begin(), e.end(), by_mag);
+        else std::sort(e.begin(), e.end(), by_mag);
         i64 keep = M;
-        if (M > 0) {
+        if (band && M > 0) {
             const double thr = std::fabs(e[(size_t)M - 1].second) * (1.0 - 1.0 / 68719476736.0);  // 1 - 2^-36
             i64 k = M;
             while (k < (i64)e.size() && std::fabs(e[(size_t)k].second) >= thr) ++k;
@@ -537,6 +609,10 @@ extern "C" i64 orc_topm(i64 nnz, const u64* rank, const double* amp, i64 M, u64*
     std::sort(e.begin(), e.end());
     for (size_t t = 0; t < e.size(); ++t) { out_rank[t] = e[t].first; out_amp[t] = e[t].second; }
     return (i64)e.size();
+}
+
+extern "C" i64 orc_topm(i64 nnz, const u64* rank, const double* amp, i64 M, u64* out_rank, double* out_amp) {
+    return orc_topm_band(nnz, rank, amp, M, out_rank, out_amp, 0);
 }
 
 // Eq. 11: divide by the 2-norm; the sum of squares runs in ascending rank.
@@ -677,30 +753,37 @@ static SVec sigma_full(const Space& S, const SVec& v) {
     return y;
 }
 
-static SVec topm_normalize(const SVec& u, i64 M) {
+static SVec topm_normalize(const SVec& u, i64 M, int band) {
     SVec w;
     w.r.resize(u.r.size()); w.a.resize(u.r.size());
-    i64 k = orc_topm((i64)u.r.size(), u.r.data(), u.a.data(), M, w.r.data(), w.a.data());
+    i64 k = orc_topm_band((i64)u.r.size(), u.r.data(), u.a.data(), M, w.r.data(), w.a.data(), band);
     w.r.resize(k); w.a.resize(k);
     orc_normalize(k, w.a.data());
     return w;
 }
 
-// u = (y - a x) - b z, entrywise over the union of supports (missing = 0).
+// u = (y - a x) - b z, entrywise over the union of supports (missing = 0),
+// ranks ascending: a merge of the three rank-sorted lists.
 static SVec lanczos_update(const SVec& y, double a, const SVec& x, double b, const SVec* z) {
-    std::vector<u64> all(y.r);
-    all.insert(all.end(), x.r.begin(), x.r.end());
-    if (z) all.insert(all.end(), z->r.begin(), z->r.end());
-    std::sort(all.begin(), all.end());
-    all.erase(std::unique(all.begin(), all.end()), all.end());
-    auto get = [](const SVec& v, u64 k) -> double {
-        auto it = std::lower_bound(v.r.begin(), v.r.end(), k);
-        return (it != v.r.end() && *it == k) ? v.a[it - v.r.begin()] : 0.0;
-    };
+    const u64 END = ~0ull;
+    size_t iy = 0, ix = 0, iz = 0;
+    const size_t nz = z ? z->r.size() : 0;
     SVec u;
-    for (u64 k : all) {
-        double val = get(y, k) - a * get(x, k);
-        if (z) val = val - b * get(*z, k);
+    u.r.reserve(y.r.size() + x.r.size() + nz);
+    u.a.reserve(y.r.size() + x.r.size() + nz);
+    while (true) {
+        const u64 ky = iy < y.r.size() ? y.r[iy] : END;
+        const u64 kx = ix < x.r.size() ? x.r[ix] : END;
+        const u64 kz = iz < nz ? z->r[iz] : END;
+        const u64 k = std::min(ky, std::min(kx, kz));
+        if (k == END) break;
+        const double gy = (ky == k) ? y.a[iy++] : 0.0;
+        const double gx = (kx == k) ? x.a[ix++] : 0.0;
+        double val = gy - a * gx;
+        if (z) {
+            const double gz = (kz == k) ? z->a[iz++] : 0.0;
+            val = val - b * gz;
+        }
         if (val != 0.0) { u.r.push_back(k); u.a.push_back(val); }
     }
     return u;
@@ -760,10 +843,18 @@ static SVec project(const Roots& R, SVec y) {
 //   y = screen(H w) - sum_i c_i H Psi_i  (c_i = <Psi_i|w>/<Psi_i|Psi_i>),  then y = P y,
 // and the block-end Psi is projected before its truncation.  Root i is
 // (root_r, root_a)[root_off[i] .. root_off[i+1]), ranks ascending.
-extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
-                                 const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
-                                 double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
-                                 int n_roots, const i64* root_off, const u64* root_r, const double* root_a) {
+// band: the truncation extension of orc_topm_band (0 = the paper's rule).
+// conv_eps > 0: the halting test of Sec. 2.1 -- after block n >= 1 the run
+// stops when E(n-1) - E(n) < conv_eps (the signed difference, as the paper
+// writes it); *blocks_run (may be NULL) receives the number of blocks run and
+// energies[] beyond it are left untouched.  basis_nnz (may be NULL, n_iter
+// entries) receives the entry count of every basis vector w_j, block after
+// block.
+extern "C" i64 orc_lanczos_ex(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
+                              const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
+                              double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
+                              int n_roots, const i64* root_off, const u64* root_r, const double* root_a, int band,
+                              double conv_eps, int* blocks_run, i64* basis_nnz) {
     Space S = make_space(n, na, nb, h, g);
     Roots R;
     for (int i = 0; i < n_roots; ++i) {
@@ -779,15 +870,17 @@ extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const d
     SVec w0;
     w0.r.assign(r0, r0 + nnz0);
     w0.a.assign(a0, a0 + nnz0);
-    if (n_roots > 0) w0 = topm_normalize(project(R, w0), M);
+    if (n_roots > 0) w0 = topm_normalize(project(R, w0), M, band);
     else orc_normalize((i64)w0.a.size(), w0.a.data());
     int nblocks = n_iter / nL;
     SVec psi;
+    if (blocks_run) *blocks_run = 0;
     for (int blk = 0; blk < nblocks; ++blk) {
         std::vector<SVec> w(nL);
         w[0] = w0;
         std::vector<double> T(nL * nL, 0.0), Sm(nL * nL, 0.0);
         for (int j = 0; j < nL; ++j) {
+            if (basis_nnz) basis_nnz[(size_t)blk * nL + j] = (i64)w[j].r.size();
             SVec y = sigma_full(S, w[j]);
             if (eps > 0.0) {
                 SVec ys;
@@ -812,7 +905,7 @@ extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const d
             if (j + 1 < nL) {
                 SVec u = lanczos_update(y, T[j * nL + j], w[j], j >= 1 ? T[(j - 1) * nL + j] : 0.0,
                                         j >= 1 ? &w[j - 1] : nullptr);
-                w[j + 1] = topm_normalize(u, M);
+                w[j + 1] = topm_normalize(u, M, band);
             }
         }
         if (Tout) std::memcpy(Tout + (size_t)blk * nL * nL, T.data(), sizeof(double) * nL * nL);
@@ -841,7 +934,9 @@ extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const d
                 if (pp.a[t] != 0.0) { nz.r.push_back(pp.r[t]); nz.a.push_back(pp.a[t]); }
             psi = nz;
         }
-        w0 = topm_normalize(psi, M);
+        w0 = topm_normalize(psi, M, band);
+        if (blocks_run) *blocks_run = blk + 1;
+        if (conv_eps > 0.0 && blk >= 1 && energies[blk - 1] - energies[blk] < conv_eps) break;
     }
     if ((i64)psi.r.size() <= psi_cap && psi_rank && psi_amp) {
         std::copy(psi.r.begin(), psi.r.end(), psi_rank);
@@ -850,11 +945,19 @@ extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const d
     return (i64)psi.r.size();
 }
 
+extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
+                                 const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
+                                 double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
+                                 int n_roots, const i64* root_off, const u64* root_r, const double* root_a) {
+    return orc_lanczos_ex(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
+                          psi_cap, eps, n_roots, root_off, root_r, root_a, 0, 0.0, nullptr, nullptr);
+}
+
 extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
                            const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
                            double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps) {
-    return orc_lanczos_roots(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
-                             psi_cap, eps, 0, nullptr, nullptr, nullptr);
+    return orc_lanczos_ex(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
+                          psi_cap, eps, 0, nullptr, nullptr, nullptr, 0, 0.0, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -153,10 +154,13 @@ void dense_sigma(sfci_problem* P, const SigmaLaunch& sl, int dedup, unsigned lon
     }
 }
 
-namespace {
-
-
-}  // namespace
+bool halt_after_block(sfci_problem* P, const sfci_lanczos_opts* o, const double* energies_d, int b) {
+    if (!(o->conv_eps > 0.0) || b < 1) return false;
+    double e[2];
+    SFCI_CHECK_HIP(hipMemcpyAsync(e, energies_d + b - 1, sizeof(e), hipMemcpyDeviceToHost, P->stream));
+    sfci_sync(P);
+    return e[0] - e[1] < o->conv_eps;
+}
 
 extern "C" {
 
@@ -296,7 +300,9 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     if (!P || !v || !opts || !out) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
     if (v->nnz && (!v->rank || !v->amp)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL input arrays");
     if (opts->dedup < 0 || opts->dedup > 3) return (sfci_status)sfci_set_error(SFCI_E_ARG, "bad dedup mode");
+    if (!(opts->screen_eps >= 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps must be >= 0");
     validate_vec(P, v->rank, v->nnz);
+    P->tie_band = opts->tie_band ? 1 : 0;
     hipEvent_t e0, e1;
     SFCI_CHECK_HIP(hipEventCreate(&e0));
     SFCI_CHECK_HIP(hipEventCreate(&e1));
@@ -321,7 +327,7 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
         u64 distinct = 0;
         const u64 need = sigma_list_topm(P, sl, opts->M, out->rank, out->amp,
                                          (out->rank && out->amp) ? out->capacity : 0, &scal[1], &distinct,
-                                         list_tiles);
+                                         list_tiles, opts->screen_eps);
         SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
         const u64 emitted = read_u64(P, &scal[1]);
         out->nnz = need;
@@ -342,7 +348,7 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
         return rc;
     }
     CandSrc src{};
-    dense_sigma(P, sl, opts->dedup, (unsigned long long*)&scal[1]);
+    dense_sigma(P, sl, opts->dedup, (unsigned long long*)&scal[1], opts->screen_eps);
     src.dense = P->d_D;
     select_prepare(P, src, opts->M, &scal[2]);
     u64 hs[4];
@@ -377,10 +383,12 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     SFCI_GUARD_END
 }
 
-sfci_status sfci_topm(sfci_problem* P, const sfci_svec* v, uint64_t M, int32_t normalise, sfci_svec* out) {
+sfci_status sfci_topm(sfci_problem* P, const sfci_svec* v, uint64_t M, int32_t normalise, int32_t tie_band,
+                      sfci_svec* out) {
     SFCI_GUARD_BEGIN
     if (!P || !v || !out) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
     validate_vec(P, v->rank, v->nnz);
+    P->tie_band = tie_band ? 1 : 0;
     u64* scal = (u64*)P->ws_lz[0].get(8 * sizeof(u64));
     launch_fill_u64(scal, 8, 0, P->stream);
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, P->stream, scal, (u64)v->nnz);
@@ -429,16 +437,19 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
     if (o->n_L < 1 || o->n_L > 32 || o->n_iter < o->n_L)
         return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
     if (v0->nnz == 0) return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty start vector");
+    if (!(o->screen_eps >= 0.0) || !(o->conv_eps >= 0.0))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps and conv_eps must be >= 0");
     validate_vec(P, v0->rank, v0->nnz);
+    P->tie_band = o->tie_band ? 1 : 0;
     const int nL = o->n_L;
     const int nblk = o->n_iter / nL;
     const bool det = o->deterministic != 0;
     const bool list_mode = o->no_dense != 0 || !ensure_dense(P);
     if (list_mode && n_roots > 0)
         return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "projected roots need the dense accumulator");
-    // a truncated vector holds at most M + SFCI_TIE_SLACK entries
+    // a truncated vector holds at most M entries (M + SFCI_TIE_SLACK with the tie band)
     const u64 cap = (o->M >= P->Ndet) ? P->Ndet
-                                      : std::min<u64>(std::max<u64>(o->M + SFCI_TIE_SLACK, v0->nnz), P->Ndet);
+                                      : std::min<u64>(std::max<u64>(o->M + tie_extra(P), v0->nnz), P->Ndet);
     const u64 tps = terms_per_source(P->n, P->na, P->nb);
     // basis storage
     u64* Wr = (u64*)P->ws_lz[1].get((size_t)nL * cap * sizeof(u64));
@@ -522,9 +533,10 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
     u64 sigma_calls = 0;
     u64* nnz_hist = (u64*)P->ws_lz[7].get((size_t)(nblk * nL + 1) * sizeof(u64));
     u64 psi_n = 0;
+    int blocks_run = 0;
     if (list_mode) {
         ListBasis LB{cap, Wr, Wa, sc, Td, Sd, xd, lam, energies_d, status, nnz_hist};
-        lanczos_list(P, o, LB, psi_out, &psi_n, &sigma_calls, tsig);
+        lanczos_list(P, o, LB, psi_out, &psi_n, &sigma_calls, tsig, &blocks_run);
     }
     for (int b = 0; b < (list_mode ? 0 : nblk); ++b) {
         double* T = Td + (size_t)b * nL * nL;
@@ -585,12 +597,14 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
         if (n_roots > 0) project_dense();
         CandSrc src{};
         src.dense = P->d_D;
-        if (b + 1 < nblk) {
+        blocks_run = b + 1;
+        if (b + 1 < nblk && !halt_after_block(P, o, energies_d, b)) {
             DVec w0 = W(0);
             select_topm(P, src, o->M, w0.r, w0.a, w0.nnz, true);
             launch_normalise(P, w0.a, w0.nnz, cap, det);
         } else {
             select_prepare(P, src, UINT64_MAX, sc + 34);
+            break;
         }
     }
     // Final Psi (untruncated) into psi_out when it fits.
@@ -619,14 +633,15 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
     }
     }
     SFCI_CHECK_HIP(hipEventRecord(e1, P->stream));
-    SFCI_CHECK_HIP(hipMemcpyAsync(energies, energies_d, nblk * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    for (int b = 0; b < nblk; ++b) energies[b] = std::numeric_limits<double>::quiet_NaN();
+    SFCI_CHECK_HIP(hipMemcpyAsync(energies, energies_d, blocks_run * sizeof(double), hipMemcpyDeviceToHost, P->stream));
     int hstat = 0;
     SFCI_CHECK_HIP(hipMemcpyAsync(&hstat, status, sizeof(int), hipMemcpyDeviceToHost, P->stream));
     if (T_out)
         SFCI_CHECK_HIP(hipMemcpyAsync(T_out, Td, (size_t)nblk * nL * nL * sizeof(double), hipMemcpyDeviceToHost, P->stream));
     if (S_out)
         SFCI_CHECK_HIP(hipMemcpyAsync(S_out, Sd, (size_t)nblk * nL * nL * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    std::vector<u64> nh((size_t)nblk * nL);
+    std::vector<u64> nh((size_t)blocks_run * nL);
     SFCI_CHECK_HIP(hipMemcpyAsync(nh.data(), nnz_hist, nh.size() * sizeof(u64), hipMemcpyDeviceToHost, P->stream));
     u64 emitted = 0;
     SFCI_CHECK_HIP(hipMemcpyAsync(&emitted, sc + 32, sizeof(u64), hipMemcpyDeviceToHost, P->stream));
@@ -641,6 +656,7 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
         for (u64 x : nh) en_terms += x * tps;
         stats->terms_enumerated = en_terms;
         stats->terms_emitted = emitted;
+        stats->blocks_run = blocks_run;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

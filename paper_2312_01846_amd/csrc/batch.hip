@@ -128,6 +128,10 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
     if (o->no_dense)
         return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "the batched iteration keeps dense accumulators");
+    if (o->conv_eps != 0.0)
+        return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED,
+                                           "the batched iteration runs n_iter / n_L blocks (no conv_eps halting)");
+    if (!(o->screen_eps >= 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps must be >= 0");
     const int nL = o->n_L, nblk = o->n_iter / nL, n = B->n;
     const bool det = o->deterministic != 0;
     const bool use_graph = !det && (o->dedup != SFCI_DEDUP_DENSE_ATOMIC);
@@ -159,9 +163,10 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         if (!det && o->dedup != SFCI_DEDUP_DENSE_ATOMIC && !rowtile_available(P)) all_tiles = false;
         Inst& q = I[k];
         q.P = P;
+        P->tie_band = o->tie_band ? 1 : 0;
         q.M = Ms[k];
         q.cap = (Ms[k] >= P->Ndet) ? P->Ndet
-                                   : std::min<u64>(std::max<u64>(Ms[k] + SFCI_TIE_SLACK, v0s[k].nnz), P->Ndet);
+                                   : std::min<u64>(std::max<u64>(Ms[k] + tie_extra(P), v0s[k].nnz), P->Ndet);
         q.tps = terms_per_source(P->n, P->na, P->nb);
         q.Wr = (u64*)P->ws_lz[1].get((size_t)nL * q.cap * sizeof(u64));
         q.Wa = (double*)P->ws_lz[2].get((size_t)nL * q.cap * sizeof(double));

@@ -473,8 +473,10 @@ void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* 
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
-void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered) {
-    double* part = (double*)P->ws_red.get((RGRID + 8) * sizeof(double));
+u64 normalise_ws_doubles() { return RGRID + 8; }
+
+void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered, double* part_ws) {
+    double* part = part_ws ? part_ws : (double*)P->ws_red.get((RGRID + 8) * sizeof(double));
     double* ss = part + RGRID;
     if (ordered) {
         hipLaunchKernelGGL(k_ordered<OS_SUMSQ>, dim3(1), dim3(64), 0, P->stream, (const u64*)nullptr, a, nnz,

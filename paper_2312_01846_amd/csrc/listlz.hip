@@ -12,10 +12,11 @@
 //     range; T_lj is then the same ordered (or tree) dot as with a dense y;
 //   * Eq. 10 touches y only on supp(w_j) and supp(w_{j-1}); every other entry
 //     of u equals y, is final, and goes to a running candidate list.  Once
-//     that list holds more than K = M + SFCI_TIE_SLACK + 1 entries it is cut
-//     back to its K best (by |c|, then rank); later entries must beat the
-//     K-th |c| to join, since their ranks are larger.  The global K best are
-//     always among the kept ones, which is all the tie rule needs;
+//     that list holds more than 2K entries (K = M, or M + SFCI_TIE_SLACK + 1
+//     with the tie band) it is cut back to its K best (by |c|, then rank);
+//     later entries must beat the K-th |c| to join, since their ranks are
+//     larger.  The global K best are always among the kept ones, which is all
+//     the truncation needs;
 //   * after the last pass, u on supp(w_j) U supp(w_{j-1}) is formed from the
 //     gathered y (the same two subtractions, in the same order, as the dense
 //     scatters), appended, and the top-M of the whole list is w_{j+1}.
@@ -392,6 +393,14 @@ struct ListPassSink : SortPassSink {
     }
 };
 
+// How many of the best entries the running candidate list must keep so that
+// the final selection sees all it needs: M (at least 1), and with the tie
+// band its reach plus one more, which tells whether the band overflows.
+u64 list_keep(const sfci_problem* P, u64 M) {
+    if (M == UINT64_MAX) return UINT64_MAX;
+    return P->tie_band ? M + SFCI_TIE_SLACK + 1 : std::max<u64>(M, 1);
+}
+
 // Selected entries come out in the candidate list's order: sort them by rank.
 void sort_by_rank(sfci_problem* P, u64* r, double* a, u64 n) {
     if (n < 2) return;
@@ -412,11 +421,11 @@ void sort_by_rank(sfci_problem* P, u64* r, double* a, u64 n) {
 u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, double eps);
 
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
-                    u64* emitted_dev, u64* distinct_host, bool tiles_ok) {
+                    u64* emitted_dev, u64* distinct_host, bool tiles_ok, double eps) {
     ListWs& ws = P->list_ws;
     u64* ls = (u64*)ws.scal.get(128 * sizeof(u64));  // [0] Rn [1] bound [2] pass count [3] overflow [4] distinct [8..) bounds
     launch_fill_u64(ls, 128, 0, P->stream);
-    ListCands C{P, ws, M == UINT64_MAX ? UINT64_MAX : M + SFCI_TIE_SLACK + 1, 0, 0, ls, ls + 1, (int*)(ls + 3)};
+    ListCands C{P, ws, list_keep(P, M), 0, 0, ls, ls + 1, (int*)(ls + 3)};
     C.reset();
     ListPassSink sink;
     sink.P = P;
@@ -425,9 +434,9 @@ u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank,
     sink.pcount = ls + 2;
     sink.distinct = ls + 4;
     if (tiles_ok && list_sigma_tiles(P, read_dev(P, v.v_nnz)))
-        sigma_dense_passes(P, v, sink, emitted_dev, 0.0);
+        sigma_dense_passes(P, v, sink, emitted_dev, eps);
     else
-        sigma_sorted_passes(P, v, sink, emitted_dev, 0, 0.0);
+        sigma_sorted_passes(P, v, sink, emitted_dev, 0, eps);
     check_overflow(P, (const int*)(ls + 3));
     C.n_upper = read_dev(P, C.Rn);
     CandSrc src{};
@@ -528,7 +537,7 @@ u64 sigma_list_full(sfci_problem* P, const SigmaLaunch& v, u64* emitted_dev, u64
 }
 
 void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& Bs, sfci_svec* psi_out,
-                  u64* psi_n_out, u64* sigma_calls, EventTimer& tsig) {
+                  u64* psi_n_out, u64* sigma_calls, EventTimer& tsig, int* blocks_run) {
     const int nL = o->n_L;
     const int nblk = o->n_iter / nL;
     const bool det = o->deterministic != 0;
@@ -540,7 +549,7 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
     u64* ls = (u64*)ws.scal.get(128 * sizeof(u64));
     // ls: [0] Rn [1] bound [2] pass count [3] overflow [8..72) bounds [80] psi count [81] zero [88..) offsets
     launch_fill_u64(ls, 128, 0, P->stream);
-    const u64 K = (o->M == UINT64_MAX) ? UINT64_MAX : o->M + SFCI_TIE_SLACK + 1;
+    const u64 K = list_keep(P, o->M);
     ListCands C{P, ws, K, 2 * cap, 0, ls, ls + 1, (int*)(ls + 3)};
     double* Y = (double*)ws.yg.get((size_t)nL * cap * sizeof(double));
     unsigned char* taken = (unsigned char*)ws.taken.get(cap);
@@ -640,7 +649,9 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
         u64* pn = ls + 80;
         launch_fill_u64(pn, 1, 0, P->stream);
         segmented_sum_append(P, ks, vs, tot, 0, 0.0, pn, tot, pr, pa);
-        if (b + 1 < nblk) {
+        *blocks_run = b + 1;
+        const bool last = (b + 1 == nblk) || halt_after_block(P, o, Bs.energies_d, b);
+        if (!last) {
             CandSrc src{};
             src.lrank = pr;
             src.lval = pa;
@@ -654,6 +665,7 @@ void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& 
                 SFCI_CHECK_HIP(hipMemcpyAsync(psi_out->rank, pr, np * sizeof(u64), hipMemcpyDeviceToDevice, P->stream));
                 SFCI_CHECK_HIP(hipMemcpyAsync(psi_out->amp, pa, np * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
             }
+            break;
         }
     }
 }

@@ -106,6 +106,76 @@ u64 sigma_full_list(sfci_problem* P, const SigmaLaunch& sl, bool det, u64* emitt
     return n;
 }
 
+// Gradients of E = <Psi|H|Psi>/<Psi|Psi> at fixed Psi (Hellmann-Feynman form):
+// the backward of sigma with v = Psi and cotangent Psi/<Psi|Psi>.  sc[0] holds
+// nnz(Psi) on the device; sc[5] is scratch for the transposed vector's count.
+void energy_gradients_at(sfci_problem* P, const sfci_svec* psi, u64* sc, double* dh, double* deri) {
+    const int n = P->n;
+    const u64 n2 = (u64)n * n, n4 = n2 * n2;
+    double* sbar = (double*)P->ws_cand_a.get(psi->nnz * sizeof(double));
+    launch_div_by_sumsq(P, psi->amp, sc, psi->nnz, sbar);
+    double* raw = (double*)P->ws_red.get((2048 + n2 + n4) * sizeof(double));
+    const SigmaLaunch sl{psi->rank, psi->amp, sc, psi->nnz};
+    if (rowtile_grad_available(P)) {
+        GradJob J{};
+        J.P = P;
+        J.v = sl;
+        J.s_rank = psi->rank;
+        J.s_amp = sbar;
+        J.s_nnz = sc;
+        J.s_cap = psi->nnz;
+        J.Rh = raw + 2048;
+        J.Rg = raw + 2048 + n2;
+        J.dh = dh;
+        J.dg = deri;
+        J.vt_rank = (u64*)P->ws_list_r.get(psi->nnz * sizeof(u64));
+        J.vt_amp = (double*)P->ws_list_a.get(psi->nnz * sizeof(double));
+        J.vt_nnz = sc + 5;
+        rowtile_gradients(P->stream, 1, &J, P->grad_ws);
+    } else {
+        launch_scatter_set(P, P->d_D, psi->rank, sbar, sc, psi->nnz);
+        launch_backward_dense(P, sl, P->d_D, nullptr, dh, deri, raw + 2048, raw + 2048 + n2);
+        launch_scatter_zero(P, P->d_D, psi->rank, sc, psi->nnz);
+    }
+}
+
+extern "C" sfci_status sfci_energy_gradients(sfci_problem* P, const sfci_svec* psi, int32_t deterministic,
+                                             double* energy, double* dh, double* deri) {
+    try {
+        if (!P || !psi || !energy) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
+        if (psi->nnz == 0 || !psi->rank || !psi->amp)
+            return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty vector");
+        validate_vec(P, psi->rank, psi->nnz);
+        if ((dh || deri) && !ensure_dense(P))
+            return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "gradients need the dense array (N_det doubles)");
+        const bool det = deterministic != 0;
+        u64* sc = (u64*)P->ws_lz[0].get(16 * sizeof(u64));  // [0] nnz(Psi) [1] emitted [2] |y| [5] scratch
+        double* sd = (double*)(sc + 8);                     // [0] num [1] den [2] E
+        launch_fill_u64(sc, 16, 0, P->stream);
+        launch_set_u64(P, sc, psi->nnz);
+        const SigmaLaunch sl{psi->rank, psi->amp, sc, psi->nnz};
+        u64* yr;
+        double* ya;
+        sigma_full_list(P, sl, det, sc + 1, &yr, &ya, sc + 2);
+        double* prod = (double*)P->ws_prod.get(std::max<u64>(1, psi->nnz) * sizeof(double));
+        hipLaunchKernelGGL(k_pt2_inner, dim3(grid_of(psi->nnz)), dim3(PB), 0, P->stream, yr, ya, sc + 2, psi->rank,
+                           psi->amp, (u64)psi->nnz, prod);
+        launch_sum(P, prod, sc, psi->nnz, sd + 0, det);
+        launch_sumsq(P, psi->amp, sc, psi->nnz, sd + 1, det);
+        hipLaunchKernelGGL(k_pt2_e0, dim3(1), dim3(64), 0, P->stream, sd + 0, sd + 1, sd + 2);
+        SFCI_CHECK_HIP(hipGetLastError());
+        if (dh || deri) energy_gradients_at(P, psi, sc, dh, deri);
+        double hd[3];
+        SFCI_CHECK_HIP(hipMemcpyAsync(hd, sd, sizeof(hd), hipMemcpyDeviceToHost, P->stream));
+        SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+        if (!(hd[1] > 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "Psi has zero norm");
+        *energy = hd[2];
+        return SFCI_OK;
+    } catch (const sfci_error& e) {
+        return (sfci_status)sfci_set_error(e.code, e.msg);
+    }
+}
+
 extern "C" sfci_status sfci_pt2(sfci_problem* P, const sfci_svec* psi, int32_t deterministic, double* e0,
                                 double* e2, uint64_t* n_external) {
     try {

@@ -4,7 +4,10 @@
 // entries by |c| descending and breaks exact ties by rank ascending, followed
 // by an order-preserving compaction that writes the kept entries by rank.
 // Every pass is a streaming read of the candidates (dense N_det array or a
-// rank-sorted list); no sort of the candidates is needed.
+// rank-sorted list); no sort of the candidates is needed.  Exactly min(M,
+// nonzero) entries are kept, unless the problem's tie_band extension is on
+// (then entries within a relative 2^-36 of the M-th |c| stay too, at most
+// SFCI_TIE_SLACK of them).
 #include <algorithm>
 
 #include "../../include/sfci.h"
@@ -89,11 +92,11 @@ __global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
 }
 
 // Dense sources: after the level-0 pick (the top key digit is the exponent
-// field of |c|), every entry that can still be kept -- including the tie rule's
-// reach just below the M-th magnitude -- has |c| >= 2^e (1 - 2^-36), e the
-// binade of the M-th |c|.  Those candidates are compacted into a list and the
-// rest of the selection runs on the list.
-__global__ void k_sel_cand_bound(SelState* st) {
+// field of |c|), every entry that can still be kept has |c| >= 2^e, e the
+// binade of the M-th |c| (with the tie band: >= 2^e (1 - 2^-36)).  Those
+// candidates are compacted into a list and the rest of the selection runs on
+// the list.
+__global__ void k_sel_cand_bound(SelState* st, int band) {
     if (threadIdx.x != 0) return;
     u64 b;
     if (st->take_all) {
@@ -102,7 +105,9 @@ __global__ void k_sel_cand_bound(SelState* st) {
         b = ~0ull;  // M = 0: nothing
     } else {
         const u64 d0 = st->pre_lo & (u64)(NBIN - 1);
-        b = d0 == 0 ? 1 : abs_bits(__longlong_as_double((long long)(d0 << 52)) * (1.0 - 1.0 / 68719476736.0));
+        if (d0 == 0) b = 1;
+        else if (band) b = abs_bits(__longlong_as_double((long long)(d0 << 52)) * (1.0 - 1.0 / 68719476736.0));
+        else b = d0 << 52;
     }
     st->cand_bits = b;
     st->cand = 1;
@@ -341,7 +346,11 @@ Geo make_geo(sfci_problem* P) {
 }
 
 template <class Src>
-void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_count_dev, SelState* st = nullptr) {
+void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_count_dev, SelState* st = nullptr,
+                 u64* cnt_ws = nullptr, u64* bsum_ws = nullptr) {
+    // k_sel_min always runs: its cmin (the smallest kept |c|) bounds the list
+    // iteration's running candidate list.  The band's three steps only with
+    // the extension on.
     Geo g = make_geo(P);
     if (!st) st = (SelState*)P->ws_sel.get(sizeof(SelState));
     int take_all = (M == UINT64_MAX) ? 1 : 0;
@@ -355,27 +364,29 @@ void run_prepare(sfci_problem* P, const Src& src, u64 n_upper, u64 M, u64* out_c
             hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_T), 0, P->stream, st, g, L, M);
         }
         hipLaunchKernelGGL(k_sel_min<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st, g);
-        hipLaunchKernelGGL(k_sel_thr, dim3(1), dim3(64), 0, P->stream, st);
-        hipLaunchKernelGGL(k_sel_count_thr<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st);
-        hipLaunchKernelGGL(k_sel_mode, dim3(1), dim3(64), 0, P->stream, st, M);
+        if (P->tie_band) {
+            hipLaunchKernelGGL(k_sel_thr, dim3(1), dim3(64), 0, P->stream, st);
+            hipLaunchKernelGGL(k_sel_count_thr<Src>, dim3(hgrid), dim3(256), 0, P->stream, src, st);
+            hipLaunchKernelGGL(k_sel_mode, dim3(1), dim3(64), 0, P->stream, st, M);
+        }
     }
     u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
     if (nblk < 1) nblk = 1;
-    u64* cnt = (u64*)P->ws_cnt.get(nblk * sizeof(u64));
+    u64* cnt = cnt_ws ? cnt_ws : (u64*)P->ws_cnt.get(nblk * sizeof(u64));
     hipLaunchKernelGGL(k_compact_count<Src>, dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, src, st, g, cnt);
-    exclusive_scan_u64(P, cnt, cnt, nblk, &st->count_out);
+    exclusive_scan_u64(P, cnt, cnt, nblk, &st->count_out, bsum_ws);
     if (out_count_dev) hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, P->stream, &st->count_out, out_count_dev);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
 template <class Src>
 void run_write(sfci_problem* P, const Src& src, u64 n_upper, u64* out_rank, double* out_amp, bool zero_dense,
-               double* Dz, SelState* st = nullptr) {
+               double* Dz, SelState* st = nullptr, u64* cnt_ws = nullptr) {
     Geo g = make_geo(P);
     if (!st) st = (SelState*)P->ws_sel.p;
     u64 nblk = (n_upper + CCHUNK - 1) / CCHUNK;
     if (nblk < 1) nblk = 1;
-    u64* cnt = (u64*)P->ws_cnt.p;
+    u64* cnt = cnt_ws ? cnt_ws : (u64*)P->ws_cnt.p;
     if (zero_dense)
         hipLaunchKernelGGL((k_compact_write<Src, true>), dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, src, st, g,
                            cnt, out_rank, out_amp, Dz);
@@ -407,6 +418,18 @@ void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* ou
     }
 }
 
+u64 select_chunks(u64 n_upper) { return std::max<u64>(1, (n_upper + CCHUNK - 1) / CCHUNK); }
+
+void select_prepare_ws(sfci_problem* P, const CandSrc& src, u64 M, u64* count_dev, const SelWs& ws) {
+    ListSrc s{src.lrank, src.lval, src.lcount};
+    run_prepare(P, s, src.lcap, M, count_dev, ws.st, ws.cnt, ws.bsum);
+}
+
+void select_write_ws(sfci_problem* P, const CandSrc& src, u64* out_rank, double* out_amp, const SelWs& ws) {
+    ListSrc s{src.lrank, src.lval, src.lcount};
+    run_write(P, s, src.lcap, out_rank, out_amp, false, nullptr, ws.st, ws.cnt);
+}
+
 void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, double* out_amp, u64* out_count_dev,
                  bool zero_dense) {
     if (!src.dense || !zero_dense || M == UINT64_MAX || M == 0) {
@@ -428,7 +451,7 @@ void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, doub
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, P->stream, st, M, 0, 0);
     hipLaunchKernelGGL(k_sel_hist<DenseSrc>, dim3(hgrid), dim3(256), 0, P->stream, ds, st, g, 0);
     hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(PICK_T), 0, P->stream, st, g, 0, M);
-    hipLaunchKernelGGL(k_sel_cand_bound, dim3(1), dim3(64), 0, P->stream, st);
+    hipLaunchKernelGGL(k_sel_cand_bound, dim3(1), dim3(64), 0, P->stream, st, P->tie_band ? 1 : 0);
     const u64 nblk = std::max<u64>(1, (P->Ndet + CCHUNK - 1) / CCHUNK);
     u64* cnt = (u64*)P->ws_cnt.get(nblk * sizeof(u64));
     hipLaunchKernelGGL(k_compact_count<DenseSrc>, dim3((unsigned)nblk), dim3(CBLOCK), 0, P->stream, ds, st, g, cnt);

@@ -112,7 +112,14 @@ struct sfci_problem {
     // projected roots of the excited-state iteration: H Psi_i lists and scalars
     DevBuf ws_hroot_r[SFCI_MAX_ROOTS], ws_hroot_a[SFCI_MAX_ROOTS], ws_roots_sc, ws_roots_cnt;
     bool borrowed = false;  // true for such a shadow: d_h, d_g, d_binom, d_D belong to another problem
+    // Truncation extension (off = the paper's rule, exactly min(M, nonzero)
+    // entries kept): also keep entries within a relative 2^-36 of the M-th
+    // |c|, at most SFCI_TIE_SLACK of them.  Set from the options of each call.
+    int tie_band = 0;
 };
+
+// Entries a truncated vector can hold beyond M (the tie band's reach).
+inline u64 tie_extra(const sfci_problem* P) { return P->tie_band ? (u64)SFCI_TIE_SLACK : 0; }
 
 // ---- launchers (sigma.hip) ----
 struct SigmaLaunch {
@@ -207,8 +214,10 @@ void launch_symmetrise(sfci_problem* P, const double* Rh, const double* Rg, doub
 // ---- utilities (util.hip) ----
 void launch_fill_f64(double* p, u64 n, double val, hipStream_t s);
 void launch_fill_u64(u64* p, u64 n, u64 val, hipStream_t s);
-// exclusive scan of n u64 counts into out (may alias); total -> *total_dev (device scalar)
-void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* total_dev);
+// exclusive scan of n u64 counts into out (may alias); total -> *total_dev (device scalar).
+// bsum_ws (may be NULL: the problem's buffer) holds scan_block_sums(n) u64.
+void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* total_dev, u64* bsum_ws = nullptr);
+u64 scan_block_sums(u64 n);
 
 // ---- selection (select.hip) ----
 // Source of candidates: either a dense array (index = rank) or a list.
@@ -230,6 +239,17 @@ void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, doub
 // other selection may run in between.
 void select_prepare(sfci_problem* P, const CandSrc& src, u64 M, u64* count_dev);
 void select_write(sfci_problem* P, const CandSrc& src, u64* out_rank, double* out_amp, bool zero_dense);
+// The same two phases on a candidate list with caller-given working memory
+// (no allocation): the state, select_chunks(lcap) per-chunk counts and
+// scan_block_sums(select_chunks(lcap)) scan sums.
+struct SelWs {
+    SelState* st;
+    u64* cnt;
+    u64* bsum;
+};
+u64 select_chunks(u64 n_upper);
+void select_prepare_ws(sfci_problem* P, const CandSrc& src, u64 M, u64* count_dev, const SelWs& ws);
+void select_write_ws(sfci_problem* P, const CandSrc& src, u64* out_rank, double* out_amp, const SelWs& ws);
 
 // ---- sort path (sortpath.hip) ----
 // sigma = H v by stable sort + in-order segmented sum; result sorted by rank,
@@ -293,7 +313,9 @@ void launch_dot_sparse(sfci_problem* P, const u64* xr, const double* xa, const u
                        const double* ya, const u64* yn, double* out1, double* out2, bool ordered);
 void launch_axpy_scatter(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap,
                          const double* coef, double sign);
-void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered);
+void launch_normalise(sfci_problem* P, double* a, const u64* nnz, u64 cap, bool ordered, double* part_ws = nullptr);
+// doubles of working memory launch_normalise needs (part_ws)
+u64 normalise_ws_doubles();
 void launch_scatter_set(sfci_problem* P, double* D, const u64* r, const double* a, const u64* nnz, u64 cap);
 // energy_slot[blk ? *blk : 0] receives lambda (blk: device block index, may be null)
 void launch_geneig_full(sfci_problem* P, int m, const double* T, const double* S, double* lambda, double* x,
@@ -355,7 +377,7 @@ struct EventTimer {
 // the selected count; *distinct_host (may be NULL) receives the number of
 // distinct nonzero entries.
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
-                    u64* emitted_dev, u64* distinct_host, bool tiles_ok);
+                    u64* emitted_dev, u64* distinct_host, bool tiles_ok, double eps = 0.0);
 // Fast mode's per-sigma choice between the tile kernel's slices (true) and
 // the sort path, from the input's size (SFCI_LIST_SIGMA=tile|sort forces one).
 bool list_sigma_tiles(sfci_problem* P, u64 nnz);
@@ -382,7 +404,11 @@ struct ListBasis {
 // w_0 must already hold the normalised start vector.  *psi_n_out receives the
 // last Psi's length; it is copied to psi_out when it fits.
 void lanczos_list(sfci_problem* P, const sfci_lanczos_opts* o, const ListBasis& B, sfci_svec* psi_out, u64* psi_n_out,
-                  u64* sigma_calls, EventTimer& tsig);
+                  u64* sigma_calls, EventTimer& tsig, int* blocks_run);
+// Halting test of Sec. 2.1 after block b (energies on the device): true when
+// o->conv_eps > 0, b >= 1 and E(b-1) - E(b) < conv_eps.  Synchronises when it
+// has to look.
+bool halt_after_block(sfci_problem* P, const sfci_lanczos_opts* o, const double* energies_d, int b);
 
 // Device-resident sparse vector with a device nnz (Lanczos basis storage).
 struct DVec {

@@ -1,4 +1,6 @@
 // Small device utilities: fills and a three-phase exclusive scan of u64 counts.
+#include <algorithm>
+
 #include "sfci_internal.h"
 
 namespace {
@@ -132,10 +134,11 @@ void launch_fill_u64(u64* p, u64 n, u64 val, hipStream_t s) {
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
-void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* total_dev) {
-    u64 nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (nb < 1) nb = 1;
-    u64* bsum = (u64*)P->ws_scan.get(nb * sizeof(u64));
+u64 scan_block_sums(u64 n) { return std::max<u64>(1, (n + SCAN_TILE - 1) / SCAN_TILE); }
+
+void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* total_dev, u64* bsum_ws) {
+    const u64 nb = scan_block_sums(n);
+    u64* bsum = bsum_ws ? bsum_ws : (u64*)P->ws_scan.get(nb * sizeof(u64));
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_BLOCK), 0, P->stream, bsum, nb, total_dev);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum, out);

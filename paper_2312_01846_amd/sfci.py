@@ -14,10 +14,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsfci.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "sfci.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADER = os.path.join(INCLUDE, "sfci.h")
 
 UINT64_MAX = (1 << 64) - 1
-TIE_SLACK = 256  # SFCI_TIE_SLACK: a truncated vector holds at most M + TIE_SLACK entries
+TIE_SLACK = 256  # SFCI_TIE_SLACK: with the tie band a truncated vector holds at most M + TIE_SLACK entries
 
 SFCI_OK = 0
 STATUS = {0: "SFCI_OK", -1: "SFCI_E_ARG", -2: "SFCI_E_RANGE", -3: "SFCI_E_DUP", -4: "SFCI_E_CAPACITY",
@@ -40,7 +41,8 @@ class SVec(C.Structure):
 
 
 class SigmaOpts(C.Structure):
-    _fields_ = [("M", C.c_uint64), ("dedup", C.c_int32), ("deterministic", C.c_int32)]
+    _fields_ = [("M", C.c_uint64), ("dedup", C.c_int32), ("deterministic", C.c_int32), ("screen_eps", C.c_double),
+                ("tie_band", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SigmaStats(C.Structure):
@@ -51,12 +53,13 @@ class SigmaStats(C.Structure):
 class LanczosOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
                 ("dedup", C.c_int32), ("screen_eps", C.c_double), ("no_dense", C.c_int32),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("conv_eps", C.c_double), ("tie_band", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LanczosStats(C.Structure):
     _fields_ = [("sigma_calls", C.c_uint64), ("terms_enumerated", C.c_uint64), ("terms_emitted", C.c_uint64),
-                ("sigma_ms", C.c_double), ("total_ms", C.c_double)]
+                ("sigma_ms", C.c_double), ("total_ms", C.c_double), ("blocks_run", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class BatchStats(C.Structure):
@@ -66,6 +69,11 @@ class BatchStats(C.Structure):
                 ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32), ("tune_trials", C.c_int32),
                 ("tune_b1_chunk", C.c_uint32), ("tune_bb_chunk", C.c_uint32), ("tune_per_cu", C.c_uint32),
                 ("tune_default_ms", C.c_double), ("tune_best_ms", C.c_double)]
+
+
+class Roof(C.Structure):
+    _fields_ = [("copy_GBps", C.c_double), ("gather_Gops", C.c_double * 3), ("atomic_Gops", C.c_double * 3),
+                ("lds_atomic_Gops", C.c_double * 2), ("lds_read_Gops", C.c_double), ("big_bytes", C.c_uint64)]
 
 
 _lib = None
@@ -79,7 +87,7 @@ _SIGS = {
     "sfci_unrank": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "sfci_sigma": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(SigmaOpts), C.POINTER(SVec),
                              C.POINTER(SigmaStats)]),
-    "sfci_topm": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_uint64, C.c_int32, C.POINTER(SVec)]),
+    "sfci_topm": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_uint64, C.c_int32, C.c_int32, C.POINTER(SVec)]),
     "sfci_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(LanczosOpts), C.c_void_p, C.POINTER(SVec),
                                C.c_void_p, C.c_void_p, C.POINTER(LanczosStats)]),
     "sfci_lanczos_roots": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(LanczosOpts), C.POINTER(SVec),
@@ -89,11 +97,14 @@ _SIGS = {
                                       C.c_void_p]),
     "sfci_pt2": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                            C.POINTER(C.c_uint64)]),
+    "sfci_energy_gradients": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_int32, C.POINTER(C.c_double), C.c_void_p,
+                                        C.c_void_p]),
     "sfci_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "sfci_batch_destroy": (C.c_int, [C.c_void_p]),
     "sfci_batch_lanczos": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.POINTER(C.c_uint64), C.POINTER(LanczosOpts),
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchStats)]),
     "sfci_last_error": (C.c_char_p, []),
+    "sfci_roof_probe": (C.c_int, [C.c_uint64, C.c_void_p, C.POINTER(Roof)]),
 }
 
 
@@ -184,7 +195,8 @@ class Problem:
         return a, b
 
     # -- sigma = H v, truncated ----------------------------------------------------
-    def sigma(self, ranks, amps, M=None, dedup="auto", deterministic=False, capacity=None):
+    def sigma(self, ranks, amps, M=None, dedup="auto", deterministic=False, capacity=None, screen_eps=0.0,
+              tie_band=False):
         """Returns (ranks int64, amps float64, stats dict) on the GPU."""
         torch = _torch()
         r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
@@ -194,8 +206,8 @@ class Problem:
         if cap is None:
             cap = min(self.n_det, max(1, r.numel()) * self.tps)
             if M is not None:
-                cap = min(cap, int(M) + TIE_SLACK)
-        opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0)
+                cap = min(cap, int(M) + (TIE_SLACK if tie_band else 0))
+        opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0, float(screen_eps), 1 if tie_band else 0, 0)
         for _ in range(2):
             o_r = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
             o_a = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
@@ -212,7 +224,7 @@ class Problem:
             return o_r[:k], o_a[:k], stats
         raise SfciError(-4, "capacity retry failed")
 
-    def topm(self, ranks, amps, M, normalise=False):
+    def topm(self, ranks, amps, M, normalise=False, tie_band=False):
         torch = _torch()
         r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
         a = torch.as_tensor(amps, device="cuda").to(torch.float64).contiguous()
@@ -221,7 +233,8 @@ class Problem:
         o_a = torch.empty(cap, dtype=torch.float64, device="cuda")
         out = SVec(o_r.data_ptr(), o_a.data_ptr(), 0, cap)
         Mv = UINT64_MAX if M is None else int(M)
-        _check(load_library().sfci_topm(self._h, C.byref(_svec(r, a)), Mv, 1 if normalise else 0, C.byref(out)))
+        _check(load_library().sfci_topm(self._h, C.byref(_svec(r, a)), Mv, 1 if normalise else 0,
+                                        1 if tie_band else 0, C.byref(out)))
         k = int(out.nnz)
         return o_r[:k], o_a[:k]
 
@@ -253,20 +266,29 @@ class Problem:
                                                   dg.data_ptr() if dg is not None else None))
         return (vbar[:vr.numel()] if vbar is not None else None), dh, dg
 
-    def energy_gradients(self, psi_rank, psi_amp):
+    def energy_gradients(self, psi_rank, psi_amp, deterministic=False, want_grad=True):
         """E = <psi|H|psi>/<psi|psi> and its gradients dE/dh, dE/d(pq|rs) at fixed psi
-        (Hellmann-Feynman form): one backward call with sbar = psi/<psi|psi>."""
+        (Hellmann-Feynman form), all computed by sfci_energy_gradients."""
         torch = _torch()
-        pa = torch.as_tensor(psi_amp, device="cuda").to(torch.float64)
-        nrm2 = torch.dot(pa, pa)
-        vbar, dh, dg = self.sigma_backward(psi_rank, pa, psi_rank, pa / nrm2)
-        return float(torch.dot(pa, vbar)), dh, dg
+        r = torch.as_tensor(psi_rank, device="cuda").to(torch.int64).contiguous()
+        a = torch.as_tensor(psi_amp, device="cuda").to(torch.float64).contiguous()
+        n = self.n
+        dh = torch.empty((n, n), dtype=torch.float64, device="cuda") if want_grad else None
+        dg = torch.empty((n, n, n, n), dtype=torch.float64, device="cuda") if want_grad else None
+        e = C.c_double(0.0)
+        _check(load_library().sfci_energy_gradients(self._h, C.byref(_svec(r, a)), 1 if deterministic else 0,
+                                                    C.byref(e), dh.data_ptr() if want_grad else None,
+                                                    dg.data_ptr() if want_grad else None))
+        return e.value, dh, dg
 
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
-                want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False, roots=None):
+                want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False, roots=None, conv_eps=0.0,
+                tie_band=False):
         """roots: list of (ranks, amps) of previously found eigenvectors projected out
-        of the effective Hamiltonian (the iteration then finds the next state)."""
+        of the effective Hamiltonian (the iteration then finds the next state).
+        conv_eps > 0: halt once a block lowers the energy by less than conv_eps
+        (the result's "blocks_run"; energies of blocks not run are NaN)."""
         torch = _torch()
         r = torch.as_tensor(ranks0, device="cuda").to(torch.int64).contiguous()
         a = torch.as_tensor(amps0, device="cuda").to(torch.float64).contiguous()
@@ -276,11 +298,12 @@ class Problem:
         S = np.zeros(nblk * n_L * n_L) if want_T else None
         Mv = UINT64_MAX if M is None else int(M)
         opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps),
-                           1 if no_dense else 0)
+                           1 if no_dense else 0, 0, float(conv_eps), 1 if tie_band else 0, 0)
         st = LanczosStats()
         psi = None
         if want_psi:
-            cap = psi_capacity or min(self.n_det, n_L * (Mv + TIE_SLACK if M is not None else self.n_det))
+            extra = TIE_SLACK if tie_band else 0
+            cap = psi_capacity or min(self.n_det, n_L * (Mv + extra if M is not None else self.n_det))
             p_r = torch.empty(cap, dtype=torch.int64, device="cuda")
             p_a = torch.empty(cap, dtype=torch.float64, device="cuda")
             psi = SVec(p_r.data_ptr(), p_a.data_ptr(), 0, cap)
@@ -299,9 +322,9 @@ class Problem:
                                                T.ctypes.data_as(C.c_void_p) if want_T else None,
                                                S.ctypes.data_as(C.c_void_p) if want_T else None, C.byref(st))
         _check(rc)
-        out = dict(energies=energies, stats=dict(sigma_calls=st.sigma_calls, terms_enumerated=st.terms_enumerated,
-                                                 terms_emitted=st.terms_emitted, sigma_ms=st.sigma_ms,
-                                                 total_ms=st.total_ms))
+        out = dict(energies=energies, blocks_run=int(st.blocks_run),
+                   stats=dict(sigma_calls=st.sigma_calls, terms_enumerated=st.terms_enumerated,
+                              terms_emitted=st.terms_emitted, sigma_ms=st.sigma_ms, total_ms=st.total_ms))
         if want_psi:
             k = int(psi.nnz)
             out["psi_rank"] = p_r[:k]
@@ -337,7 +360,7 @@ class Batch:
             pass
 
     def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True,
-                screen_eps=0.0, autotune=False):
+                screen_eps=0.0, autotune=False, tie_band=False, conv_eps=0.0):
         """starts: list of (ranks, amps); Ms: truncation per instance.  Returns
         dict(energies (n_inst, n_blocks), dh [list of (n,n)], dg [list of (n,n,n,n)], stats)."""
         torch = _torch()
@@ -361,7 +384,7 @@ class Batch:
             dh_all = torch.empty(n2, dtype=torch.float64, device="cuda")
             dg_all = torch.empty(n4, dtype=torch.float64, device="cuda")
         opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps), 0,
-                           1 if autotune else 0)
+                           1 if autotune else 0, float(conv_eps), 1 if tie_band else 0, 0)
         st = BatchStats()
         rc = load_library().sfci_batch_lanczos(self._h, vecs, Marr, C.byref(opts),
                                                energies.ctypes.data_as(C.c_void_p),
@@ -396,9 +419,24 @@ def terms_per_source(n, na, nb):
     return 1 + sa + sb + pa * qa + pb * qb + sa * sb
 
 
-def declared_symbols(header: str = HEADER):
-    """Function names declared in include/sfci.h."""
+def declared_symbols(header: str | None = None):
+    """Function names declared in include/*.h (or in one header)."""
+    import glob
     import re
 
-    text = open(header).read()
+    files = [header] if header else sorted(glob.glob(os.path.join(INCLUDE, "*.h")))
+    text = "".join(open(f).read() for f in files)
     return sorted(set(re.findall(r"\b(sfci_[a-z_]+)\s*\(", text)))
+
+
+def roof_probe(big_bytes=1 << 30):
+    """Device ceilings (sfci_roof_probe) as a dict: copy GB/s and rates in
+    operations per ns for random gathers / global FP64 atomics (2 MiB,
+    128 MiB, big_bytes arrays) and LDS FP64 atomics / reads."""
+    torch = _torch()
+    out = Roof()
+    _check(load_library().sfci_roof_probe(int(big_bytes), C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                          C.byref(out)))
+    return dict(copy_GBps=out.copy_GBps, gather_Gops=list(out.gather_Gops), atomic_Gops=list(out.atomic_Gops),
+                lds_atomic_Gops=list(out.lds_atomic_Gops), lds_read_Gops=out.lds_read_Gops,
+                big_bytes=int(out.big_bytes))

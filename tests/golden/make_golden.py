@@ -3,12 +3,13 @@
 Every value stored here comes from ``oracle`` run on the seeded inputs of
 ``paper_2312_01846_amd.synth``; nothing is taken from the HIP path.  Usage:
 
-    python tests/golden/make_golden.py [--out FILE] [case ...]
+    python tests/golden/make_golden.py [--threads T] [--out FILE] [case ...]
     python tests/golden/make_golden.py --merge FILE ...
 
 Without case names all cases are (re)computed; existing entries for other
 cases are kept.  --out writes to another file (for parallel runs), --merge
-copies such files into the golden file.
+copies such files into the golden file.  --threads sets the oracle's sigma
+threads (default: all host cores); the values do not depend on it.
 """
 import hashlib
 import json
@@ -55,7 +56,7 @@ def case_defs():
             return 20, 4, 4, h, g, start
         return b
 
-    return {
+    cases = {
         "c0_Mall_30": (mol(8, 3, 3, 16, 0), None, 10, 30),
         "c0_M300_30": (mol(8, 3, 3, 16, 0), 300, 10, 30),
         "c1_U4_M1e5_60": (hub(12, 4.0), 100_000, 10, 60),
@@ -71,7 +72,22 @@ def case_defs():
         # 12 electrons in 28 orbitals (1.42e11 determinants): the list iteration's shape
         "c3_M1e3_10": (mol(28, 6, 6, 56, 3), 1_000, 5, 10),
         "c3p_M1e3_10": (mol(28, 6, 6, 56, 3, True), 1_000, 5, 10),
+        # 10 electrons in 26 orbitals at the dense workload's smallest truncation
+        "c2_M1e5_30": (mol(26, 5, 5, 52, 2), 100_000, 10, 30),
+        "c2p_M1e5_30": (mol(26, 5, 5, 52, 2, True), 100_000, 10, 30),
     }
+    # the 32-instance bond-stretch batch as the benchmark runs it (perturbed
+    # start, each instance at its own truncation, N_L = 10, 30 sigma), for the
+    # instances whose truncation the oracle finishes in minutes
+    Ms = synth.batch_truncations(32)
+    for j, M in enumerate(Ms):
+        if M <= C4_BENCH_MAX_M:
+            cases[f"c4bench_inst{j:02d}"] = (c4(j, True), int(M), 10, 30)
+    return cases
+
+
+# largest truncation of a batch instance with a stored benchmark-configuration energy
+C4_BENCH_MAX_M = 123_712
 
 
 def excited_defs():
@@ -124,6 +140,10 @@ def main(argv):
             data.update(json.load(open(f)))
         json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
         return
+    threads = os.cpu_count() or 1
+    if argv[:1] == ["--threads"]:
+        threads, argv = int(argv[1]), argv[2:]
+    oracle.set_threads(threads)
     if argv[:1] == ["--out"]:
         out, argv = argv[1], argv[2:]
     data = json.load(open(out)) if os.path.exists(out) else {}

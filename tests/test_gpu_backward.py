@@ -155,3 +155,30 @@ def test_converged_vector_gradients_20_orbitals(torch, S, orc):
     _, oh, og = Po.backward(r, a, r, a / nrm2)
     assert np.allclose(_np(dh), oh, rtol=1e-6, atol=1e-10)
     assert np.allclose(_np(dg), og, rtol=1e-6, atol=1e-10)
+
+
+@pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
+def test_energy_gradients_call_matches_oracle(torch, S, orc, det):
+    # sfci_energy_gradients: E = <Psi|H|Psi>/<Psi|Psi> (bit for bit with the
+    # oracle's ordered evaluation in deterministic mode) and the gradients of
+    # that quotient at fixed Psi (the oracle's explicit-operator backward with
+    # sbar = Psi/<Psi|Psi>), for a vector that is not normalised
+    h, g = synth.molecule_like(10, 20, 5)
+    P = S.Problem(10, 4, 3, h, g)
+    Po = orc.Problem(10, 4, 3, h, g)
+    r, a = synth.random_sparse_vector(P.n_det, 700, seed=11)
+    a = 3.0 * a
+    E, dh, dg = P.energy_gradients(r.astype(np.int64), a, deterministic=det)
+    e0, _, _ = Po.pt2(r, a)
+    if det:
+        assert E == e0
+    else:
+        assert abs(E - e0) <= 1e-12 * abs(e0)
+    _, oh, og = Po.backward(r, a, r, a / float(a @ a), explicit=True)
+    assert np.allclose(_np(dh), oh, rtol=1e-9, atol=1e-12)
+    assert np.allclose(_np(dg), og, rtol=1e-9, atol=1e-12)
+    E2, dh2, dg2 = P.energy_gradients(r.astype(np.int64), a, deterministic=det, want_grad=False)
+    assert E2 == E and dh2 is None and dg2 is None
+    with pytest.raises(S.SfciError) as e:
+        P.energy_gradients(np.zeros(0, dtype=np.int64), np.zeros(0))
+    assert e.value.code == -1

@@ -102,14 +102,14 @@ def test_batch_deterministic_matches_goldens(torch, S):
 
 def test_batch_fast_mixed_sizes(torch, S, orc):
     # 8 and 20 orbitals in one tile launch; the untruncated 8-orbital run is
-    # plain Lanczos and must match the oracle, the truncated 8-orbital run
-    # (perturbed start, no exact ties) its golden.
-    gc0, g31 = _gold("c0p_M300_30"), _gold("c4_inst31_M3e3_30")
+    # plain Lanczos and must match the oracle, the truncated runs (perturbed
+    # starts, no exact ties at the cut) their goldens.
+    gc0, g31 = _gold("c0p_M300_30"), _gold("c4p_inst31_M3e3_30")
     Pa, hc, ec = _c0(S)
     Pb, _, _ = _c0(S)
     P31, h31, e31 = _c4(S, 31)
     B = S.Batch([Pa, P31, Pb])
-    out = B.lanczos([AUFBAU, AUFBAU, _perturbed(Pb)], [None, g31["M"], gc0["M"]], n_L=10, n_iter=30,
+    out = B.lanczos([AUFBAU, _perturbed(P31), _perturbed(Pb)], [None, g31["M"], gc0["M"]], n_L=10, n_iter=30,
                     deterministic=False)
     st = out["stats"]
     assert st["batched_sigma"] == 1 and st["graph_replayed_blocks"] == 2 and st["sigma_calls"] == 30
@@ -117,12 +117,21 @@ def test_batch_fast_mixed_sizes(torch, S, orc):
     E = out["energies"]
     assert np.all(np.abs(E[0] - ref["energies"]) < 1e-9)
     assert np.all(np.abs(E[2] - np.array(gc0["energies"])) < 1e-9)
-    # closed-shell 20-orbital instance: exchange partners tie at the cut and
-    # are kept together, so the fast path matches the oracle too
     assert np.all(np.abs(E[1] - np.array(g31["energies"])) < 1e-9)
     for k, (h, g) in enumerate([(hc, ec), (h31, e31), (hc, ec)]):
         assert abs(_euler(out["dh"][k], out["dg"][k], h, g) - E[k, -1]) < 1e-9
     assert abs(np.trace(_np(out["dh"][0])) - 6) < 1e-10  # dE/dh_pp sums to the electron count
+
+
+def test_batch_tie_band_deterministic(torch, S, orc):
+    # the opt-in truncation extension: the batch's deterministic run equals the
+    # oracle's iteration with the same extension, bit for bit
+    Pc, hc, ec = _c0(S)
+    B = S.Batch([Pc])
+    out = B.lanczos([AUFBAU], [300], n_L=10, n_iter=30, deterministic=True, want_grad=False, tie_band=True)
+    ref = orc.Problem(8, 3, 3, hc, ec).lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 30,
+                                               tie_band=True)
+    assert np.array_equal(out["energies"][0], ref["energies"])
 
 
 def test_batch_fast_gradients_match_oracle(torch, S, orc):
@@ -183,6 +192,9 @@ def test_batch_rejects_bad_arguments(torch, S):
     B = S.Batch([P])
     with pytest.raises(S.SfciError):
         B.lanczos([AUFBAU], [100], n_L=10, n_iter=5)
+    with pytest.raises(S.SfciError) as e:  # no halting test in the batched iteration
+        B.lanczos([AUFBAU], [100], n_L=5, n_iter=10, conv_eps=1e-6)
+    assert e.value.code == -8
 
 
 @pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])

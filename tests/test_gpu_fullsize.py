@@ -4,8 +4,10 @@ determinants each), truncations M log-uniform in [1e4, 1e6], N_L = 10, one
 batched tile-kernel launch per sigma step with the work sizes the batch tunes
 during its warm-up, then the gradients.
 
-The oracle cannot run these iterations, so the checks are the ones it can
-decide at this size:
+Checks:
+  * every instance whose truncation the oracle finishes in minutes (18 of the
+    32, M <= 123 712) against the oracle's energies of the same iteration at
+    the same M, all three blocks, within 1e-9 Ha;
   * each batched energy and gradient against the same instance iterated alone
     (smallest and largest M): the iteration's result does not depend on how
     the instances are launched (1e-9 Ha; gradients 1e-6 relative);
@@ -15,12 +17,17 @@ decide at this size:
     absent from the GPU output and zero in the oracle;
   * the gradients' Euler identity E = sum h dE/dh + sum g dE/dg (E is linear
     in the integrals at fixed Psi), for every instance."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2312_01846_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "lanczos_energies.json")
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +67,19 @@ def test_benchmark_workload_full_size(torch, S, orc):
     out = B.lanczos([v0] * 32, Ms, n_L=10, n_iter=30)
     E = out["energies"]
     assert np.all(np.isfinite(E))
+    # every instance with an oracle energy at its benchmark truncation (the
+    # oracle finishes M <= 123 712 in minutes): within 1e-9 Ha, all blocks
+    gold = json.load(open(GOLD))
+    checked = 0
+    for k in range(32):
+        gd = gold.get(f"c4bench_inst{k:02d}")
+        if gd is None:
+            continue
+        assert gd["M"] == Ms[k] and gd["n_iter"] == 30
+        dE = np.abs(E[k] - np.array(gd["energies"]))
+        assert np.all(dE < 1e-9), (k, dE)
+        checked += 1
+    assert checked == sum(1 for m in Ms if m <= 123_712), checked
     for k, (_, h, g) in enumerate(inst):
         euler = float((_np(out["dh"][k]) * h).sum() + (_np(out["dg"][k]) * g).sum())
         assert abs(euler - E[k, -1]) < 1e-9, k

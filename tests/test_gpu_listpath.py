@@ -129,13 +129,13 @@ def test_list_iteration_untruncated_matches_oracle(torch, S, orc, monkeypatch):
 
 
 @pytest.mark.parametrize("sigma", ["tile", "sort", "auto"])
-@pytest.mark.parametrize("name,rows", [("c2p_M2e3_20", 5000), ("c4_inst31_M3e3_30", 700), ("c3_M1e3_10", 20000),
-                                       ("c3p_M1e3_10", 30000)])
+@pytest.mark.parametrize("name,rows", [("c2p_M2e3_20", 5000), ("c4p_inst31_M3e3_30", 700), ("c3p_M1e3_10", 30000)])
 def test_list_iteration_fast_mode(torch, S, monkeypatch, name, rows, sigma):
     # fast mode: sigma through the tile kernel a slice of target rows at a
     # time (SFCI_LIST_PASS_ROWS forces many slices), or through the sort
     # path, or the per-sigma choice between them; tree reductions; energies
-    # within 1e-9 Ha of the oracle at equal M
+    # within 1e-9 Ha of the oracle at equal M (starts without the alpha/beta
+    # exchange symmetry, so no exact ties reach a truncation cut)
     gd = _gold(name)
     P, start, _ = _case(S, name)
     monkeypatch.setenv("SFCI_LIST_PASS_ROWS", str(rows))

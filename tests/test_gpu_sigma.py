@@ -97,19 +97,46 @@ def test_sigma_matches_oracle(torch, S, orc, name, n, na, nb, mk, nnz, mode):
 
 
 @pytest.mark.parametrize("mode", ["dense", "dense_atomic", "sort"])
-def test_sigma_truncated_support(torch, S, orc, mode):
+def test_sigma_truncated_support(torch, S, orc, support_band, mode):
     h, g = synth.molecule_like(10, 20, 5)
     P, Po = _prob(S, orc, 10, 4, 3, h, g)
     r, a = synth.random_sparse_vector(P.n_det, 900, seed=3)
-    orr, oa = Po.sigma(r, a)
+    orr, oa, oab = Po.sigma(r, a, with_abs=True)
     for M in [1, 77, 1000, len(orr) - 1, len(orr), len(orr) + 5]:
         kr, ka = orc.topm(orr, oa, M)
         gr, ga, _ = P.sigma(r.astype(np.int64), a, M=M, dedup=mode, deterministic=(mode == "sort"))
-        assert np.array_equal(_np(gr).astype(np.uint64), kr), M
+        gr, ga = _np(gr).astype(np.uint64), _np(ga)
         if mode == "sort":
-            assert np.array_equal(_np(ga), ka)
+            assert np.array_equal(gr, kr), M
+            assert np.array_equal(ga, ka)
         else:
-            assert np.allclose(_np(ga), ka, rtol=1e-12, atol=1e-14)
+            support_band(gr, ga, orr, oa, oab, M)
+
+
+@pytest.mark.parametrize("mode", ["dense", "dense_atomic", "sort"])
+def test_sigma_screen_eps(torch, S, orc, support_band, mode):
+    # Sec. 3 screening inside sfci_sigma: merged entries below eps are dropped
+    # before the truncation (strict <: an entry equal to eps stays)
+    h, g = synth.molecule_like(10, 20, 5)
+    P, Po = _prob(S, orc, 10, 4, 3, h, g)
+    r, a = synth.random_sparse_vector(P.n_det, 900, seed=3)
+    orr, oa, oab = Po.sigma(r, a, with_abs=True)
+    eps = float(np.quantile(np.abs(oa), 0.6))
+    keep = ~(np.abs(oa) < eps)
+    sr, sa, sab = orr[keep], oa[keep], oab[keep]
+    for M in [None, 500]:
+        gr, ga, _ = P.sigma(r.astype(np.int64), a, M=M, dedup=mode, deterministic=(mode == "sort"), screen_eps=eps)
+        gr, ga = _np(gr).astype(np.uint64), _np(ga)
+        if mode == "sort":
+            kr, ka = orc.topm(sr, sa, M)
+            assert np.array_equal(gr, kr) and np.array_equal(ga, ka), M
+        elif M is None:
+            # unordered sums may round an entry next to eps across it
+            diff = np.setxor1d(gr, sr)
+            dpos = np.searchsorted(orr, diff)
+            assert np.all(np.abs(np.abs(oa[dpos]) - eps) <= 1e-12 * oab[dpos])
+        else:
+            support_band(gr, ga, sr, sa, sab, M)
 
 
 def test_topm_bit_exact_with_ties(torch, S, orc):
@@ -127,14 +154,22 @@ def test_topm_bit_exact_with_ties(torch, S, orc):
         gr, ga = P.topm(ranks.astype(np.int64), amps, M)
         assert np.array_equal(_np(gr).astype(np.uint64), kr), M
         assert np.array_equal(_np(ga), ka), M
-    # partners one ulp apart straddling the cut are kept together, as in the oracle
+    # partners one ulp apart straddling the cut: the strict rule keeps the
+    # larger; the tie-band extension keeps both, as in the oracle
     near = amps.copy()
     near[[300, 301, 302]] = [9.0, 9.0 * (1 + 2.0 ** -52), 9.0 * (1 - 2.0 ** -50)]
     for M in [1, 2, 4, 5]:  # these 3 lead, then the 3 entries of 7.0
-        kr, ka = orc.topm(ranks, near, M)
-        gr, ga = P.topm(ranks.astype(np.int64), near, M)
-        assert np.array_equal(_np(gr).astype(np.uint64), kr), M
-        assert np.array_equal(_np(ga), ka), M
+        for band in (False, True):
+            kr, ka = orc.topm(ranks, near, M, tie_band=band)
+            gr, ga = P.topm(ranks.astype(np.int64), near, M, tie_band=band)
+            assert np.array_equal(_np(gr).astype(np.uint64), kr), (M, band)
+            assert np.array_equal(_np(ga), ka), (M, band)
+            if not band:
+                assert len(kr) == M
+    # exact ties of the tie band beyond its reach: exactly M
+    kr, _ = orc.topm(ranks, amps, 2000, tie_band=True)
+    gr, _ = P.topm(ranks.astype(np.int64), amps, 2000, tie_band=True)
+    assert np.array_equal(_np(gr).astype(np.uint64), kr)
     # normalised form equals the oracle's Eq. 11 division
     kr, ka = orc.topm(ranks, amps, 3000)
     kan, _ = orc.normalize(ka)
@@ -218,9 +253,9 @@ def test_sigma_degenerate_spin_spaces(torch, S, orc, n, na, nb, mode):
     r = np.sort(rng.choice(nd, size=k, replace=False)).astype(np.uint64)
     a = rng.standard_normal(k)
     gr, ga, _ = P.sigma(r.astype(np.int64), a, dedup=mode, deterministic=(mode == "sort"))
-    orr, oa = Po.sigma(r, a)
+    orr, oa, oab = Po.sigma(r, a, with_abs=True)
     assert np.array_equal(_np(gr).astype(np.uint64), orr)
     if mode == "sort":
         assert np.array_equal(_np(ga), oa)
     else:
-        assert np.allclose(_np(ga), oa, rtol=0, atol=1e-12 * max(1.0, np.abs(oa).max()))
+        assert np.all(np.abs(_np(ga) - oa) <= 1e-12 * oab)

@@ -117,10 +117,18 @@ def test_truncated_blocks_are_variational(orc):
 
 
 def test_truncated_vectors_have_M_entries(orc):
+    # Sec. 2.1: every basis vector holds N_d = M entries (the start vector
+    # holds its own single determinant).  The closed-shell start gives
+    # alpha/beta-exchanged partners of equal magnitude, so ties reach the cut.
     P, _ = _dense_case(orc)
-    out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 50, 10, 10)
-    assert len(out["psi_rank"]) <= 10 * (50 + 256)  # each vector: M plus kept near-ties at the cut
+    out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 50, 10, 30)
+    bn = out["basis_nnz"]
+    assert bn[0, 0] == 1
+    assert np.all(bn.ravel()[1:] == 50)
     assert np.all(np.diff(out["psi_rank"].astype(np.int64)) > 0)
+    assert len(out["psi_rank"]) <= 10 * 50
+    band = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 50, 10, 30, tie_band=True)
+    assert band["basis_nnz"].max() > 50  # the extension keeps tied partners together
 
 
 def test_screening_matches_manual_block(orc):
@@ -203,3 +211,45 @@ def test_no_roots_is_the_plain_iteration(orc):
     a = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20)
     b = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20, roots=[])
     assert np.array_equal(a["energies"], b["energies"]) and np.array_equal(a["psi_amp"], b["psi_amp"])
+
+
+def test_halting_stops_at_the_first_small_change(orc):
+    # Sec. 2.1: the run halts after block n once E(n-1) - E(n) < eps; the
+    # blocks it runs are the full run's blocks, bit for bit
+    P, _ = _dense_case(orc)
+    full = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 5, 50)
+    E = full["energies"]
+    assert full["blocks_run"] == 10
+    for eps in (1.0, 1e-2, 1e-4, 1e-6, 1e-12):
+        out = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 5, 50, conv_eps=eps)
+        nb = out["blocks_run"]
+        assert np.array_equal(out["energies"][:nb], E[:nb])
+        assert np.all(out["energies"][nb:] == 0.0)
+        drops = E[:-1] - E[1:]
+        first = next((b + 2 for b in range(len(drops)) if drops[b] < eps), 10)
+        assert nb == first, (eps, nb, first)
+    # eps = 1: the first block with a predecessor already halts
+    assert P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 5, 50, conv_eps=1.0)["blocks_run"] == 2
+
+
+def test_thread_count_does_not_change_bits(orc):
+    # the bucketed parallel sigma (Sec. 2.2) and the parallel truncation sort
+    # give the sequential results bit for bit
+    P, _ = _dense_case(orc)
+    rng = np.random.default_rng(8)
+    r = np.sort(rng.choice(P.n_det, 600, replace=False)).astype(np.uint64)
+    a = rng.normal(size=600)
+    old = orc.get_threads()
+    try:
+        orc.set_threads(1)
+        s1 = P.sigma(r, a, with_abs=True)
+        l1 = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 200, 10, 20, want_T=True)
+        orc.set_threads(5)
+        s5 = P.sigma(r, a, with_abs=True)
+        l5 = P.lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 200, 10, 20, want_T=True)
+    finally:
+        orc.set_threads(old)
+    for x, y in zip(s1, s5):
+        assert np.array_equal(x, y)
+    for k in ("energies", "psi_rank", "psi_amp", "T", "S"):
+        assert np.array_equal(l1[k], l5[k]), k

@@ -136,7 +136,30 @@ def test_hubbard_sigma_sparse_structure(orc):
         assert len(tgt) <= 12
 
 
-def test_topm_matches_full_sort_and_ties(orc):
+def _check_is_top_m(ranks, amps, M, kr, ka):
+    """The defining properties of the truncation (Sec. 2.1, Eqs. 10-11): the
+    kept set holds min(M, nonzero) entries, unchanged and by ascending rank;
+    no dropped entry is larger in magnitude than a kept one; where magnitudes
+    tie across the cut, the kept entries have the lower ranks; zeros never stay."""
+    nz = amps != 0.0
+    want_n = int(nz.sum()) if M is None else min(int(M), int(nz.sum()))
+    assert len(kr) == want_n
+    assert np.all(np.diff(kr.astype(np.int64)) > 0)
+    pos = np.searchsorted(ranks, kr)
+    assert np.array_equal(ranks[pos], kr) and np.array_equal(amps[pos], ka)
+    assert np.all(ka != 0.0)
+    dropped = np.ones(len(ranks), dtype=bool)
+    dropped[pos] = False
+    dropped &= nz
+    if want_n and dropped.any():
+        kmin = np.abs(ka).min()
+        dmax = np.abs(amps[dropped]).max()
+        assert kmin >= dmax
+        if kmin == dmax:
+            assert kr[np.abs(ka) == kmin].max() < ranks[dropped & (np.abs(amps) == kmin)].min()
+
+
+def test_topm_is_the_M_largest(orc):
     rng = np.random.default_rng(3)
     ranks = np.sort(rng.choice(10_000, 2000, replace=False)).astype(np.uint64)
     amps = rng.normal(size=2000)
@@ -144,38 +167,57 @@ def test_topm_matches_full_sort_and_ties(orc):
     amps[100:140] = 0.25
     amps[140:160] = -0.25
     amps[160:180] = 0.0
-    for M in [1, 10, 50, 110, 1000, 1990, 5000, None]:
-        kr, ka = orc.topm(ranks, amps, M)
-        keys = sorted([(-abs(x), int(r), x) for r, x in zip(ranks, amps) if x != 0.0])
-        keep = keys if M is None else keys[:M]
-        if M is not None and 0 < M < len(keys):
-            # plus everything within a relative 2^-36 of the M-th magnitude, if that adds <= 256
-            thr = -keep[-1][0] * (1.0 - 2.0 ** -36)
-            extra = [k for k in keys[M:] if -k[0] >= thr]
-            if len(extra) <= 256:
-                keep = keep + extra
-        want = sorted((r, x) for _, r, x in keep)
-        assert [int(x) for x in kr] == [r for r, _ in want]
-        assert np.array_equal(ka, np.array([x for _, x in want]))
-    # the 60 planted ties of magnitude 0.25 are split only when more than 256 would have to be added
-    many = amps.copy()
-    many[:400] = 0.5
-    kr, _ = orc.topm(ranks, many, 100)
-    assert len(kr) == 100
     above = int(np.sum(np.abs(amps) > 0.25))
-    kr, _ = orc.topm(ranks, amps, above + 5)  # the M-th entry is one of the 0.25 ties: all 60 are kept
-    assert len(kr) == above + 60
-    assert np.sum(np.abs(amps[np.isin(ranks, kr)]) == 0.25) == 60
+    for M in [0, 1, 10, 50, 110, above + 5, above + 59, above + 60, 1000, 1820, 1990, 5000, None]:
+        kr, ka = orc.topm(ranks, amps, M)
+        _check_is_top_m(ranks, amps, M, kr, ka)
+    # the library sort: numpy's lexsort on (rank, -|c|) and the first M
+    for M in [7, above + 5, 1234]:
+        order = np.lexsort((ranks, -np.abs(amps)))
+        order = order[amps[order] != 0.0][:M]
+        kr, ka = orc.topm(ranks, amps, M)
+        assert np.array_equal(kr, np.sort(ranks[order]))
 
 
-def test_topm_keeps_near_ties(orc):
-    # partners equal up to rounding are kept together; a real gap still cuts
+def test_topm_hand_cases(orc):
     ranks = np.arange(10, dtype=np.uint64)
+    # a one-ulp near-tie straddling the cut is cut: 0.7 (rank 3) is smaller than 0.7 (1 + 2^-52) (rank 4)
     amps = np.array([1.0, 0.9, 0.8, 0.7, 0.7 * (1 + 2.0 ** -52), 0.6, 0.5, 0.4, 0.3, 0.2])
-    kr, ka = orc.topm(ranks, amps, 4)
-    assert kr.tolist() == [0, 1, 2, 3, 4]
-    kr, ka = orc.topm(ranks, amps, 3)
-    assert kr.tolist() == [0, 1, 2]
+    assert amps[4] > amps[3]
+    assert orc.topm(ranks, amps, 4)[0].tolist() == [0, 1, 2, 4]
+    assert orc.topm(ranks, amps, 3)[0].tolist() == [0, 1, 2]
+    assert orc.topm(ranks, amps, 5)[0].tolist() == [0, 1, 2, 3, 4]
+    # exact ties across the cut go to the lower rank, whatever the sign
+    r = np.array([3, 5, 7, 9], dtype=np.uint64)
+    a = np.array([0.5, -0.5, 0.75, 0.5])
+    assert orc.topm(r, a, 2)[0].tolist() == [3, 7]
+    assert orc.topm(r, a, 3)[0].tolist() == [3, 5, 7]
+    # M = 0 keeps nothing; M >= nonzero keeps every nonzero entry
+    assert len(orc.topm(r, a, 0)[0]) == 0
+    z = np.array([0.0, 1.0, 0.0, -2.0])
+    assert orc.topm(r, z, 3)[0].tolist() == [5, 9]
+
+
+def test_topm_band_extension(orc):
+    # the opt-in extension: entries within a relative 2^-36 of the M-th |c|
+    # stay with it, unless more than 256 would be added
+    ranks = np.arange(10, dtype=np.uint64)
+    amps = np.array([1.0, 0.9, 0.8, 0.7 * (1 + 2.0 ** -52), 0.7, 0.6, 0.5, 0.4, 0.3, 0.2])
+    assert orc.topm(ranks, amps, 4, tie_band=True)[0].tolist() == [0, 1, 2, 3, 4]
+    assert orc.topm(ranks, amps, 4)[0].tolist() == [0, 1, 2, 3]
+    gap = amps.copy()
+    gap[4] = 0.7 * (1 - 2.0 ** -30)  # a real gap still cuts
+    assert orc.topm(ranks, gap, 4, tie_band=True)[0].tolist() == [0, 1, 2, 3]
+    rng = np.random.default_rng(3)
+    r = np.sort(rng.choice(10_000, 2000, replace=False)).astype(np.uint64)
+    x = rng.normal(size=2000)
+    x[100:160] = 0.25 * np.sign(rng.normal(size=60))
+    above = int(np.sum(np.abs(x) > 0.25))
+    kr, _ = orc.topm(r, x, above + 5, tie_band=True)  # the M-th entry is one of 60 ties: all kept
+    assert len(kr) == above + 60
+    x[:400] = 0.5
+    kr, _ = orc.topm(r, x, 100, tie_band=True)  # 400 ties: more than 256 extra, exactly M kept
+    assert len(kr) == 100
 
 
 def test_normalize(orc):
