@@ -100,6 +100,9 @@ typedef struct {
                           truncation (the paper uses 5e-5); 0 = off */
     int32_t tie_band;  /* 1: the truncation extension described at SFCI_TIE_SLACK; 0 = the paper's rule */
     int32_t reserved;  /* must be 0 */
+    double excite_eps; /* excitation screen (the heat-bath idea Sec. 4 names for future work): a double
+                          excitation's term H_ki v_i with |H_ki v_i| < excite_eps is not generated; singles
+                          and the diagonal always are.  0 = off */
 } sfci_sigma_opts;
 
 typedef struct {
@@ -162,6 +165,8 @@ typedef struct {
                               Not available in the batched call (SFCI_E_UNSUPPORTED there). */
     int32_t tie_band;      /* 1: the truncation extension described at SFCI_TIE_SLACK; 0 = the paper's rule */
     int32_t reserved;      /* must be 0 */
+    double excite_eps;     /* excitation screen of every H w_j, as in sfci_sigma_opts; 0 = off.  The
+                              gradients of the batched call are those of the unscreened energy at Psi. */
 } sfci_lanczos_opts;
 
 typedef struct {
@@ -245,14 +250,16 @@ sfci_status sfci_energy_gradients(sfci_problem* prob, const sfci_svec* psi, int3
  * Many instances (e.g. points along a bond-stretch curve) with uneven
  * truncations M_k, and possibly different orbital counts, iterate together:
  * each sigma application of all instances is one launch of the target-owned
- * tile kernel, and after one eager block every iteration step is replayed
- * from a captured hipGraph.  All problems must share one device and stream. */
+ * tile kernel, and after one eager block every iteration step (its
+ * preparation, the tile launch and the vector operations) is replayed from
+ * one captured hipGraph.  All problems must share one device and stream. */
 typedef struct sfci_batch sfci_batch;
 
 typedef struct {
     double fwd_ms;              /* device time of the iteration (all blocks) */
     double bwd_ms;              /* device time of the gradient pass */
-    double sigma_ms;            /* sum over the sigma launches (events bracket each launch) */
+    double sigma_ms;            /* sum over the sigma launches: HIP events around each eager launch and
+                                   event-record nodes around the launch inside each replayed step graph */
     uint64_t terms_emitted;     /* nonzero-element terms over all sigma applications and instances */
     uint64_t nnz_in_total;      /* input entries over all sigma applications and instances */
     uint64_t sigma_calls;       /* sigma applications per instance (= launches when batched_sigma) */
@@ -265,6 +272,8 @@ typedef struct {
     uint32_t tune_per_cu;
     double tune_default_ms;     /* trial time of the default sizes and of the chosen ones (when tuned) */
     double tune_best_ms;
+    int32_t sigma_in_graph;     /* 1: each replayed step was one graph, the tile launch inside it */
+    int32_t reserved;
 } sfci_batch_stats;
 
 /* probs: n_inst problem handles (kept, not owned). */

@@ -59,6 +59,8 @@ def lib():
         L.orc_source_terms.argtypes = [i32, i32, i32, f64p, f64p, u64, vp, vp, i64]
         L.orc_sigma.restype = i64
         L.orc_sigma.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, vp, vp, vp, i64]
+        L.orc_sigma_x.restype = i64
+        L.orc_sigma_x.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, vp, vp, vp, i64, dbl]
         L.orc_sigma_entry.restype = dbl
         L.orc_sigma_entry.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, u64, C.POINTER(dbl)]
         L.orc_topm.restype = i64; L.orc_topm.argtypes = [i64, u64p, f64p, i64, u64p, f64p]
@@ -74,7 +76,7 @@ def lib():
                                         vp, vp, i64, dbl, i32, vp, vp, vp]
         L.orc_lanczos_ex.restype = i64
         L.orc_lanczos_ex.argtypes = [i32, i32, i32, f64p, f64p, i64, u64p, f64p, i64, i32, i32, f64p, vp, vp,
-                                     vp, vp, i64, dbl, i32, vp, vp, vp, i32, dbl, C.POINTER(i32), vp]
+                                     vp, vp, i64, dbl, i32, vp, vp, vp, i32, dbl, C.POINTER(i32), vp, dbl]
         L.orc_set_threads.restype = None; L.orc_set_threads.argtypes = [i32]
         L.orc_get_threads.restype = i32; L.orc_get_threads.argtypes = []
         L.orc_pt2.restype = i32
@@ -153,16 +155,17 @@ class Problem:
         lib().orc_source_terms(*self._a(), int(src), _ptr(t), _ptr(e), need)
         return t, e
 
-    def sigma(self, ranks, amps, with_abs=False):
+    def sigma(self, ranks, amps, with_abs=False, eps_x=0.0):
+        """eps_x > 0: double-excitation terms with |H_ki v_i| < eps_x are not generated."""
         r, a = _u64(ranks), _f64(amps)
-        need = lib().orc_sigma(*self._a(), r.size, r, a, None, None, None, 0)
+        need = lib().orc_sigma_x(*self._a(), r.size, r, a, None, None, None, 0, float(eps_x))
         if need == -1:
             raise ValueError("invalid input vector")
         cnt = -need if need < 0 else need
         orank = np.empty(cnt, dtype=np.uint64)
         oamp = np.empty(cnt, dtype=np.float64)
         oabs = np.empty(cnt, dtype=np.float64)
-        got = lib().orc_sigma(*self._a(), r.size, r, a, _ptr(orank), _ptr(oamp), _ptr(oabs), cnt)
+        got = lib().orc_sigma_x(*self._a(), r.size, r, a, _ptr(orank), _ptr(oamp), _ptr(oabs), cnt, float(eps_x))
         assert got == cnt
         return (orank, oamp, oabs) if with_abs else (orank, oamp)
 
@@ -172,7 +175,7 @@ class Problem:
         return v, ab.value
 
     def lanczos(self, ranks0, amps0, M, n_L, n_iter, want_T=False, eps=0.0, roots=None, tie_band=False,
-                conv_eps=0.0):
+                conv_eps=0.0, eps_x=0.0):
         """roots: list of (ranks, amps) of previously found eigenvectors to project out.
         tie_band: the truncation extension of orc_topm_band (default: the paper's rule).
         conv_eps > 0: halt after block n >= 1 once E(n-1) - E(n) < conv_eps; the
@@ -194,7 +197,7 @@ class Problem:
         nrun = C.c_int(0)
         bnnz = np.zeros(nblk * n_L, dtype=np.int64)
         args = (float(eps), len(roots), _ptr(off), _ptr(rcat), _ptr(acat), 1 if tie_band else 0, float(conv_eps),
-                C.byref(nrun), _ptr(bnnz))
+                C.byref(nrun), _ptr(bnnz), float(eps_x))
         # Psi holds at most n_L truncated vectors (or the whole space): one run
         # fills it; a second run happens only if that bound is too small
         cap = self.n_det if M < 0 else min(self.n_det, n_L * (M + (256 if tie_band else 0)))

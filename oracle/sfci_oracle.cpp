@@ -322,24 +322,27 @@ static double single_element(const Space& S, u64 same, const std::vector<int>& o
 // Enumerate all (target alpha, target beta, element) of one source in the
 // canonical order: diagonal; alpha singles; beta singles; alpha-alpha doubles
 // (i<j, a<b lexicographic); beta-beta doubles; alpha-beta doubles (i,a,j,b).
-// Elements that are exactly 0.0 are not reported.
+// Elements that are exactly 0.0 are not reported.  f(A', B', element, kind)
+// with kind 0 = diagonal, 1 = single, 2 = double excitation.
+enum { TERM_DIAG = 0, TERM_SINGLE = 1, TERM_DOUBLE = 2 };
+
 template <class F>
-static void sc_terms(const Space& S, u64 A, u64 B, F&& f) {
+static void sc_terms_kind(const Space& S, u64 A, u64 B, F&& f) {
     const int n = S.n;
     static thread_local std::vector<int> oa, va, ob, vb;
     occ_virt(A, n, oa, va);
     occ_virt(B, n, ob, vb);
     double e = diag_element(S, oa, ob);
-    if (e != 0.0) f(A, B, e);
+    if (e != 0.0) f(A, B, e, TERM_DIAG);
     for (int i : oa)
         for (int a : va) {
             double x = single_element(S, A, oa, ob, i, a);
-            if (x != 0.0) f(A ^ (1ull << i) ^ (1ull << a), B, x);
+            if (x != 0.0) f(A ^ (1ull << i) ^ (1ull << a), B, x, TERM_SINGLE);
         }
     for (int i : ob)
         for (int a : vb) {
             double x = single_element(S, B, ob, oa, i, a);
-            if (x != 0.0) f(A, B ^ (1ull << i) ^ (1ull << a), x);
+            if (x != 0.0) f(A, B ^ (1ull << i) ^ (1ull << a), x, TERM_SINGLE);
         }
     for (int spin = 0; spin < 2; ++spin) {
         u64 Str = spin == 0 ? A : B;
@@ -355,7 +358,7 @@ static void sc_terms(const Space& S, u64 A, u64 B, F&& f) {
                         double v = (double)sg * (S.G(i, a, j, b) - S.G(i, b, j, a));
                         if (v == 0.0) continue;
                         u64 T = mid ^ (1ull << j) ^ (1ull << b);
-                        if (spin == 0) f(T, B, v); else f(A, T, v);
+                        if (spin == 0) f(T, B, v, TERM_DOUBLE); else f(A, T, v, TERM_DOUBLE);
                     }
     }
     for (int i : oa)
@@ -367,9 +370,14 @@ static void sc_terms(const Space& S, u64 A, u64 B, F&& f) {
                     int sb = single_sign(B, j, b);
                     double v = (double)(sa * sb) * S.G(i, a, j, b);
                     if (v == 0.0) continue;
-                    f(A2, B ^ (1ull << j) ^ (1ull << b), v);
+                    f(A2, B ^ (1ull << j) ^ (1ull << b), v, TERM_DOUBLE);
                 }
         }
+}
+
+template <class F>
+static void sc_terms(const Space& S, u64 A, u64 B, F&& f) {
+    sc_terms_kind(S, A, B, [&](u64 A2, u64 B2, double e, int) { f(A2, B2, e); });
 }
 
 // Matrix element <target|H|source> by Slater-Condon generation from the
@@ -438,7 +446,16 @@ static void merge_chunk(std::vector<Acc>& run, const std::vector<Tup>& tup) {
     run.swap(next);
 }
 
-static std::vector<Acc> sigma_merged_seq(const Space& S, i64 nnz, const u64* rank, const double* amp) {
+// eps_x > 0: the excitation screen -- a double excitation's term H_ki v_i is
+// not generated when |H_ki v_i| < eps_x (the element of a double depends only
+// on its four orbitals: the heat-bath idea named for future work in Sec. 4).
+// Singles and the diagonal are always generated.
+static inline bool screened(int kind, double t, double eps_x) {
+    return kind == TERM_DOUBLE && std::fabs(t) < eps_x;
+}
+
+static std::vector<Acc> sigma_merged_seq(const Space& S, i64 nnz, const u64* rank, const double* amp,
+                                         double eps_x) {
     const int na = S.na, nb = S.nb;
     std::vector<Acc> run;       // merged so far, ascending rank
     std::vector<Tup> tup;
@@ -450,8 +467,10 @@ static std::vector<Acc> sigma_merged_seq(const Space& S, i64 nnz, const u64* ran
         while (t < nnz && tup.size() < chunk_cap) {
             u64 A = orc_str_unrank(rank[t] / S.Nb, na), B = orc_str_unrank(rank[t] % S.Nb, nb);
             double vi = amp[t];
-            sc_terms(S, A, B, [&](u64 A2, u64 B2, double e) {
-                tup.push_back({orc_str_rank(A2) * S.Nb + orc_str_rank(B2), e * vi});
+            sc_terms_kind(S, A, B, [&](u64 A2, u64 B2, double e, int kind) {
+                const double tv = e * vi;
+                if (screened(kind, tv, eps_x)) return;
+                tup.push_back({orc_str_rank(A2) * S.Nb + orc_str_rank(B2), tv});
             });
             ++t;
         }
@@ -474,7 +493,8 @@ static int g_threads = 1;
 extern "C" void orc_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
 extern "C" int orc_get_threads(void) { return g_threads; }
 
-static std::vector<Acc> sigma_merged_buckets(const Space& S, i64 nnz, const u64* rank, const double* amp, int T) {
+static std::vector<Acc> sigma_merged_buckets(const Space& S, i64 nnz, const u64* rank, const double* amp, int T,
+                                             double eps_x) {
     const int na = S.na, nb = S.nb, n = S.n;
     const int NB = 16 * T;
     const u64 width = S.Ndet / (u64)NB + 1;
@@ -493,9 +513,11 @@ static std::vector<Acc> sigma_merged_buckets(const Space& S, i64 nnz, const u64*
             for (i64 t = lo; t < hi; ++t) {
                 u64 A = orc_str_unrank(rank[t] / S.Nb, na), B = orc_str_unrank(rank[t] % S.Nb, nb);
                 double vi = amp[t];
-                sc_terms(S, A, B, [&](u64 A2, u64 B2, double e) {
+                sc_terms_kind(S, A, B, [&](u64 A2, u64 B2, double e, int kind) {
+                    const double tv = e * vi;
+                    if (screened(kind, tv, eps_x)) return;
                     const u64 R = orc_str_rank(A2) * S.Nb + orc_str_rank(B2);
-                    loc[k][R / width].push_back({R, e * vi});
+                    loc[k][R / width].push_back({R, tv});
                 });
             }
         }
@@ -515,20 +537,21 @@ static std::vector<Acc> sigma_merged_buckets(const Space& S, i64 nnz, const u64*
     return out;
 }
 
-static std::vector<Acc> sigma_merged(const Space& S, i64 nnz, const u64* rank, const double* amp) {
-    if (g_threads > 1) return sigma_merged_buckets(S, nnz, rank, amp, g_threads);
-    return sigma_merged_seq(S, nnz, rank, amp);
+static std::vector<Acc> sigma_merged(const Space& S, i64 nnz, const u64* rank, const double* amp,
+                                     double eps_x = 0.0) {
+    if (g_threads > 1) return sigma_merged_buckets(S, nnz, rank, amp, g_threads, eps_x);
+    return sigma_merged_seq(S, nnz, rank, amp, eps_x);
 }
 
-extern "C" i64 orc_sigma(int n, int na, int nb, const double* h, const double* g, i64 nnz,
-                         const u64* rank, const double* amp, u64* out_rank, double* out_amp,
-                         double* out_abs, i64 cap) {
+extern "C" i64 orc_sigma_x(int n, int na, int nb, const double* h, const double* g, i64 nnz,
+                           const u64* rank, const double* amp, u64* out_rank, double* out_amp,
+                           double* out_abs, i64 cap, double eps_x) {
     Space S = make_space(n, na, nb, h, g);
     for (i64 t = 0; t < nnz; ++t) {
         if (rank[t] >= S.Ndet) return -1;
         if (t > 0 && rank[t] <= rank[t - 1]) return -1;
     }
-    std::vector<Acc> run = sigma_merged(S, nnz, rank, amp);
+    std::vector<Acc> run = sigma_merged(S, nnz, rank, amp, eps_x);
     i64 cnt = 0;
     for (const Acc& e : run)
         if (e.v != 0.0) ++cnt;
@@ -541,6 +564,12 @@ extern "C" i64 orc_sigma(int n, int na, int nb, const double* h, const double* g
         ++o;
     }
     return cnt;
+}
+
+extern "C" i64 orc_sigma(int n, int na, int nb, const double* h, const double* g, i64 nnz,
+                         const u64* rank, const double* amp, u64* out_rank, double* out_amp,
+                         double* out_abs, i64 cap) {
+    return orc_sigma_x(n, na, nb, h, g, nnz, rank, amp, out_rank, out_amp, out_abs, cap, 0.0);
 }
 
 // One output entry by its plain definition: sigma_k = sum_i H_ki v_i with the
@@ -745,8 +774,8 @@ static double sdot(const SVec& x, const SVec& y) {
     return s;
 }
 
-static SVec sigma_full(const Space& S, const SVec& v) {
-    std::vector<Acc> run = sigma_merged(S, (i64)v.r.size(), v.r.data(), v.a.data());
+static SVec sigma_full(const Space& S, const SVec& v, double eps_x = 0.0) {
+    std::vector<Acc> run = sigma_merged(S, (i64)v.r.size(), v.r.data(), v.a.data(), eps_x);
     SVec y;
     for (const Acc& e : run)
         if (e.v != 0.0) { y.r.push_back(e.r); y.a.push_back(e.v); }
@@ -849,12 +878,13 @@ static SVec project(const Roots& R, SVec y) {
 // writes it); *blocks_run (may be NULL) receives the number of blocks run and
 // energies[] beyond it are left untouched.  basis_nnz (may be NULL, n_iter
 // entries) receives the entry count of every basis vector w_j, block after
-// block.
+// block.  eps_x > 0: every H w_j with the excitation screen of sigma_merged
+// (the roots' H Psi_i are not screened).
 extern "C" i64 orc_lanczos_ex(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
                               const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
                               double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
                               int n_roots, const i64* root_off, const u64* root_r, const double* root_a, int band,
-                              double conv_eps, int* blocks_run, i64* basis_nnz) {
+                              double conv_eps, int* blocks_run, i64* basis_nnz, double eps_x) {
     Space S = make_space(n, na, nb, h, g);
     Roots R;
     for (int i = 0; i < n_roots; ++i) {
@@ -881,7 +911,7 @@ extern "C" i64 orc_lanczos_ex(int n, int na, int nb, const double* h, const doub
         std::vector<double> T(nL * nL, 0.0), Sm(nL * nL, 0.0);
         for (int j = 0; j < nL; ++j) {
             if (basis_nnz) basis_nnz[(size_t)blk * nL + j] = (i64)w[j].r.size();
-            SVec y = sigma_full(S, w[j]);
+            SVec y = sigma_full(S, w[j], eps_x);
             if (eps > 0.0) {
                 SVec ys;
                 for (size_t t = 0; t < y.r.size(); ++t)
@@ -950,14 +980,14 @@ extern "C" i64 orc_lanczos_roots(int n, int na, int nb, const double* h, const d
                                  double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps,
                                  int n_roots, const i64* root_off, const u64* root_r, const double* root_a) {
     return orc_lanczos_ex(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
-                          psi_cap, eps, n_roots, root_off, root_r, root_a, 0, 0.0, nullptr, nullptr);
+                          psi_cap, eps, n_roots, root_off, root_r, root_a, 0, 0.0, nullptr, nullptr, 0.0);
 }
 
 extern "C" i64 orc_lanczos(int n, int na, int nb, const double* h, const double* g, i64 nnz0, const u64* r0,
                            const double* a0, i64 M, int nL, int n_iter, double* energies, double* Tout,
                            double* Sout, u64* psi_rank, double* psi_amp, i64 psi_cap, double eps) {
     return orc_lanczos_ex(n, na, nb, h, g, nnz0, r0, a0, M, nL, n_iter, energies, Tout, Sout, psi_rank, psi_amp,
-                          psi_cap, eps, 0, nullptr, nullptr, nullptr, 0, 0.0, nullptr, nullptr);
+                          psi_cap, eps, 0, nullptr, nullptr, nullptr, 0, 0.0, nullptr, nullptr, 0.0);
 }
 
 // ---------------------------------------------------------------------------

@@ -253,6 +253,8 @@ sfci_status sfci_problem_destroy(sfci_problem* P) {
     P->ws_rt_beta.release();
     P->ws_rt_nbr.release();
     P->ws_rt_desc.release();
+    for (DevBuf* b : {&P->ws_ab_rc, &P->ws_ab_cr, &P->ws_ab_off, &P->ws_ab_it, &P->ws_rt_phase})
+        b->release();
     P->grad_ws.release();
     P->list_ws.release();
     for (int i = 0; i < SFCI_MAX_ROOTS; ++i) {
@@ -300,9 +302,11 @@ sfci_status sfci_sigma(sfci_problem* P, const sfci_svec* v, const sfci_sigma_opt
     if (!P || !v || !opts || !out) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL argument");
     if (v->nnz && (!v->rank || !v->amp)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "NULL input arrays");
     if (opts->dedup < 0 || opts->dedup > 3) return (sfci_status)sfci_set_error(SFCI_E_ARG, "bad dedup mode");
-    if (!(opts->screen_eps >= 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps must be >= 0");
+    if (!(opts->screen_eps >= 0.0) || !(opts->excite_eps >= 0.0))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps and excite_eps must be >= 0");
     validate_vec(P, v->rank, v->nnz);
     P->tie_band = opts->tie_band ? 1 : 0;
+    P->excite_eps = opts->excite_eps;
     hipEvent_t e0, e1;
     SFCI_CHECK_HIP(hipEventCreate(&e0));
     SFCI_CHECK_HIP(hipEventCreate(&e1));
@@ -437,10 +441,11 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
     if (o->n_L < 1 || o->n_L > 32 || o->n_iter < o->n_L)
         return (sfci_status)sfci_set_error(SFCI_E_ARG, "need 1 <= n_L <= 32 and n_iter >= n_L");
     if (v0->nnz == 0) return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty start vector");
-    if (!(o->screen_eps >= 0.0) || !(o->conv_eps >= 0.0))
-        return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps and conv_eps must be >= 0");
+    if (!(o->screen_eps >= 0.0) || !(o->conv_eps >= 0.0) || !(o->excite_eps >= 0.0))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps, conv_eps and excite_eps must be >= 0");
     validate_vec(P, v0->rank, v0->nnz);
     P->tie_band = o->tie_band ? 1 : 0;
+    P->excite_eps = o->excite_eps;
     const int nL = o->n_L;
     const int nblk = o->n_iter / nL;
     const bool det = o->deterministic != 0;
@@ -493,7 +498,9 @@ sfci_status sfci_lanczos_roots(sfci_problem* P, const sfci_svec* v0, const sfci_
         u64 *yr;
         double* ya;
         const SigmaLaunch rl{roots[i].rank, roots[i].amp, rcnt + i, roots[i].nnz};
+        P->excite_eps = 0.0;  // H Psi_i in full
         const u64 ny = sigma_full_list(P, rl, det, sc + 40, &yr, &ya, rcnt + SFCI_MAX_ROOTS + i);
+        P->excite_eps = o->excite_eps;
         hcap[i] = std::max<u64>(1, ny);
         u64* hr = (u64*)P->ws_hroot_r[i].get(hcap[i] * sizeof(u64));
         double* ha = (double*)P->ws_hroot_a[i].get(hcap[i] * sizeof(double));

@@ -4,7 +4,8 @@
 // ONE launch of the target-owned tile kernel; the rest of an iteration (T/S
 // gathers, Eq. 10, truncation, Eq. 11) is issued per instance on the shared
 // stream.  After one eager block has sized and allocated every buffer, each
-// iteration step and the block end are captured into hipGraphs and replayed.
+// iteration step (preparation, the tile launch, the vector operations) and
+// the block end are captured into hipGraphs and replayed.
 // After the last block each instance's gradient of E = <Psi|H|Psi>/<Psi|Psi>
 // with respect to h and (pq|rs) is computed at fixed Psi.
 #include <algorithm>
@@ -131,7 +132,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     if (o->conv_eps != 0.0)
         return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED,
                                            "the batched iteration runs n_iter / n_L blocks (no conv_eps halting)");
-    if (!(o->screen_eps >= 0.0)) return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps must be >= 0");
+    if (!(o->screen_eps >= 0.0) || !(o->excite_eps >= 0.0))
+        return (sfci_status)sfci_set_error(SFCI_E_ARG, "screen_eps and excite_eps must be >= 0");
     const int nL = o->n_L, nblk = o->n_iter / nL, n = B->n;
     const bool det = o->deterministic != 0;
     const bool use_graph = !det && (o->dedup != SFCI_DEDUP_DENSE_ATOMIC);
@@ -164,6 +166,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         Inst& q = I[k];
         q.P = P;
         P->tie_band = o->tie_band ? 1 : 0;
+        P->excite_eps = o->excite_eps;
         q.M = Ms[k];
         q.cap = (Ms[k] >= P->Ndet) ? P->Ndet
                                    : std::min<u64>(std::max<u64>(Ms[k] + tie_extra(P), v0s[k].nnz), P->Ndet);
@@ -389,9 +392,10 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         });
     };
 
-    // events: whole run, gradients, and one pair around every sigma launch
+    // events: whole run, gradients, one pair around every eager sigma launch,
+    // and one pair per iteration step recorded from inside the step graphs
     const int n_sig = nblk * nL;
-    std::vector<hipEvent_t> ev(3 + 2 * (size_t)n_sig, nullptr);
+    std::vector<hipEvent_t> ev(3 + 2 * (size_t)n_sig + 2 * (size_t)nL, nullptr);
     struct EvFree {
         std::vector<hipEvent_t>& v;
         ~EvFree() {
@@ -401,53 +405,113 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     } ev_free{ev};
     for (auto& e : ev) SFCI_CHECK_HIP(hipEventCreate(&e));
     hipEvent_t e0 = ev[0], e1 = ev[1], e2 = ev[2];
-    std::vector<hipGraphExec_t> gprep, grest;
+    hipEvent_t* gev = ev.data() + 3 + 2 * (size_t)n_sig;  // [2j], [2j+1]: step j inside its graph
+    // replayed steps: one graph per step (gstep), or, where the runtime
+    // refuses event-record nodes in a graph, the preparation and the rest of
+    // the step as two graphs with the tile launch between them (gprep, grest)
+    std::vector<hipGraphExec_t> gstep, gprep, grest;
     hipGraphExec_t gend = nullptr;
     struct GraphFree {
         std::vector<hipGraphExec_t>& a;
         std::vector<hipGraphExec_t>& b;
-        hipGraphExec_t& c;
+        std::vector<hipGraphExec_t>& c;
+        hipGraphExec_t& d;
         ~GraphFree() {
-            for (auto x : a) (void)hipGraphExecDestroy(x);
-            for (auto x : b) (void)hipGraphExecDestroy(x);
-            if (c) (void)hipGraphExecDestroy(c);
+            for (auto* v : {&a, &b, &c})
+                for (auto x : *v) (void)hipGraphExecDestroy(x);
+            if (d) (void)hipGraphExecDestroy(d);
         }
-    } graph_free{gprep, grest, gend};
-    auto capture = [&](auto&& body) {
+    } graph_free{gstep, gprep, grest, gend};
+    bool split_steps = false;
+    auto capture_graph = [&](auto&& body) {
         hipGraph_t g;
         SFCI_CHECK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         body();
         SFCI_CHECK_HIP(hipStreamEndCapture(st, &g));
+        return g;
+    };
+    auto instantiate = [&](hipGraph_t g) {
         hipGraphExec_t ex;
         hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         SFCI_CHECK_HIP(e);
         return ex;
     };
+    auto capture = [&](auto&& body) { return instantiate(capture_graph(body)); };
+    // One iteration step as one graph: the captured preparation, tile launch
+    // and vector operations as child graphs, chained through event-record
+    // nodes around the tile launch (the events time it on every replay).
+    auto step_graph = [&](int j) {
+        hipGraph_t gA = capture_graph([&] { sigma_prepare(j, false); });
+        hipGraph_t gB = capture_graph([&] { sigma_launch(j); });
+        hipGraph_t gC = capture_graph([&] { iteration_rest(j); });
+        hipGraph_t g = nullptr;
+        hipError_t e = hipGraphCreate(&g, 0);
+        hipGraphNode_t nA, e1, nB, e2, nC;
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nA, g, nullptr, 0, gA);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, g, &nA, 1, gev[2 * j]);
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nB, g, &e1, 1, gB);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e2, g, &nB, 1, gev[2 * j + 1]);
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nC, g, &e2, 1, gC);
+        (void)hipGraphDestroy(gA);  // the child nodes hold their own copies
+        (void)hipGraphDestroy(gB);
+        (void)hipGraphDestroy(gC);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (g) (void)hipGraphDestroy(g);
+            return (hipGraphExec_t) nullptr;
+        }
+        return instantiate(g);
+    };
+    double sigma_ms = 0.0;
     SFCI_CHECK_HIP(hipEventRecord(e0, st));
     int sig = 0;
     for (int b = 0; b < nblk; ++b) {
         const bool last = (b + 1 == nblk);
         const bool replay = use_graph && b >= 1;
-        if (replay && gprep.empty()) {
-            // capture the preparation and the remainder of every iteration
-            // step, and the (non-final) block end, once; the sigma launch
-            // itself stays outside the graphs so that events bracket it
-            for (int j = 0; j < nL; ++j) {
-                gprep.push_back(capture([&] { sigma_prepare(j, false); }));
-                grest.push_back(capture([&] { iteration_rest(j); }));
+        if (replay && gstep.empty()) {
+            // one graph per iteration step (step_graph) and one for the
+            // (non-final) block end
+            for (int j = 0; j < nL && !split_steps; ++j) {
+                hipGraphExec_t x = step_graph(j);
+                if (x) gstep.push_back(x);
+                else split_steps = true;
             }
+            if (split_steps)
+                for (int j = 0; j < nL; ++j) {
+                    gprep.push_back(capture([&] { sigma_prepare(j, false); }));
+                    grest.push_back(capture([&] { iteration_rest(j); }));
+                }
             gend = capture([&] { block_end(false); });
         }
         for (int j = 0; j < nL; ++j, ++sig) {
-            if (replay) SFCI_CHECK_HIP(hipGraphLaunch(gprep[j], st));
-            else sigma_prepare(j, true);
+            if (replay && !split_steps) {
+                SFCI_CHECK_HIP(hipGraphLaunch(gstep[j], st));
+                continue;
+            }
+            if (replay) {
+                SFCI_CHECK_HIP(hipGraphLaunch(gprep[j], st));
+                SFCI_CHECK_HIP(hipEventRecord(gev[2 * j], st));
+                sigma_launch(j);
+                SFCI_CHECK_HIP(hipEventRecord(gev[2 * j + 1], st));
+                SFCI_CHECK_HIP(hipGraphLaunch(grest[j], st));
+                continue;
+            }
+            sigma_prepare(j, true);
             if (autotune && !B->tuned && b == 0 && j == nL - 1) tune_on_step(j);
             SFCI_CHECK_HIP(hipEventRecord(ev[3 + 2 * sig], st));
             sigma_launch(j);
             SFCI_CHECK_HIP(hipEventRecord(ev[4 + 2 * sig], st));
-            if (replay) SFCI_CHECK_HIP(hipGraphLaunch(grest[j], st));
-            else iteration_rest(j);
+            iteration_rest(j);
+        }
+        if (replay) {
+            // the step graphs' events hold this block's sigma times until the next replay
+            for (int j = 0; j < nL; ++j) {
+                SFCI_CHECK_HIP(hipEventSynchronize(gev[2 * j + 1]));
+                float ms = 0.f;
+                SFCI_CHECK_HIP(hipEventElapsedTime(&ms, gev[2 * j], gev[2 * j + 1]));
+                sigma_ms += ms;
+            }
         }
         if (replay && !last) SFCI_CHECK_HIP(hipGraphLaunch(gend, st));
         else block_end(last);
@@ -513,8 +577,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         SFCI_CHECK_HIP(hipEventElapsedTime(&bw, e1, e2));
         stats->fwd_ms = f;
         stats->bwd_ms = bw;
-        double sms = 0.0;
+        double sms = sigma_ms;
         for (int i = 0; i < n_sig; ++i) {
+            if (use_graph && i >= nL) break;  // replayed steps: counted from the graphs' events above
             float ms = 0.f;
             SFCI_CHECK_HIP(hipEventElapsedTime(&ms, ev[3 + 2 * i], ev[4 + 2 * i]));
             sms += ms;
@@ -538,6 +603,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         stats->tune_per_cu = batched_sigma ? B->tune.per_cu : 0u;
         stats->tune_default_ms = tune_default_ms;
         stats->tune_best_ms = tune_best_ms;
+        stats->sigma_in_graph = (use_graph && nblk > 1 && !split_steps) ? 1 : 0;
+        stats->reserved = 0;
     }
     for (int k = 0; k < n; ++k)
         if (hstat[k]) return (sfci_status)sfci_set_error(SFCI_E_DEVICE, "generalized eigenproblem failed");

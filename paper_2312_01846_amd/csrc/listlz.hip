@@ -493,7 +493,7 @@ u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink
     }
     double* Dp = (double*)ws.dpass.p;
     u64* sc = (u64*)ws.scal2.get(8 * sizeof(u64));  // [0] pass count
-    const RowTileDesc all = rowtile_prepare(P, v, Dp, (unsigned long long*)emitted_dev, eps);
+    const RowTileDesc all = rowtile_prepare(P, v, Dp, (unsigned long long*)emitted_dev, eps, true);
     u64 passes = 0;
     for (u64 lo = 0; lo < P->Na; lo += rows) {
         const u64 hi = std::min<u64>(P->Na, lo + rows);

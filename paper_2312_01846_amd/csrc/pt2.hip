@@ -146,6 +146,7 @@ extern "C" sfci_status sfci_energy_gradients(sfci_problem* P, const sfci_svec* p
         if (psi->nnz == 0 || !psi->rank || !psi->amp)
             return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty vector");
         validate_vec(P, psi->rank, psi->nnz);
+        P->excite_eps = 0.0;  // the energy of the full H
         if ((dh || deri) && !ensure_dense(P))
             return (sfci_status)sfci_set_error(SFCI_E_UNSUPPORTED, "gradients need the dense array (N_det doubles)");
         const bool det = deterministic != 0;
@@ -183,6 +184,7 @@ extern "C" sfci_status sfci_pt2(sfci_problem* P, const sfci_svec* psi, int32_t d
         if (psi->nnz == 0 || !psi->rank || !psi->amp)
             return (sfci_status)sfci_set_error(SFCI_E_ARG, "empty vector");
         validate_vec(P, psi->rank, psi->nnz);
+        P->excite_eps = 0.0;  // the correction of the full H
         const bool det = deterministic != 0;
         u64* sc = (u64*)P->ws_lz[0].get(16 * sizeof(u64));  // [0] nnz(Psi) [1] emitted [2] |y| [3] n_ext
         double* sd = (double*)(sc + 8);                     // [0] num [1] den [2] E0 [3] sum

@@ -56,10 +56,15 @@ struct RPConst {
     const u32* row_end;
     int sA, sB, PA, QA, PB, QB;
     u64 c_id, c_s;  // tuples per entry of an identity pair / a single pair
-    // beta singles of every beta string (target rank | j << 21 | b << 26 |
+    // beta singles of every beta string (target rank | (j n + b) << 21 |
     // phase << 31), or nullptr: then they are enumerated and ranked per entry
     const u32* T1;
+    // excitation screen: a double's term below this magnitude is emitted as
+    // 0.0 (an exact zero leaves every in-order sum's bits unchanged)
+    double eps_x;
 };
+
+__device__ __forceinline__ double xterm(double t, double eps_x) { return xscreened(t, eps_x) ? 0.0 : t; }
 
 __device__ __forceinline__ u64 wave_sum(u64 x) {
     for (int off = 32; off >= 1; off >>= 1) x += (u64)__shfl_xor((long long)x, off);
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(RPP_BLOCK) void k_rp_pairs(RPConst c, u64 lo, u64 h
             // (pair, entry) list, each lane's pair found by a binary search
             // over the lanes' prefix counts
             const u64 dne = dbl ? pr.ne : 0;
-            if (dbl && pr.e2 != 0.0) nz += dne;
+            if (dbl && pr.e2 != 0.0 && !(c.eps_x > 0.0)) nz += dne;
             u64 dtot;
             const u64 dpre = wave_excl_scan(dne, &dtot);
             const u64 src_base = (u64)pr.src_row * Nb - (u64)pr.tgt_local * Nb;  // rank shift, mod 2^64
@@ -340,7 +345,9 @@ __global__ __launch_bounds__(RPP_BLOCK) void k_rp_pairs(RPConst c, u64 lo, u64 h
                 for (int u = 0; u < DU; ++u) {
                     if (f0 + (u64)u * 64 + lane < dtot) {
                         tkeys[o[u]] = (u32)(rk[u] - sb[u]);
-                        tvals[o[u]] = e2[u] * am[u];
+                        const double tv = xterm(e2[u] * am[u], c.eps_x);
+                        tvals[o[u]] = tv;
+                        if (c.eps_x > 0.0) nz += (e2[u] != 0.0 && tv != 0.0) ? 1 : 0;
                     }
                 }
             }
@@ -442,15 +449,16 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
 #pragma unroll
                     for (int u = 0; u < EU; ++u) t[u] = c.T1[rB[u] * sBn + o[u]];
 #pragma unroll
-                    for (int u = 0; u < EU; ++u) el[u] = gia[((t[u] >> 21) & 31u) * n + ((t[u] >> 26) & 31u)];
+                    for (int u = 0; u < EU; ++u) el[u] = gia[(t[u] >> 21) & 1023u];  // (i a | j b), j n + b from the table
 #pragma unroll
                     for (int u = 0; u < EU; ++u) {
                         if (f0 + (u32)u * 64 + lane >= nf) continue;
                         double e = el[u];
                         if (pa ^ (int)(t[u] >> 31)) e = -e;
                         keys[at[u]] = (u32)(tgt_base + (t[u] & 0x1FFFFFu));
-                        vals[at[u]] = e * am[u];
-                        nz += (e != 0.0) ? 1 : 0;
+                        const double tv = xterm(e * am[u], c.eps_x);
+                        vals[at[u]] = tv;
+                        nz += (e != 0.0 && !(tv == 0.0 && c.eps_x > 0.0)) ? 1 : 0;
                     }
                 }
                 continue;
@@ -502,9 +510,13 @@ __global__ __launch_bounds__(RP_BLOCK) void k_rp_emit(RPConst c, const RPPair* _
                         if (par) el = -el;
                         tb = str_rank(B2, B);
                     }
+                    // the alpha-beta doubles of a single pair (o >= 1) and the
+                    // beta-beta doubles of the identity pair (o > sB) are screened
+                    const bool dbl = (type == RP_SINGLE) ? (o >= 1) : ((int)o > c.sB);
+                    const double tv = dbl ? xterm(el * amp, c.eps_x) : el * amp;
                     keys[base + o] = (u32)(tgt_base + tb);
-                    vals[base + o] = el * amp;
-                    nz += (el != 0.0) ? 1 : 0;
+                    vals[base + o] = tv;
+                    nz += (el != 0.0 && !(dbl && tv == 0.0 && c.eps_x > 0.0)) ? 1 : 0;
                 }
             }
         }
@@ -543,6 +555,7 @@ u64 sigma_rowpass(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64
     c.c_id = 1 + (u64)c.sB + (u64)c.PB * c.QB;
     c.c_s = 1 + (u64)c.sB;
     c.T1 = rowtile_T1(P);
+    c.eps_x = P->excite_eps;
     const int K = 1 + c.sA + c.PA * c.QA;
     if (K > 65536) throw sfci_error(-8, "sort path: more than 65536 alpha neighbours per string");
     u32 Kp2 = 1;

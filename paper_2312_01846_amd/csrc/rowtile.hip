@@ -40,7 +40,7 @@ struct RTParams {
     const u64* rowbeg;     // per alpha rank: first input entry of that row
     const u64* rowend;     // per alpha rank: one past the last (== rowbeg when empty)
     const u32* rtb;        // per alpha rank, ntiles + 1 entry offsets: first entry with beta rank >= tile_lo[t]
-    const u32* T1;         // beta singles per beta rank, sorted by target: rank | j << 21 | b << 26 | par << 31
+    const u32* T1;         // beta singles per beta rank, sorted by target: rank | (j n + b) << 21 | par << 31
     const uint16_t* toff;  // per beta rank, ntiles + 1 offsets into its T1 slice
     const u64* tile_lo;    // ntiles + 1 rank boundaries
     int ntiles;
@@ -53,13 +53,30 @@ struct RTParams {
     const double* TS;            // per T1 entry: h_jb + sum_{k in beta\j} [(jb|kk) - (jk|kb)]
     const double* K4;            // [(i<j), (a<b)] pair-indexed (ia|jb) - (ib|ja), pair (x<y) -> y(y-1)/2 + x
     const u32* T2r;              // per beta rank, its beta-beta doubles: target beta rank
-    const double* T2e;           //   and element with both phases, (ia|jb) - (ib|ja) signed
-                                 // (rows of one tile with a small table only; else nullptr)
+    const double* T2e;           //   and element with both phases, (ia|jb) - (ib|ja) signed,
+                                 // grouped by target tile (pair order within a tile); nullptr
+                                 // when the table is not built (too large)
+    const uint16_t* toff2;       // per beta rank, ntiles + 1 offsets of the tile groups in its T2 slice
     double eps;                  // sigma: screening threshold (Sec. 3), 0 = off
+    double eps_x;                // sigma: excitation screen of the doubles' terms, 0 = off
     u64 item_base;               // items of this description start at this global item
     u64 row_base;                // D holds target rows from this alpha rank on
     u32 tile_chunk;              // consecutive tiles of one row per work unit
     u32 pad_chunk;
+    // Rows of several tiles (sigma): the alpha-beta doubles' items of every
+    // input chunk (up to AB_CHUNK consecutive entries of one alpha row), by
+    // target tile: the items of (chunk c, tile t) are ab_it[ab_off[c ntiles
+    // + t] .. ab_off[c ntiles + t + 1]), each a beta single of one of the
+    // chunk's entries packed as ab_item below.  ab_rowchunk[r]: first chunk of
+    // alpha row r.  nullptr where the lists were not built.
+    const u32* ab_it;
+    const u64* ab_off;
+    const u64* ab_rowchunk;
+    // sigma: optional per-phase wavefront time (wall clock ticks), 8 bins
+    // summed over wavefronts: neighbour records, direct targets, alpha-beta
+    // units, identity beta-single units, beta-beta units, barrier wait and
+    // tile write, other units, work fetch.  nullptr = off.
+    unsigned long long* phase_ns;
 };
 
 // One contributing source row of the current (target row, tile).
@@ -76,11 +93,22 @@ struct WaveScratch {
     uint8_t occ[32], vir[32];
 };
 
-// Packed beta single (T1 entry): target beta rank, j (annihilated), b (created), phase.
+// Packed beta single (T1 entry): target beta rank (bits 0..20), j n + b for
+// the annihilated j and created b (bits 21..30: the index of (xx|jb) within
+// an n x n slab of the integrals), phase (bit 31).
 __device__ __forceinline__ u32 t1_rank(u32 t) { return t & 0x1FFFFFu; }
-__device__ __forceinline__ int t1_j(u32 t) { return (int)((t >> 21) & 31u); }
-__device__ __forceinline__ int t1_b(u32 t) { return (int)((t >> 26) & 31u); }
+__device__ __forceinline__ u32 t1_jb(u32 t) { return (t >> 21) & 1023u; }
 __device__ __forceinline__ int t1_par(u32 t) { return (int)(t >> 31); }
+
+// Input entries per chunk of the alpha-beta item lists (one wavefront's lanes).
+constexpr unsigned AB_CHUNK = 64;
+
+// An alpha-beta item: target beta rank within its tile (bits 0..13, tiles
+// hold at most 16 384 ranks), j n + b of the beta single (bits 14..23), the
+// entry within its chunk (bits 24..29), beta phase (bit 31, as in T1).
+__device__ __forceinline__ u32 ab_item(u32 rank_in_tile, u32 te, u32 entry) {
+    return rank_in_tile | (((te >> 21) & 1023u) << 14) | (entry << 24) | (te & 0x80000000u);
+}
 
 // Entries of the identity row per beta-beta-double and per beta-single work unit.
 // Default work per unit of the identity row's beta-beta doubles and beta
@@ -160,7 +188,7 @@ enum { RT_SIGMA = 0, RT_GRAD_A = 1, RT_GRAD_B = 2 };
 // One launch serves one or many problem instances: item i belongs to the
 // instance whose [item_prefix[k], item_prefix[k+1]) holds it; a workgroup
 // reloads the instance description when consecutive items change instance.
-template <int MODE>
+template <int MODE, bool TIMED = false>
 __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
                                              int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off,
@@ -172,7 +200,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     __shared__ WaveScratch sw[RT_WAVES];
     __shared__ uint8_t occA[32], virA[32];
     __shared__ uint16_t pairNA[SFCI_MAX_PAIRS], pairVA[SFCI_MAX_PAIRS], pairNB[SFCI_MAX_PAIRS], pairVB[SFCI_MAX_PAIRS];
-    __shared__ unsigned s_nbr, s_nlist, s_next, s_next2, s_touched, s_idb, s_ide;
+    // the item's records: alpha-single source rows at list[0, s_nlist), the
+    // others at list[nbr_cap - s_nlist2, nbr_cap) (phase 3 visits only the former)
+    __shared__ unsigned s_nbr, s_nlist, s_nlist2, s_next, s_next2, s_touched, s_idb, s_ide;
     __shared__ u64 s_item, s_left;  // current item (row * ntiles + tile); tiles of its row still to do
     __shared__ int s_inst, s_cur;
     // sigma with several tiles per row: the row's neighbour records, kept
@@ -181,11 +211,37 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     __shared__ int s_cache_inst;
     __shared__ unsigned s_nrow;
     __shared__ RTParams p;
+    __shared__ unsigned long long s_ph[RT_WAVES][8];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < RT_WAVES * 8) s_ph[threadIdx.x >> 3][threadIdx.x & 7] = 0;
+    u64 t_mark = 0;  // phase timing: the last timestamp of this wavefront
+    auto ph_add = [&](bool on, int bin) {
+        if (on) {
+            const u64 now = wall_clock64();
+            if (lane == 0 && t_mark) s_ph[wave][bin] += now - t_mark;
+            t_mark = now;
+        }
+    };
     WaveScratch& W = sw[wave];
     NbrRec* list = (NbrRec*)nbr_scratch + (u64)blockIdx.x * 2 * nbr_cap;
     NbrRec* rowlist = list + nbr_cap;
+    // append the kept records of a wavefront: alpha singles at the front, the rest from the back
+    auto push = [&](const NbrRec& r, bool keep) {
+        const bool k1 = keep && r.type == 1;
+        const bool k2 = keep && r.type != 1;
+        const u64 m1 = __ballot(k1), m2 = __ballot(k2);
+        unsigned s1 = 0, s2 = 0;
+        if (lane_id() == 0) {
+            if (m1) s1 = atomicAdd(&s_nlist, (unsigned)__popcll(m1));
+            if (m2) s2 = atomicAdd(&s_nlist2, (unsigned)__popcll(m2));
+        }
+        s1 = __shfl(s1, 0);
+        s2 = __shfl(s2, 0);
+        const u64 lt = (1ull << lane_id()) - 1ull;
+        if (k1) list[s1 + __popcll(m1 & lt)] = r;
+        if (k2) list[nbr_cap - 1 - (s2 + __popcll(m2 & lt))] = r;
+    };
     const u64 total_items = item_prefix[n_inst];
     load_binom(sB, descs[0].binom);  // the binomial table is the same for every instance
     // gradient passes: per wavefront, an n^2 slab of (j, b) weights (first
@@ -202,6 +258,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         s_nrow = 0;
     }
     u64 my_terms = 0;
+    u32 wterms = 0;  // terms counted per wavefront (ballot), folded into lane 0's my_terms
 
     // The counter hands out target rows (item_prefix counts rows per
     // instance); a workgroup then takes the row's tiles one after another.
@@ -233,6 +290,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             }
             s_nbr = 0;
             s_nlist = 0;
+            s_nlist2 = 0;
             s_next = 0;
             s_next2 = 0;
             s_touched = 0;
@@ -243,6 +301,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         if (s_item == ~0ull) break;
         if (s_inst != s_cur) {
             // new instance: flush the term count of the previous one, load the description
+            if (lane == 0) my_terms += wterms;
+            wterms = 0;
             for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
             if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
             my_terms = 0;
@@ -267,6 +327,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             if (threadIdx.x == 0) s_cur = s_inst;
             __syncthreads();
         }
+        const bool timing = TIMED && !GRAD && p.phase_ns != nullptr;
+        ph_add(timing, 7);
         const int n = p.sp.n, na = p.sp.na, nb = p.sp.nb;
         const int nva = n - na, nvb = n - nb;
         const u64 Nb = p.sp.Nb;
@@ -316,12 +378,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     }
                     if (r.type == 2 && r.e1 <= r.e0) r.type = 255;
                 }
-                const bool keep = r.type != 255;
-                const u64 m = __ballot(keep);
-                unsigned slot0 = 0;
-                if (lane == 0 && m) slot0 = atomicAdd(&s_nlist, (unsigned)__popcll(m));
-                slot0 = __shfl(slot0, 0);
-                if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
+                push(r, r.type != 255);
             }
         }
         for (;;) {
@@ -418,12 +475,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     rowlist[rs0 + __popcll(mr & ((1ull << lane) - 1ull))] = rr;
                 }
             }
-            const bool keep = r.type != 255;
-            const u64 m = __ballot(keep);
-            unsigned slot0 = 0;
-            if (lane == 0 && m) slot0 = atomicAdd(&s_nlist, (unsigned)__popcll(m));
-            slot0 = __shfl(slot0, 0);
-            if (keep) list[slot0 + __popcll(m & ((1ull << lane) - 1ull))] = r;
+            push(r, r.type != 255);
         }
         if (multi && !cached) {
             __syncthreads();
@@ -439,7 +491,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             itab[2 * n * n + 32] = x;
         }
         __syncthreads();
-        const unsigned nlist = s_nlist;
+        ph_add(timing, 0);
+        const unsigned n1 = s_nlist, nlist = s_nlist + s_nlist2;
+        auto rec = [&](unsigned li) -> const NbrRec& { return list[li < n1 ? li : nbr_cap - 1 - (li - n1)]; };
         if (nlist == 0) continue;  // nothing lands here: D stays zero
         if (threadIdx.x == 0) s_touched = 1;
 
@@ -447,7 +501,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         // per source row; long ranges: one wavefront, lanes over the entries.
         if (!GRAD) {
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
-                const NbrRec r = list[li];
+                const NbrRec r = rec(li);
                 if (r.e1 - r.e0 > 32) continue;
                 // RT_UNROLL entries at a time, their loads in flight together
                 for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
@@ -464,8 +518,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     for (int u = 0; u < RT_UNROLL; ++u) {
                         if (k0 + (u32)u >= r.e1) continue;
                         const double e = (r.type == 2) ? r.cst : direct_element(p, r, bt[u], itab, nullptr);
-                        if (e != 0.0) {
-                            atomicAdd(&acc[rb[u] - tlo], e * c[u]);
+                        const double t = e * c[u];
+                        if (e != 0.0 && !(r.type == 2 && xscreened(t, p.eps_x))) {
+                            atomicAdd(&acc[rb[u] - tlo], t);
                             ++my_terms;
                         }
                     }
@@ -476,7 +531,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (lane == 0) li = atomicAdd(&s_next2, 1u);
                 li = __shfl(li, 0);
                 if (li >= nlist) break;
-                const NbrRec r = list[li];
+                const NbrRec r = rec(li);
                 if (r.e1 - r.e0 <= 32) continue;
                 const double* gq = nullptr;
                 if (r.type == 1) {
@@ -506,8 +561,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     for (int u = 0; u < RT_UNROLL; ++u) {
                         if (k0 + (u32)u * 64 + lane >= r.e1) continue;
                         const double e = (r.type == 2) ? r.cst : direct_element(p, r, bt[u], itab, gq);
-                        if (e != 0.0) {
-                            atomicAdd(&acc[rb[u] - tlo], e * c[u]);
+                        const double t = e * c[u];
+                        if (e != 0.0 && !(r.type == 2 && xscreened(t, p.eps_x))) {
+                            atomicAdd(&acc[rb[u] - tlo], t);
                             ++my_terms;
                         }
                     }
@@ -521,7 +577,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             const u32 n2 = (u32)n * n;
             auto gi = [&](int a_, int b_, int c_, int d_) { return (((u32)a_ * n + b_) * n + c_) * n + d_; };
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
-                const NbrRec r = list[li];
+                const NbrRec r = rec(li);
                 if (r.type != 2 || r.e1 - r.e0 > 32) continue;
                 double w = 0.0;
                 // RT_UNROLL entries' loads in flight together; the sum keeps entry order
@@ -550,7 +606,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (lane == 0) li = atomicAdd(&s_next2, 1u);
                 li = __shfl(li, 0);
                 if (li >= nlist) break;
-                const NbrRec r = list[li];
+                const NbrRec r = rec(li);
                 const int T = r.type;
                 if (T == 2 && r.e1 - r.e0 <= 32) continue;
                 if (r.e1 <= r.e0) continue;
@@ -642,6 +698,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             }
         }
 
+        ph_add(timing, 1);
         // Phase 3: beta singles of the identity and alpha-single source rows
         // (the alpha-beta doubles), one list row per work unit; then the
         // identity row's beta-beta doubles, bb_chunk entries per unit, so
@@ -649,30 +706,41 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         const u32 idb = s_idb, ide = s_ide;
         const unsigned n_b1 = (!GRAD && ide > idb) ? (ide - idb + b1_chunk - 1) / b1_chunk : 0u;
         const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + bb_chunk - 1) / bb_chunk : 0u;
-        const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : nlist + n_b1 + n_bb;
+        const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : n1 + n_b1 + n_bb;
         const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
         const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
+        int ph_bin = 6;
         for (;;) {
             unsigned li = 0;
             if (lane == 0) li = atomicAdd(&s_next, 1u);
             li = __shfl(li, 0);
+            ph_add(timing, ph_bin);
             if (li >= n_units) break;
-            if (!GRAD && li >= nlist + n_b1) {
+            if (timing) ph_bin = (li >= n1 + n_b1) ? 4 : (li >= n1) ? 3 : 2;
+            if (!GRAD && li >= n1 + n_b1) {
                 // beta-beta doubles of identity-row entries [k0, k1)
-                const u32 k0 = idb + (li - nlist - n_b1) * bb_chunk;
+                const u32 k0 = idb + (li - n1 - n_b1) * bb_chunk;
                 const u32 k1 = min(ide, k0 + bb_chunk);
                 const auto K4g = gl(p.K4);
                 const int np2 = n * (n - 1) / 2;
                 if (p.T2r) {
-                    // tabulated target rank and signed element per double;
-                    // RT_UNROLL groups of 64 doubles have their loads in flight
+                    // tabulated target rank and signed element per double, the
+                    // entry's doubles that land in this tile only; RT_UNROLL
+                    // groups of 64 doubles have their loads in flight
                     const auto T2rg = gl(p.T2r);
                     const auto T2eg = gl(p.T2e);
                     const u32 tot = (u32)(PB * QB);
                     for (u32 k = k0; k < k1; ++k) {
-                        const u64 base = (u64)p.v_rb[k] * tot;
+                        const u64 rbk = (u64)p.v_rb[k];
+                        const u64 base = rbk * tot;
                         const double c = p.v_amp[k];
-                        for (u32 t0 = 0; t0 < tot; t0 += 64 * RT_UNROLL) {
+                        u32 x0 = 0, x1 = tot;
+                        if (!whole_rows) {
+                            const uint16_t* to2 = p.toff2 + rbk * (u64)(p.ntiles + 1) + tile;
+                            x0 = to2[0];
+                            x1 = to2[1];
+                        }
+                        for (u32 t0 = x0; t0 < x1; t0 += 64 * RT_UNROLL) {
                             u32 rt[RT_UNROLL];
                             double e[RT_UNROLL];
 #pragma unroll
@@ -680,15 +748,16 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 const u32 t = t0 + (u32)u * 64 + lane;
                                 rt[u] = 0xFFFFFFFFu;
                                 e[u] = 0.0;
-                                if (t < tot) {
+                                if (t < x1) {
                                     rt[u] = T2rg[base + t];
                                     e[u] = T2eg[base + t];
                                 }
                             }
 #pragma unroll
                             for (int u = 0; u < RT_UNROLL; ++u) {
-                                if (rt[u] >= tlo && rt[u] < thi && e[u] != 0.0) {
-                                    atomicAdd(&acc[rt[u] - tlo], e[u] * c);
+                                const double t = e[u] * c;
+                                if (rt[u] >= tlo && rt[u] < thi && e[u] != 0.0 && !xscreened(t, p.eps_x)) {
+                                    atomicAdd(&acc[rt[u] - tlo], t);
                                     ++my_terms;
                                 }
                             }
@@ -724,8 +793,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                     // (i2 a2|j2 b2) - (i2 b2|j2 a2), tabulated by orbital pairs
                                     double e = K4g[(u32)(j2 * (j2 - 1) / 2 + i2) * (u32)np2 + (u32)(b2 * (b2 - 1) / 2 + a2)];
                                     if (par) e = -e;
-                                    if (e != 0.0) {
-                                        atomicAdd(&acc[rt - tlo], e * c);
+                                    const double t = e * c;
+                                    if (e != 0.0 && !xscreened(t, p.eps_x)) {
+                                        atomicAdd(&acc[rt - tlo], t);
                                         ++my_terms;
                                     }
                                 }
@@ -739,9 +809,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 continue;
             }
             NbrRec r;
-            if (!GRAD && li >= nlist) {
+            if (!GRAD && li >= n1) {
                 // beta singles of identity-row entries, b1_chunk per unit
-                const u32 k0 = idb + (li - nlist) * b1_chunk;
+                const u32 k0 = idb + (li - n1) * b1_chunk;
                 r.As = At;
                 r.rAs = (u32)rAt;
                 r.rowb = k0;
@@ -760,14 +830,88 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             double* slab = wslab;  // gradient: this row's (j, b) weights; sigma: the (ia|..) slab
             const bool gs = !GRAD && T == 1 && slab_n2 != 0;
             if (gs) {
-                // stage (ia|jb) for all j, b of this source row's alpha single
+                // stage this source row's alpha single's (ia|jb) as slab[j n + b]
+                // (the index a table entry carries), with the alpha single's
+                // phase folded in
                 const u32 n2 = (u32)n * n;
                 const double* Gia = p.I.g + ((u32)I_ * n + A_) * n2;
+                const u64 sgn = r.par ? 0x8000000000000000ull : 0ull;
                 wave_sync();
-                for (u32 t = lane; t < n2; t += 64) slab[t] = Gia[t];
+                for (u32 t = lane; t < n2; t += 64)
+                    slab[t] = __longlong_as_double((long long)((u64)__double_as_longlong(Gia[t]) ^ sgn));
                 wave_sync();
             }
-            if (whole_rows && T == 1) {
+            if (!GRAD && whole_rows && T == 1 && gs) {
+                // Alpha-beta doubles, the bulk of the work.  Lanes over the
+                // single-excitation index; 64 entries at a time are loaded one
+                // per lane and taken in turn: an entry's table row and
+                // amplitude are wavefront-uniform (readlane), so a term costs
+                // one table load at a fixed per-lane offset, one slab read, a
+                // multiply, a sign flip and one LDS add.  Terms are counted per
+                // wavefront (ballot).
+                auto run = [&](auto SCR) {
+                    constexpr bool kScr = decltype(SCR)::value;
+                    const auto rbg = gl(p.v_rb);
+                    const auto ampg = gl(p.v_amp);
+                    const double eps_x = p.eps_x;
+                    for (int s0 = 0; s0 < sBn; s0 += 64) {
+                        const int sidx = s0 + lane;
+                        const bool act = sidx < sBn;
+                        const u32 sl = act ? (u32)sidx : 0u;
+                        for (u32 kb = r.rowb; kb < r.rowe; kb += 64) {
+                            const u32 kk = kb + lane;
+                            u32 rk = 0;
+                            double ck = 0.0;
+                            if (kk < r.rowe) {
+                                rk = rbg[kk];
+                                ck = ampg[kk];
+                            }
+                            const int cnt = (int)min(64u, r.rowe - kb);
+                            auto trow = [&](int q) { return gl(p.T1 + (u64)rl32(rk, q) * (u32)sBn); };
+                            int q = 0;
+                            u32 te_next[RT_UNROLL];
+                            if (RT_UNROLL <= cnt) {
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) te_next[u] = trow(u)[sl];
+                            }
+                            for (; q + RT_UNROLL <= cnt; q += RT_UNROLL) {
+                                u32 te[RT_UNROLL];
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) te[u] = te_next[u];
+                                if (q + 2 * RT_UNROLL <= cnt) {
+#pragma unroll
+                                    for (int u = 0; u < RT_UNROLL; ++u) te_next[u] = trow(q + RT_UNROLL + u)[sl];
+                                }
+                                double x[RT_UNROLL];
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) x[u] = slab[t1_jb(te[u])];
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u) {
+                                    const double c = rlf64(ck, q + u);
+                                    const double pr = x[u] * c;
+                                    const double t = __hiloint2double(__double2hiint(pr) ^ (int)(te[u] & 0x80000000u),
+                                                                      __double2loint(pr));
+                                    const bool keep = act && (!kScr || !xscreened(t, eps_x));
+                                    if (keep) atomicAdd(&acc[te[u] & 0x1FFFFFu], t);
+                                    wterms += (u32)__popcll(__ballot(keep && x[u] != 0.0));
+                                }
+                            }
+                            for (; q < cnt; ++q) {
+                                const u32 te = trow(q)[sl];
+                                const double x = slab[t1_jb(te)];
+                                const double pr = x * rlf64(ck, q);
+                                const double t = __hiloint2double(__double2hiint(pr) ^ (int)(te & 0x80000000u),
+                                                                  __double2loint(pr));
+                                const bool keep = act && (!kScr || !xscreened(t, eps_x));
+                                if (keep) atomicAdd(&acc[te & 0x1FFFFFu], t);
+                                wterms += (u32)__popcll(__ballot(keep && x != 0.0));
+                            }
+                        }
+                    }
+                };
+                if (p.eps_x > 0.0) run(std::true_type{});
+                else run(std::false_type{});
+            } else if (whole_rows && T == 1) {
                 // Alpha-beta doubles, the bulk of the work.  Lanes over the
                 // single-excitation index; 64 entries at a time are loaded one
                 // per lane and taken in turn (readlane), RT_UNROLL table reads
@@ -793,7 +937,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         auto sweep = [&](auto GS) {
                             constexpr bool kGS = decltype(GS)::value;
                             auto element = [&](u32 te) -> double {
-                                return kGS ? slab[t1_j(te) * n + t1_b(te)] : p.I.G(I_, A_, t1_j(te), t1_b(te));
+                                return kGS ? slab[t1_jb(te)] : p.I.g[((u32)I_ * n + A_) * (u32)(n * n) + t1_jb(te)];
                             };
                             // sign of both phases applied to x by flipping its sign bit
                             auto signed_ = [&](double x, u32 te) {
@@ -825,7 +969,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
 #pragma unroll
                                     for (int u = 0; u < RT_UNROLL; ++u) {
                                         const double c = rlf64(ck, q + u);
-                                        if (sb[u] != 0.0) atomicAdd(&slab[t1_j(te[u]) * n + t1_b(te[u])], signed_(sb[u] * c, te[u]));
+                                        if (sb[u] != 0.0) atomicAdd(&slab[t1_jb(te[u])], signed_(sb[u] * c, te[u]));
                                     }
                                 } else {
                                     // all element reads first, then the accumulations (adding an exact
@@ -836,8 +980,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
 #pragma unroll
                                     for (int u = 0; u < RT_UNROLL; ++u) {
                                         const double c = rlf64(ck, q + u);
-                                        atomicAdd(&acc[t1_rank(te[u]) - tlo], signed_(x[u], te[u]) * c);
-                                        my_terms += (x[u] != 0.0) ? 1u : 0u;
+                                        const double t = signed_(x[u], te[u]) * c;
+                                        if (!xscreened(t, p.eps_x)) {
+                                            atomicAdd(&acc[t1_rank(te[u]) - tlo], t);
+                                            my_terms += (x[u] != 0.0) ? 1u : 0u;
+                                        }
                                     }
                                 }
                             }
@@ -847,11 +994,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 const double c = rlf64(ck, q);
                                 if (GRAD) {
                                     const double sb = acc[t1_rank(te) - tlo];
-                                    if (sb != 0.0) atomicAdd(&slab[t1_j(te) * n + t1_b(te)], signed_(sb * c, te));
+                                    if (sb != 0.0) atomicAdd(&slab[t1_jb(te)], signed_(sb * c, te));
                                 } else {
                                     const double x = element(te);
-                                    atomicAdd(&acc[t1_rank(te) - tlo], signed_(x, te) * c);
-                                    my_terms += (x != 0.0) ? 1u : 0u;
+                                    const double t = signed_(x, te) * c;
+                                    if (!xscreened(t, p.eps_x)) {
+                                        atomicAdd(&acc[t1_rank(te) - tlo], t);
+                                        my_terms += (x != 0.0) ? 1u : 0u;
+                                    }
                                 }
                             }
                         };
@@ -888,7 +1038,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         for (u32 m = At; m; m &= m - 1u) {
                             const int kq = __builtin_ctz(m);
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) x[u] += p.I.G(t1_j(te[u]), t1_b(te[u]), kq, kq);
+                            for (int u = 0; u < RT_UNROLL; ++u)
+                                x[u] += p.I.g[(t1_jb(te[u]) * (u32)n + kq) * (u32)n + kq];
                         }
 #pragma unroll
                         for (int u = 0; u < RT_UNROLL; ++u) {
@@ -898,6 +1049,50 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 atomicAdd(&acc[t1_rank(te[u]) - tlo], x[u] * c[u]);
                                 ++my_terms;
                             }
+                        }
+                    }
+                }
+            } else if (!GRAD && T == 1 && p.ab_it) {
+                // Alpha-beta doubles of a row of several tiles: the source
+                // row's items that land in this tile, listed per input chunk;
+                // lanes over the items, RT_UNROLL groups of 64 loads in flight.
+                // The element is the staged slab's (alpha phase folded in) or
+                // (ia|jb) from global memory with the alpha phase; the beta
+                // phase flips the product's sign bit.
+                const auto itg = gl(p.ab_it);
+                const auto ampg = gl(p.v_amp);
+                const auto grow = gl(p.I.g + ((u32)I_ * n + A_) * (u32)(n * n));
+                const u64 nt = (u64)p.ntiles;
+                const u64 c0 = p.ab_rowchunk[r.rAs];
+                const u64 c1 = c0 + (r.rowe - r.rowb + AB_CHUNK - 1) / AB_CHUNK;
+                const u32 pa_bit = (gs ? 0u : (u32)r.par) << 31;
+                const double eps_x = p.eps_x;
+                for (u64 c = c0; c < c1; ++c) {
+                    const u64 x0 = p.ab_off[c * nt + (u64)tile], x1 = p.ab_off[c * nt + (u64)tile + 1];
+                    const u64 kc = (u64)r.rowb + (c - c0) * AB_CHUNK;  // the chunk's first entry
+                    for (u64 xb = x0; xb < x1; xb += 64 * RT_UNROLL) {
+                        u32 it[RT_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            const u64 x = xb + (u64)u * 64 + lane;
+                            it[u] = (x < x1) ? itg[x] : 0u;
+                        }
+                        double e[RT_UNROLL], cc[RT_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            const u32 jb = (it[u] >> 14) & 1023u;
+                            e[u] = gs ? slab[jb] : grow[jb];
+                            cc[u] = ampg[kc + ((it[u] >> 24) & 63u)];
+                        }
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            const bool act = xb + (u64)u * 64 + lane < x1;
+                            const double pr = e[u] * cc[u];
+                            const double t = __hiloint2double(
+                                __double2hiint(pr) ^ (int)((it[u] ^ pa_bit) & 0x80000000u), __double2loint(pr));
+                            const bool keep = act && !xscreened(t, eps_x);
+                            if (keep) atomicAdd(&acc[it[u] & 0x3FFFu], t);
+                            wterms += (u32)__popcll(__ballot(keep && e[u] != 0.0));
                         }
                     }
                 }
@@ -954,31 +1149,33 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         if (q < total) {
                             const u32 te = tg[u];
                             const u32 rt = t1_rank(te);
-                            const int jj = t1_j(te), bb = t1_b(te);
+                            const u32 jb = t1_jb(te);
                             const int par_b = t1_par(te);
                             if (GRAD) {
                                 const double sb = acc[rt - tlo];
                                 if (sb != 0.0) {
                                     double w = sb * cx;
                                     if (r.par ^ par_b) w = -w;
-                                    atomicAdd(&slab[jj * n + bb], w);
+                                    atomicAdd(&slab[jb], w);
                                 }
                                 continue;
                             }
                             double e;
                             if (T == 1) {
-                                e = gs ? slab[jj * n + bb] : p.I.G(I_, A_, jj, bb);
-                                if (r.par ^ par_b) e = -e;
+                                // the staged slab carries the alpha single's phase
+                                e = gs ? slab[jb] : p.I.g[((u32)I_ * n + A_) * (u32)(n * n) + jb];
+                                if ((gs ? 0 : r.par) ^ par_b) e = -e;
                             } else {
                                 e = p.TS[ig[u]];
                                 for (u32 m = At; m; m &= m - 1u) {
                                     const int kq = __builtin_ctz(m);
-                                    e += p.I.G(jj, bb, kq, kq);
+                                    e += p.I.g[(jb * (u32)n + kq) * (u32)n + kq];
                                 }
                                 if (par_b) e = -e;
                             }
-                            if (e != 0.0) {
-                                atomicAdd(&acc[rt - tlo], e * cx);
+                            const double t = e * cx;
+                            if (e != 0.0 && !(T == 1 && xscreened(t, p.eps_x))) {
+                                atomicAdd(&acc[rt - tlo], t);
                                 ++my_terms;
                             }
                         }
@@ -1001,6 +1198,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 wave_sync();
             }
         }
+        if (lane == 0) my_terms += wterms;  // the per-wavefront count, folded once per item
+        wterms = 0;
         __syncthreads();
         if (!GRAD && s_touched) {
             double* dst = p.D + (rAt - p.row_base) * Nb + tlo;
@@ -1010,7 +1209,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             else
                 for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = acc[x];
         }
+        ph_add(timing, 5);
     }
+    if (TIMED && !GRAD && s_cur >= 0 && p.phase_ns) {
+        __syncthreads();
+        if (threadIdx.x < RT_WAVES * 8 && s_ph[threadIdx.x >> 3][threadIdx.x & 7])
+            atomicAdd(p.phase_ns + (threadIdx.x & 7), s_ph[threadIdx.x >> 3][threadIdx.x & 7]);
+    }
+    if (lane == 0) my_terms += wterms;
     for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
     if (lane == 0 && s_cur >= 0 && p.emitted && my_terms) atomicAdd(p.emitted, (unsigned long long)my_terms);
 }
@@ -1024,6 +1230,18 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                                                             unsigned itab_off, unsigned b1_chunk, unsigned bb_chunk) {
     rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, itab_off,
                            b1_chunk, bb_chunk);
+}
+
+// The same with per-phase timing (a diagnostic build of the kernel, launched
+// only when the description asks for it).
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile_timed(const RTParams* __restrict__ descs,
+                                                                  const u64* __restrict__ item_prefix, int n_inst,
+                                                                  unsigned* __restrict__ counter, void* nbr_scratch,
+                                                                  u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
+                                                                  unsigned itab_off, unsigned b1_chunk,
+                                                                  unsigned bb_chunk) {
+    rowtile_body<RT_SIGMA, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2,
+                                 itab_off, b1_chunk, bb_chunk);
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
@@ -1080,7 +1298,7 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
             for (int u = 0; u < sBn; ++u) pos += ((key[u] & 0xFFFFFFFFull) < me) ? 1 : 0;
             const u64 kt = key[t];
             const int jj = (int)((kt >> 32) & 31), bb = (int)((kt >> 40) & 31);
-            T1[rb * (u64)sBn + pos] = (u32)(kt & 0xFFFFFFFFull) | ((u32)jj << 21) | ((u32)bb << 26) |
+            T1[rb * (u64)sBn + pos] = (u32)(kt & 0xFFFFFFFFull) | ((u32)(jj * sp.n + bb) << 21) |
                                       ((u32)((kt >> 48) & 1) << 31);
             // h_jb + sum_{k in beta, k != j} [(jb|kk) - (jk|kb)]: the leading part of the
             // single-excitation element, in the reference's order (the alpha part follows)
@@ -1102,13 +1320,33 @@ __global__ __launch_bounds__(64) void k_build_T1(SpaceDev sp, const u64* __restr
 
 // T2: for every beta string, its beta-beta doubles (i < j occupied -> a < b
 // virtual, pairs in lexicographic order): the target rank, and the element
-// (ia|jb) - (ib|ja) from the pair-indexed table with both phases applied.
-// One wavefront per beta string.
+// (ia|jb) - (ib|ja) from the pair-indexed table with both phases applied,
+// grouped by the target's tile (a stable grouping: pair order within a
+// tile; with one tile per row, pair order) with per-tile offsets toff2.
+// One wavefront per beta string; the doubles are generated twice, once to
+// count per tile and once to place.
+__device__ __forceinline__ void t2_double(int t, int QB, int nb, int nvb, u32 beta, const uint8_t* occ,
+                                          const uint8_t* vir, u32 np2, const BinomLds& sB,
+                                          const double* __restrict__ K4, u32& rt, double& e) {
+    const uint16_t pa = decode_pair(t / QB, nb), pv = decode_pair(t % QB, nvb);
+    const int i2 = occ[pa & 255], j2 = occ[pa >> 8];
+    const int a2 = vir[pv & 255], b2 = vir[pv >> 8];
+    const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
+    const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
+    rt = (u32)str_rank(B2, sB);
+    const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
+    const u32 k4 = (u32)(j2 * (j2 - 1) / 2 + i2) * np2 + (u32)(b2 * (b2 - 1) / 2 + a2);
+    e = K4[k4];
+    if (par) e = -e;
+}
+
 __global__ __launch_bounds__(64) void k_build_T2(SpaceDev sp, const u64* __restrict__ binom,
-                                                 const double* __restrict__ K4, u32* __restrict__ T2r,
-                                                 double* __restrict__ T2e) {
+                                                 const double* __restrict__ K4, int nt, u32 step,
+                                                 u32* __restrict__ T2r, double* __restrict__ T2e,
+                                                 uint16_t* __restrict__ toff2) {
     __shared__ BinomLds sB;
     __shared__ uint8_t occ[32], vir[32];
+    __shared__ u32 cnt[64];
     load_binom(sB, binom);
     __syncthreads();
     const int n = sp.n, nb = sp.nb, nvb = n - nb;
@@ -1123,20 +1361,54 @@ __global__ __launch_bounds__(64) void k_build_T2(SpaceDev sp, const u64* __restr
             if ((beta >> lane) & 1u) occ[__popc(beta & below)] = (uint8_t)lane;
             else vir[lane - __popc(beta & below)] = (uint8_t)lane;
         }
+        cnt[lane] = 0;
         __syncthreads();
         for (int t = lane; t < tot; t += 64) {
-            const uint16_t pa = decode_pair(t / QB, nb), pv = decode_pair(t % QB, nvb);
-            const int i2 = occ[pa & 255], j2 = occ[pa >> 8];
-            const int a2 = vir[pv & 255], b2 = vir[pv >> 8];
-            const u32 midb = beta ^ (1u << i2) ^ (1u << a2);
-            const u32 B2 = midb ^ (1u << j2) ^ (1u << b2);
-            const u64 rt = str_rank(B2, sB);
-            const int par = between_parity(beta, i2, a2) ^ between_parity(midb, j2, b2);
-            const u32 k4 = (u32)(j2 * (j2 - 1) / 2 + i2) * np2 + (u32)(b2 * (b2 - 1) / 2 + a2);
-            double e = K4[k4];
-            if (par) e = -e;
-            T2r[rb * (u64)tot + t] = (u32)rt;
-            T2e[rb * (u64)tot + t] = e;
+            u32 rt;
+            double e;
+            t2_double(t, QB, nb, nvb, beta, occ, vir, np2, sB, K4, rt, e);
+            atomicAdd(&cnt[min(rt / step, (u32)(nt - 1))], 1u);
+        }
+        __syncthreads();
+        // exclusive scan of the tile counts (lane = tile), offsets to toff2, cursors to cnt
+        const u32 mine = (lane < nt) ? cnt[lane] : 0u;
+        u32 incl = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 y = (u32)__shfl_up((int)incl, off);
+            if (lane >= off) incl += y;
+        }
+        const u32 excl = incl - mine;
+        __syncthreads();
+        if (lane <= nt) toff2[rb * (u64)(nt + 1) + lane] = (uint16_t)(lane < nt ? excl : (u32)tot);
+        cnt[lane] = excl;
+        __syncthreads();
+        for (int t0 = 0; t0 < tot; t0 += 64) {
+            const int t = t0 + lane;
+            const bool act = t < tot;
+            u32 rt = 0;
+            double e = 0.0;
+            u32 tl = 0;
+            if (act) {
+                t2_double(t, QB, nb, nvb, beta, occ, vir, np2, sB, K4, rt, e);
+                tl = min(rt / step, (u32)(nt - 1));
+            }
+            // place the chunk tile by tile, lanes in order within a tile
+            u64 left = __ballot(act);
+            while (left) {
+                const int first = __ffsll((long long)left) - 1;
+                const u32 tf = (u32)__shfl((int)tl, first);
+                const u64 m = __ballot(act && tl == tf);
+                const u32 base = cnt[tf];
+                if (act && tl == tf) {
+                    const u64 at = rb * (u64)tot + base + (u32)__popcll(m & ((1ull << lane) - 1ull));
+                    T2r[at] = rt;
+                    T2e[at] = e;
+                }
+                wave_sync();
+                if (lane == first) cnt[tf] = base + (u32)__popcll(m);
+                wave_sync();
+                left &= ~m;
+            }
         }
     }
 }
@@ -1202,6 +1474,89 @@ __global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __
     }
 }
 
+// ---- alpha-beta item lists of rows of several tiles (per sigma) ----
+// An alpha-single source row feeds a target tile only through the beta
+// singles of its entries that land in that tile.  Listing those items per
+// (input chunk, tile) once per sigma lets every target tile stream exactly its
+// items instead of revisiting each source entry once per tile of the row.
+
+// Chunks of AB_CHUNK entries per alpha row.
+__global__ void k_ab_nchunks(const u64* __restrict__ rowbeg, const u64* __restrict__ rowend, u64 Na,
+                             u64* __restrict__ nch) {
+    for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < Na; r += (u64)gridDim.x * blockDim.x)
+        nch[r] = (rowend[r] - rowbeg[r] + AB_CHUNK - 1) / AB_CHUNK;
+}
+
+// chunkrow[c] = the alpha row of chunk c (rowchunk: Na + 1 exclusive offsets).
+__global__ void k_ab_chunkmap(const u64* __restrict__ rowchunk, u64 Na, u32* __restrict__ chunkrow) {
+    for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < Na; r += (u64)gridDim.x * blockDim.x)
+        for (u64 c = rowchunk[r]; c < rowchunk[r + 1]; ++c) chunkrow[c] = (u32)r;
+}
+
+// cnt[c * nt + t]: items of chunk c landing in tile t.  One wavefront per
+// chunk, lanes over its entries.
+__global__ __launch_bounds__(256) void k_ab_count(const u64* __restrict__ rowbeg, const u64* __restrict__ rowend,
+                                                  const u64* __restrict__ rowchunk, const u32* __restrict__ chunkrow,
+                                                  u64 Na, const u32* __restrict__ vrb,
+                                                  const uint16_t* __restrict__ toff, int nt, u64* __restrict__ cnt) {
+    const u64 nch = rowchunk[Na];
+    const int lane = threadIdx.x & 63;
+    for (u64 c = ((u64)blockIdx.x * 256 + threadIdx.x) >> 6; c < nch; c += (u64)gridDim.x * 4) {
+        const u32 r = chunkrow[c];
+        const u64 k = rowbeg[r] + (c - rowchunk[r]) * AB_CHUNK + lane;
+        const bool on = k < rowend[r];
+        const uint16_t* to = toff + (on ? (u64)vrb[k] * (u64)(nt + 1) : 0);
+        u32 prev = on ? to[0] : 0u;
+        for (int t = 0; t < nt; ++t) {
+            const u32 nx = on ? (u32)to[t + 1] : 0u;
+            u32 len = nx - prev;
+            prev = nx;
+            for (int off = 32; off >= 1; off >>= 1) len += (u32)__shfl_xor((int)len, off);
+            if (lane == 0) cnt[c * (u64)nt + t] = len;
+        }
+    }
+}
+
+// Fill the lists: one wavefront per chunk, its entries in order, lanes over
+// each entry's beta singles (already sorted by target rank, so a tile's items
+// of one entry are consecutive).  Within (chunk, tile) the items keep entry
+// order, then the table's order.
+__global__ __launch_bounds__(256) void k_ab_fill(const u64* __restrict__ rowbeg, const u64* __restrict__ rowend,
+                                                 const u64* __restrict__ rowchunk, const u32* __restrict__ chunkrow,
+                                                 u64 Na, const u32* __restrict__ vrb,
+                                                 const uint16_t* __restrict__ toff, int nt, const u64* __restrict__ off,
+                                                 const u32* __restrict__ T1, int sBn, u32 step, u64 items_cap,
+                                                 u32* __restrict__ it_out) {
+    __shared__ u64 s_cur[4][64];
+    __shared__ u32 s_o[4][64];
+    const u64 nch = rowchunk[Na];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (u64 c = ((u64)blockIdx.x * 256 + threadIdx.x) >> 6; c < nch; c += (u64)gridDim.x * 4) {
+        const u32 r = chunkrow[c];
+        const u64 k0 = rowbeg[r] + (c - rowchunk[r]) * AB_CHUNK;
+        const u64 k1 = min(rowend[r], k0 + AB_CHUNK);
+        wave_sync();
+        if (lane < nt) s_cur[w][lane] = off[c * (u64)nt + lane];
+        for (u64 k = k0; k < k1; ++k) {
+            const u64 rb = vrb[k];
+            wave_sync();
+            if (lane <= nt) s_o[w][lane] = toff[rb * (u64)(nt + 1) + lane];
+            wave_sync();
+            for (int s0 = 0; s0 < sBn; s0 += 64) {
+                const int sidx = s0 + lane;
+                if (sidx < sBn) {
+                    const u32 te = T1[rb * (u64)sBn + sidx];
+                    const u32 t = min((te & 0x1FFFFFu) / step, (u32)(nt - 1));
+                    const u64 dst = s_cur[w][t] + (u64)((u32)sidx - s_o[w][t]);
+                    if (dst < items_cap) it_out[dst] = ab_item((te & 0x1FFFFFu) - t * step, te, (u32)(k - k0));
+                }
+            }
+            wave_sync();
+            if (lane < nt) s_cur[w][lane] += (u64)(s_o[w][lane + 1] - s_o[w][lane]);
+        }
+    }
+}
+
 u64 binom_u64(int a, int b) {
     if (b < 0 || a < b) return 0;
     u64 r = 1;
@@ -1219,7 +1574,8 @@ static size_t rt_static_lds() {
     static size_t cached = 0;
     if (cached == 0) {
         size_t mx = 0;
-        for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b}) {
+        for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_sigma_rowtile_timed,
+                              (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b}) {
             hipFuncAttributes attr{};
             SFCI_CHECK_HIP(hipFuncGetAttributes(&attr, f));
             mx = std::max(mx, (size_t)attr.sharedSizeBytes);
@@ -1240,8 +1596,9 @@ struct RowTileState {
     u32* d_T1 = nullptr;
     double* d_TS = nullptr;
     double* d_K4 = nullptr;
-    u32* d_T2r = nullptr;  // beta-beta doubles per beta string (rows of one tile only):
+    u32* d_T2r = nullptr;  // beta-beta doubles per beta string, grouped by target tile:
     double* d_T2e = nullptr;  // target rank, signed element
+    uint16_t* d_toff2 = nullptr;  // per beta string, ntiles + 1 group offsets
     double* d_K = nullptr;  // (pp|qq) - (pq|qp), n^2
     uint16_t* d_toff = nullptr;
 };
@@ -1323,11 +1680,21 @@ bool rowtile_available(sfci_problem* P) {
         const u64 tot = (u64)(P->nb * (P->nb - 1) / 2) * (u64)((P->n - P->nb) * (P->n - P->nb - 1) / 2);
         const u64 bytes = P->Nb * tot * (sizeof(u32) + sizeof(double));
         const char* env = getenv("SFCI_NO_T2");
-        if (S->ntiles == 1 && tot > 0 && bytes <= (1ull << 30) && !(env && env[0] == '1')) {
+        // rows of one tile: up to 1 GiB (measured a win at 20 orbitals, 42 MB
+        // per instance); rows of several tiles, where the on-the-fly walk
+        // enumerates every double of an entry once per tile: up to a quarter
+        // of the free memory
+        size_t freeb = 0, totb = 0;
+        SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+        const bool fits = (S->ntiles == 1) ? bytes <= (1ull << 30) : (bytes <= freeb / 4 && S->ntiles < 64);
+        if (tot > 0 && tot < 65536 && fits && !(env && env[0] == '1')) {
             SFCI_CHECK_HIP(hipMalloc(&S->d_T2r, P->Nb * tot * sizeof(u32)));
             SFCI_CHECK_HIP(hipMalloc(&S->d_T2e, P->Nb * tot * sizeof(double)));
+            SFCI_CHECK_HIP(hipMalloc(&S->d_toff2, P->Nb * (u64)(S->ntiles + 1) * sizeof(uint16_t)));
+            const u32 step = (u32)(S->tile_lo.size() > 1 ? S->tile_lo[1] - S->tile_lo[0] : P->Nb);
             hipLaunchKernelGGL(k_build_T2, dim3(g), dim3(64), 0, P->stream, SpaceDev{P->n, P->na, P->nb, P->Na, P->Nb},
-                               P->d_binom, (const double*)S->d_K4, S->d_T2r, S->d_T2e);
+                               P->d_binom, (const double*)S->d_K4, S->ntiles, std::max<u32>(1, step), S->d_T2r,
+                               S->d_T2e, S->d_toff2);
             SFCI_CHECK_HIP(hipGetLastError());
         }
     }
@@ -1337,7 +1704,8 @@ bool rowtile_available(sfci_problem* P) {
     SFCI_CHECK_HIP(hipGetLastError());
     S->maxlds = maxlds;
     const int dyn_max = maxlds - (int)rt_static_lds();
-    for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b})
+    for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_sigma_rowtile_timed,
+                          (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b})
         SFCI_CHECK_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_max));
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
     S->ready = true;
@@ -1353,16 +1721,64 @@ void rowtile_release(sfci_problem* P) {
     if (S->d_K4) (void)hipFree(S->d_K4);
     if (S->d_T2r) (void)hipFree(S->d_T2r);
     if (S->d_T2e) (void)hipFree(S->d_T2e);
+    if (S->d_toff2) (void)hipFree(S->d_toff2);
     if (S->d_K) (void)hipFree(S->d_K);
     if (S->d_toff) (void)hipFree(S->d_toff);
     delete S;
     P->rowtile = nullptr;
 }
 
+// The alpha-beta item lists of a sigma over rows of several tiles (see
+// k_ab_fill), when the tiles are fewer than 64 and the lists take at most a
+// third of the free device memory; otherwise the kernel walks each source
+// entry's table slice per tile.  SFCI_AB_LISTS=0 switches them off.
+static void build_ab_lists(sfci_problem* P, RowTileState* S, const SigmaLaunch& v, const u64* rowbeg,
+                           const u64* rowend, const u32* vrb, RTParams& rp) {
+    const u64 nt = (u64)S->ntiles;
+    if (nt < 2 || nt >= 64) return;
+    if (const char* env = getenv("SFCI_AB_LISTS"))
+        if (env[0] == '0') return;
+    const u64 cap = std::max<u64>(1, v.cap);
+    const u64 sBn = (u64)rp.sB;
+    const u64 chunks_max = cap / AB_CHUNK + std::min<u64>(P->Na, cap) + 1;
+    const u64 items = cap * sBn;
+    const u64 n_off = chunks_max * nt + 1;
+    const size_t need = items * sizeof(u32) + n_off * sizeof(u64) + (P->Na + 1) * sizeof(u64) +
+                        chunks_max * sizeof(u32);
+    size_t freeb = 0, totb = 0;
+    SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+    const size_t held = P->ws_ab_rc.bytes + P->ws_ab_cr.bytes + P->ws_ab_off.bytes + P->ws_ab_it.bytes;
+    if (need > (freeb + held) / 3 || S->tile_max > 16384) return;
+    u64* rowchunk = (u64*)P->ws_ab_rc.get((P->Na + 1) * sizeof(u64));
+    u32* chunkrow = (u32*)P->ws_ab_cr.get(chunks_max * sizeof(u32));
+    u64* off = (u64*)P->ws_ab_off.get(n_off * sizeof(u64));
+    u32* it = (u32*)P->ws_ab_it.get(items * sizeof(u32));
+    hipStream_t st = P->stream;
+    const unsigned gr = (unsigned)std::min<u64>((P->Na + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_ab_nchunks, dim3(gr), dim3(256), 0, st, rowbeg, rowend, P->Na, rowchunk);
+    exclusive_scan_u64(P, rowchunk, rowchunk, P->Na, rowchunk + P->Na);
+    hipLaunchKernelGGL(k_ab_chunkmap, dim3(gr), dim3(256), 0, st, (const u64*)rowchunk, P->Na, chunkrow);
+    launch_fill_u64(off, n_off, 0, st);
+    // four wavefronts per block, one chunk each at a time
+    const unsigned gc = (unsigned)std::min<u64>((chunks_max + 3) / 4, (u64)P->num_cu * 32);
+    hipLaunchKernelGGL(k_ab_count, dim3(gc), dim3(256), 0, st, rowbeg, rowend, (const u64*)rowchunk,
+                       (const u32*)chunkrow, P->Na, vrb, (const uint16_t*)S->d_toff, (int)nt, off);
+    exclusive_scan_u64(P, off, off, n_off, nullptr);
+    const u32 step = (u32)(S->tile_lo.size() > 1 ? S->tile_lo[1] - S->tile_lo[0] : P->Nb);
+    hipLaunchKernelGGL(k_ab_fill, dim3(gc), dim3(256), 0, st, rowbeg, rowend, (const u64*)rowchunk,
+                       (const u32*)chunkrow, P->Na, vrb, (const uint16_t*)S->d_toff, (int)nt, (const u64*)off,
+                       (const u32*)S->d_T1, (int)sBn, step, items, it);
+    SFCI_CHECK_HIP(hipGetLastError());
+    rp.ab_it = it;
+    rp.ab_off = off;
+    rp.ab_rowchunk = rowchunk;
+}
+
 // Per-instance preparation on the instance's stream: row pointers, per-tile
 // entry offsets and beta strings of the input vector; returns the kernel's
 // description of this instance.  rowtile_available(P) must hold.
-RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps) {
+RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps,
+                            bool ab_lists) {
     RowTileState* S = rt_state(P);
     const u64 cap = std::max<u64>(1, v.cap);
     const u64 nt1 = (u64)S->ntiles + 1;
@@ -1405,9 +1821,23 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.K4 = S->d_K4;
     rp.T2r = S->d_T2r;
     rp.T2e = S->d_T2e;
+    rp.toff2 = S->d_toff2;
     rp.eps = eps;
+    rp.eps_x = P->excite_eps;
     rp.item_base = 0;
     rp.row_base = 0;
+    rp.ab_it = nullptr;
+    rp.ab_off = nullptr;
+    rp.ab_rowchunk = nullptr;
+    if (ab_lists) build_ab_lists(P, S, v, rowbeg, rowend, vrb, rp);
+    rp.phase_ns = nullptr;
+    if (const char* env = getenv("SFCI_RT_PHASES"))
+        if (env[0] == '1') {
+            if (!P->ws_rt_phase.p) {
+                launch_fill_u64((u64*)P->ws_rt_phase.get(8 * sizeof(u64)), 8, 0, P->stream);
+            }
+            rp.phase_ns = (unsigned long long*)P->ws_rt_phase.p;
+        }
     const int na = P->na, nva = P->n - P->na;
     // work units: chunks of up to tile_chunk consecutive tiles of one target
     // row (a workgroup walks a chunk's tiles in turn, reusing the row's
@@ -1450,10 +1880,11 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
 
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
                  unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
-                 bool fill_counter, const RowTileTune& tune) {
+                 bool fill_counter, const RowTileTune& tune, bool timed) {
     if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
     const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items, tune.per_cu);
-    hipLaunchKernelGGL(k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream, (const RTParams*)d_descs,
+    hipLaunchKernelGGL(timed ? k_sigma_rowtile_timed : k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream,
+                       (const RTParams*)d_descs,
                        d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off,
                        tune.b1_chunk ? tune.b1_chunk : RT_B1_CHUNK, tune.bb_chunk ? tune.bb_chunk : RT_BB_CHUNK);
     SFCI_CHECK_HIP(hipGetLastError());
@@ -1467,8 +1898,26 @@ unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned pe
 
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid * 2 * nbr_cap * sizeof(NbrRec); }
 
+// SFCI_RT_PHASES=1: the tile kernel's wavefront time per phase since the last
+// report, printed to stderr as shares (a diagnostic; it synchronises the stream).
+static void report_phases(sfci_problem* P, const char* what) {
+    if (!P->ws_rt_phase.p) return;
+    u64 h[8] = {};
+    SFCI_CHECK_HIP(hipMemcpyAsync(h, P->ws_rt_phase.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+    SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    launch_fill_u64((u64*)P->ws_rt_phase.p, 8, 0, P->stream);
+    double tot = 0;
+    for (u64 x : h) tot += (double)x;
+    if (tot <= 0) return;
+    static const char* names[8] = {"records", "direct", "alpha-beta", "id-beta-singles", "beta-beta",
+                                   "wait+write", "other-units", "fetch"};
+    std::fprintf(stderr, "# tile kernel phases (%s, %.3g wave-ticks):", what, tot);
+    for (int k = 0; k < 8; ++k) std::fprintf(stderr, " %s %.1f%%", names[k], 100.0 * (double)h[k] / tot);
+    std::fprintf(stderr, "\n");
+}
+
 void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps) {
-    RowTileDesc d = rowtile_prepare(P, v, D, emitted, eps);
+    RowTileDesc d = rowtile_prepare(P, v, D, emitted, eps, true);
     // descriptor | prefix (2 words) | counter
     char* buf = (char*)P->ws_rt_desc.get(sizeof(RTParams) + 64);
     u64 prefix[2] = {0, d.n_items};
@@ -1477,8 +1926,11 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
     const RowTileGeom geom = rowtile_geom(&d, 1);
     const unsigned grid = rowtile_grid(P->num_cu, geom.lds, d.n_items);
     void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
+    const bool timed = ((RTParams*)d.raw)->phase_ns != nullptr;
     rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
-                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items);
+                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items, true, RowTileTune{},
+                timed);
+    if (timed) report_phases(P, "sigma");
 }
 
 void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, double* Dp) {
@@ -1496,9 +1948,11 @@ void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, 
     const unsigned grid = rowtile_grid(P->num_cu, geom.lds, d.n_items);
     void* scratch = P->ws_rt_nbr.get(rowtile_scratch_bytes(grid, d.nbr_cap));
     rowtile_run(P->stream, P->num_cu, buf, (const u64*)(buf + sizeof(RTParams)), 1,
-                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items);
+                (unsigned*)(buf + sizeof(RTParams) + 16), scratch, d.nbr_cap, geom, d.n_items, true, RowTileTune{},
+                rp.phase_ns != nullptr);
     // the host buffers above are copied before this returns
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+    if (rp.phase_ns && hi == P->Na) report_phases(P, "sigma, all row slices");
 }
 
 // ---- integral gradients through the tiles ----

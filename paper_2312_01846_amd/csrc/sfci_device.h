@@ -167,9 +167,15 @@ struct AlphaRange {
 // beta-beta double, 5 alpha-beta double), the orbitals (i->a, j->b; for a beta
 // single the orbitals are in i, a), the phase parity and the source strings.
 struct Term {
-    int cls, i, a, j, b, par;
+    int cls, i, a, j, b, par;  // cls: 0 diagonal, 1/2 alpha/beta single, 3/4/5 alpha-alpha/beta-beta/alpha-beta double
     u32 A, Bs;
 };
+
+// Excitation screen (the heat-bath idea named for future work in Sec. 4): a
+// double excitation's term value t = H_ki v_i is dropped when |t| < eps_x
+// (the element of a double depends only on its four orbitals).  eps_x = 0
+// keeps everything.
+__device__ __forceinline__ bool xscreened(double t, double eps_x) { return fabs(t) < eps_x; }
 
 // Number of (source, excitation) pairs visited per source.
 __host__ __device__ inline u64 terms_per_source(int n, int na, int nb) {

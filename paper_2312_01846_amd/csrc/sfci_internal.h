@@ -102,6 +102,8 @@ struct sfci_problem {
     DevBuf ws_sel2, ws_cand_r, ws_cand_a;  // top-M of a dense source: candidate list and its selection state
     DevBuf ws_lz[8];
     DevBuf ws_rt_rows, ws_rt_beta, ws_rt_nbr, ws_rt_desc;
+    DevBuf ws_ab_rc, ws_ab_cr, ws_ab_off, ws_ab_it;  // alpha-beta item lists (rows of several tiles)
+    DevBuf ws_rt_phase;  // optional per-phase timing of the tile kernel (SFCI_RT_PHASES=1)
     void* rowtile = nullptr;  // tables of the target-owned dense kernel (rowtile.hip)
     // The same space with alpha and beta exchanged (gradient second pass):
     // shares this problem's integrals, binomial table and dense array.
@@ -116,6 +118,10 @@ struct sfci_problem {
     // entries kept): also keep entries within a relative 2^-36 of the M-th
     // |c|, at most SFCI_TIE_SLACK of them.  Set from the options of each call.
     int tie_band = 0;
+    // Excitation screen of the sigma kernels (0 = off): a double excitation's
+    // term H_ki v_i with |H_ki v_i| < excite_eps is not added.  Set from the
+    // options of each call.
+    double excite_eps = 0.0;
 };
 
 // Entries a truncated vector can hold beyond M (the tie band's reach).
@@ -154,7 +160,7 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
 // Batched form: prepare each instance, put the descriptions on the device,
 // then one launch drains the items of all instances.
 struct RowTileDesc {
-    alignas(8) unsigned char raw[256];  // kernel-side description of one instance
+    alignas(8) unsigned char raw[320];  // kernel-side description of one instance
     u64 n_items, nbr_cap;
     size_t lds_bytes;  // the tile
     unsigned n2;       // n^2 of the instance
@@ -175,8 +181,10 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 struct RowTileTune {
     unsigned b1_chunk = 0, bb_chunk = 0, per_cu = 0;
 };
+// ab_lists: for rows of several tiles, also list the alpha-beta doubles' items
+// per (input chunk, target tile) for the sigma kernel (when they fit in memory).
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
-                            double eps = 0.0);
+                            double eps = 0.0, bool ab_lists = false);
 size_t rowtile_desc_bytes();
 // Target alpha rows [lo, hi) of a prepared description only, written into
 // Dp[rank - lo * N_beta] (touched tiles are overwritten, the rest is left
@@ -185,9 +193,10 @@ void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, 
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned per_cu_override = 0);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 // fill_counter = false: the caller has already zeroed *d_counter on the stream.
+// timed: the diagnostic build with per-phase timing (descriptions carrying phase_ns).
 void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64* d_prefix, int n_inst,
                  unsigned* d_counter, void* scratch, u64 nbr_cap, const RowTileGeom& geom, u64 total_items,
-                 bool fill_counter = true, const RowTileTune& tune = RowTileTune{});
+                 bool fill_counter = true, const RowTileTune& tune = RowTileTune{}, bool timed = false);
 
 // Integral gradients through the target-owned tiles: for each job,
 // L = s^T H(h, g) v with s and v sparse (ascending unique ranks).  Raw

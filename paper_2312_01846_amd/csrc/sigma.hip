@@ -12,14 +12,21 @@ struct SigmaParams {
     const u64* v_rank;
     const double* v_amp;
     const u64* v_nnz;
+    double eps_x;  // excitation screen of the doubles (0 = off)
 };
+
+// A term that survives the excitation screen (doubles with |e c| < eps_x go).
+__device__ __forceinline__ bool kept_term(bool ok, double e, double c, const Term& tm, double eps_x) {
+    return ok && !(tm.cls >= 3 && xscreened(e * c, eps_x));
+}
 
 // Dense dedup: every term is added into D[target] with a hardware FP64 atomic.
 struct SinkDense {
     double* D;
     u64 cnt;
-    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c, const Term&) {
-        if (ok) {
+    double eps_x;
+    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c, const Term& tm) {
+        if (kept_term(ok, e, c, tm, eps_x)) {
             unsafeAtomicAdd(D + tgt, e * c);
             ++cnt;
         }
@@ -28,7 +35,10 @@ struct SinkDense {
 
 struct SinkCount {
     u64 cnt;
-    __device__ __forceinline__ void operator()(bool ok, u64, double, double, const Term&) { cnt += ok ? 1 : 0; }
+    double eps_x;
+    __device__ __forceinline__ void operator()(bool ok, u64, double e, double c, const Term& tm) {
+        cnt += kept_term(ok, e, c, tm, eps_x) ? 1 : 0;
+    }
 };
 
 // Tuple emission at deterministic positions: within one source, lanes write
@@ -38,7 +48,9 @@ struct SinkEmit {
     double* vals;
     u64 pos;       // next slot of this source (wave-uniform)
     u64 key_base;  // subtracted from the rank to form the sort key
-    __device__ __forceinline__ void operator()(bool ok, u64 tgt, double e, double c, const Term&) {
+    double eps_x;
+    __device__ __forceinline__ void operator()(bool ok_, u64 tgt, double e, double c, const Term& tm) {
+        const bool ok = kept_term(ok_, e, c, tm, eps_x);
         u64 m = __ballot(ok);
         if (ok) {
             u64 below = m & ((1ull << lane_id()) - 1ull);
@@ -63,7 +75,7 @@ __global__ __launch_bounds__(SFCI_BLOCK) void k_sigma_dense(SigmaParams p, doubl
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const u64 nnz = *p.v_nnz;
-    SinkDense sink{D, 0};
+    SinkDense sink{D, 0, p.eps_x};
     AlphaRange all{0, 0};
     for (u64 s = (u64)blockIdx.x * SFCI_WAVES_PER_BLOCK + wave; s < nnz; s += (u64)gridDim.x * SFCI_WAVES_PER_BLOCK) {
         enumerate_source<false>(p.sp, p.I, sB, sW[wave], p.v_rank[s], p.v_amp[s], all, sink);
@@ -80,7 +92,7 @@ __global__ __launch_bounds__(SFCI_BLOCK) void k_sigma_count(SigmaParams p, Alpha
     const int wave = threadIdx.x >> 6;
     const u64 nnz = *p.v_nnz;
     for (u64 s = (u64)blockIdx.x * SFCI_WAVES_PER_BLOCK + wave; s < nnz; s += (u64)gridDim.x * SFCI_WAVES_PER_BLOCK) {
-        SinkCount sink{0};
+        SinkCount sink{0, p.eps_x};
         enumerate_source<true>(p.sp, p.I, sB, sW[wave], p.v_rank[s], p.v_amp[s], rng, sink);
         u64 tot = wave_sum_u64(sink.cnt);
         if (lane_id() == 0) counts[s] = tot;
@@ -97,7 +109,7 @@ __global__ __launch_bounds__(SFCI_BLOCK) void k_sigma_emit(SigmaParams p, AlphaR
     const int wave = threadIdx.x >> 6;
     const u64 nnz = *p.v_nnz;
     for (u64 s = (u64)blockIdx.x * SFCI_WAVES_PER_BLOCK + wave; s < nnz; s += (u64)gridDim.x * SFCI_WAVES_PER_BLOCK) {
-        SinkEmit sink{keys, vals, offs[s], key_base};
+        SinkEmit sink{keys, vals, offs[s], key_base, p.eps_x};
         enumerate_source<true>(p.sp, p.I, sB, sW[wave], p.v_rank[s], p.v_amp[s], rng, sink);
     }
 }
@@ -147,6 +159,7 @@ SigmaParams make_params(sfci_problem* P, const SigmaLaunch& v) {
     p.v_rank = v.v_rank;
     p.v_amp = v.v_amp;
     p.v_nnz = v.v_nnz;
+    p.eps_x = P->excite_eps;
     return p;
 }
 

@@ -42,7 +42,7 @@ class SVec(C.Structure):
 
 class SigmaOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("dedup", C.c_int32), ("deterministic", C.c_int32), ("screen_eps", C.c_double),
-                ("tie_band", C.c_int32), ("reserved", C.c_int32)]
+                ("tie_band", C.c_int32), ("reserved", C.c_int32), ("excite_eps", C.c_double)]
 
 
 class SigmaStats(C.Structure):
@@ -53,7 +53,8 @@ class SigmaStats(C.Structure):
 class LanczosOpts(C.Structure):
     _fields_ = [("M", C.c_uint64), ("n_L", C.c_int32), ("n_iter", C.c_int32), ("deterministic", C.c_int32),
                 ("dedup", C.c_int32), ("screen_eps", C.c_double), ("no_dense", C.c_int32),
-                ("autotune", C.c_int32), ("conv_eps", C.c_double), ("tie_band", C.c_int32), ("reserved", C.c_int32)]
+                ("autotune", C.c_int32), ("conv_eps", C.c_double), ("tie_band", C.c_int32), ("reserved", C.c_int32),
+                ("excite_eps", C.c_double)]
 
 
 class LanczosStats(C.Structure):
@@ -68,7 +69,8 @@ class BatchStats(C.Structure):
                 ("psi_nnz_total", C.c_uint64),
                 ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32), ("tune_trials", C.c_int32),
                 ("tune_b1_chunk", C.c_uint32), ("tune_bb_chunk", C.c_uint32), ("tune_per_cu", C.c_uint32),
-                ("tune_default_ms", C.c_double), ("tune_best_ms", C.c_double)]
+                ("tune_default_ms", C.c_double), ("tune_best_ms", C.c_double), ("sigma_in_graph", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Roof(C.Structure):
@@ -196,7 +198,7 @@ class Problem:
 
     # -- sigma = H v, truncated ----------------------------------------------------
     def sigma(self, ranks, amps, M=None, dedup="auto", deterministic=False, capacity=None, screen_eps=0.0,
-              tie_band=False):
+              tie_band=False, excite_eps=0.0):
         """Returns (ranks int64, amps float64, stats dict) on the GPU."""
         torch = _torch()
         r = torch.as_tensor(ranks, device="cuda").to(torch.int64).contiguous()
@@ -207,7 +209,8 @@ class Problem:
             cap = min(self.n_det, max(1, r.numel()) * self.tps)
             if M is not None:
                 cap = min(cap, int(M) + (TIE_SLACK if tie_band else 0))
-        opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0, float(screen_eps), 1 if tie_band else 0, 0)
+        opts = SigmaOpts(Mv, DEDUP[dedup], 1 if deterministic else 0, float(screen_eps), 1 if tie_band else 0, 0,
+                         float(excite_eps))
         for _ in range(2):
             o_r = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
             o_a = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
@@ -284,7 +287,7 @@ class Problem:
     # -- the SFCI iteration ----------------------------------------------------
     def lanczos(self, ranks0, amps0, M=None, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_T=False,
                 want_psi=True, psi_capacity=None, screen_eps=0.0, no_dense=False, roots=None, conv_eps=0.0,
-                tie_band=False):
+                tie_band=False, excite_eps=0.0):
         """roots: list of (ranks, amps) of previously found eigenvectors projected out
         of the effective Hamiltonian (the iteration then finds the next state).
         conv_eps > 0: halt once a block lowers the energy by less than conv_eps
@@ -298,7 +301,7 @@ class Problem:
         S = np.zeros(nblk * n_L * n_L) if want_T else None
         Mv = UINT64_MAX if M is None else int(M)
         opts = LanczosOpts(Mv, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps),
-                           1 if no_dense else 0, 0, float(conv_eps), 1 if tie_band else 0, 0)
+                           1 if no_dense else 0, 0, float(conv_eps), 1 if tie_band else 0, 0, float(excite_eps))
         st = LanczosStats()
         psi = None
         if want_psi:
@@ -360,7 +363,7 @@ class Batch:
             pass
 
     def lanczos(self, starts, Ms, n_L=10, n_iter=30, deterministic=False, dedup="auto", want_grad=True,
-                screen_eps=0.0, autotune=False, tie_band=False, conv_eps=0.0):
+                screen_eps=0.0, autotune=False, tie_band=False, conv_eps=0.0, excite_eps=0.0):
         """starts: list of (ranks, amps); Ms: truncation per instance.  Returns
         dict(energies (n_inst, n_blocks), dh [list of (n,n)], dg [list of (n,n,n,n)], stats)."""
         torch = _torch()
@@ -384,7 +387,7 @@ class Batch:
             dh_all = torch.empty(n2, dtype=torch.float64, device="cuda")
             dg_all = torch.empty(n4, dtype=torch.float64, device="cuda")
         opts = LanczosOpts(UINT64_MAX, n_L, n_iter, 1 if deterministic else 0, DEDUP[dedup], float(screen_eps), 0,
-                           1 if autotune else 0, float(conv_eps), 1 if tie_band else 0, 0)
+                           1 if autotune else 0, float(conv_eps), 1 if tie_band else 0, 0, float(excite_eps))
         st = BatchStats()
         rc = load_library().sfci_batch_lanczos(self._h, vecs, Marr, C.byref(opts),
                                                energies.ctypes.data_as(C.c_void_p),
@@ -397,6 +400,7 @@ class Batch:
                               sigma_calls=st.sigma_calls,
                               psi_nnz_total=st.psi_nnz_total, graph_replayed_blocks=st.graph_replayed_blocks,
                               batched_sigma=st.batched_sigma, tune_trials=st.tune_trials,
+                              sigma_in_graph=st.sigma_in_graph,
                               tune=dict(b1_chunk=st.tune_b1_chunk, bb_chunk=st.tune_bb_chunk,
                                         per_cu=st.tune_per_cu, default_ms=st.tune_default_ms,
                                         best_ms=st.tune_best_ms)))

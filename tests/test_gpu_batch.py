@@ -113,6 +113,8 @@ def test_batch_fast_mixed_sizes(torch, S, orc):
                     deterministic=False)
     st = out["stats"]
     assert st["batched_sigma"] == 1 and st["graph_replayed_blocks"] == 2 and st["sigma_calls"] == 30
+    print("tile launch inside the step graphs:", st["sigma_in_graph"])
+    assert 0 < st["sigma_ms"] < st["fwd_ms"]
     ref = orc.Problem(8, 3, 3, hc, ec).lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), None, 10, 30)
     E = out["energies"]
     assert np.all(np.abs(E[0] - ref["energies"]) < 1e-9)

@@ -96,6 +96,38 @@ def test_sigma_matches_oracle(torch, S, orc, name, n, na, nb, mk, nnz, mode):
     assert st["candidates"] == len(orr)
 
 
+@pytest.mark.parametrize("no_t2", ["0", "1"], ids=["bb_table", "bb_walk"])
+@pytest.mark.parametrize("lists", ["1", "0"], ids=["item_lists", "table_slices"])
+def test_sigma_multitile_rows(torch, S, orc, monkeypatch, support_band, lists, no_t2):
+    # Rows of several LDS tiles: 16 orbitals with 5 alpha and 5 beta electrons
+    # (4 368 beta strings) in tiles of at most 1 024 ranks, five per row.  A
+    # few alpha rows hold hundreds of entries (several 64-entry input chunks),
+    # the rest are scattered.  The alpha-beta doubles come from the per
+    # (chunk, tile) item lists or from each entry's table slice per tile; the
+    # beta-beta doubles from the tile-grouped table or the on-the-fly walk.
+    monkeypatch.setenv("SFCI_TILE_MAX", "1024")
+    monkeypatch.setenv("SFCI_AB_LISTS", lists)
+    monkeypatch.setenv("SFCI_NO_T2", no_t2)
+    h, g = synth.molecule_like(16, 32, 11)
+    P, Po = _prob(S, orc, 16, 5, 5, h, g)
+    nb_ = 4368
+    rng = np.random.default_rng(29)
+    parts = [np.uint64(ra) * np.uint64(nb_) + rng.choice(nb_, size=k, replace=False).astype(np.uint64)
+             for ra, k in ((0, 700), (1, 130), (37, 65), (4367, 300))]
+    parts.append(rng.choice(P.n_det, size=2500, replace=False).astype(np.uint64))
+    r = np.unique(np.concatenate(parts))
+    a = rng.normal(0.0, 1.0, size=r.size)
+    orr, oa, oab = Po.sigma(r, a, with_abs=True)
+    gr, ga, st = P.sigma(r.astype(np.int64), a, dedup="dense")
+    gr, ga = _np(gr).astype(np.uint64), _np(ga)
+    assert np.array_equal(gr, orr)
+    assert np.all(np.abs(ga - oa) <= 1e-12 * oab)
+    assert st["terms_enumerated"] == r.size * P.tps
+    for M in (1, 5000, len(orr) // 3):
+        gr, ga, _ = P.sigma(r.astype(np.int64), a, M=M, dedup="dense")
+        support_band(_np(gr).astype(np.uint64), _np(ga), orr, oa, oab, M)
+
+
 @pytest.mark.parametrize("mode", ["dense", "dense_atomic", "sort"])
 def test_sigma_truncated_support(torch, S, orc, support_band, mode):
     h, g = synth.molecule_like(10, 20, 5)

@@ -224,3 +224,72 @@ def test_normalize(orc):
     a = np.array([3.0, 4.0])
     out, nrm = orc.normalize(a)
     assert nrm == 5.0 and np.array_equal(out, [0.6, 0.8])
+
+
+def _distinct_tiny(n, seed, tiny):
+    """Integrals whose (pq|rs) with four distinct indices are tiny (scale
+    `tiny`) and all others O(1): the two-body integrals a double excitation
+    with four distinct orbitals uses are then tiny, while every single,
+    diagonal and repeated-orbital alpha-beta double element stays O(1)."""
+    h, g = synth.molecule_like(n, 2 * n, seed)
+    g = g.reshape(n, n, n, n).copy()
+    rng = np.random.default_rng(seed + 100)
+    for p in range(n):
+        for q in range(n):
+            for r in range(n):
+                for s in range(n):
+                    if len({p, q, r, s}) == 4 and (p, q, r, s) == min(
+                            [(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r), (r, s, p, q), (s, r, p, q),
+                             (r, s, q, p), (s, r, q, p)]):
+                        v = tiny * rng.uniform(0.5, 1.0)
+                        for t in [(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r), (r, s, p, q), (s, r, p, q),
+                                  (r, s, q, p), (s, r, q, p)]:
+                            g[t] = v
+    return h, g
+
+
+def test_excitation_screen_zero_is_identity(orc):
+    h, g = synth.molecule_like(8, 16, 0)
+    P = orc.Problem(8, 3, 3, h, g)
+    r, a = synth.random_sparse_vector(P.n_det, 400, seed=5)
+    full = P.sigma(r, a, with_abs=True)
+    zero = P.sigma(r, a, with_abs=True, eps_x=0.0)
+    for x, y in zip(full, zero):
+        assert np.array_equal(x, y)
+
+
+def test_excitation_screen_hand_count(orc):
+    # One source determinant (aufbau of 2 alpha + 2 beta in 6 orbitals) with
+    # amplitude 1.  With the four-distinct-orbital integrals at 1e-9 and the
+    # screen at 1e-6, exactly those doubles go: 6 alpha-alpha (C(2,2) C(4,2)),
+    # 6 beta-beta, and the 2*4*1*3 = 24 alpha-beta doubles with i, a, j, b
+    # all different; the 64 - 24 = 40 alpha-beta doubles sharing an orbital
+    # (j = i or b = a) and every single and the diagonal stay.
+    h, g = _distinct_tiny(6, 3, 1e-9)
+    P = orc.Problem(6, 2, 2, h, g)
+    r0 = np.array([0], dtype=np.uint64)
+    full = P.sigma(r0, np.array([1.0]))
+    scr = P.sigma(r0, np.array([1.0]), eps_x=1e-6)
+    assert len(full[0]) == 1 + 8 + 8 + 6 + 6 + 64
+    assert len(scr[0]) == len(full[0]) - 36
+    assert np.isin(scr[0], full[0]).all()
+    pos = np.searchsorted(full[0], scr[0])
+    assert np.array_equal(full[1][pos], scr[1])  # one term per target: the kept values are unchanged
+
+
+def test_excitation_screen_equals_dropping_the_tiny_integrals(orc):
+    # Several sources with |v_i| in [0.5, 1]: the screened sigma equals sigma
+    # of the Hamiltonian without the four-distinct-orbital integrals (which
+    # enter only those doubles), by explicit second quantization
+    h, g = _distinct_tiny(7, 4, 1e-10)
+    P = orc.Problem(7, 3, 2, h, g)
+    rng = np.random.default_rng(2)
+    r = np.sort(rng.choice(P.n_det, 60, replace=False)).astype(np.uint64)
+    a = rng.uniform(0.5, 1.0, 60) * rng.choice([-1.0, 1.0], 60)
+    sr, sa, sab = P.sigma(r, a, with_abs=True, eps_x=1e-7)
+    g0 = g.copy()
+    g0[np.abs(g0) < 1e-8] = 0.0
+    ref = orc.Problem(7, 3, 2, h, g0).sigma_explicit_dense(r, a)
+    dense = np.zeros(P.n_det)
+    dense[sr.astype(np.int64)] = sa
+    assert np.all(np.abs(dense - ref) <= 1e-13 * np.maximum(1.0, np.abs(ref)))
