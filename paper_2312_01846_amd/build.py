@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfci.so")
 
-SOURCES = ["sigma.hip", "select.hip", "sortpath.hip", "lanczos.hip", "util.hip", "abi.hip", "backward.hip", "rowtile.hip", "batch.hip", "listlz.hip", "rowpass.hip", "pt2.hip", "probe.hip"]
+SOURCES = ["sigma.hip", "select.hip", "sortpath.hip", "lanczos.hip", "util.hip", "abi.hip", "backward.hip", "rowtile.hip", "batch.hip", "listlz.hip", "rowpass.hip", "pt2.hip", "probe.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

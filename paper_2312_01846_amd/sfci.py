@@ -107,6 +107,7 @@ _SIGS = {
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(BatchStats)]),
     "sfci_last_error": (C.c_char_p, []),
     "sfci_roof_probe": (C.c_int, [C.c_uint64, C.c_void_p, C.POINTER(Roof)]),
+    "sfci_topm_noalloc": (C.c_int, [C.c_void_p, C.POINTER(SVec), C.c_uint64, C.c_int32, C.c_int32, C.POINTER(SVec)]),
 }
 
 
