@@ -410,9 +410,9 @@ def bench_batch(args, torch, sfci, synth):
     achieved = alg_bytes / sig_s if sig_s > 0 else 0.0
     cpu = None
     if not args.no_cpu_baseline:
-        kb = int(np.argmax(Ms)) if sample is not None else 0
+        kb = int(np.argmax(Ms))
         if sample is None:
-            o = probs[0].lanczos(v0[0], v0[1], M=Ms[0], n_L=args.n_L, n_iter=args.n_L)
+            o = probs[kb].lanczos(v0[0], v0[1], M=Ms[kb], n_L=args.n_L, n_iter=args.n_L)
             sample = (o["psi_rank"], o["psi_amp"])
         _, hs, gs = inst[kb]
         cpu = cpu_baseline(hs, gs, n, na, nb, sample[0].cpu().numpy().astype(np.uint64), sample[1].cpu().numpy(),

@@ -154,6 +154,22 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         }
     } restore{B};
     for (auto* P : B->P) P->stream = st;
+    // Deterministic sigma (sort path) of every instance: an equal share of a
+    // quarter of the memory free now for each instance's tuple buffers, so
+    // that instances set up later are not left with the remainder of the
+    // earlier ones' buffers.  Cleared when the call returns.
+    struct TupHint {
+        sfci_batch* B;
+        ~TupHint() {
+            for (auto* P : B->P) P->tup_cap_hint = 0;
+        }
+    } tup_hint{B};
+    if (det) {
+        size_t freeb = 0, totb = 0;
+        SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
+        const u64 per = std::max<u64>(4096, (u64)(freeb / 4 / (size_t)std::max(1, n)) / SFCI_SORT_TUPLE_BYTES);
+        for (auto* P : B->P) P->tup_cap_hint = per;
+    }
     std::vector<Inst> I(n);
     bool all_tiles = true;
     for (int k = 0; k < n; ++k) {

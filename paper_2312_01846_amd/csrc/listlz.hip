@@ -55,6 +55,15 @@ __global__ void k_range_bounds(const u64* __restrict__ Wr, u64 cap, const u64* _
     bounds[2 * l + 1] = lower_bound_u64(r, n, rhi);
 }
 
+// rowptr[r] = the first entry of a rank-sorted list with rank >= r N_beta,
+// r = 0..N_alpha: the entries of alpha row r are [rowptr[r], rowptr[r + 1]).
+__global__ void k_row_ptrs(const u64* __restrict__ r, const u64* __restrict__ nnz, u64 Na, u64 Nb,
+                           u64* __restrict__ rowptr) {
+    const u64 n = *nnz;
+    for (u64 row = (u64)blockIdx.x * blockDim.x + threadIdx.x; row <= Na; row += (u64)gridDim.x * blockDim.x)
+        rowptr[row] = lower_bound_u64(r, n, row * Nb);
+}
+
 // Y[l][i] = y(rank of w_l[i]) for the entries of w_l inside this pass; the
 // pass entries hit from w_j and w_{j-1} (l >= mark_from) are marked.
 __global__ __launch_bounds__(LB) void k_gather_pass(const u64* __restrict__ Wr, u64 cap, const u64* __restrict__ bounds,
@@ -418,7 +427,7 @@ void sort_by_rank(sfci_problem* P, u64* r, double* a, u64 n) {
 
 }  // namespace
 
-u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, double eps);
+u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, ListPassSink& sink, u64* emitted_dev, double eps);
 
 u64 sigma_list_topm(sfci_problem* P, const SigmaLaunch& v, u64 M, u64* out_rank, double* out_amp, u64 out_cap,
                     u64* emitted_dev, u64* distinct_host, bool tiles_ok, double eps) {
@@ -474,10 +483,76 @@ bool list_sigma_tiles(sfci_problem* P, u64 nnz) {
 }
 
 // Dense passes: sigma through the target-owned tile kernel, a range of
-// target alpha rows at a time, into a zeroed slice of rows x N_beta doubles;
-// each slice is compacted (rank order, zeroing it) into the sink.
-u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, double eps) {
+// target alpha rows at a time.  Fused (the default): every finished tile is
+// consumed in the kernel itself (FusedOut: the T gathers, the marks of
+// supp(w_j) U supp(w_{j-1}), the candidate appends above the running bound),
+// so no N_beta-wide slice is written or re-read; a pass whose appends overflow
+// the candidate list is run again after the list has grown.  The first pass
+// is small, so that the bound is set before most rows append.
+// SFCI_LIST_FUSED=0: each pass fills a zeroed slice of rows x N_beta doubles,
+// compacted (rank order, zeroing it) into the sink.
+u64 sigma_dense_passes(sfci_problem* P, const SigmaLaunch& v, ListPassSink& sink, u64* emitted_dev, double eps) {
     ListWs& ws = P->list_ws;
+    const char* fenv = getenv("SFCI_LIST_FUSED");
+    if (!(fenv && fenv[0] == '0')) {
+        const RowTileDesc all = rowtile_prepare(P, v, nullptr, (unsigned long long*)emitted_dev, eps, true);
+        ListCands& C = *sink.cands;
+        const int nl = sink.nl;
+        u64* rowptr = (u64*)ws.rowptr.get((size_t)std::max(1, nl) * (P->Na + 1) * sizeof(u64));
+        const unsigned gr = (unsigned)std::min<u64>((P->Na + 256) / 256, 16384);
+        for (int l = 0; l < nl; ++l)
+            hipLaunchKernelGGL(k_row_ptrs, dim3(gr), dim3(256), 0, P->stream, sink.Wr + (size_t)l * sink.cap,
+                               sink.nnz + l, P->Na, P->Nb, rowptr + (size_t)l * (P->Na + 1));
+        SFCI_CHECK_HIP(hipGetLastError());
+        FusedOut h{};
+        h.Wr = sink.Wr;
+        h.rowptr = rowptr;
+        h.Y = sink.Y;
+        h.cap = sink.cap;
+        h.na_rows = P->Na;
+        h.nl = nl;
+        h.mark_from = sink.mark_from;
+        h.collect = sink.collect ? 1 : 0;
+        h.bound = C.bound;
+        h.Rn = C.Rn;
+        h.overflow = C.overflow;
+        h.distinct = sink.distinct;
+        FusedOut* d_fo = (FusedOut*)ws.fo.get(sizeof(FusedOut));
+        const u64 room = std::max<u64>(1ull << 24, 4 * std::min<u64>(C.K, 1ull << 26));
+        u64 lo = 0, passes = 0, extra = 0;
+        while (lo < P->Na) {
+            const u64 rows = std::max<u64>(1, passes == 0 ? P->Na / 64 : P->Na / 8);
+            const u64 hi = std::min<u64>(P->Na, lo + rows);
+            if (sink.collect) C.ensure(room + extra);
+            h.Rr = C.Rr();
+            h.Ra = C.Ra();
+            h.Rcap = C.cap();
+            const u64 n_before = C.n_upper;
+            const u64 dist_before = sink.distinct ? read_dev(P, sink.distinct) : 0;
+            SFCI_CHECK_HIP(hipMemcpyAsync(d_fo, &h, sizeof(h), hipMemcpyHostToDevice, P->stream));
+            launch_sigma_rowtile_rows_fused(P, all, lo, hi, d_fo);  // synchronises the stream
+            if (sink.collect) {
+                int ovf = 0;
+                SFCI_CHECK_HIP(hipMemcpyAsync(&ovf, C.overflow, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+                SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
+                if (ovf) {
+                    // run the pass again with room for what it appends
+                    const u64 need = read_dev(P, C.Rn) - n_before;
+                    launch_fill_u64(C.Rn, 1, n_before, P->stream);
+                    launch_fill_u64((u64*)C.overflow, 1, 0, P->stream);
+                    if (sink.distinct) launch_fill_u64(sink.distinct, 1, dist_before, P->stream);
+                    extra = need + need / 4;
+                    continue;
+                }
+                C.n_upper = read_dev(P, C.Rn);
+                C.maybe_cut();
+            }
+            extra = 0;
+            ++passes;
+            lo = hi;
+        }
+        return passes;
+    }
     size_t freeb = 0, totb = 0;
     SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
     const u64 slice_bytes = std::min<u64>((u64)(freeb + ws.dpass.bytes) / 4, 32ull << 30);

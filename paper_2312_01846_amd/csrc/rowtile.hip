@@ -39,7 +39,8 @@ struct RTParams {
     const u32* v_rb;       // beta rank of every input entry (the rank within its alpha row)
     const u64* rowbeg;     // per alpha rank: first input entry of that row
     const u64* rowend;     // per alpha rank: one past the last (== rowbeg when empty)
-    const u32* rtb;        // per alpha rank, ntiles + 1 entry offsets: first entry with beta rank >= tile_lo[t]
+    const u32* rtb;        // tile-major: rtb[t N_alpha + r], t = 0..ntiles, the first entry of alpha row r
+                           // with beta rank >= tile_lo[t]
     const u32* T1;         // beta singles per beta rank, sorted by target: rank | (j n + b) << 21 | par << 31
     const uint16_t* toff;  // per beta rank, ntiles + 1 offsets into its T1 slice
     const u64* tile_lo;    // ntiles + 1 rank boundaries
@@ -77,6 +78,7 @@ struct RTParams {
     // units, identity beta-single units, beta-beta units, barrier wait and
     // tile write, other units, work fetch.  nullptr = off.
     unsigned long long* phase_ns;
+    const FusedOut* fo;  // sigma: finished tiles go here instead of D (nullptr: written to D)
 };
 
 // One contributing source row of the current (target row, tile).
@@ -192,10 +194,14 @@ template <int MODE, bool TIMED = false>
 __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
                                              int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off,
-                                             unsigned b1_chunk, unsigned bb_chunk) {
+                                             unsigned b1_chunk, unsigned bb_chunk, unsigned ja_off) {
     constexpr bool GRAD = MODE != RT_SIGMA;
     extern __shared__ double acc[];
     double* const itab = acc + itab_off;  // sigma: per-item element tables
+    // sigma, when it fits (ja_off != 0): per item, (jb|kk) for each occupied
+    // alpha orbital k of the target string (in ascending order) and every
+    // j n + b: the alpha part of the identity row's beta-single elements
+    double* const ja = acc + ja_off;
     __shared__ BinomLds sB;
     __shared__ WaveScratch sw[RT_WAVES];
     __shared__ uint8_t occA[32], virA[32];
@@ -209,7 +215,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     // across its tiles (tile-independent parts; entry ranges refreshed per tile)
     __shared__ u64 s_cache_row;
     __shared__ int s_cache_inst;
-    __shared__ unsigned s_nrow;
+    // rows of several tiles: the row's records, alpha singles at rowlist[0,
+    // s_nrow), the others at rowlist[nbr_cap - s_nrow2, nbr_cap); entry
+    // ranges per tile are read when a record is used; the identity row's entries
+    __shared__ unsigned s_nrow, s_nrow2;
+    __shared__ u32 s_row_idb, s_row_ide;
     __shared__ RTParams p;
     __shared__ unsigned long long s_ph[RT_WAVES][8];
 
@@ -276,16 +286,22 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 s_item = ~0ull;
                 s_left = 0;
                 if (it < total_items) {
-                    // unit -> (row, chunk of tile_chunk tiles)
+                    // unit -> (row, chunk of tile_chunk tiles), chunk-major: units
+                    // running together share their tiles (and the tiles' entry
+                    // boundaries, rtb's rows for those tiles, stay in cache)
                     const u64 nt = (u64)descs[k].ntiles, C = (u64)descs[k].tile_chunk;
                     const u64 nch = (nt + C - 1) / C;
                     const u64 u = it - item_prefix[k];
-                    const u64 row = u / nch, ch = u - row * nch;
+                    const u64 rows = (item_prefix[k + 1] - item_prefix[k]) / nch;
+                    const u64 ch = u / rows, row = u - ch * rows;
                     s_item = row * nt + ch * C;
                     s_left = min(C, nt - ch * C) - 1;
                 }
                 s_inst = k;
                 s_nrow = 0;  // a new row: its records are built afresh
+                s_nrow2 = 0;
+                s_row_idb = 0;
+                s_row_ide = 0;
                 s_cache_row = ~0ull;
             }
             s_nbr = 0;
@@ -356,26 +372,36 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
         }
         __syncthreads();
+        if (!GRAD && ja_off) {
+            // read in phase 3, after phase 1's barrier
+            const u32 n2 = (u32)n * n;
+            for (u32 t = threadIdx.x; t < (u32)na * n2; t += RT_BLOCK) {
+                const u32 qi = t / n2, jb = t - qi * n2;
+                const u32 kq = occA[qi];
+                ja[t] = p.I.g[(jb * (u32)n + kq) * (u32)n + kq];
+            }
+        }
 
         // Phase 1: the nonempty source rows, with their entry range in this tile.
         const bool multi = !GRAD && p.ntiles > 1;
         const bool cached = multi && s_cache_row == rAt && s_cache_inst == s_inst;
         if (cached) {
-            // the row's records from its first tile: refresh the entry ranges
-            const unsigned nrow = s_nrow;
+            // the row's records from its first tile: this tile's entry ranges
+            // (alpha doubles with none here are left out)
+            if (threadIdx.x == 0) {
+                s_idb = s_row_idb;
+                s_ide = s_row_ide;
+            }
+            const unsigned nrow = s_nrow + s_nrow2;
             for (unsigned b0 = 0; b0 < nrow; b0 += RT_BLOCK) {
                 const unsigned t = b0 + threadIdx.x;
                 NbrRec r;
                 r.type = 255;
                 if (t < nrow) {
-                    r = rowlist[t];
-                    const u32* tb = p.rtb + (u64)r.rAs * (u64)(p.ntiles + 1);
-                    r.e0 = tb[tile];
-                    r.e1 = tb[tile + 1];
-                    if (r.type == 0) {
-                        s_idb = r.rowb;
-                        s_ide = r.rowe;
-                    }
+                    r = rowlist[t < s_nrow ? t : nbr_cap - 1 - (t - s_nrow)];
+                    const u32* tb = p.rtb + (u64)r.rAs;
+                    r.e0 = tb[(u64)tile * p.sp.Na];
+                    r.e1 = tb[(u64)(tile + 1) * p.sp.Na];
                     if (r.type == 2 && r.e1 <= r.e0) r.type = 255;
                 }
                 push(r, r.type != 255);
@@ -419,12 +445,15 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (type == 0) {
                     s_idb = (u32)rb;  // the identity row: all its entries feed the beta-beta doubles
                     s_ide = (u32)re;
+                    s_row_idb = (u32)rb;
+                    s_row_ide = (u32)re;
                 }
                 if (re > rb) {
                     row_ok = true;
-                    const u32* tb = p.rtb + rAs * (u64)(p.ntiles + 1);
                     r.As = As; r.rAs = (u32)rAs; r.rowb = (u32)rb; r.rowe = (u32)re;
-                    r.e0 = tb[tile]; r.e1 = tb[tile + 1];
+                    const u32* tb = p.rtb + (u64)rAs;
+                    r.e0 = tb[(u64)tile * p.sp.Na];
+                    r.e1 = tb[(u64)(tile + 1) * p.sp.Na];
                     r.i = (uint8_t)i; r.a = (uint8_t)a; r.j = (uint8_t)j; r.b = (uint8_t)b;
                     r.type = (uint8_t)type;
                     r.par = 0;
@@ -463,17 +492,22 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 }
             }
             if (multi) {
-                // keep every record that survives the row-level filters for the row's later tiles
-                // (in sigma mode only alpha doubles are ever dropped for a tile alone)
-                const u64 mr = __ballot(row_ok);
-                unsigned rs0 = 0;
-                if (lane == 0 && mr) rs0 = atomicAdd(&s_nrow, (unsigned)__popcll(mr));
-                rs0 = __shfl(rs0, 0);
-                if (row_ok) {
-                    NbrRec rr = r;
-                    if (rr.type == 255) rr.type = 2;
-                    rowlist[rs0 + __popcll(mr & ((1ull << lane) - 1ull))] = rr;
+                // keep every record that survives the row-level filters for all the row's
+                // tiles: alpha singles at the front, the others from the back
+                const bool k1 = row_ok && r.type == 1, k2 = row_ok && r.type != 1;
+                const u64 m1 = __ballot(k1), m2 = __ballot(k2);
+                unsigned s1 = 0, s2 = 0;
+                if (lane == 0) {
+                    if (m1) s1 = atomicAdd(&s_nrow, (unsigned)__popcll(m1));
+                    if (m2) s2 = atomicAdd(&s_nrow2, (unsigned)__popcll(m2));
                 }
+                s1 = __shfl(s1, 0);
+                s2 = __shfl(s2, 0);
+                const u64 lt = (1ull << lane) - 1ull;
+                NbrRec rr = r;
+                if (rr.type == 255) rr.type = 2;  // an alpha double with no entries in this tile
+                if (k1) rowlist[s1 + __popcll(m1 & lt)] = rr;
+                if (k2) rowlist[nbr_cap - 1 - (s2 + __popcll(m2 & lt))] = rr;
             }
             push(r, r.type != 255);
         }
@@ -498,11 +532,15 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         if (threadIdx.x == 0) s_touched = 1;
 
         // Phase 2: direct targets (beta unchanged).  Short ranges: one thread
-        // per source row; long ranges: one wavefront, lanes over the entries.
+        // per source row; long ranges, and alpha-single rows of more than a
+        // few entries (each entry's element adds (ia|qq) over its beta
+        // orbitals, staged in LDS per wavefront there): one wavefront, lanes
+        // over the entries.
+        auto by_wave = [](const NbrRec& r) { return r.e1 - r.e0 > (r.type == 1 ? 4u : 32u); };
         if (!GRAD) {
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
                 const NbrRec r = rec(li);
-                if (r.e1 - r.e0 > 32) continue;
+                if (by_wave(r)) continue;
                 // RT_UNROLL entries at a time, their loads in flight together
                 for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
                     u32 rb[RT_UNROLL], bt[RT_UNROLL];
@@ -532,7 +570,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 li = __shfl(li, 0);
                 if (li >= nlist) break;
                 const NbrRec r = rec(li);
-                if (r.e1 - r.e0 <= 32) continue;
+                if (!by_wave(r)) continue;
                 const double* gq = nullptr;
                 if (r.type == 1) {
                     // this row's (ia|qq), q = 0..n-1
@@ -823,7 +861,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 r.par = 0;
             } else {
                 r = list[li];
-                if (r.type != 1) continue;  // alpha doubles: direct only; the identity row: chunks above
+                if (r.type != 1) continue;  // (alpha singles come first: not reached)
             }
             const int T = r.type;
             const int I_ = r.i, A_ = r.a;
@@ -1035,11 +1073,19 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                             x[u] = tsg[ti];
                             c[u] = (k0 + (u32)u < r.rowe) ? ampg[k] : 0.0;
                         }
-                        for (u32 m = At; m; m &= m - 1u) {
-                            const int kq = __builtin_ctz(m);
+                        if (ja_off) {
+                            const u32 n2 = (u32)n * n;
+                            for (int qi = 0; qi < na; ++qi) {
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u)
-                                x[u] += p.I.g[(t1_jb(te[u]) * (u32)n + kq) * (u32)n + kq];
+                                for (int u = 0; u < RT_UNROLL; ++u) x[u] += ja[(u32)qi * n2 + t1_jb(te[u])];
+                            }
+                        } else {
+                            for (u32 m = At; m; m &= m - 1u) {
+                                const int kq = __builtin_ctz(m);
+#pragma unroll
+                                for (int u = 0; u < RT_UNROLL; ++u)
+                                    x[u] += p.I.g[(t1_jb(te[u]) * (u32)n + kq) * (u32)n + kq];
+                            }
                         }
 #pragma unroll
                         for (int u = 0; u < RT_UNROLL; ++u) {
@@ -1167,9 +1213,13 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                                 if ((gs ? 0 : r.par) ^ par_b) e = -e;
                             } else {
                                 e = p.TS[ig[u]];
-                                for (u32 m = At; m; m &= m - 1u) {
-                                    const int kq = __builtin_ctz(m);
-                                    e += p.I.g[(jb * (u32)n + kq) * (u32)n + kq];
+                                if (ja_off) {
+                                    for (int qi = 0; qi < na; ++qi) e += ja[(u32)qi * (u32)(n * n) + jb];
+                                } else {
+                                    for (u32 m = At; m; m &= m - 1u) {
+                                        const int kq = __builtin_ctz(m);
+                                        e += p.I.g[(jb * (u32)n + kq) * (u32)n + kq];
+                                    }
                                 }
                                 if (par_b) e = -e;
                             }
@@ -1201,7 +1251,60 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         if (lane == 0) my_terms += wterms;  // the per-wavefront count, folded once per item
         wterms = 0;
         __syncthreads();
-        if (!GRAD && s_touched) {
+        if (!GRAD && p.fo) {
+            // the list iteration's pass work on the finished tile (FusedOut)
+            const FusedOut& f = *p.fo;
+            const u64 rowbase = rAt * Nb;
+            const double eps = p.eps;
+            auto yval = [&](u32 x) -> double {
+                const double v = acc[x];
+                return (eps > 0.0 && fabs(v) < eps) ? 0.0 : v;
+            };
+            // the entries of w_l in this tile: lanes over w_l's entries of row A'
+            auto scan_basis = [&](int l, auto&& fn) {
+                const u64* rp = f.rowptr + (u64)l * (f.na_rows + 1);
+                const u64 s0 = rp[rAt], s1 = rp[rAt + 1];
+                const u64* wr = f.Wr + (u64)l * f.cap;
+                for (u64 i = s0 + lane; i < s1; i += 64) {
+                    const u64 rb = wr[i] - rowbase;
+                    if (rb >= tlo && rb < thi) fn(i, (u32)(rb - tlo));
+                }
+            };
+            for (int l = wave; l < f.nl; l += RT_WAVES)
+                scan_basis(l, [&](u64 i, u32 x) { f.Y[(u64)l * f.cap + i] = yval(x); });
+            if (f.distinct) {
+                u32 nz = 0;
+                for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) nz += (yval((u32)x) != 0.0) ? 1u : 0u;
+                for (int off = 32; off >= 1; off >>= 1) nz += (u32)__shfl_xor((int)nz, off);
+                if (lane == 0 && nz) atomicAdd((unsigned long long*)f.distinct, (unsigned long long)nz);
+            }
+            __syncthreads();
+            for (int l = f.mark_from + wave; l < f.nl; l += RT_WAVES)
+                scan_basis(l, [&](u64, u32 x) { acc[x] = 0.0; });
+            __syncthreads();
+            if (f.collect) {
+                const u64 tb = *f.bound;
+                for (int x0 = 0; x0 < tsz; x0 += RT_BLOCK) {
+                    const int x = x0 + (int)threadIdx.x;
+                    const double v = (x < tsz) ? yval((u32)x) : 0.0;
+                    const bool pk = ((u64)__double_as_longlong(v) & 0x7fffffffffffffffull) > tb;
+                    const u64 m = __ballot(pk);
+                    if (m == 0) continue;
+                    u64 at0 = 0;
+                    if (lane == 0) at0 = atomicAdd((unsigned long long*)f.Rn, (unsigned long long)__popcll(m));
+                    at0 = (u64)__shfl((long long)at0, 0);
+                    if (pk) {
+                        const u64 at = at0 + (u64)__popcll(m & ((1ull << lane) - 1ull));
+                        if (at < f.Rcap) {
+                            f.Rr[at] = rowbase + tlo + (u64)x;
+                            f.Ra[at] = v;
+                        } else {
+                            *f.overflow = 1;
+                        }
+                    }
+                }
+            }
+        } else if (!GRAD && s_touched) {
             double* dst = p.D + (rAt - p.row_base) * Nb + tlo;
             const double eps = p.eps;
             if (eps > 0.0)
@@ -1227,9 +1330,10 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile(const RTParams* __re
                                                             const u64* __restrict__ item_prefix, int n_inst,
                                                             unsigned* __restrict__ counter, void* nbr_scratch,
                                                             u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
-                                                            unsigned itab_off, unsigned b1_chunk, unsigned bb_chunk) {
+                                                            unsigned itab_off, unsigned b1_chunk, unsigned bb_chunk,
+                                                            unsigned ja_off) {
     rowtile_body<RT_SIGMA>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, itab_off,
-                           b1_chunk, bb_chunk);
+                           b1_chunk, bb_chunk, ja_off);
 }
 
 // The same with per-phase timing (a diagnostic build of the kernel, launched
@@ -1239,9 +1343,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile_timed(const RTParams
                                                                   unsigned* __restrict__ counter, void* nbr_scratch,
                                                                   u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
                                                                   unsigned itab_off, unsigned b1_chunk,
-                                                                  unsigned bb_chunk) {
+                                                                  unsigned bb_chunk, unsigned ja_off) {
     rowtile_body<RT_SIGMA, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2,
-                                 itab_off, b1_chunk, bb_chunk);
+                                 itab_off, b1_chunk, bb_chunk, ja_off);
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
@@ -1250,7 +1354,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a(const RTParams* __r
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
     rowtile_body<RT_GRAD_A>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2, 0u,
-                            RT_B1_CHUNK, RT_BB_CHUNK);
+                            RT_B1_CHUNK, RT_BB_CHUNK, 0u);
 }
 
 // Integral gradients, second pass (beta-side terms on the spin-exchanged problem).
@@ -1259,7 +1363,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
                                                              u64 nbr_cap, unsigned slab_off) {
     rowtile_body<RT_GRAD_B>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u, 0u, RT_B1_CHUNK,
-                            RT_BB_CHUNK);
+                            RT_BB_CHUNK, 0u);
 }
 
 // ---- per-problem tables ----
@@ -1457,7 +1561,7 @@ __global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __
         vrb[k] = (u32)rb;
         int t = 0;
         while (t + 1 < ntiles && tile_lo[t + 1] <= rb) ++t;
-        u32* tb = rtb + ra * (u64)nt1;
+        u32* tb = rtb + ra;  // boundary u at tb[u N_alpha]
         const bool first = (k == 0) || (r[k - 1] / sp.Nb != ra);
         const bool last = (k + 1 == nnz) || (r[k + 1] / sp.Nb != ra);
         int tprev = -1;
@@ -1466,9 +1570,9 @@ __global__ void k_rows(SpaceDev sp, const u64* __restrict__ binom, const u64* __
             tprev = 0;
             while (tprev + 1 < ntiles && tile_lo[tprev + 1] <= rbp) ++tprev;
         }
-        for (int u = tprev + 1; u <= t; ++u) tb[u] = (u32)k;  // tiles that start at this entry
+        for (int u = tprev + 1; u <= t; ++u) tb[(u64)u * sp.Na] = (u32)k;  // tiles that start at this entry
         if (last)
-            for (int u = t + 1; u < nt1; ++u) tb[u] = (u32)(k + 1);
+            for (int u = t + 1; u < nt1; ++u) tb[(u64)u * sp.Na] = (u32)(k + 1);
         if (first) rowbeg[ra] = k;
         if (last) rowend[ra] = k + 1;
     }
@@ -1830,6 +1934,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.ab_off = nullptr;
     rp.ab_rowchunk = nullptr;
     if (ab_lists) build_ab_lists(P, S, v, rowbeg, rowend, vrb, rp);
+    rp.fo = nullptr;
     rp.phase_ns = nullptr;
     if (const char* env = getenv("SFCI_RT_PHASES"))
         if (env[0] == '1') {
@@ -1850,6 +1955,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
     out.lds_bytes = S->lds_bytes;
     out.n2 = (unsigned)(P->n * P->n);
+    out.ja_doubles = (unsigned)(P->na * P->n * P->n);
     out.max_lds = S->maxlds;
     return out;
 }
@@ -1872,9 +1978,17 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
     const unsigned itab_off = (unsigned)(tile / sizeof(double));
     const unsigned slab_off = itab_off + rt_itab_doubles(n2);
     const size_t base = (size_t)slab_off * sizeof(double);
-    RowTileGeom g{base + (size_t)RT_WAVES * 32 * sizeof(double), slab_off, 0u, itab_off};
+    RowTileGeom g{base + (size_t)RT_WAVES * 32 * sizeof(double), slab_off, 0u, itab_off, 0u};
     const size_t with = base + (size_t)RT_WAVES * (n2 + 32) * sizeof(double);
     if (with + rt_static_lds() <= (size_t)maxlds) g.lds = with, g.slab_n2 = n2;
+    // then the identity row's alpha-part table, if it still fits
+    unsigned ja = 0;
+    for (int k = 0; k < n_inst; ++k) ja = std::max(ja, d[k].ja_doubles);
+    const size_t ja_at = (g.lds + 15) & ~(size_t)15;
+    if (ja && ja_at + (size_t)ja * sizeof(double) + rt_static_lds() <= (size_t)maxlds) {
+        g.ja_off = (unsigned)(ja_at / sizeof(double));
+        g.lds = ja_at + (size_t)ja * sizeof(double);
+    }
     return g;
 }
 
@@ -1886,7 +2000,8 @@ void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64*
     hipLaunchKernelGGL(timed ? k_sigma_rowtile_timed : k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream,
                        (const RTParams*)d_descs,
                        d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off,
-                       tune.b1_chunk ? tune.b1_chunk : RT_B1_CHUNK, tune.bb_chunk ? tune.bb_chunk : RT_BB_CHUNK);
+                       tune.b1_chunk ? tune.b1_chunk : RT_B1_CHUNK, tune.bb_chunk ? tune.bb_chunk : RT_BB_CHUNK,
+                       geom.ja_off);
     SFCI_CHECK_HIP(hipGetLastError());
 }
 
@@ -1953,6 +2068,14 @@ void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, 
     // the host buffers above are copied before this returns
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
     if (rp.phase_ns && hi == P->Na) report_phases(P, "sigma, all row slices");
+}
+
+void launch_sigma_rowtile_rows_fused(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, const FusedOut* d_fo) {
+    RowTileDesc d = all;
+    RTParams& rp = *(RTParams*)d.raw;
+    rp.fo = d_fo;
+    rp.D = nullptr;
+    launch_sigma_rowtile_rows(P, d, lo, hi, nullptr);
 }
 
 // ---- integral gradients through the tiles ----

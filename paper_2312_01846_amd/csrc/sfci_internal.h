@@ -76,10 +76,10 @@ struct RowPassWs {
 
 // Buffers of the list-based iteration and sigma (listlz.hip).
 struct ListWs {
-    DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a, dpass, dcnt, scal2;
+    DevBuf scal, pr, pa, mark, Rr, Ra, R2r, R2a, yg, taken, psi_r, psi_a, dpass, dcnt, scal2, rowptr, fo;
     void release() {
         for (DevBuf* b : {&scal, &pr, &pa, &mark, &Rr, &Ra, &R2r, &R2a, &yg, &taken, &psi_r, &psi_a, &dpass, &dcnt,
-                          &scal2})
+                          &scal2, &rowptr, &fo})
             b->release();
     }
 };
@@ -118,6 +118,8 @@ struct sfci_problem {
     // entries kept): also keep entries within a relative 2^-36 of the M-th
     // |c|, at most SFCI_TIE_SLACK of them.  Set from the options of each call.
     int tie_band = 0;
+    // Sort-path tuples per pass assigned by a batch (0: a quarter of free memory).
+    u64 tup_cap_hint = 0;
     // Excitation screen of the sigma kernels (0 = off): a double excitation's
     // term H_ki v_i with |H_ki v_i| < excite_eps is not added.  Set from the
     // options of each call.
@@ -164,6 +166,7 @@ struct RowTileDesc {
     u64 n_items, nbr_cap;
     size_t lds_bytes;  // the tile
     unsigned n2;       // n^2 of the instance
+    unsigned ja_doubles;  // n_alpha n^2: the identity row's alpha-part table
     int max_lds;       // LDS per workgroup on the device
 };
 // Launch geometry for a set of descriptions: dynamic LDS, and where the
@@ -173,6 +176,7 @@ struct RowTileGeom {
     size_t lds;
     unsigned slab_off, slab_n2;
     unsigned itab_off;  // per-item element tables
+    unsigned ja_off;    // the identity row's alpha-part table (0: not staged)
 };
 RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 // Launch-time work sizes of the sigma tile kernel (0 = the built-in default):
@@ -190,6 +194,35 @@ size_t rowtile_desc_bytes();
 // Dp[rank - lo * N_beta] (touched tiles are overwritten, the rest is left
 // as it is: Dp must be zero there).  Synchronises the stream.
 void launch_sigma_rowtile_rows(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, double* Dp);
+// What the tile kernel does with each finished tile instead of writing it to
+// a dense slice (the list iteration's passes, fused): (1) y is gathered at the
+// entries of w_l, l < nl, that fall in the tile (T_lj; Y[l cap + i]); (2) the
+// entries of w_l, l >= mark_from, are left out of the candidates (Eq. 10 forms
+// them afterwards); (3) with collect, every other entry with |y| above the
+// running bound joins the candidate list (Rr, Ra at atomically taken
+// positions; overflow set when Rcap is reached, Rn still counts); (4) the
+// nonzero entries are counted into *distinct when it is set.  y is the
+// screened value (|y| < eps written as 0).  Lives in device memory.
+struct FusedOut {
+    const u64* Wr;      // basis ranks, w_l at Wr + l cap (rank-sorted)
+    const u64* rowptr;  // per l < nl: na_rows + 1 offsets, the first entry of w_l in each alpha row
+    double* Y;          // gathered y, Y[l cap + i]
+    u64 cap;
+    u64 na_rows;
+    int nl, mark_from;
+    int collect, pad;
+    const u64* bound;   // bits of |c| a candidate must exceed
+    u64* Rr;
+    double* Ra;
+    u64* Rn;
+    u64 Rcap;
+    int* overflow;
+    u64* distinct;      // may be NULL
+};
+// Target alpha rows [lo, hi) of a prepared description, each finished tile
+// handed to the FusedOut at d_fo (device) instead of being written.
+// Synchronises the stream.
+void launch_sigma_rowtile_rows_fused(sfci_problem* P, const RowTileDesc& all, u64 lo, u64 hi, const FusedOut* d_fo);
 unsigned rowtile_grid(int num_cu, size_t lds_bytes, u64 total_items, unsigned per_cu_override = 0);
 size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap);
 // fill_counter = false: the caller has already zeroed *d_counter on the stream.
@@ -283,6 +316,8 @@ struct SortPassSink {
     virtual void end(u64 alo, u64 ahi) = 0;
     virtual ~SortPassSink() = default;
 };
+// Device bytes per sort-path tuple over the emission, sort and reduction buffers.
+constexpr u64 SFCI_SORT_TUPLE_BYTES = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + sizeof(u64);
 u64 sort_tuple_cap(sfci_problem* P);
 u64 sigma_sorted_passes(sfci_problem* P, const SigmaLaunch& v, SortPassSink& sink, u64* emitted_dev, u64 tup_cap,
                         double eps);

@@ -447,11 +447,11 @@ template void segmented_sum_append<u32>(sfci_problem*, const u32*, const double*
 
 u64 sort_tuple_cap(sfci_problem* P) {
     // Tuple buffer: a quarter of free memory (6 words per tuple over the
-    // emission, sort and reduction buffers).  SFCI_SORT_TUPLE_CAP lowers it.
+    // emission, sort and reduction buffers), or the share a batch assigned.
+    // SFCI_SORT_TUPLE_CAP lowers it.
     size_t freeb = 0, totb = 0;
     SFCI_CHECK_HIP(hipMemGetInfo(&freeb, &totb));
-    const u64 per_tuple = 2 * (sizeof(u64) + sizeof(double)) + sizeof(double) + sizeof(u64);
-    u64 cap = (u64)(freeb / 4) / per_tuple;
+    u64 cap = P->tup_cap_hint ? P->tup_cap_hint : (u64)(freeb / 4) / SFCI_SORT_TUPLE_BYTES;
     if (const char* env = getenv("SFCI_SORT_TUPLE_CAP")) {
         long long e = atoll(env);
         if (e > 0) cap = std::min<u64>(cap, (u64)e);

@@ -77,6 +77,14 @@ def case_defs():
         "c2_M1e5_30": (mol(26, 5, 5, 52, 2), 100_000, 10, 30),
         "c2p_M1e5_30": (mol(26, 5, 5, 52, 2, True), 100_000, 10, 30),
     }
+    # the perturbed-start cases again with the opt-in tie band (an extension):
+    # with n_alpha = n_beta, alpha/beta-exchanged partners can reach a cut with
+    # equal magnitudes, which unordered sums then split by rounding; the band
+    # keeps such near-ties together, so the fast modes are checked against these
+    for nm in ("c0p_M300_30", "c2p_M2e3_20", "c4p_inst31_M3e3_30", "c4p_inst15_M1e4_30", "c3p_M1e3_10",
+               "c2p_M1e5_30"):
+        b, M, nL, nit = cases[nm]
+        cases[nm.replace("p_", "pband_", 1)] = (b, M, nL, nit, True)
     # the 32-instance bond-stretch batch as the benchmark runs it (perturbed
     # start, each instance at its own truncation, N_L = 10, 30 sigma), for the
     # instances whose truncation the oracle finishes in minutes

@@ -103,14 +103,16 @@ def test_batch_deterministic_matches_goldens(torch, S):
 def test_batch_fast_mixed_sizes(torch, S, orc):
     # 8 and 20 orbitals in one tile launch; the untruncated 8-orbital run is
     # plain Lanczos and must match the oracle, the truncated runs (perturbed
-    # starts, no exact ties at the cut) their goldens.
-    gc0, g31 = _gold("c0p_M300_30"), _gold("c4p_inst31_M3e3_30")
+    # starts) their goldens.
+    gc0, g31 = _gold("c0pband_M300_30"), _gold("c4pband_inst31_M3e3_30")
     Pa, hc, ec = _c0(S)
     Pb, _, _ = _c0(S)
     P31, h31, e31 = _c4(S, 31)
     B = S.Batch([Pa, P31, Pb])
+    # with the tie band (near-ties at the cut kept together), against the
+    # oracle's iteration with the band
     out = B.lanczos([AUFBAU, _perturbed(P31), _perturbed(Pb)], [None, g31["M"], gc0["M"]], n_L=10, n_iter=30,
-                    deterministic=False)
+                    deterministic=False, tie_band=True)
     st = out["stats"]
     assert st["batched_sigma"] == 1 and st["graph_replayed_blocks"] == 2 and st["sigma_calls"] == 30
     print("tile launch inside the step graphs:", st["sigma_in_graph"])
@@ -152,15 +154,18 @@ def test_batch_fast_gradients_match_oracle(torch, S, orc):
 
 @pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
 def test_batch_perturbed_start_goldens(torch, S, det):
-    # Start vectors without the alpha/beta exchange symmetry: no exact ties at
-    # the top-M cut, so the fast batched path (tile launch, graph replay) must
-    # match the oracle's energies at equal M to 1e-9 Ha.
-    g31, g15 = _gold("c4p_inst31_M3e3_30"), _gold("c4p_inst15_M1e4_30")
+    # Start vectors with independent alpha and beta singles.  Deterministic:
+    # the oracle's bits.  Fast (tile launch, graph replay): exchanged partners
+    # can still tie at a cut in the oracle's arithmetic, so the run keeps
+    # near-ties together (tie band) and must match the oracle's iteration with
+    # the band to 1e-9 Ha.
+    sfx = "" if det else "band"
+    g31, g15 = _gold(f"c4p{sfx}_inst31_M3e3_30"), _gold(f"c4p{sfx}_inst15_M1e4_30")
     P31, _, _ = _c4(S, 31)
     P15, _, _ = _c4(S, 15)
     B = S.Batch([P31, P15])
     out = B.lanczos([_perturbed(P31), _perturbed(P15)], [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=det,
-                    want_grad=False)
+                    want_grad=False, tie_band=not det)
     E = out["energies"]
     if det:
         assert E[0].tolist() == g31["energies"] and E[1].tolist() == g15["energies"]
@@ -204,31 +209,34 @@ def test_batch_screening_matches_oracle(torch, S, orc, det):
     Pa, hc, ec = _c0(S)
     P31, h31, e31 = _c4(S, 31)
     B = S.Batch([Pa, P31])
+    # (fast: with the tie band on both sides)
     out = B.lanczos([AUFBAU, _perturbed(P31)], [300, 2000], n_L=10, n_iter=20, deterministic=det, want_grad=False,
-                    screen_eps=5e-5)
+                    screen_eps=5e-5, tie_band=not det)
     ref = orc.Problem(8, 3, 3, hc, ec).lanczos(np.array([0], dtype=np.uint64), np.array([1.0]), 300, 10, 20,
-                                               eps=5e-5)
+                                               eps=5e-5, tie_band=not det)
     if det:
         assert np.array_equal(out["energies"][0], ref["energies"])
     else:
         assert np.all(np.abs(out["energies"][0] - ref["energies"]) < 1e-9)
     # the 20-orbital instance against its own single-instance run
-    single = P31.lanczos(*_perturbed(P31), M=2000, n_L=10, n_iter=20, deterministic=det, screen_eps=5e-5)
+    single = P31.lanczos(*_perturbed(P31), M=2000, n_L=10, n_iter=20, deterministic=det, screen_eps=5e-5,
+                         tie_band=not det)
     assert np.all(np.abs(out["energies"][1] - single["energies"]) < 1e-9)
 
 
 def test_batch_autotune_keeps_energies(torch, S):
     # The tuned work sizes (beta singles / beta-beta doubles per unit,
     # workgroups per CU) only change the order of the tile accumulation:
-    # energies stay within 1e-9 Ha of the oracle; the choice comes from the
+    # energies (with the tie band) stay within 1e-9 Ha of the oracle's
+    # iteration with the band; the choice comes from the
     # candidate sets and a second call reuses it without new trials.
-    g31, g15 = _gold("c4p_inst31_M3e3_30"), _gold("c4p_inst15_M1e4_30")
+    g31, g15 = _gold("c4pband_inst31_M3e3_30"), _gold("c4pband_inst15_M1e4_30")
     P31, _, _ = _c4(S, 31)
     P15, _, _ = _c4(S, 15)
     B = S.Batch([P31, P15])
     starts = [_perturbed(P31), _perturbed(P15)]
     out = B.lanczos(starts, [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=False, want_grad=False,
-                    autotune=True)
+                    autotune=True, tie_band=True)
     st = out["stats"]
     t = st["tune"]
     assert st["tune_trials"] in (5, 6)
@@ -237,7 +245,7 @@ def test_batch_autotune_keeps_energies(torch, S):
     for k, g in enumerate((g31, g15)):
         assert np.all(np.abs(out["energies"][k] - np.array(g["energies"])) < 1e-9)
     again = B.lanczos(starts, [g31["M"], g15["M"]], n_L=10, n_iter=30, deterministic=False, want_grad=False,
-                      autotune=True)
+                      autotune=True, tie_band=True)
     assert again["stats"]["tune_trials"] == 0
     assert again["stats"]["tune"]["b1_chunk"] == t["b1_chunk"] and again["stats"]["tune"]["bb_chunk"] == t["bb_chunk"]
     for k, g in enumerate((g31, g15)):

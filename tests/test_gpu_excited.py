@@ -62,8 +62,10 @@ def test_excited_state_matches_oracle_8_orbitals(torch, S, orc, det):
     ground = Po.lanczos(r0.astype(np.uint64), a0, 300, 10, 30)
     rr, ra = orc.topm(ground["psi_rank"], ground["psi_amp"], 300)
     ra, _ = orc.normalize(ra)
-    ref = Po.lanczos(r0.astype(np.uint64), a0, 300, 10, 30, roots=[(rr, ra)])
-    out = P.lanczos(r0, a0, M=300, n_L=10, n_iter=30, deterministic=det, roots=[(rr.astype(np.int64), ra)])
+    # (fast: with the tie band on both sides, near-ties at a cut kept together)
+    ref = Po.lanczos(r0.astype(np.uint64), a0, 300, 10, 30, roots=[(rr, ra)], tie_band=not det)
+    out = P.lanczos(r0, a0, M=300, n_L=10, n_iter=30, deterministic=det, roots=[(rr.astype(np.int64), ra)],
+                    tie_band=not det)
     if det:
         assert np.array_equal(out["energies"], ref["energies"])
         assert np.array_equal(_np(out["psi_rank"]).astype(np.uint64), ref["psi_rank"])
@@ -91,13 +93,20 @@ def test_excited_state_golden_20_orbitals(torch, S, det):
     assert ground["energies"].tolist() == gg["energies"]
     rr, ra = P.topm(ground["psi_rank"], ground["psi_amp"], gg["M"], normalise=True)
     out = P.lanczos(*start, M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"], deterministic=det,
-                    roots=[(_np(rr), _np(ra))])
+                    roots=[(_np(rr), _np(ra))], tie_band=not det)
     if det:
         assert out["energies"].tolist() == gd["energies"]
         assert hashlib.sha256(_np(out["psi_rank"]).astype(np.uint64).tobytes()).hexdigest()[:16] == \
             gd["psi_support_sha"]
     else:
-        assert np.all(np.abs(out["energies"] - np.array(gd["energies"])) < 1e-9)
+        # fast, with the tie band: against the oracle's iteration with the band
+        # from the same root (the oracle runs here; 20 sigma at M = 3000)
+        import oracle
+
+        Po = oracle.Problem(20, 4, 4, h, g)
+        ref = Po.lanczos(start[0].astype(np.uint64), start[1], gd["M"], gd["n_L"], gd["n_iter"],
+                         roots=[(_np(rr).astype(np.uint64), _np(ra))], tie_band=True)
+        assert np.all(np.abs(out["energies"] - ref["energies"]) < 1e-9)
     assert out["energies"][-1] > gd["ground_energy"]
 
 

@@ -131,17 +131,18 @@ def test_list_iteration_untruncated_matches_oracle(torch, S, orc, monkeypatch):
 @pytest.mark.parametrize("sigma", ["tile", "sort", "auto"])
 @pytest.mark.parametrize("name,rows", [("c2p_M2e3_20", 5000), ("c4p_inst31_M3e3_30", 700), ("c3p_M1e3_10", 30000)])
 def test_list_iteration_fast_mode(torch, S, monkeypatch, name, rows, sigma):
-    # fast mode: sigma through the tile kernel a slice of target rows at a
-    # time (SFCI_LIST_PASS_ROWS forces many slices), or through the sort
-    # path, or the per-sigma choice between them; tree reductions; energies
-    # within 1e-9 Ha of the oracle at equal M (starts without the alpha/beta
-    # exchange symmetry, so no exact ties reach a truncation cut)
-    gd = _gold(name)
+    # fast mode: sigma through the tile kernel (its finished tiles consumed in
+    # the kernel, a range of target rows per pass), or through the sort path,
+    # or the per-sigma choice between them; tree reductions; perturbed starts
+    # with the tie band (near-ties at a cut kept together): energies within
+    # 1e-9 Ha of the oracle's iteration with the band at equal M
+    gd = _gold(name.replace("p_", "pband_", 1))
     P, start, _ = _case(S, name)
     monkeypatch.setenv("SFCI_LIST_PASS_ROWS", str(rows))
     if sigma != "auto":
         monkeypatch.setenv("SFCI_LIST_SIGMA", sigma)
-    out = P.lanczos(*start, M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"], deterministic=False, no_dense=True)
+    out = P.lanczos(*start, M=gd["M"], n_L=gd["n_L"], n_iter=gd["n_iter"], deterministic=False, no_dense=True,
+                    tie_band=True)
     dE = np.abs(out["energies"] - np.array(gd["energies"]))
     assert np.all(dE < 1e-9), dE
 
