@@ -338,10 +338,10 @@ def main():
             "excited": excited,
             "parallelism": "single GPU",
         },
-        "roofline": {
+        "roofline": (tile_roofline(st, alg_bytes, None, sfci.roof_probe(1 << 30))
+                     if (not args.det and args.dedup == "dense") else {
             "bound": "hbm",
-            "kernel": ("k_rs_scatter" if args.det else
-                       "k_sigma_rowtile" if args.dedup == "dense" else "k_sigma_dense"),
+            "kernel": "k_rs_scatter" if args.det else "k_sigma_dense",
             "achieved": achieved / 1e9,
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
@@ -350,7 +350,7 @@ def main():
             "sigma_kernel_ms_per_launch": st["sigma_ms"] / max(1, st["sigma_calls"]),
             "alg_bytes_per_launch": alg_bytes / max(1, st["sigma_calls"]),
             "sigma_terms_per_s_kernel": terms / sig_s if sig_s > 0 else 0.0,
-        },
+        }),
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))

@@ -269,6 +269,32 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     }
     u64 my_terms = 0;
     u32 wterms = 0;  // terms counted per wavefront (ballot), folded into lane 0's my_terms
+    // sigma: an alpha double's entries in the tile, added by the calling
+    // thread (element constant); true when it took them (ranges of at most 32)
+    auto take_double = [&](const NbrRec& r, u32 tlo_, const RTParams& pp) -> bool {
+        if (r.e1 - r.e0 > 32) return false;
+        for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
+            u32 rb[RT_UNROLL];
+            double c[RT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RT_UNROLL; ++u) {
+                const u32 k = min(k0 + (u32)u, r.e1 - 1u);
+                rb[u] = pp.v_rb[k];
+                c[u] = pp.v_amp[k];
+            }
+#pragma unroll
+            for (int u = 0; u < RT_UNROLL; ++u) {
+                if (k0 + (u32)u >= r.e1) continue;
+                const double t = r.cst * c[u];
+                if (!xscreened(t, pp.eps_x)) {
+                    atomicAdd(&acc[rb[u] - tlo_], t);
+                    ++my_terms;
+                }
+            }
+        }
+        if (r.e1 > r.e0) s_touched = 1;  // terms landed (the item is not skipped)
+        return true;
+    };
 
     // The counter hands out target rows (item_prefix counts rows per
     // instance); a workgroup then takes the row's tiles one after another.
@@ -402,7 +428,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     const u32* tb = p.rtb + (u64)r.rAs;
                     r.e0 = tb[(u64)tile * p.sp.Na];
                     r.e1 = tb[(u64)(tile + 1) * p.sp.Na];
-                    if (r.type == 2 && r.e1 <= r.e0) r.type = 255;
+                    // an alpha double's few entries here are added at once (no list entry)
+                    if (r.type == 2 && (r.e1 <= r.e0 || take_double(r, (u32)tlo, p))) r.type = 255;
                 }
                 push(r, r.type != 255);
             }
@@ -474,6 +501,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         }
                         // (a gradient pass keeps zero elements: their derivative need not vanish)
                         if (r.e1 <= r.e0) r.type = 255;
+                        else if (!GRAD && r.type == 2 && take_double(r, (u32)tlo, p)) r.type = 255;
                     } else if (type == 1) {
                         if (!GRAD) {
                             double e = p.I.H(i, a);
@@ -528,7 +556,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         ph_add(timing, 0);
         const unsigned n1 = s_nlist, nlist = s_nlist + s_nlist2;
         auto rec = [&](unsigned li) -> const NbrRec& { return list[li < n1 ? li : nbr_cap - 1 - (li - n1)]; };
-        if (nlist == 0) continue;  // nothing lands here: D stays zero
+        if (nlist == 0 && !s_touched) continue;  // nothing lands here: D stays zero
         if (threadIdx.x == 0) s_touched = 1;
 
         // Phase 2: direct targets (beta unchanged).  Short ranges: one thread
@@ -564,12 +592,19 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     }
                 }
             }
-            for (;;) {
-                unsigned li = 0;
-                if (lane == 0) li = atomicAdd(&s_next2, 1u);
-                li = __shfl(li, 0);
-                if (li >= nlist) break;
-                const NbrRec r = rec(li);
+            // the next row's record is fetched while this one is worked on
+            auto fetch2 = [&]() -> unsigned {
+                unsigned v = 0;
+                if (lane == 0) v = atomicAdd(&s_next2, 1u);
+                return (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
+            };
+            unsigned li = fetch2();
+            NbrRec r_next;
+            if (li < nlist) r_next = rec(li);
+            while (li < nlist) {
+                const NbrRec r = r_next;
+                li = fetch2();
+                if (li < nlist) r_next = rec(li);
                 if (!by_wave(r)) continue;
                 const double* gq = nullptr;
                 if (r.type == 1) {
