@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--M", type=float, default=1e6)
     ap.add_argument("--n_L", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--dedup", default="dense", choices=["dense", "dense_atomic", "sort"],
                     help="dense: target-owned LDS tiles; dense_atomic: one FP64 atomic per term")
     ap.add_argument("--no-autotune", action="store_true",
