@@ -592,50 +592,101 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     }
                 }
             }
-            // the next row's record is fetched while this one is worked on
-            auto fetch2 = [&]() -> unsigned {
-                unsigned v = 0;
-                if (lane == 0) v = atomicAdd(&s_next2, 1u);
-                return (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
-            };
-            unsigned li = fetch2();
-            NbrRec r_next;
-            if (li < nlist) r_next = rec(li);
-            while (li < nlist) {
-                const NbrRec r = r_next;
-                li = fetch2();
-                if (li < nlist) r_next = rec(li);
-                if (!by_wave(r)) continue;
-                const double* gq = nullptr;
-                if (r.type == 1) {
-                    // this row's (ia|qq), q = 0..n-1
-                    wave_sync();
-                    if (lane < n) wo[lane] = p.I.G(r.i, r.a, lane, lane);
-                    wave_sync();
-                    gq = wo;
+            // Long rows by wavefront, DB records at a time.  The alpha doubles
+            // (constant element) of a batch are one stream of entries: lanes over
+            // their concatenated entry ranges, RT_UNROLL groups of 64 loads in
+            // flight across row boundaries.  The other long rows (the diagonal's,
+            // alpha singles') one at a time, alpha singles with (ia|qq) staged.
+            constexpr int DB = 8;
+            for (;;) {
+                unsigned base = 0;
+                if (lane == 0) base = atomicAdd(&s_next2, (unsigned)DB);
+                base = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)base, 0));
+                if (base >= nlist) break;
+                u32 d_e0 = 0, d_len = 0;
+                double d_cst = 0.0;
+                bool other = false;
+                if (lane < DB && base + (unsigned)lane < nlist) {
+                    const NbrRec r = rec(base + (unsigned)lane);
+                    if (by_wave(r)) {
+                        if (r.type == 2) {
+                            d_e0 = r.e0;
+                            d_len = r.e1 - r.e0;
+                            d_cst = r.cst;
+                        } else {
+                            other = true;
+                        }
+                    }
                 }
-                // RT_UNROLL chunks of 64 entries at a time, their loads in flight together
-                for (u32 k0 = r.e0; k0 < r.e1; k0 += 64 * RT_UNROLL) {
-                    u32 rb[RT_UNROLL], bt[RT_UNROLL];
-                    double c[RT_UNROLL];
+                for (u64 om = __ballot(other); om; om &= om - 1) {
+                    const unsigned j = (unsigned)(__ffsll((long long)om) - 1);
+                    const NbrRec r = rec(base + j);
+                    const double* gq = nullptr;
+                    if (r.type == 1) {
+                        // this row's (ia|qq), q = 0..n-1
+                        wave_sync();
+                        if (lane < n) wo[lane] = p.I.G(r.i, r.a, lane, lane);
+                        wave_sync();
+                        gq = wo;
+                    }
+                    // RT_UNROLL chunks of 64 entries at a time, their loads in flight together
+                    for (u32 k0 = r.e0; k0 < r.e1; k0 += 64 * RT_UNROLL) {
+                        u32 rb[RT_UNROLL], bt[RT_UNROLL];
+                        double c[RT_UNROLL];
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            const u32 k = k0 + (u32)u * 64 + lane;
+                            rb[u] = 0;
+                            bt[u] = 0;
+                            c[u] = 0.0;
+                            if (k < r.e1) {
+                                rb[u] = p.v_rb[k];
+                                c[u] = p.v_amp[k];
+                                bt[u] = p.v_beta[k];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < RT_UNROLL; ++u) {
+                            if (k0 + (u32)u * 64 + lane >= r.e1) continue;
+                            const double e = direct_element(p, r, bt[u], itab, gq);
+                            const double t = e * c[u];
+                            if (e != 0.0) {
+                                atomicAdd(&acc[rb[u] - tlo], t);
+                                ++my_terms;
+                            }
+                        }
+                    }
+                }
+                // exclusive prefix of the alpha doubles' lengths over lanes 0..DB-1
+                u32 pfx = 0, total = 0;
+                for (int j = 0; j < DB; ++j) {
+                    const u32 lj = rl32(d_len, j);
+                    if (lane == j) pfx = total;
+                    total += lj;
+                }
+                for (u32 q0 = 0; q0 < total; q0 += 64 * RT_UNROLL) {
+                    u32 rb[RT_UNROLL];
+                    double c[RT_UNROLL], e[RT_UNROLL];
 #pragma unroll
                     for (int u = 0; u < RT_UNROLL; ++u) {
-                        const u32 k = k0 + (u32)u * 64 + lane;
+                        const u32 q = q0 + (u32)u * 64 + lane;
+                        // the row of stream position q: the last of the batch starting at or before it
+                        int j = 0;
+                        for (int jj = 1; jj < DB; ++jj) j += (rl32(pfx, jj) <= q) ? 1 : 0;
+                        const u32 k = (u32)__shfl((int)d_e0, j) + (q - (u32)__shfl((int)pfx, j));
+                        e[u] = __shfl(d_cst, j);
                         rb[u] = 0;
-                        bt[u] = 0;
                         c[u] = 0.0;
-                        if (k < r.e1) {
+                        if (q < total) {
                             rb[u] = p.v_rb[k];
                             c[u] = p.v_amp[k];
-                            if (r.type != 2) bt[u] = p.v_beta[k];
                         }
                     }
 #pragma unroll
                     for (int u = 0; u < RT_UNROLL; ++u) {
-                        if (k0 + (u32)u * 64 + lane >= r.e1) continue;
-                        const double e = (r.type == 2) ? r.cst : direct_element(p, r, bt[u], itab, gq);
-                        const double t = e * c[u];
-                        if (e != 0.0 && !(r.type == 2 && xscreened(t, p.eps_x))) {
+                        if (q0 + (u32)u * 64 + lane >= total) continue;
+                        const double t = e[u] * c[u];
+                        if (!xscreened(t, p.eps_x)) {
                             atomicAdd(&acc[rb[u] - tlo], t);
                             ++my_terms;
                         }
