@@ -369,8 +369,12 @@ def bench_batch(args, torch, sfci, synth):
     v0 = (r0[order], a0[order])
     B = sfci.Batch(probs)
     if args.warmup:
+        # The warm-up call has the timed call's shape (at least as many
+        # iterations as the warm-up asks for): it tunes the tile kernel's work
+        # sizes and captures the step graphs, both kept by the batch for the
+        # timed call.
+        args.warmup = max(args.warmup, args.steps)
         print(f"# warm-up: {args.warmup} batched iterations + gradients", file=sys.stderr, flush=True)
-        # the warm-up also tunes the tile kernel's work sizes (kept by the batch)
         wout = B.lanczos([v0] * len(probs), Ms, n_L=args.n_L, n_iter=args.warmup, autotune=not args.no_autotune)
         tune = wout["stats"]["tune"]
         print(f"# tuned work sizes: {tune}", file=sys.stderr, flush=True)
@@ -381,7 +385,8 @@ def bench_batch(args, torch, sfci, synth):
     wall = time.perf_counter() - t0
     st = out["stats"]
     E = out["energies"]
-    print(f"# batched: {wall:.3f} s (fwd {st['fwd_ms']:.0f} ms, bwd {st['bwd_ms']:.0f} ms, sigma {st['sigma_ms']:.0f} ms)",
+    print(f"# batched: {wall:.3f} s (fwd {st['fwd_ms']:.0f} ms, bwd {st['bwd_ms']:.0f} ms, sigma {st['sigma_ms']:.0f} ms; "
+          f"step graphs {'kept from the warm-up' if st['graphs_reused'] else 'captured in this call'})",
           file=sys.stderr, flush=True)
     plain = None
     sample = None
@@ -447,6 +452,7 @@ def bench_batch(args, torch, sfci, synth):
             "terms_emitted": terms,
             "psi_nnz_total": st["psi_nnz_total"],
             "graph_replayed_blocks": st["graph_replayed_blocks"],
+            "graphs_reused": st["graphs_reused"],
             "tile_work_sizes": st["tune"],
             "final_energies": [float(x) for x in E[:, -1]],
             "plain_path": plain,

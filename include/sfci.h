@@ -252,7 +252,10 @@ sfci_status sfci_energy_gradients(sfci_problem* prob, const sfci_svec* psi, int3
  * each sigma application of all instances is one launch of the target-owned
  * tile kernel, and after one eager block every iteration step (its
  * preparation, the tile launch and the vector operations) is replayed from
- * one captured hipGraph.  All problems must share one device and stream. */
+ * one captured hipGraph.  The batch keeps those graphs: a later call with the
+ * same truncations, options and start-vector sizes, made while no library
+ * buffer has been freed or regrown in between, replays them from its first
+ * block on.  All problems must share one device and stream. */
 typedef struct sfci_batch sfci_batch;
 
 typedef struct {
@@ -273,7 +276,7 @@ typedef struct {
     double tune_default_ms;     /* trial time of the default sizes and of the chosen ones (when tuned) */
     double tune_best_ms;
     int32_t sigma_in_graph;     /* 1: each replayed step was one graph, the tile launch inside it */
-    int32_t reserved;
+    int32_t graphs_reused;      /* 1: the step graphs came from an earlier call, every block replayed */
 } sfci_batch_stats;
 
 /* probs: n_inst problem handles (kept, not owned). */

@@ -1,6 +1,7 @@
 // C ABI of libsfci: problem lifecycle, sigma, truncation and the SFCI
 // iteration driver (Sec. 2.1).  All device work goes to the problem's stream.
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <limits>
@@ -17,10 +18,17 @@ int sfci_set_error(int code, const std::string& msg) {
     return code;
 }
 
+static std::atomic<u64> g_free_epoch{0};
+
+u64 device_free_epoch() { return g_free_epoch.load(); }
+
+void note_device_free() { g_free_epoch.fetch_add(1); }
+
 void DevBuf::release() {
     if (p) {
         (void)hipDeviceSynchronize();
         (void)hipFree(p);
+        note_device_free();
     }
     p = nullptr;
     bytes = 0;
@@ -235,6 +243,7 @@ sfci_status sfci_problem_create(const sfci_space* sp, const double* h, const dou
 sfci_status sfci_problem_destroy(sfci_problem* P) {
     if (!P) return SFCI_OK;
     (void)hipStreamSynchronize(P->stream);
+    note_device_free();
     if (P->swapped) sfci_problem_destroy(P->swapped);
     if (!P->borrowed) {
         if (P->d_h) (void)hipFree(P->d_h);

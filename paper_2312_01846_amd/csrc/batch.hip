@@ -5,7 +5,9 @@
 // gathers, Eq. 10, truncation, Eq. 11) is issued per instance on the shared
 // stream.  After one eager block has sized and allocated every buffer, each
 // iteration step (preparation, the tile launch, the vector operations) and
-// the block end are captured into hipGraphs and replayed.
+// the block end are captured into hipGraphs and replayed; the batch keeps
+// them, and a later call with the same signature (instances, buffers,
+// truncations, options, work sizes) replays them from its first block on.
 // After the last block each instance's gradient of E = <Psi|H|Psi>/<Psi|Psi>
 // with respect to h and (pq|rs) is computed at fixed Psi.
 #include <algorithm>
@@ -31,6 +33,26 @@ struct sfci_batch {
     // work sizes of the sigma tile launches (chosen by autotuning, kept across calls)
     RowTileTune tune;
     bool tuned = false;
+    // Step graphs (one per iteration step) and the block-end graph, kept for
+    // later calls.  A call whose instances, buffers, truncations, options and
+    // work sizes (gsig) equal those of the capture, with no library buffer
+    // freed since (gepoch), replays them from its first block on.
+    std::vector<hipGraphExec_t> gstep;
+    hipGraphExec_t gend = nullptr;
+    std::vector<hipEvent_t> gev;  // recorded by event nodes inside the step graphs: [2j], [2j+1] around step j's sigma
+    std::vector<u64> gsig;
+    u64 gepoch = 0;
+    void drop_graphs() {
+        if (own) (void)hipStreamSynchronize(own);
+        for (auto x : gstep) (void)hipGraphExecDestroy(x);
+        gstep.clear();
+        if (gend) (void)hipGraphExecDestroy(gend);
+        gend = nullptr;
+        for (auto e : gev)
+            if (e) (void)hipEventDestroy(e);
+        gev.clear();
+        gsig.clear();
+    }
 };
 
 namespace {
@@ -106,6 +128,7 @@ sfci_status sfci_batch_create(int32_t n_inst, sfci_problem* const* probs, sfci_b
 sfci_status sfci_batch_destroy(sfci_batch* B) {
     if (!B) return SFCI_OK;
     (void)hipStreamSynchronize(B->stream);
+    B->drop_graphs();
     for (auto& d : B->descs) d.release();
     B->prefix.release();
     B->counter.release();
@@ -220,6 +243,39 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     const bool autotune = o->autotune != 0 && batched_sigma;
     int tune_trials = 0;
     double tune_default_ms = 0.0, tune_best_ms = 0.0;
+    // The gradient pass's buffers at their full size before any graph is
+    // captured: growing one later would free memory the graphs use.
+    if (!det && (dh_all || deri_all))
+        for (const Inst& q : I) {
+            const u64 n2 = (u64)q.P->n * q.P->n;
+            const u64 pcap = std::min<u64>(q.P->Ndet, (u64)nL * q.cap);
+            (void)q.P->ws_red.get((2048 + n2 + n2 * n2) * sizeof(double));
+            (void)q.P->ws_list_r.get(pcap * sizeof(u64));
+            (void)q.P->ws_list_a.get(pcap * sizeof(double));
+            // rowtile_prepare's per-entry words (two u32 per input entry), for Psi
+            if (rowtile_available(q.P)) (void)q.P->ws_rt_beta.get(2 * std::max<u64>(1, pcap) * sizeof(u32));
+        }
+    // What the step graphs depend on besides device data: kept graphs serve
+    // a later call only when its signature is the same.
+    auto signature = [&] {
+        std::vector<u64> g;
+        auto bits = [](double d) {
+            u64 b;
+            std::memcpy(&b, &d, sizeof b);
+            return b;
+        };
+        auto ptr = [](const void* p) { return (u64)(uintptr_t)p; };
+        g.insert(g.end(), {(u64)n, (u64)nL, (u64)o->dedup, (u64)(o->tie_band != 0), bits(o->screen_eps),
+                           bits(o->excite_eps), (u64)batched_sigma, B->tune.b1_chunk, B->tune.bb_chunk,
+                           B->tune.per_cu});
+        for (const Inst& q : I)
+            g.insert(g.end(), {ptr(q.P), q.M, q.cap, ptr(q.Wr), ptr(q.Wa), ptr(q.sc), ptr(q.T), ptr(q.psi_r),
+                               ptr(q.psi_a), ptr(q.P->d_D)});
+        return g;
+    };
+    const bool graphs_reused = use_graph && !B->gstep.empty() && (!autotune || B->tuned) &&
+                               B->gepoch == device_free_epoch() && B->gsig == signature();
+    if (!graphs_reused) B->drop_graphs();
 
     // One sigma application for every instance, in two parts: the per-instance
     // preparation (row pointers, tile offsets, input-size bookkeeping) and the
@@ -408,10 +464,10 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         });
     };
 
-    // events: whole run, gradients, one pair around every eager sigma launch,
-    // and one pair per iteration step recorded from inside the step graphs
+    // events: whole run, gradients, and one pair around every eager sigma
+    // launch; the pairs recorded inside the step graphs are the batch's (gev)
     const int n_sig = nblk * nL;
-    std::vector<hipEvent_t> ev(3 + 2 * (size_t)n_sig + 2 * (size_t)nL, nullptr);
+    std::vector<hipEvent_t> ev(3 + 2 * (size_t)n_sig, nullptr);
     struct EvFree {
         std::vector<hipEvent_t>& v;
         ~EvFree() {
@@ -421,23 +477,28 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     } ev_free{ev};
     for (auto& e : ev) SFCI_CHECK_HIP(hipEventCreate(&e));
     hipEvent_t e0 = ev[0], e1 = ev[1], e2 = ev[2];
-    hipEvent_t* gev = ev.data() + 3 + 2 * (size_t)n_sig;  // [2j], [2j+1]: step j inside its graph
-    // replayed steps: one graph per step (gstep), or, where the runtime
-    // refuses event-record nodes in a graph, the preparation and the rest of
-    // the step as two graphs with the tile launch between them (gprep, grest)
-    std::vector<hipGraphExec_t> gstep, gprep, grest;
-    hipGraphExec_t gend = nullptr;
+    // replayed steps: one graph per step (B->gstep, kept for later calls), or,
+    // where the runtime refuses event-record nodes in a graph, the
+    // preparation and the rest of the step as two graphs with the tile launch
+    // between them (gprep, grest: this call only)
+    std::vector<hipGraphExec_t> gprep, grest;
     struct GraphFree {
         std::vector<hipGraphExec_t>& a;
         std::vector<hipGraphExec_t>& b;
-        std::vector<hipGraphExec_t>& c;
-        hipGraphExec_t& d;
         ~GraphFree() {
-            for (auto* v : {&a, &b, &c})
+            for (auto* v : {&a, &b})
                 for (auto x : *v) (void)hipGraphExecDestroy(x);
-            if (d) (void)hipGraphExecDestroy(d);
         }
-    } graph_free{gstep, gprep, grest, gend};
+    } graph_free{gprep, grest};
+    // kept graphs are dropped unless this call ends with them intact
+    struct KeepGuard {
+        sfci_batch* B;
+        bool keep = false;
+        ~KeepGuard() {
+            if (!keep) B->drop_graphs();
+        }
+    } keep_guard{B};
+    std::vector<hipGraphExec_t>& gstep = B->gstep;
     bool split_steps = false;
     auto capture_graph = [&](auto&& body) {
         hipGraph_t g;
@@ -465,9 +526,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         hipError_t e = hipGraphCreate(&g, 0);
         hipGraphNode_t nA, e1, nB, e2, nC;
         if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nA, g, nullptr, 0, gA);
-        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, g, &nA, 1, gev[2 * j]);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, g, &nA, 1, B->gev[2 * j]);
         if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nB, g, &e1, 1, gB);
-        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e2, g, &nB, 1, gev[2 * j + 1]);
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e2, g, &nB, 1, B->gev[2 * j + 1]);
         if (e == hipSuccess) e = hipGraphAddChildGraphNode(&nC, g, &e2, 1, gC);
         (void)hipGraphDestroy(gA);  // the child nodes hold their own copies
         (void)hipGraphDestroy(gB);
@@ -480,26 +541,37 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         return instantiate(g);
     };
     double sigma_ms = 0.0;
+    int replayed_blocks = 0;
     SFCI_CHECK_HIP(hipEventRecord(e0, st));
     int sig = 0;
     for (int b = 0; b < nblk; ++b) {
         const bool last = (b + 1 == nblk);
-        const bool replay = use_graph && b >= 1;
-        if (replay && gstep.empty()) {
+        const bool replay = use_graph && (b >= 1 || graphs_reused);
+        if (replay && gstep.empty() && !split_steps) {
             // one graph per iteration step (step_graph) and one for the
             // (non-final) block end
+            B->gev.assign(2 * (size_t)nL, nullptr);
+            for (auto& e : B->gev) SFCI_CHECK_HIP(hipEventCreate(&e));
             for (int j = 0; j < nL && !split_steps; ++j) {
                 hipGraphExec_t x = step_graph(j);
                 if (x) gstep.push_back(x);
                 else split_steps = true;
             }
-            if (split_steps)
+            if (split_steps) {
+                for (auto x : gstep) (void)hipGraphExecDestroy(x);
+                gstep.clear();
                 for (int j = 0; j < nL; ++j) {
                     gprep.push_back(capture([&] { sigma_prepare(j, false); }));
                     grest.push_back(capture([&] { iteration_rest(j); }));
                 }
-            gend = capture([&] { block_end(false); });
+            }
+            B->gend = capture([&] { block_end(false); });
+            if (!split_steps) {
+                B->gsig = signature();
+                B->gepoch = device_free_epoch();
+            }
         }
+        if (replay) ++replayed_blocks;
         for (int j = 0; j < nL; ++j, ++sig) {
             if (replay && !split_steps) {
                 SFCI_CHECK_HIP(hipGraphLaunch(gstep[j], st));
@@ -507,9 +579,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             }
             if (replay) {
                 SFCI_CHECK_HIP(hipGraphLaunch(gprep[j], st));
-                SFCI_CHECK_HIP(hipEventRecord(gev[2 * j], st));
+                SFCI_CHECK_HIP(hipEventRecord(B->gev[2 * j], st));
                 sigma_launch(j);
-                SFCI_CHECK_HIP(hipEventRecord(gev[2 * j + 1], st));
+                SFCI_CHECK_HIP(hipEventRecord(B->gev[2 * j + 1], st));
                 SFCI_CHECK_HIP(hipGraphLaunch(grest[j], st));
                 continue;
             }
@@ -523,13 +595,13 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         if (replay) {
             // the step graphs' events hold this block's sigma times until the next replay
             for (int j = 0; j < nL; ++j) {
-                SFCI_CHECK_HIP(hipEventSynchronize(gev[2 * j + 1]));
+                SFCI_CHECK_HIP(hipEventSynchronize(B->gev[2 * j + 1]));
                 float ms = 0.f;
-                SFCI_CHECK_HIP(hipEventElapsedTime(&ms, gev[2 * j], gev[2 * j + 1]));
+                SFCI_CHECK_HIP(hipEventElapsedTime(&ms, B->gev[2 * j], B->gev[2 * j + 1]));
                 sigma_ms += ms;
             }
         }
-        if (replay && !last) SFCI_CHECK_HIP(hipGraphLaunch(gend, st));
+        if (replay && !last) SFCI_CHECK_HIP(hipGraphLaunch(B->gend, st));
         else block_end(last);
     }
     SFCI_CHECK_HIP(hipEventRecord(e1, st));
@@ -587,6 +659,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         SFCI_CHECK_HIP(hipMemcpyAsync(&hsc[(size_t)k * 64], I[k].sc, 64 * sizeof(u64), hipMemcpyDeviceToHost, st));
     }
     SFCI_CHECK_HIP(hipStreamSynchronize(st));
+    // the step graphs stay for later calls while every buffer they use is alive
+    keep_guard.keep = !split_steps && !gstep.empty() && B->gepoch == device_free_epoch();
     if (stats) {
         float f = 0.f, bw = 0.f;
         SFCI_CHECK_HIP(hipEventElapsedTime(&f, e0, e1));
@@ -595,7 +669,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         stats->bwd_ms = bw;
         double sms = sigma_ms;
         for (int i = 0; i < n_sig; ++i) {
-            if (use_graph && i >= nL) break;  // replayed steps: counted from the graphs' events above
+            if (i >= (nblk - replayed_blocks) * nL) break;  // replayed steps: counted from the graphs' events above
             float ms = 0.f;
             SFCI_CHECK_HIP(hipEventElapsedTime(&ms, ev[3 + 2 * i], ev[4 + 2 * i]));
             sms += ms;
@@ -611,7 +685,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         stats->nnz_in_total = nin;
         stats->sigma_calls = (u64)n_sig;
         stats->psi_nnz_total = psi_total;
-        stats->graph_replayed_blocks = use_graph ? std::max(0, nblk - 1) : 0;
+        stats->graph_replayed_blocks = replayed_blocks;
         stats->batched_sigma = batched_sigma ? 1 : 0;
         stats->tune_trials = tune_trials;
         stats->tune_b1_chunk = batched_sigma ? B->tune.b1_chunk : 0u;
@@ -619,8 +693,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         stats->tune_per_cu = batched_sigma ? B->tune.per_cu : 0u;
         stats->tune_default_ms = tune_default_ms;
         stats->tune_best_ms = tune_best_ms;
-        stats->sigma_in_graph = (use_graph && nblk > 1 && !split_steps) ? 1 : 0;
-        stats->reserved = 0;
+        stats->sigma_in_graph = (replayed_blocks > 0 && !split_steps) ? 1 : 0;
+        stats->graphs_reused = graphs_reused ? 1 : 0;
     }
     for (int k = 0; k < n; ++k)
         if (hstat[k]) return (sfci_status)sfci_set_error(SFCI_E_DEVICE, "generalized eigenproblem failed");

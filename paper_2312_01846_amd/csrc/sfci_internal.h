@@ -30,6 +30,13 @@ struct DevBuf {
     void release();
 };
 
+// Counter of frees of library-owned device memory (workspaces, tables,
+// problem arrays), process-wide.  A captured graph stays launchable only
+// while the counter is unchanged since its capture: every buffer it points
+// to is then still allocated.
+u64 device_free_epoch();
+void note_device_free();
+
 // Launch buffers of the gradient passes through the target-owned tiles.
 struct RowTileGradWs {
     DevBuf desc, prefix, counter, scratch;

@@ -70,7 +70,7 @@ class BatchStats(C.Structure):
                 ("graph_replayed_blocks", C.c_int32), ("batched_sigma", C.c_int32), ("tune_trials", C.c_int32),
                 ("tune_b1_chunk", C.c_uint32), ("tune_bb_chunk", C.c_uint32), ("tune_per_cu", C.c_uint32),
                 ("tune_default_ms", C.c_double), ("tune_best_ms", C.c_double), ("sigma_in_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("graphs_reused", C.c_int32)]
 
 
 class Roof(C.Structure):
@@ -401,7 +401,7 @@ class Batch:
                               sigma_calls=st.sigma_calls,
                               psi_nnz_total=st.psi_nnz_total, graph_replayed_blocks=st.graph_replayed_blocks,
                               batched_sigma=st.batched_sigma, tune_trials=st.tune_trials,
-                              sigma_in_graph=st.sigma_in_graph,
+                              sigma_in_graph=st.sigma_in_graph, graphs_reused=st.graphs_reused,
                               tune=dict(b1_chunk=st.tune_b1_chunk, bb_chunk=st.tune_bb_chunk,
                                         per_cu=st.tune_per_cu, default_ms=st.tune_default_ms,
                                         best_ms=st.tune_best_ms)))

@@ -192,6 +192,52 @@ def test_batch_repeat_and_shrink(torch, S):
     assert np.array_equal(second["energies"][1], single["energies"])
 
 
+def test_batch_kept_graphs(torch, S):
+    # The step graphs captured by one call serve the next call of the same
+    # shape from its first block on; a changed truncation, or a library
+    # buffer freed in between, makes the call capture anew.  Every call's
+    # energies stay within 1e-9 Ha of the oracle's iteration with the band,
+    # and the gradients of a replayed call match those of the capturing call.
+    g31, g15 = _gold("c4pband_inst31_M3e3_30"), _gold("c4pband_inst15_M1e4_30")
+    P31, _, _ = _c4(S, 31)
+    P15, _, _ = _c4(S, 15)
+    B = S.Batch([P31, P15])
+    starts = [_perturbed(P31), _perturbed(P15)]
+    Ms = [g31["M"], g15["M"]]
+
+    def run(ms):
+        return B.lanczos(starts, ms, n_L=10, n_iter=30, deterministic=False, tie_band=True)
+
+    def check(out):
+        for k, g in enumerate((g31, g15)):
+            assert np.all(np.abs(out["energies"][k] - np.array(g["energies"])) < 1e-9)
+
+    first = run(Ms)
+    assert first["stats"]["graphs_reused"] == 0 and first["stats"]["graph_replayed_blocks"] == 2
+    check(first)
+    again = run(Ms)
+    st = again["stats"]
+    assert st["graphs_reused"] == 1 and st["graph_replayed_blocks"] == 3 and st["sigma_in_graph"] == 1
+    assert 0 < st["sigma_ms"] < st["fwd_ms"]
+    check(again)
+    for k in range(2):
+        for key in ("dh", "dg"):
+            ref = _np(first[key][k])
+            assert np.abs(_np(again[key][k]) - ref).max() <= 1e-9 * max(1.0, float(np.abs(ref).max()))
+    # another truncation: new graphs, then kept for the same shape
+    other = run([g31["M"], 5000])
+    assert other["stats"]["graphs_reused"] == 0
+    check_other = run([g31["M"], 5000])
+    assert check_other["stats"]["graphs_reused"] == 1
+    assert np.abs(check_other["energies"] - other["energies"]).max() < 1e-9
+    # a library buffer freed between calls (another problem destroyed)
+    Q, _, _ = _c0(S)
+    Q.close()
+    after = run(Ms)
+    assert after["stats"]["graphs_reused"] == 0
+    check(after)
+
+
 def test_batch_rejects_bad_arguments(torch, S):
     P, _, _ = _c0(S)
     with pytest.raises(S.SfciError):
