@@ -126,8 +126,15 @@ __global__ __launch_bounds__(256) void k_sel_min(Src src, SelState* __restrict__
         src.get(i, r, c);
         if (sel_pred(s, g, r, c)) m = min(m, abs_bits(c));
     }
+    // one atomic per workgroup: wavefront minima, then the workgroup's
+    __shared__ u64 wmin[4];
     for (int off = 32; off >= 1; off >>= 1) m = min(m, (u64)__shfl_xor((long long)m, off));
-    if ((threadIdx.x & 63) == 0 && m != ~0ull) atomicMin((unsigned long long*)&st->cmin, (unsigned long long)m);
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = min(m, wmin[w]);
+        if (m != ~0ull) atomicMin((unsigned long long*)&st->cmin, (unsigned long long)m);
+    }
 }
 
 // ... the threshold cmin * (1 - 2^-36) ...
@@ -150,8 +157,14 @@ __global__ __launch_bounds__(256) void k_sel_count_thr(Src src, SelState* __rest
         src.get(i, r, c);
         c_ += (c != 0.0 && abs_bits(c) >= thr) ? 1ull : 0ull;
     }
+    __shared__ unsigned long long wsum[4];
     for (int off = 32; off >= 1; off >>= 1) c_ += (unsigned long long)__shfl_xor((long long)c_, off);
-    if ((threadIdx.x & 63) == 0 && c_) atomicAdd((unsigned long long*)&st->count_thr, c_);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c_;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) c_ += wsum[w];
+        if (c_) atomicAdd((unsigned long long*)&st->count_thr, c_);
+    }
 }
 
 // ... and whether they are kept (at most SFCI_TIE_SLACK beyond M).
@@ -196,7 +209,6 @@ __global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict_
 constexpr int PICK_T = 256;
 constexpr int PICK_PER = NBIN / PICK_T;
 __global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L, u64 M) {
-    __shared__ u64 part[PICK_T];
     __shared__ int s_d;
     __shared__ u64 s_acc;
     const int t = threadIdx.x;
@@ -217,15 +229,23 @@ __global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L,
         h[k] = st->hist[t * PICK_PER + k];
         mine += h[k];
     }
-    part[t] = mine;
     if (t == 0) {
         s_d = 0;
         s_acc = 0;
     }
+    // exclusive suffix sum over threads (bins above this thread's block):
+    // suffix scan within the wavefront, then the totals of later wavefronts
+    __shared__ u64 wtot[PICK_T / 64];
+    const int lane = t & 63;
+    u64 suf = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const u64 y = (u64)__shfl_down((long long)suf, off);
+        if (lane + off < 64) suf += y;
+    }
+    if (lane == 0) wtot[t >> 6] = suf;
     __syncthreads();
-    // exclusive suffix sum over threads (bins above this thread's block)
-    u64 above = 0;
-    for (int u = t + 1; u < PICK_T; ++u) above += part[u];
+    u64 above = suf - mine;
+    for (int w = (t >> 6) + 1; w < PICK_T / 64; ++w) above += wtot[w];
     u64 incl = above;  // entries in bins > current bin
     for (int k = PICK_PER - 1; k >= 0; --k) {
         const int b = t * PICK_PER + k;
@@ -242,7 +262,7 @@ __global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L,
     if (d == 0) {
         // no bin >= 1 reaches `need`: the digit is 0, with everything above it taken
         acc = 0;
-        for (int u = 0; u < PICK_T; ++u) acc += part[u];
+        for (int w = 0; w < PICK_T / 64; ++w) acc += wtot[w];
         acc -= st->hist[0];
     }
     const u64 hd = st->hist[d];

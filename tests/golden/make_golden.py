@@ -73,8 +73,8 @@ def case_defs():
         # 12 electrons in 28 orbitals (1.42e11 determinants): the list iteration's shape
         "c3_M1e3_10": (mol(28, 6, 6, 56, 3), 1_000, 5, 10),
         "c3p_M1e3_10": (mol(28, 6, 6, 56, 3, True), 1_000, 5, 10),
-        "c3_M1e5_10": (mol(28, 6, 6, 56, 3), 100_000, 5, 10),
-        "c3p_M1e5_10": (mol(28, 6, 6, 56, 3, True), 100_000, 5, 10),
+        "c3_M1e4_10": (mol(28, 6, 6, 56, 3), 10_000, 5, 10),
+        "c3p_M1e4_10": (mol(28, 6, 6, 56, 3, True), 10_000, 5, 10),
         # 10 electrons in 26 orbitals at the dense workload's smallest truncation
         "c2_M1e5_30": (mol(26, 5, 5, 52, 2), 100_000, 10, 30),
         "c2p_M1e5_30": (mol(26, 5, 5, 52, 2, True), 100_000, 10, 30),
@@ -84,7 +84,7 @@ def case_defs():
     # equal magnitudes, which unordered sums then split by rounding; the band
     # keeps such near-ties together, so the fast modes are checked against these
     for nm in ("c0p_M300_30", "c2p_M2e3_20", "c4p_inst31_M3e3_30", "c4p_inst15_M1e4_30", "c3p_M1e3_10",
-               "c2p_M1e5_30", "c3p_M1e5_10"):
+               "c2p_M1e5_30", "c3p_M1e4_10"):
         b, M, nL, nit = cases[nm]
         cases[nm.replace("p_", "pband_", 1)] = (b, M, nL, nit, True)
     # the 32-instance bond-stretch batch as the benchmark runs it (perturbed

@@ -208,14 +208,14 @@ def test_row_emission_equals_source_emission(torch, S, monkeypatch, case):
 
 
 @pytest.mark.parametrize("mode", ["deterministic", "fast_band", "fast"])
-def test_28_orbitals_M1e5_goldens(torch, S, monkeypatch, mode):
-    # 12 electrons in 28 orbitals at M = 1e5, two blocks of N_L = 5 (2.5e9
+def test_28_orbitals_M1e4_goldens(torch, S, monkeypatch, mode):
+    # 12 electrons in 28 orbitals at M = 1e4, two blocks of N_L = 5 (2.5e8
     # terms per sigma): deterministic from the aufbau determinant bit for bit
     # against the oracle; fast (the tile kernel forced, finished tiles
     # consumed in the kernel) from the perturbed start with the tie band within
     # 1e-9 Ha of the oracle's iteration with the band, and under the paper's
     # rule reported against the oracle (ties at a cut may split differently)
-    name = {"deterministic": "c3_M1e5_10", "fast_band": "c3pband_M1e5_10", "fast": "c3p_M1e5_10"}[mode]
+    name = {"deterministic": "c3_M1e4_10", "fast_band": "c3pband_M1e4_10", "fast": "c3p_M1e4_10"}[mode]
     gd = _gold(name)
     P, start, tup_cap = _case(S, name)
     monkeypatch.setenv("SFCI_SORT_TUPLE_CAP", str(tup_cap))
@@ -230,5 +230,5 @@ def test_28_orbitals_M1e5_goldens(torch, S, monkeypatch, mode):
     elif mode == "fast_band":
         assert np.all(dE < 1e-9), dE
     else:
-        print(f"28 orbitals, M = 1e5, fast under the paper's rule: |dE| = {dE}")
+        print(f"28 orbitals, M = 1e4, fast under the paper's rule: |dE| = {dE}")
         assert np.all(dE < 1e-2), dE
