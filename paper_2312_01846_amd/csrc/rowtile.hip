@@ -63,7 +63,8 @@ struct RTParams {
     u64 item_base;               // items of this description start at this global item
     u64 row_base;                // D holds target rows from this alpha rank on
     u32 tile_chunk;              // consecutive tiles of one row per work unit
-    u32 pad_chunk;
+    u32 short_dbl;               // sigma: alpha doubles with at most this many entries in the tile are added
+                                 // while the records are built, longer ones by wavefront in the direct phase
     // Rows of several tiles (sigma): the alpha-beta doubles' items of every
     // input chunk (up to AB_CHUNK consecutive entries of one alpha row), by
     // target tile: the items of (chunk c, tile t) are ab_it[ab_off[c ntiles
@@ -272,7 +273,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     // sigma: an alpha double's entries in the tile, added by the calling
     // thread (element constant); true when it took them (ranges of at most 32)
     auto take_double = [&](const NbrRec& r, u32 tlo_, const RTParams& pp) -> bool {
-        if (r.e1 - r.e0 > 32) return false;
+        if (r.e1 - r.e0 > pp.short_dbl) return false;
         for (u32 k0 = r.e0; k0 < r.e1; k0 += RT_UNROLL) {
             u32 rb[RT_UNROLL];
             double c[RT_UNROLL];
@@ -298,6 +299,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
 
     // The counter hands out target rows (item_prefix counts rows per
     // instance); a workgroup then takes the row's tiles one after another.
+    // A workgroup's units come in increasing order, so its instance index
+    // never decreases: the search starts at the current one.
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -306,7 +309,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 s_left -= 1;
             } else {
                 const u64 it = atomicAdd(counter, 1u);
-                int k = 0;
+                int k = s_cur > 0 ? s_cur : 0;
                 if (it < total_items)
                     while (k + 1 < n_inst && item_prefix[k + 1] <= it) ++k;
                 s_item = ~0ull;
@@ -468,6 +471,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     type = 2;
                 }
                 const u64 rAs = str_rank(As, sB);
+                // an alpha double's integrals are read together with the row bounds
+                const double g2 = (!GRAD && type == 2) ? p.I.G(i, a, j, b) - p.I.G(i, b, j, a) : 0.0;
                 const u64 rb = p.rowbeg[rAs], re = p.rowend[rAs];
                 if (type == 0) {
                     s_idb = (u32)rb;  // the identity row: all its entries feed the beta-beta doubles
@@ -478,9 +483,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 if (re > rb) {
                     row_ok = true;
                     r.As = As; r.rAs = (u32)rAs; r.rowb = (u32)rb; r.rowe = (u32)re;
-                    const u32* tb = p.rtb + (u64)rAs;
-                    r.e0 = tb[(u64)tile * p.sp.Na];
-                    r.e1 = tb[(u64)(tile + 1) * p.sp.Na];
+                    if (whole_rows) {
+                        r.e0 = (u32)rb;  // one tile: the whole row
+                        r.e1 = (u32)re;
+                    } else {
+                        const u32* tb = p.rtb + (u64)rAs;
+                        r.e0 = tb[(u64)tile * p.sp.Na];
+                        r.e1 = tb[(u64)(tile + 1) * p.sp.Na];
+                    }
                     r.i = (uint8_t)i; r.a = (uint8_t)a; r.j = (uint8_t)j; r.b = (uint8_t)b;
                     r.type = (uint8_t)type;
                     r.par = 0;
@@ -491,7 +501,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         const int par = between_parity(As, i, a) ^ between_parity(mid, j, b);
                         r.par = (uint8_t)par;
                         if (!GRAD) {
-                            double e = (p.I.G(i, a, j, b) - p.I.G(i, b, j, a));
+                            double e = g2;
                             if (par) e = -e;
                             r.cst = e;
                             if (e == 0.0) {
@@ -564,7 +574,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         // few entries (each entry's element adds (ia|qq) over its beta
         // orbitals, staged in LDS per wavefront there): one wavefront, lanes
         // over the entries.
-        auto by_wave = [](const NbrRec& r) { return r.e1 - r.e0 > (r.type == 1 ? 4u : 32u); };
+        auto by_wave = [&](const NbrRec& r) {
+            return r.e1 - r.e0 > (r.type == 1 ? 4u : (r.type == 2 ? p.short_dbl : 32u));
+        };
         if (!GRAD) {
             for (unsigned li = threadIdx.x; li < nlist; li += RT_BLOCK) {
                 const NbrRec r = rec(li);
@@ -2036,7 +2048,12 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     unsigned chunk = 2;  // measured at 28 orbitals: 1, 2, 4, 7, 28 tiles -> 9.8, 9.0, 9.3, 10.7, 21.8 s
     if (const char* env = getenv("SFCI_TILE_CHUNK")) chunk = (unsigned)std::max(1, atoi(env));
     rp.tile_chunk = std::min<unsigned>(chunk, (unsigned)S->ntiles);
-    rp.pad_chunk = 0;
+    // alpha doubles added while the records are built: one thread walks the
+    // entries (RT_UNROLL loads at a time), so only short ranges; whole rows
+    // hand ranges above 8 entries to the direct phase's wavefront stream.
+    // SFCI_SHORT_DOUBLE overrides.
+    rp.short_dbl = (S->ntiles == 1) ? 8u : 32u;
+    if (const char* env = getenv("SFCI_SHORT_DOUBLE")) rp.short_dbl = (u32)std::max(0, atoi(env));
     out.n_items = P->Na * (u64)((S->ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
     out.lds_bytes = S->lds_bytes;
