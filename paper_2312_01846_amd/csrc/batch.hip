@@ -637,6 +637,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
                 J.vt_rank = (u64*)P->ws_list_r.get(pcap * sizeof(u64));
                 J.vt_amp = (double*)P->ws_list_a.get(pcap * sizeof(double));
                 J.vt_nnz = q.sc + 36;
+                J.pair_sym = true;  // sbar = Psi / <Psi|Psi>
                 jobs.push_back(J);
             } else {
                 launch_scatter_set(P, P->d_D, q.psi_r, q.sbar, q.sc + 34, pcap);

@@ -131,6 +131,7 @@ void energy_gradients_at(sfci_problem* P, const sfci_svec* psi, u64* sc, double*
         J.vt_rank = (u64*)P->ws_list_r.get(psi->nnz * sizeof(u64));
         J.vt_amp = (double*)P->ws_list_a.get(psi->nnz * sizeof(double));
         J.vt_nnz = sc + 5;
+        J.pair_sym = true;  // sbar = Psi / <Psi|Psi>
         rowtile_gradients(P->stream, 1, &J, P->grad_ws);
     } else {
         launch_scatter_set(P, P->d_D, psi->rank, sbar, sc, psi->nnz);

@@ -65,6 +65,9 @@ struct RTParams {
     u32 tile_chunk;              // consecutive tiles of one row per work unit
     u32 short_dbl;               // sigma: alpha doubles with at most this many entries in the tile are added
                                  // while the records are built, longer ones by wavefront in the direct phase
+    u32 pair_half;               // gradient passes with sbar a multiple of v: a pair of distinct rows is
+                                 // visited once, from the lower source rank, and counted twice
+    u32 pad_ph;
     // Rows of several tiles (sigma): the alpha-beta doubles' items of every
     // input chunk (up to AB_CHUNK consecutive entries of one alpha row), by
     // target tile: the items of (chunk c, tile t) are ab_it[ab_off[c ntiles
@@ -473,7 +476,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const u64 rAs = str_rank(As, sB);
                 // an alpha double's integrals are read together with the row bounds
                 const double g2 = (!GRAD && type == 2) ? p.I.G(i, a, j, b) - p.I.G(i, b, j, a) : 0.0;
-                const u64 rb = p.rowbeg[rAs], re = p.rowend[rAs];
+                // gradient with sbar proportional to v: sbar(J) v(I) = sbar(I) v(J), so of a pair of
+                // rows only the visit from the lower source rank is made (and weighted twice)
+                const bool mirror = GRAD && p.pair_half && type != 0 && rAs > rAt;
+                u64 rb = 0, re = 0;
+                if (!mirror) {
+                    rb = p.rowbeg[rAs];
+                    re = p.rowend[rAs];
+                }
                 if (type == 0) {
                     s_idb = (u32)rb;  // the identity row: all its entries feed the beta-beta doubles
                     s_ide = (u32)re;
@@ -732,6 +742,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 }
                 if (w != 0.0) {
                     if (r.par) w = -w;
+                    if (p.pair_half) w *= 2.0;
                     atomicAdd(p.Rg + gi(r.i, r.a, r.j, r.b), w);
                     atomicAdd(p.Rg + gi(r.i, r.b, r.j, r.a), -w);
                 }
@@ -781,7 +792,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         }
                     }
                 }
-                const double Wr = wave_sum(wl);
+                // a pair of distinct rows counted twice (pair_half); the identity row once
+                const double pf = (p.pair_half && T != 0) ? 2.0 : 1.0;
+                const double Wr = wave_sum(wl) * pf;
                 wave_sync();
                 if (T == 2) {
                     if (lane == 0 && Wr != 0.0) {
@@ -796,7 +809,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     if (lane < n) {
                         const int q = lane;
                         const bool spect = q != i && ((r.As >> q) & 1u);
-                        const double add = sg * (wo[q] + (spect ? Wr : 0.0));
+                        const double add = sg * (wo[q] * pf + (spect ? Wr : 0.0));
                         wo[q] = 0.0;
                         if (add != 0.0) atomicAdd(p.Rg + gi(i, a, q, q), add);
                         if (spect && Wr != 0.0) atomicAdd(p.Rg + gi(i, q, q, a), -sg * Wr);
@@ -1336,10 +1349,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 wave_sync();
                 const u32 n2 = (u32)n * n;
                 double* Rrow = p.Rg + ((u32)I_ * n + A_) * n2;
+                const double pf = p.pair_half ? 2.0 : 1.0;  // the items are alpha-single rows
                 for (u32 t = lane; t < n2; t += 64) {
                     const double v = slab[t];
                     if (v != 0.0) {
-                        atomicAdd(Rrow + t, v);
+                        atomicAdd(Rrow + t, v * pf);
                         slab[t] = 0.0;
                     }
                 }
@@ -2053,6 +2067,8 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     // hand ranges above 8 entries to the direct phase's wavefront stream.
     // SFCI_SHORT_DOUBLE overrides.
     rp.short_dbl = (S->ntiles == 1) ? 8u : 32u;
+    rp.pair_half = 0;
+    rp.pad_ph = 0;
     if (const char* env = getenv("SFCI_SHORT_DOUBLE")) rp.short_dbl = (u32)std::max(0, atoi(env));
     out.n_items = P->Na * (u64)((S->ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);
@@ -2301,6 +2317,7 @@ void rowtile_gradients(hipStream_t st, int n_jobs, const GradJob* jobs, RowTileG
         RTParams& rp = *(RTParams*)d[k].raw;
         rp.Rh = J.Rh;
         rp.Rg = J.Rg;
+        rp.pair_half = J.pair_sym ? 1u : 0u;
         slab_n2 = std::max(slab_n2, (unsigned)n2);
         num_cu = P->num_cu;
     }
@@ -2324,6 +2341,7 @@ void rowtile_gradients(hipStream_t st, int n_jobs, const GradJob* jobs, RowTileG
         RTParams& rp = *(RTParams*)d[k].raw;
         rp.Rh = J.Rh;
         rp.Rg = J.Rg;
+        rp.pair_half = J.pair_sym ? 1u : 0u;
     }
     grad_pass(st, 1, d, 0u, num_cu, ws);
     for (int k = 0; k < n_jobs; ++k) {

@@ -255,6 +255,9 @@ struct GradJob {
     u64* vt_rank;
     double* vt_amp;
     u64* vt_nnz;
+    // sbar is v scaled by a constant (the energy's gradient): each pair of
+    // distinct connected rows is then visited once and counted twice
+    bool pair_sym;
 };
 bool rowtile_grad_available(sfci_problem* P);
 void rowtile_gradients(hipStream_t st, int n_jobs, const GradJob* jobs, RowTileGradWs& ws);

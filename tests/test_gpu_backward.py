@@ -157,6 +157,30 @@ def test_converged_vector_gradients_20_orbitals(torch, S, orc):
     assert np.allclose(_np(dg), og, rtol=1e-6, atol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["hub12", "n14_5_5_tiles"])
+def test_energy_gradients_pair_symmetric_passes(torch, S, orc, case, monkeypatch):
+    # The energy's gradient (sbar = Psi / <Psi|Psi>) visits each pair of
+    # distinct connected rows once, from the lower source rank, and counts it
+    # twice; against the oracle's backward with both visits, on a Hubbard
+    # space (zero elements) and on rows of two tiles
+    if case == "hub12":
+        n, na, nb = 12, 6, 6
+        h, g = synth.hubbard_ring(12, 1.0, 4.0)
+        nv = 5000
+    else:
+        monkeypatch.setenv("SFCI_TILE_MAX", "1024")  # C(14,5) = 2002 beta strings: two tiles per row
+        n, na, nb = 14, 5, 5
+        h, g = synth.molecule_like(14, 28, 6)
+        nv = 8000
+    P = S.Problem(n, na, nb, h, g)
+    Po = orc.Problem(n, na, nb, h, g)
+    r, a = synth.random_sparse_vector(P.n_det, nv, seed=12)
+    E, dh, dg = P.energy_gradients(r.astype(np.int64), a, deterministic=False)
+    _, oh, og = Po.backward(r, a, r, a / float(a @ a))
+    assert np.allclose(_np(dh), oh, rtol=1e-9, atol=1e-12)
+    assert np.allclose(_np(dg), og, rtol=1e-9, atol=1e-12)
+
+
 @pytest.mark.parametrize("det", [True, False], ids=["deterministic", "fast"])
 def test_energy_gradients_call_matches_oracle(torch, S, orc, det):
     # sfci_energy_gradients: E = <Psi|H|Psi>/<Psi|Psi> (bit for bit with the
