@@ -25,6 +25,7 @@ struct sfci_batch {
     hipStream_t own = nullptr;         // capture-capable stream used during a batched run
     std::vector<DevBuf> descs;  // per iteration step j: the n instance descriptions
     DevBuf prefix, counter, scratch;
+    DevBuf binst, bscan;        // batched vector steps: the instances (BInst), the two scans' jobs
     RowTileGradWs grad_ws;
     // per-instance chains run on these streams (forked from and joined to `own`)
     std::vector<hipStream_t> aux;
@@ -131,6 +132,8 @@ sfci_status sfci_batch_destroy(sfci_batch* B) {
     B->drop_graphs();
     for (auto& d : B->descs) d.release();
     B->prefix.release();
+    B->binst.release();
+    B->bscan.release();
     B->counter.release();
     B->scratch.release();
     B->grad_ws.release();
@@ -243,6 +246,68 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
     const bool autotune = o->autotune != 0 && batched_sigma;
     int tune_trials = 0;
     double tune_default_ms = 0.0, tune_best_ms = 0.0;
+    // The vector steps of a tile-batched iteration (dots, Eq. 10, truncation,
+    // Eq. 11, the block end) run as one launch per step for all instances
+    // (SFCI_BATCH_REST=0: per instance, as the other modes do).
+    bool batched_rest = batched_sigma;
+    if (const char* env = getenv("SFCI_BATCH_REST")) batched_rest = batched_rest && env[0] != '0';
+    const BInst* d_bi = nullptr;
+    const BScanJob* d_scan_dense = nullptr;
+    const BScanJob* d_scan_list = nullptr;
+    u64 max_cap = 1, max_ndet = 1;
+    int max_ndig = 1;
+    if (batched_rest) {
+        std::vector<BInst> hb(n);
+        std::vector<BScanJob> hs(2 * (size_t)n);
+        for (int k = 0; k < n; ++k) {
+            Inst& q = I[k];
+            sfci_problem* P = q.P;
+            const u64 nch = select_chunks(P->Ndet);
+            const u64 n2 = (u64)P->n * P->n;
+            BInst& b = hb[k];
+            b.Wr = q.Wr;
+            b.Wa = q.Wa;
+            b.sc = q.sc;
+            b.cap = q.cap;
+            b.D = P->d_D;
+            b.Ndet = P->Ndet;
+            b.T = q.T;
+            b.S = q.S;
+            b.x = q.x;
+            b.lam = q.lam;
+            b.energies = q.energies;
+            b.blk = q.blk;
+            b.status = q.status;
+            // also the gradient pass's raw sums and the per-instance reductions
+            b.red = (double*)P->ws_red.get(std::max<u64>(bstep_red_doubles(nL), 2048 + n2 + n2 * n2) * sizeof(double));
+            b.st = (SelState*)P->ws_sel.get(sizeof(SelState));
+            b.st2 = (SelState*)P->ws_sel2.get(sizeof(SelState));
+            b.cr = (u64*)P->ws_cand_r.get(P->Ndet * sizeof(u64));
+            b.ca = (double*)P->ws_cand_a.get(P->Ndet * sizeof(double));
+            b.cnt = (u64*)P->ws_cnt.get(nch * sizeof(u64));
+            b.bsum = (u64*)P->ws_scan.get(scan_block_sums(nch) * sizeof(u64));
+            b.psi_r = q.psi_r;
+            b.psi_a = q.psi_a;
+            b.psi_n = q.sc + 34;
+            b.M = q.M;
+            b.ndet_m1 = P->kg.ndet_m1;
+            b.rank_bits = P->kg.rank_bits;
+            b.nL = nL;
+            hs[k] = BScanJob{b.cnt, b.cnt, nch, b.bsum, &b.st->count_cand};
+            hs[n + k] = BScanJob{b.cnt, b.cnt, nch, b.bsum, &b.st2->count_out};
+            max_cap = std::max(max_cap, q.cap);
+            max_ndet = std::max(max_ndet, P->Ndet);
+            max_ndig = std::max(max_ndig, (63 + P->kg.rank_bits + 10) / 11);
+        }
+        BInst* dbi = (BInst*)B->binst.get((size_t)n * sizeof(BInst));
+        BScanJob* dsj = (BScanJob*)B->bscan.get(2 * (size_t)n * sizeof(BScanJob));
+        SFCI_CHECK_HIP(hipMemcpyAsync(dbi, hb.data(), hb.size() * sizeof(BInst), hipMemcpyHostToDevice, st));
+        SFCI_CHECK_HIP(hipMemcpyAsync(dsj, hs.data(), hs.size() * sizeof(BScanJob), hipMemcpyHostToDevice, st));
+        SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host arrays go out of scope
+        d_bi = dbi;
+        d_scan_dense = dsj;
+        d_scan_list = dsj + n;
+    }
     // The gradient pass's buffers at their full size before any graph is
     // captured: growing one later would free memory the graphs use.
     if (!det && (dh_all || deri_all))
@@ -266,8 +331,8 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         };
         auto ptr = [](const void* p) { return (u64)(uintptr_t)p; };
         g.insert(g.end(), {(u64)n, (u64)nL, (u64)o->dedup, (u64)(o->tie_band != 0), bits(o->screen_eps),
-                           bits(o->excite_eps), (u64)batched_sigma, B->tune.b1_chunk, B->tune.bb_chunk,
-                           B->tune.per_cu});
+                           bits(o->excite_eps), (u64)batched_sigma, (u64)batched_rest, B->tune.b1_chunk,
+                           B->tune.bb_chunk, B->tune.per_cu});
         for (const Inst& q : I)
             g.insert(g.end(), {ptr(q.P), q.M, q.cap, ptr(q.Wr), ptr(q.Wa), ptr(q.sc), ptr(q.T), ptr(q.psi_r),
                                ptr(q.psi_a), ptr(q.P->d_D)});
@@ -415,7 +480,21 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             SFCI_CHECK_HIP(hipMemcpyAsync(I[k].sc + 32, I[k].sc + 40, sizeof(u64), hipMemcpyDeviceToDevice, st));
         launch_fill_u64((u64*)d_cnt, 1, 0, st);  // the real launch starts from item 0
     };
+    const int band = o->tie_band ? 1 : 0;
     auto iteration_rest = [&](int j) {
+        if (batched_rest) {
+            bstep_dots(st, d_bi, n, j, nL);
+            if (j + 1 < nL) {
+                bstep_axpy(st, d_bi, n, j, j, 0, max_cap);
+                if (j >= 1) bstep_axpy(st, d_bi, n, j - 1, j, 0, max_cap);
+                bstep_select(st, d_bi, n, BOUT_NEXT, j, max_ndet, B->P[0]->num_cu, band, max_ndig, d_scan_dense,
+                             d_scan_list, 0);
+                bstep_normalise(st, d_bi, n, BOUT_NEXT, j, max_cap);
+            } else {
+                bstep_fill_zero(st, d_bi, n, max_ndet);
+            }
+            return;
+        }
         fan([&](int k) {
             Inst& q = I[k];
             sfci_problem* P = q.P;
@@ -443,6 +522,21 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
         });
     };
     auto block_end = [&](bool last) {
+        if (batched_rest) {
+            bstep_geneig(st, d_bi, n, nL);
+            for (int j = 0; j < nL; ++j) bstep_axpy(st, d_bi, n, j, 0, 1, max_cap);
+            if (!last) {
+                bstep_select(st, d_bi, n, BOUT_W0, 0, max_ndet, B->P[0]->num_cu, band, max_ndig, d_scan_dense,
+                             d_scan_list, 0);
+                bstep_normalise(st, d_bi, n, BOUT_W0, 0, max_cap);
+            } else {
+                // every nonzero entry of Psi (capacity n_L * cap suffices)
+                bstep_select(st, d_bi, n, BOUT_PSI, 0, max_ndet, B->P[0]->num_cu, band, max_ndig, d_scan_dense,
+                             d_scan_list, 1);
+            }
+            bstep_inc_blk(st, d_bi, n);
+            return;
+        }
         fan([&](int k) {
             Inst& q = I[k];
             sfci_problem* P = q.P;

@@ -299,9 +299,9 @@ __device__ void jacobi_dev(int m, double (*A)[GE_MAX], double (*V)[GE_MAX], doub
 // X = U_k s_k^(-1/2), Jacobi on X^T T X, x = X y for the lowest eigenvalue,
 // sign fixed so that the largest |x_i| (lowest i on ties) is positive.
 // One wavefront; every sum keeps the reference's order.
-__global__ __launch_bounds__(64) void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S,
-                                               double* lambda, double* x, double* energy_slot, const int* blk,
-                                               int* status) {
+__device__ __forceinline__ void geneig_body(int m, const double* __restrict__ T, const double* __restrict__ S,
+                                            double* lambda, double* x, double* energy_slot, const int* blk,
+                                            int* status) {
     __shared__ double A[GE_MAX][GE_MAX], U[GE_MAX][GE_MAX], X[GE_MAX][GE_MAX], TX[GE_MAX][GE_MAX];
     __shared__ double sv[GE_MAX], lam[GE_MAX], xs[GE_MAX];
     __shared__ int keep[GE_MAX];
@@ -379,6 +379,12 @@ __global__ __launch_bounds__(64) void k_geneig(int m, const double* __restrict__
         if (energy_slot) energy_slot[blk ? *blk : 0] = lam[best];
         *status = 0;
     }
+}
+
+__global__ __launch_bounds__(64) void k_geneig(int m, const double* __restrict__ T, const double* __restrict__ S,
+                                               double* lambda, double* x, double* energy_slot, const int* blk,
+                                               int* status) {
+    geneig_body(m, T, S, lambda, x, energy_slot, blk, status);
 }
 
 unsigned gsz(u64 cap) {
@@ -547,5 +553,170 @@ void launch_div_by_sumsq(sfci_problem* P, const double* a, const u64* nnz, u64 c
     hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(RB), 0, P->stream, a, nnz, part);
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(RB), 0, P->stream, part, (int)g, ss, (double*)nullptr);
     hipLaunchKernelGGL(k_scale_copy, dim3(gsz(cap)), dim3(256), 0, P->stream, a, nnz, ss, out);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+// ---- batched steps: every instance of a batch in one launch (blockIdx.y or
+// blockIdx.z picks the instance).  The same products and sums as the
+// per-instance fast reductions above, over a fixed grid of BG partials.
+namespace {
+
+constexpr unsigned BG = 256;  // partial sums per dot
+
+__device__ __forceinline__ void bvec(const BInst& b, int l, const u64*& r, const double*& a, u64& n) {
+    r = b.Wr + (u64)l * b.cap;
+    a = b.Wa + (u64)l * b.cap;
+    n = b.sc[l];
+}
+
+__device__ __forceinline__ int bout_index(int kind, int j) { return kind == BOUT_W0 ? 0 : j + 1; }
+
+// grid (BG, 2 (j + 1), n): y = 2 l, <w_l|D>; y = 2 l + 1, <w_l|w_j>
+__global__ __launch_bounds__(RB) void k_bdot_part(const BInst* __restrict__ B, int j) {
+    const BInst& b = B[blockIdx.z];
+    __shared__ double sh[RB];
+    const int l = (int)(blockIdx.y >> 1);
+    const u64* xr;
+    const double* xa;
+    u64 nx;
+    bvec(b, l, xr, xa, nx);
+    double s = 0.0;
+    if ((blockIdx.y & 1u) == 0) {
+        for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < nx; i += (u64)BG * RB) s += xa[i] * b.D[xr[i]];
+    } else {
+        const u64* yr;
+        const double* ya;
+        u64 ny;
+        bvec(b, j, yr, ya, ny);
+        for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < nx; i += (u64)BG * RB) {
+            const double yv = y_at(yr, ya, ny, xr[i]);
+            if (yv != 0.0) s += xa[i] * yv;
+        }
+    }
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) b.red[(u64)blockIdx.y * BG + blockIdx.x] = t;
+}
+
+// grid (2 (j + 1), n): the BG partials of each dot into T or S (both triangles)
+__global__ __launch_bounds__(RB) void k_bdot_final(const BInst* __restrict__ B, int j) {
+    const BInst& b = B[blockIdx.y];
+    __shared__ double sh[RB];
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < BG; i += RB) s += b.red[(u64)blockIdx.x * BG + i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const int l = (int)(blockIdx.x >> 1);
+        double* M = (blockIdx.x & 1u) ? b.S : b.T;
+        M[l * b.nL + j] = t;
+        M[j * b.nL + l] = t;
+    }
+}
+
+// kind 0: D[r_i] = D[r_i] - T[l][j] a_i;  kind 1: D[r_i] = D[r_i] + x[l] a_i
+__global__ void k_baxpy(const BInst* __restrict__ B, int l, int j, int kind) {
+    const BInst& b = B[blockIdx.y];
+    const u64* r;
+    const double* a;
+    u64 n;
+    bvec(b, l, r, a, n);
+    const double c = kind ? b.x[l] : b.T[l * b.nL + j];
+    double* D = b.D;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+        const double prod = c * a[i];
+        const u64 k = r[i];
+        if (kind) D[k] = D[k] + prod;
+        else D[k] = D[k] - prod;
+    }
+}
+
+// Eq. 11 on w_{j+1} (or w_0): partial sums of squares, their sum, the division
+__global__ __launch_bounds__(RB) void k_bsumsq_part(const BInst* __restrict__ B, int kind, int j) {
+    const BInst& b = B[blockIdx.y];
+    __shared__ double sh[RB];
+    const u64* r;
+    const double* a;
+    u64 n;
+    bvec(b, bout_index(kind, j), r, a, n);
+    double s = 0.0;
+    for (u64 i = (u64)blockIdx.x * RB + threadIdx.x; i < n; i += (u64)BG * RB) s += a[i] * a[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) b.red[(u64)2 * b.nL * BG + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(RB) void k_bsumsq_final(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    __shared__ double sh[RB];
+    const double* part = b.red + (u64)2 * b.nL * BG;
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < BG; i += RB) s += part[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) b.red[(u64)2 * b.nL * BG + BG] = t;
+}
+
+__global__ void k_bdiv(const BInst* __restrict__ B, int kind, int j) {
+    const BInst& b = B[blockIdx.y];
+    const double ss = b.red[(u64)2 * b.nL * BG + BG];
+    if (!(ss > 0.0)) return;
+    const double nrm = sqrt(ss);
+    const int l = bout_index(kind, j);
+    double* a = b.Wa + (u64)l * b.cap;
+    const u64 n = b.sc[l];
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) a[i] = a[i] / nrm;
+}
+
+__global__ void k_bfill_zero(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < b.Ndet; i += (u64)gridDim.x * blockDim.x) b.D[i] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_bgeneig(const BInst* __restrict__ B, int m) {
+    const BInst& b = B[blockIdx.y];
+    geneig_body(m, b.T, b.S, b.lam, b.x, b.energies, b.blk, b.status);
+}
+
+__global__ void k_binc_blk(const BInst* __restrict__ B) {
+    if (threadIdx.x == 0) *B[blockIdx.y].blk += 1;
+}
+
+unsigned bgrid(u64 n, u64 per, u64 cap) {
+    u64 g = (n + per - 1) / per;
+    return (unsigned)std::max<u64>(1, std::min<u64>(g, cap));
+}
+
+}  // namespace
+
+u64 bstep_red_doubles(int nL) { return (u64)2 * nL * BG + BG + 8; }
+
+void bstep_dots(hipStream_t st, const BInst* d, int n, int j, int nL) {
+    (void)nL;
+    hipLaunchKernelGGL(k_bdot_part, dim3(BG, 2 * (j + 1), n), dim3(RB), 0, st, d, j);
+    hipLaunchKernelGGL(k_bdot_final, dim3(2 * (j + 1), n), dim3(RB), 0, st, d, j);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bstep_axpy(hipStream_t st, const BInst* d, int n, int l, int j, int kind, u64 max_cap) {
+    hipLaunchKernelGGL(k_baxpy, dim3(bgrid(max_cap, 256, 16384), n), dim3(256), 0, st, d, l, j, kind);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bstep_normalise(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_cap) {
+    hipLaunchKernelGGL(k_bsumsq_part, dim3(BG, n), dim3(RB), 0, st, d, out_kind, j);
+    hipLaunchKernelGGL(k_bsumsq_final, dim3(1, n), dim3(RB), 0, st, d);
+    hipLaunchKernelGGL(k_bdiv, dim3(bgrid(max_cap, 256, 16384), n), dim3(256), 0, st, d, out_kind, j);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bstep_fill_zero(hipStream_t st, const BInst* d, int n, u64 max_ndet) {
+    hipLaunchKernelGGL(k_bfill_zero, dim3(bgrid(max_ndet, 256 * 16, 65535), n), dim3(256), 0, st, d);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bstep_geneig(hipStream_t st, const BInst* d, int n, int nL) {
+    hipLaunchKernelGGL(k_bgeneig, dim3(1, n), dim3(64), 0, st, d, nL);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bstep_inc_blk(hipStream_t st, const BInst* d, int n) {
+    hipLaunchKernelGGL(k_binc_blk, dim3(1, n), dim3(64), 0, st, d);
     SFCI_CHECK_HIP(hipGetLastError());
 }

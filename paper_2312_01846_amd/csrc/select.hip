@@ -70,7 +70,7 @@ __device__ __forceinline__ bool sel_pred(const SelState& st, const Geo& g, u64 r
     return (K >> sh) >= pre;
 }
 
-__global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
+__device__ __forceinline__ void sel_init_body(SelState* st, u64 M, int take_all, int take_none) {
     for (int t = threadIdx.x; t < NBIN; t += blockDim.x) st->hist[t] = 0;
     if (threadIdx.x == 0) {
         st->need = M;
@@ -91,12 +91,14 @@ __global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) {
     }
 }
 
+__global__ void k_sel_init(SelState* st, u64 M, int take_all, int take_none) { sel_init_body(st, M, take_all, take_none); }
+
 // Dense sources: after the level-0 pick (the top key digit is the exponent
 // field of |c|), every entry that can still be kept has |c| >= 2^e, e the
 // binade of the M-th |c| (with the tie band: >= 2^e (1 - 2^-36)).  Those
 // candidates are compacted into a list and the rest of the selection runs on
 // the list.
-__global__ void k_sel_cand_bound(SelState* st, int band) {
+__device__ __forceinline__ void sel_cand_bound_body(SelState* st, int band) {
     if (threadIdx.x != 0) return;
     u64 b;
     if (st->take_all) {
@@ -113,14 +115,16 @@ __global__ void k_sel_cand_bound(SelState* st, int band) {
     st->cand = 1;
 }
 
+__global__ void k_sel_cand_bound(SelState* st, int band) { sel_cand_bound_body(st, band); }
+
 // Ties at the cut: the smallest |c| among the M selected (exact rule) ...
 template <class Src>
-__global__ __launch_bounds__(256) void k_sel_min(Src src, SelState* __restrict__ st, Geo g) {
+__device__ __forceinline__ void sel_min_body(const Src& src, SelState* __restrict__ st, const Geo& g, unsigned bx, unsigned gx) {
     const SelState s = *st;
     if (s.take_all || !s.done || s.level == 0) return;
     const u64 n = src.size();
     u64 m = ~0ull;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    for (u64 i = (u64)bx * blockDim.x + threadIdx.x; i < n; i += (u64)gx * blockDim.x) {
         u64 r;
         double c;
         src.get(i, r, c);
@@ -137,21 +141,28 @@ __global__ __launch_bounds__(256) void k_sel_min(Src src, SelState* __restrict__
     }
 }
 
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_min(Src src, SelState* __restrict__ st, Geo g) {
+    sel_min_body(src, st, g, blockIdx.x, gridDim.x);
+}
+
 // ... the threshold cmin * (1 - 2^-36) ...
-__global__ void k_sel_thr(SelState* st) {
+__device__ __forceinline__ void sel_thr_body(SelState* st) {
     if (threadIdx.x != 0 || st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
     const double thr = __longlong_as_double((long long)st->cmin) * (1.0 - 1.0 / 68719476736.0);
     st->thr_bits = abs_bits(thr);
 }
 
+__global__ void k_sel_thr(SelState* st) { sel_thr_body(st); }
+
 // ... how many nonzero candidates reach it ...
 template <class Src>
-__global__ __launch_bounds__(256) void k_sel_count_thr(Src src, SelState* __restrict__ st) {
+__device__ __forceinline__ void sel_count_thr_body(const Src& src, SelState* __restrict__ st, unsigned bx, unsigned gx) {
     if (st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
     const u64 thr = st->thr_bits;
     const u64 n = src.size();
     unsigned long long c_ = 0;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    for (u64 i = (u64)bx * blockDim.x + threadIdx.x; i < n; i += (u64)gx * blockDim.x) {
         u64 r;
         double c;
         src.get(i, r, c);
@@ -167,14 +178,21 @@ __global__ __launch_bounds__(256) void k_sel_count_thr(Src src, SelState* __rest
     }
 }
 
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_count_thr(Src src, SelState* __restrict__ st) {
+    sel_count_thr_body(src, st, blockIdx.x, gridDim.x);
+}
+
 // ... and whether they are kept (at most SFCI_TIE_SLACK beyond M).
-__global__ void k_sel_mode(SelState* st, u64 M) {
+__device__ __forceinline__ void sel_mode_body(SelState* st, u64 M) {
     if (threadIdx.x != 0 || st->take_all || !st->done || st->level == 0 || st->cmin == ~0ull) return;
     st->use_thr = (st->count_thr <= M + (u64)SFCI_TIE_SLACK) ? 1 : 0;
 }
 
+__global__ void k_sel_mode(SelState* st, u64 M) { sel_mode_body(st, M); }
+
 template <class Src>
-__global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict__ st, Geo g, int L) {
+__device__ __forceinline__ void sel_hist_body(const Src& src, SelState* __restrict__ st, const Geo& g, int L, unsigned bx, unsigned gx) {
     if (st->done) return;
     __shared__ unsigned int h[NBIN];
     __shared__ unsigned long long blk_total;
@@ -186,7 +204,7 @@ __global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict_
     const int hi_sh = g.tb - DIG * L;  // bits above the current digit
     const u64 n = src.size();
     u64 my_total = 0;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    for (u64 i = (u64)bx * blockDim.x + threadIdx.x; i < n; i += (u64)gx * blockDim.x) {
         u64 r;
         double c;
         src.get(i, r, c);
@@ -204,11 +222,16 @@ __global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict_
     if (L == 0 && threadIdx.x == 0 && blk_total) atomicAdd((unsigned long long*)&st->total, blk_total);
 }
 
+template <class Src>
+__global__ __launch_bounds__(256) void k_sel_hist(Src src, SelState* __restrict__ st, Geo g, int L) {
+    sel_hist_body(src, st, g, L, blockIdx.x, gridDim.x);
+}
+
 // Pick the digit of level L: the largest d >= 1 whose bins d.. hold at least
 // `need` entries (else 0), as a block-wide suffix scan over the histogram.
 constexpr int PICK_T = 256;
 constexpr int PICK_PER = NBIN / PICK_T;
-__global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L, u64 M) {
+__device__ __forceinline__ void sel_pick_body(SelState* st, const Geo& g, int L, u64 M) {
     __shared__ int s_d;
     __shared__ u64 s_acc;
     const int t = threadIdx.x;
@@ -281,13 +304,15 @@ __global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L,
     }
 }
 
+__global__ __launch_bounds__(PICK_T) void k_sel_pick(SelState* st, Geo g, int L, u64 M) { sel_pick_body(st, g, L, M); }
+
 template <class Src>
-__global__ __launch_bounds__(CBLOCK) void k_compact_count(Src src, const SelState* __restrict__ st, Geo g,
-                                                          u64* __restrict__ cnt) {
+__device__ __forceinline__ void compact_count_body(const Src& src, const SelState* __restrict__ st, const Geo& g,
+                                                   u64* __restrict__ cnt, unsigned bx) {
     const u64 n = src.size();
-    const u64 base = (u64)blockIdx.x * CCHUNK;
+    const u64 base = (u64)bx * CCHUNK;
     if (base >= n) {  // grid sized for capacity; chunk beyond the live size
-        if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
+        if (threadIdx.x == 0) cnt[bx] = 0;
         return;
     }
     const SelState s = *st;
@@ -308,20 +333,26 @@ __global__ __launch_bounds__(CBLOCK) void k_compact_count(Src src, const SelStat
     if (threadIdx.x == 0) {
         u64 t = 0;
         for (int w = 0; w < CBLOCK / 64; ++w) t += sh[w];
-        cnt[blockIdx.x] = t;
+        cnt[bx] = t;
     }
 }
 
+template <class Src>
+__global__ __launch_bounds__(CBLOCK) void k_compact_count(Src src, const SelState* __restrict__ st, Geo g,
+                                                          u64* __restrict__ cnt) {
+    compact_count_body(src, st, g, cnt, blockIdx.x);
+}
+
 template <class Src, bool ZERO>
-__global__ __launch_bounds__(CBLOCK) void k_compact_write(Src src, const SelState* __restrict__ st, Geo g,
-                                                          const u64* __restrict__ off, u64* __restrict__ out_r,
-                                                          double* __restrict__ out_a, double* __restrict__ Dz) {
+__device__ __forceinline__ void compact_write_body(const Src& src, const SelState* __restrict__ st, const Geo& g,
+                                                   const u64* __restrict__ off, u64* __restrict__ out_r,
+                                                   double* __restrict__ out_a, double* __restrict__ Dz, unsigned bx) {
     const u64 n = src.size();
-    const u64 base = (u64)blockIdx.x * CCHUNK;
+    const u64 base = (u64)bx * CCHUNK;
     if (base >= n) return;
     const SelState s = *st;
     __shared__ unsigned wtot[CBLOCK / 64];
-    u64 run = off[blockIdx.x];
+    u64 run = off[bx];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k = 0; k < CITEMS; ++k) {
         u64 i = base + (u64)k * CBLOCK + threadIdx.x;
@@ -352,8 +383,117 @@ __global__ __launch_bounds__(CBLOCK) void k_compact_write(Src src, const SelStat
     }
 }
 
+template <class Src, bool ZERO>
+__global__ __launch_bounds__(CBLOCK) void k_compact_write(Src src, const SelState* __restrict__ st, Geo g,
+                                                          const u64* __restrict__ off, u64* __restrict__ out_r,
+                                                          double* __restrict__ out_a, double* __restrict__ Dz) {
+    compact_write_body<Src, ZERO>(src, st, g, off, out_r, out_a, Dz, blockIdx.x);
+}
+
 __global__ void k_copy_count(const u64* src, u64* dst) {
     if (threadIdx.x == 0) *dst = *src;
+}
+
+// ---- batched selection: each launch serves every instance of a batch
+// (blockIdx.y), the same steps as select_topm on a dense source ----
+__device__ __forceinline__ Geo bgeo(const BInst& b) {
+    Geo g;
+    g.rank_bits = b.rank_bits;
+    g.tb = 63 + b.rank_bits;
+    g.ndig = (g.tb + DIG - 1) / DIG;
+    g.ndet_m1 = b.ndet_m1;
+    return g;
+}
+__device__ __forceinline__ u64 bchunks(const BInst& b) { return b.Ndet ? (b.Ndet + CCHUNK - 1) / CCHUNK : 1; }
+__device__ __forceinline__ ListSrc blist(const BInst& b) { return ListSrc{b.cr, b.ca, &b.st->count_cand}; }
+__device__ __forceinline__ void bout_vec(const BInst& b, int kind, int j, u64*& r, double*& a, u64*& n) {
+    if (kind == BOUT_PSI) {
+        r = b.psi_r;
+        a = b.psi_a;
+        n = b.psi_n;
+    } else {
+        const u64 l = kind == BOUT_W0 ? 0 : (u64)j + 1;
+        r = b.Wr + l * b.cap;
+        a = b.Wa + l * b.cap;
+        n = b.sc + l;
+    }
+}
+
+// list = 0: the dense pass's state, 1: the candidate list's; M = UINT64_MAX
+// keeps every nonzero entry, M = 0 none (the dense pass then lists all, or no,
+// nonzero entries as candidates)
+__global__ void k_bsel_init(const BInst* __restrict__ B, int list, int all) {
+    const BInst& b = B[blockIdx.y];
+    const u64 M = all ? UINT64_MAX : b.M;
+    sel_init_body(list ? b.st2 : b.st, M, M == UINT64_MAX ? 1 : 0, M == 0 ? 1 : 0);
+}
+
+__global__ __launch_bounds__(256) void k_bsel_hist_dense(const BInst* __restrict__ B, int L) {
+    const BInst& b = B[blockIdx.y];
+    sel_hist_body(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), L, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_bsel_hist_list(const BInst* __restrict__ B, int L) {
+    const BInst& b = B[blockIdx.y];
+    sel_hist_body(blist(b), b.st2, bgeo(b), L, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(PICK_T) void k_bsel_pick(const BInst* __restrict__ B, int list, int L) {
+    const BInst& b = B[blockIdx.y];
+    sel_pick_body(list ? b.st2 : b.st, bgeo(b), L, b.M);
+}
+
+__global__ void k_bsel_cand_bound(const BInst* __restrict__ B, int band) { sel_cand_bound_body(B[blockIdx.y].st, band); }
+
+__global__ __launch_bounds__(CBLOCK) void k_bcompact_count_dense(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    if (blockIdx.x >= bchunks(b)) return;  // past this instance's chunks (and its count array)
+    compact_count_body(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), b.cnt, blockIdx.x);
+}
+
+__global__ __launch_bounds__(CBLOCK) void k_bcompact_write_dense(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    if (blockIdx.x >= bchunks(b)) return;
+    compact_write_body<DenseSrc, true>(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), b.cnt, b.cr, b.ca, b.D, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_bsel_min_list(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    sel_min_body(blist(b), b.st2, bgeo(b), blockIdx.x, gridDim.x);
+}
+
+__global__ void k_bsel_thr(const BInst* __restrict__ B) { sel_thr_body(B[blockIdx.y].st2); }
+
+__global__ __launch_bounds__(256) void k_bsel_count_thr_list(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    sel_count_thr_body(blist(b), b.st2, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_bsel_mode(const BInst* __restrict__ B) { sel_mode_body(B[blockIdx.y].st2, B[blockIdx.y].M); }
+
+__global__ __launch_bounds__(CBLOCK) void k_bcompact_count_list(const BInst* __restrict__ B) {
+    const BInst& b = B[blockIdx.y];
+    if (blockIdx.x >= bchunks(b)) return;
+    compact_count_body(blist(b), b.st2, bgeo(b), b.cnt, blockIdx.x);
+}
+
+__global__ void k_bcopy_count(const BInst* __restrict__ B, int kind, int j) {
+    const BInst& b = B[blockIdx.y];
+    u64* r;
+    double* a;
+    u64* n;
+    bout_vec(b, kind, j, r, a, n);
+    if (threadIdx.x == 0) *n = b.st2->count_out;
+}
+
+__global__ __launch_bounds__(CBLOCK) void k_bcompact_write_list(const BInst* __restrict__ B, int kind, int j) {
+    const BInst& b = B[blockIdx.y];
+    if (blockIdx.x >= bchunks(b)) return;
+    u64* r;
+    double* a;
+    u64* n;
+    bout_vec(b, kind, j, r, a, n);
+    compact_write_body<ListSrc, false>(blist(b), b.st2, bgeo(b), b.cnt, r, a, nullptr, blockIdx.x);
 }
 
 Geo make_geo(sfci_problem* P) {
@@ -482,4 +622,37 @@ void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, doub
     ListSrc ls{cr, ca, &st->count_cand};
     run_prepare(P, ls, P->Ndet, M, out_count_dev, st2);
     run_write(P, ls, P->Ndet, out_rank, out_amp, false, nullptr, st2);
+}
+
+void bstep_select(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_ndet, int num_cu, int band,
+                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all) {
+    const unsigned N = (unsigned)n;
+    const unsigned hgrid = (unsigned)std::max<u64>(1, std::min<u64>((max_ndet + 255) / 256, (u64)num_cu * 8));
+    const u64 nch = select_chunks(max_ndet);
+    // the dense pass: the binade of the M-th |c|, then every entry at or above
+    // it compacted into the candidate list by rank (the accumulator zeroed)
+    hipLaunchKernelGGL(k_bsel_init, dim3(1, N), dim3(256), 0, st, d, 0, all);
+    hipLaunchKernelGGL(k_bsel_hist_dense, dim3(hgrid, N), dim3(256), 0, st, d, 0);
+    hipLaunchKernelGGL(k_bsel_pick, dim3(1, N), dim3(PICK_T), 0, st, d, 0, 0);
+    hipLaunchKernelGGL(k_bsel_cand_bound, dim3(1, N), dim3(64), 0, st, d, band);
+    hipLaunchKernelGGL(k_bcompact_count_dense, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
+    bscan_u64(st, d_scan_dense, n, nch);
+    hipLaunchKernelGGL(k_bcompact_write_dense, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
+    // the full selection on the candidate list
+    hipLaunchKernelGGL(k_bsel_init, dim3(1, N), dim3(256), 0, st, d, 1, all);
+    for (int L = 0; L < max_ndig; ++L) {
+        hipLaunchKernelGGL(k_bsel_hist_list, dim3(hgrid, N), dim3(256), 0, st, d, L);
+        hipLaunchKernelGGL(k_bsel_pick, dim3(1, N), dim3(PICK_T), 0, st, d, 1, L);
+    }
+    hipLaunchKernelGGL(k_bsel_min_list, dim3(hgrid, N), dim3(256), 0, st, d);
+    if (band) {
+        hipLaunchKernelGGL(k_bsel_thr, dim3(1, N), dim3(64), 0, st, d);
+        hipLaunchKernelGGL(k_bsel_count_thr_list, dim3(hgrid, N), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_bsel_mode, dim3(1, N), dim3(64), 0, st, d);
+    }
+    hipLaunchKernelGGL(k_bcompact_count_list, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
+    bscan_u64(st, d_scan_list, n, nch);
+    hipLaunchKernelGGL(k_bcopy_count, dim3(1, N), dim3(64), 0, st, d, out_kind, j);
+    hipLaunchKernelGGL(k_bcompact_write_list, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d, out_kind, j);
+    SFCI_CHECK_HIP(hipGetLastError());
 }

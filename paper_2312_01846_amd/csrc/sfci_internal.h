@@ -280,6 +280,66 @@ struct CandSrc {
     const u64* lcount;    // device scalar
     u64 lcap;
 };
+// ---- batched iteration steps: one launch serves every instance ----
+// One instance of a batch, in a device array indexed by blockIdx.y: its basis
+// vectors, dense accumulator, block matrices, and selection workspaces.
+struct BInst {
+    u64* Wr;                  // basis vector l: ranks Wr + l cap, amplitudes Wa + l cap, count sc[l]
+    double* Wa;
+    u64* sc;
+    u64 cap;
+    double* D;                // dense accumulator, N_det doubles (all zero between steps)
+    u64 Ndet;
+    double* T;                // n_L x n_L, T[l n_L + j]
+    double* S;
+    double* x;                // block end: the lowest eigenvector, its eigenvalue, energies[*blk]
+    double* lam;
+    double* energies;
+    int* blk;
+    int* status;
+    double* red;              // reduction partials, bstep_red_doubles(n_L)
+    SelState* st;             // selection on the dense accumulator, then on the candidate list
+    SelState* st2;
+    u64* cr;                  // candidate list (N_det capacity)
+    double* ca;
+    u64* cnt;                 // per-chunk counts (select chunks of N_det) and their scan's block sums
+    u64* bsum;
+    u64* psi_r;               // the final Psi of the last block
+    double* psi_a;
+    u64* psi_n;
+    u64 M;                    // truncation (UINT64_MAX: every nonzero entry)
+    u64 ndet_m1;              // key geometry of the selection
+    int rank_bits;
+    int nL;
+};
+// Where a batched selection writes: w_{j+1}, w_0 (a block end) or Psi.
+enum { BOUT_NEXT = 0, BOUT_W0 = 1, BOUT_PSI = 2 };
+u64 bstep_red_doubles(int nL);
+// T[l][j] = T[j][l] = <w_l|D> and S[l][j] = S[j][l] = <w_l|w_j> for l <= j
+void bstep_dots(hipStream_t st, const BInst* d, int n, int j, int nL);
+// kind 0: D -= T[l][j] w_l;  kind 1: D += x[l] w_l
+void bstep_axpy(hipStream_t st, const BInst* d, int n, int l, int j, int kind, u64 max_cap);
+// Eq. 11 on the selection's output vector
+void bstep_normalise(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_cap);
+void bstep_fill_zero(hipStream_t st, const BInst* d, int n, u64 max_ndet);
+void bstep_geneig(hipStream_t st, const BInst* d, int n, int nL);
+void bstep_inc_blk(hipStream_t st, const BInst* d, int n);
+// Exclusive scans of u64 counts, one per job: out[i] = sum in[0..i), *total = sum (may be null).
+struct BScanJob {
+    const u64* in;
+    u64* out;
+    u64 n;
+    u64* bsum;  // scan_block_sums(n) words
+    u64* total;
+};
+void bscan_u64(hipStream_t st, const BScanJob* d_jobs, int n_jobs, u64 max_n);
+// select_topm of every instance's dense accumulator (zeroed on the way) into
+// the out_kind vector, keeping M entries (all != 0: every nonzero entry);
+// scan jobs: the accumulator's chunk counts (total to st->count_cand) and the
+// candidate list's (total to st2->count_out).
+void bstep_select(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_ndet, int num_cu, int band,
+                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all);
+
 // Select the M largest (|c|, then lower rank) nonzero candidates and write them
 // by ascending rank to (out_rank, out_amp); *out_count_dev receives the count.
 // If zero_dense, the dense source is cleared to 0.0 in the same pass.

@@ -45,9 +45,9 @@ __device__ __forceinline__ u64 block_excl_scan(u64 x, u64* sh, u64* total) {
     return pre + inc - x;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const u64* __restrict__ in, u64 n, u64* __restrict__ bsum) {
+__device__ __forceinline__ void scan_reduce_body(const u64* __restrict__ in, u64 n, u64* __restrict__ bsum, unsigned bx) {
     __shared__ u64 sh[SCAN_BLOCK / 64];
-    const u64 base = (u64)blockIdx.x * SCAN_TILE;
+    const u64 base = (u64)bx * SCAN_TILE;
     u64 s = 0;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -60,12 +60,16 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const u64* __restric
     if (threadIdx.x == 0) {
         u64 t = 0;
         for (int k = 0; k < SCAN_BLOCK / 64; ++k) t += sh[k];
-        bsum[blockIdx.x] = t;
+        bsum[bx] = t;
     }
 }
 
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const u64* __restrict__ in, u64 n, u64* __restrict__ bsum) {
+    scan_reduce_body(in, n, bsum, blockIdx.x);
+}
+
 // Single block: exclusive scan of nb block sums in place, total to *total.
-__global__ __launch_bounds__(TOP_BLOCK) void k_scan_top(u64* __restrict__ bsum, u64 nb, u64* __restrict__ total) {
+__device__ __forceinline__ void scan_top_body(u64* __restrict__ bsum, u64 nb, u64* __restrict__ total) {
     __shared__ u64 sh[TOP_BLOCK / 64];
     u64 carry = 0;
     for (u64 base = 0; base < nb; base += TOP_BLOCK) {
@@ -79,13 +83,17 @@ __global__ __launch_bounds__(TOP_BLOCK) void k_scan_top(u64* __restrict__ bsum, 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+__global__ __launch_bounds__(TOP_BLOCK) void k_scan_top(u64* __restrict__ bsum, u64 nb, u64* __restrict__ total) {
+    scan_top_body(bsum, nb, total);
+}
+
 // Each thread scans SCAN_ITEMS consecutive counts.  in and out may be the
 // same array (every thread reads its own counts before writing them).
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const u64* in, u64 n, const u64* __restrict__ boff,
-                                                          u64* out) {
+__device__ __forceinline__ void scan_down_body(const u64* in, u64 n, const u64* __restrict__ boff, u64* out,
+                                               unsigned bx) {
     __shared__ u64 sh[SCAN_BLOCK / 64];
-    const u64 first = (u64)blockIdx.x * SCAN_TILE + (u64)threadIdx.x * SCAN_ITEMS;
-    const bool full = (u64)(blockIdx.x + 1) * SCAN_TILE <= n;
+    const u64 first = (u64)bx * SCAN_TILE + (u64)threadIdx.x * SCAN_ITEMS;
+    const bool full = (u64)(bx + 1) * SCAN_TILE <= n;
     u64 v[SCAN_ITEMS];
     u64 s = 0;
     if (full) {
@@ -98,7 +106,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const u64* in, u64 n, 
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
     u64 tot;
-    u64 run = boff[blockIdx.x] + block_excl_scan<SCAN_BLOCK>(s, sh, &tot);
+    u64 run = boff[bx] + block_excl_scan<SCAN_BLOCK>(s, sh, &tot);
     if (full) {
 #pragma unroll
         for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -111,6 +119,29 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const u64* in, u64 n, 
             run += v[k];
         }
     }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_down(const u64* in, u64 n, const u64* __restrict__ boff,
+                                                          u64* out) {
+    scan_down_body(in, n, boff, out, blockIdx.x);
+}
+
+// One scan per job (blockIdx.y); blocks past a job's own size return at once.
+__global__ __launch_bounds__(SCAN_BLOCK) void k_bscan_reduce(const BScanJob* __restrict__ jobs) {
+    const BScanJob J = jobs[blockIdx.y];
+    if ((u64)blockIdx.x * SCAN_TILE >= (J.n ? J.n : 1)) return;  // n = 0: block 0 writes a zero sum
+    scan_reduce_body(J.in, J.n, J.bsum, blockIdx.x);
+}
+
+__global__ __launch_bounds__(TOP_BLOCK) void k_bscan_top(const BScanJob* __restrict__ jobs) {
+    const BScanJob J = jobs[blockIdx.y];
+    scan_top_body(J.bsum, (J.n + SCAN_TILE - 1) / SCAN_TILE, J.total);
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_bscan_down(const BScanJob* __restrict__ jobs) {
+    const BScanJob J = jobs[blockIdx.y];
+    if ((u64)blockIdx.x * SCAN_TILE >= J.n) return;
+    scan_down_body(J.in, J.n, J.bsum, J.out, blockIdx.x);
 }
 
 unsigned grid1d(u64 n, u64 per, u64 cap = 65536) {
@@ -142,5 +173,13 @@ void exclusive_scan_u64(sfci_problem* P, const u64* in, u64* out, u64 n, u64* to
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TOP_BLOCK), 0, P->stream, bsum, nb, total_dev);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, P->stream, in, n, bsum, out);
+    SFCI_CHECK_HIP(hipGetLastError());
+}
+
+void bscan_u64(hipStream_t st, const BScanJob* d_jobs, int n_jobs, u64 max_n) {
+    const u64 nb = scan_block_sums(max_n);
+    hipLaunchKernelGGL(k_bscan_reduce, dim3((unsigned)nb, (unsigned)n_jobs), dim3(SCAN_BLOCK), 0, st, d_jobs);
+    hipLaunchKernelGGL(k_bscan_top, dim3(1, (unsigned)n_jobs), dim3(TOP_BLOCK), 0, st, d_jobs);
+    hipLaunchKernelGGL(k_bscan_down, dim3((unsigned)nb, (unsigned)n_jobs), dim3(SCAN_BLOCK), 0, st, d_jobs);
     SFCI_CHECK_HIP(hipGetLastError());
 }
