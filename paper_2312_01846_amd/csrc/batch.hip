@@ -386,7 +386,7 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             launch_add_u64(I[k].P, I[k].sc + 35, I[k].sc + j);
             DVec w = I[k].W(j);
             descs[k] = rowtile_prepare(I[k].P, SigmaLaunch{w.r, w.a, w.nnz, w.cap}, I[k].P->d_D,
-                                       (unsigned long long*)(I[k].sc + 32), o->screen_eps);
+                                       (unsigned long long*)(I[k].sc + 32), o->screen_eps, false, batched_rest);
         });
         for (int k = 0; k < n; ++k) {
             pre[k + 1] = pre[k] + descs[k].n_items;
@@ -487,8 +487,9 @@ sfci_status sfci_batch_lanczos(sfci_batch* B, const sfci_svec* v0s, const uint64
             if (j + 1 < nL) {
                 bstep_axpy(st, d_bi, n, j, j, 0, max_cap);
                 if (j >= 1) bstep_axpy(st, d_bi, n, j - 1, j, 0, max_cap);
+                // D is left as it is: the next sigma launch writes every row (full_rows)
                 bstep_select(st, d_bi, n, BOUT_NEXT, j, max_ndet, B->P[0]->num_cu, band, max_ndig, d_scan_dense,
-                             d_scan_list, 0);
+                             d_scan_list, 0, false);
                 bstep_normalise(st, d_bi, n, BOUT_NEXT, j, max_cap);
             } else {
                 bstep_fill_zero(st, d_bi, n, max_ndet);

@@ -67,7 +67,8 @@ struct RTParams {
                                  // while the records are built, longer ones by wavefront in the direct phase
     u32 pair_half;               // gradient passes with sbar a multiple of v: a pair of distinct rows is
                                  // visited once, from the lower source rank, and counted twice
-    u32 pad_ph;
+    u32 full_rows;               // sigma into D: rows no term reaches are written as zeros too, so D
+                                 // need not be zero before the launch
     // Rows of several tiles (sigma): the alpha-beta doubles' items of every
     // input chunk (up to AB_CHUNK consecutive entries of one alpha row), by
     // target tile: the items of (chunk c, tile t) are ab_it[ab_off[c ntiles
@@ -576,7 +577,14 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         ph_add(timing, 0);
         const unsigned n1 = s_nlist, nlist = s_nlist + s_nlist2;
         auto rec = [&](unsigned li) -> const NbrRec& { return list[li < n1 ? li : nbr_cap - 1 - (li - n1)]; };
-        if (nlist == 0 && !s_touched) continue;  // nothing lands here: D stays zero
+        if (nlist == 0 && !s_touched) {
+            // nothing lands here: D keeps its zeros, or gets them (full_rows)
+            if (!GRAD && p.full_rows && !p.fo) {
+                double* dst = p.D + (rAt - p.row_base) * Nb + tlo;
+                for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) dst[x] = 0.0;
+            }
+            continue;
+        }
         if (threadIdx.x == 0) s_touched = 1;
 
         // Phase 2: direct targets (beta unchanged).  Short ranges: one thread
@@ -1994,7 +2002,7 @@ static void build_ab_lists(sfci_problem* P, RowTileState* S, const SigmaLaunch& 
 // entry offsets and beta strings of the input vector; returns the kernel's
 // description of this instance.  rowtile_available(P) must hold.
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted, double eps,
-                            bool ab_lists) {
+                            bool ab_lists, bool full_rows) {
     RowTileState* S = rt_state(P);
     const u64 cap = std::max<u64>(1, v.cap);
     const u64 nt1 = (u64)S->ntiles + 1;
@@ -2068,7 +2076,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     // SFCI_SHORT_DOUBLE overrides.
     rp.short_dbl = (S->ntiles == 1) ? 8u : 32u;
     rp.pair_half = 0;
-    rp.pad_ph = 0;
+    rp.full_rows = full_rows ? 1u : 0u;
     if (const char* env = getenv("SFCI_SHORT_DOUBLE")) rp.short_dbl = (u32)std::max(0, atoi(env));
     out.n_items = P->Na * (u64)((S->ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);

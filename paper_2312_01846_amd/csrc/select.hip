@@ -451,10 +451,11 @@ __global__ __launch_bounds__(CBLOCK) void k_bcompact_count_dense(const BInst* __
     compact_count_body(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), b.cnt, blockIdx.x);
 }
 
+template <bool ZERO>
 __global__ __launch_bounds__(CBLOCK) void k_bcompact_write_dense(const BInst* __restrict__ B) {
     const BInst& b = B[blockIdx.y];
     if (blockIdx.x >= bchunks(b)) return;
-    compact_write_body<DenseSrc, true>(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), b.cnt, b.cr, b.ca, b.D, blockIdx.x);
+    compact_write_body<DenseSrc, ZERO>(DenseSrc{b.D, b.Ndet}, b.st, bgeo(b), b.cnt, b.cr, b.ca, b.D, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_bsel_min_list(const BInst* __restrict__ B) {
@@ -625,7 +626,7 @@ void select_topm(sfci_problem* P, const CandSrc& src, u64 M, u64* out_rank, doub
 }
 
 void bstep_select(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_ndet, int num_cu, int band,
-                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all) {
+                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all, bool zero) {
     const unsigned N = (unsigned)n;
     const unsigned hgrid = (unsigned)std::max<u64>(1, std::min<u64>((max_ndet + 255) / 256, (u64)num_cu * 8));
     const u64 nch = select_chunks(max_ndet);
@@ -637,7 +638,8 @@ void bstep_select(hipStream_t st, const BInst* d, int n, int out_kind, int j, u6
     hipLaunchKernelGGL(k_bsel_cand_bound, dim3(1, N), dim3(64), 0, st, d, band);
     hipLaunchKernelGGL(k_bcompact_count_dense, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
     bscan_u64(st, d_scan_dense, n, nch);
-    hipLaunchKernelGGL(k_bcompact_write_dense, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
+    if (zero) hipLaunchKernelGGL(k_bcompact_write_dense<true>, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
+    else hipLaunchKernelGGL(k_bcompact_write_dense<false>, dim3((unsigned)nch, N), dim3(CBLOCK), 0, st, d);
     // the full selection on the candidate list
     hipLaunchKernelGGL(k_bsel_init, dim3(1, N), dim3(256), 0, st, d, 1, all);
     for (int L = 0; L < max_ndig; ++L) {

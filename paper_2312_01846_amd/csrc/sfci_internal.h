@@ -194,8 +194,10 @@ struct RowTileTune {
 };
 // ab_lists: for rows of several tiles, also list the alpha-beta doubles' items
 // per (input chunk, target tile) for the sigma kernel (when they fit in memory).
+// full_rows: every target row of D is written (zeros where no term lands), so
+// D need not be zero before the launch.
 RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, unsigned long long* emitted,
-                            double eps = 0.0, bool ab_lists = false);
+                            double eps = 0.0, bool ab_lists = false, bool full_rows = false);
 size_t rowtile_desc_bytes();
 // Target alpha rows [lo, hi) of a prepared description only, written into
 // Dp[rank - lo * N_beta] (touched tiles are overwritten, the rest is left
@@ -333,12 +335,12 @@ struct BScanJob {
     u64* total;
 };
 void bscan_u64(hipStream_t st, const BScanJob* d_jobs, int n_jobs, u64 max_n);
-// select_topm of every instance's dense accumulator (zeroed on the way) into
-// the out_kind vector, keeping M entries (all != 0: every nonzero entry);
+// select_topm of every instance's dense accumulator (zeroed on the way unless
+// !zero) into the out_kind vector, keeping M entries (all != 0: every nonzero entry);
 // scan jobs: the accumulator's chunk counts (total to st->count_cand) and the
 // candidate list's (total to st2->count_out).
 void bstep_select(hipStream_t st, const BInst* d, int n, int out_kind, int j, u64 max_ndet, int num_cu, int band,
-                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all);
+                  int max_ndig, const BScanJob* d_scan_dense, const BScanJob* d_scan_list, int all, bool zero = true);
 
 // Select the M largest (|c|, then lower rank) nonzero candidates and write them
 // by ascending rank to (out_rank, out_amp); *out_count_dev receives the count.
