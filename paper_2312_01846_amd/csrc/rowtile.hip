@@ -69,6 +69,9 @@ struct RTParams {
                                  // visited once, from the lower source rank, and counted twice
     u32 full_rows;               // sigma into D: rows no term reaches are written as zeros too, so D
                                  // need not be zero before the launch
+    u32 gs_min;                  // sigma, alpha-beta doubles: a source row's (ia|jb) slab is staged in LDS
+                                 // when it has more than this many entries (else elements are read globally)
+    u32 pad_gs;
     // Rows of several tiles (sigma): the alpha-beta doubles' items of every
     // input chunk (up to AB_CHUNK consecutive entries of one alpha row), by
     // target tile: the items of (chunk c, tile t) are ab_it[ab_off[c ntiles
@@ -985,7 +988,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             const int T = r.type;
             const int I_ = r.i, A_ = r.a;
             double* slab = wslab;  // gradient: this row's (j, b) weights; sigma: the (ia|..) slab
-            const bool gs = !GRAD && T == 1 && slab_n2 != 0;
+            const bool gs = !GRAD && T == 1 && slab_n2 != 0 && r.rowe - r.rowb > p.gs_min;
             if (gs) {
                 // stage this source row's alpha single's (ia|jb) as slab[j n + b]
                 // (the index a table entry carries), with the alpha single's
@@ -2077,6 +2080,14 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     rp.short_dbl = (S->ntiles == 1) ? 8u : 32u;
     rp.pair_half = 0;
     rp.full_rows = full_rows ? 1u : 0u;
+    // one-tile rows: a source row of at most 32 entries reads its elements from
+    // global memory (staging n^2 of them would cost more than its terms);
+    // measured on the 32-instance benchmark: thresholds 0, 4, 16, 32, 64, 256
+    // and never staged give 1086, 1074, 1071, 1070, 1072, 1100 and 1180 ms of
+    // sigma per run.  SFCI_GS_MIN overrides.
+    rp.gs_min = (S->ntiles == 1) ? 32u : 0u;
+    if (const char* env = getenv("SFCI_GS_MIN")) rp.gs_min = (u32)std::max(0, atoi(env));
+    rp.pad_gs = 0;
     if (const char* env = getenv("SFCI_SHORT_DOUBLE")) rp.short_dbl = (u32)std::max(0, atoi(env));
     out.n_items = P->Na * (u64)((S->ntiles + rp.tile_chunk - 1) / rp.tile_chunk);
     out.nbr_cap = 1 + (u64)na * nva + (u64)(na * (na - 1) / 2) * (u64)(nva * (nva - 1) / 2);

@@ -169,7 +169,7 @@ void launch_sigma_rowtile(sfci_problem* P, const SigmaLaunch& v, double* D, unsi
 // Batched form: prepare each instance, put the descriptions on the device,
 // then one launch drains the items of all instances.
 struct RowTileDesc {
-    alignas(8) unsigned char raw[320];  // kernel-side description of one instance
+    alignas(8) unsigned char raw[384];  // kernel-side description of one instance
     u64 n_items, nbr_cap;
     size_t lds_bytes;  // the tile
     unsigned n2;       // n^2 of the instance
