@@ -28,6 +28,7 @@ namespace {
 
 constexpr int RT_WAVES = 16;
 constexpr int RT_BLOCK = 64 * RT_WAVES;
+constexpr int RT_PH = 10;  // phase-timing bins
 
 struct RTParams {
     SpaceDev sp;
@@ -81,10 +82,11 @@ struct RTParams {
     const u32* ab_it;
     const u64* ab_off;
     const u64* ab_rowchunk;
-    // sigma: optional per-phase wavefront time (wall clock ticks), 8 bins
+    // sigma: optional per-phase wavefront time (wall clock ticks), RT_PH bins
     // summed over wavefronts: neighbour records, direct targets, alpha-beta
     // units, identity beta-single units, beta-beta units, barrier wait and
-    // tile write, other units, work fetch.  nullptr = off.
+    // tile write, other units, work fetch, tile clearing, the wait at the end
+    // of the records.  nullptr = off.
     unsigned long long* phase_ns;
     const FusedOut* fo;  // sigma: finished tiles go here instead of D (nullptr: written to D)
 };
@@ -219,6 +221,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     __shared__ unsigned s_nbr, s_nlist, s_nlist2, s_next, s_next2, s_touched, s_idb, s_ide;
     __shared__ u64 s_item, s_left;  // current item (row * ntiles + tile); tiles of its row still to do
     __shared__ int s_inst, s_cur;
+    __shared__ u64 s_pfx0, s_pfx1;  // the loaded instance's items [s_pfx0, s_pfx1)
     // sigma with several tiles per row: the row's neighbour records, kept
     // across its tiles (tile-independent parts; entry ranges refreshed per tile)
     __shared__ u64 s_cache_row;
@@ -229,15 +232,16 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     __shared__ unsigned s_nrow, s_nrow2;
     __shared__ u32 s_row_idb, s_row_ide;
     __shared__ RTParams p;
-    __shared__ unsigned long long s_ph[RT_WAVES][8];
+    // phase timing (timed build only): per wavefront, RT_PH bins
+    __shared__ unsigned long long s_ph[TIMED ? RT_WAVES : 1][TIMED ? RT_PH : 1];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < RT_WAVES * 8) s_ph[threadIdx.x >> 3][threadIdx.x & 7] = 0;
+    if (TIMED && threadIdx.x < RT_WAVES * RT_PH) s_ph[threadIdx.x / RT_PH][threadIdx.x % RT_PH] = 0;
     u64 t_mark = 0;  // phase timing: the last timestamp of this wavefront
     auto ph_add = [&](bool on, int bin) {
         if (on) {
             const u64 now = wall_clock64();
-            if (lane == 0 && t_mark) s_ph[wave][bin] += now - t_mark;
+            if (TIMED && lane == 0 && t_mark) s_ph[TIMED ? wave : 0][TIMED ? bin : 0] += now - t_mark;
             t_mark = now;
         }
     };
@@ -316,8 +320,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 s_left -= 1;
             } else {
                 const u64 it = atomicAdd(counter, 1u);
+                // a unit of the loaded instance needs no global reads
+                const bool cur = s_cur >= 0 && it >= s_pfx0 && it < s_pfx1;
                 int k = s_cur > 0 ? s_cur : 0;
-                if (it < total_items)
+                if (!cur && it < total_items)
                     while (k + 1 < n_inst && item_prefix[k + 1] <= it) ++k;
                 s_item = ~0ull;
                 s_left = 0;
@@ -325,10 +331,12 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                     // unit -> (row, chunk of tile_chunk tiles), chunk-major: units
                     // running together share their tiles (and the tiles' entry
                     // boundaries, rtb's rows for those tiles, stay in cache)
-                    const u64 nt = (u64)descs[k].ntiles, C = (u64)descs[k].tile_chunk;
+                    const u64 nt = cur ? (u64)p.ntiles : (u64)descs[k].ntiles;
+                    const u64 C = cur ? (u64)p.tile_chunk : (u64)descs[k].tile_chunk;
+                    const u64 lo = cur ? s_pfx0 : item_prefix[k], hi = cur ? s_pfx1 : item_prefix[k + 1];
                     const u64 nch = (nt + C - 1) / C;
-                    const u64 u = it - item_prefix[k];
-                    const u64 rows = (item_prefix[k + 1] - item_prefix[k]) / nch;
+                    const u64 u = it - lo;
+                    const u64 rows = (hi - lo) / nch;
                     const u64 ch = u / rows, row = u - ch * rows;
                     s_item = row * nt + ch * C;
                     s_left = min(C, nt - ch * C) - 1;
@@ -376,7 +384,11 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 }
                 for (int t = threadIdx.x; t < n_; t += RT_BLOCK) itab[2 * n2_ + t] = p.I.H(t, t);
             }
-            if (threadIdx.x == 0) s_cur = s_inst;
+            if (threadIdx.x == 0) {
+                s_cur = s_inst;
+                s_pfx0 = item_prefix[s_inst];
+                s_pfx1 = item_prefix[s_inst + 1];
+            }
             __syncthreads();
         }
         const bool timing = TIMED && !GRAD && p.phase_ns != nullptr;
@@ -392,9 +404,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         const u64 item = s_item + p.item_base;
         const u64 rAt = item / (u64)p.ntiles;
         const int tile = (int)(item - rAt * (u64)p.ntiles);
-        const u64 tlo = p.tile_lo[tile], thi = p.tile_lo[tile + 1];
+        const u64 tlo = whole_rows ? 0 : p.tile_lo[tile], thi = whole_rows ? Nb : p.tile_lo[tile + 1];
         const int tsz = (int)(thi - tlo);
-        const u32 At = str_unrank(rAt, na, n, sB);
+        const u32 At = str_unrank_wave(rAt, na, n, sB);
         if (threadIdx.x < (unsigned)n) {
             int q = threadIdx.x;
             u32 below = (1u << q) - 1u;
@@ -408,6 +420,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (int x = threadIdx.x; x < tsz; x += RT_BLOCK) acc[x] = 0.0;
         }
         __syncthreads();
+        ph_add(timing, 8);
         if (!GRAD && ja_off) {
             // read in phase 3, after phase 1's barrier
             const u32 n2 = (u32)n * n;
@@ -576,8 +589,9 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             for (u32 m = At; m; m &= m - 1u) x += p.I.H(__builtin_ctz(m), __builtin_ctz(m));
             itab[2 * n * n + 32] = x;
         }
-        __syncthreads();
         ph_add(timing, 0);
+        __syncthreads();
+        ph_add(timing, 9);
         const unsigned n1 = s_nlist, nlist = s_nlist + s_nlist2;
         auto rec = [&](unsigned li) -> const NbrRec& { return list[li < n1 ? li : nbr_cap - 1 - (li - n1)]; };
         if (nlist == 0 && !s_touched) {
@@ -867,8 +881,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         const unsigned n_b1 = (!GRAD && ide > idb) ? (ide - idb + b1_chunk - 1) / b1_chunk : 0u;
         const unsigned n_bb = (!GRAD && PB > 0 && QB > 0) ? (ide - idb + bb_chunk - 1) / bb_chunk : 0u;
         const unsigned n_units = (MODE == RT_GRAD_B) ? 0u : n1 + n_b1 + n_bb;
-        const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank(tlo, nb, n, sB)) : 0;
-        const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank(thi - 1, nb, n, sB)) : 0;
+        const int top_lo = (nb > 0) ? 31 - __clz((int)str_unrank_wave(tlo, nb, n, sB)) : 0;
+        const int top_hi = (nb > 0) ? 31 - __clz((int)str_unrank_wave(thi - 1, nb, n, sB)) : 0;
         int ph_bin = 6;
         for (;;) {
             unsigned li = 0;
@@ -1439,8 +1453,8 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
     }
     if (TIMED && !GRAD && s_cur >= 0 && p.phase_ns) {
         __syncthreads();
-        if (threadIdx.x < RT_WAVES * 8 && s_ph[threadIdx.x >> 3][threadIdx.x & 7])
-            atomicAdd(p.phase_ns + (threadIdx.x & 7), s_ph[threadIdx.x >> 3][threadIdx.x & 7]);
+        if (threadIdx.x < RT_WAVES * RT_PH && s_ph[threadIdx.x / RT_PH][threadIdx.x % RT_PH])
+            atomicAdd(p.phase_ns + (threadIdx.x % RT_PH), s_ph[threadIdx.x / RT_PH][threadIdx.x % RT_PH]);
     }
     if (lane == 0) my_terms += wterms;
     for (int off = 32; off >= 1; off >>= 1) my_terms += __shfl_xor(my_terms, off);
@@ -2062,7 +2076,7 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     if (const char* env = getenv("SFCI_RT_PHASES"))
         if (env[0] == '1') {
             if (!P->ws_rt_phase.p) {
-                launch_fill_u64((u64*)P->ws_rt_phase.get(8 * sizeof(u64)), 8, 0, P->stream);
+                launch_fill_u64((u64*)P->ws_rt_phase.get(RT_PH * sizeof(u64)), RT_PH, 0, P->stream);
             }
             rp.phase_ns = (unsigned long long*)P->ws_rt_phase.p;
         }
@@ -2155,17 +2169,17 @@ size_t rowtile_scratch_bytes(unsigned grid, u64 nbr_cap) { return (size_t)grid *
 // report, printed to stderr as shares (a diagnostic; it synchronises the stream).
 static void report_phases(sfci_problem* P, const char* what) {
     if (!P->ws_rt_phase.p) return;
-    u64 h[8] = {};
+    u64 h[RT_PH] = {};
     SFCI_CHECK_HIP(hipMemcpyAsync(h, P->ws_rt_phase.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
-    launch_fill_u64((u64*)P->ws_rt_phase.p, 8, 0, P->stream);
+    launch_fill_u64((u64*)P->ws_rt_phase.p, RT_PH, 0, P->stream);
     double tot = 0;
     for (u64 x : h) tot += (double)x;
     if (tot <= 0) return;
-    static const char* names[8] = {"records", "direct", "alpha-beta", "id-beta-singles", "beta-beta",
-                                   "wait+write", "other-units", "fetch"};
+    static const char* names[RT_PH] = {"records", "direct", "alpha-beta", "id-beta-singles", "beta-beta",
+                                       "wait+write", "other-units", "fetch", "clear", "records-wait"};
     std::fprintf(stderr, "# tile kernel phases (%s, %.3g wave-ticks):", what, tot);
-    for (int k = 0; k < 8; ++k) std::fprintf(stderr, " %s %.1f%%", names[k], 100.0 * (double)h[k] / tot);
+    for (int k = 0; k < RT_PH; ++k) std::fprintf(stderr, " %s %.1f%%", names[k], 100.0 * (double)h[k] / tot);
     std::fprintf(stderr, "\n");
 }
 

@@ -60,6 +60,23 @@ __device__ __forceinline__ u32 str_unrank(u64 r, int k, int n, const BinomLds& B
     return bits;
 }
 
+// The same, by a whole wavefront (every lane active, every lane gets the
+// string): electron t's orbital is the highest c below the previous one with
+// C(c, t) <= r, found by one ballot over lanes c instead of a downward scan.
+__device__ __forceinline__ u32 str_unrank_wave(u64 r, int k, int n, const BinomLds& B) {
+    const int lane = (int)(threadIdx.x & 63u);
+    u32 bits = 0;
+    int hi = n;
+    for (int t = k; t >= 1; --t) {
+        const bool ok = lane < hi && B.c[lane][t] <= r;
+        const int c = 63 - __clzll((long long)__ballot(ok));  // C(c, t) = 0 <= r for c < t: never empty
+        bits |= 1u << c;
+        r -= B.c[c][t];
+        hi = c;
+    }
+    return bits;
+}
+
 // Parity of the occupied orbitals strictly between i and a (i != a).
 __device__ __forceinline__ int between_parity(u32 S, int i, int a) {
     int lo = i < a ? i : a, hi = i < a ? a : i;
