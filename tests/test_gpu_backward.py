@@ -202,7 +202,11 @@ def test_energy_gradients_call_matches_oracle(torch, S, orc, det):
     assert np.allclose(_np(dh), oh, rtol=1e-9, atol=1e-12)
     assert np.allclose(_np(dg), og, rtol=1e-9, atol=1e-12)
     E2, dh2, dg2 = P.energy_gradients(r.astype(np.int64), a, deterministic=det, want_grad=False)
-    assert E2 == E and dh2 is None and dg2 is None
+    assert dh2 is None and dg2 is None
+    if det:
+        assert E2 == E
+    else:  # the tile kernel's LDS adds run in no fixed order: equal to rounding
+        assert abs(E2 - E) <= 1e-12 * abs(E)
     with pytest.raises(S.SfciError) as e:
         P.energy_gradients(np.zeros(0, dtype=np.int64), np.zeros(0))
     assert e.value.code == -1
