@@ -175,6 +175,21 @@ def test_batch_perturbed_start_goldens(torch, S, det):
         assert np.all(np.abs(E[1] - np.array(g15["energies"])) < 1e-9)
 
 
+def test_batch_per_instance_vector_steps(torch, S, monkeypatch):
+    # SFCI_BATCH_REST=0: the vector steps run per instance (the path the
+    # deterministic and atomic modes take) around the same batched tile
+    # launches; energies against the oracle's iteration with the band
+    monkeypatch.setenv("SFCI_BATCH_REST", "0")
+    g31, g15 = _gold("c4pband_inst31_M3e3_30"), _gold("c4pband_inst15_M1e4_30")
+    P31, _, _ = _c4(S, 31)
+    P15, _, _ = _c4(S, 15)
+    out = S.Batch([P31, P15]).lanczos([_perturbed(P31), _perturbed(P15)], [g31["M"], g15["M"]], n_L=10, n_iter=30,
+                                      deterministic=False, want_grad=False, tie_band=True)
+    assert out["stats"]["batched_sigma"] == 1
+    for k, g in enumerate((g31, g15)):
+        assert np.all(np.abs(out["energies"][k] - np.array(g["energies"])) < 1e-9)
+
+
 def test_batch_repeat_and_shrink(torch, S):
     # a second call on the same batch with smaller truncations reuses the
     # workspaces; results equal a fresh batch's
