@@ -53,7 +53,9 @@ def parse():
                     help="timed Lanczos iterations, rounded up to whole blocks of n_L (default 30 for c4batch, "
                          "10 otherwise)")
     ap.add_argument("--warmup", type=int, default=10,
-                    help="warm-up Lanczos iterations, rounded up to whole blocks of n_L")
+                    help="warm-up Lanczos iterations, rounded up to whole blocks of n_L (c4batch: at least "
+                         "the timed iterations, so that the warm-up call captures the step graphs the timed "
+                         "call replays)")
     ap.add_argument("--workload", default="c4batch", choices=sorted(WORKLOADS) + ["c4batch"])
     ap.add_argument("--no-plain", action="store_true", help="c4batch: skip the plain-path comparison")
     ap.add_argument("--n-inst", type=int, default=32)
