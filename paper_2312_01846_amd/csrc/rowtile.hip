@@ -2084,14 +2084,18 @@ RowTileDesc rowtile_prepare(sfci_problem* P, const SigmaLaunch& v, double* D, un
     // work units: chunks of up to tile_chunk consecutive tiles of one target
     // row (a workgroup walks a chunk's tiles in turn, reusing the row's
     // neighbour records); SFCI_TILE_CHUNK overrides the default
-    unsigned chunk = 2;  // measured at 28 orbitals: 1, 2, 4, 7, 28 tiles -> 9.8, 9.0, 9.3, 10.7, 21.8 s
+    // (M = 1e7, sigma per step: 28 orbitals, 24 tiles a row: 2, 3, 4, 6 tiles -> 2.297, 2.242,
+    // 2.226, 2.232 s; 26 orbitals, 5 tiles: 1, 2, 3, 5 -> 0.351, 0.354, 0.356, 0.362 s)
+    unsigned chunk = (S->ntiles >= 16) ? 4u : 2u;
     if (const char* env = getenv("SFCI_TILE_CHUNK")) chunk = (unsigned)std::max(1, atoi(env));
     rp.tile_chunk = std::min<unsigned>(chunk, (unsigned)S->ntiles);
     // alpha doubles added while the records are built: one thread walks the
-    // entries (RT_UNROLL loads at a time), so only short ranges; whole rows
-    // hand ranges above 8 entries to the direct phase's wavefront stream.
-    // SFCI_SHORT_DOUBLE overrides.
-    rp.short_dbl = (S->ntiles == 1) ? 8u : 32u;
+    // entries (RT_UNROLL loads at a time), so only short ranges; ranges above
+    // 8 entries go to the direct phase's wavefront stream (rows of several
+    // tiles, M = 1e7: thresholds 4, 8, 16, 32, 64 give 2.297, 2.297, 2.315,
+    // 2.347, 2.393 s per sigma at 28 orbitals and 0.354, 0.354, 0.357, 0.366,
+    // 0.381 s at 26 orbitals).  SFCI_SHORT_DOUBLE overrides.
+    rp.short_dbl = 8u;
     rp.pair_half = 0;
     rp.full_rows = full_rows ? 1u : 0u;
     // one-tile rows: a source row of at most 32 entries reads its elements from
