@@ -1236,8 +1236,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 }
             } else if (!GRAD && T == 1 && p.ab_it) {
                 // Alpha-beta doubles of a row of several tiles: the source
-                // row's items that land in this tile, listed per input chunk;
-                // lanes over the items, RT_UNROLL groups of 64 loads in flight.
+                // row's items that land in this tile, listed per input chunk
+                // (the chunks' item ranges read 64 at a time, a chunk per
+                // lane); lanes over the items, RT_UNROLL groups of 64 loads in
+                // flight.
                 // The element is the staged slab's (alpha phase folded in) or
                 // (ia|jb) from global memory with the alpha phase; the beta
                 // phase flips the product's sign bit.
@@ -1249,32 +1251,42 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 const u64 c1 = c0 + (r.rowe - r.rowb + AB_CHUNK - 1) / AB_CHUNK;
                 const u32 pa_bit = (gs ? 0u : (u32)r.par) << 31;
                 const double eps_x = p.eps_x;
-                for (u64 c = c0; c < c1; ++c) {
-                    const u64 x0 = p.ab_off[c * nt + (u64)tile], x1 = p.ab_off[c * nt + (u64)tile + 1];
-                    const u64 kc = (u64)r.rowb + (c - c0) * AB_CHUNK;  // the chunk's first entry
-                    for (u64 xb = x0; xb < x1; xb += 64 * RT_UNROLL) {
-                        u32 it[RT_UNROLL];
+                for (u64 cb = c0; cb < c1; cb += 64) {
+                    // the item ranges in this tile of the row's next 64 chunks, one chunk per lane
+                    u64 xl0 = 0, xl1 = 0;
+                    if (cb + (u64)lane < c1) {
+                        xl0 = p.ab_off[(cb + (u64)lane) * nt + (u64)tile];
+                        xl1 = p.ab_off[(cb + (u64)lane) * nt + (u64)tile + 1];
+                    }
+                    const int ncb = (int)min((u64)64, c1 - cb);
+                    for (int jc = 0; jc < ncb; ++jc) {
+                        const u64 c = cb + (u64)jc;
+                        const u64 x0 = rl64(xl0, jc), x1 = rl64(xl1, jc);
+                        const u64 kc = (u64)r.rowb + (c - c0) * AB_CHUNK;  // the chunk's first entry
+                        for (u64 xb = x0; xb < x1; xb += 64 * RT_UNROLL) {
+                            u32 it[RT_UNROLL];
 #pragma unroll
-                        for (int u = 0; u < RT_UNROLL; ++u) {
-                            const u64 x = xb + (u64)u * 64 + lane;
-                            it[u] = (x < x1) ? itg[x] : 0u;
-                        }
-                        double e[RT_UNROLL], cc[RT_UNROLL];
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                const u64 x = xb + (u64)u * 64 + lane;
+                                it[u] = (x < x1) ? itg[x] : 0u;
+                            }
+                            double e[RT_UNROLL], cc[RT_UNROLL];
 #pragma unroll
-                        for (int u = 0; u < RT_UNROLL; ++u) {
-                            const u32 jb = (it[u] >> 14) & 1023u;
-                            e[u] = gs ? slab[jb] : grow[jb];
-                            cc[u] = ampg[kc + ((it[u] >> 24) & 63u)];
-                        }
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                const u32 jb = (it[u] >> 14) & 1023u;
+                                e[u] = gs ? slab[jb] : grow[jb];
+                                cc[u] = ampg[kc + ((it[u] >> 24) & 63u)];
+                            }
 #pragma unroll
-                        for (int u = 0; u < RT_UNROLL; ++u) {
-                            const bool act = xb + (u64)u * 64 + lane < x1;
-                            const double pr = e[u] * cc[u];
-                            const double t = __hiloint2double(
-                                __double2hiint(pr) ^ (int)((it[u] ^ pa_bit) & 0x80000000u), __double2loint(pr));
-                            const bool keep = act && !xscreened(t, eps_x);
-                            if (keep) atomicAdd(&acc[it[u] & 0x3FFFu], t);
-                            wterms += (u32)__popcll(__ballot(keep && e[u] != 0.0));
+                            for (int u = 0; u < RT_UNROLL; ++u) {
+                                const bool act = xb + (u64)u * 64 + lane < x1;
+                                const double pr = e[u] * cc[u];
+                                const double t = __hiloint2double(
+                                    __double2hiint(pr) ^ (int)((it[u] ^ pa_bit) & 0x80000000u), __double2loint(pr));
+                                const bool keep = act && !xscreened(t, eps_x);
+                                if (keep) atomicAdd(&acc[it[u] & 0x3FFFu], t);
+                                wterms += (u32)__popcll(__ballot(keep && e[u] != 0.0));
+                            }
                         }
                     }
                 }
