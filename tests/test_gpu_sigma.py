@@ -96,18 +96,26 @@ def test_sigma_matches_oracle(torch, S, orc, name, n, na, nb, mk, nnz, mode):
     assert st["candidates"] == len(orr)
 
 
+@pytest.mark.parametrize("chunk", [None, "4", "8"], ids=["unit_default", "unit4", "unit8"])
 @pytest.mark.parametrize("no_t2", ["0", "1"], ids=["bb_table", "bb_walk"])
 @pytest.mark.parametrize("lists", ["1", "0"], ids=["item_lists", "table_slices"])
-def test_sigma_multitile_rows(torch, S, orc, monkeypatch, support_band, lists, no_t2):
+def test_sigma_multitile_rows(torch, S, orc, monkeypatch, support_band, lists, no_t2, chunk):
     # Rows of several LDS tiles: 16 orbitals with 5 alpha and 5 beta electrons
     # (4 368 beta strings) in tiles of at most 1 024 ranks, five per row.  A
     # few alpha rows hold hundreds of entries (several 64-entry input chunks),
     # the rest are scattered.  The alpha-beta doubles come from the per
     # (chunk, tile) item lists or from each entry's table slice per tile; the
     # beta-beta doubles from the tile-grouped table or the on-the-fly walk.
+    # `chunk`: tiles of a row per work unit (the records are built at a unit's
+    # first tile and their tile boundaries kept for the others; 4 and 8 leave
+    # a short last unit of the five tiles).
+    if chunk is not None and (lists, no_t2) != ("1", "0"):
+        pytest.skip("unit sizes are varied on one path only")
     monkeypatch.setenv("SFCI_TILE_MAX", "1024")
     monkeypatch.setenv("SFCI_AB_LISTS", lists)
     monkeypatch.setenv("SFCI_NO_T2", no_t2)
+    if chunk is not None:
+        monkeypatch.setenv("SFCI_TILE_CHUNK", chunk)
     h, g = synth.molecule_like(16, 32, 11)
     P, Po = _prob(S, orc, 16, 5, 5, h, g)
     nb_ = 4368
