@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -92,7 +93,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sigma_rowtile_c4batch_traffic.m
 
 
 def measured_traffic():
-    """HBM bytes per k_sigma_rowtile launch from the committed counter summary
+    """HBM bytes per k_sigma_rowtile_whole launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel source
     has changed since the counters were taken."""
     import hashlib
@@ -181,7 +182,7 @@ def cpu_baseline(h, g, n, na, nb, ranks, amps, target_s):
 LDS_ADD_PEAK = 256 * 16 * 2.4e9
 
 
-def tile_roofline(st, alg_bytes, traffic, roof):
+def tile_roofline(st, alg_bytes, traffic, roof, kernel="k_sigma_rowtile"):
     """The tile kernel's roofline.  Every emitted term is one FP64 add into the
     workgroup's LDS tile (the accumulators never go to HBM), and the targets
     are random slots of the tile: the binding roof is the device's random
@@ -195,7 +196,7 @@ def tile_roofline(st, alg_bytes, traffic, roof):
     lds_peak = roof["lds_atomic_Gops"][1] * 1e9
     out = {
         "bound": "lds",
-        "kernel": "k_sigma_rowtile",
+        "kernel": kernel,
         "achieved": terms_s / 1e9,
         "peak": lds_peak / 1e9,
         "unit": "G FP64 LDS adds/s (one per emitted term; peak: random-slot ds_add_f64, measured)",
@@ -340,7 +341,10 @@ def main():
             "excited": excited,
             "parallelism": "single GPU",
         },
-        "roofline": (tile_roofline(st, alg_bytes, None, sfci.roof_probe(1 << 30))
+        # rows of at most 16 384 beta ranks are one LDS tile: the one-tile kernel runs
+        "roofline": (tile_roofline(st, alg_bytes, None, sfci.roof_probe(1 << 30),
+                                   kernel=("k_sigma_rowtile_whole" if math.comb(n, nb) <= 16384
+                                           else "k_sigma_rowtile"))
                      if (not args.det and args.dedup == "dense") else {
             "bound": "hbm",
             "kernel": "k_rs_scatter" if args.det else "k_sigma_dense",
@@ -461,7 +465,7 @@ def bench_batch(args, torch, sfci, synth):
             "batched_speedup_vs_plain": plain["speedup"] if plain else None,
             "parallelism": "single GPU",
         },
-        "roofline": tile_roofline(st, alg_bytes, traffic, roof),
+        "roofline": tile_roofline(st, alg_bytes, traffic, roof, kernel="k_sigma_rowtile_whole"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))

@@ -129,6 +129,10 @@ constexpr unsigned RT_BB_CHUNK = 4;
 constexpr unsigned RT_B1_CHUNK = 16;
 // Input entries whose table reads are issued together in the beta-single loop.
 constexpr int RT_UNROLL = 4;
+// Groups of 64 alpha-beta items whose loads are in flight together (rows of
+// several tiles; measured at 26 orbitals, M = 1e7: 4, 6, 8 groups -> 0.346,
+// 0.328, 0.330 s per sigma launch).
+constexpr int AB_UNROLL = 6;
 
 // Global-memory view of a device pointer (plain global loads, not flat ones).
 template <class T>
@@ -200,7 +204,7 @@ enum { RT_SIGMA = 0, RT_GRAD_A = 1, RT_GRAD_B = 2 };
 // One launch serves one or many problem instances: item i belongs to the
 // instance whose [item_prefix[k], item_prefix[k+1]) holds it; a workgroup
 // reloads the instance description when consecutive items change instance.
-template <int MODE, bool TIMED = false>
+template <int MODE, bool TIMED = false, bool WHOLE = false>
 __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs, const u64* __restrict__ item_prefix,
                                              int n_inst, unsigned* __restrict__ counter, void* nbr_scratch,
                                              u64 nbr_cap, unsigned slab_off, unsigned slab_n2, unsigned itab_off,
@@ -400,10 +404,10 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         const int PB = nb * (nb - 1) / 2, QB = nvb * (nvb - 1) / 2;
         const int sA = na * nva, sBn = p.sB;
         const u64 n_nbr = 1 + (u64)sA + (u64)PA * QA;
-        const bool whole_rows = (p.ntiles == 1);
+        const bool whole_rows = WHOLE || p.ntiles == 1;
         const u64 item = s_item + p.item_base;
-        const u64 rAt = item / (u64)p.ntiles;
-        const int tile = (int)(item - rAt * (u64)p.ntiles);
+        const u64 rAt = WHOLE ? item : item / (u64)p.ntiles;
+        const int tile = WHOLE ? 0 : (int)(item - rAt * (u64)p.ntiles);
         const u64 tlo = whole_rows ? 0 : p.tile_lo[tile], thi = whole_rows ? Nb : p.tile_lo[tile + 1];
         const int tsz = (int)(thi - tlo);
         const u32 At = str_unrank_wave(rAt, na, n, sB);
@@ -432,7 +436,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
         }
 
         // Phase 1: the nonempty source rows, with their entry range in this tile.
-        const bool multi = !GRAD && p.ntiles > 1;
+        const bool multi = !WHOLE && !GRAD && p.ntiles > 1;
         const bool cached = multi && s_cache_row == rAt && s_cache_inst == s_inst;
         if (cached) {
             // the row's records from its first tile: this tile's entry ranges
@@ -1238,7 +1242,7 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                 // Alpha-beta doubles of a row of several tiles: the source
                 // row's items that land in this tile, listed per input chunk
                 // (the chunks' item ranges read 64 at a time, a chunk per
-                // lane); lanes over the items, RT_UNROLL groups of 64 loads in
+                // lane); lanes over the items, AB_UNROLL groups of 64 loads in
                 // flight.
                 // The element is the staged slab's (alpha phase folded in) or
                 // (ia|jb) from global memory with the alpha phase; the beta
@@ -1263,22 +1267,22 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
                         const u64 c = cb + (u64)jc;
                         const u64 x0 = rl64(xl0, jc), x1 = rl64(xl1, jc);
                         const u64 kc = (u64)r.rowb + (c - c0) * AB_CHUNK;  // the chunk's first entry
-                        for (u64 xb = x0; xb < x1; xb += 64 * RT_UNROLL) {
-                            u32 it[RT_UNROLL];
+                        for (u64 xb = x0; xb < x1; xb += 64 * AB_UNROLL) {
+                            u32 it[AB_UNROLL];
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
+                            for (int u = 0; u < AB_UNROLL; ++u) {
                                 const u64 x = xb + (u64)u * 64 + lane;
                                 it[u] = (x < x1) ? itg[x] : 0u;
                             }
-                            double e[RT_UNROLL], cc[RT_UNROLL];
+                            double e[AB_UNROLL], cc[AB_UNROLL];
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
+                            for (int u = 0; u < AB_UNROLL; ++u) {
                                 const u32 jb = (it[u] >> 14) & 1023u;
                                 e[u] = gs ? slab[jb] : grow[jb];
                                 cc[u] = ampg[kc + ((it[u] >> 24) & 63u)];
                             }
 #pragma unroll
-                            for (int u = 0; u < RT_UNROLL; ++u) {
+                            for (int u = 0; u < AB_UNROLL; ++u) {
                                 const bool act = xb + (u64)u * 64 + lane < x1;
                                 const double pr = e[u] * cc[u];
                                 const double t = __hiloint2double(
@@ -1498,6 +1502,27 @@ __global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile_timed(const RTParams
 }
 
 // Integral gradients, first pass (alpha-side and alpha-beta terms).
+// The same for launches whose rows are all one tile (the multi-tile code compiled out).
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile_whole(const RTParams* __restrict__ descs,
+                                                                  const u64* __restrict__ item_prefix, int n_inst,
+                                                                  unsigned* __restrict__ counter, void* nbr_scratch,
+                                                                  u64 nbr_cap, unsigned slab_off, unsigned slab_n2,
+                                                                  unsigned itab_off, unsigned b1_chunk,
+                                                                  unsigned bb_chunk, unsigned ja_off) {
+    rowtile_body<RT_SIGMA, false, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2,
+                                        itab_off, b1_chunk, bb_chunk, ja_off);
+}
+__global__ __launch_bounds__(RT_BLOCK) void k_sigma_rowtile_whole_timed(const RTParams* __restrict__ descs,
+                                                                        const u64* __restrict__ item_prefix,
+                                                                        int n_inst, unsigned* __restrict__ counter,
+                                                                        void* nbr_scratch, u64 nbr_cap,
+                                                                        unsigned slab_off, unsigned slab_n2,
+                                                                        unsigned itab_off, unsigned b1_chunk,
+                                                                        unsigned bb_chunk, unsigned ja_off) {
+    rowtile_body<RT_SIGMA, true, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, slab_n2,
+                                       itab_off, b1_chunk, bb_chunk, ja_off);
+}
+
 __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a(const RTParams* __restrict__ descs,
                                                              const u64* __restrict__ item_prefix, int n_inst,
                                                              unsigned* __restrict__ counter, void* nbr_scratch,
@@ -1828,6 +1853,7 @@ static size_t rt_static_lds() {
     if (cached == 0) {
         size_t mx = 0;
         for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_sigma_rowtile_timed,
+                              (const void*)k_sigma_rowtile_whole, (const void*)k_sigma_rowtile_whole_timed,
                               (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b}) {
             hipFuncAttributes attr{};
             SFCI_CHECK_HIP(hipFuncGetAttributes(&attr, f));
@@ -1958,6 +1984,7 @@ bool rowtile_available(sfci_problem* P) {
     S->maxlds = maxlds;
     const int dyn_max = maxlds - (int)rt_static_lds();
     for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_sigma_rowtile_timed,
+                          (const void*)k_sigma_rowtile_whole, (const void*)k_sigma_rowtile_whole_timed,
                           (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b})
         SFCI_CHECK_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_max));
     SFCI_CHECK_HIP(hipStreamSynchronize(P->stream));
@@ -2146,7 +2173,8 @@ RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst) {
     const unsigned itab_off = (unsigned)(tile / sizeof(double));
     const unsigned slab_off = itab_off + rt_itab_doubles(n2);
     const size_t base = (size_t)slab_off * sizeof(double);
-    RowTileGeom g{base + (size_t)RT_WAVES * 32 * sizeof(double), slab_off, 0u, itab_off, 0u};
+    RowTileGeom g{base + (size_t)RT_WAVES * 32 * sizeof(double), slab_off, 0u, itab_off, 0u, true};
+    for (int k = 0; k < n_inst; ++k) g.whole = g.whole && ((const RTParams*)d[k].raw)->ntiles == 1;
     const size_t with = base + (size_t)RT_WAVES * (n2 + 32) * sizeof(double);
     if (with + rt_static_lds() <= (size_t)maxlds) g.lds = with, g.slab_n2 = n2;
     // then the identity row's alpha-part table, if it still fits
@@ -2165,7 +2193,9 @@ void rowtile_run(hipStream_t stream, int num_cu, const void* d_descs, const u64*
                  bool fill_counter, const RowTileTune& tune, bool timed) {
     if (fill_counter) launch_fill_u64((u64*)d_counter, 1, 0, stream);
     const unsigned grid = rowtile_grid(num_cu, geom.lds, total_items, tune.per_cu);
-    hipLaunchKernelGGL(timed ? k_sigma_rowtile_timed : k_sigma_rowtile, dim3(grid), dim3(RT_BLOCK), geom.lds, stream,
+    auto* kern = geom.whole ? (timed ? k_sigma_rowtile_whole_timed : k_sigma_rowtile_whole)
+                            : (timed ? k_sigma_rowtile_timed : k_sigma_rowtile);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(RT_BLOCK), geom.lds, stream,
                        (const RTParams*)d_descs,
                        d_prefix, n_inst, d_counter, scratch, nbr_cap, geom.slab_off, geom.slab_n2, geom.itab_off,
                        tune.b1_chunk ? tune.b1_chunk : RT_B1_CHUNK, tune.bb_chunk ? tune.bb_chunk : RT_BB_CHUNK,

@@ -184,6 +184,7 @@ struct RowTileGeom {
     unsigned slab_off, slab_n2;
     unsigned itab_off;  // per-item element tables
     unsigned ja_off;    // the identity row's alpha-part table (0: not staged)
+    bool whole = false; // every instance's rows are one tile (the one-tile kernel runs)
 };
 RowTileGeom rowtile_geom(const RowTileDesc* d, int n_inst);
 // Launch-time work sizes of the sigma tile kernel (0 = the built-in default):
