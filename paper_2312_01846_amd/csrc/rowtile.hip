@@ -1540,6 +1540,22 @@ __global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b(const RTParams* __r
                             RT_BB_CHUNK, 0u);
 }
 
+// The two passes for launches whose rows are all one tile.
+__global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_a_whole(const RTParams* __restrict__ descs,
+                                                                   const u64* __restrict__ item_prefix, int n_inst,
+                                                                   unsigned* __restrict__ counter, void* nbr_scratch,
+                                                                   u64 nbr_cap, unsigned slab_off, unsigned slab_n2) {
+    rowtile_body<RT_GRAD_A, false, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off,
+                                         slab_n2, 0u, RT_B1_CHUNK, RT_BB_CHUNK, 0u);
+}
+__global__ __launch_bounds__(RT_BLOCK) void k_grad_rowtile_b_whole(const RTParams* __restrict__ descs,
+                                                                   const u64* __restrict__ item_prefix, int n_inst,
+                                                                   unsigned* __restrict__ counter, void* nbr_scratch,
+                                                                   u64 nbr_cap, unsigned slab_off) {
+    rowtile_body<RT_GRAD_B, false, true>(descs, item_prefix, n_inst, counter, nbr_scratch, nbr_cap, slab_off, 0u,
+                                         0u, RT_B1_CHUNK, RT_BB_CHUNK, 0u);
+}
+
 // ---- per-problem tables ----
 // T1: for every beta string, its singles sorted by target rank; toff: per-tile
 // offsets into that sorted slice.  One wavefront per beta string; the sort is
@@ -1854,7 +1870,8 @@ static size_t rt_static_lds() {
         size_t mx = 0;
         for (const void* f : {(const void*)k_sigma_rowtile, (const void*)k_sigma_rowtile_timed,
                               (const void*)k_sigma_rowtile_whole, (const void*)k_sigma_rowtile_whole_timed,
-                              (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b}) {
+                              (const void*)k_grad_rowtile_a, (const void*)k_grad_rowtile_b,
+                              (const void*)k_grad_rowtile_a_whole, (const void*)k_grad_rowtile_b_whole}) {
             hipFuncAttributes attr{};
             SFCI_CHECK_HIP(hipFuncGetAttributes(&attr, f));
             mx = std::max(mx, (size_t)attr.sharedSizeBytes);
@@ -2362,16 +2379,18 @@ void grad_pass(hipStream_t st, int pass, std::vector<RowTileDesc>& d, unsigned s
     launch_fill_u64((u64*)cnt, 1, 0, st);
     const unsigned grid = rowtile_grid(num_cu, lds, pre[n]);
     void* scr = ws.scratch.get(rowtile_scratch_bytes(grid, nbr_cap));
+    bool whole = true;  // every row one tile: the kernels with the multi-tile code compiled out
+    for (int k = 0; k < n; ++k) whole = whole && ((const RTParams*)d[k].raw)->ntiles == 1;
     if (pass == 0) {
-        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_grad_rowtile_a, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
-        hipLaunchKernelGGL(k_grad_rowtile_a, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt,
-                           scr, nbr_cap, slab_off, slab_n2);
+        auto* kern = whole ? k_grad_rowtile_a_whole : k_grad_rowtile_a;
+        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt, scr, nbr_cap,
+                           slab_off, slab_n2);
     } else {
-        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)k_grad_rowtile_b, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds));
-        hipLaunchKernelGGL(k_grad_rowtile_b, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt,
-                           scr, nbr_cap, slab_off);
+        auto* kern = whole ? k_grad_rowtile_b_whole : k_grad_rowtile_b;
+        SFCI_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(RT_BLOCK), lds, st, (const RTParams*)dd, dpre, n, cnt, scr, nbr_cap,
+                           slab_off);
     }
     SFCI_CHECK_HIP(hipGetLastError());
     SFCI_CHECK_HIP(hipStreamSynchronize(st));  // the host staging buffer goes out of scope
