@@ -649,26 +649,49 @@ __device__ __forceinline__ void rowtile_body(const RTParams* __restrict__ descs,
             // flight across row boundaries.  The other long rows (the diagonal's,
             // alpha singles') one at a time, alpha singles with (ia|qq) staged.
             constexpr int DB = 8;
+            // a batch's records are read while the previous batch streams
+            auto claim = [&]() {
+                unsigned b = 0;
+                if (lane == 0) b = atomicAdd(&s_next2, (unsigned)DB);
+                return (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)b, 0));
+            };
+            unsigned nbase = claim();
+            u32 n_e0 = 0, n_e1 = 0, n_type = 255;
+            double n_cst = 0.0;
+            auto fetch = [&]() {
+                n_type = 255;
+                if (lane < DB && nbase + (unsigned)lane < nlist) {
+                    const NbrRec& r = rec(nbase + (unsigned)lane);
+                    n_e0 = r.e0;
+                    n_e1 = r.e1;
+                    n_type = r.type;
+                    n_cst = r.cst;
+                }
+            };
+            if (nbase < nlist) fetch();
             for (;;) {
-                unsigned base = 0;
-                if (lane == 0) base = atomicAdd(&s_next2, (unsigned)DB);
-                base = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl((int)base, 0));
+                const unsigned base = nbase;
                 if (base >= nlist) break;
                 u32 d_e0 = 0, d_len = 0;
                 double d_cst = 0.0;
                 bool other = false;
-                if (lane < DB && base + (unsigned)lane < nlist) {
-                    const NbrRec r = rec(base + (unsigned)lane);
+                if (n_type != 255) {
+                    NbrRec r;
+                    r.e0 = n_e0;
+                    r.e1 = n_e1;
+                    r.type = (uint8_t)n_type;
                     if (by_wave(r)) {
                         if (r.type == 2) {
-                            d_e0 = r.e0;
-                            d_len = r.e1 - r.e0;
-                            d_cst = r.cst;
+                            d_e0 = n_e0;
+                            d_len = n_e1 - n_e0;
+                            d_cst = n_cst;
                         } else {
                             other = true;
                         }
                     }
                 }
+                nbase = claim();
+                if (nbase < nlist) fetch();
                 for (u64 om = __ballot(other); om; om &= om - 1) {
                     const unsigned j = (unsigned)(__ffsll((long long)om) - 1);
                     const NbrRec r = rec(base + j);
